@@ -1,0 +1,600 @@
+"""Plain FP64 CPU oracle of the CC-MSAV-BDF2 vesicle step.
+
+TEST INFRASTRUCTURE ONLY. Only the tests, the smoke check and the CPU-baseline
+leg of the benchmark may import this module; the product path never does.
+
+It follows the paper (Zhang, Li, Lowengrub & Wise, arXiv 2601.10057) as
+written, in its order and notation, with numpy for array arithmetic:
+
+* discrete operators, inner products and Neumann ghosts: App. D;
+* SAV functionals V, U, W, Z: eq. (aux_vars), Sec. 2.2;
+* basis functions S, H, Q, K, P: Sec. 2.2 (variational derivatives) with the
+  discrete forms of Sec. 3.4.1;
+* one BDF2 step: eqs. (AC_BDF2)-(Z_BDF2), solved by the procedure of App. B
+  (f^n, g^n, seven elliptic solves, the 5x5 system, field recovery, SAV
+  update of Algorithm 1); the first step uses the BDF1 variant of App. B;
+* elliptic solves: App. C (2D DCT, divide by the operator spectrum, inverse
+  DCT); the DCT is the orthonormal DCT-II written out as a matrix
+  (definition), with scipy's DCT as an equivalent fast library primitive for
+  large grids;
+* modified discrete energy: eq. (modified_discrete_energy); the dissipation
+  quantities K^n, ||mu||^2, ||c + d/2||^2 of Thm. 3.1 / App. A.
+
+Readings where the paper is silent or ambiguous (all stated in the design doc):
+face mobility is M_psi of the face-averaged phi*; the face average of phi^2
+in div(phi^2 grad phi) is (phi_i^2 + phi_{i+1}^2)/2; the cell |grad phi|^2
+is the mean of the squared face gradients around the cell; DCTs are
+orthonormal; the zero mode is divided like every other mode (its eigenvalue
+is C1 > 0 or 3/(2 dt) > 0); the arc-length target A defaults to the discrete
+surface energy of phi0; d^{n+1} and c^{n+1} live on faces.
+
+Arrays are ``[ny][nx]`` (x fastest); ``u[j, i]`` is the cell (i, j).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+SQ2 = math.sqrt(2.0)
+
+# Above this size the DCT matrix products are replaced by scipy's DCT.
+MATRIX_DCT_MAX = 512
+
+
+# ---------------------------------------------------------------------------
+# Discrete operators on the staggered cell-centred grid (App. D)
+# ---------------------------------------------------------------------------
+
+def with_ghosts(u: np.ndarray) -> np.ndarray:
+    """Ghost ring phi_0 = phi_1, phi_{m+1} = phi_m (App. D, boundary conditions)."""
+    return np.pad(u, 1, mode="edge")
+
+
+def Dx(u, h):
+    """(D_x u)_{i+1/2, j} on all east-west faces i = 0..m, shape (ny, nx+1)."""
+    g = with_ghosts(u)[1:-1, :]
+    return (g[:, 1:] - g[:, :-1]) / h
+
+
+def Dy(u, h):
+    """(D_y u)_{i, j+1/2} on all north-south faces j = 0..n, shape (ny+1, nx)."""
+    g = with_ghosts(u)[:, 1:-1]
+    return (g[1:, :] - g[:-1, :]) / h
+
+
+def Ax(u):
+    """(A_x u)_{i+1/2, j} = (u_i + u_{i+1}) / 2 on east-west faces."""
+    g = with_ghosts(u)[1:-1, :]
+    return 0.5 * (g[:, 1:] + g[:, :-1])
+
+
+def Ay(u):
+    """(A_y u)_{i, j+1/2} = (u_j + u_{j+1}) / 2 on north-south faces."""
+    g = with_ghosts(u)[:, 1:-1]
+    return 0.5 * (g[1:, :] + g[:-1, :])
+
+
+def dx(f, h):
+    """Edge-to-centre difference (d_x f)_{i,j} = (f_{i+1/2} - f_{i-1/2}) / h."""
+    return (f[:, 1:] - f[:, :-1]) / h
+
+
+def dy(g, h):
+    """Edge-to-centre difference (d_y g)_{i,j} = (g_{j+1/2} - g_{j-1/2}) / h."""
+    return (g[1:, :] - g[:-1, :]) / h
+
+
+def lap(u, h):
+    """Five-point Laplacian Delta_h = d_x D_x + d_y D_y with Neumann ghosts."""
+    return dx(Dx(u, h), h) + dy(Dy(u, h), h)
+
+
+def div_mobility_grad(mob_x, mob_y, u, h):
+    """d_x(M_x D_x u) + d_y(M_y D_y u) with face mobilities (Sec. 3.4.1)."""
+    return dx(mob_x * Dx(u, h), h) + dy(mob_y * Dy(u, h), h)
+
+
+def grad_sq_cell(u, h):
+    """Cell value of |grad u|^2: mean of the squared face gradients (Sec. 3.4.1)."""
+    gx = Dx(u, h) ** 2
+    gy = Dy(u, h) ** 2
+    return 0.5 * (gx[:, 1:] + gx[:, :-1]) + 0.5 * (gy[1:, :] + gy[:-1, :])
+
+
+def ip(a, b, h):
+    """Discrete L2 inner product (a, b)_h = h^2 sum a b (App. D)."""
+    return h * h * float(np.sum(np.asarray(a) * np.asarray(b)))
+
+
+def integral(a, h):
+    """Discrete integral h^2 sum a."""
+    return h * h * float(np.sum(a))
+
+
+def face_ip(fx, fy, gx, gy, h):
+    """[f, g]_ew + [f, g]_ns with the half-weighted two-face sums of App. D."""
+    ew = 0.5 * h * h * (np.sum(fx[:, 1:] * gx[:, 1:]) + np.sum(fx[:, :-1] * gx[:, :-1]))
+    ns = 0.5 * h * h * (np.sum(fy[1:, :] * gy[1:, :]) + np.sum(fy[:-1, :] * gy[:-1, :]))
+    return float(ew + ns)
+
+
+def grad_norm_sq(u, h):
+    """||grad_h u||^2 = [D_x u, D_x u]_ew + [D_y u, D_y u]_ns (App. D)."""
+    gx, gy = Dx(u, h), Dy(u, h)
+    return face_ip(gx, gy, gx, gy, h)
+
+
+def lap_matrix(nx, ny, h):
+    """Dense matrix of Delta_h, built by applying the stencil to unit vectors."""
+    n = nx * ny
+    L = np.zeros((n, n))
+    e = np.zeros((ny, nx))
+    for c in range(n):
+        e.flat[c] = 1.0
+        L[:, c] = lap(e, h).ravel()
+        e.flat[c] = 0.0
+    return L
+
+
+# ---------------------------------------------------------------------------
+# DCT and the fast direct solver (App. C)
+# ---------------------------------------------------------------------------
+
+def dct_matrix(n: int) -> np.ndarray:
+    """Orthonormal DCT-II matrix C[k, i] = s_k cos(pi k (2 i + 1) / (2 n))."""
+    k = np.arange(n)[:, None]
+    i = np.arange(n)[None, :]
+    C = np.cos(math.pi * k * (2 * i + 1) / (2.0 * n))
+    C[0, :] *= math.sqrt(1.0 / n)
+    C[1:, :] *= math.sqrt(2.0 / n)
+    return C
+
+
+_DCT_CACHE: Dict[int, np.ndarray] = {}
+
+
+def _cmat(n):
+    if n not in _DCT_CACHE:
+        _DCT_CACHE[n] = dct_matrix(n)
+    return _DCT_CACHE[n]
+
+
+def dct2(u: np.ndarray, use_matrix: Optional[bool] = None) -> np.ndarray:
+    """2D orthonormal DCT-II of a cell field: C_y u C_x^T."""
+    ny, nx = u.shape
+    if use_matrix is None:
+        use_matrix = max(nx, ny) <= MATRIX_DCT_MAX
+    if use_matrix:
+        return _cmat(ny) @ u @ _cmat(nx).T
+    from scipy.fft import dctn
+    return dctn(u, type=2, norm="ortho")
+
+
+def idct2(U: np.ndarray, use_matrix: Optional[bool] = None) -> np.ndarray:
+    """2D orthonormal DCT-III (inverse of dct2): C_y^T U C_x."""
+    ny, nx = U.shape
+    if use_matrix is None:
+        use_matrix = max(nx, ny) <= MATRIX_DCT_MAX
+    if use_matrix:
+        return _cmat(ny).T @ U @ _cmat(nx)
+    from scipy.fft import idctn
+    return idctn(U, type=2, norm="ortho")
+
+
+def neumann_lap_eigs(nx, ny, h):
+    """Eigenvalues lambda_ij of Delta_h (App. C): -(4/h^2)(sin^2(pi i/2m) + sin^2(pi j/2n)).
+
+    Returned on the ``[ky, kx]`` grid matching ``dct2``.
+    """
+    lx = -(4.0 / h ** 2) * np.sin(math.pi * np.arange(nx) / (2.0 * nx)) ** 2
+    ly = -(4.0 / h ** 2) * np.sin(math.pi * np.arange(ny) / (2.0 * ny)) ** 2
+    return ly[:, None] + lx[None, :]
+
+
+def spectral_solve(rhs, spectrum, use_matrix=None):
+    """Fast direct solve of an operator diagonal in the DCT basis (App. C)."""
+    return idct2(dct2(rhs, use_matrix) / spectrum, use_matrix)
+
+
+# ---------------------------------------------------------------------------
+# Model pieces (Sec. 2)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Params:
+    nx: int
+    ny: int
+    h: float
+    dt: float
+    eps: float
+    M_phi: float
+    M0: float
+    gamma_surf: float
+    gamma_bend: float
+    gamma_area: float
+    A: float
+    gamma_in: float
+    gamma_out: float
+    psi_in: float
+    psi_out: float
+    beta_in: float
+    beta_out: float
+    theta: float
+    lam: float
+    beta: float
+
+    @classmethod
+    def from_dict(cls, d: Dict) -> "Params":
+        names = cls.__dataclass_fields__.keys()
+        return cls(**{k: d[k] for k in names})
+
+
+def p_interp(phi):
+    """Interpolation p(phi) = sin(pi phi / 2) (Sec. 2.1)."""
+    return np.sin(0.5 * math.pi * phi)
+
+
+def dp_interp(phi):
+    """p'(phi) = (pi/2) cos(pi phi / 2)."""
+    return 0.5 * math.pi * np.cos(0.5 * math.pi * phi)
+
+
+def f_in(psi, p: Params):
+    """f^in(psi) = gamma_in/2 (psi - psi_in)^2 + beta_in (Sec. 2.1)."""
+    return 0.5 * p.gamma_in * (psi - p.psi_in) ** 2 + p.beta_in
+
+
+def f_out(psi, p: Params):
+    """f^out(psi) = gamma_out/2 (psi - psi_out)^2 + beta_out (Sec. 2.1)."""
+    return 0.5 * p.gamma_out * (psi - p.psi_out) ** 2 + p.beta_out
+
+
+def mobility_psi(phi, p: Params):
+    """Cahn-Hilliard mobility M_psi(phi) = 1 - M0 (phi^2 - 1)^2 (Sec. 2.1)."""
+    return 1.0 - p.M0 * (phi * phi - 1.0) ** 2
+
+
+def double_well(phi):
+    """g(phi) = (phi^2 - 1)^2 / 4."""
+    return 0.25 * (phi * phi - 1.0) ** 2
+
+
+def f_surf(phi, p: Params):
+    """Surface density (3 sqrt2/4)(g/eps + eps/2 |grad phi|^2), cell form."""
+    return 0.75 * SQ2 * (double_well(phi) / p.eps
+                         + 0.5 * p.eps * grad_sq_cell(phi, p.h))
+
+
+def sav_V(phi, p: Params):
+    """V = sqrt(int (phi^2 - 1 - beta)^2 / (4 eps)) (eq. aux_VW)."""
+    return math.sqrt(integral((phi * phi - 1.0 - p.beta) ** 2 / (4.0 * p.eps), p.h))
+
+
+def sav_U(phi, p: Params):
+    """U = int f_surf - A (eq. aux_ZU)."""
+    return integral(f_surf(phi, p), p.h) - p.A
+
+
+def w_density(phi, p: Params):
+    """Integrand of W^2: 6 phi^2 |grad phi|^2 + (phi^3 - phi)^2 / eps^2."""
+    return (6.0 * phi * phi * grad_sq_cell(phi, p.h)
+            + (phi ** 3 - phi) ** 2 / p.eps ** 2)
+
+
+def sav_W(phi, p: Params):
+    """W = sqrt(int w_density) (eq. aux_VW)."""
+    return math.sqrt(integral(w_density(phi, p), p.h))
+
+
+def osm_twice(phi, psi, p: Params):
+    """2 f_osm = (1 + p) f_in + (1 - p) f_out (eq. osm_density)."""
+    pp = p_interp(phi)
+    return (1.0 + pp) * f_in(psi, p) + (1.0 - pp) * f_out(psi, p)
+
+
+def sav_Z(phi, psi, p: Params):
+    """Z = sqrt(2 int f_osm) (eq. aux_ZU)."""
+    return math.sqrt(integral(osm_twice(phi, psi, p), p.h))
+
+
+def basis_S(phi, p: Params):
+    """S(phi) = phi (phi^2 - 1 - beta)/eps / (2 sqrt(int (phi^2-1-beta)^2/(4 eps)))."""
+    return (phi * (phi * phi - 1.0 - p.beta) / p.eps) / (2.0 * sav_V(phi, p))
+
+
+def basis_H(phi, p: Params):
+    """H(phi) = (3 sqrt2/4)(phi (phi^2 - 1)/eps - eps Delta_h phi)."""
+    return 0.75 * SQ2 * (phi * (phi * phi - 1.0) / p.eps - p.eps * lap(phi, p.h))
+
+
+def basis_Q(phi, p: Params):
+    """Q(phi) = {6 [phi|grad phi|^2 - div(phi^2 grad phi)] + (phi^3-phi)(3phi^2-1)/eps^2} / W.
+
+    [phi |grad phi|^2] and [div(phi^2 grad phi)] follow Sec. 3.4.1 with the
+    face average of phi^2 taken as (phi_i^2 + phi_{i+1}^2)/2.
+    """
+    h = p.h
+    sq = phi * phi
+    term_a = phi * grad_sq_cell(phi, h)
+    term_b = dx(Ax(sq) * Dx(phi, h), h) + dy(Ay(sq) * Dy(phi, h), h)
+    num = 6.0 * (term_a - term_b) + (phi ** 3 - phi) * (3.0 * sq - 1.0) / p.eps ** 2
+    return num / sav_W(phi, p)
+
+
+def basis_K(phi, psi, p: Params):
+    """K = p'(phi)(f_in - f_out) / (2 sqrt(int[(1+p) f_in + (1-p) f_out]))."""
+    return dp_interp(phi) * (f_in(psi, p) - f_out(psi, p)) / (2.0 * sav_Z(phi, psi, p))
+
+
+def basis_P(phi, psi, p: Params):
+    """P = [gamma_in (1+p)(psi - psi_in) + gamma_out (1-p)(psi - psi_out)] / (2 Z)."""
+    pp = p_interp(phi)
+    num = (p.gamma_in * (1.0 + pp) * (psi - p.psi_in)
+           + p.gamma_out * (1.0 - pp) * (psi - p.psi_out))
+    return num / (2.0 * sav_Z(phi, psi, p))
+
+
+def face_mobility(phi, p: Params):
+    """M_psi evaluated at the face-averaged phi (Sec. 3.4.1)."""
+    return mobility_psi(Ax(phi), p), mobility_psi(Ay(phi), p)
+
+
+# ---------------------------------------------------------------------------
+# Time stepping (Sec. 3.2 and App. B)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class State:
+    """Two time levels of the fields plus the SAVs and the energy accumulator."""
+    p: Params
+    phi: np.ndarray              # level n
+    psi: np.ndarray
+    phi_prev: Optional[np.ndarray]   # level n-1 (None before the first step)
+    psi_prev: Optional[np.ndarray]
+    sav: np.ndarray              # (V, U, W, Z) at level n
+    sav_prev: Optional[np.ndarray]
+    n: int = 0
+    d_acc: float = 0.0           # sum_{j>=2} (dt/2) ||d^j||^2
+    history: List[Dict] = field(default_factory=list)
+
+
+def initial_state(phi0, psi0, params: Dict) -> State:
+    """Initial fields and SAVs (eq. msav_ic); A defaults to int f_surf(phi0)."""
+    p = Params.from_dict(params)
+    phi0 = np.array(phi0, dtype=np.float64)
+    psi0 = np.array(psi0, dtype=np.float64)
+    if not math.isfinite(p.A):
+        p.A = integral(f_surf(phi0, p), p.h)
+    sav = np.array([sav_V(phi0, p), sav_U(phi0, p), sav_W(phi0, p),
+                    sav_Z(phi0, psi0, p)])
+    return State(p, phi0, psi0, None, None, sav, None)
+
+
+def chi_coefficients(p: Params, alpha: float):
+    """C1, C2, C3 of the Allen-Cahn operator chi (App. B, Step 3)."""
+    C1 = alpha + p.M_phi * p.gamma_surf * 3.0 * SQ2 * p.beta / (4.0 * p.eps)
+    C2 = p.M_phi * (p.gamma_surf * 3.0 * SQ2 * p.eps / 4.0 + p.theta)
+    C3 = p.M_phi * p.gamma_bend * 3.0 * SQ2 * p.eps / 8.0
+    return C1, C2, C3
+
+
+def theta_tilde(p: Params):
+    """theta + gamma_bend 3 sqrt2 / (4 eps) (Sec. 3.3)."""
+    return p.theta + p.gamma_bend * 3.0 * SQ2 / (4.0 * p.eps)
+
+
+def sav_weights(p: Params):
+    """c_gs, c_ga, c_gb, c_go of App. B, Step 3."""
+    return (p.M_phi * p.gamma_surf * 3.0 * SQ2 / 2.0,
+            p.M_phi * p.gamma_area,
+            p.M_phi * p.gamma_bend * 3.0 * SQ2 / (8.0 * p.eps),
+            p.M_phi)
+
+
+def step(st: State, use_matrix: Optional[bool] = None, keep: bool = False) -> Dict:
+    """Advance one step: BDF1 variant first (App. B remark), BDF2 after.
+
+    Returns a dict of intermediate quantities (the 5x5 system, etc.).
+    """
+    p = st.p
+    h, dt = p.h, p.dt
+    bdf2 = st.phi_prev is not None
+    phi_n, psi_n = st.phi, st.psi
+    Vn, Un, Wn, Zn = st.sav
+    if bdf2:
+        phi_m, psi_m = st.phi_prev, st.psi_prev
+        Vm, Um, Wm, Zm = st.sav_prev
+        phis = 2.0 * phi_n - phi_m
+        psis = 2.0 * psi_n - psi_m
+        alpha = 3.0 / (2.0 * dt)
+    else:
+        phis, psis = phi_n, psi_n
+        alpha = 1.0 / dt
+
+    S = basis_S(phis, p)
+    H = basis_H(phis, p)
+    Q = basis_Q(phis, p)
+    K = basis_K(phis, psis, p)
+    P = basis_P(phis, psis, p)
+    mx, my = face_mobility(phis, p)
+    LP_src = div_mobility_grad(mx, my, P, h)    # div(M_psi(phi*) grad P*)
+
+    # Bracketed explicit SAV parts: BDF2 carries the 1/3 of the paper's f^n.
+    if bdf2:
+        dphi = -4.0 * phi_n + phi_m
+        dpsi = -4.0 * psi_n + psi_m
+        sV = (4.0 * Vn - Vm + ip(S, dphi, h)) / 3.0
+        sU = (4.0 * Un - Um + ip(H, dphi, h)) / 3.0
+        sW = (4.0 * Wn - Wm + ip(Q, dphi, h)) / 3.0
+        sZ = (4.0 * Zn - Zm + ip(K, dphi, h) + ip(P, dpsi, h)) / 3.0
+        a_phi = (4.0 * phi_n - phi_m) / (2.0 * dt)
+        a_psi = (4.0 * psi_n - psi_m) / (2.0 * dt)
+    else:
+        sV = Vn + ip(S, -phi_n, h)
+        sU = Un + ip(H, -phi_n, h)
+        sW = Wn + ip(Q, -phi_n, h)
+        sZ = Zn + ip(K, -phi_n, h) + ip(P, -psi_n, h)
+        a_phi = phi_n / dt
+        a_psi = psi_n / dt
+
+    tt = theta_tilde(p)
+    f = a_phi - p.M_phi * (tt * lap(phis, h)
+                           + p.gamma_surf * 1.5 * SQ2 * sV * S
+                           + p.gamma_area * sU * H
+                           + p.gamma_bend * 3.0 * SQ2 / (8.0 * p.eps) * sW * Q
+                           + sZ * K)
+    nu_tilde = sZ * P
+    g = a_psi - p.lam * lap(psis, h) + div_mobility_grad(mx, my, nu_tilde, h)
+
+    C1, C2, C3 = chi_coefficients(p, alpha)
+    lam_h = neumann_lap_eigs(p.nx, p.ny, h)
+    sigma = C1 - C2 * lam_h + C3 * lam_h ** 2
+    tau = alpha - p.lam * lam_h
+
+    chi_inv = lambda r: spectral_solve(r, sigma, use_matrix)   # noqa: E731
+    zeta_inv = lambda r: spectral_solve(r, tau, use_matrix)    # noqa: E731
+    f_hat = chi_inv(f)
+    S_hat, H_hat, Q_hat, K_hat = chi_inv(S), chi_inv(H), chi_inv(Q), chi_inv(K)
+    g_hat = zeta_inv(g)
+    Lam_P = zeta_inv(LP_src)
+
+    cgs, cga, cgb, cgo = sav_weights(p)
+    F = [S, H, Q, K]
+    Fh = [S_hat, H_hat, Q_hat, K_hat]
+    cw = [cgs, cga, cgb, cgo]
+    M = np.zeros((5, 5))
+    b = np.zeros(5)
+    for i in range(4):
+        for j in range(4):
+            M[i, j] = cw[j] * ip(F[i], Fh[j], h) + (1.0 if i == j else 0.0)
+        M[i, 4] = cgo * ip(F[i], K_hat, h)
+        b[i] = ip(F[i], f_hat, h)
+    PL = ip(P, Lam_P, h)
+    M[4, 3] = -PL
+    M[4, 4] = 1.0 - PL
+    b[4] = ip(P, g_hat, h)
+    x = np.linalg.solve(M, b)
+    B, C, D, E, G = x
+
+    phi_new = f_hat - cgs * B * S_hat - cga * C * H_hat - cgb * D * Q_hat \
+        - cgo * (E + G) * K_hat
+    psi_new = g_hat + (E + G) * Lam_P
+    sav_new = np.array([B + sV, C + sU, D + sW, E + G + sZ])
+
+    info = dict(bdf2=bdf2, M=M, b=b, x=x, s=np.array([sV, sU, sW, sZ]),
+                norms=np.array([sav_V(phis, p), sav_W(phis, p), sav_Z(phis, psis, p)]))
+    if keep:
+        info.update(S=S, H=H, Q=Q, K=K, P=P, LP=LP_src, f=f, g=g,
+                    phis=phis, psis=psis, sigma=sigma, tau=tau)
+
+    if bdf2:
+        st.d_acc += 0.5 * dt * d_norm_sq(psi_new, psis, phis, p)
+    st.phi_prev, st.psi_prev, st.sav_prev = phi_n, psi_n, st.sav
+    st.phi, st.psi, st.sav = phi_new, psi_new, sav_new
+    st.n += 1
+    return info
+
+
+def run(phi0, psi0, params: Dict, nsteps: int, use_matrix=None) -> State:
+    """Initialise and take ``nsteps`` steps."""
+    st = initial_state(phi0, psi0, params)
+    for _ in range(nsteps):
+        step(st, use_matrix)
+    return st
+
+
+# ---------------------------------------------------------------------------
+# Energy and mass (Sec. 3.3, App. A, App. D)
+# ---------------------------------------------------------------------------
+
+def d_faces(psi_new, psis, phis, p: Params):
+    """d^{n+1} = lambda D(psi^{n+1} - psi*) / sqrt(M_psi(A phi*)) on faces."""
+    mx, my = face_mobility(phis, p)
+    dpsi = psi_new - psis
+    return (p.lam * Dx(dpsi, p.h) / np.sqrt(mx),
+            p.lam * Dy(dpsi, p.h) / np.sqrt(my))
+
+
+def d_norm_sq(psi_new, psis, phis, p: Params):
+    """||d^{n+1}||^2 with the face inner products of App. D."""
+    fx, fy = d_faces(psi_new, psis, phis, p)
+    return face_ip(fx, fy, fx, fy, p.h)
+
+
+def modified_energy(phi1, phi0, sav1, sav0, d_acc, p: Params) -> Dict:
+    """E^{n+1,n}_mod of eq. (modified_discrete_energy) with discrete norms.
+
+    ``phi1``/``sav1`` are level n+1, ``phi0``/``sav0`` level n, ``d_acc`` is
+    sum_{j=2}^{n+1} (dt/2) ||d^j||^2.
+    """
+    h = p.h
+    V1, U1, W1, Z1 = sav1
+    V0, U0, W0, Z0 = sav0
+    tt = theta_tilde(p)
+    l1, l0 = lap(phi1, h), lap(phi0, h)
+    bend = 0.5 * p.gamma_bend * 3.0 * SQ2 * p.eps / 8.0 * (
+        ip(l1, l1, h) + ip(2.0 * l1 - l0, 2.0 * l1 - l0, h))
+    g1 = grad_norm_sq(phi1, h)
+    g2 = grad_norm_sq(2.0 * phi1 - phi0, h)
+    gd = grad_norm_sq(phi1 - phi0, h)
+    surf = 0.5 * (p.gamma_surf * 3.0 * SQ2 * p.eps / 4.0 + p.theta) * (g1 + g2)
+    stab = -0.5 * tt * (g1 + g2 - 2.0 * gd)
+    lin = 0.5 * p.gamma_surf * 3.0 * SQ2 * p.beta / (4.0 * p.eps) * (
+        ip(phi1, phi1, h) + ip(2.0 * phi1 - phi0, 2.0 * phi1 - phi0, h))
+    sv = 0.5 * p.gamma_surf * 1.5 * SQ2 * (V1 ** 2 + (2.0 * V1 - V0) ** 2)
+    su = 0.5 * p.gamma_area * (U1 ** 2 + (2.0 * U1 - U0) ** 2)
+    sw = 0.5 * p.gamma_bend * 3.0 * SQ2 / (8.0 * p.eps) * (W1 ** 2 + (2.0 * W1 - W0) ** 2)
+    sz = 0.5 * (Z1 ** 2 + (2.0 * Z1 - Z0) ** 2)
+    parts = dict(bend=bend, surf=surf, stab=stab, lin=lin, V=sv, U=su, W=sw, Z=sz,
+                 acc=-d_acc)
+    parts["E"] = float(sum(parts.values()))
+    return parts
+
+
+def energy(st: State) -> Dict:
+    """E^{n,n-1}_mod of the current state (levels n and n-1)."""
+    if st.phi_prev is None:
+        raise ValueError("energy needs two time levels")
+    return modified_energy(st.phi, st.phi_prev, st.sav, st.sav_prev, st.d_acc, st.p)
+
+
+def dissipation_terms(phi2, phi1, phi0, sav2, sav1, sav0, psi2, psis, phis, p: Params):
+    """K^n and the right-hand side quantities of Thm. 3.1 for step n -> n+1.
+
+    Level indices: 2 = n+1, 1 = n, 0 = n-1. Returns K^n, ||mu^{n+1}||^2 and
+    ||c^{n+1} + d^{n+1}/2||^2, with mu^{n+1} from eq. (AC_BDF2) and
+    nu^{n+1} = Z^{n+1} P* from eq. (nu_BDF2).
+    """
+    h = p.h
+    tt = theta_tilde(p)
+    sec = phi2 - 2.0 * phi1 + phi0
+    lsec = lap(sec, h)
+    gsec = grad_norm_sq(sec, h)
+    Kn = (0.5 * p.gamma_bend * 3.0 * SQ2 * p.eps / 8.0 * ip(lsec, lsec, h)
+          + 0.5 * (p.gamma_surf * 3.0 * SQ2 * p.eps / 4.0 + p.theta) * gsec
+          + 1.5 * tt * gsec
+          + 0.5 * p.gamma_surf * 3.0 * SQ2 * p.beta / (4.0 * p.eps) * ip(sec, sec, h))
+    ssec = np.asarray(sav2) - 2.0 * np.asarray(sav1) + np.asarray(sav0)
+    Kn += 0.5 * p.gamma_surf * 1.5 * SQ2 * ssec[0] ** 2
+    Kn += 0.5 * p.gamma_area * ssec[1] ** 2
+    Kn += 0.5 * p.gamma_bend * 3.0 * SQ2 / (8.0 * p.eps) * ssec[2] ** 2
+    Kn += 0.5 * ssec[3] ** 2
+    mu = -(3.0 * phi2 - 4.0 * phi1 + phi0) / (2.0 * p.dt * p.M_phi)
+    mu_sq = ip(mu, mu, h)
+    P = basis_P(phis, psis, p)
+    nu = sav2[3] * P
+    mx, my = face_mobility(phis, p)
+    cx = np.sqrt(mx) * Dx(nu, h)
+    cy = np.sqrt(my) * Dy(nu, h)
+    dxf, dyf = d_faces(psi2, psis, phis, p)
+    ex, ey = cx + 0.5 * dxf, cy + 0.5 * dyf
+    cd_sq = face_ip(ex, ey, ex, ey, h)
+    return Kn, mu_sq, cd_sq
+
+
+def mass(st: State):
+    """(h^2 sum psi, h^2 sum phi); only psi is conserved (App. D)."""
+    return integral(st.psi, st.p.h), integral(st.phi, st.p.h)
