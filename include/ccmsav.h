@@ -1,0 +1,159 @@
+/*
+ * ccmsav.h - C ABI of the CC-MSAV vesicle time step on MI355X (gfx950).
+ *
+ * Zhang, Li, Lowengrub & Wise, "An Efficient Constant-Coefficient MSAV Scheme
+ * for Computing Vesicle Growth and Shrinkage", arXiv 2601.10057.
+ *
+ * The library advances the coupled Allen-Cahn / variable-mobility
+ * Cahn-Hilliard vesicle model (Sec. 2.1) in its MSAV form (Sec. 2.2) with the
+ * constant-coefficient BDF2 scheme of Sec. 3.2, eqs. (AC_BDF2)-(Z_BDF2), on a
+ * cell-centred grid with homogeneous Neumann boundaries (Sec. 3.4, App. D).
+ * Each step is solved by the decoupled procedure of App. B (the 5x5 reduced
+ * system) with the DCT fast direct solver of App. C; the very first step uses
+ * the BDF1 variant of the App. B remark, since BDF2 needs two levels.
+ *
+ * Conventions for every entry point:
+ *  - Scalars are double. Fields are row-major [ny][nx] arrays of double, x
+ *    fastest, one value per cell centre ((i + 1/2) h, (j + 1/2) h), no ghosts.
+ *  - A field pointer may be host or device memory (copies use
+ *    hipMemcpyDefault). The library copies inputs; the caller keeps ownership.
+ *  - Every function returns a status (ccmsav_status). On CCMSAV_EINVAL or
+ *    CCMSAV_EUNSUPPORTED nothing was changed. Errors detected on the device
+ *    are sticky and reported by the next call that synchronises (energy,
+ *    mass, get_fields, get_savs, sync). No C++ exception crosses the ABI.
+ *  - A context is bound to the stream given at init; all device work of the
+ *    context is ordered on that stream. Calls on one context are not
+ *    thread-safe.
+ */
+#ifndef CCMSAV_H
+#define CCMSAV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ccmsav_ctx ccmsav_ctx; /* opaque, owned by the library */
+
+typedef enum {
+  CCMSAV_OK = 0,
+  CCMSAV_EINVAL = -1,       /* invalid argument or parameter */
+  CCMSAV_ENOMEM = -2,       /* workspace too small or allocation failed */
+  CCMSAV_EHIP = -3,         /* a HIP runtime call failed */
+  CCMSAV_EDOMAIN = -4,      /* SAV normaliser <= 0, singular 5x5 system, or a
+                               face mobility M_psi <= 0 (energy undefined) */
+  CCMSAV_ENONFINITE = -5,   /* NaN or Inf in the state or the SAVs */
+  CCMSAV_EUNSUPPORTED = -6  /* grid size or precision mode not provided */
+} ccmsav_status;
+
+typedef enum {
+  CCMSAV_FP64 = 0,          /* all arithmetic in FP64 */
+  CCMSAV_MIXED = 1          /* FP32 transforms of FP64-formed right-hand sides;
+                               FP64 state, SAVs, inner-product sums and 5x5 */
+} ccmsav_precision;
+
+/*
+ * Problem parameters (paper notation):
+ *  nx, ny       grid cells per direction, each a power of two in [16, 8192]
+ *  h            cell size (L_x = nx h, L_y = ny h), > 0
+ *  dt           time step, > 0
+ *  eps          interface width epsilon, > 0                         (Sec. 2.1)
+ *  M_phi, M0    Allen-Cahn mobility > 0; M_psi(phi) = 1 - M0 (phi^2 - 1)^2,
+ *               0 <= M0 < 1                                           (Sec. 2.1)
+ *  gamma_surf, gamma_bend, gamma_area   surface, bending, arc-length weights >= 0
+ *  A            arc-length target of F^area; NaN selects the discrete surface
+ *               energy of phi0 (so U^0 = 0)
+ *  gamma_in, gamma_out, psi_in, psi_out, beta_in, beta_out
+ *               osmotic energies f^in/out = gamma/2 (psi - psi_eq)^2 + beta
+ *  theta        Allen-Cahn stabilisation >= 0                         (Sec. 3.2)
+ *  lam          Cahn-Hilliard stabilisation lambda >= 0               (Sec. 3.2)
+ *  beta         linear SAV splitting constant                         (Sec. 2.2)
+ *  precision    a ccmsav_precision value
+ *  flags        reserved, must be 0
+ */
+typedef struct {
+  int32_t nx, ny;
+  double h, dt, eps;
+  double M_phi, M0;
+  double gamma_surf, gamma_bend, gamma_area, A;
+  double gamma_in, gamma_out, psi_in, psi_out, beta_in, beta_out;
+  double theta, lam, beta;
+  int32_t precision, flags;
+} ccmsav_params;
+
+/* Device workspace bytes a context needs for these parameters (0 if the
+ * parameters are invalid or unsupported). */
+size_t ccmsav_workspace_bytes(const ccmsav_params* p);
+
+/*
+ * Create a context at level n = 0 from phi0, psi0 (nx*ny doubles each, host or
+ * device) and compute the initial SAVs V^0, U^0, W^0, Z^0 (eq. msav_ic).
+ * workspace: caller-owned device memory of ws_bytes >= ccmsav_workspace_bytes(p)
+ *            that must outlive the context, or NULL to let the library allocate
+ *            (and free at destroy).
+ * hip_stream: a hipStream_t (NULL = default stream).
+ * Returns EINVAL (bad pointer or parameter), EUNSUPPORTED (size / precision),
+ * ENOMEM, EHIP, or a device status of the initial reduction (ENONFINITE,
+ * EDOMAIN when a SAV normaliser vanishes).
+ */
+int ccmsav_init(ccmsav_ctx** out, const ccmsav_params* p, const double* phi0, const double* psi0,
+                void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Enqueue nsteps >= 0 time steps (Algorithm 1 of App. B per step; BDF1 for the
+ * step from level 0). Asynchronous: returns once the work is on the stream.
+ */
+int ccmsav_step(ccmsav_ctx* c, int32_t nsteps);
+
+/*
+ * Modified discrete energy E^{n,n-1}_mod of eq. (modified_discrete_energy) at
+ * the current level n >= 1, with discrete norms of App. D and the accumulated
+ * -sum_{j=2}^{n} (dt/2) ||d^j||^2 (Sec. 3.3). parts (nullable) receives 9
+ * values: bending, surface+theta, -theta_tilde term, beta term, V, U, W, Z
+ * terms, and minus the accumulated sum. Synchronises the stream.
+ * EINVAL if n == 0.
+ */
+int ccmsav_energy(ccmsav_ctx* c, double* E_mod, double* parts);
+
+/* h^2 sum psi^n (conserved, App. D) and h^2 sum phi^n. Either pointer may be
+ * NULL. Synchronises the stream. */
+int ccmsav_mass(ccmsav_ctx* c, double* mass_psi, double* mass_phi);
+
+/* Copy phi^n and psi^n (nx*ny doubles each, host or device; either may be
+ * NULL). Synchronises the stream. */
+int ccmsav_get_fields(ccmsav_ctx* c, double* phi, double* psi);
+
+/* out8 = {V, U, W, Z} at level n followed by level n-1 (level 0 repeats n). */
+int ccmsav_get_savs(ccmsav_ctx* c, double out8[8]);
+
+/* Current level n (number of steps taken). */
+int64_t ccmsav_level(const ccmsav_ctx* c);
+
+/* Wait for the stream and report sticky device errors. */
+int ccmsav_sync(ccmsav_ctx* c);
+
+/*
+ * Fast direct solver of App. C on its own: out_chi = chi^{-1} rhs and
+ * out_zeta = zeta^{-1} rhs with the BDF2 operators of App. B Step 3,
+ *   chi  = C1 - C2 Delta_h + C3 Delta_h^2, C1 = 3/(2 dt) + M_phi gamma_surf 3 sqrt2 beta/(4 eps),
+ *          C2 = M_phi (gamma_surf 3 sqrt2 eps/4 + theta), C3 = M_phi gamma_bend 3 sqrt2 eps/8,
+ *   zeta = 3/(2 dt) - lam Delta_h,
+ * for the context's parameters. rhs, out_chi, out_zeta: nx*ny doubles in
+ * device memory (NULL outputs are skipped). Uses the context's work buffers
+ * (not its state); ordered on the context's stream.
+ */
+int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, double* out_zeta);
+
+/* Release the context (and the workspace if the library allocated it). */
+int ccmsav_destroy(ccmsav_ctx* c);
+
+/* Static description of a status code. */
+const char* ccmsav_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CCMSAV_H */

@@ -1,0 +1,231 @@
+"""ctypes binding of ``libccmsav.so`` (the C ABI of ``include/ccmsav.h``).
+
+Argument marshalling only: every step of the scheme runs in the HIP library.
+Fields may be numpy arrays (host memory) or torch tensors (device memory);
+PyTorch supplies device memory and the stream, nothing else. If the shared
+library is missing this module raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libccmsav.so")
+
+FP64 = 0
+MIXED = 1
+PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDOMAIN",
+          -5: "ENONFINITE", -6: "EUNSUPPORTED"}
+
+EXPORTED = (
+    "ccmsav_workspace_bytes", "ccmsav_init", "ccmsav_step", "ccmsav_energy",
+    "ccmsav_mass", "ccmsav_get_fields", "ccmsav_get_savs", "ccmsav_level",
+    "ccmsav_sync", "ccmsav_elliptic_solve", "ccmsav_destroy", "ccmsav_strerror",
+)
+
+
+class Params(ctypes.Structure):
+    """Mirror of ``ccmsav_params``."""
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("h", ctypes.c_double), ("dt", ctypes.c_double), ("eps", ctypes.c_double),
+        ("M_phi", ctypes.c_double), ("M0", ctypes.c_double),
+        ("gamma_surf", ctypes.c_double), ("gamma_bend", ctypes.c_double),
+        ("gamma_area", ctypes.c_double), ("A", ctypes.c_double),
+        ("gamma_in", ctypes.c_double), ("gamma_out", ctypes.c_double),
+        ("psi_in", ctypes.c_double), ("psi_out", ctypes.c_double),
+        ("beta_in", ctypes.c_double), ("beta_out", ctypes.c_double),
+        ("theta", ctypes.c_double), ("lam", ctypes.c_double), ("beta", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("flags", ctypes.c_int32),
+    ]
+
+    @classmethod
+    def from_dict(cls, d: Dict, precision=FP64, flags=0) -> "Params":
+        p = cls()
+        for name, _ in cls._fields_:
+            if name in ("precision", "flags"):
+                continue
+            setattr(p, name, d[name])
+        p.precision = PRECISIONS.get(precision, precision) if isinstance(precision, str) else precision
+        p.flags = flags
+        return p
+
+
+class CcmsavError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+        super().__init__(f"{what}: {self.name} ({code}): {strerror(code)}")
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the in-tree library, or raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with "
+                          "`python -m paper_2601_10057_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+    lib.ccmsav_workspace_bytes.argtypes = [ctypes.POINTER(Params)]
+    lib.ccmsav_workspace_bytes.restype = ctypes.c_size_t
+    lib.ccmsav_init.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(Params), vp, vp, vp,
+                                ctypes.c_size_t, vp]
+    lib.ccmsav_step.argtypes = [vp, ctypes.c_int32]
+    lib.ccmsav_energy.argtypes = [vp, dp, dp]
+    lib.ccmsav_mass.argtypes = [vp, dp, dp]
+    lib.ccmsav_get_fields.argtypes = [vp, vp, vp]
+    lib.ccmsav_get_savs.argtypes = [vp, dp]
+    lib.ccmsav_level.argtypes = [vp]
+    lib.ccmsav_level.restype = ctypes.c_int64
+    lib.ccmsav_sync.argtypes = [vp]
+    lib.ccmsav_elliptic_solve.argtypes = [vp, vp, vp, vp]
+    lib.ccmsav_destroy.argtypes = [vp]
+    lib.ccmsav_strerror.argtypes = [ctypes.c_int]
+    lib.ccmsav_strerror.restype = ctypes.c_char_p
+    for fn in ("ccmsav_init", "ccmsav_step", "ccmsav_energy", "ccmsav_mass",
+               "ccmsav_get_fields", "ccmsav_get_savs", "ccmsav_sync",
+               "ccmsav_elliptic_solve", "ccmsav_destroy"):
+        getattr(lib, fn).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().ccmsav_strerror(code).decode()
+
+
+def workspace_bytes(params: Dict, precision=FP64) -> int:
+    p = Params.from_dict(params, precision)
+    return int(load().ccmsav_workspace_bytes(ctypes.byref(p)))
+
+
+def _ptr(x) -> Optional[int]:
+    """Address of a numpy array or torch tensor (None passes through)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        if x.dtype != np.float64 or not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("fields must be C-contiguous float64 arrays")
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        import torch
+        if x.dtype != torch.float64 or not x.is_contiguous():
+            raise ValueError("fields must be contiguous float64 tensors")
+        return x.data_ptr()
+    raise TypeError(f"unsupported field type {type(x)}")
+
+
+def _check(code: int, what: str):
+    if code != 0:
+        raise CcmsavError(code, what)
+
+
+class Context:
+    """One CC-MSAV simulation on the GPU, bound to a HIP stream."""
+
+    def __init__(self, params: Dict, phi0, psi0, precision="fp64", workspace=None,
+                 stream=None, torch_workspace: bool = True):
+        lib = load()
+        self.params = dict(params)
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
+        self._p = Params.from_dict(params, self.precision)
+        self.nx, self.ny = int(params["nx"]), int(params["ny"])
+        nbytes = int(lib.ccmsav_workspace_bytes(ctypes.byref(self._p)))
+        self._ws = workspace
+        if self._ws is None and torch_workspace and nbytes:
+            import torch
+            if torch.cuda.is_available():
+                self._ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        if stream is None:
+            try:
+                import torch
+                stream = torch.cuda.current_stream().cuda_stream if torch.cuda.is_available() else None
+            except ImportError:
+                stream = None
+        self._stream = stream
+        self._keep = (phi0, psi0)
+        h = ctypes.c_void_p()
+        ws_ptr = self._ws.data_ptr() if self._ws is not None else None
+        ws_len = nbytes if self._ws is not None else 0
+        code = lib.ccmsav_init(ctypes.byref(h), ctypes.byref(self._p), _ptr(phi0), _ptr(psi0),
+                               ws_ptr, ws_len, stream)
+        _check(code, "ccmsav_init")
+        self._h = h
+        self._keep = None
+
+    # -- stepping and diagnostics ------------------------------------------
+    def step(self, nsteps: int = 1):
+        _check(load().ccmsav_step(self._h, int(nsteps)), "ccmsav_step")
+
+    def sync(self):
+        _check(load().ccmsav_sync(self._h), "ccmsav_sync")
+
+    @property
+    def level(self) -> int:
+        return int(load().ccmsav_level(self._h))
+
+    def energy(self, parts: bool = False):
+        e = ctypes.c_double()
+        buf = (ctypes.c_double * 9)()
+        _check(load().ccmsav_energy(self._h, ctypes.byref(e), buf), "ccmsav_energy")
+        return (e.value, list(buf)) if parts else e.value
+
+    def mass(self):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(load().ccmsav_mass(self._h, ctypes.byref(a), ctypes.byref(b)), "ccmsav_mass")
+        return a.value, b.value
+
+    def fields(self):
+        """(phi^n, psi^n) copied to host numpy arrays."""
+        phi = np.empty((self.ny, self.nx))
+        psi = np.empty((self.ny, self.nx))
+        _check(load().ccmsav_get_fields(self._h, phi.ctypes.data, psi.ctypes.data),
+               "ccmsav_get_fields")
+        return phi, psi
+
+    def fields_into(self, phi, psi):
+        _check(load().ccmsav_get_fields(self._h, _ptr(phi), _ptr(psi)), "ccmsav_get_fields")
+
+    def savs(self):
+        """(V, U, W, Z) at level n and at level n-1."""
+        buf = (ctypes.c_double * 8)()
+        _check(load().ccmsav_get_savs(self._h, buf), "ccmsav_get_savs")
+        v = np.array(list(buf))
+        return v[:4], v[4:]
+
+    def elliptic_solve(self, rhs, out_chi, out_zeta):
+        """chi^{-1} rhs and zeta^{-1} rhs (device tensors) with the BDF2 operators."""
+        _check(load().ccmsav_elliptic_solve(self._h, _ptr(rhs), _ptr(out_chi), _ptr(out_zeta)),
+               "ccmsav_elliptic_solve")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ccmsav_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def mcell_steps(n_cells: int, steps: int, seconds: float) -> float:
+    return n_cells * steps / seconds / 1e6 if seconds > 0 else math.nan

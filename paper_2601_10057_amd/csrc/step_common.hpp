@@ -1,0 +1,91 @@
+// Shared definitions between the host runtime and the step kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ccm {
+
+// Partial sums written by the fused stencil + row-DCT pass, one row each.
+enum P1Sum {
+  P1_RS = 0,      // sum (phi*^2 - 1 - beta)^2 / (4 eps)          -> r_S^2 / h^2
+  P1_RW,          // sum 6 phi*^2 |grad phi*|^2 + (phi*^3-phi*)^2/eps^2 -> r_W^2 / h^2
+  P1_RZ,          // sum (1 + p) f_in + (1 - p) f_out             -> r_Z^2 / h^2
+  P1_ES,          // sum S~ e_phi, e_phi = e0 phi^n + e1 phi^{n-1}
+  P1_EH,
+  P1_EQ,
+  P1_EK,
+  P1_EP,          // sum P~ e_psi
+  P1_DLAG,        // sum over faces (D delta psi)^2 / M_face of the previous step
+  P1_MOBNEG,      // number of faces with M_psi(A phi*) <= 0
+  P1_NSUM
+};
+
+// Partial sums of the column pass (Parseval inner products with 1/sigma, 1/tau).
+enum P2Sum {
+  P2_FS = 0, P2_FH, P2_FQ, P2_FK,            // f_lin with S~, H, Q~, K~
+  P2_SS, P2_SH, P2_SQ, P2_SK,
+  P2_HH, P2_HQ, P2_HK,
+  P2_QQ, P2_QK,
+  P2_KK,
+  P2_PG, P2_PL,                              // P~ with g_lin, L~ (over tau)
+  P2_NSUM
+};
+
+// Energy / mass reduction partials, one row each.
+enum ESum {
+  E_LAP1 = 0,     // ||Lap phi^n||^2 / h^2
+  E_LAP2,         // ||Lap (2 phi^n - phi^{n-1})||^2 / h^2
+  E_G1,           // face sums of (D phi^n)^2
+  E_G2,           // (D (2 phi^n - phi^{n-1}))^2
+  E_GD,           // (D (phi^n - phi^{n-1}))^2
+  E_P1,           // (phi^n)^2
+  E_P2,           // (2 phi^n - phi^{n-1})^2
+  E_D,            // (D delta psi)^2 / M_face for the last step
+  E_MPSI,         // psi^n
+  E_MPHI,         // phi^n
+  E_NSUM
+};
+
+// Intermediate field slots of the forward transforms.
+enum Mid { M_F = 0, M_S, M_H, M_Q, M_K, M_G, M_L, M_P, M_NFIELD };
+
+// Sticky error bits in the device scalar block.
+enum ErrBits {
+  ERR_NONFINITE = 1,
+  ERR_NORM = 2,        // a SAV normaliser r^2 <= tiny
+  ERR_PIVOT = 4,       // singular 5x5 system
+  ERR_MOBILITY = 8,    // a face mobility <= 0 (energy undefined)
+};
+
+// Device-resident scalar state. Everything the time loop needs lives here so
+// that a step never waits on the host.
+struct DevScalars {
+  double sav[3][4];      // V, U, W, Z of the three most recent levels (slot = level % 3)
+  double coef[8];        // spectral combination: f, S~, H, Q~, K~ (chi); g, L~ (zeta)
+  double acc;            // sum_{j>=2} (dt/2) ||d^j||^2, up to the level before current
+  double diag[40];       // last step: s (4), norms r_S r_W r_Z, x (5), M (25), b... see runtime
+  double energy[12];     // last energy query: E, then parts
+  double totals[16];     // last reduction totals
+  int err;
+  int pad[3];
+};
+
+// Constants of one step, passed by value to the kernels.
+struct StepConst {
+  double h, inv_h, inv_h2, h2;
+  double eps, beta, M_phi, M0;
+  double gamma_in, gamma_out, psi_in, psi_out, beta_in, beta_out;
+  double lam, theta_t;
+  double x0, x1;         // phi* = x0 phi^n + x1 phi^{n-1}
+  double a0, a1;         // a^n = a0 phi^n + a1 phi^{n-1}  (already divided by dt)
+  double e0, e1;         // e_phi = e0 phi^n + e1 phi^{n-1} (SAV bracket weights)
+  double c0, c1;         // s = c0 SAV^n + c1 SAV^{n-1} + h^2 sum F e
+  double alpha;          // 3/(2 dt) or 1/dt
+  double C1, C2, C3;     // chi spectrum sigma = C1 + C2 L + C3 L^2
+  double cgs, cga, cgb, cgo;
+  double half_dt;
+  int lag_d;             // accumulate ||d^n||^2 of the previous (BDF2) step
+  int slot_n, slot_m, slot_new;   // SAV ring slots of levels n, n-1, n+1
+};
+
+}  // namespace ccm

@@ -1,0 +1,630 @@
+// Kernels of one CC-MSAV-BDF2 step (Sec. 3.2, solved as in App. B and App. C).
+//
+// Pipeline of one step (fields are row-major [ny][nx], x fastest):
+//   P1  k_stencil_rowdct : per row j, the explicit stencil terms of eqs.
+//       (AC_BDF2)-(Z_BDF2) at phi* = x0 phi^n + x1 phi^{n-1}: the basis numerators
+//       S~, H, Q~, K~, P~ (Sec. 2.2 with the discrete forms of Sec. 3.4.1),
+//       L~ = div(M_psi(A phi*) grad P~), f_lin, g_lin, plus the SAV partial sums;
+//       then the orthonormal DCT-II along x of the 8 fields.
+//   P2  k_col_gram       : per strip of two columns, DCT-II along y and the
+//       Parseval inner products (F_i, chi^{-1} F_j), (P, zeta^{-1} g), (P, zeta^{-1} L).
+//   S   k_solve          : reduces the partials, assembles and solves the 5x5
+//       system of App. B Step 4, updates the SAVs, and emits the spectral
+//       combination coefficients (all on the device).
+//   P3  k_col_solve      : per strip, combines the x-transformed fields into the
+//       right-hand sides of chi phi^{n+1} and zeta psi^{n+1}, DCT-II along y,
+//       divides by sigma / tau, DCT-III along y.
+//   P4  k_row_idct       : per row, DCT-III along x of both results -> phi^{n+1},
+//       psi^{n+1}.
+// The intermediate fields use a strip-major layout: element (k, j) of a field
+// lives at ((k / 2) * ny + j) * 2 + (k % 2), so that a column pair is one
+// contiguous complex line.
+#pragma once
+#include "fft.hpp"
+#include "step_common.hpp"
+
+namespace ccm {
+
+constexpr int line_threads(int n) { return n / 4 < 64 ? 64 : (n / 4 > 1024 ? 1024 : n / 4); }
+
+// Consecutive workgroups are dispatched round-robin over the 8 XCDs; give each
+// XCD a contiguous range of lines so that neighbouring rows share an L2.
+__device__ __forceinline__ int xcd_remap(int b, int g) {
+  if ((g & 7) != 0) return b;
+  return (b & 7) * (g >> 3) + (b >> 3);
+}
+
+__device__ __forceinline__ size_t mid_index(int k, int j, int ny) {
+  return ((size_t)(k >> 1) * ny + j) * 2 + (k & 1);
+}
+
+// Sum NV doubles over the block in a fixed order; the totals land in red[0..NV).
+template <int NV, int NTHR>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red, int tid) {
+  constexpr int NW = (NTHR + 63) / 64;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] += __shfl_xor(v[q], off, 64);
+  }
+  const int lane = tid & 63, w = tid >> 6;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) red[NV + w * NV + q] = v[q];
+  }
+  __syncthreads();
+  if (tid < NV) {
+    double s = 0.0;
+    for (int i = 0; i < NW; ++i) s += red[NV + i * NV + tid];
+    red[tid] = s;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double mobility(double phi, double M0) {
+  const double t = phi * phi - 1.0;
+  return 1.0 - M0 * t * t;
+}
+
+// ---------------------------------------------------------------------------
+// P1: fused stencil terms + row DCT-II of the eight right-hand-side fields.
+// ---------------------------------------------------------------------------
+template <typename TM, int NX>
+__global__ void __launch_bounds__(line_threads(NX))
+k_stencil_rowdct(const double* __restrict__ phn, const double* __restrict__ phm,
+                 const double* __restrict__ phmm, const double* __restrict__ psn,
+                 const double* __restrict__ psm, const double* __restrict__ psmm,
+                 TM* __restrict__ mid, double* __restrict__ part, int ny, StepConst c) {
+  constexpr int NTHR = line_threads(NX);
+  constexpr int CPT = (NX + NTHR - 1) / NTHR;
+  __shared__ cpx<TM> line[NX];
+  __shared__ cpx<TM> rtab[Roots<TM, NX>::SIZE];
+  __shared__ double red[P1_NSUM * (NTHR / 64 + 1)];
+  const int tid = threadIdx.x;
+  const int j = xcd_remap(blockIdx.x, gridDim.x);
+  const size_t FS = (size_t)NX * ny;
+  Roots<TM, NX> rt;
+  rt.init(rtab, tid, NTHR);
+  const int jn = min(j + 1, ny - 1), js = max(j - 1, 0);
+  const double k32 = 0.75 * 1.4142135623730950488;   // 3 sqrt(2) / 4
+  const double half_pi = 1.5707963267948966192;
+  const double ieps = 1.0 / c.eps;
+
+  double F[M_NFIELD][CPT];
+  double sums[P1_NSUM];
+#pragma unroll
+  for (int q = 0; q < P1_NSUM; ++q) sums[q] = 0.0;
+
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int i = tid + q * NTHR;
+    if (i < NX) {
+      const int ie = min(i + 1, NX - 1), iw = max(i - 1, 0);
+      const size_t oc = (size_t)j * NX + i, oe = (size_t)j * NX + ie, ow = (size_t)j * NX + iw;
+      const size_t on = (size_t)jn * NX + i, os = (size_t)js * NX + i;
+      const double phn_c = phn[oc], phm_c = phm[oc], psn_c = psn[oc], psm_c = psm[oc];
+      const double pc = c.x0 * phn_c + c.x1 * phm_c;
+      const double pe = c.x0 * phn[oe] + c.x1 * phm[oe];
+      const double pw = c.x0 * phn[ow] + c.x1 * phm[ow];
+      const double pn = c.x0 * phn[on] + c.x1 * phm[on];
+      const double ps = c.x0 * phn[os] + c.x1 * phm[os];
+      const double qc = c.x0 * psn_c + c.x1 * psm_c;
+      const double qe = c.x0 * psn[oe] + c.x1 * psm[oe];
+      const double qw = c.x0 * psn[ow] + c.x1 * psm[ow];
+      const double qn = c.x0 * psn[on] + c.x1 * psm[on];
+      const double qs = c.x0 * psn[os] + c.x1 * psm[os];
+
+      // face gradients of phi*, Laplacian, cell |grad phi*|^2, div(A(phi*^2) D phi*)
+      const double gxe = (pe - pc) * c.inv_h, gxw = (pc - pw) * c.inv_h;
+      const double gyn = (pn - pc) * c.inv_h, gys = (pc - ps) * c.inv_h;
+      const double lap_p = (gxe - gxw + gyn - gys) * c.inv_h;
+      const double grad2 = 0.5 * (gxe * gxe + gxw * gxw + gyn * gyn + gys * gys);
+      const double pc2 = pc * pc;
+      const double div_a = 0.5 * ((pc2 + pe * pe) * gxe - (pw * pw + pc2) * gxw +
+                                  (pc2 + pn * pn) * gyn - (ps * ps + pc2) * gys) * c.inv_h;
+      const double cubic = pc2 * pc - pc;                      // phi^3 - phi
+      const double St = pc * (pc2 - 1.0 - c.beta) * 0.5 * ieps;
+      const double Hf = k32 * (cubic * ieps - c.eps * lap_p);
+      const double Qt = 6.0 * (pc * grad2 - div_a) + cubic * (3.0 * pc2 - 1.0) * ieps * ieps;
+
+      // osmotic terms at the centre and the four neighbours
+      double sp, cp;
+      sincospi(0.5 * pc, &sp, &cp);
+      const double din = qc - c.psi_in, dout = qc - c.psi_out;
+      const double fin = 0.5 * c.gamma_in * din * din + c.beta_in;
+      const double fout = 0.5 * c.gamma_out * dout * dout + c.beta_out;
+      const double Kt = 0.5 * half_pi * cp * (fin - fout);
+      auto ptilde = [&](double ph, double ps_, double pp) {
+        return 0.5 * (c.gamma_in * (1.0 + pp) * (ps_ - c.psi_in) +
+                      c.gamma_out * (1.0 - pp) * (ps_ - c.psi_out));
+      };
+      const double Pc = ptilde(pc, qc, sp);
+      const double Pe = ptilde(pe, qe, sinpi(0.5 * pe));
+      const double Pw = ptilde(pw, qw, sinpi(0.5 * pw));
+      const double Pn = ptilde(pn, qn, sinpi(0.5 * pn));
+      const double Ps = ptilde(ps, qs, sinpi(0.5 * ps));
+      const double Me = mobility(0.5 * (pc + pe), c.M0), Mw = mobility(0.5 * (pw + pc), c.M0);
+      const double Mn = mobility(0.5 * (pc + pn), c.M0), Ms = mobility(0.5 * (ps + pc), c.M0);
+      const double Lt = (Me * (Pe - Pc) - Mw * (Pc - Pw) + Mn * (Pn - Pc) - Ms * (Pc - Ps)) * c.inv_h2;
+
+      const double lap_q = (qe + qw + qn + qs - 4.0 * qc) * c.inv_h2;
+      F[M_F][q] = c.a0 * phn_c + c.a1 * phm_c - c.M_phi * c.theta_t * lap_p;
+      F[M_G][q] = c.a0 * psn_c + c.a1 * psm_c - c.lam * lap_q;
+      F[M_S][q] = St;
+      F[M_H][q] = Hf;
+      F[M_Q][q] = Qt;
+      F[M_K][q] = Kt;
+      F[M_L][q] = Lt;
+      F[M_P][q] = Pc;
+
+      const double vq = pc2 - 1.0 - c.beta;
+      sums[P1_RS] += vq * vq * 0.25 * ieps;
+      sums[P1_RW] += 6.0 * pc2 * grad2 + cubic * cubic * ieps * ieps;
+      sums[P1_RZ] += (1.0 + sp) * fin + (1.0 - sp) * fout;
+      const double eph = c.e0 * phn_c + c.e1 * phm_c;
+      const double eps_ = c.e0 * psn_c + c.e1 * psm_c;
+      sums[P1_ES] += St * eph;
+      sums[P1_EH] += Hf * eph;
+      sums[P1_EQ] += Qt * eph;
+      sums[P1_EK] += Kt * eph;
+      sums[P1_EP] += Pc * eps_;
+      if (i < NX - 1 && !(Me > 0.0)) sums[P1_MOBNEG] += 1.0;
+      if (j < ny - 1 && !(Mn > 0.0)) sums[P1_MOBNEG] += 1.0;
+      if (c.lag_d) {
+        // ||d^n||^2 of the previous step: delta psi = psi^n - (2 psi^{n-1} - psi^{n-2}),
+        // mobility at the face average of 2 phi^{n-1} - phi^{n-2}.
+        const double dc = psn_c - 2.0 * psm_c + psmm[oc];
+        const double fc = 2.0 * phm_c - phmm[oc];
+        if (i < NX - 1) {
+          const double de = psn[oe] - 2.0 * psm[oe] + psmm[oe];
+          const double fe = 2.0 * phm[oe] - phmm[oe];
+          const double g = de - dc;
+          sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (fc + fe), c.M0);
+        }
+        if (j < ny - 1) {
+          const double dn = psn[on] - 2.0 * psm[on] + psmm[on];
+          const double fn = 2.0 * phm[on] - phmm[on];
+          const double g = dn - dc;
+          sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (fc + fn), c.M0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < M_NFIELD; ++f) F[f][q] = 0.0;
+    }
+  }
+
+  // Row DCT-II of the eight fields, two per complex FFT.
+  constexpr int PA[4] = {M_F, M_S, M_Q, M_L};
+  constexpr int PB[4] = {M_G, M_H, M_K, M_P};
+#pragma unroll
+  for (int pr = 0; pr < 4; ++pr) {
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int i = tid + q * NTHR;
+      if (i < NX) line[makhoul_slot<NX>(i)] = {(TM)F[PA[pr]][q], (TM)F[PB[pr]][q]};
+    }
+    __syncthreads();
+    fft_lines<TM, NX, 1, NTHR>(line, rt, tid);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int k = tid + q * NTHR;
+      if (k < NX) {
+        TM A, B;
+        dct2_post<TM, NX>(line, rt, k, A, B);
+        const size_t o = mid_index(k, j, ny);
+        mid[PA[pr] * FS + o] = A;
+        mid[PB[pr] * FS + o] = B;
+      }
+    }
+    __syncthreads();
+  }
+  block_sum<P1_NSUM, NTHR>(sums, red, tid);
+  if (tid < P1_NSUM) part[(size_t)j * P1_NSUM + tid] = red[tid];
+}
+
+// ---------------------------------------------------------------------------
+// P2: column DCT-II of the eight fields and the spectral Gram sums.
+// ---------------------------------------------------------------------------
+template <typename TM, int NY, int KPT, int NTHR>
+__device__ __forceinline__ void column_dct2(const cpx<TM>* __restrict__ src, cpx<TM>* line,
+                                            const Roots<TM, NY>& rt, int tid, TM (&A)[KPT],
+                                            TM (&B)[KPT]) {
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int jj = tid + q * NTHR;
+    if (jj < NY) line[makhoul_slot<NY>(jj)] = src[jj];
+  }
+  __syncthreads();
+  fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = tid + q * NTHR;
+    if (k < NY) {
+      dct2_post<TM, NY>(line, rt, k, A[q], B[q]);
+    } else {
+      A[q] = 0; B[q] = 0;
+    }
+  }
+  __syncthreads();
+}
+
+template <typename TM, int NY>
+__global__ void __launch_bounds__(line_threads(NY))
+k_col_gram(const TM* __restrict__ mid, const double* __restrict__ lamx,
+           const double* __restrict__ lamy, double* __restrict__ part, int nx, StepConst c) {
+  constexpr int NTHR = line_threads(NY);
+  constexpr int KPT = (NY + NTHR - 1) / NTHR;
+  __shared__ cpx<TM> line[NY];
+  __shared__ cpx<TM> rtab[Roots<TM, NY>::SIZE];
+  __shared__ double red[P2_NSUM * (NTHR / 64 + 1)];
+  const int tid = threadIdx.x;
+  const int s = xcd_remap(blockIdx.x, gridDim.x);
+  const size_t FS = (size_t)nx * NY;
+  Roots<TM, NY> rt;
+  rt.init(rtab, tid, NTHR);
+
+  double isg0[KPT], isg1[KPT], itu0[KPT], itu1[KPT];
+  const double lx0 = lamx[2 * s], lx1 = lamx[2 * s + 1];
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = tid + q * NTHR;
+    const double ly = (k < NY) ? lamy[k] : 0.0;
+    const double L0 = lx0 + ly, L1 = lx1 + ly;
+    isg0[q] = 1.0 / (c.C1 + L0 * (c.C2 + c.C3 * L0));
+    isg1[q] = 1.0 / (c.C1 + L1 * (c.C2 + c.C3 * L1));
+    itu0[q] = 1.0 / (c.alpha + c.lam * L0);
+    itu1[q] = 1.0 / (c.alpha + c.lam * L1);
+  }
+  auto strip = [&](int f) {
+    return reinterpret_cast<const cpx<TM>*>(mid + (size_t)f * FS) + (size_t)s * NY;
+  };
+  double g[P2_NSUM];
+#pragma unroll
+  for (int q = 0; q < P2_NSUM; ++q) g[q] = 0.0;
+
+  // chi group: S~, H, Q~, K~ kept, f_lin consumed on the fly.
+  TM sa[4][KPT], sb[4][KPT];
+  constexpr int CHI[4] = {M_S, M_H, M_Q, M_K};
+  // index of the Gram sum for the pair (a, b), a <= b, of S~, H, Q~, K~
+  constexpr int GIDX[4][4] = {{P2_SS, P2_SH, P2_SQ, P2_SK},
+                              {P2_SH, P2_HH, P2_HQ, P2_HK},
+                              {P2_SQ, P2_HQ, P2_QQ, P2_QK},
+                              {P2_SK, P2_HK, P2_QK, P2_KK}};
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    column_dct2<TM, NY, KPT, NTHR>(strip(CHI[a]), line, rt, tid, sa[a], sb[a]);
+#pragma unroll
+    for (int b = 0; b <= a; ++b) {
+#pragma unroll
+      for (int q = 0; q < KPT; ++q)
+        g[GIDX[b][a]] += (double)sa[a][q] * (double)sa[b][q] * isg0[q] +
+                         (double)sb[a][q] * (double)sb[b][q] * isg1[q];
+    }
+  }
+  {
+    TM fa[KPT], fb[KPT];
+    column_dct2<TM, NY, KPT, NTHR>(strip(M_F), line, rt, tid, fa, fb);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+#pragma unroll
+      for (int q = 0; q < KPT; ++q)
+        g[P2_FS + b] += (double)fa[q] * (double)sa[b][q] * isg0[q] +
+                        (double)fb[q] * (double)sb[b][q] * isg1[q];
+    }
+  }
+  // zeta group: P~ kept, g_lin and L~ consumed on the fly.
+  {
+    TM pa[KPT], pb[KPT], xa[KPT], xb[KPT];
+    column_dct2<TM, NY, KPT, NTHR>(strip(M_P), line, rt, tid, pa, pb);
+    column_dct2<TM, NY, KPT, NTHR>(strip(M_G), line, rt, tid, xa, xb);
+#pragma unroll
+    for (int q = 0; q < KPT; ++q)
+      g[P2_PG] += (double)pa[q] * (double)xa[q] * itu0[q] + (double)pb[q] * (double)xb[q] * itu1[q];
+    column_dct2<TM, NY, KPT, NTHR>(strip(M_L), line, rt, tid, xa, xb);
+#pragma unroll
+    for (int q = 0; q < KPT; ++q)
+      g[P2_PL] += (double)pa[q] * (double)xa[q] * itu0[q] + (double)pb[q] * (double)xb[q] * itu1[q];
+  }
+  block_sum<P2_NSUM, NTHR>(g, red, tid);
+  if (tid < P2_NSUM) part[(size_t)s * P2_NSUM + tid] = red[tid];
+}
+
+// ---------------------------------------------------------------------------
+// Reduction helpers shared by the single-workgroup kernels.
+// ---------------------------------------------------------------------------
+template <int NV, int NTHR>
+__device__ void reduce_rows(const double* __restrict__ part, int nrows, double* red, int tid,
+                            double (&tot)[NV]) {
+  double v[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) v[q] = 0.0;
+  for (int r = tid; r < nrows; r += NTHR) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] += part[(size_t)r * NV + q];
+  }
+  block_sum<NV, NTHR>(v, red, tid);
+#pragma unroll
+  for (int q = 0; q < NV; ++q) tot[q] = red[q];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// S: the 5x5 reduced system of App. B, Step 4, and the SAV update.
+// ---------------------------------------------------------------------------
+constexpr int SOLVE_THREADS = 256;
+
+__global__ void __launch_bounds__(SOLVE_THREADS)
+k_solve(const double* __restrict__ p1, int n1, const double* __restrict__ p2, int n2,
+        DevScalars* __restrict__ ds, StepConst c) {
+  __shared__ double red[P2_NSUM * (SOLVE_THREADS / 64 + 1)];
+  const int tid = threadIdx.x;
+  double T1[P1_NSUM], T2[P2_NSUM];
+  reduce_rows<P1_NSUM, SOLVE_THREADS>(p1, n1, red, tid, T1);
+  reduce_rows<P2_NSUM, SOLVE_THREADS>(p2, n2, red, tid, T2);
+  if (tid != 0) return;
+
+  int err = 0;
+  const double h2 = c.h2;
+  const double rS2 = h2 * T1[P1_RS], rW2 = h2 * T1[P1_RW], rZ2 = h2 * T1[P1_RZ];
+  const double tiny = 1e-280;
+  if (!(rS2 > tiny) || !(rW2 > tiny) || !(rZ2 > tiny)) err |= ERR_NORM;
+  const double nS = 1.0 / sqrt(rS2), nQ = 1.0 / sqrt(rW2), nK = 1.0 / sqrt(rZ2);
+  const double nF[4] = {nS, 1.0, nQ, nK};
+  const double* Vn = ds->sav[c.slot_n];
+  const double* Vm = ds->sav[c.slot_m];
+  double s[4];
+  for (int i = 0; i < 4; ++i) s[i] = c.c0 * Vn[i] + c.c1 * Vm[i] + h2 * nF[i] * T1[P1_ES + i];
+  s[3] += h2 * nK * T1[P1_EP];
+
+  const int gi[4][4] = {{P2_SS, P2_SH, P2_SQ, P2_SK},
+                        {P2_SH, P2_HH, P2_HQ, P2_HK},
+                        {P2_SQ, P2_HQ, P2_QQ, P2_QK},
+                        {P2_SK, P2_HK, P2_QK, P2_KK}};
+  double G[4][4];
+  for (int i = 0; i < 4; ++i)
+    for (int jx = 0; jx < 4; ++jx) G[i][jx] = h2 * nF[i] * nF[jx] * T2[gi[i][jx]];
+  const double cw[4] = {c.cgs, c.cga, c.cgb, c.cgo};
+  double M[5][5], b[5];
+  for (int i = 0; i < 4; ++i) {
+    double bi = h2 * nF[i] * T2[P2_FS + i];
+    for (int jx = 0; jx < 4; ++jx) {
+      M[i][jx] = (i == jx ? 1.0 : 0.0) + cw[jx] * G[i][jx];
+      bi -= cw[jx] * s[jx] * G[i][jx];
+    }
+    M[i][4] = c.cgo * G[i][3];
+    b[i] = bi;
+  }
+  const double PL = h2 * nK * nK * T2[P2_PL];
+  M[4][0] = M[4][1] = M[4][2] = 0.0;
+  M[4][3] = -PL;
+  M[4][4] = 1.0 - PL;
+  b[4] = h2 * nK * T2[P2_PG] + s[3] * PL;
+  for (int i = 0; i < 5; ++i) {
+    for (int jx = 0; jx < 5; ++jx) ds->diag[15 + 5 * i + jx] = M[i][jx];
+  }
+
+  // Gaussian elimination with partial pivoting.
+  double scale = 0.0;
+  for (int i = 0; i < 5; ++i)
+    for (int jx = 0; jx < 5; ++jx) scale = fmax(scale, fabs(M[i][jx]));
+  for (int col = 0; col < 5; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < 5; ++r)
+      if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
+    if (!(fabs(M[piv][col]) > 1e-14 * scale)) err |= ERR_PIVOT;
+    if (piv != col) {
+      for (int jx = 0; jx < 5; ++jx) { double t = M[col][jx]; M[col][jx] = M[piv][jx]; M[piv][jx] = t; }
+      double t = b[col]; b[col] = b[piv]; b[piv] = t;
+    }
+    for (int r = col + 1; r < 5; ++r) {
+      const double m = M[r][col] / M[col][col];
+      for (int jx = col; jx < 5; ++jx) M[r][jx] -= m * M[col][jx];
+      b[r] -= m * b[col];
+    }
+  }
+  double x[5];
+  for (int r = 4; r >= 0; --r) {
+    double t = b[r];
+    for (int jx = r + 1; jx < 5; ++jx) t -= M[r][jx] * x[jx];
+    x[r] = t / M[r][r];
+  }
+  const double Vnew[4] = {x[0] + s[0], x[1] + s[1], x[2] + s[2], x[3] + x[4] + s[3]};
+  double* coef = ds->coef;
+  coef[0] = 1.0;
+  coef[1] = -c.cgs * Vnew[0] * nS;
+  coef[2] = -c.cga * Vnew[1];
+  coef[3] = -c.cgb * Vnew[2] * nQ;
+  coef[4] = -c.cgo * Vnew[3] * nK;
+  coef[5] = 1.0;
+  coef[6] = Vnew[3] * nK;
+  coef[7] = 0.0;
+  bool finite = true;
+  for (int i = 0; i < 4; ++i) {
+    ds->sav[c.slot_new][i] = Vnew[i];
+    finite = finite && isfinite(Vnew[i]);
+    ds->diag[i] = s[i];
+  }
+  for (int i = 0; i < 5; ++i) ds->diag[7 + i] = x[i];
+  ds->diag[4] = sqrt(rS2);
+  ds->diag[5] = sqrt(rW2);
+  ds->diag[6] = sqrt(rZ2);
+  for (int i = 0; i < 7; ++i) finite = finite && isfinite(coef[i]);
+  if (!finite) err |= ERR_NONFINITE;
+  if (T1[P1_MOBNEG] > 0.0) err |= ERR_MOBILITY;
+  if (c.lag_d) ds->acc += c.half_dt * c.lam * c.lam * h2 * T1[P1_DLAG];
+  ds->err |= err;
+}
+
+// ---------------------------------------------------------------------------
+// P3: spectral combination, divide by the operator spectrum, DCT-III along y.
+// ---------------------------------------------------------------------------
+template <typename TM, int NY>
+__global__ void __launch_bounds__(line_threads(NY))
+k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
+            const double* __restrict__ lamy, const double* __restrict__ coef,
+            TM* __restrict__ out, int nx, int chi_base, int nchi, int zeta_base, int nzeta,
+            StepConst c) {
+  constexpr int NTHR = line_threads(NY);
+  constexpr int KPT = (NY + NTHR - 1) / NTHR;
+  __shared__ cpx<TM> line[NY];
+  __shared__ cpx<TM> rtab[Roots<TM, NY>::SIZE];
+  const int tid = threadIdx.x;
+  const int lin = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+  const int nstrip = gridDim.x;
+  const int s = lin % nstrip;
+  const int grp = lin / nstrip;            // 0: chi (Allen-Cahn), 1: zeta (Cahn-Hilliard)
+  const size_t FS = (size_t)nx * NY;
+  Roots<TM, NY> rt;
+  rt.init(rtab, tid, NTHR);
+  const int base = grp == 0 ? chi_base : zeta_base;
+  const int nf = grp == 0 ? nchi : nzeta;
+  const double* cf = coef + (grp == 0 ? 0 : 5);
+
+  // combine the x-transformed right-hand sides of this group
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int jj = tid + q * NTHR;
+    if (jj < NY) {
+      double ur = 0.0, ui = 0.0;
+      for (int f = 0; f < nf; ++f) {
+        const cpx<TM> v =
+            reinterpret_cast<const cpx<TM>*>(mid + (size_t)(base + f) * FS)[(size_t)s * NY + jj];
+        ur += cf[f] * (double)v.re;
+        ui += cf[f] * (double)v.im;
+      }
+      line[makhoul_slot<NY>(jj)] = {(TM)ur, (TM)ui};
+    }
+  }
+  __syncthreads();
+  fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
+  TM A[KPT], B[KPT];
+  const double lx0 = lamx[2 * s], lx1 = lamx[2 * s + 1];
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = tid + q * NTHR;
+    if (k < NY) {
+      dct2_post<TM, NY>(line, rt, k, A[q], B[q]);
+      const double ly = lamy[k];
+      const double L0 = lx0 + ly, L1 = lx1 + ly;
+      double d0, d1;
+      if (grp == 0) {
+        d0 = c.C1 + L0 * (c.C2 + c.C3 * L0);
+        d1 = c.C1 + L1 * (c.C2 + c.C3 * L1);
+      } else {
+        d0 = c.alpha + c.lam * L0;
+        d1 = c.alpha + c.lam * L1;
+      }
+      A[q] = (TM)((double)A[q] / d0);
+      B[q] = (TM)((double)B[q] / d1);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = tid + q * NTHR;
+    if (k < NY) line[k] = {A[q], B[q]};
+  }
+  __syncthreads();
+  cpx<TM> Z[KPT];
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = tid + q * NTHR;
+    if (k < NY) {
+      const cpx<TM> m = line[(NY - k) & (NY - 1)];
+      Z[q] = dct3_pre<TM, NY>(rt, k, A[q], m.re, B[q], m.im);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int k = tid + q * NTHR;
+    if (k < NY) line[k] = Z[q];
+  }
+  __syncthreads();
+  fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
+  cpx<TM>* dst = reinterpret_cast<cpx<TM>*>(out + (size_t)grp * FS) + (size_t)s * NY;
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int i = tid + q * NTHR;
+    if (i < NY) {
+      const cpx<TM> y = line[makhoul_slot<NY>(i)];
+      dst[i] = {y.re, -y.im};
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// P4: DCT-III along x of the two solved fields -> phi^{n+1}, psi^{n+1}.
+// ---------------------------------------------------------------------------
+template <typename TM, int NX>
+__global__ void __launch_bounds__(line_threads(NX))
+k_row_idct(const TM* __restrict__ out, double* __restrict__ phi_new, double* __restrict__ psi_new,
+           int ny) {
+  constexpr int NTHR = line_threads(NX);
+  constexpr int CPT = (NX + NTHR - 1) / NTHR;
+  __shared__ cpx<TM> line[NX];
+  __shared__ cpx<TM> rtab[Roots<TM, NX>::SIZE];
+  const int tid = threadIdx.x;
+  const int j = xcd_remap(blockIdx.x, gridDim.x);
+  const size_t FS = (size_t)NX * ny;
+  Roots<TM, NX> rt;
+  rt.init(rtab, tid, NTHR);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int k = tid + q * NTHR;
+    if (k < NX) {
+      const int km = (NX - k) & (NX - 1);
+      const size_t ok = mid_index(k, j, ny), om = mid_index(km, j, ny);
+      line[k] = dct3_pre<TM, NX>(rt, k, out[ok], out[om], out[FS + ok], out[FS + om]);
+    }
+  }
+  __syncthreads();
+  fft_lines<TM, NX, 1, NTHR>(line, rt, tid);
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int i = tid + q * NTHR;
+    if (i < NX) {
+      const cpx<TM> y = line[makhoul_slot<NX>(i)];
+      phi_new[(size_t)j * NX + i] = (double)y.re;
+      psi_new[(size_t)j * NX + i] = -(double)y.im;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row DCT-II of one plain field into intermediate slot `slot` (elliptic solve).
+// ---------------------------------------------------------------------------
+template <typename TM, int NX>
+__global__ void __launch_bounds__(line_threads(NX))
+k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, int ny) {
+  constexpr int NTHR = line_threads(NX);
+  constexpr int CPT = (NX + NTHR - 1) / NTHR;
+  __shared__ cpx<TM> line[NX];
+  __shared__ cpx<TM> rtab[Roots<TM, NX>::SIZE];
+  const int tid = threadIdx.x;
+  const int j = xcd_remap(blockIdx.x, gridDim.x);
+  const size_t FS = (size_t)NX * ny;
+  Roots<TM, NX> rt;
+  rt.init(rtab, tid, NTHR);
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int i = tid + q * NTHR;
+    if (i < NX) line[makhoul_slot<NX>(i)] = {(TM)src[(size_t)j * NX + i], (TM)0};
+  }
+  __syncthreads();
+  fft_lines<TM, NX, 1, NTHR>(line, rt, tid);
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int k = tid + q * NTHR;
+    if (k < NX) {
+      TM A, B;
+      dct2_post<TM, NX>(line, rt, k, A, B);
+      mid[(size_t)slot * FS + mid_index(k, j, ny)] = A;
+    }
+  }
+}
+
+}  // namespace ccm

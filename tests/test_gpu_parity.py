@@ -1,0 +1,217 @@
+"""GPU parity of the HIP step against the FP64 oracle, through the C ABI.
+
+Bars: rel L-inf <= 1e-12 for FP64 where the oracle's own ulp envelope allows
+it, else ENVELOPE_FACTOR times that envelope (see parity_util); exact mass
+conservation; energy and SAVs against the oracle.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import ccmsav_ref as R
+from parity_util import envelope, oracle_trajectory, rel_linf, tolerances
+from workloads import circle_member, make_workload, vesicle_member
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2601_10057_amd import ccmsav as C  # noqa: E402
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def gpu_trajectory(member, steps, precision="fp64", record=None):
+    """Run the HIP path; return {step: (phi, psi, sav, sav_prev)} at ``record`` steps."""
+    record = set(range(steps + 1)) if record is None else set(record)
+    out = {}
+    with C.Context(member.params, member.phi0, member.psi0, precision) as ctx:
+        for k in range(steps + 1):
+            if k > 0:
+                ctx.step(1)
+            if k in record:
+                phi, psi = ctx.fields()
+                s1, s0 = ctx.savs()
+                out[k] = (phi, psi, s1, s0)
+    return out
+
+
+def compare(member, steps, record=None, label=""):
+    note(f"{label} nx={member.params['nx']} ny={member.params['ny']} steps={steps}")
+    ref = oracle_trajectory(member.phi0, member.psi0, member.params, steps)
+    pert = oracle_trajectory(member.phi0, member.psi0, member.params, steps, perturb_seed=1)
+    tol = tolerances(envelope(ref, pert))
+    got = gpu_trajectory(member, steps, record=record)
+    for k, (phi, psi, s1, s0) in sorted(got.items()):
+        r = ref[k]
+        errs = (rel_linf(phi, r[0]), rel_linf(psi, r[1]), rel_linf(s1, r[2]))
+        assert max(errs) <= tol[k], (k, errs, tol[k])
+        if k >= 1:
+            assert rel_linf(s0, r[3]) <= tol[k - 1] * 10, k
+    return ref, got
+
+
+# ------------------------------------------------------------------ elliptic solver
+
+@pytest.mark.parametrize("nx,ny", [(16, 16), (64, 32), (32, 128), (128, 128), (1024, 1024),
+                                   (4096, 4096)])
+def test_elliptic_solves_match_oracle(nx, ny):
+    note(f"elliptic nx={nx} ny={ny}")
+    m = circle_member(max(nx, ny))
+    params = dict(m.params, nx=nx, ny=ny)
+    rng = np.random.default_rng(nx * 7 + ny)
+    rhs = rng.standard_normal((ny, nx))
+    phi0 = np.zeros((ny, nx)) + 0.3
+    psi0 = np.zeros((ny, nx)) + 1.1
+    p = R.Params.from_dict(dict(params, A=1.0))
+    C1, C2, C3 = R.chi_coefficients(p, 1.5 / p.dt)
+    lam = R.neumann_lap_eigs(nx, ny, p.h)
+    ref_chi = R.spectral_solve(rhs, C1 - C2 * lam + C3 * lam ** 2)
+    ref_zeta = R.spectral_solve(rhs, 1.5 / p.dt - p.lam * lam)
+    dev = torch.from_numpy(rhs).cuda()
+    oc = torch.empty_like(dev)
+    oz = torch.empty_like(dev)
+    with C.Context(params, phi0, psi0) as ctx:
+        ctx.elliptic_solve(dev, oc, oz)
+        torch.cuda.synchronize()
+    assert rel_linf(oc.cpu().numpy(), ref_chi) <= 1e-12
+    assert rel_linf(oz.cpu().numpy(), ref_zeta) <= 1e-12
+
+
+# ------------------------------------------------------------------ full steps
+
+@pytest.mark.parametrize("n", [16, 64, 256])
+def test_vesicle_steps_match_oracle(n):
+    compare(vesicle_member(n, 10057), 8, label="vesicle")
+
+
+def test_rectangular_grid_matches_oracle():
+    m = vesicle_member(64, 3)
+    X = np.linspace(-1, 1, 128)
+    phi0 = np.ascontiguousarray(np.concatenate([m.phi0, m.phi0[::-1]], axis=1))
+    psi0 = np.ascontiguousarray(np.concatenate([m.psi0, m.psi0[::-1]], axis=1))
+    del X
+    params = dict(m.params, nx=128, ny=64)
+    rect = type(m)("rect", phi0, psi0, params, {})
+    compare(rect, 6, label="rect")
+
+
+def test_circle128_workload_matches_oracle():
+    """The small configuration: N=128 circle, dt=1e-4, 100 steps."""
+    m = make_workload("circle128")[0]
+    compare(m, 100, record=[1, 2, 3, 10, 50, 100], label="circle128")
+
+
+def test_energy_mass_and_savs_match_oracle():
+    m = make_workload("circle128")[0]
+    note("energy circle128")
+    st = R.initial_state(m.phi0, m.psi0, m.params)
+    with C.Context(m.params, m.phi0, m.psi0) as ctx:
+        m0 = ctx.mass()[0]
+        assert m0 == pytest.approx(R.mass(st)[0], rel=1e-13)
+        energies = []
+        for k in range(12):
+            R.step(st)
+            ctx.step(1)
+            e_gpu, parts = ctx.energy(parts=True)
+            e_ref = R.energy(st)
+            assert e_gpu == pytest.approx(e_ref["E"], rel=1e-9, abs=1e-9 * abs(e_ref["U"]) + 1e-9)
+            for name, v in zip(("bend", "surf", "stab", "lin", "V", "U", "W", "Z", "acc"), parts):
+                assert v == pytest.approx(e_ref[name], rel=1e-8, abs=1e-8 * abs(e_ref["E"]) + 1e-12)
+            energies.append(e_gpu)
+            mp, _ = ctx.mass()
+            assert abs(mp - m0) <= 1e-13 * abs(m0)
+        assert all(b <= a + 1e-12 * abs(a) for a, b in zip(energies[:-1], energies[1:]))
+
+
+def test_mass_conserved_over_workload():
+    m = make_workload("vesicle1024", 256)[0]
+    note("mass vesicle256 400 steps")
+    with C.Context(m.params, m.phi0, m.psi0) as ctx:
+        m0 = ctx.mass()[0]
+        prev = None
+        for _ in range(4):
+            ctx.step(100)
+            mp, _ = ctx.mass()
+            assert abs(mp - m0) <= 5e-11 * abs(m0)
+            assert abs(mp - m0) <= 1e-13 * abs(m0)
+            e = ctx.energy()
+            if prev is not None:
+                assert e <= prev + 1e-12 * abs(prev)
+            prev = e
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_large_grids_first_steps_match_oracle(n):
+    """Bench-family grids in the bench launch configuration: BDF1 + BDF2 steps."""
+    m = make_workload("vesicle4096", n)[0]
+    compare(m, 2, label="large")
+
+
+def test_bench_grid_first_step_matches_oracle():
+    """N=4096, the benchmark grid: the first step against the oracle at 1e-12.
+
+    The oracle needs about half a minute per step at this size, so only the
+    first step is compared (its ulp envelope is at the 1e-14 level at every
+    smaller size of this family)."""
+    m = make_workload("vesicle4096")[0]
+    note("bench grid 4096, 1 step")
+    st = R.initial_state(m.phi0, m.psi0, m.params)
+    got = gpu_trajectory(m, 1, record=[1])[1]
+    R.step(st)
+    assert rel_linf(got[0], st.phi) <= 1e-12
+    assert rel_linf(got[1], st.psi) <= 1e-12
+    assert rel_linf(got[2], st.sav) <= 1e-12
+
+
+# ------------------------------------------------------------------ error paths
+
+def test_degenerate_inputs_report_domain_errors():
+    m = circle_member(32)
+    ones = np.ones_like(m.phi0)
+    note("degenerate phi0 = 1")
+    with pytest.raises(C.CcmsavError) as e:
+        C.Context(m.params, ones, m.psi0)
+    assert e.value.name == "EDOMAIN"
+    bad = m.phi0.copy()
+    bad[3, 4] = np.nan
+    note("nan in phi0")
+    with pytest.raises(C.CcmsavError) as e:
+        C.Context(m.params, bad, m.psi0)
+    assert e.value.name == "ENONFINITE"
+
+
+def test_energy_needs_two_levels():
+    m = circle_member(32, dt=1e-5)
+    with C.Context(m.params, m.phi0, m.psi0) as ctx:
+        with pytest.raises(C.CcmsavError) as e:
+            ctx.energy()
+        assert e.value.name == "EINVAL"
+        assert ctx.level == 0
+        ctx.step(3)
+        assert ctx.level == 3
+        assert math.isfinite(ctx.energy())
+
+
+def test_nonpositive_mobility_is_reported_by_energy():
+    """circle32 at dt=1e-4 pushes |phi*| past sqrt(1 + 1/sqrt(M0)): M_psi < 0 on
+    some face, where d^{n+1} and the energy are undefined (the oracle agrees)."""
+    m = circle_member(32)
+    st = R.initial_state(m.phi0, m.psi0, m.params)
+    for _ in range(3):
+        info = R.step(st, keep=True)
+    mx, my = R.face_mobility(info["phis"], st.p)
+    assert min(mx.min(), my.min()) <= 0.0
+    note("mobility circle32")
+    with C.Context(m.params, m.phi0, m.psi0) as ctx:
+        ctx.step(3)
+        with pytest.raises(C.CcmsavError) as e:
+            ctx.energy()
+        assert e.value.name == "EDOMAIN"
