@@ -1,0 +1,193 @@
+#!/usr/bin/env python3
+"""Throughput of the CC-MSAV vesicle time step on one MI355X.
+
+One "step" is one full CC-MSAV-BDF2 time step (stencil terms, SAV inner
+products, 5x5 solve, DCT elliptic solves) of the named synthetic workload; the
+inputs are resident in device memory before the timed region starts. Prints
+one JSON line: the throughput in Mcell-steps/s, a roofline entry for the
+dominant kernel (algorithmic bytes per launch over its mean duration from HIP
+events on the library's stream), and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mcell-steps/s at N=2048/4096, mixed-prec & batched vs FP64, rel err ≤1e-6"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per cell for one launch of each kernel of the step.
+# State fields are FP64; the eight transform intermediates and the two solved
+# fields are FP64 (fp64) or FP32 (mixed). The stencil pass reads phi, psi at
+# levels n, n-1 (and n-2 for the lagged ||d||^2) and writes eight fields; the
+# column pass reads the eight; the column solve reads seven and writes two;
+# the row inverse reads two and writes the two new state fields.
+def kernel_bytes_per_cell(precision: str):
+    m = 8 if precision == "fp64" else 4
+    return {
+        "stencil_rowdct": 6 * 8 + 8 * m,
+        "col_gram": 8 * m,
+        "solve5": 0,
+        "col_solve": 7 * m + 2 * m,
+        "row_idct": 2 * m + 2 * 8,
+    }
+
+
+def source_digest() -> str:
+    """Hash of the HIP sources, to tell whether stored counters are stale."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2601_10057_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(workload: str, precision: str, kernel: str, cells: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(member):
+    """FP64 oracle timed on this host: one step of the same workload."""
+    from oracle import ccmsav_ref as R
+    st = R.initial_state(member.phi0, member.psi0, member.params)
+    t0 = time.perf_counter()
+    R.step(st)
+    dt = time.perf_counter() - t0
+    cells = member.phi0.size
+    return {"value": cells / dt / 1e6, "unit": "Mcell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 step (the first, BDF1 form, same operation count as a BDF2 step) of "
+                      f"{member.name} at N={member.params['nx']}: {dt:.2f} s single-threaded "
+                      f"numpy/scipy"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="vesicle4096")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--profile-steps", type=int, default=50,
+                    help="steps of the per-kernel event pass that feeds the roofline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="after timing, copy this many MiB with a plain torch copy "
+                         "(a known-size kernel that calibrates rocprofv3 byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the single-grid step is run on one MI355X).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2601_10057_amd import ccmsav as C
+    from workloads import WORKLOADS, make_workload
+
+    spec = WORKLOADS[args.workload]
+    if spec["kind"] != "single":
+        raise SystemExit("bench.py times single-grid workloads")
+    member = make_workload(args.workload)[0]
+    nx, ny = member.params["nx"], member.params["ny"]
+    cells = nx * ny
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    phi0 = torch.from_numpy(member.phi0).to(dev)
+    psi0 = torch.from_numpy(member.psi0).to(dev)
+    stream = torch.cuda.current_stream(dev)
+
+    ctx = C.Context(member.params, phi0, psi0, args.precision, stream=stream.cuda_stream)
+    ctx.step(args.warmup)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    ctx.step(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.sync()                       # raises on any device-side error of the run
+    ev_ms = ev0.elapsed_time(ev1)
+    ms_per_step = 1e3 * wall / args.steps
+    value = cells * args.steps / wall / 1e6
+    print(f"[bench] {args.workload} {args.precision}: {ms_per_step:.4f} ms/step (wall), "
+          f"{ev_ms / args.steps:.4f} ms/step (events), {value:.1f} Mcell-steps/s",
+          file=sys.stderr, flush=True)
+
+    prof = ctx.profile_steps(args.profile_steps)
+    per_cell = kernel_bytes_per_cell(args.precision)
+    for k, ms in prof.items():
+        gbs = per_cell[k] * cells / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        print(f"[bench] kernel {k}: {ms * 1e3:.1f} us/launch, {per_cell[k]} B/cell, "
+              f"{gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    dom = max(prof, key=prof.get)
+    dom_bytes = per_cell[dom] * cells
+    achieved = dom_bytes / (prof[dom] * 1e-3) / 1e9
+    traffic = stored_traffic(args.workload, args.precision, dom, cells)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "bytes_per_launch": dom_bytes, "us_per_launch": prof[dom] * 1e3}
+    mass = ctx.mass()[0]
+    energy = ctx.energy()
+    ctx.close()
+
+    if args.copy_probe_mib > 0:
+        a = torch.empty(args.copy_probe_mib * 2 ** 18, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(member)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "nx": nx, "ny": ny, "cells": cells,
+                   "precision": args.precision, "dt": member.params["dt"],
+                   "eps_cells": member.meta.get("eps_cells", 4.0)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "check": {"mass_psi": mass, "E_mod": energy, "finite": bool(np.isfinite(energy))},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

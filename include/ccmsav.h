@@ -131,6 +131,16 @@ int ccmsav_get_savs(ccmsav_ctx* c, double out8[8]);
 /* Current level n (number of steps taken). */
 int64_t ccmsav_level(const ccmsav_ctx* c);
 
+/*
+ * Take nsteps >= 1 steps like ccmsav_step, with HIP events recorded on the
+ * context's stream around each of the five kernels of a step, then wait and
+ * write the mean duration in milliseconds of each kernel launch to
+ * ms_per_phase[5]: stencil + row DCT-II, column DCT-II + inner products,
+ * 5x5 solve, column solve (combine, divide, DCT-III), row DCT-III.
+ * Creates and destroys 10 * nsteps events (nsteps <= 100000).
+ */
+int ccmsav_profile_steps(ccmsav_ctx* c, int32_t nsteps, double* ms_per_phase);
+
 /* Wait for the stream and report sticky device errors. */
 int ccmsav_sync(ccmsav_ctx* c);
 

@@ -27,7 +27,9 @@ EXPORTED = (
     "ccmsav_workspace_bytes", "ccmsav_init", "ccmsav_step", "ccmsav_energy",
     "ccmsav_mass", "ccmsav_get_fields", "ccmsav_get_savs", "ccmsav_level",
     "ccmsav_sync", "ccmsav_elliptic_solve", "ccmsav_destroy", "ccmsav_strerror",
+    "ccmsav_profile_steps",
 )
+PHASES = ("stencil_rowdct", "col_gram", "solve5", "col_solve", "row_idct")
 
 
 class Params(ctypes.Structure):
@@ -89,13 +91,14 @@ def load() -> ctypes.CDLL:
     lib.ccmsav_level.argtypes = [vp]
     lib.ccmsav_level.restype = ctypes.c_int64
     lib.ccmsav_sync.argtypes = [vp]
+    lib.ccmsav_profile_steps.argtypes = [vp, ctypes.c_int32, dp]
     lib.ccmsav_elliptic_solve.argtypes = [vp, vp, vp, vp]
     lib.ccmsav_destroy.argtypes = [vp]
     lib.ccmsav_strerror.argtypes = [ctypes.c_int]
     lib.ccmsav_strerror.restype = ctypes.c_char_p
     for fn in ("ccmsav_init", "ccmsav_step", "ccmsav_energy", "ccmsav_mass",
                "ccmsav_get_fields", "ccmsav_get_savs", "ccmsav_sync",
-               "ccmsav_elliptic_solve", "ccmsav_destroy"):
+               "ccmsav_elliptic_solve", "ccmsav_destroy", "ccmsav_profile_steps"):
         getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -167,6 +170,12 @@ class Context:
     # -- stepping and diagnostics ------------------------------------------
     def step(self, nsteps: int = 1):
         _check(load().ccmsav_step(self._h, int(nsteps)), "ccmsav_step")
+
+    def profile_steps(self, nsteps: int) -> Dict[str, float]:
+        """Take ``nsteps`` steps with HIP events around each kernel; mean ms per launch."""
+        buf = (ctypes.c_double * len(PHASES))()
+        _check(load().ccmsav_profile_steps(self._h, int(nsteps), buf), "ccmsav_profile_steps")
+        return dict(zip(PHASES, list(buf)))
 
     def sync(self):
         _check(load().ccmsav_sync(self._h), "ccmsav_sync")

@@ -19,6 +19,7 @@ constexpr int kMinLog = 4;    // 16
 constexpr int kMaxLog = 13;   // 8192
 constexpr int kNumSizes = kMaxLog - kMinLog + 1;
 constexpr size_t kAlign = 256;
+constexpr int kNumPhases = 5;   // stencil+row DCT, column Gram, 5x5 solve, column solve, row IDCT
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -246,8 +247,16 @@ int read_err(ccmsav_ctx* c, int* err) {
   return CCMSAV_OK;
 }
 
+// Optional per-phase timing: events[2*ph], events[2*ph+1] bracket phase ph.
+struct PhaseEvents {
+  hipEvent_t* ev;   // 2 * kNumPhases events of this step, or nullptr
+  void mark(int i, hipStream_t s) const {
+    if (ev) (void)hipEventRecord(ev[i], s);
+  }
+};
+
 template <typename TM>
-void enqueue_step(ccmsav_ctx* c) {
+void enqueue_step(ccmsav_ctx* c, PhaseEvents pe = PhaseEvents{nullptr}) {
   const int nx = c->p.nx, ny = c->p.ny;
   const bool bdf2 = c->level >= 1;
   StepConst k = make_const(c, bdf2);
@@ -266,13 +275,23 @@ void enqueue_step(ccmsav_ctx* c) {
   TM* mid = static_cast<TM*>(c->mid);
   TM* outc = static_cast<TM*>(c->outc);
   using LT = typename Launch<TM>::T;
+  pe.mark(0, c->stream);
   LT::t1[c->lx - kMinLog](c->stream, ny, phn, phm, phmm, psn, psm, psmm, mid, c->part1, ny, k);
+  pe.mark(1, c->stream);
+  pe.mark(2, c->stream);
   LT::t2[c->ly - kMinLog](c->stream, nx / 2, mid, c->lamx, c->lamy, c->part2, nx, k);
+  pe.mark(3, c->stream);
+  pe.mark(4, c->stream);
   hipLaunchKernelGGL(k_solve, dim3(1), dim3(SOLVE_THREADS), 0, c->stream, c->part1, ny, c->part2,
                      nx / 2, c->ds, k);
+  pe.mark(5, c->stream);
+  pe.mark(6, c->stream);
   LT::t3[c->ly - kMinLog](c->stream, nx / 2, mid, c->lamx, c->lamy, c->ds->coef, outc, nx, M_F, 5,
                           M_G, 2, k);
+  pe.mark(7, c->stream);
+  pe.mark(8, c->stream);
   LT::t4[c->lx - kMinLog](c->stream, ny, outc, c->phi[snew], c->psi[snew], ny);
+  pe.mark(9, c->stream);
   c->level += 1;
 }
 
@@ -426,6 +445,49 @@ int ccmsav_step(ccmsav_ctx* c, int32_t nsteps) {
   }
   if (hipGetLastError() != hipSuccess) return CCMSAV_EHIP;
   return CCMSAV_OK;
+}
+
+int ccmsav_profile_steps(ccmsav_ctx* c, int32_t nsteps, double* ms_per_phase) {
+  if (!c || nsteps <= 0 || nsteps > 100000 || !ms_per_phase) return CCMSAV_EINVAL;
+  const int nev = 2 * kNumPhases;
+  hipEvent_t* ev = new (std::nothrow) hipEvent_t[(size_t)nev * nsteps];
+  if (!ev) return CCMSAV_ENOMEM;
+  int created = 0;
+  int rc = CCMSAV_OK;
+  for (; created < nev * nsteps; ++created) {
+    if (hipEventCreate(&ev[created]) != hipSuccess) {
+      rc = CCMSAV_EHIP;
+      break;
+    }
+  }
+  if (rc == CCMSAV_OK) {
+    for (int32_t s = 0; s < nsteps; ++s) {
+      PhaseEvents pe{ev + (size_t)nev * s};
+      if (c->p.precision == CCMSAV_MIXED)
+        enqueue_step<float>(c, pe);
+      else
+        enqueue_step<double>(c, pe);
+    }
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+      rc = CCMSAV_EHIP;
+  }
+  if (rc == CCMSAV_OK) {
+    for (int ph = 0; ph < kNumPhases; ++ph) {
+      double tot = 0.0;
+      for (int32_t s = 0; s < nsteps; ++s) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[(size_t)nev * s + 2 * ph],
+                                ev[(size_t)nev * s + 2 * ph + 1]) != hipSuccess)
+          rc = CCMSAV_EHIP;
+        tot += ms;
+      }
+      ms_per_phase[ph] = tot / nsteps;
+    }
+  }
+  for (int i = 0; i < created; ++i) (void)hipEventDestroy(ev[i]);
+  delete[] ev;
+  if (rc != CCMSAV_OK) return rc;
+  return ccmsav_sync(c);
 }
 
 int ccmsav_sync(ccmsav_ctx* c) {

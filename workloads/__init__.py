@@ -13,4 +13,5 @@ from .generators import (  # noqa: F401
     vesicle_member,
     make_workload,
     table_g_params,
+    vesicle_dt,
 )
