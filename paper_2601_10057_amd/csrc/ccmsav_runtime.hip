@@ -33,9 +33,7 @@ int log2_exact(int n) {
 // ---- launch tables over the line length --------------------------------------
 
 template <typename TM> struct Launch {
-  using P1 = void (*)(hipStream_t, int, const double*, const double*, const double*,
-                      const double*, const double*, const double*, TM*, double*, int,
-                      const StepConst&);
+  using P1 = void (*)(hipStream_t, int, const RowArgs&, TM*, double*, int, const StepConst&);
   using P2 = void (*)(hipStream_t, int, const TM*, const double*, const double*, double*, int,
                       const StepConst&);
   using P3 = void (*)(hipStream_t, int, const TM*, const double*, const double*, const double*,
@@ -44,11 +42,10 @@ template <typename TM> struct Launch {
   using RD = void (*)(hipStream_t, int, const double*, TM*, int, int);
 
   template <int N>
-  static void p1(hipStream_t st, int grid, const double* a, const double* b, const double* cc,
-                 const double* d, const double* e, const double* f, TM* mid, double* part,
-                 int ny, const StepConst& k) {
-    hipLaunchKernelGGL((k_stencil_rowdct<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, a, b,
-                       cc, d, e, f, mid, part, ny, k);
+  static void p1(hipStream_t st, int grid, const RowArgs& a, TM* mid, double* part, int ny,
+                 const StepConst& k) {
+    hipLaunchKernelGGL((k_stencil_rowdct<TM, N>), dim3(grid), dim3(stencil_threads<TM>(N)), 0, st,
+                       a, mid, part, ny, k);
   }
   template <int N>
   static void p2(hipStream_t st, int grid, const TM* mid, const double* lx, const double* ly,
@@ -276,7 +273,8 @@ void enqueue_step(ccmsav_ctx* c, PhaseEvents pe = PhaseEvents{nullptr}) {
   TM* outc = static_cast<TM*>(c->outc);
   using LT = typename Launch<TM>::T;
   pe.mark(0, c->stream);
-  LT::t1[c->lx - kMinLog](c->stream, ny, phn, phm, phmm, psn, psm, psmm, mid, c->part1, ny, k);
+  const RowArgs ra{phn, phm, phmm, psn, psm, psmm};
+  LT::t1[c->lx - kMinLog](c->stream, ny, ra, mid, c->part1, ny, k);
   pe.mark(1, c->stream);
   pe.mark(2, c->stream);
   LT::t2[c->ly - kMinLog](c->stream, nx / 2, mid, c->lamx, c->lamy, c->part2, nx, k);

@@ -7,8 +7,9 @@
 //     X_k = s_k Re(exp(-i pi k / (2N)) V_k),  s_0 = sqrt(1/N), s_k = sqrt(2/N),
 // and two real lines a, b share one complex FFT of z = v_a + i v_b
 // (V_a = (Z_k + conj Z_{-k})/2, V_b = (Z_k - conj Z_{-k})/(2i)). The DCT-III
-// runs the same steps backwards. The complex FFT is a Stockham autosort
-// transform in LDS with radix-2/4/8/16 butterflies held in registers.
+// runs the same steps backwards. The complex FFT is an in-place
+// decimation-in-frequency transform in LDS (radix-8 butterflies in registers,
+// digit-reversed output).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -107,65 +108,70 @@ template <int N> struct Plan {
   static constexpr int FIRST = (LOGN % 3 == 0) ? 8 : (LOGN % 3 == 1 ? 2 : 4);
 };
 
-// One Stockham stage over NL independent lines of length N stored back to back.
-// Stage with current sub-transform length NS and radix R:
-//   j in [0, N/R): k = j mod NS, v_r = x[j + r N/R] * exp(-2 pi i r k / (NS R)),
-//   V = DFT_R(v), y[(j / NS) NS R + k + r NS] = V_r.
-// The stage is in place: every thread reads its inputs before the barrier and
-// writes its outputs after it.
-template <typename T, int N, int NL, int NTHR, int R, int NS>
-__device__ __forceinline__ void stockham_stage(cpx<T>* buf, const Roots<T, N>& rt, int tid) {
+// One in-place decimation-in-frequency stage over NL independent lines of
+// length N stored back to back. With block length L and radix R, butterfly m
+// of a block reads x[m + r L/R] (r < R), forms the R-point DFT y_q and stores
+// y_q exp(-2 pi i m q / L) back at x[m + q L/R]. Butterflies own disjoint
+// positions, so a thread handles its butterflies one after another with only
+// R values live; the barrier separates the stages.
+template <typename T, int N, int NL, int NTHR, int R, int L>
+__device__ __forceinline__ void dif_stage(cpx<T>* buf, const Roots<T, N>& rt, int tid) {
   constexpr int NB = N / R;
   constexpr int TOT = NB * NL;
-  constexpr int PER = (TOT + NTHR - 1) / NTHR;
-  cpx<T> v[PER][R];
+  constexpr int S = L / R;
+  for (int b = tid; b < TOT; b += NTHR) {
+    const int line = b / NB, jb = b % NB;
+    const int blk = jb / S, m = jb % S;
+    cpx<T>* x = buf + line * N + blk * L + m;
+    cpx<T> v[R];
 #pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int b = tid + p * NTHR;
-    if (TOT % NTHR == 0 || b < TOT) {
-      const int line = b / NB, j = b % NB;
-      const cpx<T>* x = buf + line * N;
+    for (int r = 0; r < R; ++r) v[r] = x[r * S];
+    SmallDFT<T, R>::run(v);
+    if (L > R) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[p][r] = x[j + r * NB];
+      for (int q = 1; q < R; ++q) v[q] = cmul(v[q], rt.tw(m * q * (N / L)));
     }
-  }
-  __syncthreads();
 #pragma unroll
-  for (int p = 0; p < PER; ++p) {
-    const int b = tid + p * NTHR;
-    if (TOT % NTHR == 0 || b < TOT) {
-      const int line = b / NB, j = b % NB;
-      const int k = j & (NS - 1);
-      if (NS > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[p][r] = cmul(v[p][r], rt.tw(r * k * (N / (NS * R))));
-      }
-      SmallDFT<T, R>::run(v[p]);
-      cpx<T>* y = buf + line * N;
-      const int base = (j / NS) * NS * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) y[base + r * NS] = v[p][r];
-    }
+    for (int q = 0; q < R; ++q) x[q * S] = v[q];
   }
   __syncthreads();
 }
 
-template <typename T, int N, int NL, int NTHR, int NS>
-struct StageRunner {
+template <typename T, int N, int NL, int NTHR, int L, bool FIRST>
+struct DifRunner {
   static __device__ __forceinline__ void run(cpx<T>* buf, const Roots<T, N>& rt, int tid) {
-    if constexpr (NS < N) {
-      constexpr int R = (NS == 1) ? Plan<N>::FIRST : 8;
-      stockham_stage<T, N, NL, NTHR, R, NS>(buf, rt, tid);
-      StageRunner<T, N, NL, NTHR, NS * R>::run(buf, rt, tid);
+    if constexpr (L > 1) {
+      constexpr int R = FIRST ? Plan<N>::FIRST : 8;
+      dif_stage<T, N, NL, NTHR, R, L>(buf, rt, tid);
+      DifRunner<T, N, NL, NTHR, L / R, false>::run(buf, rt, tid);
     }
   }
 };
 
-// Forward complex FFT (exp(-2 pi i n k / N)) of NL lines in LDS. The caller
-// must have synchronised after writing the input.
+// Forward complex FFT (exp(-2 pi i n k / N)) of NL lines in LDS, in place:
+// natural order in, bin k found at fft_pos<N>(k) out. The caller must have
+// synchronised after writing the input; the FFT ends with a barrier.
 template <typename T, int N, int NL, int NTHR>
 __device__ __forceinline__ void fft_lines(cpx<T>* buf, const Roots<T, N>& rt, int tid) {
-  StageRunner<T, N, NL, NTHR, 1>::run(buf, rt, tid);
+  DifRunner<T, N, NL, NTHR, N, true>::run(buf, rt, tid);
+}
+
+// Position of DFT bin k after fft_lines: the mixed-radix digits of k
+// (first radix, then radix 8) in reverse order.
+template <int N> __device__ __forceinline__ int fft_pos(int k) {
+  constexpr int R1 = Plan<N>::FIRST;
+  constexpr int LR1 = ilog2(R1);
+  constexpr int ND = (Plan<N>::LOGN - LR1) / 3;
+  int span = N / R1;
+  int p = (k & (R1 - 1)) * span;
+  k >>= LR1;
+#pragma unroll
+  for (int d = 0; d < ND; ++d) {
+    span >>= 3;
+    p += (k & 7) * span;
+    k >>= 3;
+  }
+  return p;
 }
 
 // Makhoul position of natural index i inside the reordered line.
@@ -177,13 +183,13 @@ template <int N> __device__ __forceinline__ int makhoul_index(int n) {
   return (n < N / 2) ? 2 * n : 2 * (N - 1 - n) + 1;
 }
 
-// DCT-II post-processing of bin k after the FFT of z = v_a + i v_b:
+// DCT-II post-processing of bin k after fft_lines of z = v_a + i v_b:
 // returns the orthonormal coefficients A_k (line a) and B_k (line b).
 template <typename T, int N>
 __device__ __forceinline__ void dct2_post(const cpx<T>* Z, const Roots<T, N>& rt, int k,
                                           T& A, T& B) {
-  const cpx<T> z = Z[k];
-  const cpx<T> zm = Z[(N - k) & (N - 1)];
+  const cpx<T> z = Z[fft_pos<N>(k)];
+  const cpx<T> zm = Z[fft_pos<N>((N - k) & (N - 1))];
   const T s = (k == 0) ? (T)(0.5 * sqrt(1.0 / N)) : (T)(0.5 * sqrt(2.0 / N));
   const T v1r = z.re + zm.re, v1i = z.im - zm.im;
   const T v2r = z.im + zm.im, v2i = zm.re - z.re;

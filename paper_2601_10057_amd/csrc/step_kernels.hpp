@@ -20,12 +20,27 @@
 // lives at ((k / 2) * ny + j) * 2 + (k % 2), so that a column pair is one
 // contiguous complex line.
 #pragma once
+#include <type_traits>
+
 #include "fft.hpp"
 #include "step_common.hpp"
 
 namespace ccm {
 
-constexpr int line_threads(int n) { return n / 4 < 64 ? 64 : (n / 4 > 1024 ? 1024 : n / 4); }
+constexpr int clamp_threads(int t) { return t < 64 ? 64 : (t > 1024 ? 1024 : t); }
+// Threads of a line kernel: four elements per thread.
+constexpr int line_threads(int n) { return clamp_threads(n / 4); }
+// The stencil kernel holds several FP64 fields per thread: with eight
+// elements per thread the workgroup has half as many waves, so each wave may
+// use twice the registers at the same occupancy (one workgroup per CU).
+template <typename TM> constexpr int stencil_threads(int n) {
+  return clamp_threads(n / 4);
+}
+// Field-pair lines of the row pass that fit in LDS next to the twiddle tables.
+template <typename TM> constexpr int lds_lines(int n) {
+  const int fit = (136 * 1024) / (n * (int)sizeof(cpx<TM>));
+  return fit >= 4 ? 4 : (fit >= 2 ? 2 : 1);
+}
 
 // Consecutive workgroups are dispatched round-robin over the 8 XCDs; give each
 // XCD a contiguous range of lines so that neighbouring rows share an L2.
@@ -70,15 +85,155 @@ __device__ __forceinline__ double mobility(double phi, double M0) {
 // ---------------------------------------------------------------------------
 // P1: fused stencil terms + row DCT-II of the eight right-hand-side fields.
 // ---------------------------------------------------------------------------
+// Field pairs of the row pass (two real fields per complex FFT line).
+enum Pair { PR_FG = 0, PR_SH = 1, PR_QK = 2, PR_LP = 3 };
+constexpr int PAIR_A[4] = {M_F, M_S, M_Q, M_L};
+constexpr int PAIR_B[4] = {M_G, M_H, M_K, M_P};
+
+struct RowArgs {
+  const double* phn;   // phi^n
+  const double* phm;   // phi^{n-1}
+  const double* phmm;  // phi^{n-2} (lagged ||d||^2 only)
+  const double* psn;
+  const double* psm;
+  const double* psmm;
+};
+
+__device__ __forceinline__ double ptilde(const StepConst& c, double psi, double p) {
+  return 0.5 * (c.gamma_in * (1.0 + p) * (psi - c.psi_in) +
+                c.gamma_out * (1.0 - p) * (psi - c.psi_out));
+}
+
+// One pass over the row: computes the field pairs whose bit is set in MASK at
+// every cell and stores them into LDS line (rank of the pair within MASK),
+// at the Makhoul slot of the cell; adds the partial sums whose inputs the pass
+// already has.
+template <typename TM, int NX, int NTHR, int MASK>
+__device__ __forceinline__ void stencil_pass(const RowArgs& a, cpx<TM>* line, double* sums, int j,
+                                             int ny, int tid, const StepConst& c) {
+  constexpr bool FG = MASK & (1 << PR_FG), SH = MASK & (1 << PR_SH);
+  constexpr bool QK = MASK & (1 << PR_QK), LP = MASK & (1 << PR_LP);
+  constexpr int LFG = 0;
+  constexpr int LSH = FG ? 1 : 0;
+  constexpr int LQK = (FG ? 1 : 0) + (SH ? 1 : 0);
+  constexpr int LLP = LQK + (QK ? 1 : 0);
+  const int jn = min(j + 1, ny - 1), js = max(j - 1, 0);
+  const double k32 = 0.75 * 1.4142135623730950488;   // 3 sqrt(2) / 4
+  const double half_pi = 1.5707963267948966192;
+  const double ieps = 1.0 / c.eps;
+#pragma unroll 1
+  for (int i = tid; i < NX; i += NTHR) {
+    const int ie = min(i + 1, NX - 1), iw = max(i - 1, 0);
+    const size_t oc = (size_t)j * NX + i, oe = (size_t)j * NX + ie, ow = (size_t)j * NX + iw;
+    const size_t on = (size_t)jn * NX + i, os = (size_t)js * NX + i;
+    const int slot = makhoul_slot<NX>(i);
+    const double phn_c = a.phn[oc], phm_c = a.phm[oc];
+    // phi* = x0 phi^n + x1 phi^{n-1} at the cell and its four neighbours
+    const double pc = c.x0 * phn_c + c.x1 * phm_c;
+    const double pe = c.x0 * a.phn[oe] + c.x1 * a.phm[oe];
+    const double pw = c.x0 * a.phn[ow] + c.x1 * a.phm[ow];
+    const double pn = c.x0 * a.phn[on] + c.x1 * a.phm[on];
+    const double ps = c.x0 * a.phn[os] + c.x1 * a.phm[os];
+    const double gxe = (pe - pc) * c.inv_h, gxw = (pc - pw) * c.inv_h;
+    const double gyn = (pn - pc) * c.inv_h, gys = (pc - ps) * c.inv_h;
+    const double pc2 = pc * pc;
+    const double cubic = pc2 * pc - pc;                      // phi*^3 - phi*
+    const double eph = c.e0 * phn_c + c.e1 * phm_c;          // SAV bracket weight
+    if constexpr (FG || SH) {
+      const double lap_p = (gxe - gxw + gyn - gys) * c.inv_h;
+      if constexpr (FG) {
+        const double psn_c = a.psn[oc], psm_c = a.psm[oc];
+        const double qc = c.x0 * psn_c + c.x1 * psm_c;
+        const double qe = c.x0 * a.psn[oe] + c.x1 * a.psm[oe];
+        const double qw = c.x0 * a.psn[ow] + c.x1 * a.psm[ow];
+        const double qn = c.x0 * a.psn[on] + c.x1 * a.psm[on];
+        const double qs = c.x0 * a.psn[os] + c.x1 * a.psm[os];
+        const double lap_q = (qe + qw + qn + qs - 4.0 * qc) * c.inv_h2;
+        const double f_lin = c.a0 * phn_c + c.a1 * phm_c - c.M_phi * c.theta_t * lap_p;
+        const double g_lin = c.a0 * psn_c + c.a1 * psm_c - c.lam * lap_q;
+        line[LFG * NX + slot] = {(TM)f_lin, (TM)g_lin};
+        if (c.lag_d) {
+          // ||d^n||^2 of the previous step: delta psi = psi^n - (2 psi^{n-1} - psi^{n-2}),
+          // mobility at the face average of 2 phi^{n-1} - phi^{n-2}.
+          const double dc = psn_c - 2.0 * psm_c + a.psmm[oc];
+          const double fc = 2.0 * phm_c - a.phmm[oc];
+          if (i < NX - 1) {
+            const double de = a.psn[oe] - 2.0 * a.psm[oe] + a.psmm[oe];
+            const double fe = 2.0 * a.phm[oe] - a.phmm[oe];
+            const double g = de - dc;
+            sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (fc + fe), c.M0);
+          }
+          if (j < ny - 1) {
+            const double dn = a.psn[on] - 2.0 * a.psm[on] + a.psmm[on];
+            const double fn = 2.0 * a.phm[on] - a.phmm[on];
+            const double g = dn - dc;
+            sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (fc + fn), c.M0);
+          }
+        }
+      }
+      if constexpr (SH) {
+        const double St = pc * (pc2 - 1.0 - c.beta) * 0.5 * ieps;
+        const double Hf = k32 * (cubic * ieps - c.eps * lap_p);
+        line[LSH * NX + slot] = {(TM)St, (TM)Hf};
+        const double vq = pc2 - 1.0 - c.beta;
+        sums[P1_RS] += vq * vq * 0.25 * ieps;
+        sums[P1_ES] += St * eph;
+        sums[P1_EH] += Hf * eph;
+      }
+    }
+    if constexpr (QK || LP) {
+      const double psn_c = a.psn[oc], psm_c = a.psm[oc];
+      const double qc = c.x0 * psn_c + c.x1 * psm_c;
+      double sp, cp;
+      sincospi(0.5 * pc, &sp, &cp);
+      const double din = qc - c.psi_in, dout = qc - c.psi_out;
+      const double fin = 0.5 * c.gamma_in * din * din + c.beta_in;
+      const double fout = 0.5 * c.gamma_out * dout * dout + c.beta_out;
+      const double Pc = ptilde(c, qc, sp);
+      if constexpr (QK) {
+        const double grad2 = 0.5 * (gxe * gxe + gxw * gxw + gyn * gyn + gys * gys);
+        const double div_a = 0.5 * ((pc2 + pe * pe) * gxe - (pw * pw + pc2) * gxw +
+                                    (pc2 + pn * pn) * gyn - (ps * ps + pc2) * gys) * c.inv_h;
+        const double Qt = 6.0 * (pc * grad2 - div_a) + cubic * (3.0 * pc2 - 1.0) * ieps * ieps;
+        const double Kt = 0.5 * half_pi * cp * (fin - fout);
+        line[LQK * NX + slot] = {(TM)Qt, (TM)Kt};
+        sums[P1_RW] += 6.0 * pc2 * grad2 + cubic * cubic * ieps * ieps;
+        sums[P1_RZ] += (1.0 + sp) * fin + (1.0 - sp) * fout;
+        sums[P1_EQ] += Qt * eph;
+        sums[P1_EK] += Kt * eph;
+      }
+      if constexpr (LP) {
+        const double qe = c.x0 * a.psn[oe] + c.x1 * a.psm[oe];
+        const double qw = c.x0 * a.psn[ow] + c.x1 * a.psm[ow];
+        const double qn = c.x0 * a.psn[on] + c.x1 * a.psm[on];
+        const double qs = c.x0 * a.psn[os] + c.x1 * a.psm[os];
+        const double Pe = ptilde(c, qe, sinpi(0.5 * pe));
+        const double Pw = ptilde(c, qw, sinpi(0.5 * pw));
+        const double Pn = ptilde(c, qn, sinpi(0.5 * pn));
+        const double Ps = ptilde(c, qs, sinpi(0.5 * ps));
+        const double Me = mobility(0.5 * (pc + pe), c.M0), Mw = mobility(0.5 * (pw + pc), c.M0);
+        const double Mn = mobility(0.5 * (pc + pn), c.M0), Ms = mobility(0.5 * (ps + pc), c.M0);
+        const double Lt =
+            (Me * (Pe - Pc) - Mw * (Pc - Pw) + Mn * (Pn - Pc) - Ms * (Pc - Ps)) * c.inv_h2;
+        line[LLP * NX + slot] = {(TM)Lt, (TM)Pc};
+        sums[P1_EP] += Pc * (c.e0 * psn_c + c.e1 * psm_c);
+        if (i < NX - 1 && !(Me > 0.0)) sums[P1_MOBNEG] += 1.0;
+        if (j < ny - 1 && !(Mn > 0.0)) sums[P1_MOBNEG] += 1.0;
+      }
+    }
+  }
+}
+
 template <typename TM, int NX>
-__global__ void __launch_bounds__(line_threads(NX))
-k_stencil_rowdct(const double* __restrict__ phn, const double* __restrict__ phm,
-                 const double* __restrict__ phmm, const double* __restrict__ psn,
-                 const double* __restrict__ psm, const double* __restrict__ psmm,
-                 TM* __restrict__ mid, double* __restrict__ part, int ny, StepConst c) {
-  constexpr int NTHR = line_threads(NX);
+__global__ void __launch_bounds__(stencil_threads<TM>(NX))
+k_stencil_rowdct(RowArgs a, TM* __restrict__ mid, double* __restrict__ part, int ny,
+                 StepConst c) {
+  constexpr int NTHR = stencil_threads<TM>(NX);
   constexpr int CPT = (NX + NTHR - 1) / NTHR;
-  __shared__ cpx<TM> line[NX];
+  // Each round computes NLINE field pairs straight into LDS lines and
+  // transforms them with one batched FFT; 4 / NLINE rounds cover the pairs.
+  constexpr int NLINE = lds_lines<TM>(NX);
+  __shared__ cpx<TM> line[NLINE * NX];
   __shared__ cpx<TM> rtab[Roots<TM, NX>::SIZE];
   __shared__ double red[P1_NSUM * (NTHR / 64 + 1)];
   const int tid = threadIdx.x;
@@ -86,139 +241,38 @@ k_stencil_rowdct(const double* __restrict__ phn, const double* __restrict__ phm,
   const size_t FS = (size_t)NX * ny;
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
-  const int jn = min(j + 1, ny - 1), js = max(j - 1, 0);
-  const double k32 = 0.75 * 1.4142135623730950488;   // 3 sqrt(2) / 4
-  const double half_pi = 1.5707963267948966192;
-  const double ieps = 1.0 / c.eps;
-
-  double F[M_NFIELD][CPT];
   double sums[P1_NSUM];
 #pragma unroll
   for (int q = 0; q < P1_NSUM; ++q) sums[q] = 0.0;
 
-#pragma unroll
-  for (int q = 0; q < CPT; ++q) {
-    const int i = tid + q * NTHR;
-    if (i < NX) {
-      const int ie = min(i + 1, NX - 1), iw = max(i - 1, 0);
-      const size_t oc = (size_t)j * NX + i, oe = (size_t)j * NX + ie, ow = (size_t)j * NX + iw;
-      const size_t on = (size_t)jn * NX + i, os = (size_t)js * NX + i;
-      const double phn_c = phn[oc], phm_c = phm[oc], psn_c = psn[oc], psm_c = psm[oc];
-      const double pc = c.x0 * phn_c + c.x1 * phm_c;
-      const double pe = c.x0 * phn[oe] + c.x1 * phm[oe];
-      const double pw = c.x0 * phn[ow] + c.x1 * phm[ow];
-      const double pn = c.x0 * phn[on] + c.x1 * phm[on];
-      const double ps = c.x0 * phn[os] + c.x1 * phm[os];
-      const double qc = c.x0 * psn_c + c.x1 * psm_c;
-      const double qe = c.x0 * psn[oe] + c.x1 * psm[oe];
-      const double qw = c.x0 * psn[ow] + c.x1 * psm[ow];
-      const double qn = c.x0 * psn[on] + c.x1 * psm[on];
-      const double qs = c.x0 * psn[os] + c.x1 * psm[os];
-
-      // face gradients of phi*, Laplacian, cell |grad phi*|^2, div(A(phi*^2) D phi*)
-      const double gxe = (pe - pc) * c.inv_h, gxw = (pc - pw) * c.inv_h;
-      const double gyn = (pn - pc) * c.inv_h, gys = (pc - ps) * c.inv_h;
-      const double lap_p = (gxe - gxw + gyn - gys) * c.inv_h;
-      const double grad2 = 0.5 * (gxe * gxe + gxw * gxw + gyn * gyn + gys * gys);
-      const double pc2 = pc * pc;
-      const double div_a = 0.5 * ((pc2 + pe * pe) * gxe - (pw * pw + pc2) * gxw +
-                                  (pc2 + pn * pn) * gyn - (ps * ps + pc2) * gys) * c.inv_h;
-      const double cubic = pc2 * pc - pc;                      // phi^3 - phi
-      const double St = pc * (pc2 - 1.0 - c.beta) * 0.5 * ieps;
-      const double Hf = k32 * (cubic * ieps - c.eps * lap_p);
-      const double Qt = 6.0 * (pc * grad2 - div_a) + cubic * (3.0 * pc2 - 1.0) * ieps * ieps;
-
-      // osmotic terms at the centre and the four neighbours
-      double sp, cp;
-      sincospi(0.5 * pc, &sp, &cp);
-      const double din = qc - c.psi_in, dout = qc - c.psi_out;
-      const double fin = 0.5 * c.gamma_in * din * din + c.beta_in;
-      const double fout = 0.5 * c.gamma_out * dout * dout + c.beta_out;
-      const double Kt = 0.5 * half_pi * cp * (fin - fout);
-      auto ptilde = [&](double ph, double ps_, double pp) {
-        return 0.5 * (c.gamma_in * (1.0 + pp) * (ps_ - c.psi_in) +
-                      c.gamma_out * (1.0 - pp) * (ps_ - c.psi_out));
-      };
-      const double Pc = ptilde(pc, qc, sp);
-      const double Pe = ptilde(pe, qe, sinpi(0.5 * pe));
-      const double Pw = ptilde(pw, qw, sinpi(0.5 * pw));
-      const double Pn = ptilde(pn, qn, sinpi(0.5 * pn));
-      const double Ps = ptilde(ps, qs, sinpi(0.5 * ps));
-      const double Me = mobility(0.5 * (pc + pe), c.M0), Mw = mobility(0.5 * (pw + pc), c.M0);
-      const double Mn = mobility(0.5 * (pc + pn), c.M0), Ms = mobility(0.5 * (ps + pc), c.M0);
-      const double Lt = (Me * (Pe - Pc) - Mw * (Pc - Pw) + Mn * (Pn - Pc) - Ms * (Pc - Ps)) * c.inv_h2;
-
-      const double lap_q = (qe + qw + qn + qs - 4.0 * qc) * c.inv_h2;
-      F[M_F][q] = c.a0 * phn_c + c.a1 * phm_c - c.M_phi * c.theta_t * lap_p;
-      F[M_G][q] = c.a0 * psn_c + c.a1 * psm_c - c.lam * lap_q;
-      F[M_S][q] = St;
-      F[M_H][q] = Hf;
-      F[M_Q][q] = Qt;
-      F[M_K][q] = Kt;
-      F[M_L][q] = Lt;
-      F[M_P][q] = Pc;
-
-      const double vq = pc2 - 1.0 - c.beta;
-      sums[P1_RS] += vq * vq * 0.25 * ieps;
-      sums[P1_RW] += 6.0 * pc2 * grad2 + cubic * cubic * ieps * ieps;
-      sums[P1_RZ] += (1.0 + sp) * fin + (1.0 - sp) * fout;
-      const double eph = c.e0 * phn_c + c.e1 * phm_c;
-      const double eps_ = c.e0 * psn_c + c.e1 * psm_c;
-      sums[P1_ES] += St * eph;
-      sums[P1_EH] += Hf * eph;
-      sums[P1_EQ] += Qt * eph;
-      sums[P1_EK] += Kt * eph;
-      sums[P1_EP] += Pc * eps_;
-      if (i < NX - 1 && !(Me > 0.0)) sums[P1_MOBNEG] += 1.0;
-      if (j < ny - 1 && !(Mn > 0.0)) sums[P1_MOBNEG] += 1.0;
-      if (c.lag_d) {
-        // ||d^n||^2 of the previous step: delta psi = psi^n - (2 psi^{n-1} - psi^{n-2}),
-        // mobility at the face average of 2 phi^{n-1} - phi^{n-2}.
-        const double dc = psn_c - 2.0 * psm_c + psmm[oc];
-        const double fc = 2.0 * phm_c - phmm[oc];
-        if (i < NX - 1) {
-          const double de = psn[oe] - 2.0 * psm[oe] + psmm[oe];
-          const double fe = 2.0 * phm[oe] - phmm[oe];
-          const double g = de - dc;
-          sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (fc + fe), c.M0);
-        }
-        if (j < ny - 1) {
-          const double dn = psn[on] - 2.0 * psm[on] + psmm[on];
-          const double fn = 2.0 * phm[on] - phmm[on];
-          const double g = dn - dc;
-          sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (fc + fn), c.M0);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int f = 0; f < M_NFIELD; ++f) F[f][q] = 0.0;
-    }
-  }
-
-  // Row DCT-II of the eight fields, two per complex FFT.
-  constexpr int PA[4] = {M_F, M_S, M_Q, M_L};
-  constexpr int PB[4] = {M_G, M_H, M_K, M_P};
-#pragma unroll
-  for (int pr = 0; pr < 4; ++pr) {
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int i = tid + q * NTHR;
-      if (i < NX) line[makhoul_slot<NX>(i)] = {(TM)F[PA[pr]][q], (TM)F[PB[pr]][q]};
-    }
+  auto round = [&](auto ir) {
+    constexpr int r = decltype(ir)::value;
+    constexpr int MASK = ((1 << NLINE) - 1) << (r * NLINE);
+    stencil_pass<TM, NX, NTHR, MASK>(a, line, sums, j, ny, tid, c);
     __syncthreads();
-    fft_lines<TM, NX, 1, NTHR>(line, rt, tid);
+    fft_lines<TM, NX, NLINE, NTHR>(line, rt, tid);
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      const int k = tid + q * NTHR;
-      if (k < NX) {
-        TM A, B;
-        dct2_post<TM, NX>(line, rt, k, A, B);
-        const size_t o = mid_index(k, j, ny);
-        mid[PA[pr] * FS + o] = A;
-        mid[PB[pr] * FS + o] = B;
+    for (int l = 0; l < NLINE; ++l) {
+      const int pr = r * NLINE + l;
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int k = tid + q * NTHR;
+        if (k < NX) {
+          TM A, B;
+          dct2_post<TM, NX>(line + l * NX, rt, k, A, B);
+          const size_t o = mid_index(k, j, ny);
+          mid[PAIR_A[pr] * FS + o] = A;
+          mid[PAIR_B[pr] * FS + o] = B;
+        }
       }
     }
     __syncthreads();
+  };
+  round(std::integral_constant<int, 0>{});
+  if constexpr (NLINE <= 2) round(std::integral_constant<int, 1>{});
+  if constexpr (NLINE == 1) {
+    round(std::integral_constant<int, 2>{});
+    round(std::integral_constant<int, 3>{});
   }
   block_sum<P1_NSUM, NTHR>(sums, red, tid);
   if (tid < P1_NSUM) part[(size_t)j * P1_NSUM + tid] = red[tid];
@@ -250,85 +304,144 @@ __device__ __forceinline__ void column_dct2(const cpx<TM>* __restrict__ src, cpx
   __syncthreads();
 }
 
+// Sum NV per-thread values over the block and add them to acc[IDX[q]].
+template <int NV, int NTHR>
+__device__ __forceinline__ void stage_accumulate(double (&v)[NV], const int (&idx)[NV],
+                                                 double* red, double* acc, int tid) {
+  block_sum<NV, NTHR>(v, red, tid);
+  if (tid < NV) acc[idx[tid]] += red[tid];
+}
+
 template <typename TM, int NY>
 __global__ void __launch_bounds__(line_threads(NY))
 k_col_gram(const TM* __restrict__ mid, const double* __restrict__ lamx,
            const double* __restrict__ lamy, double* __restrict__ part, int nx, StepConst c) {
   constexpr int NTHR = line_threads(NY);
   constexpr int KPT = (NY + NTHR - 1) / NTHR;
+  // FP64 up to 4096: the S~ spectrum waits in LDS, H, Q~, K~ in registers;
+  // otherwise all four stay in registers.
+  constexpr bool S_LDS = sizeof(TM) == 8 && NY <= 4096;
   __shared__ cpx<TM> line[NY];
+  __shared__ cpx<TM> keep[S_LDS ? NY : 1];
   __shared__ cpx<TM> rtab[Roots<TM, NY>::SIZE];
-  __shared__ double red[P2_NSUM * (NTHR / 64 + 1)];
+  __shared__ double red[8 * (NTHR / 64 + 1)];
+  __shared__ double acc[P2_NSUM];
   const int tid = threadIdx.x;
   const int s = xcd_remap(blockIdx.x, gridDim.x);
   const size_t FS = (size_t)nx * NY;
   Roots<TM, NY> rt;
   rt.init(rtab, tid, NTHR);
-
-  double isg0[KPT], isg1[KPT], itu0[KPT], itu1[KPT];
+  if (tid < P2_NSUM) acc[tid] = 0.0;
   const double lx0 = lamx[2 * s], lx1 = lamx[2 * s + 1];
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = tid + q * NTHR;
-    const double ly = (k < NY) ? lamy[k] : 0.0;
-    const double L0 = lx0 + ly, L1 = lx1 + ly;
-    isg0[q] = 1.0 / (c.C1 + L0 * (c.C2 + c.C3 * L0));
-    isg1[q] = 1.0 / (c.C1 + L1 * (c.C2 + c.C3 * L1));
-    itu0[q] = 1.0 / (c.alpha + c.lam * L0);
-    itu1[q] = 1.0 / (c.alpha + c.lam * L1);
-  }
   auto strip = [&](int f) {
     return reinterpret_cast<const cpx<TM>*>(mid + (size_t)f * FS) + (size_t)s * NY;
   };
-  double g[P2_NSUM];
-#pragma unroll
-  for (int q = 0; q < P2_NSUM; ++q) g[q] = 0.0;
-
-  // chi group: S~, H, Q~, K~ kept, f_lin consumed on the fly.
-  TM sa[4][KPT], sb[4][KPT];
+  // 1/sigma (chi) or 1/tau (zeta) at (2s, k) and (2s+1, k)
+  auto inv_op = [&](int k, bool chi, double& i0, double& i1) {
+    const double ly = (k < NY) ? lamy[k] : 0.0;
+    const double L0 = lx0 + ly, L1 = lx1 + ly;
+    if (chi) {
+      i0 = 1.0 / (c.C1 + L0 * (c.C2 + c.C3 * L0));
+      i1 = 1.0 / (c.C1 + L1 * (c.C2 + c.C3 * L1));
+    } else {
+      i0 = 1.0 / (c.alpha + c.lam * L0);
+      i1 = 1.0 / (c.alpha + c.lam * L1);
+    }
+  };
+  // Spectra kept for the pairwise products: index 0 = S~ (unless in LDS),
+  // 1 = H, 2 = Q~, 3 = K~.
+  TM ka[4][KPT], kb[4][KPT];
+  auto kept = [&](int f, int q, TM& a, TM& b) {
+    if (S_LDS && f == 0) {
+      const cpx<TM> v = keep[tid + q * NTHR];
+      a = v.re;
+      b = v.im;
+    } else {
+      a = ka[f][q];
+      b = kb[f][q];
+    }
+  };
   constexpr int CHI[4] = {M_S, M_H, M_Q, M_K};
-  // index of the Gram sum for the pair (a, b), a <= b, of S~, H, Q~, K~
   constexpr int GIDX[4][4] = {{P2_SS, P2_SH, P2_SQ, P2_SK},
                               {P2_SH, P2_HH, P2_HQ, P2_HK},
                               {P2_SQ, P2_HQ, P2_QQ, P2_QK},
                               {P2_SK, P2_HK, P2_QK, P2_KK}};
+  // chi group: S~, H, Q~, K~ in turn, each multiplied with the earlier ones.
+  auto chi_stage = [&](auto ia) {
+    constexpr int a = decltype(ia)::value;
+    TM A[KPT], B[KPT];
+    column_dct2<TM, NY, KPT, NTHR>(strip(CHI[a]), line, rt, tid, A, B);
+    double v[a + 1];
+    int idx[a + 1];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    column_dct2<TM, NY, KPT, NTHR>(strip(CHI[a]), line, rt, tid, sa[a], sb[a]);
+    for (int b = 0; b <= a; ++b) { v[b] = 0.0; idx[b] = GIDX[b][a]; }
 #pragma unroll
-    for (int b = 0; b <= a; ++b) {
+    for (int q = 0; q < KPT; ++q) {
+      if (tid + q * NTHR >= NY) continue;     // blocks wider than the line
+      double i0, i1;
+      inv_op(tid + q * NTHR, true, i0, i1);
 #pragma unroll
-      for (int q = 0; q < KPT; ++q)
-        g[GIDX[b][a]] += (double)sa[a][q] * (double)sa[b][q] * isg0[q] +
-                         (double)sb[a][q] * (double)sb[b][q] * isg1[q];
+      for (int b = 0; b < a; ++b) {
+        TM ea, eb;
+        kept(b, q, ea, eb);
+        v[b] += (double)A[q] * (double)ea * i0 + (double)B[q] * (double)eb * i1;
+      }
+      v[a] += (double)A[q] * (double)A[q] * i0 + (double)B[q] * (double)B[q] * i1;
+      if (S_LDS && a == 0) {
+        keep[tid + q * NTHR] = {A[q], B[q]};
+      } else {
+        ka[a][q] = A[q];
+        kb[a][q] = B[q];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    stage_accumulate<a + 1, NTHR>(v, idx, red, acc, tid);
+  };
+  chi_stage(std::integral_constant<int, 0>{});
+  chi_stage(std::integral_constant<int, 1>{});
+  chi_stage(std::integral_constant<int, 2>{});
+  chi_stage(std::integral_constant<int, 3>{});
+  // f_lin against the four kept spectra.
+  {
+    TM A[KPT], B[KPT];
+    column_dct2<TM, NY, KPT, NTHR>(strip(M_F), line, rt, tid, A, B);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    const int idx[4] = {P2_FS, P2_FH, P2_FQ, P2_FK};
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      if (tid + q * NTHR >= NY) continue;
+      double i0, i1;
+      inv_op(tid + q * NTHR, true, i0, i1);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        TM ea, eb;
+        kept(b, q, ea, eb);
+        v[b] += (double)A[q] * (double)ea * i0 + (double)B[q] * (double)eb * i1;
+      }
+    }
+    stage_accumulate<4, NTHR>(v, idx, red, acc, tid);
+  }
+  // zeta group: P~ kept (in the H slot), then g_lin and L~.
+  {
+    column_dct2<TM, NY, KPT, NTHR>(strip(M_P), line, rt, tid, ka[1], kb[1]);
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      TM A[KPT], B[KPT];
+      column_dct2<TM, NY, KPT, NTHR>(strip(g == 0 ? M_G : M_L), line, rt, tid, A, B);
+      double v[1] = {0.0};
+      const int idx[1] = {g == 0 ? P2_PG : P2_PL};
+#pragma unroll
+      for (int q = 0; q < KPT; ++q) {
+        if (tid + q * NTHR >= NY) continue;
+        double i0, i1;
+        inv_op(tid + q * NTHR, false, i0, i1);
+        v[0] += (double)A[q] * (double)ka[1][q] * i0 + (double)B[q] * (double)kb[1][q] * i1;
+      }
+      stage_accumulate<1, NTHR>(v, idx, red, acc, tid);
     }
   }
-  {
-    TM fa[KPT], fb[KPT];
-    column_dct2<TM, NY, KPT, NTHR>(strip(M_F), line, rt, tid, fa, fb);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-#pragma unroll
-      for (int q = 0; q < KPT; ++q)
-        g[P2_FS + b] += (double)fa[q] * (double)sa[b][q] * isg0[q] +
-                        (double)fb[q] * (double)sb[b][q] * isg1[q];
-    }
-  }
-  // zeta group: P~ kept, g_lin and L~ consumed on the fly.
-  {
-    TM pa[KPT], pb[KPT], xa[KPT], xb[KPT];
-    column_dct2<TM, NY, KPT, NTHR>(strip(M_P), line, rt, tid, pa, pb);
-    column_dct2<TM, NY, KPT, NTHR>(strip(M_G), line, rt, tid, xa, xb);
-#pragma unroll
-    for (int q = 0; q < KPT; ++q)
-      g[P2_PG] += (double)pa[q] * (double)xa[q] * itu0[q] + (double)pb[q] * (double)xb[q] * itu1[q];
-    column_dct2<TM, NY, KPT, NTHR>(strip(M_L), line, rt, tid, xa, xb);
-#pragma unroll
-    for (int q = 0; q < KPT; ++q)
-      g[P2_PL] += (double)pa[q] * (double)xa[q] * itu0[q] + (double)pb[q] * (double)xb[q] * itu1[q];
-  }
-  block_sum<P2_NSUM, NTHR>(g, red, tid);
-  if (tid < P2_NSUM) part[(size_t)s * P2_NSUM + tid] = red[tid];
+  __syncthreads();
+  if (tid < P2_NSUM) part[(size_t)s * P2_NSUM + tid] = acc[tid];
 }
 
 // ---------------------------------------------------------------------------
@@ -549,7 +662,7 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
   for (int q = 0; q < KPT; ++q) {
     const int i = tid + q * NTHR;
     if (i < NY) {
-      const cpx<TM> y = line[makhoul_slot<NY>(i)];
+      const cpx<TM> y = line[fft_pos<NY>(makhoul_slot<NY>(i))];
       dst[i] = {y.re, -y.im};
     }
   }
@@ -587,7 +700,7 @@ k_row_idct(const TM* __restrict__ out, double* __restrict__ phi_new, double* __r
   for (int q = 0; q < CPT; ++q) {
     const int i = tid + q * NTHR;
     if (i < NX) {
-      const cpx<TM> y = line[makhoul_slot<NX>(i)];
+      const cpx<TM> y = line[fft_pos<NX>(makhoul_slot<NX>(i))];
       phi_new[(size_t)j * NX + i] = (double)y.re;
       psi_new[(size_t)j * NX + i] = -(double)y.im;
     }
