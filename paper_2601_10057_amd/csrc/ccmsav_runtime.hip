@@ -50,7 +50,7 @@ template <typename TM> struct Launch {
   template <int N>
   static void p2(hipStream_t st, int grid, const TM* mid, const double* lx, const double* ly,
                  double* part, int nx, const StepConst& k) {
-    hipLaunchKernelGGL((k_col_gram<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, mid, lx, ly,
+    hipLaunchKernelGGL((k_col_gram<TM, N>), dim3(grid), dim3(gram_threads(N)), 0, st, mid, lx, ly,
                        part, nx, k);
   }
   template <int N>

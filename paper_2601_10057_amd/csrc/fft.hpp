@@ -68,45 +68,74 @@ template <typename T> struct SmallDFT<T, 1> {
   static __device__ __forceinline__ void run(cpx<T>*) {}
 };
 
-// Roots of unity omega(m) = exp(-2 pi i m / (4N)) from two short tables in LDS:
-// omega(m) = hi[m >> S] * lo[m & (2^S - 1)], both entries from sincospi in FP64.
+// Roots of unity omega(m) = exp(-2 pi i m / (4N)) from two short FP64 tables in
+// LDS: omega(m) = hi[m >> S] * lo[m & (2^S - 1)], entries from sincospi.
 template <typename T, int N> struct Roots {
   static constexpr int M = 4 * N;
   static constexpr int LOGM = ilog2(M);
   static constexpr int S = (LOGM + 1) / 2;
   static constexpr int NLO = 1 << S;
   static constexpr int NHI = M >> S;
-  static constexpr int SIZE = NLO + NHI;     // complex entries of LDS needed
-  cpx<T>* lo;
-  cpx<T>* hi;
+  static constexpr int SIZE = NLO + NHI;     // FP64 complex entries of LDS needed
+  cpx<double>* lo;
+  cpx<double>* hi;
 
-  __device__ void init(cpx<T>* smem, int tid, int nthr) {
+  __device__ void init(cpx<double>* smem, int tid, int nthr) {
     lo = smem;
     hi = smem + NLO;
     for (int q = tid; q < NLO; q += nthr) {
       double s, c;
       sincospi(-2.0 * (double)q / (double)M, &s, &c);
-      lo[q] = {(T)c, (T)s};
+      lo[q] = {c, s};
     }
     for (int q = tid; q < NHI; q += nthr) {
       double s, c;
       sincospi(-2.0 * (double)q * (double)NLO / (double)M, &s, &c);
-      hi[q] = {(T)c, (T)s};
+      hi[q] = {c, s};
     }
   }
-  __device__ __forceinline__ cpx<T> omega(int m) const {
+  __device__ __forceinline__ cpx<double> omega64(int m) const {
     return cmul(hi[m >> S], lo[m & (NLO - 1)]);
   }
-  // exp(-2 pi i m / N)
-  __device__ __forceinline__ cpx<T> tw(int m) const { return omega(4 * m); }
+  __device__ __forceinline__ cpx<T> omega(int m) const {
+    const cpx<double> w = omega64(m);
+    return {(T)w.re, (T)w.im};
+  }
+  // exp(-2 pi i m / N) in FP64
+  __device__ __forceinline__ cpx<double> tw64(int m) const { return omega64(4 * m); }
 };
 
-// Radix plan: radix-8 stages, with one smaller stage first when log2 N is not
-// a multiple of 3.
-template <int N> struct Plan {
+// Radix of the FFT stages: 16 for FP32 lines, 8 for FP64 lines (register
+// budget of one butterfly).
+template <typename T> constexpr int fft_radix() { return sizeof(T) == 4 ? 16 : 8; }
+
+// Stage plan: radix-RADIX stages with one smaller stage first when log2 N is
+// not a multiple of log2 RADIX.
+template <int N, int RADIX> struct Plan {
   static constexpr int LOGN = ilog2(N);
-  static constexpr int FIRST = (LOGN % 3 == 0) ? 8 : (LOGN % 3 == 1 ? 2 : 4);
+  static constexpr int LR = ilog2(RADIX);
+  static constexpr int REM = LOGN % LR;
+  static constexpr int FIRST = REM == 0 ? RADIX : (1 << REM);
 };
+
+// LDS position of element e of a line: an XOR swizzle inside aligned groups of
+// 32 elements that keeps every FFT stage, including the short-stride last
+// ones, free of bank conflicts for 8- and 16-byte elements.
+__device__ __forceinline__ int lds_pos(int e) { return e ^ ((e >> 5) & 31); }
+
+// Multiplies v[q] by w^q, q = 1..R-1, for w = exp(-2 pi i t / N): one table
+// lookup, then the powers by a running FP64 product (relative error about
+// R ulp of FP64), each rounded to T.
+template <typename T, int N, int R>
+__device__ __forceinline__ void apply_twiddles(const Roots<T, N>& rt, int t, cpx<T>* v) {
+  const cpx<double> w1 = rt.tw64(t);
+  cpx<double> w = w1;
+#pragma unroll
+  for (int q = 1; q < R; ++q) {
+    v[q] = cmul(v[q], cpx<T>{(T)w.re, (T)w.im});
+    if (q + 1 < R) w = cmul(w, w1);
+  }
+}
 
 // One in-place decimation-in-frequency stage over NL independent lines of
 // length N stored back to back. With block length L and radix R, butterfly m
@@ -122,17 +151,15 @@ __device__ __forceinline__ void dif_stage(cpx<T>* buf, const Roots<T, N>& rt, in
   for (int b = tid; b < TOT; b += NTHR) {
     const int line = b / NB, jb = b % NB;
     const int blk = jb / S, m = jb % S;
-    cpx<T>* x = buf + line * N + blk * L + m;
+    cpx<T>* x = buf + line * N;
+    const int e0 = blk * L + m;
     cpx<T> v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = x[r * S];
+    for (int r = 0; r < R; ++r) v[r] = x[lds_pos(e0 + r * S)];
     SmallDFT<T, R>::run(v);
-    if (L > R) {
+    if (L > R) apply_twiddles<T, N, R>(rt, m * (N / L), v);
 #pragma unroll
-      for (int q = 1; q < R; ++q) v[q] = cmul(v[q], rt.tw(m * q * (N / L)));
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q) x[q * S] = v[q];
+    for (int q = 0; q < R; ++q) x[lds_pos(e0 + q * S)] = v[q];
   }
   __syncthreads();
 }
@@ -141,7 +168,8 @@ template <typename T, int N, int NL, int NTHR, int L, bool FIRST>
 struct DifRunner {
   static __device__ __forceinline__ void run(cpx<T>* buf, const Roots<T, N>& rt, int tid) {
     if constexpr (L > 1) {
-      constexpr int R = FIRST ? Plan<N>::FIRST : 8;
+      constexpr int RADIX = fft_radix<T>();
+      constexpr int R = FIRST ? Plan<N, RADIX>::FIRST : RADIX;
       dif_stage<T, N, NL, NTHR, R, L>(buf, rt, tid);
       DifRunner<T, N, NL, NTHR, L / R, false>::run(buf, rt, tid);
     }
@@ -149,29 +177,37 @@ struct DifRunner {
 };
 
 // Forward complex FFT (exp(-2 pi i n k / N)) of NL lines in LDS, in place:
-// natural order in, bin k found at fft_pos<N>(k) out. The caller must have
-// synchronised after writing the input; the FFT ends with a barrier.
+// element e of a line lives at lds_pos(e); input in natural order, bin k found
+// at bin_pos<T, N>(k). The caller must have synchronised after writing the
+// input; the FFT ends with a barrier.
 template <typename T, int N, int NL, int NTHR>
 __device__ __forceinline__ void fft_lines(cpx<T>* buf, const Roots<T, N>& rt, int tid) {
   DifRunner<T, N, NL, NTHR, N, true>::run(buf, rt, tid);
 }
 
-// Position of DFT bin k after fft_lines: the mixed-radix digits of k
-// (first radix, then radix 8) in reverse order.
-template <int N> __device__ __forceinline__ int fft_pos(int k) {
-  constexpr int R1 = Plan<N>::FIRST;
+// Position of DFT bin k after fft_lines (before the swizzle): the mixed-radix
+// digits of k (first radix, then the stage radix) in reverse order.
+template <typename T, int N> __device__ __forceinline__ int fft_pos(int k) {
+  constexpr int RADIX = fft_radix<T>();
+  using P = Plan<N, RADIX>;
+  constexpr int R1 = P::FIRST;
   constexpr int LR1 = ilog2(R1);
-  constexpr int ND = (Plan<N>::LOGN - LR1) / 3;
+  constexpr int ND = (P::LOGN - LR1) / P::LR;
   int span = N / R1;
   int p = (k & (R1 - 1)) * span;
   k >>= LR1;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    span >>= 3;
-    p += (k & 7) * span;
-    k >>= 3;
+    span >>= P::LR;
+    p += (k & (RADIX - 1)) * span;
+    k >>= P::LR;
   }
   return p;
+}
+
+// LDS position of bin k after fft_lines.
+template <typename T, int N> __device__ __forceinline__ int bin_pos(int k) {
+  return lds_pos(fft_pos<T, N>(k));
 }
 
 // Makhoul position of natural index i inside the reordered line.
@@ -188,8 +224,8 @@ template <int N> __device__ __forceinline__ int makhoul_index(int n) {
 template <typename T, int N>
 __device__ __forceinline__ void dct2_post(const cpx<T>* Z, const Roots<T, N>& rt, int k,
                                           T& A, T& B) {
-  const cpx<T> z = Z[fft_pos<N>(k)];
-  const cpx<T> zm = Z[fft_pos<N>((N - k) & (N - 1))];
+  const cpx<T> z = Z[bin_pos<T, N>(k)];
+  const cpx<T> zm = Z[bin_pos<T, N>((N - k) & (N - 1))];
   const T s = (k == 0) ? (T)(0.5 * sqrt(1.0 / N)) : (T)(0.5 * sqrt(2.0 / N));
   const T v1r = z.re + zm.re, v1i = z.im - zm.im;
   const T v2r = z.im + zm.im, v2i = zm.re - z.re;

@@ -36,6 +36,9 @@ constexpr int line_threads(int n) { return clamp_threads(n / 4); }
 template <typename TM> constexpr int stencil_threads(int n) {
   return clamp_threads(n / 4);
 }
+// The Gram kernel keeps four spectra per thread: eight bins per thread give
+// each wave up to 256 registers at one workgroup per CU.
+constexpr int gram_threads(int n) { return clamp_threads(n / 8); }
 // Field-pair lines of the row pass that fit in LDS next to the twiddle tables.
 template <typename TM> constexpr int lds_lines(int n) {
   const int fit = (136 * 1024) / (n * (int)sizeof(cpx<TM>));
@@ -151,7 +154,7 @@ __device__ __forceinline__ void stencil_pass(const RowArgs& a, cpx<TM>* line, do
         const double lap_q = (qe + qw + qn + qs - 4.0 * qc) * c.inv_h2;
         const double f_lin = c.a0 * phn_c + c.a1 * phm_c - c.M_phi * c.theta_t * lap_p;
         const double g_lin = c.a0 * psn_c + c.a1 * psm_c - c.lam * lap_q;
-        line[LFG * NX + slot] = {(TM)f_lin, (TM)g_lin};
+        line[LFG * NX + lds_pos(slot)] = {(TM)f_lin, (TM)g_lin};
         if (c.lag_d) {
           // ||d^n||^2 of the previous step: delta psi = psi^n - (2 psi^{n-1} - psi^{n-2}),
           // mobility at the face average of 2 phi^{n-1} - phi^{n-2}.
@@ -174,7 +177,7 @@ __device__ __forceinline__ void stencil_pass(const RowArgs& a, cpx<TM>* line, do
       if constexpr (SH) {
         const double St = pc * (pc2 - 1.0 - c.beta) * 0.5 * ieps;
         const double Hf = k32 * (cubic * ieps - c.eps * lap_p);
-        line[LSH * NX + slot] = {(TM)St, (TM)Hf};
+        line[LSH * NX + lds_pos(slot)] = {(TM)St, (TM)Hf};
         const double vq = pc2 - 1.0 - c.beta;
         sums[P1_RS] += vq * vq * 0.25 * ieps;
         sums[P1_ES] += St * eph;
@@ -196,7 +199,7 @@ __device__ __forceinline__ void stencil_pass(const RowArgs& a, cpx<TM>* line, do
                                     (pc2 + pn * pn) * gyn - (ps * ps + pc2) * gys) * c.inv_h;
         const double Qt = 6.0 * (pc * grad2 - div_a) + cubic * (3.0 * pc2 - 1.0) * ieps * ieps;
         const double Kt = 0.5 * half_pi * cp * (fin - fout);
-        line[LQK * NX + slot] = {(TM)Qt, (TM)Kt};
+        line[LQK * NX + lds_pos(slot)] = {(TM)Qt, (TM)Kt};
         sums[P1_RW] += 6.0 * pc2 * grad2 + cubic * cubic * ieps * ieps;
         sums[P1_RZ] += (1.0 + sp) * fin + (1.0 - sp) * fout;
         sums[P1_EQ] += Qt * eph;
@@ -215,7 +218,7 @@ __device__ __forceinline__ void stencil_pass(const RowArgs& a, cpx<TM>* line, do
         const double Mn = mobility(0.5 * (pc + pn), c.M0), Ms = mobility(0.5 * (ps + pc), c.M0);
         const double Lt =
             (Me * (Pe - Pc) - Mw * (Pc - Pw) + Mn * (Pn - Pc) - Ms * (Pc - Ps)) * c.inv_h2;
-        line[LLP * NX + slot] = {(TM)Lt, (TM)Pc};
+        line[LLP * NX + lds_pos(slot)] = {(TM)Lt, (TM)Pc};
         sums[P1_EP] += Pc * (c.e0 * psn_c + c.e1 * psm_c);
         if (i < NX - 1 && !(Me > 0.0)) sums[P1_MOBNEG] += 1.0;
         if (j < ny - 1 && !(Mn > 0.0)) sums[P1_MOBNEG] += 1.0;
@@ -234,7 +237,7 @@ k_stencil_rowdct(RowArgs a, TM* __restrict__ mid, double* __restrict__ part, int
   // transforms them with one batched FFT; 4 / NLINE rounds cover the pairs.
   constexpr int NLINE = lds_lines<TM>(NX);
   __shared__ cpx<TM> line[NLINE * NX];
-  __shared__ cpx<TM> rtab[Roots<TM, NX>::SIZE];
+  __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   __shared__ double red[P1_NSUM * (NTHR / 64 + 1)];
   const int tid = threadIdx.x;
   const int j = xcd_remap(blockIdx.x, gridDim.x);
@@ -288,7 +291,7 @@ __device__ __forceinline__ void column_dct2(const cpx<TM>* __restrict__ src, cpx
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
     const int jj = tid + q * NTHR;
-    if (jj < NY) line[makhoul_slot<NY>(jj)] = src[jj];
+    if (jj < NY) line[lds_pos(makhoul_slot<NY>(jj))] = src[jj];
   }
   __syncthreads();
   fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
@@ -313,17 +316,17 @@ __device__ __forceinline__ void stage_accumulate(double (&v)[NV], const int (&id
 }
 
 template <typename TM, int NY>
-__global__ void __launch_bounds__(line_threads(NY))
+__global__ void __launch_bounds__(gram_threads(NY))
 k_col_gram(const TM* __restrict__ mid, const double* __restrict__ lamx,
            const double* __restrict__ lamy, double* __restrict__ part, int nx, StepConst c) {
-  constexpr int NTHR = line_threads(NY);
+  constexpr int NTHR = gram_threads(NY);
   constexpr int KPT = (NY + NTHR - 1) / NTHR;
   // FP64 up to 4096: the S~ spectrum waits in LDS, H, Q~, K~ in registers;
   // otherwise all four stay in registers.
   constexpr bool S_LDS = sizeof(TM) == 8 && NY <= 4096;
   __shared__ cpx<TM> line[NY];
   __shared__ cpx<TM> keep[S_LDS ? NY : 1];
-  __shared__ cpx<TM> rtab[Roots<TM, NY>::SIZE];
+  __shared__ cpx<double> rtab[Roots<TM, NY>::SIZE];
   __shared__ double red[8 * (NTHR / 64 + 1)];
   __shared__ double acc[P2_NSUM];
   const int tid = threadIdx.x;
@@ -582,7 +585,7 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
   constexpr int NTHR = line_threads(NY);
   constexpr int KPT = (NY + NTHR - 1) / NTHR;
   __shared__ cpx<TM> line[NY];
-  __shared__ cpx<TM> rtab[Roots<TM, NY>::SIZE];
+  __shared__ cpx<double> rtab[Roots<TM, NY>::SIZE];
   const int tid = threadIdx.x;
   const int lin = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
   const int nstrip = gridDim.x;
@@ -607,7 +610,7 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
         ur += cf[f] * (double)v.re;
         ui += cf[f] * (double)v.im;
       }
-      line[makhoul_slot<NY>(jj)] = {(TM)ur, (TM)ui};
+      line[lds_pos(makhoul_slot<NY>(jj))] = {(TM)ur, (TM)ui};
     }
   }
   __syncthreads();
@@ -637,7 +640,7 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
     const int k = tid + q * NTHR;
-    if (k < NY) line[k] = {A[q], B[q]};
+    if (k < NY) line[lds_pos(k)] = {A[q], B[q]};
   }
   __syncthreads();
   cpx<TM> Z[KPT];
@@ -645,7 +648,7 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
   for (int q = 0; q < KPT; ++q) {
     const int k = tid + q * NTHR;
     if (k < NY) {
-      const cpx<TM> m = line[(NY - k) & (NY - 1)];
+      const cpx<TM> m = line[lds_pos((NY - k) & (NY - 1))];
       Z[q] = dct3_pre<TM, NY>(rt, k, A[q], m.re, B[q], m.im);
     }
   }
@@ -653,7 +656,7 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
     const int k = tid + q * NTHR;
-    if (k < NY) line[k] = Z[q];
+    if (k < NY) line[lds_pos(k)] = Z[q];
   }
   __syncthreads();
   fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
@@ -662,7 +665,7 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
   for (int q = 0; q < KPT; ++q) {
     const int i = tid + q * NTHR;
     if (i < NY) {
-      const cpx<TM> y = line[fft_pos<NY>(makhoul_slot<NY>(i))];
+      const cpx<TM> y = line[lds_pos(fft_pos<TM, NY>(makhoul_slot<NY>(i)))];
       dst[i] = {y.re, -y.im};
     }
   }
@@ -678,7 +681,7 @@ k_row_idct(const TM* __restrict__ out, double* __restrict__ phi_new, double* __r
   constexpr int NTHR = line_threads(NX);
   constexpr int CPT = (NX + NTHR - 1) / NTHR;
   __shared__ cpx<TM> line[NX];
-  __shared__ cpx<TM> rtab[Roots<TM, NX>::SIZE];
+  __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   const int tid = threadIdx.x;
   const int j = xcd_remap(blockIdx.x, gridDim.x);
   const size_t FS = (size_t)NX * ny;
@@ -691,7 +694,7 @@ k_row_idct(const TM* __restrict__ out, double* __restrict__ phi_new, double* __r
     if (k < NX) {
       const int km = (NX - k) & (NX - 1);
       const size_t ok = mid_index(k, j, ny), om = mid_index(km, j, ny);
-      line[k] = dct3_pre<TM, NX>(rt, k, out[ok], out[om], out[FS + ok], out[FS + om]);
+      line[lds_pos(k)] = dct3_pre<TM, NX>(rt, k, out[ok], out[om], out[FS + ok], out[FS + om]);
     }
   }
   __syncthreads();
@@ -700,7 +703,7 @@ k_row_idct(const TM* __restrict__ out, double* __restrict__ phi_new, double* __r
   for (int q = 0; q < CPT; ++q) {
     const int i = tid + q * NTHR;
     if (i < NX) {
-      const cpx<TM> y = line[fft_pos<NX>(makhoul_slot<NX>(i))];
+      const cpx<TM> y = line[lds_pos(fft_pos<TM, NX>(makhoul_slot<NX>(i)))];
       phi_new[(size_t)j * NX + i] = (double)y.re;
       psi_new[(size_t)j * NX + i] = -(double)y.im;
     }
@@ -716,7 +719,7 @@ k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, 
   constexpr int NTHR = line_threads(NX);
   constexpr int CPT = (NX + NTHR - 1) / NTHR;
   __shared__ cpx<TM> line[NX];
-  __shared__ cpx<TM> rtab[Roots<TM, NX>::SIZE];
+  __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   const int tid = threadIdx.x;
   const int j = xcd_remap(blockIdx.x, gridDim.x);
   const size_t FS = (size_t)NX * ny;
@@ -725,7 +728,7 @@ k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, 
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int i = tid + q * NTHR;
-    if (i < NX) line[makhoul_slot<NX>(i)] = {(TM)src[(size_t)j * NX + i], (TM)0};
+    if (i < NX) line[lds_pos(makhoul_slot<NX>(i))] = {(TM)src[(size_t)j * NX + i], (TM)0};
   }
   __syncthreads();
   fft_lines<TM, NX, 1, NTHR>(line, rt, tid);
