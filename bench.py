@@ -30,7 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # fields are FP64 (fp64) or FP32 (mixed). The stencil pass reads phi, psi at
 # levels n, n-1 (and n-2 for the lagged ||d||^2) and writes eight fields; the
 # column pass reads the eight; the column solve reads seven and writes two;
-# the row inverse reads two and writes the two new state fields.
+# the row inverse reads two and writes the two new state fields. The mixed
+# path solves for increments, so its row inverse also reads phi^n, psi^n.
 def kernel_bytes_per_cell(precision: str):
     m = 8 if precision == "fp64" else 4
     return {
@@ -38,7 +39,7 @@ def kernel_bytes_per_cell(precision: str):
         "col_gram": 8 * m,
         "solve5": 0,
         "col_solve": 7 * m + 2 * m,
-        "row_idct": 2 * m + 2 * 8,
+        "row_idct": 2 * m + 2 * 8 + (2 * 8 if precision == "mixed" else 0),
     }
 
 

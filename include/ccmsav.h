@@ -50,7 +50,12 @@ typedef enum {
 
 typedef enum {
   CCMSAV_FP64 = 0,          /* all arithmetic in FP64 */
-  CCMSAV_MIXED = 1          /* FP32 transforms of FP64-formed right-hand sides;
+  CCMSAV_MIXED = 1          /* FP32 transforms; the step is solved for the
+                               increments phi^{n+1} - phi^n, psi^{n+1} - psi^n
+                               from residuals formed in FP64 (the chi residual
+                               uses the biharmonic Delta_h^2 phi^n), and the
+                               mean of the psi increment is fixed in FP64 so
+                               that h^2 sum psi is conserved to FP64 rounding.
                                FP64 state, SAVs, inner-product sums and 5x5 */
 } ccmsav_precision;
 

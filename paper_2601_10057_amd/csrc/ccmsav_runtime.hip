@@ -37,8 +37,9 @@ template <typename TM> struct Launch {
   using P2 = void (*)(hipStream_t, int, const TM*, const double*, const double*, double*, int,
                       const StepConst&);
   using P3 = void (*)(hipStream_t, int, const TM*, const double*, const double*, const double*,
-                      TM*, int, int, int, int, int, const StepConst&);
-  using P4 = void (*)(hipStream_t, int, const TM*, double*, double*, int);
+                      TM*, int, int, int, int, int, double*, const StepConst&);
+  using P4 = void (*)(hipStream_t, int, const TM*, double*, double*, int, const double*,
+                      const double*, const double*);
   using RD = void (*)(hipStream_t, int, const double*, TM*, int, int);
 
   template <int N>
@@ -56,14 +57,15 @@ template <typename TM> struct Launch {
   template <int N>
   static void p3(hipStream_t st, int grid, const TM* mid, const double* lx, const double* ly,
                  const double* coef, TM* out, int nx, int cb, int nc, int zb, int nz,
-                 const StepConst& k) {
+                 double* colsum, const StepConst& k) {
     hipLaunchKernelGGL((k_col_solve<TM, N>), dim3(grid, 2), dim3(line_threads(N)), 0, st, mid,
-                       lx, ly, coef, out, nx, cb, nc, zb, nz, k);
+                       lx, ly, coef, out, nx, cb, nc, zb, nz, colsum, k);
   }
   template <int N>
-  static void p4(hipStream_t st, int grid, const TM* out, double* phi, double* psi, int ny) {
+  static void p4(hipStream_t st, int grid, const TM* out, double* phi, double* psi, int ny,
+                 const double* phi_base, const double* psi_base, const double* colsum) {
     hipLaunchKernelGGL((k_row_idct<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, out, phi,
-                       psi, ny);
+                       psi, ny, phi_base, psi_base, colsum);
   }
   template <int N>
   static void rd(hipStream_t st, int grid, const double* src, TM* mid, int slot, int ny) {
@@ -99,6 +101,7 @@ struct ccmsav_ctx {
   double* parte;           // ny * max(E_NSUM, I_NSUM)
   double* lamx;            // (4/h^2) sin^2(pi k / (2 nx))
   double* lamy;
+  double* colsum;          // increment form: FP64 row-sum targets of the psi increment
   double* unit_coef;       // {1, 0, 0, 0, 0, 1, 0, 0} for the standalone solve
   DevScalars* ds;
   int64_t level;
@@ -111,7 +114,7 @@ namespace {
 size_t mid_elem(const ccmsav_params* p) { return p->precision == CCMSAV_MIXED ? 4 : 8; }
 
 struct Layout {
-  size_t state, mid, outc, part1, part2, parte, lamx, lamy, unit, ds, total;
+  size_t state, mid, outc, part1, part2, parte, lamx, lamy, colsum, unit, ds, total;
 };
 
 Layout layout(const ccmsav_params* p) {
@@ -126,6 +129,7 @@ Layout layout(const ccmsav_params* p) {
   L.parte = off; off = align_up(off + (size_t)p->ny * E_NSUM * sizeof(double));
   L.lamx = off;  off = align_up(off + (size_t)p->nx * sizeof(double));
   L.lamy = off;  off = align_up(off + (size_t)p->ny * sizeof(double));
+  L.colsum = off; off = align_up(off + (size_t)p->ny * sizeof(double));
   L.unit = off;  off = align_up(off + 8 * sizeof(double));
   L.ds = off;    off = align_up(off + sizeof(DevScalars));
   L.total = off;
@@ -201,6 +205,7 @@ StepConst make_const(const ccmsav_ctx* c, bool bdf2) {
   k.cga = p.M_phi * p.gamma_area;
   k.cgb = p.M_phi * p.gamma_bend * 3.0 * r2 / (8.0 * p.eps);
   k.cgo = p.M_phi;
+  k.C1b = k.C1 - k.alpha;
   k.half_dt = 0.5 * p.dt;
   return k;
 }
@@ -284,11 +289,13 @@ void enqueue_step(ccmsav_ctx* c, PhaseEvents pe = PhaseEvents{nullptr}) {
                      nx / 2, c->ds, k);
   pe.mark(5, c->stream);
   pe.mark(6, c->stream);
+  // The FP32-transform path solves for increments over level n (see increment_form).
+  double* colsum = increment_form<TM>() ? c->colsum : nullptr;
   LT::t3[c->ly - kMinLog](c->stream, nx / 2, mid, c->lamx, c->lamy, c->ds->coef, outc, nx, M_F, 5,
-                          M_G, 2, k);
+                          M_G, 2, colsum, k);
   pe.mark(7, c->stream);
   pe.mark(8, c->stream);
-  LT::t4[c->lx - kMinLog](c->stream, ny, outc, c->phi[snew], c->psi[snew], ny);
+  LT::t4[c->lx - kMinLog](c->stream, ny, outc, c->phi[snew], c->psi[snew], ny, phn, psn, colsum);
   pe.mark(9, c->stream);
   c->level += 1;
 }
@@ -302,14 +309,14 @@ void enqueue_solve(ccmsav_ctx* c, const double* rhs) {
   using LT = typename Launch<TM>::T;
   LT::trd[c->lx - kMinLog](c->stream, ny, rhs, mid, M_F, ny);
   LT::t3[c->ly - kMinLog](c->stream, nx / 2, mid, c->lamx, c->lamy, c->unit_coef, outc, nx, M_F,
-                          1, M_F, 1, k);
+                          1, M_F, 1, nullptr, k);
 }
 
 template <typename TM>
 void enqueue_final_rows(ccmsav_ctx* c, double* phi_out, double* psi_out) {
   using LT = typename Launch<TM>::T;
   LT::t4[c->lx - kMinLog](c->stream, c->p.ny, static_cast<TM*>(c->outc), phi_out, psi_out,
-                          c->p.ny);
+                          c->p.ny, nullptr, nullptr, nullptr);
 }
 
 const char* kStatusText[] = {
@@ -371,6 +378,7 @@ int ccmsav_init(ccmsav_ctx** out, const ccmsav_params* p, const double* phi0, co
   c->parte = reinterpret_cast<double*>(base + L.parte);
   c->lamx = reinterpret_cast<double*>(base + L.lamx);
   c->lamy = reinterpret_cast<double*>(base + L.lamy);
+  c->colsum = reinterpret_cast<double*>(base + L.colsum);
   c->unit_coef = reinterpret_cast<double*>(base + L.unit);
   c->ds = reinterpret_cast<DevScalars*>(base + L.ds);
   c->level = 0;

@@ -17,6 +17,11 @@ enum P1Sum {
   P1_EP,          // sum P~ e_psi
   P1_DLAG,        // sum over faces (D delta psi)^2 / M_face of the previous step
   P1_MOBNEG,      // number of faces with M_psi(A phi*) <= 0
+  P1_XS,          // increment form only: sum S~ phi^n, H phi^n, Q~ phi^n, K~ phi^n
+  P1_XH,
+  P1_XQ,
+  P1_XK,
+  P1_XP,          // increment form only: sum P~ psi^n
   P1_NSUM
 };
 
@@ -82,6 +87,7 @@ struct StepConst {
   double c0, c1;         // s = c0 SAV^n + c1 SAV^{n-1} + h^2 sum F e
   double alpha;          // 3/(2 dt) or 1/dt
   double C1, C2, C3;     // chi spectrum sigma = C1 + C2 L + C3 L^2
+  double C1b;            // C1 - alpha (the surface-energy part of C1)
   double cgs, cga, cgb, cgo;
   double half_dt;
   int lag_d;             // accumulate ||d^n||^2 of the previous (BDF2) step

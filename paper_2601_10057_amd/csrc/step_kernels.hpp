@@ -80,6 +80,12 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red, int tid)
   __syncthreads();
 }
 
+// The FP32-transform (mixed) path solves for the increments phi^{n+1} - phi^n and
+// psi^{n+1} - psi^n: right-hand sides are residuals against the current state,
+// formed in FP64, so FP32 rounding scales with the step's change rather than
+// with the fields, and the mean of the psi increment is carried in FP64.
+template <typename TM> constexpr bool increment_form() { return sizeof(TM) == 4; }
+
 __device__ __forceinline__ double mobility(double phi, double M0) {
   const double t = phi * phi - 1.0;
   return 1.0 - M0 * t * t;
@@ -116,6 +122,7 @@ __device__ __forceinline__ void stencil_pass(const RowArgs& a, cpx<TM>* line, do
                                              int ny, int tid, const StepConst& c) {
   constexpr bool FG = MASK & (1 << PR_FG), SH = MASK & (1 << PR_SH);
   constexpr bool QK = MASK & (1 << PR_QK), LP = MASK & (1 << PR_LP);
+  constexpr bool INC = increment_form<TM>();
   constexpr int LFG = 0;
   constexpr int LSH = FG ? 1 : 0;
   constexpr int LQK = (FG ? 1 : 0) + (SH ? 1 : 0);
@@ -151,10 +158,35 @@ __device__ __forceinline__ void stencil_pass(const RowArgs& a, cpx<TM>* line, do
         const double qw = c.x0 * a.psn[ow] + c.x1 * a.psm[ow];
         const double qn = c.x0 * a.psn[on] + c.x1 * a.psm[on];
         const double qs = c.x0 * a.psn[os] + c.x1 * a.psm[os];
-        const double lap_q = (qe + qw + qn + qs - 4.0 * qc) * c.inv_h2;
-        const double f_lin = c.a0 * phn_c + c.a1 * phm_c - c.M_phi * c.theta_t * lap_p;
-        const double g_lin = c.a0 * psn_c + c.a1 * psm_c - c.lam * lap_q;
-        line[LFG * NX + lds_pos(slot)] = {(TM)f_lin, (TM)g_lin};
+        if constexpr (INC) {
+          // Increment form: the residuals f_lin - chi phi^n and g_lin - zeta psi^n,
+          // written so that nothing of size phi / dt or psi / dt is ever formed:
+          //   a0 phi^n + a1 phi^{n-1} - alpha phi^n = -a1 (phi^n - phi^{n-1}),
+          //   psi* - psi^n = (x0 - 1)(psi^n - psi^{n-1}), which carries lambda Delta.
+          auto lap_n = [&](int ii, int jj) {
+            const size_t r = (size_t)jj * NX;
+            const double u = a.phn[r + ii];
+            const double ue = a.phn[r + min(ii + 1, NX - 1)], uw = a.phn[r + max(ii - 1, 0)];
+            const double un = a.phn[(size_t)min(jj + 1, ny - 1) * NX + ii];
+            const double us = a.phn[(size_t)max(jj - 1, 0) * NX + ii];
+            return (ue + uw + un + us - 4.0 * u) * c.inv_h2;
+          };
+          const double ln_c = lap_n(i, j);
+          const double bih =
+              (lap_n(ie, j) + lap_n(iw, j) + lap_n(i, jn) + lap_n(i, js) - 4.0 * ln_c) * c.inv_h2;
+          const double r_phi = -c.a1 * (phn_c - phm_c) - c.C1b * phn_c -
+                               c.M_phi * c.theta_t * lap_p + c.C2 * ln_c - c.C3 * bih;
+          const double dqc = psn_c - psm_c;
+          const double lap_dq = (a.psn[oe] - a.psm[oe] + a.psn[ow] - a.psm[ow] + a.psn[on] -
+                                 a.psm[on] + a.psn[os] - a.psm[os] - 4.0 * dqc) * c.inv_h2;
+          const double r_psi = -c.a1 * dqc - c.lam * (c.x0 - 1.0) * lap_dq;
+          line[LFG * NX + lds_pos(slot)] = {(TM)r_phi, (TM)r_psi};
+        } else {
+          const double lap_q = (qe + qw + qn + qs - 4.0 * qc) * c.inv_h2;
+          const double f_lin = c.a0 * phn_c + c.a1 * phm_c - c.M_phi * c.theta_t * lap_p;
+          const double g_lin = c.a0 * psn_c + c.a1 * psm_c - c.lam * lap_q;
+          line[LFG * NX + lds_pos(slot)] = {(TM)f_lin, (TM)g_lin};
+        }
         if (c.lag_d) {
           // ||d^n||^2 of the previous step: delta psi = psi^n - (2 psi^{n-1} - psi^{n-2}),
           // mobility at the face average of 2 phi^{n-1} - phi^{n-2}.
@@ -182,6 +214,10 @@ __device__ __forceinline__ void stencil_pass(const RowArgs& a, cpx<TM>* line, do
         sums[P1_RS] += vq * vq * 0.25 * ieps;
         sums[P1_ES] += St * eph;
         sums[P1_EH] += Hf * eph;
+        if constexpr (INC) {
+          sums[P1_XS] += St * phn_c;
+          sums[P1_XH] += Hf * phn_c;
+        }
       }
     }
     if constexpr (QK || LP) {
@@ -204,6 +240,10 @@ __device__ __forceinline__ void stencil_pass(const RowArgs& a, cpx<TM>* line, do
         sums[P1_RZ] += (1.0 + sp) * fin + (1.0 - sp) * fout;
         sums[P1_EQ] += Qt * eph;
         sums[P1_EK] += Kt * eph;
+        if constexpr (INC) {
+          sums[P1_XQ] += Qt * phn_c;
+          sums[P1_XK] += Kt * phn_c;
+        }
       }
       if constexpr (LP) {
         const double qe = c.x0 * a.psn[oe] + c.x1 * a.psm[oe];
@@ -220,6 +260,7 @@ __device__ __forceinline__ void stencil_pass(const RowArgs& a, cpx<TM>* line, do
             (Me * (Pe - Pc) - Mw * (Pc - Pw) + Mn * (Pn - Pc) - Ms * (Pc - Ps)) * c.inv_h2;
         line[LLP * NX + lds_pos(slot)] = {(TM)Lt, (TM)Pc};
         sums[P1_EP] += Pc * (c.e0 * psn_c + c.e1 * psm_c);
+        if constexpr (INC) sums[P1_XP] += Pc * psn_c;
         if (i < NX - 1 && !(Me > 0.0)) sums[P1_MOBNEG] += 1.0;
         if (j < ny - 1 && !(Mn > 0.0)) sums[P1_MOBNEG] += 1.0;
       }
@@ -504,7 +545,9 @@ k_solve(const double* __restrict__ p1, int n1, const double* __restrict__ p2, in
   const double cw[4] = {c.cgs, c.cga, c.cgb, c.cgo};
   double M[5][5], b[5];
   for (int i = 0; i < 4; ++i) {
-    double bi = h2 * nF[i] * T2[P2_FS + i];
+    // (F_i, phi^n) is zero except in the increment form, where the solved
+    // right-hand side is chi^{-1} f - phi^n.
+    double bi = h2 * nF[i] * (T2[P2_FS + i] + T1[P1_XS + i]);
     for (int jx = 0; jx < 4; ++jx) {
       M[i][jx] = (i == jx ? 1.0 : 0.0) + cw[jx] * G[i][jx];
       bi -= cw[jx] * s[jx] * G[i][jx];
@@ -516,7 +559,7 @@ k_solve(const double* __restrict__ p1, int n1, const double* __restrict__ p2, in
   M[4][0] = M[4][1] = M[4][2] = 0.0;
   M[4][3] = -PL;
   M[4][4] = 1.0 - PL;
-  b[4] = h2 * nK * T2[P2_PG] + s[3] * PL;
+  b[4] = h2 * nK * (T2[P2_PG] + T1[P1_XP]) + s[3] * PL;
   for (int i = 0; i < 5; ++i) {
     for (int jx = 0; jx < 5; ++jx) ds->diag[15 + 5 * i + jx] = M[i][jx];
   }
@@ -581,11 +624,12 @@ __global__ void __launch_bounds__(line_threads(NY))
 k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
             const double* __restrict__ lamy, const double* __restrict__ coef,
             TM* __restrict__ out, int nx, int chi_base, int nchi, int zeta_base, int nzeta,
-            StepConst c) {
+            double* __restrict__ colsum, StepConst c) {
   constexpr int NTHR = line_threads(NY);
   constexpr int KPT = (NY + NTHR - 1) / NTHR;
   __shared__ cpx<TM> line[NY];
   __shared__ cpx<double> rtab[Roots<TM, NY>::SIZE];
+  __shared__ double red[2 * (NTHR / 64 + 1)];
   const int tid = threadIdx.x;
   const int lin = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
   const int nstrip = gridDim.x;
@@ -634,6 +678,9 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
       }
       A[q] = (TM)((double)A[q] / d0);
       B[q] = (TM)((double)B[q] / d1);
+      // Increment form: the psi increment has zero mean (mass is conserved
+      // exactly by the scheme); its (0, 0) coefficient is set, not solved.
+      if (colsum && grp == 1 && s == 0 && k == 0) A[q] = (TM)0;
     }
   }
   __syncthreads();
@@ -661,12 +708,31 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
   __syncthreads();
   fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
   cpx<TM>* dst = reinterpret_cast<cpx<TM>*>(out + (size_t)grp * FS) + (size_t)s * NY;
+  TM y0[KPT];
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
     const int i = tid + q * NTHR;
+    y0[q] = (TM)0;
     if (i < NY) {
       const cpx<TM> y = line[lds_pos(fft_pos<TM, NY>(makhoul_slot<NY>(i)))];
       dst[i] = {y.re, -y.im};
+      y0[q] = y.re;
+    }
+  }
+  if (colsum && grp == 1 && s == 0) {
+    // Column k_x = 0 of the psi increment, y physical: its FP32 values sum to
+    // rounding noise instead of zero. Hand the row-inverse pass FP64 targets
+    // for the row sums that add up to zero, so that the increment it writes
+    // has zero sum in FP64 arithmetic.
+    double v[1] = {0.0};
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) v[0] += (double)y0[q];
+    block_sum<1, NTHR>(v, red, tid);
+    const double mean = red[0] / NY;
+#pragma unroll
+    for (int q = 0; q < KPT; ++q) {
+      const int i = tid + q * NTHR;
+      if (i < NY) colsum[i] = (double)y0[q] - mean;
     }
   }
 }
@@ -677,11 +743,13 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
 template <typename TM, int NX>
 __global__ void __launch_bounds__(line_threads(NX))
 k_row_idct(const TM* __restrict__ out, double* __restrict__ phi_new, double* __restrict__ psi_new,
-           int ny) {
+           int ny, const double* __restrict__ phi_base, const double* __restrict__ psi_base,
+           const double* __restrict__ colsum) {
   constexpr int NTHR = line_threads(NX);
   constexpr int CPT = (NX + NTHR - 1) / NTHR;
   __shared__ cpx<TM> line[NX];
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
+  __shared__ double red[2 * (NTHR / 64 + 1)];
   const int tid = threadIdx.x;
   const int j = xcd_remap(blockIdx.x, gridDim.x);
   const size_t FS = (size_t)NX * ny;
@@ -699,13 +767,41 @@ k_row_idct(const TM* __restrict__ out, double* __restrict__ phi_new, double* __r
   }
   __syncthreads();
   fft_lines<TM, NX, 1, NTHR>(line, rt, tid);
+  if (!colsum) {
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int i = tid + q * NTHR;
+      if (i < NX) {
+        const cpx<TM> y = line[lds_pos(fft_pos<TM, NX>(makhoul_slot<NX>(i)))];
+        phi_new[(size_t)j * NX + i] = (double)y.re;
+        psi_new[(size_t)j * NX + i] = -(double)y.im;
+      }
+    }
+    return;
+  }
+  // Increment form: new = base + increment. The psi increment of this row is
+  // shifted by a constant so that its FP64 sum equals sqrt(NX) colsum[j]
+  // (orthonormal DCT-III: the row sum is sqrt(NX) times the k = 0 input).
+  cpx<TM> Y[CPT];
+  double v[1] = {0.0};
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int i = tid + q * NTHR;
+    Y[q] = {(TM)0, (TM)0};
+    if (i < NX) {
+      Y[q] = line[lds_pos(fft_pos<TM, NX>(makhoul_slot<NX>(i)))];
+      v[0] -= (double)Y[q].im;
+    }
+  }
+  block_sum<1, NTHR>(v, red, tid);
+  const double shift = (sqrt((double)NX) * colsum[j] - red[0]) / NX;
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int i = tid + q * NTHR;
     if (i < NX) {
-      const cpx<TM> y = line[lds_pos(fft_pos<TM, NX>(makhoul_slot<NX>(i)))];
-      phi_new[(size_t)j * NX + i] = (double)y.re;
-      psi_new[(size_t)j * NX + i] = -(double)y.im;
+      const size_t o = (size_t)j * NX + i;
+      phi_new[o] = phi_base[o] + (double)Y[q].re;
+      psi_new[o] = psi_base[o] + (-(double)Y[q].im + shift);
     }
   }
 }
