@@ -3,11 +3,14 @@
 
 One "step" is one full CC-MSAV-BDF2 time step (stencil terms, SAV inner
 products, 5x5 solve, DCT elliptic solves) of the named synthetic workload; the
-inputs are resident in device memory before the timed region starts. Prints
-one JSON line: the throughput in Mcell-steps/s, a roofline entry for the
-dominant kernel (algorithmic bytes per launch over its mean duration from HIP
-events on the library's stream), and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+inputs are resident in device memory before the timed region starts. By
+default the mixed-precision path (FP32 transforms, FP64 state and scalars) is
+timed on the N = 4096 vesicle, and the FP64 path is then run for the same
+number of steps to report its throughput and the mixed path's error against
+it. Prints one JSON line: the throughput in Mcell-steps/s, a roofline entry
+for the dominant kernel (algorithmic bytes per launch over its mean duration
+from HIP events on the library's stream), and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -72,18 +75,47 @@ def stored_traffic(workload: str, precision: str, kernel: str, cells: int):
         return None
 
 
-def cpu_baseline(member):
-    """FP64 oracle timed on this host: one step of the same workload."""
+def cpu_baseline(member, steps: int = 2):
+    """FP64 oracle timed on this host: the first ``steps`` steps of the same workload."""
     from oracle import ccmsav_ref as R
     st = R.initial_state(member.phi0, member.psi0, member.params)
     t0 = time.perf_counter()
-    R.step(st)
+    for _ in range(steps):
+        R.step(st)
     dt = time.perf_counter() - t0
     cells = member.phi0.size
-    return {"value": cells / dt / 1e6, "unit": "Mcell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 step (the first, BDF1 form, same operation count as a BDF2 step) of "
-                      f"{member.name} at N={member.params['nx']}: {dt:.2f} s single-threaded "
-                      f"numpy/scipy"}
+    return {"value": cells * steps / dt / 1e6, "unit": "Mcell-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"the first {steps} steps (one BDF1, one BDF2) of {member.name} at "
+                      f"N={member.params['nx']}: {dt:.2f} s, single-threaded numpy/scipy"}
+
+
+def timed_run(C, torch, member, precision, steps, warmup, profile_steps, dev):
+    """Warm up, time ``steps`` steps between two synchronisations, then take
+    ``profile_steps`` more with per-kernel events. Returns timings and the
+    final state (after warmup + steps + profile_steps steps)."""
+    phi0 = torch.from_numpy(member.phi0).to(dev)
+    psi0 = torch.from_numpy(member.psi0).to(dev)
+    stream = torch.cuda.current_stream(dev)
+    ctx = C.Context(member.params, phi0, psi0, precision, stream=stream.cuda_stream)
+    mass0 = ctx.mass()[0]
+    ctx.step(warmup)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    ctx.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.sync()                       # raises on any device-side error of the run
+    prof = ctx.profile_steps(profile_steps) if profile_steps > 0 else {}
+    out = dict(wall=wall, ev_ms=ev0.elapsed_time(ev1), prof=prof, mass0=mass0,
+               mass=ctx.mass()[0], energy=ctx.energy(), fields=ctx.fields(), savs=ctx.savs()[0])
+    ctx.close()
+    return out
 
 
 def main():
@@ -92,9 +124,11 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="vesicle4096")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--profile-steps", type=int, default=50,
                     help="steps of the per-kernel event pass that feeds the roofline")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the FP64 run that the mixed path is checked and compared against")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, copy this many MiB with a plain torch copy "
@@ -118,46 +152,50 @@ def main():
     cells = nx * ny
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    phi0 = torch.from_numpy(member.phi0).to(dev)
-    psi0 = torch.from_numpy(member.psi0).to(dev)
-    stream = torch.cuda.current_stream(dev)
 
-    ctx = C.Context(member.params, phi0, psi0, args.precision, stream=stream.cuda_stream)
-    ctx.step(args.warmup)
-    ctx.sync()
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    ctx.step(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ctx.sync()                       # raises on any device-side error of the run
-    ev_ms = ev0.elapsed_time(ev1)
+    run = timed_run(C, torch, member, args.precision, args.steps, args.warmup,
+                    args.profile_steps, dev)
+    wall = run["wall"]
     ms_per_step = 1e3 * wall / args.steps
     value = cells * args.steps / wall / 1e6
     print(f"[bench] {args.workload} {args.precision}: {ms_per_step:.4f} ms/step (wall), "
-          f"{ev_ms / args.steps:.4f} ms/step (events), {value:.1f} Mcell-steps/s",
+          f"{run['ev_ms'] / args.steps:.4f} ms/step (events), {value:.1f} Mcell-steps/s",
           file=sys.stderr, flush=True)
 
-    prof = ctx.profile_steps(args.profile_steps)
+    prof = run["prof"]
     per_cell = kernel_bytes_per_cell(args.precision)
     for k, ms in prof.items():
         gbs = per_cell[k] * cells / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         print(f"[bench] kernel {k}: {ms * 1e3:.1f} us/launch, {per_cell[k]} B/cell, "
               f"{gbs:.0f} GB/s", file=sys.stderr, flush=True)
-    dom = max(prof, key=prof.get)
-    dom_bytes = per_cell[dom] * cells
-    achieved = dom_bytes / (prof[dom] * 1e-3) / 1e9
-    traffic = stored_traffic(args.workload, args.precision, dom, cells)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "bytes_per_launch": dom_bytes, "us_per_launch": prof[dom] * 1e3}
-    mass = ctx.mass()[0]
-    energy = ctx.energy()
-    ctx.close()
+    roofline = None
+    if prof:
+        dom = max(prof, key=prof.get)
+        dom_bytes = per_cell[dom] * cells
+        achieved = dom_bytes / (prof[dom] * 1e-3) / 1e9
+        traffic = stored_traffic(args.workload, args.precision, dom, cells)
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "bytes_per_launch": dom_bytes, "us_per_launch": prof[dom] * 1e3,
+                    "step_bytes_per_cell": sum(per_cell.values()),
+                    "step_frac": sum(per_cell.values()) * value * 1e6 / 1e9 / HBM_PEAK_GBS}
+
+    check = {"mass_drift": abs(run["mass"] - run["mass0"]) / abs(run["mass0"]),
+             "E_mod": run["energy"], "finite": bool(np.isfinite(run["energy"]))}
+    compare = None
+    if args.precision == "mixed" and not args.no_compare:
+        ref = timed_run(C, torch, member, "fp64", args.steps, args.warmup, args.profile_steps, dev)
+        rel = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())  # noqa: E731
+        check.update(rel_linf_phi_vs_fp64=rel(run["fields"][0], ref["fields"][0]),
+                     rel_linf_psi_vs_fp64=rel(run["fields"][1], ref["fields"][1]),
+                     rel_sav_vs_fp64=rel(run["savs"], ref["savs"]),
+                     steps_compared=args.warmup + args.steps + args.profile_steps)
+        fp64_value = cells * args.steps / ref["wall"] / 1e6
+        compare = {"fp64_value": fp64_value, "fp64_ms_per_step": 1e3 * ref["wall"] / args.steps,
+                   "speedup_vs_fp64": value / fp64_value}
+        print(f"[bench] fp64 path: {compare['fp64_ms_per_step']:.4f} ms/step, "
+              f"{fp64_value:.1f} Mcell-steps/s; mixed/fp64 = {compare['speedup_vs_fp64']:.3f}; "
+              f"rel err phi {check['rel_linf_phi_vs_fp64']:.2e}", file=sys.stderr, flush=True)
 
     if args.copy_probe_mib > 0:
         a = torch.empty(args.copy_probe_mib * 2 ** 18, dtype=torch.float32, device=dev).fill_(1.0)
@@ -185,7 +223,8 @@ def main():
                    "eps_cells": member.meta.get("eps_cells", 4.0)},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "check": {"mass_psi": mass, "E_mod": energy, "finite": bool(np.isfinite(energy))},
+        "vs_fp64": compare,
+        "check": check,
     }
     print(json.dumps(out), flush=True)
 

@@ -20,7 +20,7 @@ written, in its order and notation, with numpy for array arithmetic:
 * modified discrete energy: eq. (modified_discrete_energy); the dissipation
   quantities K^n, ||mu||^2, ||c + d/2||^2 of Thm. 3.1 / App. A.
 
-Readings where the paper is silent or ambiguous (all stated in the design doc):
+Readings where the paper is silent or ambiguous:
 face mobility is M_psi of the face-averaged phi*; the face average of phi^2
 in div(phi^2 grad phi) is (phi_i^2 + phi_{i+1}^2)/2; the cell |grad phi|^2
 is the mean of the squared face gradients around the cell; DCTs are
