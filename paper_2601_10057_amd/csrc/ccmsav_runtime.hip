@@ -279,13 +279,14 @@ void enqueue_step(ccmsav_ctx* c, PhaseEvents pe = PhaseEvents{nullptr}) {
   using LT = typename Launch<TM>::T;
   pe.mark(0, c->stream);
   const RowArgs ra{phn, phm, phmm, psn, psm, psmm};
-  LT::t1[c->lx - kMinLog](c->stream, ny, ra, mid, c->part1, ny, k);
+  const int p1_blocks = ny / p1_rows<TM>(nx);   // one row of partial sums per workgroup
+  LT::t1[c->lx - kMinLog](c->stream, p1_blocks, ra, mid, c->part1, ny, k);
   pe.mark(1, c->stream);
   pe.mark(2, c->stream);
   LT::t2[c->ly - kMinLog](c->stream, nx / 2, mid, c->lamx, c->lamy, c->part2, nx, k);
   pe.mark(3, c->stream);
   pe.mark(4, c->stream);
-  hipLaunchKernelGGL(k_solve, dim3(1), dim3(SOLVE_THREADS), 0, c->stream, c->part1, ny, c->part2,
+  hipLaunchKernelGGL(k_solve, dim3(1), dim3(SOLVE_THREADS), 0, c->stream, c->part1, p1_blocks, c->part2,
                      nx / 2, c->ds, k);
   pe.mark(5, c->stream);
   pe.mark(6, c->stream);

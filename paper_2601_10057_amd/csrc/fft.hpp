@@ -221,17 +221,39 @@ template <int N> __device__ __forceinline__ int makhoul_index(int n) {
 
 // DCT-II post-processing of bin k after fft_lines of z = v_a + i v_b:
 // returns the orthonormal coefficients A_k (line a) and B_k (line b).
+// What the DCT-II post-processing of bin k needs besides the line itself:
+// the LDS positions of bins k and N - k, the twiddle and the scale. Lines of
+// the same length share it.
+template <typename T> struct PostTerm {
+  int pk, pm;
+  cpx<T> w;
+  T s;
+};
+
+template <typename T, int N>
+__device__ __forceinline__ PostTerm<T> dct2_term(const Roots<T, N>& rt, int k) {
+  PostTerm<T> t;
+  t.pk = bin_pos<T, N>(k);
+  t.pm = bin_pos<T, N>((N - k) & (N - 1));
+  t.w = rt.omega(k);
+  t.s = (k == 0) ? (T)(0.5 * sqrt(1.0 / N)) : (T)(0.5 * sqrt(2.0 / N));
+  return t;
+}
+
+template <typename T>
+__device__ __forceinline__ void dct2_post(const cpx<T>* Z, const PostTerm<T>& t, T& A, T& B) {
+  const cpx<T> z = Z[t.pk];
+  const cpx<T> zm = Z[t.pm];
+  const T v1r = z.re + zm.re, v1i = z.im - zm.im;
+  const T v2r = z.im + zm.im, v2i = zm.re - z.re;
+  A = t.s * (t.w.re * v1r - t.w.im * v1i);
+  B = t.s * (t.w.re * v2r - t.w.im * v2i);
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void dct2_post(const cpx<T>* Z, const Roots<T, N>& rt, int k,
                                           T& A, T& B) {
-  const cpx<T> z = Z[bin_pos<T, N>(k)];
-  const cpx<T> zm = Z[bin_pos<T, N>((N - k) & (N - 1))];
-  const T s = (k == 0) ? (T)(0.5 * sqrt(1.0 / N)) : (T)(0.5 * sqrt(2.0 / N));
-  const T v1r = z.re + zm.re, v1i = z.im - zm.im;
-  const T v2r = z.im + zm.im, v2i = zm.re - z.re;
-  const cpx<T> w = rt.omega(k);
-  A = s * (w.re * v1r - w.im * v1i);
-  B = s * (w.re * v2r - w.im * v2i);
+  dct2_post<T>(Z, dct2_term<T, N>(rt, k), A, B);
 }
 
 // DCT-III pre-processing of bin k: from the orthonormal coefficients of two

@@ -1,11 +1,12 @@
 // Kernels of one CC-MSAV-BDF2 step (Sec. 3.2, solved as in App. B and App. C).
 //
 // Pipeline of one step (fields are row-major [ny][nx], x fastest):
-//   P1  k_stencil_rowdct : per row j, the explicit stencil terms of eqs.
+//   P1  k_stencil_rowdct : per band of 1-4 rows, the explicit stencil terms of eqs.
 //       (AC_BDF2)-(Z_BDF2) at phi* = x0 phi^n + x1 phi^{n-1}: the basis numerators
 //       S~, H, Q~, K~, P~ (Sec. 2.2 with the discrete forms of Sec. 3.4.1),
 //       L~ = div(M_psi(A phi*) grad P~), f_lin, g_lin, plus the SAV partial sums;
-//       then the orthonormal DCT-II along x of the 8 fields.
+//       then the orthonormal DCT-II along x of the 8 fields (the band's rows of
+//       a column pair leave as one 32-byte piece).
 //   P2  k_col_gram       : per strip of two columns, DCT-II along y and the
 //       Parseval inner products (F_i, chi^{-1} F_j), (P, zeta^{-1} g), (P, zeta^{-1} L).
 //   S   k_solve          : reduces the partials, assembles and solves the 5x5
@@ -39,10 +40,24 @@ template <typename TM> constexpr int stencil_threads(int n) {
 // The Gram kernel keeps four spectra per thread: eight bins per thread give
 // each wave up to 256 registers at one workgroup per CU.
 constexpr int gram_threads(int n) { return clamp_threads(n / 8); }
-// Field-pair lines of the row pass that fit in LDS next to the twiddle tables.
-template <typename TM> constexpr int lds_lines(int n) {
-  const int fit = (136 * 1024) / (n * (int)sizeof(cpx<TM>));
-  return fit >= 4 ? 4 : (fit >= 2 ? 2 : 1);
+// Complex lines of length n that fit in LDS next to the twiddle tables.
+template <typename TM> constexpr int lds_line_budget(int n) {
+  return (136 * 1024) / (n * (int)sizeof(cpx<TM>));
+}
+// Rows per workgroup of the row pass. The strip-major intermediates put the
+// rows of one column pair next to each other, so a workgroup holding R rows
+// writes each column pair of a field as one piece of 2 R values; HBM takes
+// writes in 32-byte sectors, so R is chosen to fill one (4 FP32 or 2 FP64
+// rows) as far as the LDS lines allow.
+template <typename TM> constexpr int p1_rows(int n) {
+  const int want = 32 / (2 * (int)sizeof(TM));
+  const int fit = lds_line_budget<TM>(n);
+  return fit >= want ? want : (fit >= 2 ? 2 : 1);
+}
+// Field pairs transformed together per round of the row pass (4 / pairs rounds).
+template <typename TM> constexpr int p1_pairs(int n) {
+  const int per = lds_line_budget<TM>(n) / p1_rows<TM>(n);
+  return per >= 4 ? 4 : (per >= 2 ? 2 : 1);
 }
 
 // Consecutive workgroups are dispatched round-robin over the 8 XCDs; give each
@@ -268,58 +283,76 @@ __device__ __forceinline__ void stencil_pass(const RowArgs& a, cpx<TM>* line, do
   }
 }
 
+// Column-pair piece of one field over the rows of a workgroup, stored with one
+// wide write.
+template <typename TM, int ROWS> struct alignas(2 * ROWS * sizeof(TM)) RowPiece {
+  TM v[2 * ROWS];
+};
+
 template <typename TM, int NX>
 __global__ void __launch_bounds__(stencil_threads<TM>(NX))
 k_stencil_rowdct(RowArgs a, TM* __restrict__ mid, double* __restrict__ part, int ny,
                  StepConst c) {
   constexpr int NTHR = stencil_threads<TM>(NX);
-  constexpr int CPT = (NX + NTHR - 1) / NTHR;
-  // Each round computes NLINE field pairs straight into LDS lines and
-  // transforms them with one batched FFT; 4 / NLINE rounds cover the pairs.
-  constexpr int NLINE = lds_lines<TM>(NX);
-  __shared__ cpx<TM> line[NLINE * NX];
+  constexpr int ROWS = p1_rows<TM>(NX);
+  // Each round computes NP field pairs for the ROWS rows straight into LDS
+  // lines (line of row r, pair l at (r NP + l) NX) and transforms them with
+  // one batched FFT; 4 / NP rounds cover the pairs.
+  constexpr int NP = p1_pairs<TM>(NX);
+  __shared__ cpx<TM> line[ROWS * NP * NX];
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   __shared__ double red[P1_NSUM * (NTHR / 64 + 1)];
   const int tid = threadIdx.x;
-  const int j = xcd_remap(blockIdx.x, gridDim.x);
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int j0 = blk * ROWS;
   const size_t FS = (size_t)NX * ny;
+  __shared__ double acc[P1_NSUM];
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
-  double sums[P1_NSUM];
-#pragma unroll
-  for (int q = 0; q < P1_NSUM; ++q) sums[q] = 0.0;
+  if (tid < P1_NSUM) acc[tid] = 0.0;
 
   auto round = [&](auto ir) {
     constexpr int r = decltype(ir)::value;
-    constexpr int MASK = ((1 << NLINE) - 1) << (r * NLINE);
-    stencil_pass<TM, NX, NTHR, MASK>(a, line, sums, j, ny, tid, c);
-    __syncthreads();
-    fft_lines<TM, NX, NLINE, NTHR>(line, rt, tid);
+    constexpr int MASK = ((1 << NP) - 1) << (r * NP);
+    // The round's partial sums are reduced before its FFT, so that no sum
+    // stays in registers across the transforms.
+    double sums[P1_NSUM];
 #pragma unroll
-    for (int l = 0; l < NLINE; ++l) {
-      const int pr = r * NLINE + l;
+    for (int q = 0; q < P1_NSUM; ++q) sums[q] = 0.0;
+#pragma unroll 1
+    for (int rr = 0; rr < ROWS; ++rr)
+      stencil_pass<TM, NX, NTHR, MASK>(a, line + rr * NP * NX, sums, j0 + rr, ny, tid, c);
+    block_sum<P1_NSUM, NTHR>(sums, red, tid);
+    if (tid < P1_NSUM) acc[tid] += red[tid];
+    fft_lines<TM, NX, ROWS * NP, NTHR>(line, rt, tid);
+#pragma unroll 1
+    for (int sp = tid; sp < NX / 2; sp += NTHR) {
+      const PostTerm<TM> t0 = dct2_term<TM, NX>(rt, 2 * sp);
+      const PostTerm<TM> t1 = dct2_term<TM, NX>(rt, 2 * sp + 1);
 #pragma unroll
-      for (int q = 0; q < CPT; ++q) {
-        const int k = tid + q * NTHR;
-        if (k < NX) {
-          TM A, B;
-          dct2_post<TM, NX>(line + l * NX, rt, k, A, B);
-          const size_t o = mid_index(k, j, ny);
-          mid[PAIR_A[pr] * FS + o] = A;
-          mid[PAIR_B[pr] * FS + o] = B;
+      for (int l = 0; l < NP; ++l) {
+        const int pr = r * NP + l;
+        RowPiece<TM, ROWS> pa, pb;
+#pragma unroll
+        for (int rr = 0; rr < ROWS; ++rr) {
+          const cpx<TM>* z = line + (rr * NP + l) * NX;
+          dct2_post<TM>(z, t0, pa.v[2 * rr], pb.v[2 * rr]);
+          dct2_post<TM>(z, t1, pa.v[2 * rr + 1], pb.v[2 * rr + 1]);
         }
+        const size_t o = ((size_t)sp * ny + j0) * 2;
+        *reinterpret_cast<RowPiece<TM, ROWS>*>(mid + PAIR_A[pr] * FS + o) = pa;
+        *reinterpret_cast<RowPiece<TM, ROWS>*>(mid + PAIR_B[pr] * FS + o) = pb;
       }
     }
     __syncthreads();
   };
   round(std::integral_constant<int, 0>{});
-  if constexpr (NLINE <= 2) round(std::integral_constant<int, 1>{});
-  if constexpr (NLINE == 1) {
+  if constexpr (NP <= 2) round(std::integral_constant<int, 1>{});
+  if constexpr (NP == 1) {
     round(std::integral_constant<int, 2>{});
     round(std::integral_constant<int, 3>{});
   }
-  block_sum<P1_NSUM, NTHR>(sums, red, tid);
-  if (tid < P1_NSUM) part[(size_t)j * P1_NSUM + tid] = red[tid];
+  if (tid < P1_NSUM) part[(size_t)blk * P1_NSUM + tid] = acc[tid];
 }
 
 // ---------------------------------------------------------------------------
