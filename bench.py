@@ -29,16 +29,18 @@ METRIC = "Mcell-steps/s at N=2048/4096, mixed-prec & batched vs FP64, rel err â‰
 HBM_PEAK_GBS = 8000.0
 
 # Algorithmic HBM bytes per cell for one launch of each kernel of the step.
-# State fields are FP64; the eight transform intermediates and the two solved
-# fields are FP64 (fp64) or FP32 (mixed). The stencil pass reads phi, psi at
-# levels n, n-1 (and n-2 for the lagged ||d||^2) and writes eight fields; the
-# column pass reads the eight; the column solve reads seven and writes two;
-# the row inverse reads two and writes the two new state fields. The mixed
-# path solves for increments, so its row inverse also reads phi^n, psi^n.
+# State fields are FP64; the eight stencil fields, the eight x-transformed
+# intermediates and the two solved fields are FP64 (fp64) or FP32 (mixed).
+# The stencil pass reads phi, psi at levels n, n-1 (and n-2 for the lagged
+# ||d||^2) and writes eight fields; the row DCT reads and writes eight; the
+# column pass reads eight; the column solve reads seven and writes two; the
+# row inverse reads two and writes the two new state fields. The mixed path
+# solves for increments, so its row inverse also reads phi^n, psi^n.
 def kernel_bytes_per_cell(precision: str):
     m = 8 if precision == "fp64" else 4
     return {
-        "stencil_rowdct": 6 * 8 + 8 * m,
+        "stencil": 6 * 8 + 8 * m,
+        "row_dct": 16 * m,
         "col_gram": 8 * m,
         "solve5": 0,
         "col_solve": 7 * m + 2 * m,

@@ -138,11 +138,11 @@ int64_t ccmsav_level(const ccmsav_ctx* c);
 
 /*
  * Take nsteps >= 1 steps like ccmsav_step, with HIP events recorded on the
- * context's stream around each of the five kernels of a step, then wait and
+ * context's stream around each of the six kernels of a step, then wait and
  * write the mean duration in milliseconds of each kernel launch to
- * ms_per_phase[5]: stencil + row DCT-II, column DCT-II + inner products,
+ * ms_per_phase[6]: stencil terms, row DCT-II, column DCT-II + inner products,
  * 5x5 solve, column solve (combine, divide, DCT-III), row DCT-III.
- * Creates and destroys 10 * nsteps events (nsteps <= 100000).
+ * Creates and destroys 12 * nsteps events (nsteps <= 100000).
  */
 int ccmsav_profile_steps(ccmsav_ctx* c, int32_t nsteps, double* ms_per_phase);
 

@@ -29,7 +29,7 @@ EXPORTED = (
     "ccmsav_sync", "ccmsav_elliptic_solve", "ccmsav_destroy", "ccmsav_strerror",
     "ccmsav_profile_steps",
 )
-PHASES = ("stencil_rowdct", "col_gram", "solve5", "col_solve", "row_idct")
+PHASES = ("stencil", "row_dct", "col_gram", "solve5", "col_solve", "row_idct")
 
 
 class Params(ctypes.Structure):

@@ -19,7 +19,7 @@ constexpr int kMinLog = 4;    // 16
 constexpr int kMaxLog = 13;   // 8192
 constexpr int kNumSizes = kMaxLog - kMinLog + 1;
 constexpr size_t kAlign = 256;
-constexpr int kNumPhases = 5;   // stencil+row DCT, column Gram, 5x5 solve, column solve, row IDCT
+constexpr int kNumPhases = 6;   // stencil, row DCT, column Gram, 5x5 solve, column solve, row IDCT
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -33,7 +33,7 @@ int log2_exact(int n) {
 // ---- launch tables over the line length --------------------------------------
 
 template <typename TM> struct Launch {
-  using P1 = void (*)(hipStream_t, int, const RowArgs&, TM*, double*, int, const StepConst&);
+  using P1 = void (*)(hipStream_t, int, const TM*, TM*, int);
   using P2 = void (*)(hipStream_t, int, const TM*, const double*, const double*, double*, int,
                       const StepConst&);
   using P3 = void (*)(hipStream_t, int, const TM*, const double*, const double*, const double*,
@@ -43,10 +43,8 @@ template <typename TM> struct Launch {
   using RD = void (*)(hipStream_t, int, const double*, TM*, int, int);
 
   template <int N>
-  static void p1(hipStream_t st, int grid, const RowArgs& a, TM* mid, double* part, int ny,
-                 const StepConst& k) {
-    hipLaunchKernelGGL((k_stencil_rowdct<TM, N>), dim3(grid), dim3(stencil_threads<TM>(N)), 0, st,
-                       a, mid, part, ny, k);
+  static void p1(hipStream_t st, int grid, const TM* rm, TM* mid, int ny) {
+    hipLaunchKernelGGL((k_row_dct8<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, rm, mid, ny);
   }
   template <int N>
   static void p2(hipStream_t st, int grid, const TM* mid, const double* lx, const double* ly,
@@ -94,6 +92,7 @@ struct ccmsav_ctx {
   size_t ws_bytes;
   double* phi[3];          // ring of levels, slot = level % 3
   double* psi[3];
+  void* rm;                // 8 stencil fields (row-major)
   void* mid;               // 8 intermediate fields (strip-major)
   void* outc;              // 2 solved fields, x-transformed (strip-major)
   double* part1;           // ny * P1_NSUM
@@ -114,7 +113,7 @@ namespace {
 size_t mid_elem(const ccmsav_params* p) { return p->precision == CCMSAV_MIXED ? 4 : 8; }
 
 struct Layout {
-  size_t state, mid, outc, part1, part2, parte, lamx, lamy, colsum, unit, ds, total;
+  size_t state, rm, mid, outc, part1, part2, parte, lamx, lamy, colsum, unit, ds, total;
 };
 
 Layout layout(const ccmsav_params* p) {
@@ -122,9 +121,10 @@ Layout layout(const ccmsav_params* p) {
   const size_t cells = (size_t)p->nx * p->ny;
   size_t off = 0;
   L.state = off; off = align_up(off + 6 * cells * sizeof(double));
+  L.rm = off;    off = align_up(off + M_NFIELD * cells * mid_elem(p));
   L.mid = off;   off = align_up(off + M_NFIELD * cells * mid_elem(p));
   L.outc = off;  off = align_up(off + 2 * cells * mid_elem(p));
-  L.part1 = off; off = align_up(off + (size_t)p->ny * P1_NSUM * sizeof(double));
+  L.part1 = off; off = align_up(off + (size_t)stencil_shape(p->nx, p->ny).blocks * P1_NSUM * sizeof(double));
   L.part2 = off; off = align_up(off + (size_t)(p->nx / 2) * P2_NSUM * sizeof(double));
   L.parte = off; off = align_up(off + (size_t)p->ny * E_NSUM * sizeof(double));
   L.lamx = off;  off = align_up(off + (size_t)p->nx * sizeof(double));
@@ -279,25 +279,30 @@ void enqueue_step(ccmsav_ctx* c, PhaseEvents pe = PhaseEvents{nullptr}) {
   using LT = typename Launch<TM>::T;
   pe.mark(0, c->stream);
   const RowArgs ra{phn, phm, phmm, psn, psm, psmm};
-  const int p1_blocks = ny / p1_rows<TM>(nx);   // one row of partial sums per workgroup
-  LT::t1[c->lx - kMinLog](c->stream, p1_blocks, ra, mid, c->part1, ny, k);
+  TM* rm = static_cast<TM*>(c->rm);
+  const StencilShape sh = stencil_shape(nx, ny);   // one row of partial sums per workgroup
+  hipLaunchKernelGGL(k_stencil<TM>, dim3(sh.blocks), dim3(STENCIL_THREADS), 0, c->stream, ra, rm,
+                     c->part1, nx, ny, sh.iters, k);
   pe.mark(1, c->stream);
   pe.mark(2, c->stream);
-  LT::t2[c->ly - kMinLog](c->stream, nx / 2, mid, c->lamx, c->lamy, c->part2, nx, k);
+  LT::t1[c->lx - kMinLog](c->stream, ny / p1_rows<TM>(nx), rm, mid, ny);
   pe.mark(3, c->stream);
   pe.mark(4, c->stream);
-  hipLaunchKernelGGL(k_solve, dim3(1), dim3(SOLVE_THREADS), 0, c->stream, c->part1, p1_blocks, c->part2,
-                     nx / 2, c->ds, k);
+  LT::t2[c->ly - kMinLog](c->stream, nx / 2, mid, c->lamx, c->lamy, c->part2, nx, k);
   pe.mark(5, c->stream);
   pe.mark(6, c->stream);
+  hipLaunchKernelGGL(k_solve, dim3(1), dim3(SOLVE_THREADS), 0, c->stream, c->part1, sh.blocks,
+                     c->part2, nx / 2, c->ds, k);
+  pe.mark(7, c->stream);
+  pe.mark(8, c->stream);
   // The FP32-transform path solves for increments over level n (see increment_form).
   double* colsum = increment_form<TM>() ? c->colsum : nullptr;
   LT::t3[c->ly - kMinLog](c->stream, nx / 2, mid, c->lamx, c->lamy, c->ds->coef, outc, nx, M_F, 5,
                           M_G, 2, colsum, k);
-  pe.mark(7, c->stream);
-  pe.mark(8, c->stream);
-  LT::t4[c->lx - kMinLog](c->stream, ny, outc, c->phi[snew], c->psi[snew], ny, phn, psn, colsum);
   pe.mark(9, c->stream);
+  pe.mark(10, c->stream);
+  LT::t4[c->lx - kMinLog](c->stream, ny, outc, c->phi[snew], c->psi[snew], ny, phn, psn, colsum);
+  pe.mark(11, c->stream);
   c->level += 1;
 }
 
@@ -372,6 +377,7 @@ int ccmsav_init(ccmsav_ctx** out, const ccmsav_params* p, const double* phi0, co
     c->phi[s] = st + (size_t)(2 * s) * cells;
     c->psi[s] = st + (size_t)(2 * s + 1) * cells;
   }
+  c->rm = base + L.rm;
   c->mid = base + L.mid;
   c->outc = base + L.outc;
   c->part1 = reinterpret_cast<double*>(base + L.part1);

@@ -31,12 +31,6 @@ namespace ccm {
 constexpr int clamp_threads(int t) { return t < 64 ? 64 : (t > 1024 ? 1024 : t); }
 // Threads of a line kernel: four elements per thread.
 constexpr int line_threads(int n) { return clamp_threads(n / 4); }
-// The stencil kernel holds several FP64 fields per thread: with eight
-// elements per thread the workgroup has half as many waves, so each wave may
-// use twice the registers at the same occupancy (one workgroup per CU).
-template <typename TM> constexpr int stencil_threads(int n) {
-  return clamp_threads(n / 4);
-}
 // The Gram kernel keeps four spectra per thread: eight bins per thread give
 // each wave up to 256 registers at one workgroup per CU.
 constexpr int gram_threads(int n) { return clamp_threads(n / 8); }
@@ -128,159 +122,191 @@ __device__ __forceinline__ double ptilde(const StepConst& c, double psi, double 
                 c.gamma_out * (1.0 - p) * (psi - c.psi_out));
 }
 
-// One pass over the row: computes the field pairs whose bit is set in MASK at
-// every cell and stores them into LDS line (rank of the pair within MASK),
-// at the Makhoul slot of the cell; adds the partial sums whose inputs the pass
-// already has.
-template <typename TM, int NX, int NTHR, int MASK>
-__device__ __forceinline__ void stencil_pass(const RowArgs& a, cpx<TM>* line, double* sums, int j,
-                                             int ny, int tid, const StepConst& c) {
-  constexpr bool FG = MASK & (1 << PR_FG), SH = MASK & (1 << PR_SH);
-  constexpr bool QK = MASK & (1 << PR_QK), LP = MASK & (1 << PR_LP);
-  constexpr bool INC = increment_form<TM>();
-  constexpr int LFG = 0;
-  constexpr int LSH = FG ? 1 : 0;
-  constexpr int LQK = (FG ? 1 : 0) + (SH ? 1 : 0);
-  constexpr int LLP = LQK + (QK ? 1 : 0);
+// Explicit stencil terms of eqs. (AC_BDF2)-(Z_BDF2) at cell (i, j), with
+// phi* = x0 phi^n + x1 phi^{n-1}: the eight right-hand-side fields (slot
+// order of Mid) and the cell's contributions to the partial sums. Neighbours
+// outside the grid are the ghost copies of App. D (index clamping).
+template <bool INC>
+__device__ __forceinline__ void stencil_cell(const RowArgs& a, int i, int j, int nx, int ny,
+                                             const StepConst& c, double (&sums)[P1_NSUM],
+                                             double (&out)[M_NFIELD]) {
   const int jn = min(j + 1, ny - 1), js = max(j - 1, 0);
+  const int ie = min(i + 1, nx - 1), iw = max(i - 1, 0);
   const double k32 = 0.75 * 1.4142135623730950488;   // 3 sqrt(2) / 4
   const double half_pi = 1.5707963267948966192;
   const double ieps = 1.0 / c.eps;
-#pragma unroll 1
-  for (int i = tid; i < NX; i += NTHR) {
-    const int ie = min(i + 1, NX - 1), iw = max(i - 1, 0);
-    const size_t oc = (size_t)j * NX + i, oe = (size_t)j * NX + ie, ow = (size_t)j * NX + iw;
-    const size_t on = (size_t)jn * NX + i, os = (size_t)js * NX + i;
-    const int slot = makhoul_slot<NX>(i);
-    const double phn_c = a.phn[oc], phm_c = a.phm[oc];
-    // phi* = x0 phi^n + x1 phi^{n-1} at the cell and its four neighbours
-    const double pc = c.x0 * phn_c + c.x1 * phm_c;
-    const double pe = c.x0 * a.phn[oe] + c.x1 * a.phm[oe];
-    const double pw = c.x0 * a.phn[ow] + c.x1 * a.phm[ow];
-    const double pn = c.x0 * a.phn[on] + c.x1 * a.phm[on];
-    const double ps = c.x0 * a.phn[os] + c.x1 * a.phm[os];
-    const double gxe = (pe - pc) * c.inv_h, gxw = (pc - pw) * c.inv_h;
-    const double gyn = (pn - pc) * c.inv_h, gys = (pc - ps) * c.inv_h;
-    const double pc2 = pc * pc;
-    const double cubic = pc2 * pc - pc;                      // phi*^3 - phi*
-    const double eph = c.e0 * phn_c + c.e1 * phm_c;          // SAV bracket weight
-    if constexpr (FG || SH) {
-      const double lap_p = (gxe - gxw + gyn - gys) * c.inv_h;
-      if constexpr (FG) {
-        const double psn_c = a.psn[oc], psm_c = a.psm[oc];
-        const double qc = c.x0 * psn_c + c.x1 * psm_c;
-        const double qe = c.x0 * a.psn[oe] + c.x1 * a.psm[oe];
-        const double qw = c.x0 * a.psn[ow] + c.x1 * a.psm[ow];
-        const double qn = c.x0 * a.psn[on] + c.x1 * a.psm[on];
-        const double qs = c.x0 * a.psn[os] + c.x1 * a.psm[os];
-        if constexpr (INC) {
-          // Increment form: the residuals f_lin - chi phi^n and g_lin - zeta psi^n,
-          // written so that nothing of size phi / dt or psi / dt is ever formed:
-          //   a0 phi^n + a1 phi^{n-1} - alpha phi^n = -a1 (phi^n - phi^{n-1}),
-          //   psi* - psi^n = (x0 - 1)(psi^n - psi^{n-1}), which carries lambda Delta.
-          auto lap_n = [&](int ii, int jj) {
-            const size_t r = (size_t)jj * NX;
-            const double u = a.phn[r + ii];
-            const double ue = a.phn[r + min(ii + 1, NX - 1)], uw = a.phn[r + max(ii - 1, 0)];
-            const double un = a.phn[(size_t)min(jj + 1, ny - 1) * NX + ii];
-            const double us = a.phn[(size_t)max(jj - 1, 0) * NX + ii];
-            return (ue + uw + un + us - 4.0 * u) * c.inv_h2;
-          };
-          const double ln_c = lap_n(i, j);
-          const double bih =
-              (lap_n(ie, j) + lap_n(iw, j) + lap_n(i, jn) + lap_n(i, js) - 4.0 * ln_c) * c.inv_h2;
-          const double r_phi = -c.a1 * (phn_c - phm_c) - c.C1b * phn_c -
-                               c.M_phi * c.theta_t * lap_p + c.C2 * ln_c - c.C3 * bih;
-          const double dqc = psn_c - psm_c;
-          const double lap_dq = (a.psn[oe] - a.psm[oe] + a.psn[ow] - a.psm[ow] + a.psn[on] -
-                                 a.psm[on] + a.psn[os] - a.psm[os] - 4.0 * dqc) * c.inv_h2;
-          const double r_psi = -c.a1 * dqc - c.lam * (c.x0 - 1.0) * lap_dq;
-          line[LFG * NX + lds_pos(slot)] = {(TM)r_phi, (TM)r_psi};
-        } else {
-          const double lap_q = (qe + qw + qn + qs - 4.0 * qc) * c.inv_h2;
-          const double f_lin = c.a0 * phn_c + c.a1 * phm_c - c.M_phi * c.theta_t * lap_p;
-          const double g_lin = c.a0 * psn_c + c.a1 * psm_c - c.lam * lap_q;
-          line[LFG * NX + lds_pos(slot)] = {(TM)f_lin, (TM)g_lin};
-        }
-        if (c.lag_d) {
-          // ||d^n||^2 of the previous step: delta psi = psi^n - (2 psi^{n-1} - psi^{n-2}),
-          // mobility at the face average of 2 phi^{n-1} - phi^{n-2}.
-          const double dc = psn_c - 2.0 * psm_c + a.psmm[oc];
-          const double fc = 2.0 * phm_c - a.phmm[oc];
-          if (i < NX - 1) {
-            const double de = a.psn[oe] - 2.0 * a.psm[oe] + a.psmm[oe];
-            const double fe = 2.0 * a.phm[oe] - a.phmm[oe];
-            const double g = de - dc;
-            sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (fc + fe), c.M0);
-          }
-          if (j < ny - 1) {
-            const double dn = a.psn[on] - 2.0 * a.psm[on] + a.psmm[on];
-            const double fn = 2.0 * a.phm[on] - a.phmm[on];
-            const double g = dn - dc;
-            sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (fc + fn), c.M0);
-          }
-        }
-      }
-      if constexpr (SH) {
-        const double St = pc * (pc2 - 1.0 - c.beta) * 0.5 * ieps;
-        const double Hf = k32 * (cubic * ieps - c.eps * lap_p);
-        line[LSH * NX + lds_pos(slot)] = {(TM)St, (TM)Hf};
-        const double vq = pc2 - 1.0 - c.beta;
-        sums[P1_RS] += vq * vq * 0.25 * ieps;
-        sums[P1_ES] += St * eph;
-        sums[P1_EH] += Hf * eph;
-        if constexpr (INC) {
-          sums[P1_XS] += St * phn_c;
-          sums[P1_XH] += Hf * phn_c;
-        }
-      }
+  const size_t oc = (size_t)j * nx + i, oe = (size_t)j * nx + ie, ow = (size_t)j * nx + iw;
+  const size_t on = (size_t)jn * nx + i, os = (size_t)js * nx + i;
+  const double phn_c = a.phn[oc], phm_c = a.phm[oc];
+  const double psn_c = a.psn[oc], psm_c = a.psm[oc];
+  // phi*, psi* at the cell and its four neighbours
+  const double pc = c.x0 * phn_c + c.x1 * phm_c;
+  const double pe = c.x0 * a.phn[oe] + c.x1 * a.phm[oe];
+  const double pw = c.x0 * a.phn[ow] + c.x1 * a.phm[ow];
+  const double pn = c.x0 * a.phn[on] + c.x1 * a.phm[on];
+  const double ps = c.x0 * a.phn[os] + c.x1 * a.phm[os];
+  const double qc = c.x0 * psn_c + c.x1 * psm_c;
+  const double qe = c.x0 * a.psn[oe] + c.x1 * a.psm[oe];
+  const double qw = c.x0 * a.psn[ow] + c.x1 * a.psm[ow];
+  const double qn = c.x0 * a.psn[on] + c.x1 * a.psm[on];
+  const double qs = c.x0 * a.psn[os] + c.x1 * a.psm[os];
+  const double gxe = (pe - pc) * c.inv_h, gxw = (pc - pw) * c.inv_h;
+  const double gyn = (pn - pc) * c.inv_h, gys = (pc - ps) * c.inv_h;
+  const double lap_p = (gxe - gxw + gyn - gys) * c.inv_h;
+  const double pc2 = pc * pc;
+  const double cubic = pc2 * pc - pc;                      // phi*^3 - phi*
+  const double eph = c.e0 * phn_c + c.e1 * phm_c;          // SAV bracket weights
+  const double eps_ = c.e0 * psn_c + c.e1 * psm_c;
+
+  // f_lin, g_lin (App. B, Step 2), or their increment-form residuals
+  if constexpr (INC) {
+    // Increment form: the residuals f_lin - chi phi^n and g_lin - zeta psi^n,
+    // written so that nothing of size phi / dt or psi / dt is ever formed:
+    //   a0 phi^n + a1 phi^{n-1} - alpha phi^n = -a1 (phi^n - phi^{n-1}),
+    //   psi* - psi^n = (x0 - 1)(psi^n - psi^{n-1}), which carries lambda Delta.
+    auto lap_n = [&](int ii, int jj) {
+      const size_t r = (size_t)jj * nx;
+      const double u = a.phn[r + ii];
+      const double ue = a.phn[r + min(ii + 1, nx - 1)], uw = a.phn[r + max(ii - 1, 0)];
+      const double un = a.phn[(size_t)min(jj + 1, ny - 1) * nx + ii];
+      const double us = a.phn[(size_t)max(jj - 1, 0) * nx + ii];
+      return (ue + uw + un + us - 4.0 * u) * c.inv_h2;
+    };
+    const double ln_c = lap_n(i, j);
+    const double bih =
+        (lap_n(ie, j) + lap_n(iw, j) + lap_n(i, jn) + lap_n(i, js) - 4.0 * ln_c) * c.inv_h2;
+    out[M_F] = -c.a1 * (phn_c - phm_c) - c.C1b * phn_c - c.M_phi * c.theta_t * lap_p +
+               c.C2 * ln_c - c.C3 * bih;
+    const double dqc = psn_c - psm_c;
+    const double lap_dq = (a.psn[oe] - a.psm[oe] + a.psn[ow] - a.psm[ow] + a.psn[on] -
+                           a.psm[on] + a.psn[os] - a.psm[os] - 4.0 * dqc) * c.inv_h2;
+    out[M_G] = -c.a1 * dqc - c.lam * (c.x0 - 1.0) * lap_dq;
+  } else {
+    const double lap_q = (qe + qw + qn + qs - 4.0 * qc) * c.inv_h2;
+    out[M_F] = c.a0 * phn_c + c.a1 * phm_c - c.M_phi * c.theta_t * lap_p;
+    out[M_G] = c.a0 * psn_c + c.a1 * psm_c - c.lam * lap_q;
+  }
+  if (c.lag_d) {
+    // ||d^n||^2 of the previous step: delta psi = psi^n - (2 psi^{n-1} - psi^{n-2}),
+    // mobility at the face average of 2 phi^{n-1} - phi^{n-2}.
+    const double dc = psn_c - 2.0 * psm_c + a.psmm[oc];
+    const double fc = 2.0 * phm_c - a.phmm[oc];
+    if (i < nx - 1) {
+      const double de = a.psn[oe] - 2.0 * a.psm[oe] + a.psmm[oe];
+      const double fe = 2.0 * a.phm[oe] - a.phmm[oe];
+      const double g = de - dc;
+      sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (fc + fe), c.M0);
     }
-    if constexpr (QK || LP) {
-      const double psn_c = a.psn[oc], psm_c = a.psm[oc];
-      const double qc = c.x0 * psn_c + c.x1 * psm_c;
-      double sp, cp;
-      sincospi(0.5 * pc, &sp, &cp);
-      const double din = qc - c.psi_in, dout = qc - c.psi_out;
-      const double fin = 0.5 * c.gamma_in * din * din + c.beta_in;
-      const double fout = 0.5 * c.gamma_out * dout * dout + c.beta_out;
-      const double Pc = ptilde(c, qc, sp);
-      if constexpr (QK) {
-        const double grad2 = 0.5 * (gxe * gxe + gxw * gxw + gyn * gyn + gys * gys);
-        const double div_a = 0.5 * ((pc2 + pe * pe) * gxe - (pw * pw + pc2) * gxw +
-                                    (pc2 + pn * pn) * gyn - (ps * ps + pc2) * gys) * c.inv_h;
-        const double Qt = 6.0 * (pc * grad2 - div_a) + cubic * (3.0 * pc2 - 1.0) * ieps * ieps;
-        const double Kt = 0.5 * half_pi * cp * (fin - fout);
-        line[LQK * NX + lds_pos(slot)] = {(TM)Qt, (TM)Kt};
-        sums[P1_RW] += 6.0 * pc2 * grad2 + cubic * cubic * ieps * ieps;
-        sums[P1_RZ] += (1.0 + sp) * fin + (1.0 - sp) * fout;
-        sums[P1_EQ] += Qt * eph;
-        sums[P1_EK] += Kt * eph;
-        if constexpr (INC) {
-          sums[P1_XQ] += Qt * phn_c;
-          sums[P1_XK] += Kt * phn_c;
-        }
-      }
-      if constexpr (LP) {
-        const double qe = c.x0 * a.psn[oe] + c.x1 * a.psm[oe];
-        const double qw = c.x0 * a.psn[ow] + c.x1 * a.psm[ow];
-        const double qn = c.x0 * a.psn[on] + c.x1 * a.psm[on];
-        const double qs = c.x0 * a.psn[os] + c.x1 * a.psm[os];
-        const double Pe = ptilde(c, qe, sinpi(0.5 * pe));
-        const double Pw = ptilde(c, qw, sinpi(0.5 * pw));
-        const double Pn = ptilde(c, qn, sinpi(0.5 * pn));
-        const double Ps = ptilde(c, qs, sinpi(0.5 * ps));
-        const double Me = mobility(0.5 * (pc + pe), c.M0), Mw = mobility(0.5 * (pw + pc), c.M0);
-        const double Mn = mobility(0.5 * (pc + pn), c.M0), Ms = mobility(0.5 * (ps + pc), c.M0);
-        const double Lt =
-            (Me * (Pe - Pc) - Mw * (Pc - Pw) + Mn * (Pn - Pc) - Ms * (Pc - Ps)) * c.inv_h2;
-        line[LLP * NX + lds_pos(slot)] = {(TM)Lt, (TM)Pc};
-        sums[P1_EP] += Pc * (c.e0 * psn_c + c.e1 * psm_c);
-        if constexpr (INC) sums[P1_XP] += Pc * psn_c;
-        if (i < NX - 1 && !(Me > 0.0)) sums[P1_MOBNEG] += 1.0;
-        if (j < ny - 1 && !(Mn > 0.0)) sums[P1_MOBNEG] += 1.0;
-      }
+    if (j < ny - 1) {
+      const double dn = a.psn[on] - 2.0 * a.psm[on] + a.psmm[on];
+      const double fn = 2.0 * a.phm[on] - a.phmm[on];
+      const double g = dn - dc;
+      sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (fc + fn), c.M0);
     }
   }
+
+  // S~ and H (surface energy, arc length)
+  {
+    const double St = pc * (pc2 - 1.0 - c.beta) * 0.5 * ieps;
+    const double Hf = k32 * (cubic * ieps - c.eps * lap_p);
+    out[M_S] = St;
+    out[M_H] = Hf;
+    const double vq = pc2 - 1.0 - c.beta;
+    sums[P1_RS] += vq * vq * 0.25 * ieps;
+    sums[P1_ES] += St * eph;
+    sums[P1_EH] += Hf * eph;
+    if constexpr (INC) {
+      sums[P1_XS] += St * phn_c;
+      sums[P1_XH] += Hf * phn_c;
+    }
+  }
+  // Q~ (bending), K~ and P~ (osmotic), L~ = div(M_psi(A phi*) grad P~)
+  double sp, cp;
+  sincospi(0.5 * pc, &sp, &cp);
+  const double din = qc - c.psi_in, dout = qc - c.psi_out;
+  const double fin = 0.5 * c.gamma_in * din * din + c.beta_in;
+  const double fout = 0.5 * c.gamma_out * dout * dout + c.beta_out;
+  const double Pc = ptilde(c, qc, sp);
+  {
+    const double grad2 = 0.5 * (gxe * gxe + gxw * gxw + gyn * gyn + gys * gys);
+    const double div_a = 0.5 * ((pc2 + pe * pe) * gxe - (pw * pw + pc2) * gxw +
+                                (pc2 + pn * pn) * gyn - (ps * ps + pc2) * gys) * c.inv_h;
+    const double Qt = 6.0 * (pc * grad2 - div_a) + cubic * (3.0 * pc2 - 1.0) * ieps * ieps;
+    const double Kt = 0.5 * half_pi * cp * (fin - fout);
+    out[M_Q] = Qt;
+    out[M_K] = Kt;
+    sums[P1_RW] += 6.0 * pc2 * grad2 + cubic * cubic * ieps * ieps;
+    sums[P1_RZ] += (1.0 + sp) * fin + (1.0 - sp) * fout;
+    sums[P1_EQ] += Qt * eph;
+    sums[P1_EK] += Kt * eph;
+    if constexpr (INC) {
+      sums[P1_XQ] += Qt * phn_c;
+      sums[P1_XK] += Kt * phn_c;
+    }
+  }
+  {
+    const double Pe = ptilde(c, qe, sinpi(0.5 * pe));
+    const double Pw = ptilde(c, qw, sinpi(0.5 * pw));
+    const double Pn = ptilde(c, qn, sinpi(0.5 * pn));
+    const double Ps = ptilde(c, qs, sinpi(0.5 * ps));
+    const double Me = mobility(0.5 * (pc + pe), c.M0), Mw = mobility(0.5 * (pw + pc), c.M0);
+    const double Mn = mobility(0.5 * (pc + pn), c.M0), Ms = mobility(0.5 * (ps + pc), c.M0);
+    out[M_L] = (Me * (Pe - Pc) - Mw * (Pc - Pw) + Mn * (Pn - Pc) - Ms * (Pc - Ps)) * c.inv_h2;
+    out[M_P] = Pc;
+    sums[P1_EP] += Pc * eps_;
+    if constexpr (INC) sums[P1_XP] += Pc * psn_c;
+    if (i < nx - 1 && !(Me > 0.0)) sums[P1_MOBNEG] += 1.0;
+    if (j < ny - 1 && !(Mn > 0.0)) sums[P1_MOBNEG] += 1.0;
+  }
+}
+
+// P1a: the stencil terms of a tile of cells, one cell per thread and
+// iteration; the eight fields leave row-major ([field][ny][nx], x fastest) in
+// coalesced writes. A workgroup covers tw = min(nx, 256) columns and
+// 256 / tw rows per iteration, for `iters` iterations down the grid.
+constexpr int STENCIL_THREADS = 256;
+
+template <typename TM>
+__global__ void __launch_bounds__(STENCIL_THREADS)
+k_stencil(RowArgs a, TM* __restrict__ rm, double* __restrict__ part, int nx, int ny, int iters,
+          StepConst c) {
+  constexpr bool INC = increment_form<TM>();
+  __shared__ double red[P1_NSUM * (STENCIL_THREADS / 64 + 1)];
+  const int tid = threadIdx.x;
+  const int tw = min(nx, STENCIL_THREADS);
+  const int th = STENCIL_THREADS / tw;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int nseg = nx / tw;
+  const int i = (blk % nseg) * tw + tid % tw;
+  const int j0 = (blk / nseg) * th * iters + tid / tw;
+  const size_t FS = (size_t)nx * ny;
+  double sums[P1_NSUM];
+#pragma unroll
+  for (int q = 0; q < P1_NSUM; ++q) sums[q] = 0.0;
+#pragma unroll 1
+  for (int it = 0; it < iters; ++it) {
+    const int j = j0 + it * th;
+    double out[M_NFIELD];
+    stencil_cell<INC>(a, i, j, nx, ny, c, sums, out);
+    const size_t o = (size_t)j * nx + i;
+#pragma unroll
+    for (int f = 0; f < M_NFIELD; ++f) rm[f * FS + o] = (TM)out[f];
+  }
+  block_sum<P1_NSUM, STENCIL_THREADS>(sums, red, tid);
+  if (tid < P1_NSUM) part[(size_t)blk * P1_NSUM + tid] = red[tid];
+}
+
+// Launch shape of P1a for an nx x ny grid: iterations per workgroup and the
+// number of workgroups (one row of partial sums each).
+struct StencilShape {
+  int iters, blocks;
+};
+inline StencilShape stencil_shape(int nx, int ny) {
+  const int tw = nx < STENCIL_THREADS ? nx : STENCIL_THREADS;
+  const int th = STENCIL_THREADS / tw;
+  const int rows = ny / th;                 // iterations needed for the whole height
+  const int iters = rows < 16 ? rows : 16;
+  return {iters, (nx / tw) * (rows / iters)};
 }
 
 // Column-pair piece of one field over the rows of a workgroup, stored with one
@@ -289,41 +315,41 @@ template <typename TM, int ROWS> struct alignas(2 * ROWS * sizeof(TM)) RowPiece 
   TM v[2 * ROWS];
 };
 
+// P1b: orthonormal DCT-II along x of the eight row-major fields, for a band
+// of ROWS rows, into the strip-major intermediates.
 template <typename TM, int NX>
-__global__ void __launch_bounds__(stencil_threads<TM>(NX))
-k_stencil_rowdct(RowArgs a, TM* __restrict__ mid, double* __restrict__ part, int ny,
-                 StepConst c) {
-  constexpr int NTHR = stencil_threads<TM>(NX);
+__global__ void __launch_bounds__(line_threads(NX))
+k_row_dct8(const TM* __restrict__ rm, TM* __restrict__ mid, int ny) {
+  constexpr int NTHR = line_threads(NX);
   constexpr int ROWS = p1_rows<TM>(NX);
-  // Each round computes NP field pairs for the ROWS rows straight into LDS
-  // lines (line of row r, pair l at (r NP + l) NX) and transforms them with
-  // one batched FFT; 4 / NP rounds cover the pairs.
+  // Each round loads NP field pairs of the ROWS rows into LDS lines (row r,
+  // pair l at (r NP + l) NX, two real fields per complex line) and transforms
+  // them with one batched FFT; 4 / NP rounds cover the pairs.
   constexpr int NP = p1_pairs<TM>(NX);
   __shared__ cpx<TM> line[ROWS * NP * NX];
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
-  __shared__ double red[P1_NSUM * (NTHR / 64 + 1)];
   const int tid = threadIdx.x;
   const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int j0 = blk * ROWS;
   const size_t FS = (size_t)NX * ny;
-  __shared__ double acc[P1_NSUM];
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
-  if (tid < P1_NSUM) acc[tid] = 0.0;
 
   auto round = [&](auto ir) {
     constexpr int r = decltype(ir)::value;
-    constexpr int MASK = ((1 << NP) - 1) << (r * NP);
-    // The round's partial sums are reduced before its FFT, so that no sum
-    // stays in registers across the transforms.
-    double sums[P1_NSUM];
 #pragma unroll
-    for (int q = 0; q < P1_NSUM; ++q) sums[q] = 0.0;
-#pragma unroll 1
-    for (int rr = 0; rr < ROWS; ++rr)
-      stencil_pass<TM, NX, NTHR, MASK>(a, line + rr * NP * NX, sums, j0 + rr, ny, tid, c);
-    block_sum<P1_NSUM, NTHR>(sums, red, tid);
-    if (tid < P1_NSUM) acc[tid] += red[tid];
+    for (int rr = 0; rr < ROWS; ++rr) {
+#pragma unroll
+      for (int l = 0; l < NP; ++l) {
+        const int pr = r * NP + l;
+        const TM* ra = rm + PAIR_A[pr] * FS + (size_t)(j0 + rr) * NX;
+        const TM* rb = rm + PAIR_B[pr] * FS + (size_t)(j0 + rr) * NX;
+        cpx<TM>* ln = line + (rr * NP + l) * NX;
+#pragma unroll
+        for (int i = tid; i < NX; i += NTHR) ln[lds_pos(makhoul_slot<NX>(i))] = {ra[i], rb[i]};
+      }
+    }
+    __syncthreads();
     fft_lines<TM, NX, ROWS * NP, NTHR>(line, rt, tid);
 #pragma unroll 1
     for (int sp = tid; sp < NX / 2; sp += NTHR) {
@@ -352,7 +378,6 @@ k_stencil_rowdct(RowArgs a, TM* __restrict__ mid, double* __restrict__ part, int
     round(std::integral_constant<int, 2>{});
     round(std::integral_constant<int, 3>{});
   }
-  if (tid < P1_NSUM) part[(size_t)blk * P1_NSUM + tid] = acc[tid];
 }
 
 // ---------------------------------------------------------------------------
