@@ -77,30 +77,41 @@ def stored_traffic(workload: str, precision: str, kernel: str, cells: int):
         return None
 
 
-def cpu_baseline(member, steps: int = 2):
-    """FP64 oracle timed on this host: the first ``steps`` steps of the same workload."""
+def cpu_baseline(members, budget_s: float = 12.0):
+    """FP64 oracle timed on this host over a bounded sample of the workload:
+    the first two steps (one BDF1, one BDF2) of as many members as fit in
+    about ``budget_s`` seconds (at least one)."""
     from oracle import ccmsav_ref as R
-    st = R.initial_state(member.phi0, member.psi0, member.params)
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    cells = 0
+    taken = 0
+    used = 0.0
+    for m in members:
+        st = R.initial_state(m.phi0, m.psi0, m.params)
+        t0 = time.perf_counter()
         R.step(st)
-    dt = time.perf_counter() - t0
-    cells = member.phi0.size
-    return {"value": cells * steps / dt / 1e6, "unit": "Mcell-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"the first {steps} steps (one BDF1, one BDF2) of {member.name} at "
-                      f"N={member.params['nx']}: {dt:.2f} s, single-threaded numpy/scipy"}
+        R.step(st)
+        used += time.perf_counter() - t0
+        cells += m.phi0.size * 2
+        taken += 1
+        if used > budget_s:
+            break
+    sizes = sorted({m.params["nx"] for m in members[:taken]})
+    return {"value": cells / used / 1e6, "unit": "Mcell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first 2 steps (one BDF1, one BDF2) of {taken} of {len(members)} "
+                      f"member(s) (N={sizes}): {used:.2f} s, single-threaded numpy/scipy"}
 
 
-def timed_run(C, torch, member, precision, steps, warmup, profile_steps, dev):
+def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, graph):
     """Warm up, time ``steps`` steps between two synchronisations, then take
     ``profile_steps`` more with per-kernel events. Returns timings and the
-    final state (after warmup + steps + profile_steps steps)."""
-    phi0 = torch.from_numpy(member.phi0).to(dev)
-    psi0 = torch.from_numpy(member.psi0).to(dev)
+    final states (after warmup + steps + profile_steps steps)."""
+    phi0 = [torch.from_numpy(m.phi0).to(dev) for m in members]
+    psi0 = [torch.from_numpy(m.psi0).to(dev) for m in members]
     stream = torch.cuda.current_stream(dev)
-    ctx = C.Context(member.params, phi0, psi0, precision, stream=stream.cuda_stream)
-    mass0 = ctx.mass()[0]
+    ctx = C.Context.ensemble([m.params for m in members], phi0, psi0, precision,
+                             stream=stream.cuda_stream, graph=graph)
+    nm = len(members)
+    mass0 = [ctx.mass(i)[0] for i in range(nm)]
     ctx.step(warmup)
     ctx.sync()
     torch.cuda.synchronize()
@@ -114,8 +125,12 @@ def timed_run(C, torch, member, precision, steps, warmup, profile_steps, dev):
     wall = time.perf_counter() - t0
     ctx.sync()                       # raises on any device-side error of the run
     prof = ctx.profile_steps(profile_steps) if profile_steps > 0 else {}
-    out = dict(wall=wall, ev_ms=ev0.elapsed_time(ev1), prof=prof, mass0=mass0,
-               mass=ctx.mass()[0], energy=ctx.energy(), fields=ctx.fields(), savs=ctx.savs()[0])
+    mass = [ctx.mass(i)[0] for i in range(nm)]
+    out = dict(wall=wall, ev_ms=ev0.elapsed_time(ev1), prof=prof,
+               drift=max(abs(a - b) / abs(b) for a, b in zip(mass, mass0)),
+               energy=[ctx.energy(member=i) for i in range(nm)],
+               fields=[ctx.fields(i) for i in range(nm)],
+               savs=[ctx.savs(i)[0] for i in range(nm)])
     ctx.close()
     return out
 
@@ -127,6 +142,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="vesicle4096")
     ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--graph", action="store_true",
+                    help="replay the steady-state steps from a captured HIP graph")
     ap.add_argument("--profile-steps", type=int, default=50,
                     help="steps of the per-kernel event pass that feeds the roofline")
     ap.add_argument("--no-compare", action="store_true",
@@ -144,19 +161,15 @@ def main():
     import numpy as np
     import torch
     from paper_2601_10057_amd import ccmsav as C
-    from workloads import WORKLOADS, make_workload
+    from workloads import make_workload
 
-    spec = WORKLOADS[args.workload]
-    if spec["kind"] != "single":
-        raise SystemExit("bench.py times single-grid workloads")
-    member = make_workload(args.workload)[0]
-    nx, ny = member.params["nx"], member.params["ny"]
-    cells = nx * ny
+    members = make_workload(args.workload)
+    cells = sum(m.phi0.size for m in members)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    run = timed_run(C, torch, member, args.precision, args.steps, args.warmup,
-                    args.profile_steps, dev)
+    run = timed_run(C, torch, members, args.precision, args.steps, args.warmup,
+                    args.profile_steps, dev, args.graph)
     wall = run["wall"]
     ms_per_step = 1e3 * wall / args.steps
     value = cells * args.steps / wall / 1e6
@@ -182,16 +195,18 @@ def main():
                     "step_bytes_per_cell": sum(per_cell.values()),
                     "step_frac": sum(per_cell.values()) * value * 1e6 / 1e9 / HBM_PEAK_GBS}
 
-    check = {"mass_drift": abs(run["mass"] - run["mass0"]) / abs(run["mass0"]),
-             "E_mod": run["energy"], "finite": bool(np.isfinite(run["energy"]))}
+    check = {"mass_drift": run["drift"], "E_mod": run["energy"][0],
+             "finite": bool(np.all(np.isfinite(run["energy"])))}
     compare = None
     if args.precision == "mixed" and not args.no_compare:
-        ref = timed_run(C, torch, member, "fp64", args.steps, args.warmup, args.profile_steps, dev)
+        ref = timed_run(C, torch, members, "fp64", args.steps, args.warmup, args.profile_steps,
+                        dev, args.graph)
         rel = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())  # noqa: E731
-        check.update(rel_linf_phi_vs_fp64=rel(run["fields"][0], ref["fields"][0]),
-                     rel_linf_psi_vs_fp64=rel(run["fields"][1], ref["fields"][1]),
-                     rel_sav_vs_fp64=rel(run["savs"], ref["savs"]),
-                     steps_compared=args.warmup + args.steps + args.profile_steps)
+        check.update(
+            rel_linf_phi_vs_fp64=max(rel(a[0], b[0]) for a, b in zip(run["fields"], ref["fields"])),
+            rel_linf_psi_vs_fp64=max(rel(a[1], b[1]) for a, b in zip(run["fields"], ref["fields"])),
+            rel_sav_vs_fp64=max(rel(a, b) for a, b in zip(run["savs"], ref["savs"])),
+            steps_compared=args.warmup + args.steps + args.profile_steps)
         fp64_value = cells * args.steps / ref["wall"] / 1e6
         compare = {"fp64_value": fp64_value, "fp64_ms_per_step": 1e3 * ref["wall"] / args.steps,
                    "speedup_vs_fp64": value / fp64_value}
@@ -206,7 +221,15 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(member)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(members)
+    m0 = members[0]
+    config = {"workload": args.workload, "members": len(members), "cells": cells,
+              "grids": sorted({(m.params["nx"], m.params["ny"]) for m in members}),
+              "precision": args.precision, "graph": args.graph,
+              "dt": sorted({m.params["dt"] for m in members}),
+              "eps_cells": sorted({m.meta.get("eps_cells", 4.0) for m in members})}
+    if len(members) == 1:
+        config.update(nx=m0.params["nx"], ny=m0.params["ny"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -220,9 +243,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "nx": nx, "ny": ny, "cells": cells,
-                   "precision": args.precision, "dt": member.params["dt"],
-                   "eps_cells": member.meta.get("eps_cells", 4.0)},
+        "config": config,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "vs_fp64": compare,

@@ -76,7 +76,7 @@ typedef enum {
  *  lam          Cahn-Hilliard stabilisation lambda >= 0               (Sec. 3.2)
  *  beta         linear SAV splitting constant                         (Sec. 2.2)
  *  precision    a ccmsav_precision value
- *  flags        reserved, must be 0
+ *  flags        0 or CCMSAV_FLAG_GRAPH
  */
 typedef struct {
   int32_t nx, ny;
@@ -88,9 +88,17 @@ typedef struct {
   int32_t precision, flags;
 } ccmsav_params;
 
+/* flags: capture the steady-state steps (level >= 3) once into a HIP graph of
+ * three steps and replay it from then on. The graph runs on a stream of the
+ * library's own, ordered after and before the context's stream by events. */
+#define CCMSAV_FLAG_GRAPH 1
+
 /* Device workspace bytes a context needs for these parameters (0 if the
  * parameters are invalid or unsupported). */
 size_t ccmsav_workspace_bytes(const ccmsav_params* p);
+
+/* Workspace bytes of an ensemble context of nmemb members (0 if invalid). */
+size_t ccmsav_workspace_bytes_batch(int32_t nmemb, const ccmsav_params* p);
 
 /*
  * Create a context at level n = 0 from phi0, psi0 (nx*ny doubles each, host or
@@ -105,6 +113,32 @@ size_t ccmsav_workspace_bytes(const ccmsav_params* p);
  */
 int ccmsav_init(ccmsav_ctx** out, const ccmsav_params* p, const double* phi0, const double* psi0,
                 void* workspace, size_t ws_bytes, void* hip_stream);
+
+/*
+ * Create a context that advances nmemb >= 1 independent vesicles (an
+ * ensemble) in lock step. Member m has its own parameters p[m] and initial
+ * fields phi0[m], psi0[m] (p[m].nx * p[m].ny doubles each, host or device);
+ * members may differ in grid size, eps, osmotic and all other parameters,
+ * but share the precision and the flags. Each kernel of a step is one launch
+ * per grid shape covering all members of that shape. Every other entry point
+ * applies to all members (step, sync, destroy) or to member 0 (energy, mass,
+ * get_fields, get_savs); the _m variants below take a member index.
+ * Returns like ccmsav_init; EINVAL also for nmemb outside [1, 4096] or mixed
+ * precisions or flags.
+ */
+int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
+                      const double* const* phi0, const double* const* psi0, void* workspace,
+                      size_t ws_bytes, void* hip_stream);
+
+/* Number of members of a context (-1 for NULL). */
+int32_t ccmsav_members(const ccmsav_ctx* c);
+
+/* Per-member forms of ccmsav_energy, ccmsav_mass, ccmsav_get_fields and
+ * ccmsav_get_savs (member in [0, ccmsav_members(c)), else EINVAL). */
+int ccmsav_energy_m(ccmsav_ctx* c, int32_t member, double* E_mod, double* parts);
+int ccmsav_mass_m(ccmsav_ctx* c, int32_t member, double* mass_psi, double* mass_phi);
+int ccmsav_get_fields_m(ccmsav_ctx* c, int32_t member, double* phi, double* psi);
+int ccmsav_get_savs_m(ccmsav_ctx* c, int32_t member, double out8[8]);
 
 /*
  * Enqueue nsteps >= 0 time steps (Algorithm 1 of App. B per step; BDF1 for the
@@ -150,7 +184,7 @@ int ccmsav_profile_steps(ccmsav_ctx* c, int32_t nsteps, double* ms_per_phase);
 int ccmsav_sync(ccmsav_ctx* c);
 
 /*
- * Fast direct solver of App. C on its own: out_chi = chi^{-1} rhs and
+ * Fast direct solver of App. C on its own (single-member contexts only): out_chi = chi^{-1} rhs and
  * out_zeta = zeta^{-1} rhs with the BDF2 operators of App. B Step 3,
  *   chi  = C1 - C2 Delta_h + C3 Delta_h^2, C1 = 3/(2 dt) + M_phi gamma_surf 3 sqrt2 beta/(4 eps),
  *          C2 = M_phi (gamma_surf 3 sqrt2 eps/4 + theta), C3 = M_phi gamma_bend 3 sqrt2 eps/8,

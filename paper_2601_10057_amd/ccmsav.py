@@ -23,11 +23,15 @@ PRECISIONS = {"fp64": FP64, "mixed": MIXED}
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDOMAIN",
           -5: "ENONFINITE", -6: "EUNSUPPORTED"}
 
+FLAG_GRAPH = 1
+
 EXPORTED = (
     "ccmsav_workspace_bytes", "ccmsav_init", "ccmsav_step", "ccmsav_energy",
     "ccmsav_mass", "ccmsav_get_fields", "ccmsav_get_savs", "ccmsav_level",
     "ccmsav_sync", "ccmsav_elliptic_solve", "ccmsav_destroy", "ccmsav_strerror",
-    "ccmsav_profile_steps",
+    "ccmsav_profile_steps", "ccmsav_workspace_bytes_batch", "ccmsav_init_batch",
+    "ccmsav_members", "ccmsav_energy_m", "ccmsav_mass_m", "ccmsav_get_fields_m",
+    "ccmsav_get_savs_m",
 )
 PHASES = ("stencil", "row_dct", "col_gram", "solve5", "col_solve", "row_idct")
 
@@ -94,11 +98,24 @@ def load() -> ctypes.CDLL:
     lib.ccmsav_profile_steps.argtypes = [vp, ctypes.c_int32, dp]
     lib.ccmsav_elliptic_solve.argtypes = [vp, vp, vp, vp]
     lib.ccmsav_destroy.argtypes = [vp]
+    lib.ccmsav_workspace_bytes_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Params)]
+    lib.ccmsav_workspace_bytes_batch.restype = ctypes.c_size_t
+    lib.ccmsav_init_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(Params),
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp), vp,
+                                      ctypes.c_size_t, vp]
+    lib.ccmsav_members.argtypes = [vp]
+    lib.ccmsav_members.restype = ctypes.c_int32
+    lib.ccmsav_energy_m.argtypes = [vp, ctypes.c_int32, dp, dp]
+    lib.ccmsav_mass_m.argtypes = [vp, ctypes.c_int32, dp, dp]
+    lib.ccmsav_get_fields_m.argtypes = [vp, ctypes.c_int32, vp, vp]
+    lib.ccmsav_get_savs_m.argtypes = [vp, ctypes.c_int32, dp]
     lib.ccmsav_strerror.argtypes = [ctypes.c_int]
     lib.ccmsav_strerror.restype = ctypes.c_char_p
     for fn in ("ccmsav_init", "ccmsav_step", "ccmsav_energy", "ccmsav_mass",
                "ccmsav_get_fields", "ccmsav_get_savs", "ccmsav_sync",
-               "ccmsav_elliptic_solve", "ccmsav_destroy", "ccmsav_profile_steps"):
+               "ccmsav_elliptic_solve", "ccmsav_destroy", "ccmsav_profile_steps",
+               "ccmsav_init_batch", "ccmsav_energy_m", "ccmsav_mass_m",
+               "ccmsav_get_fields_m", "ccmsav_get_savs_m"):
         getattr(lib, fn).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -135,16 +152,42 @@ def _check(code: int, what: str):
 
 
 class Context:
-    """One CC-MSAV simulation on the GPU, bound to a HIP stream."""
+    """CC-MSAV simulation of one vesicle, or of an ensemble of independent
+    vesicles advanced in lock step, on the GPU and bound to a HIP stream.
 
-    def __init__(self, params: Dict, phi0, psi0, precision="fp64", workspace=None,
-                 stream=None, torch_workspace: bool = True):
+    ``Context(params, phi0, psi0)`` holds one member; ``Context.ensemble``
+    builds a context of several (each with its own parameters and grid).
+    Member-indexed queries take ``member`` (default 0).
+    """
+
+    def __init__(self, params, phi0, psi0, precision="fp64", workspace=None,
+                 stream=None, torch_workspace: bool = True, graph: bool = False):
+        self._init([params], [phi0], [psi0], precision, workspace, stream, torch_workspace, graph)
+
+    @classmethod
+    def ensemble(cls, params_list, phi0_list, psi0_list, precision="fp64", workspace=None,
+                 stream=None, torch_workspace: bool = True, graph: bool = False) -> "Context":
+        self = cls.__new__(cls)
+        self._init(list(params_list), list(phi0_list), list(psi0_list), precision, workspace,
+                   stream, torch_workspace, graph)
+        return self
+
+    def _init(self, params_list, phi0_list, psi0_list, precision, workspace, stream,
+              torch_workspace, graph):
         lib = load()
-        self.params = dict(params)
+        self._h = None
+        n = len(params_list)
+        if n == 0 or len(phi0_list) != n or len(psi0_list) != n:
+            raise ValueError("one parameter set and two initial fields per member")
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
-        self._p = Params.from_dict(params, self.precision)
-        self.nx, self.ny = int(params["nx"]), int(params["ny"])
-        nbytes = int(lib.ccmsav_workspace_bytes(ctypes.byref(self._p)))
+        flags = FLAG_GRAPH if graph else 0
+        self.params_list = [dict(p) for p in params_list]
+        self.params = self.params_list[0]
+        parr = (Params * n)(*[Params.from_dict(p, self.precision, flags) for p in params_list])
+        self._p = parr
+        self.shapes = [(int(p["ny"]), int(p["nx"])) for p in params_list]
+        self.ny, self.nx = self.shapes[0]
+        nbytes = int(lib.ccmsav_workspace_bytes_batch(n, parr))
         self._ws = workspace
         if self._ws is None and torch_workspace and nbytes:
             import torch
@@ -157,17 +200,21 @@ class Context:
             except ImportError:
                 stream = None
         self._stream = stream
-        self._keep = (phi0, psi0)
+        ptr_phi = (ctypes.c_void_p * n)(*[_ptr(x) for x in phi0_list])
+        ptr_psi = (ctypes.c_void_p * n)(*[_ptr(x) for x in psi0_list])
         h = ctypes.c_void_p()
         ws_ptr = self._ws.data_ptr() if self._ws is not None else None
         ws_len = nbytes if self._ws is not None else 0
-        code = lib.ccmsav_init(ctypes.byref(h), ctypes.byref(self._p), _ptr(phi0), _ptr(psi0),
-                               ws_ptr, ws_len, stream)
-        _check(code, "ccmsav_init")
+        code = lib.ccmsav_init_batch(ctypes.byref(h), n, parr, ptr_phi, ptr_psi, ws_ptr, ws_len,
+                                     stream)
+        _check(code, "ccmsav_init_batch")
         self._h = h
-        self._keep = None
 
     # -- stepping and diagnostics ------------------------------------------
+    @property
+    def members(self) -> int:
+        return int(load().ccmsav_members(self._h))
+
     def step(self, nsteps: int = 1):
         _check(load().ccmsav_step(self._h, int(nsteps)), "ccmsav_step")
 
@@ -184,32 +231,35 @@ class Context:
     def level(self) -> int:
         return int(load().ccmsav_level(self._h))
 
-    def energy(self, parts: bool = False):
+    def energy(self, parts: bool = False, member: int = 0):
         e = ctypes.c_double()
         buf = (ctypes.c_double * 9)()
-        _check(load().ccmsav_energy(self._h, ctypes.byref(e), buf), "ccmsav_energy")
+        _check(load().ccmsav_energy_m(self._h, member, ctypes.byref(e), buf), "ccmsav_energy")
         return (e.value, list(buf)) if parts else e.value
 
-    def mass(self):
+    def mass(self, member: int = 0):
         a, b = ctypes.c_double(), ctypes.c_double()
-        _check(load().ccmsav_mass(self._h, ctypes.byref(a), ctypes.byref(b)), "ccmsav_mass")
+        _check(load().ccmsav_mass_m(self._h, member, ctypes.byref(a), ctypes.byref(b)),
+               "ccmsav_mass")
         return a.value, b.value
 
-    def fields(self):
-        """(phi^n, psi^n) copied to host numpy arrays."""
-        phi = np.empty((self.ny, self.nx))
-        psi = np.empty((self.ny, self.nx))
-        _check(load().ccmsav_get_fields(self._h, phi.ctypes.data, psi.ctypes.data),
+    def fields(self, member: int = 0):
+        """(phi^n, psi^n) of a member copied to host numpy arrays."""
+        ny, nx = self.shapes[member]
+        phi = np.empty((ny, nx))
+        psi = np.empty((ny, nx))
+        _check(load().ccmsav_get_fields_m(self._h, member, phi.ctypes.data, psi.ctypes.data),
                "ccmsav_get_fields")
         return phi, psi
 
-    def fields_into(self, phi, psi):
-        _check(load().ccmsav_get_fields(self._h, _ptr(phi), _ptr(psi)), "ccmsav_get_fields")
+    def fields_into(self, phi, psi, member: int = 0):
+        _check(load().ccmsav_get_fields_m(self._h, member, _ptr(phi), _ptr(psi)),
+               "ccmsav_get_fields")
 
-    def savs(self):
+    def savs(self, member: int = 0):
         """(V, U, W, Z) at level n and at level n-1."""
         buf = (ctypes.c_double * 8)()
-        _check(load().ccmsav_get_savs(self._h, buf), "ccmsav_get_savs")
+        _check(load().ccmsav_get_savs_m(self._h, member, buf), "ccmsav_get_savs")
         v = np.array(list(buf))
         return v[:4], v[4:]
 

@@ -1,11 +1,20 @@
 // Host runtime of the CC-MSAV step library: parameter checks, workspace
 // layout, the per-step launch sequence and the C ABI of include/ccmsav.h.
+//
+// A context advances one or more independent grids ("members") in lock step.
+// Members with the same grid shape form a size class; every kernel of a step
+// is one launch per size class that covers all of its members, with the
+// per-member arguments read from tables in device memory (one table per kind
+// of step: the BDF1 first step, the first BDF2 step, and the three phases of
+// the three-level state ring). Optionally the steady-state steps are captured
+// once into a HIP graph of three steps and replayed.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "ccmsav.h"
 #include "diag_kernels.hpp"
@@ -17,9 +26,13 @@ namespace {
 
 constexpr int kMinLog = 4;    // 16
 constexpr int kMaxLog = 13;   // 8192
-constexpr int kNumSizes = kMaxLog - kMinLog + 1;
 constexpr size_t kAlign = 256;
 constexpr int kNumPhases = 6;   // stencil, row DCT, column Gram, 5x5 solve, column solve, row IDCT
+constexpr int kMaxMembers = 4096;
+// Argument tables: 0 = level 0 (BDF1), 1 = level 1 (first BDF2 step, no
+// lagged ||d||^2), 2 + r = level n >= 2 with n % 3 == r; 5 = standalone solve.
+constexpr int kNumTables = 6;
+constexpr int kSolveTable = 5;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -30,41 +43,41 @@ int log2_exact(int n) {
   return l;
 }
 
+int table_of_level(int64_t n) { return n == 0 ? 0 : (n == 1 ? 1 : 2 + (int)(n % 3)); }
+
+// A level whose step uses table t (t < kSolveTable).
+int64_t level_of_table(int t) {
+  if (t <= 1) return t;
+  const int r = t - 2;
+  return r == 0 ? 3 : (r == 1 ? 4 : 2);
+}
+
 // ---- launch tables over the line length --------------------------------------
 
 template <typename TM> struct Launch {
-  using P1 = void (*)(hipStream_t, int, const TM*, TM*, int);
-  using P2 = void (*)(hipStream_t, int, const TM*, const double*, const double*, double*, int,
-                      const StepConst&);
-  using P3 = void (*)(hipStream_t, int, const TM*, const double*, const double*, const double*,
-                      TM*, int, int, int, int, int, double*, const StepConst&);
-  using P4 = void (*)(hipStream_t, int, const TM*, double*, double*, int, const double*,
-                      const double*, const double*);
-  using RD = void (*)(hipStream_t, int, const double*, TM*, int, int);
+  using K = void (*)(hipStream_t, int, const Batch&);
 
   template <int N>
-  static void p1(hipStream_t st, int grid, const TM* rm, TM* mid, int ny) {
-    hipLaunchKernelGGL((k_row_dct8<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, rm, mid, ny);
+  static void row_dct(hipStream_t st, int grid, const Batch& b) {
+    hipLaunchKernelGGL((k_row_dct8<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, b.m, b.idx,
+                       b.per);
   }
   template <int N>
-  static void p2(hipStream_t st, int grid, const TM* mid, const double* lx, const double* ly,
-                 double* part, int nx, const StepConst& k) {
-    hipLaunchKernelGGL((k_col_gram<TM, N>), dim3(grid), dim3(gram_threads(N)), 0, st, mid, lx, ly,
-                       part, nx, k);
+  static void gram(hipStream_t st, int grid, const Batch& b) {
+    hipLaunchKernelGGL((k_col_gram<TM, N>), dim3(grid), dim3(gram_threads(N)), 0, st, b.m, b.idx,
+                       b.per);
   }
   template <int N>
-  static void p3(hipStream_t st, int grid, const TM* mid, const double* lx, const double* ly,
-                 const double* coef, TM* out, int nx, int cb, int nc, int zb, int nz,
-                 double* colsum, const StepConst& k) {
-    hipLaunchKernelGGL((k_col_solve<TM, N>), dim3(grid, 2), dim3(line_threads(N)), 0, st, mid,
-                       lx, ly, coef, out, nx, cb, nc, zb, nz, colsum, k);
+  static void col_solve(hipStream_t st, int grid, const Batch& b) {
+    hipLaunchKernelGGL((k_col_solve<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, b.m, b.idx,
+                       b.per);
   }
   template <int N>
-  static void p4(hipStream_t st, int grid, const TM* out, double* phi, double* psi, int ny,
-                 const double* phi_base, const double* psi_base, const double* colsum) {
-    hipLaunchKernelGGL((k_row_idct<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, out, phi,
-                       psi, ny, phi_base, psi_base, colsum);
+  static void row_idct(hipStream_t st, int grid, const Batch& b) {
+    hipLaunchKernelGGL((k_row_idct<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, b.m, b.idx,
+                       b.per);
   }
+  using RD = void (*)(hipStream_t, int, const double*, TM*, int, int);
   template <int N>
   static void rd(hipStream_t st, int grid, const double* src, TM* mid, int slot, int ny) {
     hipLaunchKernelGGL((k_row_dct_field<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, src,
@@ -72,45 +85,16 @@ template <typename TM> struct Launch {
   }
 
   template <int... L> struct Tables {
-    static constexpr P1 t1[] = {&p1<(1 << L)>...};
-    static constexpr P2 t2[] = {&p2<(1 << L)>...};
-    static constexpr P3 t3[] = {&p3<(1 << L)>...};
-    static constexpr P4 t4[] = {&p4<(1 << L)>...};
-    static constexpr RD trd[] = {&rd<(1 << L)>...};
+    static constexpr K t_row_dct[] = {&row_dct<(1 << L)>...};
+    static constexpr K t_gram[] = {&gram<(1 << L)>...};
+    static constexpr K t_col_solve[] = {&col_solve<(1 << L)>...};
+    static constexpr K t_row_idct[] = {&row_idct<(1 << L)>...};
+    static constexpr RD t_rd[] = {&rd<(1 << L)>...};
   };
   using T = Tables<4, 5, 6, 7, 8, 9, 10, 11, 12, 13>;
 };
 
-}  // namespace
-
-struct ccmsav_ctx {
-  ccmsav_params p;
-  int lx, ly;              // log2 nx, log2 ny
-  hipStream_t stream;
-  bool owns_ws;
-  void* ws;
-  size_t ws_bytes;
-  double* phi[3];          // ring of levels, slot = level % 3
-  double* psi[3];
-  void* rm;                // 8 stencil fields (row-major)
-  void* mid;               // 8 intermediate fields (strip-major)
-  void* outc;              // 2 solved fields, x-transformed (strip-major)
-  double* part1;           // ny * P1_NSUM
-  double* part2;           // nx/2 * P2_NSUM
-  double* parte;           // ny * max(E_NSUM, I_NSUM)
-  double* lamx;            // (4/h^2) sin^2(pi k / (2 nx))
-  double* lamy;
-  double* colsum;          // increment form: FP64 row-sum targets of the psi increment
-  double* unit_coef;       // {1, 0, 0, 0, 0, 1, 0, 0} for the standalone solve
-  DevScalars* ds;
-  int64_t level;
-  double A;
-  int last_err;
-};
-
-namespace {
-
-size_t mid_elem(const ccmsav_params* p) { return p->precision == CCMSAV_MIXED ? 4 : 8; }
+size_t mid_elem(int precision) { return precision == CCMSAV_MIXED ? 4 : 8; }
 
 struct Layout {
   size_t state, rm, mid, outc, part1, part2, parte, lamx, lamy, colsum, unit, ds, total;
@@ -119,12 +103,14 @@ struct Layout {
 Layout layout(const ccmsav_params* p) {
   Layout L{};
   const size_t cells = (size_t)p->nx * p->ny;
+  const size_t me = mid_elem(p->precision);
   size_t off = 0;
   L.state = off; off = align_up(off + 6 * cells * sizeof(double));
-  L.rm = off;    off = align_up(off + M_NFIELD * cells * mid_elem(p));
-  L.mid = off;   off = align_up(off + M_NFIELD * cells * mid_elem(p));
-  L.outc = off;  off = align_up(off + 2 * cells * mid_elem(p));
-  L.part1 = off; off = align_up(off + (size_t)stencil_shape(p->nx, p->ny).blocks * P1_NSUM * sizeof(double));
+  L.rm = off;    off = align_up(off + M_NFIELD * cells * me);
+  L.mid = off;   off = align_up(off + M_NFIELD * cells * me);
+  L.outc = off;  off = align_up(off + 2 * cells * me);
+  L.part1 = off;
+  off = align_up(off + (size_t)stencil_shape(p->nx, p->ny).blocks * P1_NSUM * sizeof(double));
   L.part2 = off; off = align_up(off + (size_t)(p->nx / 2) * P2_NSUM * sizeof(double));
   L.parte = off; off = align_up(off + (size_t)p->ny * E_NSUM * sizeof(double));
   L.lamx = off;  off = align_up(off + (size_t)p->nx * sizeof(double));
@@ -141,7 +127,7 @@ bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 
 int check_params(const ccmsav_params* p) {
   if (!p) return CCMSAV_EINVAL;
-  if (p->flags != 0) return CCMSAV_EINVAL;
+  if ((p->flags & ~CCMSAV_FLAG_GRAPH) != 0) return CCMSAV_EINVAL;
   if (p->precision != CCMSAV_FP64 && p->precision != CCMSAV_MIXED) return CCMSAV_EUNSUPPORTED;
   if (p->nx <= 0 || p->ny <= 0) return CCMSAV_EINVAL;
   const int lx = log2_exact(p->nx), ly = log2_exact(p->ny);
@@ -160,13 +146,45 @@ int check_params(const ccmsav_params* p) {
   return CCMSAV_OK;
 }
 
+// All members of one context share the precision and the flags.
+int check_batch(int32_t nmemb, const ccmsav_params* p) {
+  if (nmemb <= 0 || nmemb > kMaxMembers || !p) return CCMSAV_EINVAL;
+  for (int32_t m = 0; m < nmemb; ++m) {
+    const int r = check_params(&p[m]);
+    if (r != CCMSAV_OK) return r;
+    if (p[m].precision != p[0].precision || p[m].flags != p[0].flags) return CCMSAV_EINVAL;
+  }
+  return CCMSAV_OK;
+}
+
+// Workspace of a context: the members' regions back to back, then the
+// argument tables and the member index lists.
+struct BatchLayout {
+  std::vector<size_t> member;   // offset of each member's region
+  size_t args, idx, total;
+};
+
+BatchLayout batch_layout(int32_t nmemb, const ccmsav_params* p) {
+  BatchLayout B;
+  size_t off = 0;
+  for (int32_t m = 0; m < nmemb; ++m) {
+    B.member.push_back(off);
+    off = align_up(off + layout(&p[m]).total);
+  }
+  B.args = off;
+  off = align_up(off + (size_t)kNumTables * nmemb * sizeof(MemberArgs));
+  B.idx = off;
+  off = align_up(off + (size_t)nmemb * sizeof(int));
+  B.total = off;
+  return B;
+}
+
 #define HIP_TRY(expr)                                   \
   do {                                                  \
     if ((expr) != hipSuccess) return CCMSAV_EHIP;       \
   } while (0)
 
-StepConst make_const(const ccmsav_ctx* c, bool bdf2) {
-  const ccmsav_params& p = c->p;
+StepConst make_const(const ccmsav_params& p, bool bdf2) {
   const double r2 = std::sqrt(2.0);
   StepConst k{};
   k.h = p.h;
@@ -210,8 +228,7 @@ StepConst make_const(const ccmsav_ctx* c, bool bdf2) {
   return k;
 }
 
-DiagConst make_diag(const ccmsav_ctx* c) {
-  const ccmsav_params& p = c->p;
+DiagConst make_diag(const ccmsav_params& p) {
   DiagConst d{};
   d.h = p.h;
   d.inv_h = 1.0 / p.h;
@@ -243,12 +260,6 @@ int status_from_err(int err) {
   return CCMSAV_OK;
 }
 
-int read_err(ccmsav_ctx* c, int* err) {
-  HIP_TRY(hipMemcpyAsync(err, &c->ds->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
-  return CCMSAV_OK;
-}
-
 // Optional per-phase timing: events[2*ph], events[2*ph+1] bracket phase ph.
 struct PhaseEvents {
   hipEvent_t* ev;   // 2 * kNumPhases events of this step, or nullptr
@@ -257,72 +268,229 @@ struct PhaseEvents {
   }
 };
 
+// One member (one grid) of a context.
+struct Member {
+  ccmsav_params p;
+  int lx, ly;
+  double* phi[3];          // ring of levels, slot = level % 3
+  double* psi[3];
+  void* rm;
+  void* mid;
+  void* outc;
+  double* part1;
+  double* part2;
+  double* parte;
+  double* lamx;
+  double* lamy;
+  double* colsum;
+  double* unit_coef;       // {1, 0, 0, 0, 0, 1, 0, 0} for the standalone solve
+  DevScalars* ds;
+  StencilShape sh;
+};
+
+// Members with one grid shape; d_idx lists their indices in device memory.
+struct SizeClass {
+  int lx, ly;
+  int count;
+  const int* d_idx;
+  StencilShape sh;
+};
+
+}  // namespace
+
+struct ccmsav_ctx {
+  std::vector<Member> mem;
+  std::vector<SizeClass> cls;
+  int precision = CCMSAV_FP64;
+  bool graph = false;
+  hipStream_t stream = nullptr;
+  bool owns_ws = false;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  MemberArgs* d_args = nullptr;      // kNumTables tables of mem.size() entries
+  std::vector<MemberArgs> h_args;
+  int64_t level = 0;
+  // graph replay of three steady-state steps
+  hipStream_t gstream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+};
+
+namespace {
+
+MemberArgs member_args(const Member& m, int precision, int table) {
+  MemberArgs a{};
+  const bool inc = precision == CCMSAV_MIXED;
+  a.rm = to_global(m.rm);
+  a.mid = to_global(m.mid);
+  a.outc = to_global(m.outc);
+  a.part1 = to_global(m.part1);
+  a.part2 = to_global(m.part2);
+  a.lamx = to_global<const double>(m.lamx);
+  a.lamy = to_global<const double>(m.lamy);
+  a.ds = to_global(m.ds);
+  a.nx = m.p.nx;
+  a.ny = m.p.ny;
+  a.iters = m.sh.iters;
+  a.p1_blocks = m.sh.blocks;
+  if (table == kSolveTable) {
+    // chi^{-1} and zeta^{-1} of the single field in slot M_F (App. C).
+    a.k = make_const(m.p, true);
+    a.coef = to_global<const double>(m.unit_coef);
+    a.chi_base = M_F;
+    a.nchi = 1;
+    a.zeta_base = M_F;
+    a.nzeta = 1;
+    return a;
+  }
+  const int64_t lv = level_of_table(table);
+  const bool bdf2 = lv >= 1;
+  const int sn = (int)(lv % 3), sm = (int)((lv + 2) % 3), snew = (int)((lv + 1) % 3);
+  a.k = make_const(m.p, bdf2);
+  a.k.slot_n = sn;
+  a.k.slot_m = bdf2 ? sm : sn;
+  a.k.slot_new = snew;
+  a.k.lag_d = lv >= 2 ? 1 : 0;
+  const double* phn = m.phi[sn];
+  const double* psn = m.psi[sn];
+  const double* phm = bdf2 ? m.phi[sm] : phn;
+  const double* psm = bdf2 ? m.psi[sm] : psn;
+  a.phn = to_global(phn);
+  a.psn = to_global(psn);
+  a.phm = to_global(phm);
+  a.psm = to_global(psm);
+  a.phmm = to_global<const double>(lv >= 2 ? m.phi[snew] : phm);
+  a.psmm = to_global<const double>(lv >= 2 ? m.psi[snew] : psm);
+  a.phi_new = to_global(m.phi[snew]);
+  a.psi_new = to_global(m.psi[snew]);
+  a.coef = to_global<const double>(m.ds->coef);
+  a.chi_base = M_F;
+  a.nchi = 5;
+  a.zeta_base = M_G;
+  a.nzeta = 2;
+  // The FP32-transform path solves for increments over level n (increment_form).
+  a.phi_base = inc ? a.phn : nullptr;
+  a.psi_base = inc ? a.psn : nullptr;
+  a.colsum = inc ? to_global(m.colsum) : nullptr;
+  return a;
+}
+
 template <typename TM>
-void enqueue_step(ccmsav_ctx* c, PhaseEvents pe = PhaseEvents{nullptr}) {
-  const int nx = c->p.nx, ny = c->p.ny;
-  const bool bdf2 = c->level >= 1;
-  StepConst k = make_const(c, bdf2);
+void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe) {
+  const MemberArgs* tab = c->d_args + (size_t)table * c->mem.size();
+  using LT = typename Launch<TM>::T;
+  pe.mark(0, st);
+  for (const SizeClass& k : c->cls) {
+    const Batch b{tab, k.d_idx, k.sh.blocks};
+    hipLaunchKernelGGL(k_stencil<TM>, dim3(k.count * k.sh.blocks), dim3(STENCIL_THREADS), 0, st,
+                       b.m, b.idx, b.per);
+  }
+  pe.mark(1, st);
+  pe.mark(2, st);
+  for (const SizeClass& k : c->cls) {
+    const int per = (1 << k.ly) / p1_rows<TM>(1 << k.lx);
+    LT::t_row_dct[k.lx - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
+  }
+  pe.mark(3, st);
+  pe.mark(4, st);
+  for (const SizeClass& k : c->cls) {
+    const int per = (1 << k.lx) / 2;
+    LT::t_gram[k.ly - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
+  }
+  pe.mark(5, st);
+  pe.mark(6, st);
+  for (const SizeClass& k : c->cls)
+    hipLaunchKernelGGL(k_solve, dim3(k.count), dim3(SOLVE_THREADS), 0, st, tab, k.d_idx, 1);
+  pe.mark(7, st);
+  pe.mark(8, st);
+  for (const SizeClass& k : c->cls) {
+    const int per = 1 << k.lx;     // two groups (chi, zeta) per strip of two columns
+    LT::t_col_solve[k.ly - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
+  }
+  pe.mark(9, st);
+  pe.mark(10, st);
+  for (const SizeClass& k : c->cls) {
+    const int per = 1 << k.ly;
+    LT::t_row_idct[k.lx - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
+  }
+  pe.mark(11, st);
+}
+
+void enqueue_step_level(ccmsav_ctx* c, int64_t level, hipStream_t st,
+                        PhaseEvents pe = PhaseEvents{nullptr}) {
+  const int t = table_of_level(level);
+  if (c->precision == CCMSAV_MIXED)
+    enqueue_step_kind<float>(c, t, st, pe);
+  else
+    enqueue_step_kind<double>(c, t, st, pe);
+}
+
+// Capture three steady-state steps (levels 3k, 3k+1, 3k+2, k >= 1) into a graph.
+int capture_graph(ccmsav_ctx* c) {
+  if (c->gexec) return CCMSAV_OK;
+  HIP_TRY(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeRelaxed));
+  for (int64_t lv = 3; lv < 6; ++lv) enqueue_step_level(c, lv, c->gstream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->gstream, &g);
+  if (e != hipSuccess || !g) return CCMSAV_EHIP;
+  const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    c->gexec = nullptr;
+    return CCMSAV_EHIP;
+  }
+  return CCMSAV_OK;
+}
+
+int read_err_member(ccmsav_ctx* c, int m, int* err) {
+  *err = 0;
+  HIP_TRY(hipMemcpyAsync(err, &c->mem[m].ds->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return CCMSAV_OK;
+}
+
+int read_err(ccmsav_ctx* c, int* err) {
+  *err = 0;
+  std::vector<int> e(c->mem.size(), 0);
+  for (size_t m = 0; m < c->mem.size(); ++m)
+    HIP_TRY(hipMemcpyAsync(&e[m], &c->mem[m].ds->err, sizeof(int), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int v : e) *err |= v;
+  return CCMSAV_OK;
+}
+
+void free_ctx(ccmsav_ctx* c) {
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
+  if (c->owns_ws && c->ws) (void)hipFree(c->ws);
+  delete c;
+}
+
+int run_diag(ccmsav_ctx* c, int mi, bool energy) {
+  const Member& m = c->mem[mi];
   const int64_t n = c->level;
-  const int sn = (int)(n % 3), sm = (int)((n + 2) % 3), snew = (int)((n + 1) % 3);
-  k.slot_n = sn;
-  k.slot_m = bdf2 ? sm : sn;
-  k.slot_new = snew;
-  k.lag_d = (n >= 2) ? 1 : 0;
-  const double* phn = c->phi[sn];
-  const double* psn = c->psi[sn];
-  const double* phm = bdf2 ? c->phi[sm] : phn;
-  const double* psm = bdf2 ? c->psi[sm] : psn;
-  const double* phmm = (n >= 2) ? c->phi[snew] : phm;
-  const double* psmm = (n >= 2) ? c->psi[snew] : psm;
-  TM* mid = static_cast<TM*>(c->mid);
-  TM* outc = static_cast<TM*>(c->outc);
-  using LT = typename Launch<TM>::T;
-  pe.mark(0, c->stream);
-  const RowArgs ra{phn, phm, phmm, psn, psm, psmm};
-  TM* rm = static_cast<TM*>(c->rm);
-  const StencilShape sh = stencil_shape(nx, ny);   // one row of partial sums per workgroup
-  hipLaunchKernelGGL(k_stencil<TM>, dim3(sh.blocks), dim3(STENCIL_THREADS), 0, c->stream, ra, rm,
-                     c->part1, nx, ny, sh.iters, k);
-  pe.mark(1, c->stream);
-  pe.mark(2, c->stream);
-  LT::t1[c->lx - kMinLog](c->stream, ny / p1_rows<TM>(nx), rm, mid, ny);
-  pe.mark(3, c->stream);
-  pe.mark(4, c->stream);
-  LT::t2[c->ly - kMinLog](c->stream, nx / 2, mid, c->lamx, c->lamy, c->part2, nx, k);
-  pe.mark(5, c->stream);
-  pe.mark(6, c->stream);
-  hipLaunchKernelGGL(k_solve, dim3(1), dim3(SOLVE_THREADS), 0, c->stream, c->part1, sh.blocks,
-                     c->part2, nx / 2, c->ds, k);
-  pe.mark(7, c->stream);
-  pe.mark(8, c->stream);
-  // The FP32-transform path solves for increments over level n (see increment_form).
-  double* colsum = increment_form<TM>() ? c->colsum : nullptr;
-  LT::t3[c->ly - kMinLog](c->stream, nx / 2, mid, c->lamx, c->lamy, c->ds->coef, outc, nx, M_F, 5,
-                          M_G, 2, colsum, k);
-  pe.mark(9, c->stream);
-  pe.mark(10, c->stream);
-  LT::t4[c->lx - kMinLog](c->stream, ny, outc, c->phi[snew], c->psi[snew], ny, phn, psn, colsum);
-  pe.mark(11, c->stream);
-  c->level += 1;
+  const int sn = (int)(n % 3), sm = (int)((n + 2) % 3), smm = (int)((n + 1) % 3);
+  DiagConst d = make_diag(m.p);
+  d.with_d = (energy && n >= 2) ? 1 : 0;
+  const double* p1 = m.phi[sn];
+  const double* p0 = n >= 1 ? m.phi[sm] : p1;
+  const double* pm = n >= 2 ? m.phi[smm] : p0;
+  const double* s1 = m.psi[sn];
+  const double* s0 = n >= 1 ? m.psi[sm] : s1;
+  const double* sm_ = n >= 2 ? m.psi[smm] : s0;
+  hipLaunchKernelGGL(k_energy_sums, dim3(m.p.ny), dim3(DIAG_THREADS), 0, c->stream, p1, p0, pm,
+                     s1, s0, sm_, m.parte, m.p.nx, m.p.ny, d);
+  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(DIAG_THREADS), 0, c->stream, m.parte, m.p.ny,
+                     m.ds, sn, n >= 1 ? sm : sn, d);
+  if (hipGetLastError() != hipSuccess) return CCMSAV_EHIP;
+  return CCMSAV_OK;
 }
 
-template <typename TM>
-void enqueue_solve(ccmsav_ctx* c, const double* rhs) {
-  const int nx = c->p.nx, ny = c->p.ny;
-  StepConst k = make_const(c, true);
-  TM* mid = static_cast<TM*>(c->mid);
-  TM* outc = static_cast<TM*>(c->outc);
-  using LT = typename Launch<TM>::T;
-  LT::trd[c->lx - kMinLog](c->stream, ny, rhs, mid, M_F, ny);
-  LT::t3[c->ly - kMinLog](c->stream, nx / 2, mid, c->lamx, c->lamy, c->unit_coef, outc, nx, M_F,
-                          1, M_F, 1, nullptr, k);
-}
-
-template <typename TM>
-void enqueue_final_rows(ccmsav_ctx* c, double* phi_out, double* psi_out) {
-  using LT = typename Launch<TM>::T;
-  LT::t4[c->lx - kMinLog](c->stream, c->p.ny, static_cast<TM*>(c->outc), phi_out, psi_out,
-                          c->p.ny, nullptr, nullptr, nullptr);
+bool valid_member(const ccmsav_ctx* c, int32_t member) {
+  return c && member >= 0 && member < (int32_t)c->mem.size();
 }
 
 const char* kStatusText[] = {
@@ -339,122 +507,187 @@ const char* kStatusText[] = {
 
 extern "C" {
 
-size_t ccmsav_workspace_bytes(const ccmsav_params* p) {
-  if (check_params(p) != CCMSAV_OK) return 0;
-  return layout(p).total;
+size_t ccmsav_workspace_bytes_batch(int32_t nmemb, const ccmsav_params* p) {
+  if (check_batch(nmemb, p) != CCMSAV_OK) return 0;
+  return batch_layout(nmemb, p).total;
 }
 
-int ccmsav_init(ccmsav_ctx** out, const ccmsav_params* p, const double* phi0, const double* psi0,
-                void* workspace, size_t ws_bytes, void* hip_stream) {
+size_t ccmsav_workspace_bytes(const ccmsav_params* p) {
+  return ccmsav_workspace_bytes_batch(1, p);
+}
+
+int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
+                      const double* const* phi0, const double* const* psi0, void* workspace,
+                      size_t ws_bytes, void* hip_stream) {
   if (!out || !phi0 || !psi0) return CCMSAV_EINVAL;
   *out = nullptr;
-  const int pc = check_params(p);
+  const int pc = check_batch(nmemb, p);
   if (pc != CCMSAV_OK) return pc;
-  const Layout L = layout(p);
-  if (workspace && ws_bytes < L.total) return CCMSAV_ENOMEM;
+  for (int32_t m = 0; m < nmemb; ++m)
+    if (!phi0[m] || !psi0[m]) return CCMSAV_EINVAL;
+  const BatchLayout BL = batch_layout(nmemb, p);
+  if (workspace && ws_bytes < BL.total) return CCMSAV_ENOMEM;
   if (workspace && (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0) return CCMSAV_EINVAL;
   ccmsav_ctx* c = new (std::nothrow) ccmsav_ctx();
   if (!c) return CCMSAV_ENOMEM;
-  c->p = *p;
-  c->lx = log2_exact(p->nx);
-  c->ly = log2_exact(p->ny);
+  c->precision = p[0].precision;
+  c->graph = (p[0].flags & CCMSAV_FLAG_GRAPH) != 0;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->owns_ws = workspace == nullptr;
   if (c->owns_ws) {
-    if (hipMalloc(&c->ws, L.total) != hipSuccess) {
-      delete c;
+    if (hipMalloc(&c->ws, BL.total) != hipSuccess) {
+      c->ws = nullptr;
+      free_ctx(c);
       return CCMSAV_ENOMEM;
     }
-    c->ws_bytes = L.total;
+    c->ws_bytes = BL.total;
   } else {
     c->ws = workspace;
     c->ws_bytes = ws_bytes;
   }
   char* base = static_cast<char*>(c->ws);
-  const size_t cells = (size_t)p->nx * p->ny;
-  double* st = reinterpret_cast<double*>(base + L.state);
-  for (int s = 0; s < 3; ++s) {
-    c->phi[s] = st + (size_t)(2 * s) * cells;
-    c->psi[s] = st + (size_t)(2 * s + 1) * cells;
-  }
-  c->rm = base + L.rm;
-  c->mid = base + L.mid;
-  c->outc = base + L.outc;
-  c->part1 = reinterpret_cast<double*>(base + L.part1);
-  c->part2 = reinterpret_cast<double*>(base + L.part2);
-  c->parte = reinterpret_cast<double*>(base + L.parte);
-  c->lamx = reinterpret_cast<double*>(base + L.lamx);
-  c->lamy = reinterpret_cast<double*>(base + L.lamy);
-  c->colsum = reinterpret_cast<double*>(base + L.colsum);
-  c->unit_coef = reinterpret_cast<double*>(base + L.unit);
-  c->ds = reinterpret_cast<DevScalars*>(base + L.ds);
-  c->level = 0;
-
+  c->d_args = reinterpret_cast<MemberArgs*>(base + BL.args);
+  int* d_idx = reinterpret_cast<int*>(base + BL.idx);
   auto fail = [&](int code) {
-    if (c->owns_ws) (void)hipFree(c->ws);
-    delete c;
+    (void)hipStreamSynchronize(c->stream);
+    free_ctx(c);
     return code;
   };
-  // Eigenvalues of -Delta_h per direction (App. C): (4/h^2) sin^2(pi k / (2 n)).
-  double* lx = new (std::nothrow) double[p->nx];
-  double* ly = new (std::nothrow) double[p->ny];
-  if (!lx || !ly) {
-    delete[] lx;
-    delete[] ly;
-    return fail(CCMSAV_ENOMEM);
-  }
-  for (int k = 0; k < p->nx; ++k) {
-    const double s = std::sin(M_PI * k / (2.0 * p->nx));
-    lx[k] = 4.0 / (p->h * p->h) * s * s;
-  }
-  for (int k = 0; k < p->ny; ++k) {
-    const double s = std::sin(M_PI * k / (2.0 * p->ny));
-    ly[k] = 4.0 / (p->h * p->h) * s * s;
-  }
-  const double unit[8] = {1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0};
-  bool ok = hipMemcpyAsync(c->lamx, lx, p->nx * sizeof(double), hipMemcpyHostToDevice,
-                           c->stream) == hipSuccess &&
-            hipMemcpyAsync(c->lamy, ly, p->ny * sizeof(double), hipMemcpyHostToDevice,
-                           c->stream) == hipSuccess &&
-            hipMemcpyAsync(c->unit_coef, unit, sizeof(unit), hipMemcpyHostToDevice, c->stream) ==
-                hipSuccess &&
-            hipMemsetAsync(c->ds, 0, sizeof(DevScalars), c->stream) == hipSuccess &&
-            hipMemcpyAsync(c->phi[0], phi0, cells * sizeof(double), hipMemcpyDefault,
-                           c->stream) == hipSuccess &&
-            hipMemcpyAsync(c->psi[0], psi0, cells * sizeof(double), hipMemcpyDefault,
-                           c->stream) == hipSuccess;
-  if (ok) ok = hipStreamSynchronize(c->stream) == hipSuccess;
-  delete[] lx;
-  delete[] ly;
-  if (!ok) return fail(CCMSAV_EHIP);
 
-  DiagConst d = make_diag(c);
-  hipLaunchKernelGGL(k_init_sums, dim3(p->ny), dim3(DIAG_THREADS), 0, c->stream, c->phi[0],
-                     c->psi[0], c->parte, p->nx, p->ny, d);
-  hipLaunchKernelGGL(k_init_final, dim3(1), dim3(DIAG_THREADS), 0, c->stream, c->parte, p->ny,
-                     c->ds, d);
-  if (hipGetLastError() != hipSuccess) return fail(CCMSAV_EHIP);
-  int err = 0;
-  double A = 0.0;
-  if (hipMemcpyAsync(&A, &c->ds->totals[0], sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
-          hipSuccess ||
-      read_err(c, &err) != CCMSAV_OK)
-    return fail(CCMSAV_EHIP);
-  c->A = A;
-  c->p.A = A;
-  const int st0 = status_from_err(err);
-  if (st0 != CCMSAV_OK) return fail(st0);
+  c->mem.resize(nmemb);
+  for (int32_t mi = 0; mi < nmemb; ++mi) {
+    Member& m = c->mem[mi];
+    m.p = p[mi];
+    m.lx = log2_exact(m.p.nx);
+    m.ly = log2_exact(m.p.ny);
+    m.sh = stencil_shape(m.p.nx, m.p.ny);
+    const Layout L = layout(&m.p);
+    char* mb = base + BL.member[mi];
+    const size_t cells = (size_t)m.p.nx * m.p.ny;
+    double* st = reinterpret_cast<double*>(mb + L.state);
+    for (int s = 0; s < 3; ++s) {
+      m.phi[s] = st + (size_t)(2 * s) * cells;
+      m.psi[s] = st + (size_t)(2 * s + 1) * cells;
+    }
+    m.rm = mb + L.rm;
+    m.mid = mb + L.mid;
+    m.outc = mb + L.outc;
+    m.part1 = reinterpret_cast<double*>(mb + L.part1);
+    m.part2 = reinterpret_cast<double*>(mb + L.part2);
+    m.parte = reinterpret_cast<double*>(mb + L.parte);
+    m.lamx = reinterpret_cast<double*>(mb + L.lamx);
+    m.lamy = reinterpret_cast<double*>(mb + L.lamy);
+    m.colsum = reinterpret_cast<double*>(mb + L.colsum);
+    m.unit_coef = reinterpret_cast<double*>(mb + L.unit);
+    m.ds = reinterpret_cast<DevScalars*>(mb + L.ds);
+
+    // Eigenvalues of -Delta_h per direction (App. C): (4/h^2) sin^2(pi k / (2 n)).
+    std::vector<double> lx(m.p.nx), ly(m.p.ny);
+    for (int k = 0; k < m.p.nx; ++k) {
+      const double s = std::sin(M_PI * k / (2.0 * m.p.nx));
+      lx[k] = 4.0 / (m.p.h * m.p.h) * s * s;
+    }
+    for (int k = 0; k < m.p.ny; ++k) {
+      const double s = std::sin(M_PI * k / (2.0 * m.p.ny));
+      ly[k] = 4.0 / (m.p.h * m.p.h) * s * s;
+    }
+    const double unit[8] = {1.0, 0.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0};
+    bool ok = hipMemcpyAsync(m.lamx, lx.data(), m.p.nx * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream) == hipSuccess &&
+              hipMemcpyAsync(m.lamy, ly.data(), m.p.ny * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream) == hipSuccess &&
+              hipMemcpyAsync(m.unit_coef, unit, sizeof(unit), hipMemcpyHostToDevice,
+                             c->stream) == hipSuccess &&
+              hipMemsetAsync(m.ds, 0, sizeof(DevScalars), c->stream) == hipSuccess &&
+              hipMemcpyAsync(m.phi[0], phi0[mi], cells * sizeof(double), hipMemcpyDefault,
+                             c->stream) == hipSuccess &&
+              hipMemcpyAsync(m.psi[0], psi0[mi], cells * sizeof(double), hipMemcpyDefault,
+                             c->stream) == hipSuccess;
+    if (ok) ok = hipStreamSynchronize(c->stream) == hipSuccess;
+    if (!ok) return fail(CCMSAV_EHIP);
+    const DiagConst d = make_diag(m.p);
+    hipLaunchKernelGGL(k_init_sums, dim3(m.p.ny), dim3(DIAG_THREADS), 0, c->stream, m.phi[0],
+                       m.psi[0], m.parte, m.p.nx, m.p.ny, d);
+    hipLaunchKernelGGL(k_init_final, dim3(1), dim3(DIAG_THREADS), 0, c->stream, m.parte, m.p.ny,
+                       m.ds, d);
+    if (hipGetLastError() != hipSuccess) return fail(CCMSAV_EHIP);
+  }
+  // Arc-length targets and the status of the initial reductions.
+  for (int32_t mi = 0; mi < nmemb; ++mi) {
+    Member& m = c->mem[mi];
+    double A = 0.0;
+    int err = 0;
+    if (hipMemcpyAsync(&A, &m.ds->totals[0], sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        read_err_member(c, mi, &err) != CCMSAV_OK)
+      return fail(CCMSAV_EHIP);
+    m.p.A = A;
+    const int st0 = status_from_err(err);
+    if (st0 != CCMSAV_OK) return fail(st0);
+  }
+
+  // Size classes and their member lists.
+  std::vector<int> order;
+  for (int32_t mi = 0; mi < nmemb; ++mi) {
+    bool seen = false;
+    for (const SizeClass& k : c->cls) seen = seen || (k.lx == c->mem[mi].lx && k.ly == c->mem[mi].ly);
+    if (seen) continue;
+    SizeClass k{c->mem[mi].lx, c->mem[mi].ly, 0, nullptr, c->mem[mi].sh};
+    const int start = (int)order.size();
+    for (int32_t mj = mi; mj < nmemb; ++mj)
+      if (c->mem[mj].lx == k.lx && c->mem[mj].ly == k.ly) order.push_back(mj);
+    k.count = (int)order.size() - start;
+    k.d_idx = d_idx + start;
+    c->cls.push_back(k);
+  }
+  // Argument tables.
+  c->h_args.resize((size_t)kNumTables * nmemb);
+  for (int t = 0; t < kNumTables; ++t)
+    for (int32_t mi = 0; mi < nmemb; ++mi)
+      c->h_args[(size_t)t * nmemb + mi] = member_args(c->mem[mi], c->precision, t);
+  const bool ok = hipMemcpyAsync(d_idx, order.data(), order.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+                  hipMemcpyAsync(c->d_args, c->h_args.data(),
+                                 c->h_args.size() * sizeof(MemberArgs), hipMemcpyHostToDevice,
+                                 c->stream) == hipSuccess &&
+                  hipStreamSynchronize(c->stream) == hipSuccess;
+  if (!ok) return fail(CCMSAV_EHIP);
+  if (c->graph) {
+    if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess)
+      return fail(CCMSAV_EHIP);
+  }
   *out = c;
   return CCMSAV_OK;
 }
 
+int ccmsav_init(ccmsav_ctx** out, const ccmsav_params* p, const double* phi0, const double* psi0,
+                void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!out || !phi0 || !psi0) return CCMSAV_EINVAL;
+  return ccmsav_init_batch(out, 1, p, &phi0, &psi0, workspace, ws_bytes, hip_stream);
+}
+
 int ccmsav_step(ccmsav_ctx* c, int32_t nsteps) {
   if (!c || nsteps < 0) return CCMSAV_EINVAL;
-  for (int32_t s = 0; s < nsteps; ++s) {
-    if (c->p.precision == CCMSAV_MIXED)
-      enqueue_step<float>(c);
-    else
-      enqueue_step<double>(c);
+  int32_t left = nsteps;
+  while (left > 0) {
+    if (c->graph && c->level >= 3 && c->level % 3 == 0 && left >= 3) {
+      const int r = capture_graph(c);
+      if (r != CCMSAV_OK) return r;
+      const int reps = left / 3;
+      HIP_TRY(hipEventRecord(c->ev_in, c->stream));
+      HIP_TRY(hipStreamWaitEvent(c->gstream, c->ev_in, 0));
+      for (int i = 0; i < reps; ++i) HIP_TRY(hipGraphLaunch(c->gexec, c->gstream));
+      HIP_TRY(hipEventRecord(c->ev_out, c->gstream));
+      HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_out, 0));
+      c->level += 3 * reps;
+      left -= 3 * reps;
+      continue;
+    }
+    enqueue_step_level(c, c->level, c->stream);
+    c->level += 1;
+    left -= 1;
   }
   if (hipGetLastError() != hipSuccess) return CCMSAV_EHIP;
   return CCMSAV_OK;
@@ -475,11 +708,8 @@ int ccmsav_profile_steps(ccmsav_ctx* c, int32_t nsteps, double* ms_per_phase) {
   }
   if (rc == CCMSAV_OK) {
     for (int32_t s = 0; s < nsteps; ++s) {
-      PhaseEvents pe{ev + (size_t)nev * s};
-      if (c->p.precision == CCMSAV_MIXED)
-        enqueue_step<float>(c, pe);
-      else
-        enqueue_step<double>(c, pe);
+      enqueue_step_level(c, c->level, c->stream, PhaseEvents{ev + (size_t)nev * s});
+      c->level += 1;
     }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
       rc = CCMSAV_EHIP;
@@ -511,34 +741,18 @@ int ccmsav_sync(ccmsav_ctx* c) {
   return status_from_err(err);
 }
 
-static int run_diag(ccmsav_ctx* c, bool energy) {
-  const int64_t n = c->level;
-  const int sn = (int)(n % 3), sm = (int)((n + 2) % 3), smm = (int)((n + 1) % 3);
-  DiagConst d = make_diag(c);
-  d.with_d = (energy && n >= 2) ? 1 : 0;
-  const double* p1 = c->phi[sn];
-  const double* p0 = n >= 1 ? c->phi[sm] : p1;
-  const double* pm = n >= 2 ? c->phi[smm] : p0;
-  const double* s1 = c->psi[sn];
-  const double* s0 = n >= 1 ? c->psi[sm] : s1;
-  const double* sm_ = n >= 2 ? c->psi[smm] : s0;
-  hipLaunchKernelGGL(k_energy_sums, dim3(c->p.ny), dim3(DIAG_THREADS), 0, c->stream, p1, p0, pm,
-                     s1, s0, sm_, c->parte, c->p.nx, c->p.ny, d);
-  hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(DIAG_THREADS), 0, c->stream, c->parte,
-                     c->p.ny, c->ds, sn, n >= 1 ? sm : sn, d);
-  if (hipGetLastError() != hipSuccess) return CCMSAV_EHIP;
-  return CCMSAV_OK;
-}
+int32_t ccmsav_members(const ccmsav_ctx* c) { return c ? (int32_t)c->mem.size() : -1; }
 
-int ccmsav_energy(ccmsav_ctx* c, double* E_mod, double* parts) {
-  if (!c || !E_mod) return CCMSAV_EINVAL;
+int ccmsav_energy_m(ccmsav_ctx* c, int32_t member, double* E_mod, double* parts) {
+  if (!valid_member(c, member) || !E_mod) return CCMSAV_EINVAL;
   if (c->level < 1) return CCMSAV_EINVAL;
-  int r = run_diag(c, true);
+  int r = run_diag(c, member, true);
   if (r != CCMSAV_OK) return r;
   double e[10];
-  HIP_TRY(hipMemcpyAsync(e, c->ds->energy, sizeof(e), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(e, c->mem[member].ds->energy, sizeof(e), hipMemcpyDeviceToHost,
+                         c->stream));
   int err = 0;
-  r = read_err(c, &err);
+  r = read_err_member(c, member, &err);
   if (r != CCMSAV_OK) return r;
   *E_mod = e[0];
   if (parts)
@@ -547,61 +761,92 @@ int ccmsav_energy(ccmsav_ctx* c, double* E_mod, double* parts) {
   return status_from_err(err);
 }
 
-int ccmsav_mass(ccmsav_ctx* c, double* mass_psi, double* mass_phi) {
-  if (!c) return CCMSAV_EINVAL;
-  int r = run_diag(c, false);
+int ccmsav_energy(ccmsav_ctx* c, double* E_mod, double* parts) {
+  return ccmsav_energy_m(c, 0, E_mod, parts);
+}
+
+int ccmsav_mass_m(ccmsav_ctx* c, int32_t member, double* mass_psi, double* mass_phi) {
+  if (!valid_member(c, member)) return CCMSAV_EINVAL;
+  int r = run_diag(c, member, false);
   if (r != CCMSAV_OK) return r;
   double t[3];
-  HIP_TRY(hipMemcpyAsync(t, c->ds->totals, sizeof(t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipMemcpyAsync(t, c->mem[member].ds->totals, sizeof(t), hipMemcpyDeviceToHost,
+                         c->stream));
   int err = 0;
-  r = read_err(c, &err);
+  r = read_err_member(c, member, &err);
   if (r != CCMSAV_OK) return r;
   if (mass_psi) *mass_psi = t[1];
   if (mass_phi) *mass_phi = t[2];
   return status_from_err(err);
 }
 
-int ccmsav_get_fields(ccmsav_ctx* c, double* phi, double* psi) {
-  if (!c) return CCMSAV_EINVAL;
-  const size_t bytes = (size_t)c->p.nx * c->p.ny * sizeof(double);
-  const int s = (int)(c->level % 3);
-  if (phi) HIP_TRY(hipMemcpyAsync(phi, c->phi[s], bytes, hipMemcpyDefault, c->stream));
-  if (psi) HIP_TRY(hipMemcpyAsync(psi, c->psi[s], bytes, hipMemcpyDefault, c->stream));
-  return ccmsav_sync(c);
+int ccmsav_mass(ccmsav_ctx* c, double* mass_psi, double* mass_phi) {
+  return ccmsav_mass_m(c, 0, mass_psi, mass_phi);
 }
 
-int ccmsav_get_savs(ccmsav_ctx* c, double out8[8]) {
-  if (!c || !out8) return CCMSAV_EINVAL;
+int ccmsav_get_fields_m(ccmsav_ctx* c, int32_t member, double* phi, double* psi) {
+  if (!valid_member(c, member)) return CCMSAV_EINVAL;
+  const Member& m = c->mem[member];
+  const size_t bytes = (size_t)m.p.nx * m.p.ny * sizeof(double);
+  const int s = (int)(c->level % 3);
+  if (phi) HIP_TRY(hipMemcpyAsync(phi, m.phi[s], bytes, hipMemcpyDefault, c->stream));
+  if (psi) HIP_TRY(hipMemcpyAsync(psi, m.psi[s], bytes, hipMemcpyDefault, c->stream));
+  int err = 0;
+  const int r = read_err_member(c, member, &err);
+  if (r != CCMSAV_OK) return r;
+  return status_from_err(err);
+}
+
+int ccmsav_get_fields(ccmsav_ctx* c, double* phi, double* psi) {
+  return ccmsav_get_fields_m(c, 0, phi, psi);
+}
+
+int ccmsav_get_savs_m(ccmsav_ctx* c, int32_t member, double out8[8]) {
+  if (!valid_member(c, member) || !out8) return CCMSAV_EINVAL;
   double sav[3][4];
-  HIP_TRY(hipMemcpyAsync(sav, c->ds->sav, sizeof(sav), hipMemcpyDeviceToHost, c->stream));
-  const int r = ccmsav_sync(c);
+  HIP_TRY(hipMemcpyAsync(sav, c->mem[member].ds->sav, sizeof(sav), hipMemcpyDeviceToHost,
+                         c->stream));
+  int err = 0;
+  const int r = read_err_member(c, member, &err);
   const int64_t n = c->level;
   const int sn = (int)(n % 3), sm = n >= 1 ? (int)((n + 2) % 3) : sn;
   for (int i = 0; i < 4; ++i) {
     out8[i] = sav[sn][i];
     out8[4 + i] = sav[sm][i];
   }
-  return r;
+  if (r != CCMSAV_OK) return r;
+  return status_from_err(err);
 }
+
+int ccmsav_get_savs(ccmsav_ctx* c, double out8[8]) { return ccmsav_get_savs_m(c, 0, out8); }
 
 int64_t ccmsav_level(const ccmsav_ctx* c) { return c ? c->level : -1; }
 
 int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, double* out_zeta) {
-  if (!c || !rhs) return CCMSAV_EINVAL;
-  if (c->p.precision == CCMSAV_MIXED)
-    enqueue_solve<float>(c, rhs);
-  else
-    enqueue_solve<double>(c, rhs);
+  if (!c || !rhs || c->mem.size() != 1) return CCMSAV_EINVAL;
+  const Member& m = c->mem[0];
   // The row DCT-III writes both results; an output that is not requested goes
   // to intermediate slots 2-3, which the solve does not read.
-  double* tmp = reinterpret_cast<double*>(static_cast<char*>(c->mid) +
-                                          2 * (size_t)c->p.nx * c->p.ny * mid_elem(&c->p));
-  double* a = out_chi ? out_chi : tmp;
-  double* b = out_zeta ? out_zeta : tmp;
-  if (c->p.precision == CCMSAV_MIXED)
-    enqueue_final_rows<float>(c, a, b);
+  double* tmp = reinterpret_cast<double*>(static_cast<char*>(m.mid) +
+                                          2 * (size_t)m.p.nx * m.p.ny * mid_elem(c->precision));
+  MemberArgs& a = c->h_args[(size_t)kSolveTable * c->mem.size()];
+  a.phi_new = to_global(out_chi ? out_chi : tmp);
+  a.psi_new = to_global(out_zeta ? out_zeta : tmp);
+  MemberArgs* d = c->d_args + (size_t)kSolveTable * c->mem.size();
+  HIP_TRY(hipMemcpyAsync(d, &a, sizeof(MemberArgs), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const SizeClass& k = c->cls[0];
+  auto run = [&](auto tm) {
+    using TM = decltype(tm);
+    using LT = typename Launch<TM>::T;
+    LT::t_rd[m.lx - kMinLog](c->stream, m.p.ny, rhs, static_cast<TM*>(m.mid), M_F, m.p.ny);
+    LT::t_col_solve[m.ly - kMinLog](c->stream, m.p.nx, Batch{d, k.d_idx, m.p.nx});
+    LT::t_row_idct[m.lx - kMinLog](c->stream, m.p.ny, Batch{d, k.d_idx, m.p.ny});
+  };
+  if (c->precision == CCMSAV_MIXED)
+    run(0.0f);
   else
-    enqueue_final_rows<double>(c, a, b);
+    run(0.0);
   if (hipGetLastError() != hipSuccess) return CCMSAV_EHIP;
   return CCMSAV_OK;
 }
@@ -609,8 +854,8 @@ int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, dou
 int ccmsav_destroy(ccmsav_ctx* c) {
   if (!c) return CCMSAV_EINVAL;
   (void)hipStreamSynchronize(c->stream);
-  if (c->owns_ws) (void)hipFree(c->ws);
-  delete c;
+  if (c->gstream) (void)hipStreamSynchronize(c->gstream);
+  free_ctx(c);
   return CCMSAV_OK;
 }
 

@@ -94,4 +94,50 @@ struct StepConst {
   int slot_n, slot_m, slot_new;   // SAV ring slots of levels n, n-1, n+1
 };
 
+// Pointer into global memory. The kernels read their pointers from tables in
+// device memory; typed in the global address space they are accessed with
+// global (not flat) loads and stores.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+
+template <typename T> inline gptr<T> to_global(T* p) { return (gptr<T>)p; }
+
+// State pointers of the three levels a step reads.
+struct RowArgs {
+  gptr<const double> phn;   // phi^n
+  gptr<const double> phm;   // phi^{n-1}
+  gptr<const double> phmm;  // phi^{n-2} (lagged ||d||^2 only)
+  gptr<const double> psn;
+  gptr<const double> psm;
+  gptr<const double> psmm;
+};
+
+// Everything the kernels of one step need about one grid (one member of an
+// ensemble), kept in device memory.
+struct MemberArgs {
+  gptr<const double> phn;        // phi^n, phi^{n-1}, phi^{n-2}
+  gptr<const double> phm;
+  gptr<const double> phmm;
+  gptr<const double> psn;        // psi^n, psi^{n-1}, psi^{n-2}
+  gptr<const double> psm;
+  gptr<const double> psmm;
+  gptr<double> phi_new;          // level n+1 (or the outputs of a standalone solve)
+  gptr<double> psi_new;
+  gptr<const double> phi_base;   // increment form: phi^n, psi^n added to the increments
+  gptr<const double> psi_base;
+  gptr<void> rm;                 // 8 stencil fields, row-major
+  gptr<void> mid;                // 8 x-transformed fields, strip-major
+  gptr<void> outc;               // 2 y-solved fields, strip-major
+  gptr<double> part1;            // stencil partial sums, one row per workgroup
+  gptr<double> part2;            // column partial sums, one row per strip
+  gptr<const double> lamx;       // (4/h^2) sin^2(pi k / (2 n)) per direction
+  gptr<const double> lamy;
+  gptr<double> colsum;           // increment form: row-sum targets of the psi increment
+  gptr<DevScalars> ds;
+  gptr<const double> coef;       // spectral combination (ds->coef, or unit weights)
+  int nx, ny;
+  int iters, p1_blocks;          // stencil launch shape
+  int chi_base, nchi, zeta_base, nzeta;   // field groups combined by the column solve
+  StepConst k;
+};
+
 }  // namespace ccm

@@ -108,15 +108,6 @@ enum Pair { PR_FG = 0, PR_SH = 1, PR_QK = 2, PR_LP = 3 };
 constexpr int PAIR_A[4] = {M_F, M_S, M_Q, M_L};
 constexpr int PAIR_B[4] = {M_G, M_H, M_K, M_P};
 
-struct RowArgs {
-  const double* phn;   // phi^n
-  const double* phm;   // phi^{n-1}
-  const double* phmm;  // phi^{n-2} (lagged ||d||^2 only)
-  const double* psn;
-  const double* psm;
-  const double* psmm;
-};
-
 __device__ __forceinline__ double ptilde(const StepConst& c, double psi, double p) {
   return 0.5 * (c.gamma_in * (1.0 + p) * (psi - c.psi_in) +
                 c.gamma_out * (1.0 - p) * (psi - c.psi_out));
@@ -267,15 +258,14 @@ __device__ __forceinline__ void stencil_cell(const RowArgs& a, int i, int j, int
 constexpr int STENCIL_THREADS = 256;
 
 template <typename TM>
-__global__ void __launch_bounds__(STENCIL_THREADS)
-k_stencil(RowArgs a, TM* __restrict__ rm, double* __restrict__ part, int nx, int ny, int iters,
-          StepConst c) {
+__device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restrict__ rm,
+                                             gptr<double> __restrict__ part, int nx, int ny,
+                                             int iters, const StepConst& c, int blk) {
   constexpr bool INC = increment_form<TM>();
   __shared__ double red[P1_NSUM * (STENCIL_THREADS / 64 + 1)];
   const int tid = threadIdx.x;
   const int tw = min(nx, STENCIL_THREADS);
   const int th = STENCIL_THREADS / tw;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int nseg = nx / tw;
   const int i = (blk % nseg) * tw + tid % tw;
   const int j0 = (blk / nseg) * th * iters + tid / tw;
@@ -315,11 +305,31 @@ template <typename TM, int ROWS> struct alignas(2 * ROWS * sizeof(TM)) RowPiece 
   TM v[2 * ROWS];
 };
 
+// Complex values in global memory, moved field by field (the address-space
+// qualified element has no implicit copy).
+template <typename T> __device__ __forceinline__ cpx<T> gload(gptr<const cpx<T>> p) {
+  return {p->re, p->im};
+}
+template <typename T> __device__ __forceinline__ void gstore(gptr<cpx<T>> p, cpx<T> v) {
+  p->re = v.re;
+  p->im = v.im;
+}
+
+// Store a piece as pairs (one 8- or 16-byte write each; the piece is aligned).
+template <typename TM, int ROWS>
+__device__ __forceinline__ void store_piece(gptr<TM> dst, const RowPiece<TM, ROWS>& p) {
+  typedef TM pair_t __attribute__((ext_vector_type(2)));
+  const auto d = reinterpret_cast<gptr<pair_t>>(dst);
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) d[r] = pair_t{p.v[2 * r], p.v[2 * r + 1]};
+}
+
 // P1b: orthonormal DCT-II along x of the eight row-major fields, for a band
 // of ROWS rows, into the strip-major intermediates.
 template <typename TM, int NX>
-__global__ void __launch_bounds__(line_threads(NX))
-k_row_dct8(const TM* __restrict__ rm, TM* __restrict__ mid, int ny) {
+__device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
+                                              gptr<TM> __restrict__ mid,
+                                              int ny, int blk) {
   constexpr int NTHR = line_threads(NX);
   constexpr int ROWS = p1_rows<TM>(NX);
   // Each round loads NP field pairs of the ROWS rows into LDS lines (row r,
@@ -329,7 +339,6 @@ k_row_dct8(const TM* __restrict__ rm, TM* __restrict__ mid, int ny) {
   __shared__ cpx<TM> line[ROWS * NP * NX];
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   const int tid = threadIdx.x;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
   const int j0 = blk * ROWS;
   const size_t FS = (size_t)NX * ny;
   Roots<TM, NX> rt;
@@ -342,8 +351,8 @@ k_row_dct8(const TM* __restrict__ rm, TM* __restrict__ mid, int ny) {
 #pragma unroll
       for (int l = 0; l < NP; ++l) {
         const int pr = r * NP + l;
-        const TM* ra = rm + PAIR_A[pr] * FS + (size_t)(j0 + rr) * NX;
-        const TM* rb = rm + PAIR_B[pr] * FS + (size_t)(j0 + rr) * NX;
+        const auto ra = rm + PAIR_A[pr] * FS + (size_t)(j0 + rr) * NX;
+        const auto rb = rm + PAIR_B[pr] * FS + (size_t)(j0 + rr) * NX;
         cpx<TM>* ln = line + (rr * NP + l) * NX;
 #pragma unroll
         for (int i = tid; i < NX; i += NTHR) ln[lds_pos(makhoul_slot<NX>(i))] = {ra[i], rb[i]};
@@ -366,8 +375,8 @@ k_row_dct8(const TM* __restrict__ rm, TM* __restrict__ mid, int ny) {
           dct2_post<TM>(z, t1, pa.v[2 * rr + 1], pb.v[2 * rr + 1]);
         }
         const size_t o = ((size_t)sp * ny + j0) * 2;
-        *reinterpret_cast<RowPiece<TM, ROWS>*>(mid + PAIR_A[pr] * FS + o) = pa;
-        *reinterpret_cast<RowPiece<TM, ROWS>*>(mid + PAIR_B[pr] * FS + o) = pb;
+        store_piece<TM, ROWS>(mid + PAIR_A[pr] * FS + o, pa);
+        store_piece<TM, ROWS>(mid + PAIR_B[pr] * FS + o, pb);
       }
     }
     __syncthreads();
@@ -384,13 +393,13 @@ k_row_dct8(const TM* __restrict__ rm, TM* __restrict__ mid, int ny) {
 // P2: column DCT-II of the eight fields and the spectral Gram sums.
 // ---------------------------------------------------------------------------
 template <typename TM, int NY, int KPT, int NTHR>
-__device__ __forceinline__ void column_dct2(const cpx<TM>* __restrict__ src, cpx<TM>* line,
+__device__ __forceinline__ void column_dct2(gptr<const cpx<TM>> __restrict__ src, cpx<TM>* line,
                                             const Roots<TM, NY>& rt, int tid, TM (&A)[KPT],
                                             TM (&B)[KPT]) {
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
     const int jj = tid + q * NTHR;
-    if (jj < NY) line[lds_pos(makhoul_slot<NY>(jj))] = src[jj];
+    if (jj < NY) line[lds_pos(makhoul_slot<NY>(jj))] = gload<TM>(src + jj);
   }
   __syncthreads();
   fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
@@ -415,9 +424,11 @@ __device__ __forceinline__ void stage_accumulate(double (&v)[NV], const int (&id
 }
 
 template <typename TM, int NY>
-__global__ void __launch_bounds__(gram_threads(NY))
-k_col_gram(const TM* __restrict__ mid, const double* __restrict__ lamx,
-           const double* __restrict__ lamy, double* __restrict__ part, int nx, StepConst c) {
+__device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
+                                              gptr<const double> __restrict__ lamx,
+                                              gptr<const double> __restrict__ lamy,
+                                              gptr<double> __restrict__ part, int nx,
+                                              const StepConst& c, int s) {
   constexpr int NTHR = gram_threads(NY);
   constexpr int KPT = (NY + NTHR - 1) / NTHR;
   // FP64 up to 4096: the S~ spectrum waits in LDS, H, Q~, K~ in registers;
@@ -429,14 +440,13 @@ k_col_gram(const TM* __restrict__ mid, const double* __restrict__ lamx,
   __shared__ double red[8 * (NTHR / 64 + 1)];
   __shared__ double acc[P2_NSUM];
   const int tid = threadIdx.x;
-  const int s = xcd_remap(blockIdx.x, gridDim.x);
   const size_t FS = (size_t)nx * NY;
   Roots<TM, NY> rt;
   rt.init(rtab, tid, NTHR);
   if (tid < P2_NSUM) acc[tid] = 0.0;
   const double lx0 = lamx[2 * s], lx1 = lamx[2 * s + 1];
   auto strip = [&](int f) {
-    return reinterpret_cast<const cpx<TM>*>(mid + (size_t)f * FS) + (size_t)s * NY;
+    return reinterpret_cast<gptr<const cpx<TM>>>(mid + (size_t)f * FS) + (size_t)s * NY;
   };
   // 1/sigma (chi) or 1/tau (zeta) at (2s, k) and (2s+1, k)
   auto inv_op = [&](int k, bool chi, double& i0, double& i1) {
@@ -549,9 +559,8 @@ k_col_gram(const TM* __restrict__ mid, const double* __restrict__ lamx,
 // ---------------------------------------------------------------------------
 // Reduction helpers shared by the single-workgroup kernels.
 // ---------------------------------------------------------------------------
-template <int NV, int NTHR>
-__device__ void reduce_rows(const double* __restrict__ part, int nrows, double* red, int tid,
-                            double (&tot)[NV]) {
+template <int NV, int NTHR, typename P>
+__device__ void reduce_rows(P part, int nrows, double* red, int tid, double (&tot)[NV]) {
   double v[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) v[q] = 0.0;
@@ -570,9 +579,9 @@ __device__ void reduce_rows(const double* __restrict__ part, int nrows, double* 
 // ---------------------------------------------------------------------------
 constexpr int SOLVE_THREADS = 256;
 
-__global__ void __launch_bounds__(SOLVE_THREADS)
-k_solve(const double* __restrict__ p1, int n1, const double* __restrict__ p2, int n2,
-        DevScalars* __restrict__ ds, StepConst c) {
+__device__ __forceinline__ void solve_body(gptr<const double> __restrict__ p1, int n1,
+                                           gptr<const double> __restrict__ p2, int n2,
+                                           gptr<DevScalars> __restrict__ ds, const StepConst& c) {
   __shared__ double red[P2_NSUM * (SOLVE_THREADS / 64 + 1)];
   const int tid = threadIdx.x;
   double T1[P1_NSUM], T2[P2_NSUM];
@@ -587,8 +596,8 @@ k_solve(const double* __restrict__ p1, int n1, const double* __restrict__ p2, in
   if (!(rS2 > tiny) || !(rW2 > tiny) || !(rZ2 > tiny)) err |= ERR_NORM;
   const double nS = 1.0 / sqrt(rS2), nQ = 1.0 / sqrt(rW2), nK = 1.0 / sqrt(rZ2);
   const double nF[4] = {nS, 1.0, nQ, nK};
-  const double* Vn = ds->sav[c.slot_n];
-  const double* Vm = ds->sav[c.slot_m];
+  const auto Vn = ds->sav[c.slot_n];
+  const auto Vm = ds->sav[c.slot_m];
   double s[4];
   for (int i = 0; i < 4; ++i) s[i] = c.c0 * Vn[i] + c.c1 * Vm[i] + h2 * nF[i] * T1[P1_ES + i];
   s[3] += h2 * nK * T1[P1_EP];
@@ -648,7 +657,7 @@ k_solve(const double* __restrict__ p1, int n1, const double* __restrict__ p2, in
     x[r] = t / M[r][r];
   }
   const double Vnew[4] = {x[0] + s[0], x[1] + s[1], x[2] + s[2], x[3] + x[4] + s[3]};
-  double* coef = ds->coef;
+  const auto coef = ds->coef;
   coef[0] = 1.0;
   coef[1] = -c.cgs * Vnew[0] * nS;
   coef[2] = -c.cga * Vnew[1];
@@ -678,19 +687,21 @@ k_solve(const double* __restrict__ p1, int n1, const double* __restrict__ p2, in
 // P3: spectral combination, divide by the operator spectrum, DCT-III along y.
 // ---------------------------------------------------------------------------
 template <typename TM, int NY>
-__global__ void __launch_bounds__(line_threads(NY))
-k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
-            const double* __restrict__ lamy, const double* __restrict__ coef,
-            TM* __restrict__ out, int nx, int chi_base, int nchi, int zeta_base, int nzeta,
-            double* __restrict__ colsum, StepConst c) {
+__device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
+                                               gptr<const double> __restrict__ lamx,
+                                               gptr<const double> __restrict__ lamy,
+                                               gptr<const double> __restrict__ coef,
+                                               gptr<TM> __restrict__ out, int nx, int chi_base,
+                                               int nchi, int zeta_base, int nzeta,
+                                               gptr<double> __restrict__ colsum,
+                                               const StepConst& c, int lin) {
   constexpr int NTHR = line_threads(NY);
   constexpr int KPT = (NY + NTHR - 1) / NTHR;
   __shared__ cpx<TM> line[NY];
   __shared__ cpx<double> rtab[Roots<TM, NY>::SIZE];
   __shared__ double red[2 * (NTHR / 64 + 1)];
   const int tid = threadIdx.x;
-  const int lin = xcd_remap(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
-  const int nstrip = gridDim.x;
+  const int nstrip = nx / 2;
   const int s = lin % nstrip;
   const int grp = lin / nstrip;            // 0: chi (Allen-Cahn), 1: zeta (Cahn-Hilliard)
   const size_t FS = (size_t)nx * NY;
@@ -698,7 +709,7 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
   rt.init(rtab, tid, NTHR);
   const int base = grp == 0 ? chi_base : zeta_base;
   const int nf = grp == 0 ? nchi : nzeta;
-  const double* cf = coef + (grp == 0 ? 0 : 5);
+  const auto cf = coef + (grp == 0 ? 0 : 5);
 
   // combine the x-transformed right-hand sides of this group
 #pragma unroll
@@ -707,8 +718,8 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
     if (jj < NY) {
       double ur = 0.0, ui = 0.0;
       for (int f = 0; f < nf; ++f) {
-        const cpx<TM> v =
-            reinterpret_cast<const cpx<TM>*>(mid + (size_t)(base + f) * FS)[(size_t)s * NY + jj];
+        const cpx<TM> v = gload<TM>(reinterpret_cast<gptr<const cpx<TM>>>(
+                                        mid + (size_t)(base + f) * FS) + (size_t)s * NY + jj);
         ur += cf[f] * (double)v.re;
         ui += cf[f] * (double)v.im;
       }
@@ -765,7 +776,7 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
   }
   __syncthreads();
   fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
-  cpx<TM>* dst = reinterpret_cast<cpx<TM>*>(out + (size_t)grp * FS) + (size_t)s * NY;
+  const auto dst = reinterpret_cast<gptr<cpx<TM>>>(out + (size_t)grp * FS) + (size_t)s * NY;
   TM y0[KPT];
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
@@ -773,7 +784,7 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
     y0[q] = (TM)0;
     if (i < NY) {
       const cpx<TM> y = line[lds_pos(fft_pos<TM, NY>(makhoul_slot<NY>(i)))];
-      dst[i] = {y.re, -y.im};
+      gstore<TM>(dst + i, {y.re, -y.im});
       y0[q] = y.re;
     }
   }
@@ -799,17 +810,18 @@ k_col_solve(const TM* __restrict__ mid, const double* __restrict__ lamx,
 // P4: DCT-III along x of the two solved fields -> phi^{n+1}, psi^{n+1}.
 // ---------------------------------------------------------------------------
 template <typename TM, int NX>
-__global__ void __launch_bounds__(line_threads(NX))
-k_row_idct(const TM* __restrict__ out, double* __restrict__ phi_new, double* __restrict__ psi_new,
-           int ny, const double* __restrict__ phi_base, const double* __restrict__ psi_base,
-           const double* __restrict__ colsum) {
+__device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
+                                              gptr<double> __restrict__ phi_new,
+                                              gptr<double> __restrict__ psi_new, int ny,
+                                              gptr<const double> __restrict__ phi_base,
+                                              gptr<const double> __restrict__ psi_base,
+                                              gptr<const double> __restrict__ colsum, int j) {
   constexpr int NTHR = line_threads(NX);
   constexpr int CPT = (NX + NTHR - 1) / NTHR;
   __shared__ cpx<TM> line[NX];
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   __shared__ double red[2 * (NTHR / 64 + 1)];
   const int tid = threadIdx.x;
-  const int j = xcd_remap(blockIdx.x, gridDim.x);
   const size_t FS = (size_t)NX * ny;
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
@@ -895,6 +907,79 @@ k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, 
       mid[(size_t)slot * FS + mid_index(k, j, ny)] = A;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Launches. Every kernel reads its arguments from a table of MemberArgs in
+// device memory, so that one launch can advance several independent grids of
+// the same line length (an ensemble); a single grid is a table of one. Block
+// b of a launch (after the XCD renumbering) works for member idx[b / per] as
+// that member's block b % per.
+// ---------------------------------------------------------------------------
+struct Batch {
+  const MemberArgs* m;
+  const int* idx;
+  int per;
+};
+
+// The table, the member list and `per` are separate kernel arguments, so that
+// the compiler sees the member's pointers as loaded from kernel arguments
+// before any store and can treat them as global memory.
+#define BATCH_PARAMS const MemberArgs* __restrict__ tab, const int* __restrict__ idx, int per
+
+__device__ __forceinline__ const MemberArgs& batch_member(const MemberArgs* __restrict__ tab,
+                                                         const int* __restrict__ idx, int per,
+                                                         int& local) {
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  local = b % per;
+  return tab[idx[b / per]];
+}
+
+template <typename TM>
+__global__ void __launch_bounds__(STENCIL_THREADS) k_stencil(BATCH_PARAMS) {
+  int blk;
+  const MemberArgs& m = batch_member(tab, idx, per, blk);
+  const RowArgs a{m.phn, m.phm, m.phmm, m.psn, m.psm, m.psmm};
+  stencil_body<TM>(a, static_cast<gptr<TM>>(m.rm), m.part1, m.nx, m.ny, m.iters, m.k, blk);
+}
+
+template <typename TM, int NX>
+__global__ void __launch_bounds__(line_threads(NX)) k_row_dct8(BATCH_PARAMS) {
+  int blk;
+  const MemberArgs& m = batch_member(tab, idx, per, blk);
+  row_dct8_body<TM, NX>(static_cast<gptr<const TM>>(m.rm), static_cast<gptr<TM>>(m.mid), m.ny,
+                        blk);
+}
+
+template <typename TM, int NY>
+__global__ void __launch_bounds__(gram_threads(NY)) k_col_gram(BATCH_PARAMS) {
+  int blk;
+  const MemberArgs& m = batch_member(tab, idx, per, blk);
+  col_gram_body<TM, NY>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.part2, m.nx, m.k,
+                        blk);
+}
+
+__global__ void __launch_bounds__(SOLVE_THREADS) k_solve(BATCH_PARAMS) {
+  int blk;
+  const MemberArgs& m = batch_member(tab, idx, per, blk);
+  solve_body(m.part1, m.p1_blocks, m.part2, m.nx / 2, m.ds, m.k);
+}
+
+template <typename TM, int NY>
+__global__ void __launch_bounds__(line_threads(NY)) k_col_solve(BATCH_PARAMS) {
+  int blk;
+  const MemberArgs& m = batch_member(tab, idx, per, blk);
+  col_solve_body<TM, NY>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.coef,
+                         static_cast<gptr<TM>>(m.outc), m.nx, m.chi_base, m.nchi, m.zeta_base,
+                         m.nzeta, m.colsum, m.k, blk);
+}
+
+template <typename TM, int NX>
+__global__ void __launch_bounds__(line_threads(NX)) k_row_idct(BATCH_PARAMS) {
+  int blk;
+  const MemberArgs& m = batch_member(tab, idx, per, blk);
+  row_idct_body<TM, NX>(static_cast<gptr<const TM>>(m.outc), m.phi_new, m.psi_new, m.ny,
+                        m.phi_base, m.psi_base, m.colsum, blk);
 }
 
 }  // namespace ccm

@@ -93,3 +93,31 @@ def test_init_rejects_null_and_unknown_modes():
     assert lib.ccmsav_destroy(None) == -1
     assert C.strerror(-6).startswith("unsupported")
     assert C.strerror(5) == "unknown status"
+
+
+def test_batch_workspace_and_validation_without_a_device():
+    lib = C.load()
+    a, b = _params(), _params(nx=32, ny=128, eps=0.3)
+    arr = (C.Params * 2)(a, b)
+    one = lib.ccmsav_workspace_bytes(ctypes.byref(a))
+    two = lib.ccmsav_workspace_bytes_batch(2, arr)
+    assert two > one + (6 + 8 + 2) * 32 * 128 * 8
+    assert lib.ccmsav_workspace_bytes_batch(0, arr) == 0
+    bad = (C.Params * 2)(a, _params(nx=100))
+    assert lib.ccmsav_workspace_bytes_batch(2, bad) == 0
+    h = ctypes.c_void_p()
+    buf = (ctypes.c_double * 4)()
+    ptrs = (ctypes.c_void_p * 2)(ctypes.addressof(buf), ctypes.addressof(buf))
+    # member count out of range, mixed precisions, mixed flags, a NULL field
+    assert lib.ccmsav_init_batch(ctypes.byref(h), 0, arr, ptrs, ptrs, None, 0, None) == -1
+    mixed = (C.Params * 2)(a, C.Params.from_dict(dict(circle_member(64).params), C.MIXED))
+    assert lib.ccmsav_init_batch(ctypes.byref(h), 2, mixed, ptrs, ptrs, None, 0, None) == -1
+    flagged = (C.Params * 2)(a, C.Params.from_dict(dict(circle_member(64).params), 0,
+                                                   C.FLAG_GRAPH))
+    assert lib.ccmsav_init_batch(ctypes.byref(h), 2, flagged, ptrs, ptrs, None, 0, None) == -1
+    nulls = (ctypes.c_void_p * 2)(ctypes.addressof(buf), None)
+    assert lib.ccmsav_init_batch(ctypes.byref(h), 2, arr, ptrs, nulls, None, 0, None) == -1
+    assert h.value is None
+    assert lib.ccmsav_members(None) == -1
+    e = ctypes.c_double()
+    assert lib.ccmsav_energy_m(None, 0, ctypes.byref(e), None) == -1

@@ -7,6 +7,7 @@ without sharing any of the method.
 from .generators import (  # noqa: F401
     DEFAULT_DT,
     VESICLE_DT,
+    ENSEMBLE_DT,
     WORKLOADS,
     Member,
     circle_member,
