@@ -36,6 +36,24 @@ HBM_PEAK_GBS = 8000.0
 # column pass reads eight; the column solve reads seven and writes two; the
 # row inverse reads two and writes the two new state fields. The mixed path
 # solves for increments, so its row inverse also reads phi^n, psi^n.
+def gemm_flops(members):
+    """Matrix-core flops per launch of each phase of the DCT-as-GEMM variant:
+    three bf16 products (hi hi, hi lo, lo hi) of 2 m n k flops each, for the
+    row products of 8 (forward) and 2 (inverse) fields against the nx x nx DCT
+    matrix and the column products against the ny x ny one."""
+    f = {"row_dct": 0.0, "col_gram": 0.0, "col_solve": 0.0, "row_idct": 0.0}
+    for mb in members:
+        nx, ny = mb.params["nx"], mb.params["ny"]
+        f["row_dct"] += 3 * 2.0 * (8 * ny) * nx * nx
+        f["col_gram"] += 3 * 2.0 * 8 * nx * ny * ny
+        f["col_solve"] += 3 * 2.0 * 2 * nx * ny * ny
+        f["row_idct"] += 3 * 2.0 * (2 * ny) * nx * nx
+    return f
+
+
+BF16_PEAK_TFLOPS = 2500.0
+
+
 def kernel_bytes_per_cell(precision: str):
     m = 8 if precision == "fp64" else 4
     return {
@@ -141,7 +159,7 @@ def main():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="vesicle4096")
-    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="mixed", choices=["fp64", "mixed", "gemm"])
     ap.add_argument("--graph", action="store_true",
                     help="replay the steady-state steps from a captured HIP graph")
     ap.add_argument("--profile-steps", type=int, default=50,
@@ -184,7 +202,20 @@ def main():
         print(f"[bench] kernel {k}: {ms * 1e3:.1f} us/launch, {per_cell[k]} B/cell, "
               f"{gbs:.0f} GB/s", file=sys.stderr, flush=True)
     roofline = None
-    if prof:
+    if prof and args.precision == "gemm":
+        fl = gemm_flops(members)
+        for k, v in fl.items():
+            print(f"[bench] phase {k}: {prof[k] * 1e3:.1f} us, "
+                  f"{v / (prof[k] * 1e-3) / 1e12:.1f} TFLOP/s (bf16 matrix cores, incl. splits)",
+                  file=sys.stderr, flush=True)
+        dom = max(fl, key=lambda k: prof[k])
+        achieved = fl[dom] / (prof[dom] * 1e-3) / 1e12
+        roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved,
+                    "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / BF16_PEAK_TFLOPS,
+                    "traffic": None, "flops_per_launch": fl[dom], "us_per_launch": prof[dom] * 1e3,
+                    "step_flops": sum(fl.values()),
+                    "step_frac": sum(fl.values()) / (ms_per_step * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}
+    elif prof:
         dom = max(prof, key=prof.get)
         dom_bytes = per_cell[dom] * cells
         achieved = dom_bytes / (prof[dom] * 1e-3) / 1e9
@@ -198,7 +229,7 @@ def main():
     check = {"mass_drift": run["drift"], "E_mod": run["energy"][0],
              "finite": bool(np.all(np.isfinite(run["energy"])))}
     compare = None
-    if args.precision == "mixed" and not args.no_compare:
+    if args.precision != "fp64" and not args.no_compare:
         ref = timed_run(C, torch, members, "fp64", args.steps, args.warmup, args.profile_steps,
                         dev, args.graph)
         rel = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())  # noqa: E731
@@ -241,7 +272,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": {"fp64": "f64", "mixed": "f32+f64", "gemm": "bf16x3+f32+f64"}[args.precision],
         "data": "synthetic",
         "config": config,
         "roofline": roofline,

@@ -50,13 +50,19 @@ typedef enum {
 
 typedef enum {
   CCMSAV_FP64 = 0,          /* all arithmetic in FP64 */
-  CCMSAV_MIXED = 1          /* FP32 transforms; the step is solved for the
+  CCMSAV_MIXED = 1,         /* FP32 transforms; the step is solved for the
                                increments phi^{n+1} - phi^n, psi^{n+1} - psi^n
                                from residuals formed in FP64 (the chi residual
                                uses the biharmonic Delta_h^2 phi^n), and the
                                mean of the psi increment is fixed in FP64 so
                                that h^2 sum psi is conserved to FP64 rounding.
                                FP64 state, SAVs, inner-product sums and 5x5 */
+  CCMSAV_MIXED_GEMM_BF16X3 = 2 /* as CCMSAV_MIXED, with every transform a dense
+                               product with the DCT matrix on the matrix cores:
+                               bfloat16 hi/lo splits of both operands, three
+                               products (hi hi + hi lo + lo hi) accumulated in
+                               FP32. Single-member contexts without
+                               CCMSAV_FLAG_GRAPH only (else EUNSUPPORTED). */
 } ccmsav_precision;
 
 /*

@@ -11,6 +11,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libccmsav.so")
 SOURCES = ["ccmsav_runtime.hip"]
+# rocBLAS runs the dense products of the DCT-as-GEMM variant.
+LIBS = ["-lrocblas"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
@@ -29,7 +31,7 @@ def build(verbose: bool = True) -> str:
     """Compile every HIP source into the in-tree shared library; return its path."""
     tmp = LIB + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp, *LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libccmsav.s
 
 FP64 = 0
 MIXED = 1
-PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+MIXED_GEMM_BF16X3 = 2
+PRECISIONS = {"fp64": FP64, "mixed": MIXED, "gemm": MIXED_GEMM_BF16X3}
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDOMAIN",
           -5: "ENONFINITE", -6: "EUNSUPPORTED"}

@@ -16,8 +16,11 @@
 #include <new>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "ccmsav.h"
 #include "diag_kernels.hpp"
+#include "gemm_dct.hpp"
 #include "step_kernels.hpp"
 
 using namespace ccm;
@@ -94,10 +97,25 @@ template <typename TM> struct Launch {
   using T = Tables<4, 5, 6, 7, 8, 9, 10, 11, 12, 13>;
 };
 
-size_t mid_elem(int precision) { return precision == CCMSAV_MIXED ? 4 : 8; }
+size_t mid_elem(int precision) { return precision == CCMSAV_FP64 ? 8 : 4; }
+bool is_gemm(int precision) { return precision == CCMSAV_MIXED_GEMM_BF16X3; }
+// Solved in increment form (FP32 transforms of FP64-formed residuals).
+bool is_inc(int precision) { return precision != CCMSAV_FP64; }
+// Cells per thread of the GEMM variant's inner-product kernel.
+constexpr int kGramPerThread = 16;
+size_t gemm_gram_blocks(const ccmsav_params* p) {
+  const size_t cells = (size_t)p->nx * p->ny;
+  const size_t per_block = (size_t)GEMM_THREADS * kGramPerThread;
+  return (cells + per_block - 1) / per_block;
+}
+size_t p2_rows(const ccmsav_params* p) {
+  return is_gemm(p->precision) ? gemm_gram_blocks(p) : (size_t)(p->nx / 2);
+}
 
 struct Layout {
-  size_t state, rm, mid, outc, part1, part2, parte, lamx, lamy, colsum, unit, ds, total;
+  size_t state, rm, mid, outc, part1, part2, parte, lamx, lamy, colsum, unit, ds;
+  size_t split, dx, dy;   // GEMM variant: bf16 operand halves, DCT matrices (hi, lo)
+  size_t total;
 };
 
 Layout layout(const ccmsav_params* p) {
@@ -111,13 +129,18 @@ Layout layout(const ccmsav_params* p) {
   L.outc = off;  off = align_up(off + 2 * cells * me);
   L.part1 = off;
   off = align_up(off + (size_t)stencil_shape(p->nx, p->ny).blocks * P1_NSUM * sizeof(double));
-  L.part2 = off; off = align_up(off + (size_t)(p->nx / 2) * P2_NSUM * sizeof(double));
+  L.part2 = off; off = align_up(off + p2_rows(p) * P2_NSUM * sizeof(double));
   L.parte = off; off = align_up(off + (size_t)p->ny * E_NSUM * sizeof(double));
   L.lamx = off;  off = align_up(off + (size_t)p->nx * sizeof(double));
   L.lamy = off;  off = align_up(off + (size_t)p->ny * sizeof(double));
   L.colsum = off; off = align_up(off + (size_t)p->ny * sizeof(double));
   L.unit = off;  off = align_up(off + 8 * sizeof(double));
   L.ds = off;    off = align_up(off + sizeof(DevScalars));
+  if (is_gemm(p->precision)) {
+    L.split = off; off = align_up(off + 2 * M_NFIELD * cells * sizeof(uint16_t));
+    L.dx = off;    off = align_up(off + 2 * (size_t)p->nx * p->nx * sizeof(uint16_t));
+    L.dy = off;    off = align_up(off + 2 * (size_t)p->ny * p->ny * sizeof(uint16_t));
+  }
   L.total = off;
   return L;
 }
@@ -128,7 +151,10 @@ bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 int check_params(const ccmsav_params* p) {
   if (!p) return CCMSAV_EINVAL;
   if ((p->flags & ~CCMSAV_FLAG_GRAPH) != 0) return CCMSAV_EINVAL;
-  if (p->precision != CCMSAV_FP64 && p->precision != CCMSAV_MIXED) return CCMSAV_EUNSUPPORTED;
+  if (p->precision != CCMSAV_FP64 && p->precision != CCMSAV_MIXED &&
+      p->precision != CCMSAV_MIXED_GEMM_BF16X3)
+    return CCMSAV_EUNSUPPORTED;
+  if (is_gemm(p->precision) && (p->flags & CCMSAV_FLAG_GRAPH)) return CCMSAV_EUNSUPPORTED;
   if (p->nx <= 0 || p->ny <= 0) return CCMSAV_EINVAL;
   const int lx = log2_exact(p->nx), ly = log2_exact(p->ny);
   if (lx < kMinLog || lx > kMaxLog || ly < kMinLog || ly > kMaxLog) return CCMSAV_EUNSUPPORTED;
@@ -154,6 +180,7 @@ int check_batch(int32_t nmemb, const ccmsav_params* p) {
     if (r != CCMSAV_OK) return r;
     if (p[m].precision != p[0].precision || p[m].flags != p[0].flags) return CCMSAV_EINVAL;
   }
+  if (nmemb > 1 && is_gemm(p[0].precision)) return CCMSAV_EUNSUPPORTED;
   return CCMSAV_OK;
 }
 
@@ -286,6 +313,13 @@ struct Member {
   double* unit_coef;       // {1, 0, 0, 0, 0, 1, 0, 0} for the standalone solve
   DevScalars* ds;
   StencilShape sh;
+  // GEMM variant
+  uint16_t* split_hi;      // bf16 halves of the current product operand (8 fields)
+  uint16_t* split_lo;
+  uint16_t* dx_hi;         // DCT-II matrix along x, column-major D_x (hi, lo halves)
+  uint16_t* dx_lo;
+  uint16_t* dy_hi;
+  uint16_t* dy_lo;
 };
 
 // Members with one grid shape; d_idx lists their indices in device memory.
@@ -314,13 +348,15 @@ struct ccmsav_ctx {
   hipStream_t gstream = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // DCT-as-GEMM variant
+  rocblas_handle blas = nullptr;
 };
 
 namespace {
 
 MemberArgs member_args(const Member& m, int precision, int table) {
   MemberArgs a{};
-  const bool inc = precision == CCMSAV_MIXED;
+  const bool inc = is_inc(precision);
   a.rm = to_global(m.rm);
   a.mid = to_global(m.mid);
   a.outc = to_global(m.outc);
@@ -333,6 +369,7 @@ MemberArgs member_args(const Member& m, int precision, int table) {
   a.ny = m.p.ny;
   a.iters = m.sh.iters;
   a.p1_blocks = m.sh.blocks;
+  a.p2_rows = (int)p2_rows(&m.p);
   if (table == kSolveTable) {
     // chi^{-1} and zeta^{-1} of the single field in slot M_F (App. C).
     a.k = make_const(m.p, true);
@@ -416,13 +453,99 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe)
   pe.mark(11, st);
 }
 
-void enqueue_step_level(ccmsav_ctx* c, int64_t level, hipStream_t st,
-                        PhaseEvents pe = PhaseEvents{nullptr}) {
+// ---- DCT-as-GEMM variant ------------------------------------------------------
+
+// C = op(A) op(B) with both operands given as bf16 (hi, lo) halves:
+// C = A_hi B_hi + A_hi B_lo + A_lo B_hi, FP32 accumulation (column-major).
+int gemm3(ccmsav_ctx* c, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
+          const uint16_t* a_hi, const uint16_t* a_lo, int lda, int64_t sa, const uint16_t* b_hi,
+          const uint16_t* b_lo, int ldb, int64_t sb, float* out, int ldc, int64_t sc,
+          int batch) {
+  const float one = 1.0f, zero = 0.0f;
+  const uint16_t* as[3] = {a_hi, a_hi, a_lo};
+  const uint16_t* bs[3] = {b_hi, b_lo, b_hi};
+  for (int t = 0; t < 3; ++t) {
+    const rocblas_status r = rocblas_gemm_strided_batched_ex(
+        c->blas, ta, tb, m, n, k, &one, as[t], rocblas_datatype_bf16_r, lda, sa, bs[t],
+        rocblas_datatype_bf16_r, ldb, sb, t == 0 ? &zero : &one, out, rocblas_datatype_f32_r,
+        ldc, sc, out, rocblas_datatype_f32_r, ldc, sc, batch, rocblas_datatype_f32_r,
+        rocblas_gemm_algo_standard, 0, 0);
+    if (r != rocblas_status_success) return CCMSAV_EHIP;
+  }
+  return CCMSAV_OK;
+}
+
+void split(ccmsav_ctx* c, const Member& m, const float* x, size_t n, hipStream_t st) {
+  const int grid = (int)std::min<size_t>((n + GEMM_THREADS - 1) / GEMM_THREADS, 8192);
+  hipLaunchKernelGGL(k_split_bf16, dim3(grid), dim3(GEMM_THREADS), 0, st, x, m.split_hi,
+                     m.split_lo, n);
+}
+
+// One step of the single member with every transform a product with D.
+// Data flow (FP32, row-major [field][y][x]): stencil -> rm; rows: rm D_x^T ->
+// mid; columns: D_y mid -> rm (2D spectra); inner products, 5x5; combine ->
+// outc; columns: D_y^T outc -> mid; rows: mid D_x -> outc; state update.
+int enqueue_step_gemm(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEvents pe) {
+  const Member& m = c->mem[0];
+  const SizeClass& k = c->cls[0];
+  const int nx = m.p.nx, ny = m.p.ny;
+  const size_t cells = (size_t)nx * ny;
+  const MemberArgs* tab = c->d_args + (size_t)table_of_level(level) * c->mem.size();
+  const MemberArgs& ha = c->h_args[(size_t)table_of_level(level) * c->mem.size()];
+  float* rm = static_cast<float*>(m.rm);
+  float* mid = static_cast<float*>(m.mid);
+  float* outc = static_cast<float*>(m.outc);
+  const rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
+  int r = CCMSAV_OK;
+  pe.mark(0, st);
+  hipLaunchKernelGGL(k_stencil<float>, dim3(k.sh.blocks), dim3(STENCIL_THREADS), 0, st, tab,
+                     k.d_idx, k.sh.blocks);
+  pe.mark(1, st);
+  pe.mark(2, st);
+  split(c, m, rm, M_NFIELD * cells, st);
+  r |= gemm3(c, N_, N_, nx, M_NFIELD * ny, nx, m.dx_hi, m.dx_lo, nx, 0, m.split_hi, m.split_lo,
+             nx, 0, mid, nx, 0, 1);
+  pe.mark(3, st);
+  pe.mark(4, st);
+  split(c, m, mid, M_NFIELD * cells, st);
+  r |= gemm3(c, N_, T_, nx, ny, ny, m.split_hi, m.split_lo, nx, (int64_t)cells, m.dy_hi,
+             m.dy_lo, ny, 0, rm, nx, (int64_t)cells, M_NFIELD);
+  hipLaunchKernelGGL(k_gemm_gram, dim3((unsigned)gemm_gram_blocks(&m.p)), dim3(GEMM_THREADS), 0,
+                     st, rm, m.lamx, m.lamy, m.part2, nx, ny, kGramPerThread, ha.k);
+  pe.mark(5, st);
+  pe.mark(6, st);
+  hipLaunchKernelGGL(k_solve, dim3(1), dim3(SOLVE_THREADS), 0, st, tab, k.d_idx, 1);
+  pe.mark(7, st);
+  pe.mark(8, st);
+  hipLaunchKernelGGL(k_gemm_combine, dim3((unsigned)std::min<size_t>(cells / GEMM_THREADS + 1, 8192)),
+                     dim3(GEMM_THREADS), 0, st, rm, m.ds->coef, m.lamx, m.lamy, outc, nx, ny,
+                     ha.k);
+  split(c, m, outc, 2 * cells, st);
+  r |= gemm3(c, N_, N_, nx, ny, ny, m.split_hi, m.split_lo, nx, (int64_t)cells, m.dy_hi,
+             m.dy_lo, ny, 0, mid, nx, (int64_t)cells, 2);
+  hipLaunchKernelGGL(k_gemm_colsum, dim3(1), dim3(GEMM_THREADS), 0, st, mid + cells, m.colsum,
+                     nx, ny);
+  pe.mark(9, st);
+  pe.mark(10, st);
+  split(c, m, mid, 2 * cells, st);
+  r |= gemm3(c, T_, N_, nx, 2 * ny, nx, m.dx_hi, m.dx_lo, nx, 0, m.split_hi, m.split_lo, nx, 0,
+             outc, nx, 0, 1);
+  const int sn = (int)(level % 3), snew = (int)((level + 1) % 3);
+  hipLaunchKernelGGL(k_gemm_finalize, dim3(ny), dim3(GEMM_THREADS), 0, st, outc, m.phi[sn],
+                     m.psi[sn], m.colsum, m.phi[snew], m.psi[snew], nx, ny);
+  pe.mark(11, st);
+  return r;
+}
+
+int enqueue_step_level(ccmsav_ctx* c, int64_t level, hipStream_t st,
+                       PhaseEvents pe = PhaseEvents{nullptr}) {
+  if (is_gemm(c->precision)) return enqueue_step_gemm(c, level, st, pe);
   const int t = table_of_level(level);
   if (c->precision == CCMSAV_MIXED)
     enqueue_step_kind<float>(c, t, st, pe);
   else
     enqueue_step_kind<double>(c, t, st, pe);
+  return CCMSAV_OK;
 }
 
 // Capture three steady-state steps (levels 3k, 3k+1, 3k+2, k >= 1) into a graph.
@@ -461,6 +584,7 @@ int read_err(ccmsav_ctx* c, int* err) {
 }
 
 void free_ctx(ccmsav_ctx* c) {
+  if (c->blas) (void)rocblas_destroy_handle(c->blas);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
@@ -486,6 +610,41 @@ int run_diag(ccmsav_ctx* c, int mi, bool energy) {
   hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(DIAG_THREADS), 0, c->stream, m.parte, m.p.ny,
                      m.ds, sn, n >= 1 ? sm : sn, d);
   if (hipGetLastError() != hipSuccess) return CCMSAV_EHIP;
+  return CCMSAV_OK;
+}
+
+// FP32 -> bfloat16 on the host, round to nearest even (finite inputs).
+uint16_t host_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, sizeof(u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float host_bf16_to_f32(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, sizeof(f));
+  return f;
+}
+
+// Orthonormal DCT-II matrix of size n (App. C), column-major
+// (element (k, i) = s_k cos(pi k (2i + 1) / (2n)) at k + i n), as bf16 halves.
+int upload_dct_matrix(uint16_t* d_hi, uint16_t* d_lo, int n, hipStream_t st) {
+  std::vector<uint16_t> hi((size_t)n * n), lo((size_t)n * n);
+  const double s0 = std::sqrt(1.0 / n), s1 = std::sqrt(2.0 / n);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      const double v = (k == 0 ? s0 : s1) * std::cos(M_PI * k * (2.0 * i + 1.0) / (2.0 * n));
+      const uint16_t h = host_bf16((float)v);
+      hi[(size_t)k + (size_t)i * n] = h;
+      lo[(size_t)k + (size_t)i * n] = host_bf16((float)(v - (double)host_bf16_to_f32(h)));
+    }
+  if (hipMemcpyAsync(d_hi, hi.data(), hi.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipMemcpyAsync(d_lo, lo.data(), lo.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return CCMSAV_EHIP;
   return CCMSAV_OK;
 }
 
@@ -580,6 +739,20 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
     m.colsum = reinterpret_cast<double*>(mb + L.colsum);
     m.unit_coef = reinterpret_cast<double*>(mb + L.unit);
     m.ds = reinterpret_cast<DevScalars*>(mb + L.ds);
+    if (is_gemm(m.p.precision)) {
+      m.split_hi = reinterpret_cast<uint16_t*>(mb + L.split);
+      m.split_lo = m.split_hi + M_NFIELD * cells;
+      m.dx_hi = reinterpret_cast<uint16_t*>(mb + L.dx);
+      m.dx_lo = m.dx_hi + (size_t)m.p.nx * m.p.nx;
+      m.dy_hi = reinterpret_cast<uint16_t*>(mb + L.dy);
+      m.dy_lo = m.dy_hi + (size_t)m.p.ny * m.p.ny;
+      if (upload_dct_matrix(m.dx_hi, m.dx_lo, m.p.nx, c->stream) != CCMSAV_OK ||
+          upload_dct_matrix(m.dy_hi, m.dy_lo, m.p.ny, c->stream) != CCMSAV_OK)
+        return fail(CCMSAV_EHIP);
+      if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
+          rocblas_set_stream(c->blas, c->stream) != rocblas_status_success)
+        return fail(CCMSAV_EHIP);
+    }
 
     // Eigenvalues of -Delta_h per direction (App. C): (4/h^2) sin^2(pi k / (2 n)).
     std::vector<double> lx(m.p.nx), ly(m.p.ny);
@@ -685,7 +858,8 @@ int ccmsav_step(ccmsav_ctx* c, int32_t nsteps) {
       left -= 3 * reps;
       continue;
     }
-    enqueue_step_level(c, c->level, c->stream);
+    const int r = enqueue_step_level(c, c->level, c->stream);
+    if (r != CCMSAV_OK) return r;
     c->level += 1;
     left -= 1;
   }
@@ -708,7 +882,9 @@ int ccmsav_profile_steps(ccmsav_ctx* c, int32_t nsteps, double* ms_per_phase) {
   }
   if (rc == CCMSAV_OK) {
     for (int32_t s = 0; s < nsteps; ++s) {
-      enqueue_step_level(c, c->level, c->stream, PhaseEvents{ev + (size_t)nev * s});
+      if (enqueue_step_level(c, c->level, c->stream, PhaseEvents{ev + (size_t)nev * s}) !=
+          CCMSAV_OK)
+        rc = CCMSAV_EHIP;
       c->level += 1;
     }
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
@@ -843,7 +1019,7 @@ int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, dou
     LT::t_col_solve[m.ly - kMinLog](c->stream, m.p.nx, Batch{d, k.d_idx, m.p.nx});
     LT::t_row_idct[m.lx - kMinLog](c->stream, m.p.ny, Batch{d, k.d_idx, m.p.ny});
   };
-  if (c->precision == CCMSAV_MIXED)
+  if (c->precision != CCMSAV_FP64)
     run(0.0f);
   else
     run(0.0);

@@ -136,6 +136,7 @@ struct MemberArgs {
   gptr<const double> coef;       // spectral combination (ds->coef, or unit weights)
   int nx, ny;
   int iters, p1_blocks;          // stencil launch shape
+  int p2_rows;                   // rows of column partial sums
   int chi_base, nchi, zeta_base, nzeta;   // field groups combined by the column solve
   StepConst k;
 };

@@ -962,7 +962,7 @@ __global__ void __launch_bounds__(gram_threads(NY)) k_col_gram(BATCH_PARAMS) {
 __global__ void __launch_bounds__(SOLVE_THREADS) k_solve(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
-  solve_body(m.part1, m.p1_blocks, m.part2, m.nx / 2, m.ds, m.k);
+  solve_body(m.part1, m.p1_blocks, m.part2, m.p2_rows, m.ds, m.k);
 }
 
 template <typename TM, int NY>

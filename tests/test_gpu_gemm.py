@@ -1,0 +1,72 @@
+"""The DCT-as-GEMM variant (bf16 hi/lo splits, three products, FP32
+accumulation on the matrix cores) against the FP64 path and the oracle.
+
+Each product carries a relative error of about 2^-16 (two bf16 halves per
+operand, the lo x lo term dropped) of the increment-form residuals it acts on,
+150 times the FP32 rounding of the mixed path; over these runs that leaves
+the fields within about 2e-4 of the FP64 path (bound 5e-4). A wrong sign,
+index or transpose anywhere in the products gives O(1) errors. Mass stays
+exact to FP64 rounding and the modified energy keeps decaying.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from parity_util import rel_linf
+from workloads import make_workload, circle_member
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2601_10057_amd import ccmsav as C  # noqa: E402
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def run(m, precision, steps, every):
+    out = []
+    with C.Context(m.params, m.phi0, m.psi0, precision) as ctx:
+        m0 = ctx.mass()[0]
+        for k in range(every, steps + 1, every):
+            ctx.step(every)
+            out.append((k, *ctx.fields(), ctx.savs()[0], ctx.energy(), ctx.mass()[0]))
+    return m0, out
+
+
+@pytest.mark.parametrize("name,n,steps", [("circle128", None, 100), ("vesicle1024", 512, 60),
+                                          ("vesicle2048", None, 100)])
+def test_gemm_variant_tracks_fp64(name, n, steps):
+    m = make_workload(name, n)[0]
+    note(f"gemm vs fp64 {name} n={m.params['nx']} {steps} steps")
+    m0, ref = run(m, "fp64", steps, steps // 4)
+    m0g, got = run(m, "gemm", steps, steps // 4)
+    assert m0g == m0
+    worst = 0.0
+    drift = 0.0
+    prev = None
+    for r, g in zip(ref, got):
+        worst = max(worst, rel_linf(g[1], r[1]), rel_linf(g[2], r[2]))
+        drift = max(drift, abs(g[5] - m0) / abs(m0))
+        if prev is not None:
+            assert g[4] <= prev + 1e-12 * abs(prev)
+        prev = g[4]
+    note(f"worst rel L-inf {worst:.3e}, mass drift {drift:.2e}")
+    assert worst <= 5e-4
+    assert drift <= 5e-11
+
+
+def test_gemm_variant_rejects_ensembles_and_graphs():
+    m = circle_member(32)
+    with pytest.raises(C.CcmsavError) as e:
+        C.Context.ensemble([m.params, m.params], [m.phi0] * 2, [m.psi0] * 2, "gemm")
+    assert e.value.name == "EUNSUPPORTED"
+    with pytest.raises(C.CcmsavError) as e:
+        C.Context(m.params, m.phi0, m.psi0, "gemm", graph=True)
+    assert e.value.name == "EUNSUPPORTED"
