@@ -4,8 +4,10 @@ An ensemble advances its members with one launch per kernel and grid shape;
 each member must come out bit for bit as it does in a context of its own,
 with or without the captured graph. The 48 x 256^2 + 16 x 512^2 ensemble is
 run for its full 2000 steps in mixed precision (graph-captured) and compared
-member by member with the FP64 ensemble.
+member by member with the FP64 ensemble, whose members 11 and 17 are held to
+stored oracle trajectories (tests/golden/make_ensemble_golden.py).
 """
+import os
 import sys
 
 import numpy as np
@@ -126,7 +128,9 @@ def test_ensemble_workload_mixed_against_fp64():
     checkpoints are reported. Mass drift (5e-11) and energy decay are held for
     all members at every checkpoint."""
     ms = make_workload("ensemble48x256_16x512")
-    checkpoints = (100, 500, 2000)
+    checkpoints = (100, 500, 1000, 2000)
+    golden = np.load(os.path.join(os.path.dirname(__file__), "golden",
+                                  "ensemble_member_oracle.npz"))
     nm = len(ms)
     note(f"ensemble workload {nm} members, {checkpoints[-1]} steps")
     phi32 = [m.phi0.astype(np.float32).astype(np.float64) for m in ms]
@@ -149,6 +153,15 @@ def test_ensemble_workload_mixed_against_fp64():
                 mass = [ens.mass(i)[0] for i in range(nm)]
                 drift = max(drift, max(abs(a - b) / abs(b) for a, b in zip(mass, m0)))
                 snaps[k] = [ens.fields(i) for i in range(nm)]
+                if name == "fp64" and f"m11_k{k}_phi" in golden.files:
+                    # members 11 and 17 against the stored oracle trajectories
+                    for i in (11, 17):
+                        env = golden[f"m{i}_k{k}_env"]
+                        tol = max(1e-12, 10.0 * float(env.max()))
+                        phi, psi = snaps[k][i]
+                        assert rel_linf(phi[::4, ::4], golden[f"m{i}_k{k}_phi"]) <= tol, (i, k)
+                        assert rel_linf(psi[::4, ::4], golden[f"m{i}_k{k}_psi"]) <= tol, (i, k)
+                        assert rel_linf(ens.savs(i)[0], golden[f"m{i}_k{k}_sav"]) <= tol, (i, k)
             out[name] = (snaps, drift)
             note(f"{name}: mass drift {drift:.2e}")
     assert out["fp64"][1] <= 5e-11
