@@ -101,6 +101,12 @@ template <typename T> using gptr = __attribute__((address_space(1))) T*;
 
 template <typename T> inline gptr<T> to_global(T* p) { return (gptr<T>)p; }
 
+// The operator spectra of App. C: sigma = C1 + C2 L + C3 L^2 (chi) and
+// tau = alpha + lam L (zeta), with L the eigenvalue of -Delta_h.
+struct OpConst {
+  double C1, C2, C3, alpha, lam;
+};
+
 // State pointers of the three levels a step reads.
 struct RowArgs {
   gptr<const double> phn;   // phi^n

@@ -113,149 +113,31 @@ __device__ __forceinline__ double ptilde(const StepConst& c, double psi, double 
                 c.gamma_out * (1.0 - p) * (psi - c.psi_out));
 }
 
-// Explicit stencil terms of eqs. (AC_BDF2)-(Z_BDF2) at cell (i, j), with
-// phi* = x0 phi^n + x1 phi^{n-1}: the eight right-hand-side fields (slot
-// order of Mid) and the cell's contributions to the partial sums. Neighbours
-// outside the grid are the ghost copies of App. D (index clamping).
-template <bool INC>
-__device__ __forceinline__ void stencil_cell(const RowArgs& a, int i, int j, int nx, int ny,
-                                             const StepConst& c, double (&sums)[P1_NSUM],
-                                             double (&out)[M_NFIELD]) {
-  const int jn = min(j + 1, ny - 1), js = max(j - 1, 0);
-  const int ie = min(i + 1, nx - 1), iw = max(i - 1, 0);
-  const double k32 = 0.75 * 1.4142135623730950488;   // 3 sqrt(2) / 4
-  const double half_pi = 1.5707963267948966192;
-  const double ieps = 1.0 / c.eps;
-  const size_t oc = (size_t)j * nx + i, oe = (size_t)j * nx + ie, ow = (size_t)j * nx + iw;
-  const size_t on = (size_t)jn * nx + i, os = (size_t)js * nx + i;
-  const double phn_c = a.phn[oc], phm_c = a.phm[oc];
-  const double psn_c = a.psn[oc], psm_c = a.psm[oc];
-  // phi*, psi* at the cell and its four neighbours
-  const double pc = c.x0 * phn_c + c.x1 * phm_c;
-  const double pe = c.x0 * a.phn[oe] + c.x1 * a.phm[oe];
-  const double pw = c.x0 * a.phn[ow] + c.x1 * a.phm[ow];
-  const double pn = c.x0 * a.phn[on] + c.x1 * a.phm[on];
-  const double ps = c.x0 * a.phn[os] + c.x1 * a.phm[os];
-  const double qc = c.x0 * psn_c + c.x1 * psm_c;
-  const double qe = c.x0 * a.psn[oe] + c.x1 * a.psm[oe];
-  const double qw = c.x0 * a.psn[ow] + c.x1 * a.psm[ow];
-  const double qn = c.x0 * a.psn[on] + c.x1 * a.psm[on];
-  const double qs = c.x0 * a.psn[os] + c.x1 * a.psm[os];
-  const double gxe = (pe - pc) * c.inv_h, gxw = (pc - pw) * c.inv_h;
-  const double gyn = (pn - pc) * c.inv_h, gys = (pc - ps) * c.inv_h;
-  const double lap_p = (gxe - gxw + gyn - gys) * c.inv_h;
-  const double pc2 = pc * pc;
-  const double cubic = pc2 * pc - pc;                      // phi*^3 - phi*
-  const double eph = c.e0 * phn_c + c.e1 * phm_c;          // SAV bracket weights
-  const double eps_ = c.e0 * psn_c + c.e1 * psm_c;
-
-  // f_lin, g_lin (App. B, Step 2), or their increment-form residuals
-  if constexpr (INC) {
-    // Increment form: the residuals f_lin - chi phi^n and g_lin - zeta psi^n,
-    // written so that nothing of size phi / dt or psi / dt is ever formed:
-    //   a0 phi^n + a1 phi^{n-1} - alpha phi^n = -a1 (phi^n - phi^{n-1}),
-    //   psi* - psi^n = (x0 - 1)(psi^n - psi^{n-1}), which carries lambda Delta.
-    auto lap_n = [&](int ii, int jj) {
-      const size_t r = (size_t)jj * nx;
-      const double u = a.phn[r + ii];
-      const double ue = a.phn[r + min(ii + 1, nx - 1)], uw = a.phn[r + max(ii - 1, 0)];
-      const double un = a.phn[(size_t)min(jj + 1, ny - 1) * nx + ii];
-      const double us = a.phn[(size_t)max(jj - 1, 0) * nx + ii];
-      return (ue + uw + un + us - 4.0 * u) * c.inv_h2;
-    };
-    const double ln_c = lap_n(i, j);
-    const double bih =
-        (lap_n(ie, j) + lap_n(iw, j) + lap_n(i, jn) + lap_n(i, js) - 4.0 * ln_c) * c.inv_h2;
-    out[M_F] = -c.a1 * (phn_c - phm_c) - c.C1b * phn_c - c.M_phi * c.theta_t * lap_p +
-               c.C2 * ln_c - c.C3 * bih;
-    const double dqc = psn_c - psm_c;
-    const double lap_dq = (a.psn[oe] - a.psm[oe] + a.psn[ow] - a.psm[ow] + a.psn[on] -
-                           a.psm[on] + a.psn[os] - a.psm[os] - 4.0 * dqc) * c.inv_h2;
-    out[M_G] = -c.a1 * dqc - c.lam * (c.x0 - 1.0) * lap_dq;
-  } else {
-    const double lap_q = (qe + qw + qn + qs - 4.0 * qc) * c.inv_h2;
-    out[M_F] = c.a0 * phn_c + c.a1 * phm_c - c.M_phi * c.theta_t * lap_p;
-    out[M_G] = c.a0 * psn_c + c.a1 * psm_c - c.lam * lap_q;
-  }
-  if (c.lag_d) {
-    // ||d^n||^2 of the previous step: delta psi = psi^n - (2 psi^{n-1} - psi^{n-2}),
-    // mobility at the face average of 2 phi^{n-1} - phi^{n-2}.
-    const double dc = psn_c - 2.0 * psm_c + a.psmm[oc];
-    const double fc = 2.0 * phm_c - a.phmm[oc];
-    if (i < nx - 1) {
-      const double de = a.psn[oe] - 2.0 * a.psm[oe] + a.psmm[oe];
-      const double fe = 2.0 * a.phm[oe] - a.phmm[oe];
-      const double g = de - dc;
-      sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (fc + fe), c.M0);
-    }
-    if (j < ny - 1) {
-      const double dn = a.psn[on] - 2.0 * a.psm[on] + a.psmm[on];
-      const double fn = 2.0 * a.phm[on] - a.phmm[on];
-      const double g = dn - dc;
-      sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (fc + fn), c.M0);
-    }
-  }
-
-  // S~ and H (surface energy, arc length)
-  {
-    const double St = pc * (pc2 - 1.0 - c.beta) * 0.5 * ieps;
-    const double Hf = k32 * (cubic * ieps - c.eps * lap_p);
-    out[M_S] = St;
-    out[M_H] = Hf;
-    const double vq = pc2 - 1.0 - c.beta;
-    sums[P1_RS] += vq * vq * 0.25 * ieps;
-    sums[P1_ES] += St * eph;
-    sums[P1_EH] += Hf * eph;
-    if constexpr (INC) {
-      sums[P1_XS] += St * phn_c;
-      sums[P1_XH] += Hf * phn_c;
-    }
-  }
-  // Q~ (bending), K~ and P~ (osmotic), L~ = div(M_psi(A phi*) grad P~)
-  double sp, cp;
-  sincospi(0.5 * pc, &sp, &cp);
-  const double din = qc - c.psi_in, dout = qc - c.psi_out;
-  const double fin = 0.5 * c.gamma_in * din * din + c.beta_in;
-  const double fout = 0.5 * c.gamma_out * dout * dout + c.beta_out;
-  const double Pc = ptilde(c, qc, sp);
-  {
-    const double grad2 = 0.5 * (gxe * gxe + gxw * gxw + gyn * gyn + gys * gys);
-    const double div_a = 0.5 * ((pc2 + pe * pe) * gxe - (pw * pw + pc2) * gxw +
-                                (pc2 + pn * pn) * gyn - (ps * ps + pc2) * gys) * c.inv_h;
-    const double Qt = 6.0 * (pc * grad2 - div_a) + cubic * (3.0 * pc2 - 1.0) * ieps * ieps;
-    const double Kt = 0.5 * half_pi * cp * (fin - fout);
-    out[M_Q] = Qt;
-    out[M_K] = Kt;
-    sums[P1_RW] += 6.0 * pc2 * grad2 + cubic * cubic * ieps * ieps;
-    sums[P1_RZ] += (1.0 + sp) * fin + (1.0 - sp) * fout;
-    sums[P1_EQ] += Qt * eph;
-    sums[P1_EK] += Kt * eph;
-    if constexpr (INC) {
-      sums[P1_XQ] += Qt * phn_c;
-      sums[P1_XK] += Kt * phn_c;
-    }
-  }
-  {
-    const double Pe = ptilde(c, qe, sinpi(0.5 * pe));
-    const double Pw = ptilde(c, qw, sinpi(0.5 * pw));
-    const double Pn = ptilde(c, qn, sinpi(0.5 * pn));
-    const double Ps = ptilde(c, qs, sinpi(0.5 * ps));
-    const double Me = mobility(0.5 * (pc + pe), c.M0), Mw = mobility(0.5 * (pw + pc), c.M0);
-    const double Mn = mobility(0.5 * (pc + pn), c.M0), Ms = mobility(0.5 * (ps + pc), c.M0);
-    out[M_L] = (Me * (Pe - Pc) - Mw * (Pc - Pw) + Mn * (Pn - Pc) - Ms * (Pc - Ps)) * c.inv_h2;
-    out[M_P] = Pc;
-    sums[P1_EP] += Pc * eps_;
-    if constexpr (INC) sums[P1_XP] += Pc * psn_c;
-    if (i < nx - 1 && !(Me > 0.0)) sums[P1_MOBNEG] += 1.0;
-    if (j < ny - 1 && !(Mn > 0.0)) sums[P1_MOBNEG] += 1.0;
-  }
-}
-
-// P1a: the stencil terms of a tile of cells, one cell per thread and
-// iteration; the eight fields leave row-major ([field][ny][nx], x fastest) in
-// coalesced writes. A workgroup covers tw = min(nx, 256) columns and
-// 256 / tw rows per iteration, for `iters` iterations down the grid.
+// P1a: the stencil terms of a band of rows. Each wave owns SW_OUT consecutive
+// output columns plus two halo columns on either side (64 lanes); walking down
+// the band, a lane keeps the rows above and below the current one in
+// registers and takes the values at the left and right neighbours from the
+// adjacent lanes, so every pointwise quantity (phi*, psi*, P~ and its sine) is
+// formed once per cell. Neighbours outside the grid are the ghost copies of
+// App. D (index clamping). The eight fields are the right-hand sides of
+// eqs. (AC_BDF2)-(Z_BDF2) at phi* = x0 phi^n + x1 phi^{n-1} (slot order of Mid)
+// and leave row-major ([field][ny][nx], x fastest).
 constexpr int STENCIL_THREADS = 256;
+constexpr int SW_WAVES = STENCIL_THREADS / 64;
+constexpr int SW_OUT = 60;                    // output columns per wave
+constexpr int SW_COLS = SW_WAVES * SW_OUT;    // output columns per workgroup
+constexpr int SW_BAND = 32;                   // rows per workgroup (ny if smaller)
+
+// Launch shape of P1a for an nx x ny grid: rows per workgroup and the number
+// of workgroups (one row of partial sums each).
+struct StencilShape {
+  int iters, blocks;
+};
+inline StencilShape stencil_shape(int nx, int ny) {
+  const int nseg = (nx + SW_COLS - 1) / SW_COLS;
+  const int iters = ny < SW_BAND ? ny : SW_BAND;
+  return {iters, nseg * (ny / iters)};
+}
 
 template <typename TM>
 __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restrict__ rm,
@@ -264,39 +146,181 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
   constexpr bool INC = increment_form<TM>();
   __shared__ double red[P1_NSUM * (STENCIL_THREADS / 64 + 1)];
   const int tid = threadIdx.x;
-  const int tw = min(nx, STENCIL_THREADS);
-  const int th = STENCIL_THREADS / tw;
-  const int nseg = nx / tw;
-  const int i = (blk % nseg) * tw + tid % tw;
-  const int j0 = (blk / nseg) * th * iters + tid / tw;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int nseg = (nx + SW_COLS - 1) / SW_COLS;
+  const int seg = blk % nseg, band = blk / nseg;
+  const int ci = seg * SW_COLS + wave * SW_OUT - 2 + lane;   // this lane's column
+  const int cl = min(max(ci, 0), nx - 1);                    // its ghost-clamped column
+  const bool out_lane = lane >= 2 && lane < 2 + SW_OUT && ci < nx;
+  const bool at_w = ci == 0, at_e = ci == nx - 1;
+  const int j0 = band * iters;
   const size_t FS = (size_t)nx * ny;
+  const double k32 = 0.75 * 1.4142135623730950488;   // 3 sqrt(2) / 4
+  const double half_pi = 1.5707963267948966192;
+  const double ieps = 1.0 / c.eps;
+  // neighbour values along x; at the boundary the ghost is the cell itself
+  auto west = [&](double v) {
+    const double u = __shfl_up(v, 1, 64);
+    return at_w ? v : u;
+  };
+  auto east = [&](double v) {
+    const double u = __shfl_down(v, 1, 64);
+    return at_e ? v : u;
+  };
+  auto at = [&](int r) { return (size_t)min(max(r, 0), ny - 1) * nx + cl; };
+
+  // Pointwise quantities of one row at this column.
+  struct Row {
+    double phn, phm, psn, psm;    // state
+    double p, q;                  // phi*, psi*
+    double sp, cp, P;             // sin, cos (pi phi* / 2), P~
+    double dq;                    // psi^n - psi^{n-1} (increment form)
+    double dl, fl;                // lagged delta psi and phi* of the previous step
+  };
+  auto load_row = [&](int r) {
+    Row w;
+    const size_t o = at(r);
+    w.phn = a.phn[o];
+    w.phm = a.phm[o];
+    w.psn = a.psn[o];
+    w.psm = a.psm[o];
+    w.p = c.x0 * w.phn + c.x1 * w.phm;
+    w.q = c.x0 * w.psn + c.x1 * w.psm;
+    sincospi(0.5 * w.p, &w.sp, &w.cp);
+    w.P = ptilde(c, w.q, w.sp);
+    w.dq = w.psn - w.psm;
+    if (c.lag_d) {
+      w.dl = w.psn - 2.0 * w.psm + a.psmm[o];
+      w.fl = 2.0 * w.phm - a.phmm[o];
+    } else {
+      w.dl = 0.0;
+      w.fl = 0.0;
+    }
+    return w;
+  };
+  // Delta_h phi^n of the row whose phi^n is u, with the rows above (un) and below (us).
+  auto lap_n = [&](double u, double un, double us) {
+    return (east(u) + west(u) + un + us - 4.0 * u) * c.inv_h2;
+  };
+
   double sums[P1_NSUM];
 #pragma unroll
   for (int q = 0; q < P1_NSUM; ++q) sums[q] = 0.0;
+
+  // window: rows j-1, j, j+1 (pointwise), phi^n of row j+2, Delta_h phi^n of rows j-1, j
+  Row rs = load_row(j0 - 1), rc = load_row(j0), rn = load_row(j0 + 1);
+  double Ls = 0.0, Lc = 0.0;
+  if constexpr (INC) {
+    const double u2 = a.phn[at(j0 - 2)];
+    Lc = lap_n(rc.phn, rn.phn, rs.phn);
+    Ls = (j0 == 0) ? Lc : lap_n(rs.phn, rc.phn, u2);
+  }
 #pragma unroll 1
-  for (int it = 0; it < iters; ++it) {
-    const int j = j0 + it * th;
+  for (int j = j0; j < j0 + iters; ++j) {
+    double Ln = 0.0;
+    if constexpr (INC) {
+      const double u2 = a.phn[at(j + 2)];
+      Ln = (j + 1 >= ny) ? Lc : lap_n(rn.phn, u2, rc.phn);
+    }
+    // neighbours along x of the current row
+    const double pe = east(rc.p), pw = west(rc.p);
+    const double qe = east(rc.q), qw = west(rc.q);
+    const double Pe = east(rc.P), Pw = west(rc.P);
+    const double de = east(rc.dl), fe = east(rc.fl);
+    double Le = 0.0, Lw = 0.0, dqe = 0.0, dqw = 0.0;
+    if constexpr (INC) {
+      Le = east(Lc);
+      Lw = west(Lc);
+      dqe = east(rc.dq);
+      dqw = west(rc.dq);
+    }
+    const double pc = rc.p, pn = rn.p, ps = rs.p;
+    const double gxe = (pe - pc) * c.inv_h, gxw = (pc - pw) * c.inv_h;
+    const double gyn = (pn - pc) * c.inv_h, gys = (pc - ps) * c.inv_h;
+    const double lap_p = (gxe - gxw + gyn - gys) * c.inv_h;
+    const double pc2 = pc * pc;
+    const double cubic = pc2 * pc - pc;
+    const double eph = c.e0 * rc.phn + c.e1 * rc.phm;
+    const double eps_ = c.e0 * rc.psn + c.e1 * rc.psm;
     double out[M_NFIELD];
-    stencil_cell<INC>(a, i, j, nx, ny, c, sums, out);
-    const size_t o = (size_t)j * nx + i;
+    if constexpr (INC) {
+      // Increment form: the residuals f_lin - chi phi^n and g_lin - zeta psi^n,
+      // written so that nothing of size phi / dt or psi / dt is ever formed:
+      //   a0 phi^n + a1 phi^{n-1} - alpha phi^n = -a1 (phi^n - phi^{n-1}),
+      //   psi* - psi^n = (x0 - 1)(psi^n - psi^{n-1}), which carries lambda Delta;
+      // Delta_h^2 phi^n is Delta_h applied to Delta_h phi^n, both with ghosts.
+      const double bih = (Le + Lw + Ln + Ls - 4.0 * Lc) * c.inv_h2;
+      out[M_F] = -c.a1 * (rc.phn - rc.phm) - c.C1b * rc.phn - c.M_phi * c.theta_t * lap_p +
+                 c.C2 * Lc - c.C3 * bih;
+      const double lap_dq = (dqe + dqw + rn.dq + rs.dq - 4.0 * rc.dq) * c.inv_h2;
+      out[M_G] = -c.a1 * rc.dq - c.lam * (c.x0 - 1.0) * lap_dq;
+    } else {
+      const double lap_q = (qe + qw + rn.q + rs.q - 4.0 * rc.q) * c.inv_h2;
+      out[M_F] = c.a0 * rc.phn + c.a1 * rc.phm - c.M_phi * c.theta_t * lap_p;
+      out[M_G] = c.a0 * rc.psn + c.a1 * rc.psm - c.lam * lap_q;
+    }
+    const double St = pc * (pc2 - 1.0 - c.beta) * 0.5 * ieps;
+    const double Hf = k32 * (cubic * ieps - c.eps * lap_p);
+    out[M_S] = St;
+    out[M_H] = Hf;
+    const double din = rc.q - c.psi_in, dout = rc.q - c.psi_out;
+    const double fin = 0.5 * c.gamma_in * din * din + c.beta_in;
+    const double fout = 0.5 * c.gamma_out * dout * dout + c.beta_out;
+    const double grad2 = 0.5 * (gxe * gxe + gxw * gxw + gyn * gyn + gys * gys);
+    const double div_a = 0.5 * ((pc2 + pe * pe) * gxe - (pw * pw + pc2) * gxw +
+                                (pc2 + pn * pn) * gyn - (ps * ps + pc2) * gys) * c.inv_h;
+    const double Qt = 6.0 * (pc * grad2 - div_a) + cubic * (3.0 * pc2 - 1.0) * ieps * ieps;
+    const double Kt = 0.5 * half_pi * rc.cp * (fin - fout);
+    out[M_Q] = Qt;
+    out[M_K] = Kt;
+    const double Pc = rc.P;
+    const double Me = mobility(0.5 * (pc + pe), c.M0), Mw = mobility(0.5 * (pw + pc), c.M0);
+    const double Mn = mobility(0.5 * (pc + pn), c.M0), Ms = mobility(0.5 * (ps + pc), c.M0);
+    out[M_L] = (Me * (Pe - Pc) - Mw * (Pc - Pw) + Mn * (rn.P - Pc) - Ms * (Pc - rs.P)) * c.inv_h2;
+    out[M_P] = Pc;
+    if (out_lane) {
+      const size_t o = (size_t)j * nx + ci;
 #pragma unroll
-    for (int f = 0; f < M_NFIELD; ++f) rm[f * FS + o] = (TM)out[f];
+      for (int f = 0; f < M_NFIELD; ++f) rm[f * FS + o] = (TM)out[f];
+      const double vq = pc2 - 1.0 - c.beta;
+      sums[P1_RS] += vq * vq * 0.25 * ieps;
+      sums[P1_ES] += St * eph;
+      sums[P1_EH] += Hf * eph;
+      sums[P1_RW] += 6.0 * pc2 * grad2 + cubic * cubic * ieps * ieps;
+      sums[P1_RZ] += (1.0 + rc.sp) * fin + (1.0 - rc.sp) * fout;
+      sums[P1_EQ] += Qt * eph;
+      sums[P1_EK] += Kt * eph;
+      sums[P1_EP] += Pc * eps_;
+      if constexpr (INC) {
+        sums[P1_XS] += St * rc.phn;
+        sums[P1_XH] += Hf * rc.phn;
+        sums[P1_XQ] += Qt * rc.phn;
+        sums[P1_XK] += Kt * rc.phn;
+        sums[P1_XP] += Pc * rc.psn;
+      }
+      if (ci < nx - 1 && !(Me > 0.0)) sums[P1_MOBNEG] += 1.0;
+      if (j < ny - 1 && !(Mn > 0.0)) sums[P1_MOBNEG] += 1.0;
+      if (c.lag_d) {
+        // ||d^n||^2 of the previous step over the east and north faces
+        if (ci < nx - 1) {
+          const double g = de - rc.dl;
+          sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (rc.fl + fe), c.M0);
+        }
+        if (j < ny - 1) {
+          const double g = rn.dl - rc.dl;
+          sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (rc.fl + rn.fl), c.M0);
+        }
+      }
+    }
+    // advance the window
+    rs = rc;
+    rc = rn;
+    if (j + 1 < j0 + iters) rn = load_row(j + 2);
+    Ls = Lc;
+    Lc = Ln;
   }
   block_sum<P1_NSUM, STENCIL_THREADS>(sums, red, tid);
   if (tid < P1_NSUM) part[(size_t)blk * P1_NSUM + tid] = red[tid];
-}
-
-// Launch shape of P1a for an nx x ny grid: iterations per workgroup and the
-// number of workgroups (one row of partial sums each).
-struct StencilShape {
-  int iters, blocks;
-};
-inline StencilShape stencil_shape(int nx, int ny) {
-  const int tw = nx < STENCIL_THREADS ? nx : STENCIL_THREADS;
-  const int th = STENCIL_THREADS / tw;
-  const int rows = ny / th;                 // iterations needed for the whole height
-  const int iters = rows < 16 ? rows : 16;
-  return {iters, (nx / tw) * (rows / iters)};
 }
 
 // Column-pair piece of one field over the rows of a workgroup, stored with one
@@ -428,7 +452,7 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
                                               gptr<const double> __restrict__ lamx,
                                               gptr<const double> __restrict__ lamy,
                                               gptr<double> __restrict__ part, int nx,
-                                              const StepConst& c, int s) {
+                                              const OpConst c, int s) {
   constexpr int NTHR = gram_threads(NY);
   constexpr int KPT = (NY + NTHR - 1) / NTHR;
   // FP64 up to 4096: the S~ spectrum waits in LDS, H, Q~, K~ in registers;
@@ -694,7 +718,7 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
                                                gptr<TM> __restrict__ out, int nx, int chi_base,
                                                int nchi, int zeta_base, int nzeta,
                                                gptr<double> __restrict__ colsum,
-                                               const StepConst& c, int lin) {
+                                               const OpConst c, int lin) {
   constexpr int NTHR = line_threads(NY);
   constexpr int KPT = (NY + NTHR - 1) / NTHR;
   __shared__ cpx<TM> line[NY];
@@ -955,8 +979,8 @@ template <typename TM, int NY>
 __global__ void __launch_bounds__(gram_threads(NY)) k_col_gram(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
-  col_gram_body<TM, NY>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.part2, m.nx, m.k,
-                        blk);
+  const OpConst o{m.k.C1, m.k.C2, m.k.C3, m.k.alpha, m.k.lam};
+  col_gram_body<TM, NY>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.part2, m.nx, o, blk);
 }
 
 __global__ void __launch_bounds__(SOLVE_THREADS) k_solve(BATCH_PARAMS) {
@@ -969,9 +993,10 @@ template <typename TM, int NY>
 __global__ void __launch_bounds__(line_threads(NY)) k_col_solve(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
+  const OpConst o{m.k.C1, m.k.C2, m.k.C3, m.k.alpha, m.k.lam};
   col_solve_body<TM, NY>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.coef,
                          static_cast<gptr<TM>>(m.outc), m.nx, m.chi_base, m.nchi, m.zeta_base,
-                         m.nzeta, m.colsum, m.k, blk);
+                         m.nzeta, m.colsum, o, blk);
 }
 
 template <typename TM, int NX>
