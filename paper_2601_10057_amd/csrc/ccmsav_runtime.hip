@@ -77,7 +77,7 @@ template <typename TM> struct Launch {
   }
   template <int N>
   static void row_idct(hipStream_t st, int grid, const Batch& b) {
-    hipLaunchKernelGGL((k_row_idct<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, b.m, b.idx,
+    hipLaunchKernelGGL((k_row_idct<TM, N>), dim3(grid), dim3(one_line_threads<TM>(N)), 0, st, b.m, b.idx,
                        b.per);
   }
   using RD = void (*)(hipStream_t, int, const double*, TM*, int, int);

@@ -31,6 +31,13 @@ namespace ccm {
 constexpr int clamp_threads(int t) { return t < 64 ? 64 : (t > 1024 ? 1024 : t); }
 // Threads of a line kernel: four elements per thread.
 constexpr int line_threads(int n) { return clamp_threads(n / 4); }
+// Threads of the row inverse: one butterfly of the FFT stages per thread, so
+// that no thread idles in the transforms and a CU holds several workgroups
+// (measured faster than line_threads for the row inverse, slower for the
+// column solve, whose longer combine phase wants more threads).
+template <typename TM> constexpr int one_line_threads(int n) {
+  return clamp_threads(n / (sizeof(TM) == 4 ? 16 : 8));
+}
 // The Gram kernel keeps four spectra per thread: eight bins per thread give
 // each wave up to 256 registers at one workgroup per CU.
 constexpr int gram_threads(int n) { return clamp_threads(n / 8); }
@@ -840,7 +847,7 @@ __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
                                               gptr<const double> __restrict__ phi_base,
                                               gptr<const double> __restrict__ psi_base,
                                               gptr<const double> __restrict__ colsum, int j) {
-  constexpr int NTHR = line_threads(NX);
+  constexpr int NTHR = one_line_threads<TM>(NX);
   constexpr int CPT = (NX + NTHR - 1) / NTHR;
   __shared__ cpx<TM> line[NX];
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
@@ -1000,7 +1007,7 @@ __global__ void __launch_bounds__(line_threads(NY)) k_col_solve(BATCH_PARAMS) {
 }
 
 template <typename TM, int NX>
-__global__ void __launch_bounds__(line_threads(NX)) k_row_idct(BATCH_PARAMS) {
+__global__ void __launch_bounds__(one_line_threads<TM>(NX)) k_row_idct(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
   row_idct_body<TM, NX>(static_cast<gptr<const TM>>(m.outc), m.phi_new, m.psi_new, m.ny,
