@@ -143,8 +143,9 @@ def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, g
     wall = time.perf_counter() - t0
     ctx.sync()                       # raises on any device-side error of the run
     prof = ctx.profile_steps(profile_steps) if profile_steps > 0 else {}
+    tuning = ctx.tuning()
     mass = [ctx.mass(i)[0] for i in range(nm)]
-    out = dict(wall=wall, ev_ms=ev0.elapsed_time(ev1), prof=prof,
+    out = dict(wall=wall, ev_ms=ev0.elapsed_time(ev1), prof=prof, tuning=tuning,
                drift=max(abs(a - b) / abs(b) for a, b in zip(mass, mass0)),
                energy=[ctx.energy(member=i) for i in range(nm)],
                fields=[ctx.fields(i) for i in range(nm)],
@@ -261,6 +262,7 @@ def main():
               "eps_cells": sorted({m.meta.get("eps_cells", 4.0) for m in members})}
     if len(members) == 1:
         config.update(nx=m0.params["nx"], ny=m0.params["ny"])
+    config["autotune"] = [dict(grid=[t["nx"], t["ny"]], **t["variants"]) for t in run["tuning"]]
     out = {
         "metric": METRIC,
         "value": value,

@@ -177,6 +177,21 @@ int ccmsav_get_savs(ccmsav_ctx* c, double out8[8]);
 int64_t ccmsav_level(const ccmsav_ctx* c);
 
 /*
+ * Launch variants chosen by the library's autotuner. At the first step of a
+ * context every variant of three kernels is run and timed with HIP events
+ * (all variants give bit-identical results) and the fastest is kept: the row
+ * DCT-II (variant 1 halves the band of rows per workgroup and its LDS), the
+ * column solve and the row DCT-III (variant 0: four elements per thread,
+ * variant 1: one FFT butterfly per thread). For each grid shape s of the
+ * context (s < max_shapes) info[5 s .. 5 s + 4] = {nx, ny, row DCT variant,
+ * column solve variant, row inverse variant} and, if ms is not NULL,
+ * ms[6 s .. 6 s + 5] = the best time in milliseconds of variants 0 and 1 of
+ * each of the three kernels. Returns the number of grid shapes, 0 before the
+ * first step (or for the DCT-as-GEMM precision), EINVAL for bad arguments.
+ */
+int32_t ccmsav_tuning(const ccmsav_ctx* c, int32_t max_shapes, int32_t* info, double* ms);
+
+/*
  * Take nsteps >= 1 steps like ccmsav_step, with HIP events recorded on the
  * context's stream around each of the six kernels of a step, then wait and
  * write the mean duration in milliseconds of each kernel launch to

@@ -32,7 +32,7 @@ EXPORTED = (
     "ccmsav_sync", "ccmsav_elliptic_solve", "ccmsav_destroy", "ccmsav_strerror",
     "ccmsav_profile_steps", "ccmsav_workspace_bytes_batch", "ccmsav_init_batch",
     "ccmsav_members", "ccmsav_energy_m", "ccmsav_mass_m", "ccmsav_get_fields_m",
-    "ccmsav_get_savs_m",
+    "ccmsav_get_savs_m", "ccmsav_tuning",
 )
 PHASES = ("stencil", "row_dct", "col_gram", "solve5", "col_solve", "row_idct")
 
@@ -110,6 +110,8 @@ def load() -> ctypes.CDLL:
     lib.ccmsav_mass_m.argtypes = [vp, ctypes.c_int32, dp, dp]
     lib.ccmsav_get_fields_m.argtypes = [vp, ctypes.c_int32, vp, vp]
     lib.ccmsav_get_savs_m.argtypes = [vp, ctypes.c_int32, dp]
+    lib.ccmsav_tuning.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), dp]
+    lib.ccmsav_tuning.restype = ctypes.c_int32
     lib.ccmsav_strerror.argtypes = [ctypes.c_int]
     lib.ccmsav_strerror.restype = ctypes.c_char_p
     for fn in ("ccmsav_init", "ccmsav_step", "ccmsav_energy", "ccmsav_mass",
@@ -227,6 +229,23 @@ class Context:
 
     def sync(self):
         _check(load().ccmsav_sync(self._h), "ccmsav_sync")
+
+    def tuning(self):
+        """Autotuner choices per grid shape: [{nx, ny, variants, ms}], empty before step 1."""
+        lib = load()
+        n = int(lib.ccmsav_tuning(self._h, 0, None, None))
+        if n < 0:
+            _check(n, "ccmsav_tuning")
+        if n == 0:
+            return []
+        info = (ctypes.c_int32 * (5 * n))()
+        ms = (ctypes.c_double * (6 * n))()
+        lib.ccmsav_tuning(self._h, n, info, ms)
+        names = ("row_dct", "col_solve", "row_idct")
+        return [dict(nx=info[5 * s], ny=info[5 * s + 1],
+                     variants={names[t]: info[5 * s + 2 + t] for t in range(3)},
+                     ms={names[t]: [ms[6 * s + 2 * t], ms[6 * s + 2 * t + 1]] for t in range(3)})
+                for s in range(n)]
 
     @property
     def level(self) -> int:

@@ -57,28 +57,34 @@ int64_t level_of_table(int t) {
 
 // ---- launch tables over the line length --------------------------------------
 
+// Autotuned kernels: row DCT (band height), column solve and row inverse
+// (threads per line); kNumVariants launch variants each.
+constexpr int kNumTuned = 3;
+constexpr int kNumVariants = 2;
+enum Tuned { TUNE_ROW_DCT = 0, TUNE_COL_SOLVE = 1, TUNE_ROW_IDCT = 2 };
+
 template <typename TM> struct Launch {
   using K = void (*)(hipStream_t, int, const Batch&);
 
-  template <int N>
+  template <int N, int V>
   static void row_dct(hipStream_t st, int grid, const Batch& b) {
-    hipLaunchKernelGGL((k_row_dct8<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, b.m, b.idx,
-                       b.per);
+    hipLaunchKernelGGL((k_row_dct8<TM, N, V>), dim3(grid), dim3(line_threads(N)), 0, st, b.m,
+                       b.idx, b.per);
   }
   template <int N>
   static void gram(hipStream_t st, int grid, const Batch& b) {
     hipLaunchKernelGGL((k_col_gram<TM, N>), dim3(grid), dim3(gram_threads(N)), 0, st, b.m, b.idx,
                        b.per);
   }
-  template <int N>
+  template <int N, int V>
   static void col_solve(hipStream_t st, int grid, const Batch& b) {
-    hipLaunchKernelGGL((k_col_solve<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, b.m, b.idx,
-                       b.per);
+    hipLaunchKernelGGL((k_col_solve<TM, N, V>), dim3(grid), dim3(line_threads_v<TM>(N, V)), 0, st,
+                       b.m, b.idx, b.per);
   }
-  template <int N>
+  template <int N, int V>
   static void row_idct(hipStream_t st, int grid, const Batch& b) {
-    hipLaunchKernelGGL((k_row_idct<TM, N>), dim3(grid), dim3(one_line_threads<TM>(N)), 0, st, b.m, b.idx,
-                       b.per);
+    hipLaunchKernelGGL((k_row_idct<TM, N, V>), dim3(grid), dim3(line_threads_v<TM>(N, V)), 0, st,
+                       b.m, b.idx, b.per);
   }
   using RD = void (*)(hipStream_t, int, const double*, TM*, int, int);
   template <int N>
@@ -88,14 +94,22 @@ template <typename TM> struct Launch {
   }
 
   template <int... L> struct Tables {
-    static constexpr K t_row_dct[] = {&row_dct<(1 << L)>...};
+    static constexpr K t_row_dct[kNumVariants][sizeof...(L)] = {{&row_dct<(1 << L), 0>...},
+                                                                {&row_dct<(1 << L), 1>...}};
     static constexpr K t_gram[] = {&gram<(1 << L)>...};
-    static constexpr K t_col_solve[] = {&col_solve<(1 << L)>...};
-    static constexpr K t_row_idct[] = {&row_idct<(1 << L)>...};
+    static constexpr K t_col_solve[kNumVariants][sizeof...(L)] = {
+        {&col_solve<(1 << L), 0>...}, {&col_solve<(1 << L), 1>...}};
+    static constexpr K t_row_idct[kNumVariants][sizeof...(L)] = {
+        {&row_idct<(1 << L), 0>...}, {&row_idct<(1 << L), 1>...}};
     static constexpr RD t_rd[] = {&rd<(1 << L)>...};
   };
   using T = Tables<4, 5, 6, 7, 8, 9, 10, 11, 12, 13>;
 };
+
+// Rows per workgroup of the row DCT for variant v (host side of p1_rows_v).
+int row_dct_rows(int precision, int nx, int v) {
+  return precision == CCMSAV_FP64 ? p1_rows_v<double>(nx, v) : p1_rows_v<float>(nx, v);
+}
 
 size_t mid_elem(int precision) { return precision == CCMSAV_FP64 ? 8 : 4; }
 bool is_gemm(int precision) { return precision == CCMSAV_MIXED_GEMM_BF16X3; }
@@ -328,6 +342,8 @@ struct SizeClass {
   int count;
   const int* d_idx;
   StencilShape sh;
+  int var[kNumTuned];            // chosen launch variant of each tuned kernel
+  float tune_ms[kNumTuned][kNumVariants];   // best measured time of each variant
 };
 
 }  // namespace
@@ -344,6 +360,7 @@ struct ccmsav_ctx {
   MemberArgs* d_args = nullptr;      // kNumTables tables of mem.size() entries
   std::vector<MemberArgs> h_args;
   int64_t level = 0;
+  bool tuned = false;      // launch variants chosen (at the first step)
   // graph replay of three steady-state steps
   hipStream_t gstream = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -412,8 +429,36 @@ MemberArgs member_args(const Member& m, int precision, int table) {
   return a;
 }
 
+// Autotuner: at the first step every variant of each tuned kernel is run
+// (they compute bit-identical results from the same inputs, so the step's
+// outcome does not depend on the order) and timed with HIP events on the
+// context's stream; the fastest is kept for all later steps.
+constexpr int kTuneReps = 3;
+struct Tuner {
+  bool on = false;
+  std::vector<hipEvent_t> ev;   // [class][kernel][variant][rep][2]
+  size_t at(size_t k, int t, int v, int r, int e) const {
+    return (((k * kNumTuned + t) * kNumVariants + v) * kTuneReps + r) * 2 + e;
+  }
+};
+
+template <typename TM, typename F>
+void run_tuned(ccmsav_ctx* c, Tuner& tu, size_t ki, int t, hipStream_t st, F launch) {
+  const SizeClass& k = c->cls[ki];
+  if (!tu.on) {
+    launch(k.var[t]);
+    return;
+  }
+  for (int v = 0; v < kNumVariants; ++v)
+    for (int r = 0; r < kTuneReps; ++r) {
+      (void)hipEventRecord(tu.ev[tu.at(ki, t, v, r, 0)], st);
+      launch(v);
+      (void)hipEventRecord(tu.ev[tu.at(ki, t, v, r, 1)], st);
+    }
+}
+
 template <typename TM>
-void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe) {
+void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe, Tuner& tu) {
   const MemberArgs* tab = c->d_args + (size_t)table * c->mem.size();
   using LT = typename Launch<TM>::T;
   pe.mark(0, st);
@@ -424,9 +469,12 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe)
   }
   pe.mark(1, st);
   pe.mark(2, st);
-  for (const SizeClass& k : c->cls) {
-    const int per = (1 << k.ly) / p1_rows<TM>(1 << k.lx);
-    LT::t_row_dct[k.lx - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
+  for (size_t ki = 0; ki < c->cls.size(); ++ki) {
+    const SizeClass& k = c->cls[ki];
+    run_tuned<TM>(c, tu, ki, TUNE_ROW_DCT, st, [&](int v) {
+      const int per = (1 << k.ly) / row_dct_rows(c->precision, 1 << k.lx, v);
+      LT::t_row_dct[v][k.lx - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
+    });
   }
   pe.mark(3, st);
   pe.mark(4, st);
@@ -440,15 +488,21 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe)
     hipLaunchKernelGGL(k_solve, dim3(k.count), dim3(SOLVE_THREADS), 0, st, tab, k.d_idx, 1);
   pe.mark(7, st);
   pe.mark(8, st);
-  for (const SizeClass& k : c->cls) {
-    const int per = 1 << k.lx;     // two groups (chi, zeta) per strip of two columns
-    LT::t_col_solve[k.ly - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
+  for (size_t ki = 0; ki < c->cls.size(); ++ki) {
+    const SizeClass& k = c->cls[ki];
+    run_tuned<TM>(c, tu, ki, TUNE_COL_SOLVE, st, [&](int v) {
+      const int per = 1 << k.lx;     // two groups (chi, zeta) per strip of two columns
+      LT::t_col_solve[v][k.ly - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
+    });
   }
   pe.mark(9, st);
   pe.mark(10, st);
-  for (const SizeClass& k : c->cls) {
-    const int per = 1 << k.ly;
-    LT::t_row_idct[k.lx - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
+  for (size_t ki = 0; ki < c->cls.size(); ++ki) {
+    const SizeClass& k = c->cls[ki];
+    run_tuned<TM>(c, tu, ki, TUNE_ROW_IDCT, st, [&](int v) {
+      const int per = 1 << k.ly;
+      LT::t_row_idct[v][k.lx - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
+    });
   }
   pe.mark(11, st);
 }
@@ -541,10 +595,41 @@ int enqueue_step_level(ccmsav_ctx* c, int64_t level, hipStream_t st,
                        PhaseEvents pe = PhaseEvents{nullptr}) {
   if (is_gemm(c->precision)) return enqueue_step_gemm(c, level, st, pe);
   const int t = table_of_level(level);
+  Tuner tu;
+  if (!c->tuned) {
+    tu.on = true;
+    tu.ev.resize(c->cls.size() * kNumTuned * kNumVariants * kTuneReps * 2, nullptr);
+    for (hipEvent_t& e : tu.ev)
+      if (hipEventCreate(&e) != hipSuccess) return CCMSAV_EHIP;
+  }
   if (c->precision == CCMSAV_MIXED)
-    enqueue_step_kind<float>(c, t, st, pe);
+    enqueue_step_kind<float>(c, t, st, pe, tu);
   else
-    enqueue_step_kind<double>(c, t, st, pe);
+    enqueue_step_kind<double>(c, t, st, pe, tu);
+  if (tu.on) {
+    int rc = hipStreamSynchronize(st) == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
+    for (size_t ki = 0; ki < c->cls.size() && rc == CCMSAV_OK; ++ki)
+      for (int tk = 0; tk < kNumTuned; ++tk) {
+        int best = 0;
+        for (int v = 0; v < kNumVariants; ++v) {
+          float mn = 1e30f;
+          for (int r = 0; r < kTuneReps; ++r) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, tu.ev[tu.at(ki, tk, v, r, 0)],
+                                    tu.ev[tu.at(ki, tk, v, r, 1)]) != hipSuccess)
+              rc = CCMSAV_EHIP;
+            mn = std::min(mn, ms);
+          }
+          c->cls[ki].tune_ms[tk][v] = mn;
+          if (mn < c->cls[ki].tune_ms[tk][best]) best = v;
+        }
+        c->cls[ki].var[tk] = best;
+      }
+    for (hipEvent_t e : tu.ev)
+      if (e) (void)hipEventDestroy(e);
+    if (rc != CCMSAV_OK) return rc;
+    c->tuned = true;
+  }
   return CCMSAV_OK;
 }
 
@@ -805,7 +890,7 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
     bool seen = false;
     for (const SizeClass& k : c->cls) seen = seen || (k.lx == c->mem[mi].lx && k.ly == c->mem[mi].ly);
     if (seen) continue;
-    SizeClass k{c->mem[mi].lx, c->mem[mi].ly, 0, nullptr, c->mem[mi].sh};
+    SizeClass k{c->mem[mi].lx, c->mem[mi].ly, 0, nullptr, c->mem[mi].sh, {0, 0, 1}, {}};
     const int start = (int)order.size();
     for (int32_t mj = mi; mj < nmemb; ++mj)
       if (c->mem[mj].lx == k.lx && c->mem[mj].ly == k.ly) order.push_back(mj);
@@ -998,6 +1083,23 @@ int ccmsav_get_savs(ccmsav_ctx* c, double out8[8]) { return ccmsav_get_savs_m(c,
 
 int64_t ccmsav_level(const ccmsav_ctx* c) { return c ? c->level : -1; }
 
+int32_t ccmsav_tuning(const ccmsav_ctx* c, int32_t max_shapes, int32_t* info, double* ms) {
+  if (!c || max_shapes < 0 || (max_shapes > 0 && !info)) return CCMSAV_EINVAL;
+  if (!c->tuned) return 0;
+  const int32_t n = std::min<int32_t>(max_shapes, (int32_t)c->cls.size());
+  for (int32_t s = 0; s < n; ++s) {
+    const SizeClass& k = c->cls[s];
+    info[5 * s + 0] = 1 << k.lx;
+    info[5 * s + 1] = 1 << k.ly;
+    for (int t = 0; t < kNumTuned; ++t) info[5 * s + 2 + t] = k.var[t];
+    if (ms)
+      for (int t = 0; t < kNumTuned; ++t)
+        for (int v = 0; v < kNumVariants; ++v)
+          ms[6 * s + t * kNumVariants + v] = k.tune_ms[t][v];
+  }
+  return (int32_t)c->cls.size();
+}
+
 int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, double* out_zeta) {
   if (!c || !rhs || c->mem.size() != 1) return CCMSAV_EINVAL;
   const Member& m = c->mem[0];
@@ -1016,8 +1118,10 @@ int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, dou
     using TM = decltype(tm);
     using LT = typename Launch<TM>::T;
     LT::t_rd[m.lx - kMinLog](c->stream, m.p.ny, rhs, static_cast<TM*>(m.mid), M_F, m.p.ny);
-    LT::t_col_solve[m.ly - kMinLog](c->stream, m.p.nx, Batch{d, k.d_idx, m.p.nx});
-    LT::t_row_idct[m.lx - kMinLog](c->stream, m.p.ny, Batch{d, k.d_idx, m.p.ny});
+    LT::t_col_solve[k.var[TUNE_COL_SOLVE]][m.ly - kMinLog](c->stream, m.p.nx,
+                                                           Batch{d, k.d_idx, m.p.nx});
+    LT::t_row_idct[k.var[TUNE_ROW_IDCT]][m.lx - kMinLog](c->stream, m.p.ny,
+                                                         Batch{d, k.d_idx, m.p.ny});
   };
   if (c->precision != CCMSAV_FP64)
     run(0.0f);

@@ -31,12 +31,14 @@ namespace ccm {
 constexpr int clamp_threads(int t) { return t < 64 ? 64 : (t > 1024 ? 1024 : t); }
 // Threads of a line kernel: four elements per thread.
 constexpr int line_threads(int n) { return clamp_threads(n / 4); }
-// Threads of the row inverse: one butterfly of the FFT stages per thread, so
-// that no thread idles in the transforms and a CU holds several workgroups
-// (measured faster than line_threads for the row inverse, slower for the
-// column solve, whose longer combine phase wants more threads).
+// Threads of a one-line kernel with one butterfly of the FFT stages per
+// thread: no thread idles in the transforms and a CU holds several
+// workgroups, at the price of more work per thread outside them.
 template <typename TM> constexpr int one_line_threads(int n) {
   return clamp_threads(n / (sizeof(TM) == 4 ? 16 : 8));
+}
+template <typename TM> constexpr int line_threads_v(int n, int v) {
+  return v == 0 ? line_threads(n) : one_line_threads<TM>(n);
 }
 // The Gram kernel keeps four spectra per thread: eight bins per thread give
 // each wave up to 256 registers at one workgroup per CU.
@@ -58,6 +60,19 @@ template <typename TM> constexpr int p1_rows(int n) {
 // Field pairs transformed together per round of the row pass (4 / pairs rounds).
 template <typename TM> constexpr int p1_pairs(int n) {
   const int per = lds_line_budget<TM>(n) / p1_rows<TM>(n);
+  return per >= 4 ? 4 : (per >= 2 ? 2 : 1);
+}
+// Launch variants the autotuner chooses between. Row DCT variant v halves the
+// band of rows and the LDS lines v times (shorter write pieces, more
+// workgroups per CU); line-kernel variant 0 has four elements per thread,
+// variant 1 one FFT butterfly per thread.
+template <typename TM> constexpr int p1_rows_v(int n, int v) {
+  return (p1_rows<TM>(n) >> v) > 0 ? (p1_rows<TM>(n) >> v) : 1;
+}
+template <typename TM> constexpr int p1_pairs_v(int n, int v) {
+  const int lines0 = p1_rows<TM>(n) * p1_pairs<TM>(n);
+  const int lines = (lines0 >> v) > p1_rows_v<TM>(n, v) ? (lines0 >> v) : p1_rows_v<TM>(n, v);
+  const int per = lines / p1_rows_v<TM>(n, v);
   return per >= 4 ? 4 : (per >= 2 ? 2 : 1);
 }
 
@@ -101,6 +116,19 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red, int tid)
 // formed in FP64, so FP32 rounding scales with the step's change rather than
 // with the fields, and the mean of the psi increment is carried in FP64.
 template <typename TM> constexpr bool increment_form() { return sizeof(TM) == 4; }
+
+// Sum of buf[0..N) (N a power of two) by pairwise halving: the order of the
+// additions does not depend on the number of threads, so every launch variant
+// gives the same bits. Overwrites buf; starts and ends with a barrier.
+template <int N> __device__ __forceinline__ double tree_sum(double* buf, int tid, int nthr) {
+#pragma unroll 1
+  for (int half = N / 2; half >= 1; half >>= 1) {
+    __syncthreads();
+    for (int i = tid; i < half; i += nthr) buf[i] += buf[i + half];
+  }
+  __syncthreads();
+  return buf[0];
+}
 
 __device__ __forceinline__ double mobility(double phi, double M0) {
   const double t = phi * phi - 1.0;
@@ -357,16 +385,16 @@ __device__ __forceinline__ void store_piece(gptr<TM> dst, const RowPiece<TM, ROW
 
 // P1b: orthonormal DCT-II along x of the eight row-major fields, for a band
 // of ROWS rows, into the strip-major intermediates.
-template <typename TM, int NX>
+template <typename TM, int NX, int V>
 __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
                                               gptr<TM> __restrict__ mid,
                                               int ny, int blk) {
   constexpr int NTHR = line_threads(NX);
-  constexpr int ROWS = p1_rows<TM>(NX);
+  constexpr int ROWS = p1_rows_v<TM>(NX, V);
   // Each round loads NP field pairs of the ROWS rows into LDS lines (row r,
   // pair l at (r NP + l) NX, two real fields per complex line) and transforms
   // them with one batched FFT; 4 / NP rounds cover the pairs.
-  constexpr int NP = p1_pairs<TM>(NX);
+  constexpr int NP = p1_pairs_v<TM>(NX, V);
   __shared__ cpx<TM> line[ROWS * NP * NX];
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   const int tid = threadIdx.x;
@@ -717,7 +745,7 @@ __device__ __forceinline__ void solve_body(gptr<const double> __restrict__ p1, i
 // ---------------------------------------------------------------------------
 // P3: spectral combination, divide by the operator spectrum, DCT-III along y.
 // ---------------------------------------------------------------------------
-template <typename TM, int NY>
+template <typename TM, int NY, int NTHR>
 __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
                                                gptr<const double> __restrict__ lamx,
                                                gptr<const double> __restrict__ lamy,
@@ -726,11 +754,9 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
                                                int nchi, int zeta_base, int nzeta,
                                                gptr<double> __restrict__ colsum,
                                                const OpConst c, int lin) {
-  constexpr int NTHR = line_threads(NY);
   constexpr int KPT = (NY + NTHR - 1) / NTHR;
   __shared__ cpx<TM> line[NY];
   __shared__ cpx<double> rtab[Roots<TM, NY>::SIZE];
-  __shared__ double red[2 * (NTHR / 64 + 1)];
   const int tid = threadIdx.x;
   const int nstrip = nx / 2;
   const int s = lin % nstrip;
@@ -824,11 +850,14 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
     // rounding noise instead of zero. Hand the row-inverse pass FP64 targets
     // for the row sums that add up to zero, so that the increment it writes
     // has zero sum in FP64 arithmetic.
-    double v[1] = {0.0};
+    double* buf = reinterpret_cast<double*>(line);   // the line is no longer read
+    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < KPT; ++q) v[0] += (double)y0[q];
-    block_sum<1, NTHR>(v, red, tid);
-    const double mean = red[0] / NY;
+    for (int q = 0; q < KPT; ++q) {
+      const int i = tid + q * NTHR;
+      if (i < NY) buf[i] = (double)y0[q];
+    }
+    const double mean = tree_sum<NY>(buf, tid, NTHR) / NY;
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
       const int i = tid + q * NTHR;
@@ -840,18 +869,16 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
 // ---------------------------------------------------------------------------
 // P4: DCT-III along x of the two solved fields -> phi^{n+1}, psi^{n+1}.
 // ---------------------------------------------------------------------------
-template <typename TM, int NX>
+template <typename TM, int NX, int NTHR>
 __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
                                               gptr<double> __restrict__ phi_new,
                                               gptr<double> __restrict__ psi_new, int ny,
                                               gptr<const double> __restrict__ phi_base,
                                               gptr<const double> __restrict__ psi_base,
                                               gptr<const double> __restrict__ colsum, int j) {
-  constexpr int NTHR = one_line_threads<TM>(NX);
   constexpr int CPT = (NX + NTHR - 1) / NTHR;
   __shared__ cpx<TM> line[NX];
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
-  __shared__ double red[2 * (NTHR / 64 + 1)];
   const int tid = threadIdx.x;
   const size_t FS = (size_t)NX * ny;
   Roots<TM, NX> rt;
@@ -884,18 +911,20 @@ __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
   // shifted by a constant so that its FP64 sum equals sqrt(NX) colsum[j]
   // (orthonormal DCT-III: the row sum is sqrt(NX) times the k = 0 input).
   cpx<TM> Y[CPT];
-  double v[1] = {0.0};
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int i = tid + q * NTHR;
     Y[q] = {(TM)0, (TM)0};
-    if (i < NX) {
-      Y[q] = line[lds_pos(fft_pos<TM, NX>(makhoul_slot<NX>(i)))];
-      v[0] -= (double)Y[q].im;
-    }
+    if (i < NX) Y[q] = line[lds_pos(fft_pos<TM, NX>(makhoul_slot<NX>(i)))];
   }
-  block_sum<1, NTHR>(v, red, tid);
-  const double shift = (sqrt((double)NX) * colsum[j] - red[0]) / NX;
+  double* buf = reinterpret_cast<double*>(line);     // the line is no longer read
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < CPT; ++q) {
+    const int i = tid + q * NTHR;
+    if (i < NX) buf[i] = -(double)Y[q].im;
+  }
+  const double shift = (sqrt((double)NX) * colsum[j] - tree_sum<NX>(buf, tid, NTHR)) / NX;
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int i = tid + q * NTHR;
@@ -974,11 +1003,11 @@ __global__ void __launch_bounds__(STENCIL_THREADS) k_stencil(BATCH_PARAMS) {
   stencil_body<TM>(a, static_cast<gptr<TM>>(m.rm), m.part1, m.nx, m.ny, m.iters, m.k, blk);
 }
 
-template <typename TM, int NX>
+template <typename TM, int NX, int V>
 __global__ void __launch_bounds__(line_threads(NX)) k_row_dct8(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
-  row_dct8_body<TM, NX>(static_cast<gptr<const TM>>(m.rm), static_cast<gptr<TM>>(m.mid), m.ny,
+  row_dct8_body<TM, NX, V>(static_cast<gptr<const TM>>(m.rm), static_cast<gptr<TM>>(m.mid), m.ny,
                         blk);
 }
 
@@ -996,21 +1025,21 @@ __global__ void __launch_bounds__(SOLVE_THREADS) k_solve(BATCH_PARAMS) {
   solve_body(m.part1, m.p1_blocks, m.part2, m.p2_rows, m.ds, m.k);
 }
 
-template <typename TM, int NY>
-__global__ void __launch_bounds__(line_threads(NY)) k_col_solve(BATCH_PARAMS) {
+template <typename TM, int NY, int V>
+__global__ void __launch_bounds__(line_threads_v<TM>(NY, V)) k_col_solve(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
   const OpConst o{m.k.C1, m.k.C2, m.k.C3, m.k.alpha, m.k.lam};
-  col_solve_body<TM, NY>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.coef,
+  col_solve_body<TM, NY, line_threads_v<TM>(NY, V)>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.coef,
                          static_cast<gptr<TM>>(m.outc), m.nx, m.chi_base, m.nchi, m.zeta_base,
                          m.nzeta, m.colsum, o, blk);
 }
 
-template <typename TM, int NX>
-__global__ void __launch_bounds__(one_line_threads<TM>(NX)) k_row_idct(BATCH_PARAMS) {
+template <typename TM, int NX, int V>
+__global__ void __launch_bounds__(line_threads_v<TM>(NX, V)) k_row_idct(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
-  row_idct_body<TM, NX>(static_cast<gptr<const TM>>(m.outc), m.phi_new, m.psi_new, m.ny,
+  row_idct_body<TM, NX, line_threads_v<TM>(NX, V)>(static_cast<gptr<const TM>>(m.outc), m.phi_new, m.psi_new, m.ny,
                         m.phi_base, m.psi_base, m.colsum, blk);
 }
 

@@ -179,3 +179,18 @@ def test_ensemble_workload_mixed_against_fp64():
         if k == checkpoints[0]:
             assert np.all(env <= 1e-7), k
             assert np.all(err <= 1e-6), (k, np.flatnonzero(err > 1e-6).tolist())
+
+
+def test_autotuner_reports_its_choices():
+    ms = small_members()[:2]
+    with C.Context.ensemble([m.params for m in ms], [m.phi0 for m in ms],
+                            [m.psi0 for m in ms], "mixed") as ens:
+        assert ens.tuning() == []
+        ens.step(1)
+        t = ens.tuning()
+        assert sorted((x["nx"], x["ny"]) for x in t) == [(32, 32), (64, 64)]
+        for x in t:
+            assert set(x["variants"].values()) <= {0, 1}
+            for name, (t0, t1) in x["ms"].items():
+                assert t0 > 0 and t1 > 0
+                assert x["variants"][name] == (0 if t0 <= t1 else 1)
