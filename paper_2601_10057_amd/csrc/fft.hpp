@@ -17,6 +17,14 @@ namespace ccm {
 
 template <typename T> struct cpx { T re, im; };
 
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS operations
+// and synchronises the workgroup, while global loads and stores stay in flight
+// (__syncthreads() would first wait for all of them). The kernels never pass
+// data between the threads of a workgroup through global memory.
+__device__ __forceinline__ void lds_sync() {
+  __asm__ volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 template <typename T>
 __device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
   return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
@@ -161,17 +169,16 @@ __device__ __forceinline__ void dif_stage(cpx<T>* buf, const Roots<T, N>& rt, in
 #pragma unroll
     for (int q = 0; q < R; ++q) x[lds_pos(e0 + q * S)] = v[q];
   }
-  __syncthreads();
+  lds_sync();
 }
 
-template <typename T, int N, int NL, int NTHR, int L, bool FIRST>
+template <typename T, int N, int NL, int NTHR, int L, bool FIRST, int RADIX>
 struct DifRunner {
   static __device__ __forceinline__ void run(cpx<T>* buf, const Roots<T, N>& rt, int tid) {
     if constexpr (L > 1) {
-      constexpr int RADIX = fft_radix<T>();
       constexpr int R = FIRST ? Plan<N, RADIX>::FIRST : RADIX;
       dif_stage<T, N, NL, NTHR, R, L>(buf, rt, tid);
-      DifRunner<T, N, NL, NTHR, L / R, false>::run(buf, rt, tid);
+      DifRunner<T, N, NL, NTHR, L / R, false, RADIX>::run(buf, rt, tid);
     }
   }
 };
@@ -180,15 +187,15 @@ struct DifRunner {
 // element e of a line lives at lds_pos(e); input in natural order, bin k found
 // at bin_pos<T, N>(k). The caller must have synchronised after writing the
 // input; the FFT ends with a barrier.
-template <typename T, int N, int NL, int NTHR>
+template <typename T, int N, int NL, int NTHR, int RADIX = fft_radix<T>()>
 __device__ __forceinline__ void fft_lines(cpx<T>* buf, const Roots<T, N>& rt, int tid) {
-  DifRunner<T, N, NL, NTHR, N, true>::run(buf, rt, tid);
+  DifRunner<T, N, NL, NTHR, N, true, RADIX>::run(buf, rt, tid);
 }
 
 // Position of DFT bin k after fft_lines (before the swizzle): the mixed-radix
 // digits of k (first radix, then the stage radix) in reverse order.
-template <typename T, int N> __device__ __forceinline__ int fft_pos(int k) {
-  constexpr int RADIX = fft_radix<T>();
+template <typename T, int N, int RADIX = fft_radix<T>()>
+__device__ __forceinline__ int fft_pos(int k) {
   using P = Plan<N, RADIX>;
   constexpr int R1 = P::FIRST;
   constexpr int LR1 = ilog2(R1);
@@ -206,8 +213,9 @@ template <typename T, int N> __device__ __forceinline__ int fft_pos(int k) {
 }
 
 // LDS position of bin k after fft_lines.
-template <typename T, int N> __device__ __forceinline__ int bin_pos(int k) {
-  return lds_pos(fft_pos<T, N>(k));
+template <typename T, int N, int RADIX = fft_radix<T>()>
+__device__ __forceinline__ int bin_pos(int k) {
+  return lds_pos(fft_pos<T, N, RADIX>(k));
 }
 
 // Makhoul position of natural index i inside the reordered line.
@@ -230,11 +238,11 @@ template <typename T> struct PostTerm {
   T s;
 };
 
-template <typename T, int N>
+template <typename T, int N, int RADIX = fft_radix<T>()>
 __device__ __forceinline__ PostTerm<T> dct2_term(const Roots<T, N>& rt, int k) {
   PostTerm<T> t;
-  t.pk = bin_pos<T, N>(k);
-  t.pm = bin_pos<T, N>((N - k) & (N - 1));
+  t.pk = bin_pos<T, N, RADIX>(k);
+  t.pm = bin_pos<T, N, RADIX>((N - k) & (N - 1));
   t.w = rt.omega(k);
   t.s = (k == 0) ? (T)(0.5 * sqrt(1.0 / N)) : (T)(0.5 * sqrt(2.0 / N));
   return t;
@@ -250,10 +258,10 @@ __device__ __forceinline__ void dct2_post(const cpx<T>* Z, const PostTerm<T>& t,
   B = t.s * (t.w.re * v2r - t.w.im * v2i);
 }
 
-template <typename T, int N>
+template <typename T, int N, int RADIX = fft_radix<T>()>
 __device__ __forceinline__ void dct2_post(const cpx<T>* Z, const Roots<T, N>& rt, int k,
                                           T& A, T& B) {
-  dct2_post<T>(Z, dct2_term<T, N>(rt, k), A, B);
+  dct2_post<T>(Z, dct2_term<T, N, RADIX>(rt, k), A, B);
 }
 
 // DCT-III pre-processing of bin k: from the orthonormal coefficients of two

@@ -97,18 +97,18 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red, int tid)
     for (int q = 0; q < NV; ++q) v[q] += __shfl_xor(v[q], off, 64);
   }
   const int lane = tid & 63, w = tid >> 6;
-  __syncthreads();
+  lds_sync();
   if (lane == 0) {
 #pragma unroll
     for (int q = 0; q < NV; ++q) red[NV + w * NV + q] = v[q];
   }
-  __syncthreads();
+  lds_sync();
   if (tid < NV) {
     double s = 0.0;
     for (int i = 0; i < NW; ++i) s += red[NV + i * NV + tid];
     red[tid] = s;
   }
-  __syncthreads();
+  lds_sync();
 }
 
 // The FP32-transform (mixed) path solves for the increments phi^{n+1} - phi^n and
@@ -123,10 +123,10 @@ template <typename TM> constexpr bool increment_form() { return sizeof(TM) == 4;
 template <int N> __device__ __forceinline__ double tree_sum(double* buf, int tid, int nthr) {
 #pragma unroll 1
   for (int half = N / 2; half >= 1; half >>= 1) {
-    __syncthreads();
+    lds_sync();
     for (int i = tid; i < half; i += nthr) buf[i] += buf[i + half];
   }
-  __syncthreads();
+  lds_sync();
   return buf[0];
 }
 
@@ -417,7 +417,7 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
         for (int i = tid; i < NX; i += NTHR) ln[lds_pos(makhoul_slot<NX>(i))] = {ra[i], rb[i]};
       }
     }
-    __syncthreads();
+    lds_sync();
     fft_lines<TM, NX, ROWS * NP, NTHR>(line, rt, tid);
 #pragma unroll 1
     for (int sp = tid; sp < NX / 2; sp += NTHR) {
@@ -438,7 +438,7 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
         store_piece<TM, ROWS>(mid + PAIR_B[pr] * FS + o, pb);
       }
     }
-    __syncthreads();
+    lds_sync();
   };
   round(std::integral_constant<int, 0>{});
   if constexpr (NP <= 2) round(std::integral_constant<int, 1>{});
@@ -451,27 +451,46 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
 // ---------------------------------------------------------------------------
 // P2: column DCT-II of the eight fields and the spectral Gram sums.
 // ---------------------------------------------------------------------------
+// One strip (two columns of one field) held in registers, KPT elements per
+// thread.
+template <typename TM, int KPT> struct StripRegs {
+  cpx<TM> v[KPT];
+};
+
 template <typename TM, int NY, int KPT, int NTHR>
-__device__ __forceinline__ void column_dct2(gptr<const cpx<TM>> __restrict__ src, cpx<TM>* line,
+__device__ __forceinline__ void fetch_strip(gptr<const cpx<TM>> __restrict__ src, int tid,
+                                            StripRegs<TM, KPT>& r) {
+#pragma unroll
+  for (int q = 0; q < KPT; ++q) {
+    const int jj = tid + q * NTHR;
+    r.v[q] = (jj < NY) ? gload<TM>(src + jj) : cpx<TM>{(TM)0, (TM)0};
+  }
+}
+
+// DCT-II along y of a strip held in registers: A (column 2s) and B (column
+// 2s + 1) at bins tid + q NTHR. The FFT radix R is chosen so that each stage
+// has one butterfly per thread.
+template <typename TM, int NY, int KPT, int NTHR, int R>
+__device__ __forceinline__ void column_dct2(const StripRegs<TM, KPT>& in, cpx<TM>* line,
                                             const Roots<TM, NY>& rt, int tid, TM (&A)[KPT],
                                             TM (&B)[KPT]) {
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
     const int jj = tid + q * NTHR;
-    if (jj < NY) line[lds_pos(makhoul_slot<NY>(jj))] = gload<TM>(src + jj);
+    if (jj < NY) line[lds_pos(makhoul_slot<NY>(jj))] = in.v[q];
   }
-  __syncthreads();
-  fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
+  lds_sync();
+  fft_lines<TM, NY, 1, NTHR, R>(line, rt, tid);
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
     const int k = tid + q * NTHR;
     if (k < NY) {
-      dct2_post<TM, NY>(line, rt, k, A[q], B[q]);
+      dct2_post<TM, NY, R>(line, rt, k, A[q], B[q]);
     } else {
       A[q] = 0; B[q] = 0;
     }
   }
-  __syncthreads();
+  lds_sync();
 }
 
 // Sum NV per-thread values over the block and add them to acc[IDX[q]].
@@ -532,6 +551,15 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
       b = kb[f][q];
     }
   };
+  // Fields in the order they are transformed.
+  constexpr int GR = NY / NTHR >= 8 ? 8 : (NY / NTHR >= 4 ? 4 : 2);   // radix: 1 butterfly/thread
+  constexpr int ORDER[8] = {M_S, M_H, M_Q, M_K, M_F, M_P, M_G, M_L};
+
+  auto transform_next = [&](int i, TM (&A)[KPT], TM (&B)[KPT]) {
+    StripRegs<TM, KPT> cur;
+    fetch_strip<TM, NY, KPT, NTHR>(strip(ORDER[i]), tid, cur);
+    column_dct2<TM, NY, KPT, NTHR, GR>(cur, line, rt, tid, A, B);
+  };
   constexpr int CHI[4] = {M_S, M_H, M_Q, M_K};
   constexpr int GIDX[4][4] = {{P2_SS, P2_SH, P2_SQ, P2_SK},
                               {P2_SH, P2_HH, P2_HQ, P2_HK},
@@ -541,7 +569,7 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   auto chi_stage = [&](auto ia) {
     constexpr int a = decltype(ia)::value;
     TM A[KPT], B[KPT];
-    column_dct2<TM, NY, KPT, NTHR>(strip(CHI[a]), line, rt, tid, A, B);
+    transform_next(a, A, B);
     double v[a + 1];
     int idx[a + 1];
 #pragma unroll
@@ -575,7 +603,7 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   // f_lin against the four kept spectra.
   {
     TM A[KPT], B[KPT];
-    column_dct2<TM, NY, KPT, NTHR>(strip(M_F), line, rt, tid, A, B);
+    transform_next(4, A, B);
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int idx[4] = {P2_FS, P2_FH, P2_FQ, P2_FK};
 #pragma unroll
@@ -594,11 +622,11 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   }
   // zeta group: P~ kept (in the H slot), then g_lin and L~.
   {
-    column_dct2<TM, NY, KPT, NTHR>(strip(M_P), line, rt, tid, ka[1], kb[1]);
+    transform_next(5, ka[1], kb[1]);
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
       TM A[KPT], B[KPT];
-      column_dct2<TM, NY, KPT, NTHR>(strip(g == 0 ? M_G : M_L), line, rt, tid, A, B);
+      transform_next(6 + g, A, B);
       double v[1] = {0.0};
       const int idx[1] = {g == 0 ? P2_PG : P2_PL};
 #pragma unroll
@@ -611,7 +639,7 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
       stage_accumulate<1, NTHR>(v, idx, red, acc, tid);
     }
   }
-  __syncthreads();
+  lds_sync();
   if (tid < P2_NSUM) part[(size_t)s * P2_NSUM + tid] = acc[tid];
 }
 
@@ -630,7 +658,7 @@ __device__ void reduce_rows(P part, int nrows, double* red, int tid, double (&to
   block_sum<NV, NTHR>(v, red, tid);
 #pragma unroll
   for (int q = 0; q < NV; ++q) tot[q] = red[q];
-  __syncthreads();
+  lds_sync();
 }
 
 // ---------------------------------------------------------------------------
@@ -783,7 +811,7 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
       line[lds_pos(makhoul_slot<NY>(jj))] = {(TM)ur, (TM)ui};
     }
   }
-  __syncthreads();
+  lds_sync();
   fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
   TM A[KPT], B[KPT];
   const double lx0 = lamx[2 * s], lx1 = lamx[2 * s + 1];
@@ -809,13 +837,13 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
       if (colsum && grp == 1 && s == 0 && k == 0) A[q] = (TM)0;
     }
   }
-  __syncthreads();
+  lds_sync();
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
     const int k = tid + q * NTHR;
     if (k < NY) line[lds_pos(k)] = {A[q], B[q]};
   }
-  __syncthreads();
+  lds_sync();
   cpx<TM> Z[KPT];
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
@@ -825,13 +853,13 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
       Z[q] = dct3_pre<TM, NY>(rt, k, A[q], m.re, B[q], m.im);
     }
   }
-  __syncthreads();
+  lds_sync();
 #pragma unroll
   for (int q = 0; q < KPT; ++q) {
     const int k = tid + q * NTHR;
     if (k < NY) line[lds_pos(k)] = Z[q];
   }
-  __syncthreads();
+  lds_sync();
   fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
   const auto dst = reinterpret_cast<gptr<cpx<TM>>>(out + (size_t)grp * FS) + (size_t)s * NY;
   TM y0[KPT];
@@ -851,7 +879,7 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
     // for the row sums that add up to zero, so that the increment it writes
     // has zero sum in FP64 arithmetic.
     double* buf = reinterpret_cast<double*>(line);   // the line is no longer read
-    __syncthreads();
+    lds_sync();
 #pragma unroll
     for (int q = 0; q < KPT; ++q) {
       const int i = tid + q * NTHR;
@@ -883,7 +911,7 @@ __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
   const size_t FS = (size_t)NX * ny;
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
-  __syncthreads();
+  lds_sync();
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int k = tid + q * NTHR;
@@ -893,7 +921,7 @@ __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
       line[lds_pos(k)] = dct3_pre<TM, NX>(rt, k, out[ok], out[om], out[FS + ok], out[FS + om]);
     }
   }
-  __syncthreads();
+  lds_sync();
   fft_lines<TM, NX, 1, NTHR>(line, rt, tid);
   if (!colsum) {
 #pragma unroll
@@ -918,7 +946,7 @@ __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
     if (i < NX) Y[q] = line[lds_pos(fft_pos<TM, NX>(makhoul_slot<NX>(i)))];
   }
   double* buf = reinterpret_cast<double*>(line);     // the line is no longer read
-  __syncthreads();
+  lds_sync();
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
     const int i = tid + q * NTHR;
@@ -956,7 +984,7 @@ k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, 
     const int i = tid + q * NTHR;
     if (i < NX) line[lds_pos(makhoul_slot<NX>(i))] = {(TM)src[(size_t)j * NX + i], (TM)0};
   }
-  __syncthreads();
+  lds_sync();
   fft_lines<TM, NX, 1, NTHR>(line, rt, tid);
 #pragma unroll
   for (int q = 0; q < CPT; ++q) {
