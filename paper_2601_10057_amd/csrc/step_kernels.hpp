@@ -1,32 +1,44 @@
 // Kernels of one CC-MSAV-BDF2 step (Sec. 3.2, solved as in App. B and App. C).
 //
 // Pipeline of one step (fields are row-major [ny][nx], x fastest):
-//   P1  k_stencil_rowdct : per band of 1-4 rows, the explicit stencil terms of eqs.
-//       (AC_BDF2)-(Z_BDF2) at phi* = x0 phi^n + x1 phi^{n-1}: the basis numerators
-//       S~, H, Q~, K~, P~ (Sec. 2.2 with the discrete forms of Sec. 3.4.1),
-//       L~ = div(M_psi(A phi*) grad P~), f_lin, g_lin, plus the SAV partial sums;
-//       then the orthonormal DCT-II along x of the 8 fields (the band's rows of
-//       a column pair leave as one 32-byte piece).
-//   P2  k_col_gram       : per strip of two columns, DCT-II along y and the
+//   P1a k_stencil    : the explicit stencil terms of eqs. (AC_BDF2)-(Z_BDF2) at
+//       phi* = x0 phi^n + x1 phi^{n-1}: the basis numerators S~, H, Q~, K~, P~
+//       (Sec. 2.2 with the discrete forms of Sec. 3.4.1), L~ = div(M_psi(A phi*)
+//       grad P~), f_lin and g_lin (or their increment-form residuals), plus the
+//       SAV partial sums; each wave walks down a band of rows with a register
+//       window.
+//   P1b k_row_dct8   : orthonormal DCT-II along x of the 8 fields for a band of
+//       rows (the band's rows of a column pair leave as one 32-byte piece).
+//   P2  k_col_gram   : per strip of two columns, DCT-II along y and the
 //       Parseval inner products (F_i, chi^{-1} F_j), (P, zeta^{-1} g), (P, zeta^{-1} L).
-//   S   k_solve          : reduces the partials, assembles and solves the 5x5
+//   S   k_solve      : reduces the partials, assembles and solves the 5x5
 //       system of App. B Step 4, updates the SAVs, and emits the spectral
 //       combination coefficients (all on the device).
-//   P3  k_col_solve      : per strip, combines the x-transformed fields into the
+//   P3  k_col_solve  : per strip, combines the x-transformed fields into the
 //       right-hand sides of chi phi^{n+1} and zeta psi^{n+1}, DCT-II along y,
 //       divides by sigma / tau, DCT-III along y.
-//   P4  k_row_idct       : per row, DCT-III along x of both results -> phi^{n+1},
-//       psi^{n+1}.
+//   P4  k_row_idct   : per row, DCT-III along x of both results -> phi^{n+1},
+//       psi^{n+1} (added to phi^n, psi^n in the increment form).
 // The intermediate fields use a strip-major layout: element (k, j) of a field
 // lives at ((k / 2) * ny + j) * 2 + (k % 2), so that a column pair is one
 // contiguous complex line.
 #pragma once
 #include <type_traits>
+#include <utility>
 
 #include "fft.hpp"
 #include "step_common.hpp"
 
 namespace ccm {
+
+// Calls f(std::integral_constant<int, i>{}) for i = 0 .. N-1.
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F> __device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 constexpr int clamp_threads(int t) { return t < 64 ? 64 : (t > 1024 ? 1024 : t); }
 // Threads of a line kernel: four elements per thread.
@@ -128,6 +140,17 @@ template <int N> __device__ __forceinline__ double tree_sum(double* buf, int tid
   }
   lds_sync();
   return buf[0];
+}
+
+// 1 / x for positive, normal x: the hardware reciprocal estimate refined by
+// two Newton steps r <- r + r (1 - x r), each squaring the relative error, to
+// within about 1 ulp of FP64 (cheaper than the correctly rounded division).
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
 }
 
 __device__ __forceinline__ double mobility(double phi, double M0) {
@@ -403,6 +426,18 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
 
+  using MAP = LdsMap<TM, NX, SWZ_ROW>;
+  constexpr int R = fft_radix<TM>();
+  using LS = LineSlots<NX, NTHR, R, MAP>;
+  constexpr int CPT = NX >= NTHR ? NX / NTHR : 1;            // loads per thread and line
+  constexpr int SPT = NX / 2 >= NTHR ? NX / 2 / NTHR : 1;    // column pairs per thread
+  const LS sl(tid);
+  // Post-processing slots of bins 2 sp and 2 sp + 1 and of their mirrors
+  // N - 2 sp = (N - 1) ^ (2 (sp - 1) + 1) and N - 2 sp - 1 = (N - 1) ^ 2 sp.
+  const int g2 = LS::g(2 * tid);
+  const int g2m = MAP::at(NX - 1) ^ LS::g(1) ^ LS::g((2 * tid - 2) & (NX - 1));
+  const TM S0 = (TM)(0.5 * sqrt(1.0 / NX)), S1 = (TM)(0.5 * sqrt(2.0 / NX));
+
   auto round = [&](auto ir) {
     constexpr int r = decltype(ir)::value;
 #pragma unroll
@@ -412,30 +447,43 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
         const int pr = r * NP + l;
         const auto ra = rm + PAIR_A[pr] * FS + (size_t)(j0 + rr) * NX;
         const auto rb = rm + PAIR_B[pr] * FS + (size_t)(j0 + rr) * NX;
-        cpx<TM>* ln = line + (rr * NP + l) * NX;
-#pragma unroll
-        for (int i = tid; i < NX; i += NTHR) ln[lds_pos(makhoul_slot<NX>(i))] = {ra[i], rb[i]};
+        const int lo = MAP::at((rr * NP + l) * NX);
+        static_for<CPT>([&](auto iq) {
+          constexpr int q = decltype(iq)::value;
+          const int i = tid + q * NTHR;
+          if (NX >= NTHR || i < NX) line[lo ^ sl.template mak<q>()] = {ra[i], rb[i]};
+        });
       }
     }
     lds_sync();
-    fft_lines<TM, NX, ROWS * NP, NTHR>(line, rt, tid);
+    fft_lines<TM, NX, ROWS * NP, NTHR, R, MAP>(line, rt, tid);
 #pragma unroll 1
-    for (int sp = tid; sp < NX / 2; sp += NTHR) {
-      const PostTerm<TM> t0 = dct2_term<TM, NX>(rt, 2 * sp);
-      const PostTerm<TM> t1 = dct2_term<TM, NX>(rt, 2 * sp + 1);
+    for (int it = 0; it < SPT; ++it) {
+      const int sp = tid + it * NTHR;
+      if (NX / 2 >= NTHR || sp < NX / 2) {
+        const int pk0 = g2 ^ LS::g(2 * it * NTHR);
+        const int pk1 = pk0 ^ LS::g(1);
+        const int pm1 = pk0 ^ MAP::at(NX - 1);
+        const int pm0 = tid == 0 ? (it == 0 ? 0 : (MAP::at(NX - 1) ^ LS::g(1) ^
+                                                   LS::g((2 * it * NTHR - 2) & (NX - 1))))
+                                 : (g2m ^ LS::g(2 * it * NTHR));
+        const cpx<TM> w0 = rt.omega(2 * sp), w1 = rt.omega(2 * sp + 1);
+        const TM s0 = sp == 0 ? S0 : S1;
 #pragma unroll
-      for (int l = 0; l < NP; ++l) {
-        const int pr = r * NP + l;
-        RowPiece<TM, ROWS> pa, pb;
+        for (int l = 0; l < NP; ++l) {
+          const int pr = r * NP + l;
+          RowPiece<TM, ROWS> pa, pb;
 #pragma unroll
-        for (int rr = 0; rr < ROWS; ++rr) {
-          const cpx<TM>* z = line + (rr * NP + l) * NX;
-          dct2_post<TM>(z, t0, pa.v[2 * rr], pb.v[2 * rr]);
-          dct2_post<TM>(z, t1, pa.v[2 * rr + 1], pb.v[2 * rr + 1]);
+          for (int rr = 0; rr < ROWS; ++rr) {
+            const int lo = MAP::at((rr * NP + l) * NX);
+            dct2_bin<TM>(line[lo ^ pk0], line[lo ^ pm0], w0, s0, pa.v[2 * rr], pb.v[2 * rr]);
+            dct2_bin<TM>(line[lo ^ pk1], line[lo ^ pm1], w1, S1, pa.v[2 * rr + 1],
+                         pb.v[2 * rr + 1]);
+          }
+          const size_t o = ((size_t)sp * ny + j0) * 2;
+          store_piece<TM, ROWS>(mid + PAIR_A[pr] * FS + o, pa);
+          store_piece<TM, ROWS>(mid + PAIR_B[pr] * FS + o, pb);
         }
-        const size_t o = ((size_t)sp * ny + j0) * 2;
-        store_piece<TM, ROWS>(mid + PAIR_A[pr] * FS + o, pa);
-        store_piece<TM, ROWS>(mid + PAIR_B[pr] * FS + o, pb);
       }
     }
     lds_sync();
@@ -451,45 +499,47 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
 // ---------------------------------------------------------------------------
 // P2: column DCT-II of the eight fields and the spectral Gram sums.
 // ---------------------------------------------------------------------------
-// One strip (two columns of one field) held in registers, KPT elements per
-// thread.
-template <typename TM, int KPT> struct StripRegs {
-  cpx<TM> v[KPT];
+// One strip (two columns of one field) held in registers, LPT elements per
+// thread (natural index tid + q NTHR).
+template <typename TM, int LPT> struct StripRegs {
+  cpx<TM> v[LPT];
 };
 
-template <typename TM, int NY, int KPT, int NTHR>
+template <typename TM, int NY, int LPT, int NTHR>
 __device__ __forceinline__ void fetch_strip(gptr<const cpx<TM>> __restrict__ src, int tid,
-                                            StripRegs<TM, KPT>& r) {
+                                            StripRegs<TM, LPT>& r) {
 #pragma unroll
-  for (int q = 0; q < KPT; ++q) {
+  for (int q = 0; q < LPT; ++q) {
     const int jj = tid + q * NTHR;
-    r.v[q] = (jj < NY) ? gload<TM>(src + jj) : cpx<TM>{(TM)0, (TM)0};
+    r.v[q] = (NY >= NTHR || jj < NY) ? gload<TM>(src + jj) : cpx<TM>{(TM)0, (TM)0};
   }
 }
 
 // DCT-II along y of a strip held in registers: A (column 2s) and B (column
-// 2s + 1) at bins tid + q NTHR. The FFT radix R is chosen so that each stage
-// has one butterfly per thread.
-template <typename TM, int NY, int KPT, int NTHR, int R>
-__device__ __forceinline__ void column_dct2(const StripRegs<TM, KPT>& in, cpx<TM>* line,
-                                            const Roots<TM, NY>& rt, int tid, TM (&A)[KPT],
-                                            TM (&B)[KPT]) {
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int jj = tid + q * NTHR;
-    if (jj < NY) line[lds_pos(makhoul_slot<NY>(jj))] = in.v[q];
-  }
+// 2s + 1) for the bins of the thread's pair units u = tid + q NTHR, bin u at
+// index 2q and bin pair_mirror(u) at 2q + 1. The FFT radix R gives one
+// butterfly per thread in each stage.
+template <typename TM, int NY, int LPT, int UPT, int NTHR, int R, typename MAP>
+__device__ __forceinline__ void column_dct2(const StripRegs<TM, LPT>& in, cpx<TM>* line,
+                                            const Roots<TM, NY>& rt,
+                                            const LineSlots<NY, NTHR, R, MAP>& sl, int tid,
+                                            TM (&A)[2 * UPT], TM (&B)[2 * UPT]) {
+  static_for<LPT>([&](auto iq) {
+    constexpr int q = decltype(iq)::value;
+    if (NY >= NTHR || tid + q * NTHR < NY) line[sl.template mak<q>()] = in.v[q];
+  });
   lds_sync();
-  fft_lines<TM, NY, 1, NTHR, R>(line, rt, tid);
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = tid + q * NTHR;
-    if (k < NY) {
-      dct2_post<TM, NY, R>(line, rt, k, A[q], B[q]);
+  fft_lines<TM, NY, 1, NTHR, R, MAP>(line, rt, tid);
+  static_for<UPT>([&](auto iq) {
+    constexpr int q = decltype(iq)::value;
+    const int u = tid + q * NTHR;
+    if (NY / 2 >= NTHR || u < NY / 2) {
+      dct2_unit<TM, NY>(line, sl.template bin<q>(), sl.template binm<q>(), rt, u, A[2 * q],
+                        B[2 * q], A[2 * q + 1], B[2 * q + 1]);
     } else {
-      A[q] = 0; B[q] = 0;
+      A[2 * q] = 0; B[2 * q] = 0; A[2 * q + 1] = 0; B[2 * q + 1] = 0;
     }
-  }
+  });
   lds_sync();
 }
 
@@ -508,7 +558,14 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
                                               gptr<double> __restrict__ part, int nx,
                                               const OpConst c, int s) {
   constexpr int NTHR = gram_threads(NY);
-  constexpr int KPT = (NY + NTHR - 1) / NTHR;
+  constexpr int LPT = NY >= NTHR ? NY / NTHR : 1;            // strip loads per thread
+  constexpr int UPT = NY / 2 >= NTHR ? NY / 2 / NTHR : 1;    // pair units per thread
+  constexpr int KPT = 2 * UPT;                               // bins per thread
+  constexpr int KS = NY / 2 >= NTHR ? NTHR : NY / 2;         // stride of a thread's bins in keep
+  // Radix with one butterfly per thread in each FFT stage.
+  constexpr int GR = NY / NTHR >= 8 ? 8 : (NY / NTHR >= 4 ? 4 : 2);
+  using MAP = LdsMap<TM, NY, SWZ_GRAM>;
+  using LS = LineSlots<NY, NTHR, GR, MAP>;
   // FP64 up to 4096: the S~ spectrum waits in LDS, H, Q~, K~ in registers;
   // otherwise all four stay in registers.
   constexpr bool S_LDS = sizeof(TM) == 8 && NY <= 4096;
@@ -521,46 +578,51 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   const size_t FS = (size_t)nx * NY;
   Roots<TM, NY> rt;
   rt.init(rtab, tid, NTHR);
+  const LS sl(tid);
   if (tid < P2_NSUM) acc[tid] = 0.0;
   const double lx0 = lamx[2 * s], lx1 = lamx[2 * s + 1];
   auto strip = [&](int f) {
     return reinterpret_cast<gptr<const cpx<TM>>>(mid + (size_t)f * FS) + (size_t)s * NY;
   };
+  // bin held at index j (unit tid + (j / 2) NTHR; even j: the unit's own bin)
+  auto bin_of = [&](int j) {
+    const int u = tid + (j >> 1) * NTHR;
+    return (j & 1) ? pair_mirror<NY>(u) : u;
+  };
+  auto valid = [&](int) { return NY / 2 >= NTHR || tid < NY / 2; };
   // 1/sigma (chi) or 1/tau (zeta) at (2s, k) and (2s+1, k)
   auto inv_op = [&](int k, bool chi, double& i0, double& i1) {
-    const double ly = (k < NY) ? lamy[k] : 0.0;
+    const double ly = lamy[k];
     const double L0 = lx0 + ly, L1 = lx1 + ly;
     if (chi) {
-      i0 = 1.0 / (c.C1 + L0 * (c.C2 + c.C3 * L0));
-      i1 = 1.0 / (c.C1 + L1 * (c.C2 + c.C3 * L1));
+      i0 = rcp64(c.C1 + L0 * (c.C2 + c.C3 * L0));
+      i1 = rcp64(c.C1 + L1 * (c.C2 + c.C3 * L1));
     } else {
-      i0 = 1.0 / (c.alpha + c.lam * L0);
-      i1 = 1.0 / (c.alpha + c.lam * L1);
+      i0 = rcp64(c.alpha + c.lam * L0);
+      i1 = rcp64(c.alpha + c.lam * L1);
     }
   };
   // Spectra kept for the pairwise products: index 0 = S~ (unless in LDS),
   // 1 = H, 2 = Q~, 3 = K~.
   TM ka[4][KPT], kb[4][KPT];
-  auto kept = [&](int f, int q, TM& a, TM& b) {
+  auto kept = [&](int f, int j, TM& a, TM& b) {
     if (S_LDS && f == 0) {
-      const cpx<TM> v = keep[tid + q * NTHR];
+      const cpx<TM> v = keep[tid + j * KS];
       a = v.re;
       b = v.im;
     } else {
-      a = ka[f][q];
-      b = kb[f][q];
+      a = ka[f][j];
+      b = kb[f][j];
     }
   };
   // Fields in the order they are transformed.
-  constexpr int GR = NY / NTHR >= 8 ? 8 : (NY / NTHR >= 4 ? 4 : 2);   // radix: 1 butterfly/thread
   constexpr int ORDER[8] = {M_S, M_H, M_Q, M_K, M_F, M_P, M_G, M_L};
 
   auto transform_next = [&](int i, TM (&A)[KPT], TM (&B)[KPT]) {
-    StripRegs<TM, KPT> cur;
-    fetch_strip<TM, NY, KPT, NTHR>(strip(ORDER[i]), tid, cur);
-    column_dct2<TM, NY, KPT, NTHR, GR>(cur, line, rt, tid, A, B);
+    StripRegs<TM, LPT> cur;
+    fetch_strip<TM, NY, LPT, NTHR>(strip(ORDER[i]), tid, cur);
+    column_dct2<TM, NY, LPT, UPT, NTHR, GR, MAP>(cur, line, rt, sl, tid, A, B);
   };
-  constexpr int CHI[4] = {M_S, M_H, M_Q, M_K};
   constexpr int GIDX[4][4] = {{P2_SS, P2_SH, P2_SQ, P2_SK},
                               {P2_SH, P2_HH, P2_HQ, P2_HK},
                               {P2_SQ, P2_HQ, P2_QQ, P2_QK},
@@ -575,22 +637,22 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
 #pragma unroll
     for (int b = 0; b <= a; ++b) { v[b] = 0.0; idx[b] = GIDX[b][a]; }
 #pragma unroll
-    for (int q = 0; q < KPT; ++q) {
-      if (tid + q * NTHR >= NY) continue;     // blocks wider than the line
+    for (int j = 0; j < KPT; ++j) {
+      if (!valid(j)) continue;               // blocks wider than half the line
       double i0, i1;
-      inv_op(tid + q * NTHR, true, i0, i1);
+      inv_op(bin_of(j), true, i0, i1);
 #pragma unroll
       for (int b = 0; b < a; ++b) {
         TM ea, eb;
-        kept(b, q, ea, eb);
-        v[b] += (double)A[q] * (double)ea * i0 + (double)B[q] * (double)eb * i1;
+        kept(b, j, ea, eb);
+        v[b] += (double)A[j] * (double)ea * i0 + (double)B[j] * (double)eb * i1;
       }
-      v[a] += (double)A[q] * (double)A[q] * i0 + (double)B[q] * (double)B[q] * i1;
+      v[a] += (double)A[j] * (double)A[j] * i0 + (double)B[j] * (double)B[j] * i1;
       if (S_LDS && a == 0) {
-        keep[tid + q * NTHR] = {A[q], B[q]};
+        keep[tid + j * KS] = {A[j], B[j]};
       } else {
-        ka[a][q] = A[q];
-        kb[a][q] = B[q];
+        ka[a][j] = A[j];
+        kb[a][j] = B[j];
       }
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -607,15 +669,15 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int idx[4] = {P2_FS, P2_FH, P2_FQ, P2_FK};
 #pragma unroll
-    for (int q = 0; q < KPT; ++q) {
-      if (tid + q * NTHR >= NY) continue;
+    for (int j = 0; j < KPT; ++j) {
+      if (!valid(j)) continue;
       double i0, i1;
-      inv_op(tid + q * NTHR, true, i0, i1);
+      inv_op(bin_of(j), true, i0, i1);
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         TM ea, eb;
-        kept(b, q, ea, eb);
-        v[b] += (double)A[q] * (double)ea * i0 + (double)B[q] * (double)eb * i1;
+        kept(b, j, ea, eb);
+        v[b] += (double)A[j] * (double)ea * i0 + (double)B[j] * (double)eb * i1;
       }
     }
     stage_accumulate<4, NTHR>(v, idx, red, acc, tid);
@@ -630,11 +692,11 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
       double v[1] = {0.0};
       const int idx[1] = {g == 0 ? P2_PG : P2_PL};
 #pragma unroll
-      for (int q = 0; q < KPT; ++q) {
-        if (tid + q * NTHR >= NY) continue;
+      for (int j = 0; j < KPT; ++j) {
+        if (!valid(j)) continue;
         double i0, i1;
-        inv_op(tid + q * NTHR, false, i0, i1);
-        v[0] += (double)A[q] * (double)ka[1][q] * i0 + (double)B[q] * (double)kb[1][q] * i1;
+        inv_op(bin_of(j), false, i0, i1);
+        v[0] += (double)A[j] * (double)ka[1][j] * i0 + (double)B[j] * (double)kb[1][j] * i1;
       }
       stage_accumulate<1, NTHR>(v, idx, red, acc, tid);
     }
@@ -782,7 +844,11 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
                                                int nchi, int zeta_base, int nzeta,
                                                gptr<double> __restrict__ colsum,
                                                const OpConst c, int lin) {
-  constexpr int KPT = (NY + NTHR - 1) / NTHR;
+  constexpr int LPT = NY >= NTHR ? NY / NTHR : 1;            // elements per thread
+  constexpr int UPT = NY / 2 >= NTHR ? NY / 2 / NTHR : 1;    // pair units per thread
+  constexpr int R = fft_radix<TM>();
+  using MAP = LdsMap<TM, NY, SWZ_LINE>;
+  using LS = LineSlots<NY, NTHR, R, MAP>;
   __shared__ cpx<TM> line[NY];
   __shared__ cpx<double> rtab[Roots<TM, NY>::SIZE];
   const int tid = threadIdx.x;
@@ -792,15 +858,16 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
   const size_t FS = (size_t)nx * NY;
   Roots<TM, NY> rt;
   rt.init(rtab, tid, NTHR);
+  const LS sl(tid);
   const int base = grp == 0 ? chi_base : zeta_base;
   const int nf = grp == 0 ? nchi : nzeta;
   const auto cf = coef + (grp == 0 ? 0 : 5);
 
   // combine the x-transformed right-hand sides of this group
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
+  static_for<LPT>([&](auto iq) {
+    constexpr int q = decltype(iq)::value;
     const int jj = tid + q * NTHR;
-    if (jj < NY) {
+    if (NY >= NTHR || jj < NY) {
       double ur = 0.0, ui = 0.0;
       for (int f = 0; f < nf; ++f) {
         const cpx<TM> v = gload<TM>(reinterpret_cast<gptr<const cpx<TM>>>(
@@ -808,71 +875,58 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
         ur += cf[f] * (double)v.re;
         ui += cf[f] * (double)v.im;
       }
-      line[lds_pos(makhoul_slot<NY>(jj))] = {(TM)ur, (TM)ui};
+      line[sl.template mak<q>()] = {(TM)ur, (TM)ui};
     }
-  }
+  });
   lds_sync();
-  fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
-  TM A[KPT], B[KPT];
+  fft_lines<TM, NY, 1, NTHR, R, MAP>(line, rt, tid);
+  // Per pair unit: DCT-II post-processing of both bins, divide by the operator
+  // spectrum, DCT-III pre-processing of both bins (the unit holds everything
+  // the inverse needs, so the line is rewritten directly).
   const double lx0 = lamx[2 * s], lx1 = lamx[2 * s + 1];
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = tid + q * NTHR;
-    if (k < NY) {
-      dct2_post<TM, NY>(line, rt, k, A[q], B[q]);
-      const double ly = lamy[k];
-      const double L0 = lx0 + ly, L1 = lx1 + ly;
-      double d0, d1;
-      if (grp == 0) {
-        d0 = c.C1 + L0 * (c.C2 + c.C3 * L0);
-        d1 = c.C1 + L1 * (c.C2 + c.C3 * L1);
-      } else {
-        d0 = c.alpha + c.lam * L0;
-        d1 = c.alpha + c.lam * L1;
-      }
-      A[q] = (TM)((double)A[q] / d0);
-      B[q] = (TM)((double)B[q] / d1);
+  auto op = [&](double L) {
+    return grp == 0 ? c.C1 + L * (c.C2 + c.C3 * L) : c.alpha + c.lam * L;
+  };
+  cpx<TM> Z[UPT], Zm[UPT];
+  static_for<UPT>([&](auto iq) {
+    constexpr int q = decltype(iq)::value;
+    const int u = tid + q * NTHR;
+    if (NY / 2 >= NTHR || u < NY / 2) {
+      TM A, B, Am, Bm;
+      dct2_unit<TM, NY>(line, sl.template bin<q>(), sl.template binm<q>(), rt, u, A, B, Am, Bm);
+      const double ly = lamy[u], lym = lamy[pair_mirror<NY>(u)];
+      A = (TM)((double)A * rcp64(op(lx0 + ly)));
+      B = (TM)((double)B * rcp64(op(lx1 + ly)));
+      Am = (TM)((double)Am * rcp64(op(lx0 + lym)));
+      Bm = (TM)((double)Bm * rcp64(op(lx1 + lym)));
       // Increment form: the psi increment has zero mean (mass is conserved
       // exactly by the scheme); its (0, 0) coefficient is set, not solved.
-      if (colsum && grp == 1 && s == 0 && k == 0) A[q] = (TM)0;
+      if (colsum && grp == 1 && s == 0 && u == 0) A = (TM)0;
+      dct3_pair<TM, NY>(rt, u, A, Am, B, Bm, Z[q], Zm[q]);
     }
-  }
+  });
   lds_sync();
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = tid + q * NTHR;
-    if (k < NY) line[lds_pos(k)] = {A[q], B[q]};
-  }
-  lds_sync();
-  cpx<TM> Z[KPT];
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = tid + q * NTHR;
-    if (k < NY) {
-      const cpx<TM> m = line[lds_pos((NY - k) & (NY - 1))];
-      Z[q] = dct3_pre<TM, NY>(rt, k, A[q], m.re, B[q], m.im);
+  static_for<UPT>([&](auto iq) {
+    constexpr int q = decltype(iq)::value;
+    if (NY / 2 >= NTHR || tid < NY / 2) {
+      line[sl.template nat<q>()] = Z[q];
+      line[sl.template natm<q>()] = Zm[q];
     }
-  }
+  });
   lds_sync();
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
-    const int k = tid + q * NTHR;
-    if (k < NY) line[lds_pos(k)] = Z[q];
-  }
-  lds_sync();
-  fft_lines<TM, NY, 1, NTHR>(line, rt, tid);
+  fft_lines<TM, NY, 1, NTHR, R, MAP>(line, rt, tid);
   const auto dst = reinterpret_cast<gptr<cpx<TM>>>(out + (size_t)grp * FS) + (size_t)s * NY;
-  TM y0[KPT];
-#pragma unroll
-  for (int q = 0; q < KPT; ++q) {
+  TM y0[LPT];
+  static_for<LPT>([&](auto iq) {
+    constexpr int q = decltype(iq)::value;
     const int i = tid + q * NTHR;
     y0[q] = (TM)0;
-    if (i < NY) {
-      const cpx<TM> y = line[lds_pos(fft_pos<TM, NY>(makhoul_slot<NY>(i)))];
+    if (NY >= NTHR || i < NY) {
+      const cpx<TM> y = line[sl.template out<q>()];
       gstore<TM>(dst + i, {y.re, -y.im});
       y0[q] = y.re;
     }
-  }
+  });
   if (colsum && grp == 1 && s == 0) {
     // Column k_x = 0 of the psi increment, y physical: its FP32 values sum to
     // rounding noise instead of zero. Hand the row-inverse pass FP64 targets
@@ -881,13 +935,13 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
     double* buf = reinterpret_cast<double*>(line);   // the line is no longer read
     lds_sync();
 #pragma unroll
-    for (int q = 0; q < KPT; ++q) {
+    for (int q = 0; q < LPT; ++q) {
       const int i = tid + q * NTHR;
       if (i < NY) buf[i] = (double)y0[q];
     }
     const double mean = tree_sum<NY>(buf, tid, NTHR) / NY;
 #pragma unroll
-    for (int q = 0; q < KPT; ++q) {
+    for (int q = 0; q < LPT; ++q) {
       const int i = tid + q * NTHR;
       if (i < NY) colsum[i] = (double)y0[q] - mean;
     }
@@ -904,47 +958,54 @@ __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
                                               gptr<const double> __restrict__ phi_base,
                                               gptr<const double> __restrict__ psi_base,
                                               gptr<const double> __restrict__ colsum, int j) {
-  constexpr int CPT = (NX + NTHR - 1) / NTHR;
+  constexpr int CPT = NX >= NTHR ? NX / NTHR : 1;            // outputs per thread
+  constexpr int UPT = NX / 2 >= NTHR ? NX / 2 / NTHR : 1;    // pair units per thread
+  constexpr int R = fft_radix<TM>();
+  using MAP = LdsMap<TM, NX, SWZ_LINE>;
+  using LS = LineSlots<NX, NTHR, R, MAP>;
   __shared__ cpx<TM> line[NX];
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   const int tid = threadIdx.x;
   const size_t FS = (size_t)NX * ny;
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
+  const LS sl(tid);
   lds_sync();
-#pragma unroll
-  for (int q = 0; q < CPT; ++q) {
-    const int k = tid + q * NTHR;
-    if (k < NX) {
-      const int km = (NX - k) & (NX - 1);
-      const size_t ok = mid_index(k, j, ny), om = mid_index(km, j, ny);
-      line[lds_pos(k)] = dct3_pre<TM, NX>(rt, k, out[ok], out[om], out[FS + ok], out[FS + om]);
+  static_for<UPT>([&](auto iq) {
+    constexpr int q = decltype(iq)::value;
+    const int u = tid + q * NTHR;
+    if (NX / 2 >= NTHR || u < NX / 2) {
+      const size_t ok = mid_index(u, j, ny), om = mid_index(pair_mirror<NX>(u), j, ny);
+      cpx<TM> Z, Zm;
+      dct3_pair<TM, NX>(rt, u, out[ok], out[om], out[FS + ok], out[FS + om], Z, Zm);
+      line[sl.template nat<q>()] = Z;
+      line[sl.template natm<q>()] = Zm;
     }
-  }
+  });
   lds_sync();
-  fft_lines<TM, NX, 1, NTHR>(line, rt, tid);
+  fft_lines<TM, NX, 1, NTHR, R, MAP>(line, rt, tid);
   if (!colsum) {
-#pragma unroll
-    for (int q = 0; q < CPT; ++q) {
+    static_for<CPT>([&](auto iq) {
+      constexpr int q = decltype(iq)::value;
       const int i = tid + q * NTHR;
-      if (i < NX) {
-        const cpx<TM> y = line[lds_pos(fft_pos<TM, NX>(makhoul_slot<NX>(i)))];
+      if (NX >= NTHR || i < NX) {
+        const cpx<TM> y = line[sl.template out<q>()];
         phi_new[(size_t)j * NX + i] = (double)y.re;
         psi_new[(size_t)j * NX + i] = -(double)y.im;
       }
-    }
+    });
     return;
   }
   // Increment form: new = base + increment. The psi increment of this row is
   // shifted by a constant so that its FP64 sum equals sqrt(NX) colsum[j]
   // (orthonormal DCT-III: the row sum is sqrt(NX) times the k = 0 input).
   cpx<TM> Y[CPT];
-#pragma unroll
-  for (int q = 0; q < CPT; ++q) {
+  static_for<CPT>([&](auto iq) {
+    constexpr int q = decltype(iq)::value;
     const int i = tid + q * NTHR;
     Y[q] = {(TM)0, (TM)0};
-    if (i < NX) Y[q] = line[lds_pos(fft_pos<TM, NX>(makhoul_slot<NX>(i)))];
-  }
+    if (NX >= NTHR || i < NX) Y[q] = line[sl.template out<q>()];
+  });
   double* buf = reinterpret_cast<double*>(line);     // the line is no longer read
   lds_sync();
 #pragma unroll
@@ -971,7 +1032,11 @@ template <typename TM, int NX>
 __global__ void __launch_bounds__(line_threads(NX))
 k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, int ny) {
   constexpr int NTHR = line_threads(NX);
-  constexpr int CPT = (NX + NTHR - 1) / NTHR;
+  constexpr int CPT = NX >= NTHR ? NX / NTHR : 1;
+  constexpr int UPT = NX / 2 >= NTHR ? NX / 2 / NTHR : 1;
+  constexpr int R = fft_radix<TM>();
+  using MAP = LdsMap<TM, NX, SWZ_LINE>;
+  using LS = LineSlots<NX, NTHR, R, MAP>;
   __shared__ cpx<TM> line[NX];
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   const int tid = threadIdx.x;
@@ -979,22 +1044,24 @@ k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, 
   const size_t FS = (size_t)NX * ny;
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
-#pragma unroll
-  for (int q = 0; q < CPT; ++q) {
+  const LS sl(tid);
+  static_for<CPT>([&](auto iq) {
+    constexpr int q = decltype(iq)::value;
     const int i = tid + q * NTHR;
-    if (i < NX) line[lds_pos(makhoul_slot<NX>(i))] = {(TM)src[(size_t)j * NX + i], (TM)0};
-  }
+    if (NX >= NTHR || i < NX) line[sl.template mak<q>()] = {(TM)src[(size_t)j * NX + i], (TM)0};
+  });
   lds_sync();
-  fft_lines<TM, NX, 1, NTHR>(line, rt, tid);
-#pragma unroll
-  for (int q = 0; q < CPT; ++q) {
-    const int k = tid + q * NTHR;
-    if (k < NX) {
-      TM A, B;
-      dct2_post<TM, NX>(line, rt, k, A, B);
-      mid[(size_t)slot * FS + mid_index(k, j, ny)] = A;
+  fft_lines<TM, NX, 1, NTHR, R, MAP>(line, rt, tid);
+  static_for<UPT>([&](auto iq) {
+    constexpr int q = decltype(iq)::value;
+    const int u = tid + q * NTHR;
+    if (NX / 2 >= NTHR || u < NX / 2) {
+      TM A, B, Am, Bm;
+      dct2_unit<TM, NX>(line, sl.template bin<q>(), sl.template binm<q>(), rt, u, A, B, Am, Bm);
+      mid[(size_t)slot * FS + mid_index(u, j, ny)] = A;
+      mid[(size_t)slot * FS + mid_index(pair_mirror<NX>(u), j, ny)] = Am;
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------
