@@ -171,6 +171,20 @@ __device__ __forceinline__ double ptilde(const StepConst& c, double psi, double 
                 c.gamma_out * (1.0 - p) * (psi - c.psi_out));
 }
 
+// Value of lane i - 1 (lane_from_below) or lane i + 1 (lane_from_above) of the
+// wave, by DPP whole-wave shifts of both halves of the double; the end lanes
+// get their own value back.
+__device__ __forceinline__ double lane_from_below(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_from_above(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+}
+
 // P1a: the stencil terms of a band of rows. Each wave owns SW_OUT consecutive
 // output columns plus two halo columns on either side (64 lanes); walking down
 // the band, a lane keeps the rows above and below the current one in
@@ -216,13 +230,14 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
   const double k32 = 0.75 * 1.4142135623730950488;   // 3 sqrt(2) / 4
   const double half_pi = 1.5707963267948966192;
   const double ieps = 1.0 / c.eps;
-  // neighbour values along x; at the boundary the ghost is the cell itself
+  // neighbour values along x (adjacent lanes, by DPP wave shifts); at the
+  // boundary the ghost is the cell itself
   auto west = [&](double v) {
-    const double u = __shfl_up(v, 1, 64);
+    const double u = lane_from_below(v);
     return at_w ? v : u;
   };
   auto east = [&](double v) {
-    const double u = __shfl_down(v, 1, 64);
+    const double u = lane_from_above(v);
     return at_e ? v : u;
   };
   auto at = [&](int r) { return (size_t)min(max(r, 0), ny - 1) * nx + cl; };
@@ -235,21 +250,40 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
     double dq;                    // psi^n - psi^{n-1} (increment form)
     double dl, fl;                // lagged delta psi and phi* of the previous step
   };
-  auto load_row = [&](int r) {
-    Row w;
+  // State values of one row at this column, loaded ahead of their use.
+  struct Raw {
+    double phn, phm, psn, psm, psmm, phmm;
+  };
+  auto load_raw = [&](int r) {
+    Raw w;
     const size_t o = at(r);
     w.phn = a.phn[o];
     w.phm = a.phm[o];
     w.psn = a.psn[o];
     w.psm = a.psm[o];
+    if (c.lag_d) {
+      w.psmm = a.psmm[o];
+      w.phmm = a.phmm[o];
+    } else {
+      w.psmm = 0.0;
+      w.phmm = 0.0;
+    }
+    return w;
+  };
+  auto make_row = [&](const Raw& v) {
+    Row w;
+    w.phn = v.phn;
+    w.phm = v.phm;
+    w.psn = v.psn;
+    w.psm = v.psm;
     w.p = c.x0 * w.phn + c.x1 * w.phm;
     w.q = c.x0 * w.psn + c.x1 * w.psm;
     sincospi(0.5 * w.p, &w.sp, &w.cp);
     w.P = ptilde(c, w.q, w.sp);
     w.dq = w.psn - w.psm;
     if (c.lag_d) {
-      w.dl = w.psn - 2.0 * w.psm + a.psmm[o];
-      w.fl = 2.0 * w.phm - a.phmm[o];
+      w.dl = w.psn - 2.0 * w.psm + v.psmm;
+      w.fl = 2.0 * w.phm - v.phmm;
     } else {
       w.dl = 0.0;
       w.fl = 0.0;
@@ -265,21 +299,20 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
 #pragma unroll
   for (int q = 0; q < P1_NSUM; ++q) sums[q] = 0.0;
 
-  // window: rows j-1, j, j+1 (pointwise), phi^n of row j+2, Delta_h phi^n of rows j-1, j
-  Row rs = load_row(j0 - 1), rc = load_row(j0), rn = load_row(j0 + 1);
+  // Window: rows j-1, j, j+1 (pointwise), the raw state of row j+2, and
+  // Delta_h phi^n of rows j-1, j. The loop takes two rows per trip with two
+  // raw buffers, so that a row's loads are issued one to two rows before
+  // their use.
+  Row rs = make_row(load_raw(j0 - 1)), rc = make_row(load_raw(j0)), rn = make_row(load_raw(j0 + 1));
   double Ls = 0.0, Lc = 0.0;
   if constexpr (INC) {
     const double u2 = a.phn[at(j0 - 2)];
     Lc = lap_n(rc.phn, rn.phn, rs.phn);
     Ls = (j0 == 0) ? Lc : lap_n(rs.phn, rc.phn, u2);
   }
-#pragma unroll 1
-  for (int j = j0; j < j0 + iters; ++j) {
+  auto row_step = [&](int j, const Raw& r2) {
     double Ln = 0.0;
-    if constexpr (INC) {
-      const double u2 = a.phn[at(j + 2)];
-      Ln = (j + 1 >= ny) ? Lc : lap_n(rn.phn, u2, rc.phn);
-    }
+    if constexpr (INC) Ln = (j + 1 >= ny) ? Lc : lap_n(rn.phn, r2.phn, rc.phn);
     // neighbours along x of the current row
     const double pe = east(rc.p), pw = west(rc.p);
     const double qe = east(rc.q), qw = west(rc.q);
@@ -373,9 +406,17 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
     // advance the window
     rs = rc;
     rc = rn;
-    if (j + 1 < j0 + iters) rn = load_row(j + 2);
+    if (j + 1 < j0 + iters) rn = make_row(r2);
     Ls = Lc;
     Lc = Ln;
+  };
+  Raw ra = load_raw(j0 + 2);
+#pragma unroll 1
+  for (int j = j0; j < j0 + iters; j += 2) {
+    const Raw rb = load_raw(j + 3);
+    row_step(j, ra);
+    if (j + 2 < j0 + iters) ra = load_raw(j + 4);
+    row_step(j + 1, rb);
   }
   block_sum<P1_NSUM, STENCIL_THREADS>(sums, red, tid);
   if (tid < P1_NSUM) part[(size_t)blk * P1_NSUM + tid] = red[tid];
