@@ -607,20 +607,46 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   constexpr int GR = NY / NTHR >= 8 ? 8 : (NY / NTHR >= 4 ? 4 : 2);
   using MAP = LdsMap<TM, NY, SWZ_GRAM>;
   using LS = LineSlots<NY, NTHR, GR, MAP>;
-  // FP64 up to 4096: the S~ spectrum waits in LDS, H, Q~, K~ in registers;
-  // otherwise all four stay in registers.
-  constexpr bool S_LDS = sizeof(TM) == 8 && NY <= 4096;
+  // LDS plan: the line, the S~ spectrum (waiting for its products with the
+  // later fields) and, where they fit, per-thread partial sums that are
+  // reduced over the block once per strip instead of once per field.
+  constexpr int LINE_B = NY * (int)sizeof(cpx<TM>);
+  constexpr int ROOT_B = Roots<TM, NY>::SIZE * (int)sizeof(cpx<double>);
+  // The partial sums only go to LDS while the CU still holds 8 waves of
+  // workgroups.
+  constexpr int BUDGET = 150 * 1024;
+  constexpr int WAVES = NTHR / 64;
+  constexpr int ACC_BUDGET = WAVES >= 8 ? BUDGET : (160 * 1024) / (8 / WAVES);
+  constexpr bool S_LDS = 2 * LINE_B + ROOT_B <= BUDGET;
+  constexpr bool ACC_LDS =
+      (S_LDS ? 2 : 1) * LINE_B + ROOT_B + P2_NSUM * NTHR * (int)sizeof(double) <= ACC_BUDGET &&
+      NTHR % 16 == 0;
   __shared__ cpx<TM> line[NY];
   __shared__ cpx<TM> keep[S_LDS ? NY : 1];
   __shared__ cpx<double> rtab[Roots<TM, NY>::SIZE];
   __shared__ double red[8 * (NTHR / 64 + 1)];
-  __shared__ double acc[P2_NSUM];
+  __shared__ double acc[ACC_LDS ? P2_NSUM * NTHR : P2_NSUM];
   const int tid = threadIdx.x;
   const size_t FS = (size_t)nx * NY;
   Roots<TM, NY> rt;
   rt.init(rtab, tid, NTHR);
   const LS sl(tid);
-  if (tid < P2_NSUM) acc[tid] = 0.0;
+  if constexpr (ACC_LDS) {
+#pragma unroll
+    for (int q = 0; q < P2_NSUM; ++q) acc[q * NTHR + tid] = 0.0;
+  } else {
+    if (tid < P2_NSUM) acc[tid] = 0.0;
+  }
+  // Adds the thread's stage sums v[b] to sum idx[b].
+  auto accumulate = [&](auto& v, const auto& idx) {
+    constexpr int NV = sizeof(v) / sizeof(double);
+    if constexpr (ACC_LDS) {
+#pragma unroll
+      for (int b = 0; b < NV; ++b) acc[idx[b] * NTHR + tid] += v[b];
+    } else {
+      stage_accumulate<NV, NTHR>(v, idx, red, acc, tid);
+    }
+  };
   const double lx0 = lamx[2 * s], lx1 = lamx[2 * s + 1];
   auto strip = [&](int f) {
     return reinterpret_cast<gptr<const cpx<TM>>>(mid + (size_t)f * FS) + (size_t)s * NY;
@@ -630,7 +656,7 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
     const int u = tid + (j >> 1) * NTHR;
     return (j & 1) ? pair_mirror<NY>(u) : u;
   };
-  auto valid = [&](int) { return NY / 2 >= NTHR || tid < NY / 2; };
+  const bool valid = NY / 2 >= NTHR || tid < NY / 2;
   // 1/sigma (chi) or 1/tau (zeta) at (2s, k) and (2s+1, k)
   auto inv_op = [&](int k, bool chi, double& i0, double& i1) {
     const double ly = lamy[k];
@@ -656,12 +682,22 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
       b = kb[f][j];
     }
   };
-  // Fields in the order they are transformed.
+  // Fields in the order they are transformed. With FP32 lines the strip of
+  // the next field is loaded while the current one is transformed (FP64
+  // lines have no registers to spare for it).
   constexpr int ORDER[8] = {M_S, M_H, M_Q, M_K, M_F, M_P, M_G, M_L};
-
-  auto transform_next = [&](int i, TM (&A)[KPT], TM (&B)[KPT]) {
+  constexpr bool PREFETCH = sizeof(TM) == 4;
+  StripRegs<TM, LPT> nxt;
+  if constexpr (PREFETCH) fetch_strip<TM, NY, LPT, NTHR>(strip(ORDER[0]), tid, nxt);
+  auto transform_next = [&](auto ii, TM (&A)[KPT], TM (&B)[KPT]) {
+    constexpr int i = decltype(ii)::value;
     StripRegs<TM, LPT> cur;
-    fetch_strip<TM, NY, LPT, NTHR>(strip(ORDER[i]), tid, cur);
+    if constexpr (PREFETCH) {
+      cur = nxt;
+      if constexpr (i + 1 < 8) fetch_strip<TM, NY, LPT, NTHR>(strip(ORDER[i + 1]), tid, nxt);
+    } else {
+      fetch_strip<TM, NY, LPT, NTHR>(strip(ORDER[i]), tid, cur);
+    }
     column_dct2<TM, NY, LPT, UPT, NTHR, GR, MAP>(cur, line, rt, sl, tid, A, B);
   };
   constexpr int GIDX[4][4] = {{P2_SS, P2_SH, P2_SQ, P2_SK},
@@ -672,14 +708,14 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   auto chi_stage = [&](auto ia) {
     constexpr int a = decltype(ia)::value;
     TM A[KPT], B[KPT];
-    transform_next(a, A, B);
+    transform_next(ia, A, B);
     double v[a + 1];
     int idx[a + 1];
 #pragma unroll
     for (int b = 0; b <= a; ++b) { v[b] = 0.0; idx[b] = GIDX[b][a]; }
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
-      if (!valid(j)) continue;               // blocks wider than half the line
+      if (!valid) continue;                  // blocks wider than half the line
       double i0, i1;
       inv_op(bin_of(j), true, i0, i1);
 #pragma unroll
@@ -697,7 +733,7 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
       }
       __builtin_amdgcn_sched_barrier(0);
     }
-    stage_accumulate<a + 1, NTHR>(v, idx, red, acc, tid);
+    accumulate(v, idx);
   };
   chi_stage(std::integral_constant<int, 0>{});
   chi_stage(std::integral_constant<int, 1>{});
@@ -706,12 +742,12 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   // f_lin against the four kept spectra.
   {
     TM A[KPT], B[KPT];
-    transform_next(4, A, B);
+    transform_next(std::integral_constant<int, 4>{}, A, B);
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     const int idx[4] = {P2_FS, P2_FH, P2_FQ, P2_FK};
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
-      if (!valid(j)) continue;
+      if (!valid) continue;
       double i0, i1;
       inv_op(bin_of(j), true, i0, i1);
 #pragma unroll
@@ -721,29 +757,49 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
         v[b] += (double)A[j] * (double)ea * i0 + (double)B[j] * (double)eb * i1;
       }
     }
-    stage_accumulate<4, NTHR>(v, idx, red, acc, tid);
+    accumulate(v, idx);
   }
   // zeta group: P~ kept (in the H slot), then g_lin and L~.
-  {
-    transform_next(5, ka[1], kb[1]);
+  transform_next(std::integral_constant<int, 5>{}, ka[1], kb[1]);
+  auto zeta_stage = [&](auto ig) {
+    constexpr int g = decltype(ig)::value;
+    TM A[KPT], B[KPT];
+    transform_next(std::integral_constant<int, 6 + g>{}, A, B);
+    double v[1] = {0.0};
+    const int idx[1] = {g == 0 ? P2_PG : P2_PL};
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
-      TM A[KPT], B[KPT];
-      transform_next(6 + g, A, B);
-      double v[1] = {0.0};
-      const int idx[1] = {g == 0 ? P2_PG : P2_PL};
-#pragma unroll
-      for (int j = 0; j < KPT; ++j) {
-        if (!valid(j)) continue;
-        double i0, i1;
-        inv_op(bin_of(j), false, i0, i1);
-        v[0] += (double)A[j] * (double)ka[1][j] * i0 + (double)B[j] * (double)kb[1][j] * i1;
-      }
-      stage_accumulate<1, NTHR>(v, idx, red, acc, tid);
+    for (int j = 0; j < KPT; ++j) {
+      if (!valid) continue;
+      double i0, i1;
+      inv_op(bin_of(j), false, i0, i1);
+      v[0] += (double)A[j] * (double)ka[1][j] * i0 + (double)B[j] * (double)kb[1][j] * i1;
     }
+    accumulate(v, idx);
+  };
+  zeta_stage(std::integral_constant<int, 0>{});
+  zeta_stage(std::integral_constant<int, 1>{});
+  if constexpr (ACC_LDS) {
+    // Sum the per-thread partials: thread t adds 16 consecutive threads'
+    // values of sum t / (NTHR / 16) (in a rotated order that keeps the lanes
+    // on different banks), then 16 threads add the chunks.
+    constexpr int CH = NTHR / 16;
+    lds_sync();
+    const int q = tid / CH, ch = tid % CH;
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) t += acc[q * NTHR + 16 * ch + ((i + ch) & 15)];
+    lds_sync();
+    acc[q * NTHR + ch] = t;
+    lds_sync();
+    if (tid < P2_NSUM) {
+      double u = 0.0;
+      for (int i = 0; i < CH; ++i) u += acc[tid * NTHR + i];
+      part[(size_t)s * P2_NSUM + tid] = u;
+    }
+  } else {
+    lds_sync();
+    if (tid < P2_NSUM) part[(size_t)s * P2_NSUM + tid] = acc[tid];
   }
-  lds_sync();
-  if (tid < P2_NSUM) part[(size_t)s * P2_NSUM + tid] = acc[tid];
 }
 
 // ---------------------------------------------------------------------------
