@@ -139,8 +139,11 @@ Layout layout(const ccmsav_params* p) {
   size_t off = 0;
   L.state = off; off = align_up(off + 6 * cells * sizeof(double));
   L.rm = off;    off = align_up(off + M_NFIELD * cells * me);
-  L.mid = off;   off = align_up(off + M_NFIELD * cells * me);
-  L.outc = off;  off = align_up(off + 2 * cells * me);
+  // strip-major intermediates (padded strips; the DCT-as-GEMM variant uses
+  // the first nx ny values of each field slot in its own layout)
+  const size_t sf = strip_field(p->nx, p->ny, (int)me);
+  L.mid = off;   off = align_up(off + M_NFIELD * sf * me);
+  L.outc = off;  off = align_up(off + 2 * sf * me);
   L.part1 = off;
   off = align_up(off + (size_t)stencil_shape(p->nx, p->ny).blocks * P1_NSUM * sizeof(double));
   L.part2 = off; off = align_up(off + p2_rows(p) * P2_NSUM * sizeof(double));
@@ -1105,8 +1108,9 @@ int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, dou
   const Member& m = c->mem[0];
   // The row DCT-III writes both results; an output that is not requested goes
   // to intermediate slots 2-3, which the solve does not read.
+  const size_t me = mid_elem(c->precision);
   double* tmp = reinterpret_cast<double*>(static_cast<char*>(m.mid) +
-                                          2 * (size_t)m.p.nx * m.p.ny * mid_elem(c->precision));
+                                          2 * strip_field(m.p.nx, m.p.ny, (int)me) * me);
   MemberArgs& a = c->h_args[(size_t)kSolveTable * c->mem.size()];
   a.phi_new = to_global(out_chi ? out_chi : tmp);
   a.psi_new = to_global(out_zeta ? out_zeta : tmp);

@@ -181,6 +181,7 @@ __device__ __forceinline__ void dif_stage(cpx<T>* buf, const Roots<T, N>& rt, in
     const int base = MAP::at(first(tid));
 #pragma unroll
     for (int it = 0; it < ITERS; ++it) {
+      if (ITERS > 1) __builtin_amdgcn_sched_barrier(0);   // one butterfly's registers at a time
       const int e = base ^ MAP::at(first(it * NTHR));
       const int m = (tid + it * NTHR) & (S - 1);
       cpx<T> v[R];

@@ -119,6 +119,21 @@ struct RowArgs {
 
 // Everything the kernels of one step need about one grid (one member of an
 // ensemble), kept in device memory.
+// Strip-major intermediates: strip s (columns 2s, 2s + 1) of a field starts
+// strip_stride elements after strip s - 1. The pad beyond the 2 ny values of
+// a strip keeps consecutive strips off a power-of-two stride: the row passes
+// touch one short piece per strip, and at a stride of 2^k bytes those pieces
+// crowd into a few HBM channels (measured at N = 4096: the row DCT takes
+// 403 us unpadded, 336 us with this pad; pads of 256 or 4384 bytes are worse).
+constexpr int kStripPadBytes = 1056;
+__host__ __device__ constexpr size_t strip_stride(int ny, int esize) {
+  return 2 * (size_t)ny + (size_t)(kStripPadBytes / esize);
+}
+// Elements of one strip-major field of an nx x ny grid.
+__host__ __device__ constexpr size_t strip_field(int nx, int ny, int esize) {
+  return (size_t)(nx / 2) * strip_stride(ny, esize);
+}
+
 struct MemberArgs {
   gptr<const double> phn;        // phi^n, phi^{n-1}, phi^{n-2}
   gptr<const double> phm;

@@ -95,8 +95,9 @@ __device__ __forceinline__ int xcd_remap(int b, int g) {
   return (b & 7) * (g >> 3) + (b >> 3);
 }
 
-__device__ __forceinline__ size_t mid_index(int k, int j, int ny) {
-  return ((size_t)(k >> 1) * ny + j) * 2 + (k & 1);
+// Element (k, j) of a strip-major field with strip stride ss.
+__device__ __forceinline__ size_t mid_index(int k, int j, size_t ss) {
+  return (size_t)(k >> 1) * ss + 2 * (size_t)j + (k & 1);
 }
 
 // Sum NV doubles over the block in a fixed order; the totals land in red[0..NV).
@@ -463,7 +464,9 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   const int tid = threadIdx.x;
   const int j0 = blk * ROWS;
-  const size_t FS = (size_t)NX * ny;
+  const size_t FS = (size_t)NX * ny;                            // row-major fields
+  const size_t SS = strip_stride(ny, sizeof(TM));
+  const size_t FSM = strip_field(NX, ny, sizeof(TM));           // strip-major fields
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
 
@@ -521,9 +524,9 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
             dct2_bin<TM>(line[lo ^ pk1], line[lo ^ pm1], w1, S1, pa.v[2 * rr + 1],
                          pb.v[2 * rr + 1]);
           }
-          const size_t o = ((size_t)sp * ny + j0) * 2;
-          store_piece<TM, ROWS>(mid + PAIR_A[pr] * FS + o, pa);
-          store_piece<TM, ROWS>(mid + PAIR_B[pr] * FS + o, pb);
+          const size_t o = (size_t)sp * SS + 2 * (size_t)j0;
+          store_piece<TM, ROWS>(mid + PAIR_A[pr] * FSM + o, pa);
+          store_piece<TM, ROWS>(mid + PAIR_B[pr] * FSM + o, pb);
         }
       }
     }
@@ -627,7 +630,8 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   __shared__ double red[8 * (NTHR / 64 + 1)];
   __shared__ double acc[ACC_LDS ? P2_NSUM * NTHR : P2_NSUM];
   const int tid = threadIdx.x;
-  const size_t FS = (size_t)nx * NY;
+  const size_t SS = strip_stride(NY, sizeof(TM));
+  const size_t FSM = strip_field(nx, NY, sizeof(TM));
   Roots<TM, NY> rt;
   rt.init(rtab, tid, NTHR);
   const LS sl(tid);
@@ -649,7 +653,7 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   };
   const double lx0 = lamx[2 * s], lx1 = lamx[2 * s + 1];
   auto strip = [&](int f) {
-    return reinterpret_cast<gptr<const cpx<TM>>>(mid + (size_t)f * FS) + (size_t)s * NY;
+    return reinterpret_cast<gptr<const cpx<TM>>>(mid + (size_t)f * FSM + (size_t)s * SS);
   };
   // bin held at index j (unit tid + (j / 2) NTHR; even j: the unit's own bin)
   auto bin_of = [&](int j) {
@@ -952,7 +956,8 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
   const int nstrip = nx / 2;
   const int s = lin % nstrip;
   const int grp = lin / nstrip;            // 0: chi (Allen-Cahn), 1: zeta (Cahn-Hilliard)
-  const size_t FS = (size_t)nx * NY;
+  const size_t SS = strip_stride(NY, sizeof(TM));
+  const size_t FSM = strip_field(nx, NY, sizeof(TM));
   Roots<TM, NY> rt;
   rt.init(rtab, tid, NTHR);
   const LS sl(tid);
@@ -968,7 +973,7 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
       double ur = 0.0, ui = 0.0;
       for (int f = 0; f < nf; ++f) {
         const cpx<TM> v = gload<TM>(reinterpret_cast<gptr<const cpx<TM>>>(
-                                        mid + (size_t)(base + f) * FS) + (size_t)s * NY + jj);
+                                        mid + (size_t)(base + f) * FSM + (size_t)s * SS) + jj);
         ur += cf[f] * (double)v.re;
         ui += cf[f] * (double)v.im;
       }
@@ -1012,7 +1017,7 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
   });
   lds_sync();
   fft_lines<TM, NY, 1, NTHR, R, MAP>(line, rt, tid);
-  const auto dst = reinterpret_cast<gptr<cpx<TM>>>(out + (size_t)grp * FS) + (size_t)s * NY;
+  const auto dst = reinterpret_cast<gptr<cpx<TM>>>(out + (size_t)grp * FSM + (size_t)s * SS);
   TM y0[LPT];
   static_for<LPT>([&](auto iq) {
     constexpr int q = decltype(iq)::value;
@@ -1063,7 +1068,8 @@ __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
   __shared__ cpx<TM> line[NX];
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   const int tid = threadIdx.x;
-  const size_t FS = (size_t)NX * ny;
+  const size_t SS = strip_stride(ny, sizeof(TM));
+  const size_t FSM = strip_field(NX, ny, sizeof(TM));
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
   const LS sl(tid);
@@ -1072,9 +1078,9 @@ __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
     constexpr int q = decltype(iq)::value;
     const int u = tid + q * NTHR;
     if (NX / 2 >= NTHR || u < NX / 2) {
-      const size_t ok = mid_index(u, j, ny), om = mid_index(pair_mirror<NX>(u), j, ny);
+      const size_t ok = mid_index(u, j, SS), om = mid_index(pair_mirror<NX>(u), j, SS);
       cpx<TM> Z, Zm;
-      dct3_pair<TM, NX>(rt, u, out[ok], out[om], out[FS + ok], out[FS + om], Z, Zm);
+      dct3_pair<TM, NX>(rt, u, out[ok], out[om], out[FSM + ok], out[FSM + om], Z, Zm);
       line[sl.template nat<q>()] = Z;
       line[sl.template natm<q>()] = Zm;
     }
@@ -1138,7 +1144,8 @@ k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, 
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   const int tid = threadIdx.x;
   const int j = xcd_remap(blockIdx.x, gridDim.x);
-  const size_t FS = (size_t)NX * ny;
+  const size_t SS = strip_stride(ny, sizeof(TM));
+  const size_t FSM = strip_field(NX, ny, sizeof(TM));
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
   const LS sl(tid);
@@ -1155,8 +1162,8 @@ k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, 
     if (NX / 2 >= NTHR || u < NX / 2) {
       TM A, B, Am, Bm;
       dct2_unit<TM, NX>(line, sl.template bin<q>(), sl.template binm<q>(), rt, u, A, B, Am, Bm);
-      mid[(size_t)slot * FS + mid_index(u, j, ny)] = A;
-      mid[(size_t)slot * FS + mid_index(pair_mirror<NX>(u), j, ny)] = Am;
+      mid[(size_t)slot * FSM + mid_index(u, j, SS)] = A;
+      mid[(size_t)slot * FSM + mid_index(pair_mirror<NX>(u), j, SS)] = Am;
     }
   });
 }
