@@ -86,6 +86,10 @@ def p1_pairs_v(esz, n, v):
     return 4 if per >= 4 else (2 if per >= 2 else 1)
 
 
+def row_dct_threads(n, v):
+    return line_threads(n)
+
+
 # ---- FFT index rules (mirror fft.hpp) ----------------------------------------
 def ilog2(n):
     return n.bit_length() - 1
@@ -192,21 +196,30 @@ def patterns(esz, n, cls):
     rec = Rec(esz)
     radix = fft_radix(esz)
     if cls == "SWZ_ROW":
-        nthr = line_threads(n)
         for v in (0, 1):
+            nthr = row_dct_threads(n, v)
             nl = p1_rows_v(esz, n, v) * p1_pairs_v(esz, n, v)
             for ln in range(nl):
                 rec_makhoul(rec, n, nthr, ln)
             rec_fft(rec, n, nl, nthr, radix)
+            rows = p1_rows_v(esz, n, v)
+            npairs = nl // rows
+            halves = 2 if rows >= 2 else 1
+            rh = rows // halves
+            spl = nthr // halves
             for w in lanes(nthr):
-                for s0 in range(0, n // 2, nthr):
-                    sps = [s0 + t if s0 + t < n // 2 else None for t in w]
-                    for ln in range(nl):
-                        for kk in (0, 1):
-                            ks = [None if s is None else 2 * s + kk for s in sps]
-                            rec.wave([None if k is None else ln * n + digit_rev(k, n, radix) for k in ks])
-                            rec.wave([None if k is None else ln * n + digit_rev((n - k) % n, n, radix)
-                                      for k in ks])
+                for s0 in range(0, n // 2, spl):
+                    sps = [s0 + t // halves if s0 + t // halves < n // 2 else None for t in w]
+                    hs = [t % halves for t in w]
+                    for l in range(npairs):
+                        for q in range(rh):
+                            lns = [(h * rh + q) * npairs + l for h in hs]
+                            for kk in (0, 1):
+                                ks = [None if sp is None else 2 * sp + kk for sp in sps]
+                                rec.wave([None if k is None else ln * n + digit_rev(k, n, radix)
+                                          for k, ln in zip(ks, lns)])
+                                rec.wave([None if k is None else ln * n + digit_rev((n - k) % n, n, radix)
+                                          for k, ln in zip(ks, lns)])
     elif cls == "SWZ_LINE":
         for nthr in sorted({line_threads(n), one_line_threads(esz, n)}):
             # column solve

@@ -439,13 +439,27 @@ template <typename T> __device__ __forceinline__ void gstore(gptr<cpx<T>> p, cpx
   p->im = v.im;
 }
 
-// Store a piece as pairs (one 8- or 16-byte write each; the piece is aligned).
+// Store a piece (aligned to its size) with 16-byte writes, or with one pair
+// write per row when it is shorter.
 template <typename TM, int ROWS>
 __device__ __forceinline__ void store_piece(gptr<TM> dst, const RowPiece<TM, ROWS>& p) {
-  typedef TM pair_t __attribute__((ext_vector_type(2)));
-  const auto d = reinterpret_cast<gptr<pair_t>>(dst);
+  constexpr int V = 16 / (int)sizeof(TM);
+  if constexpr (2 * ROWS >= V) {
+    typedef TM vec_t __attribute__((ext_vector_type(V)));
+    const auto d = reinterpret_cast<gptr<vec_t>>(dst);
 #pragma unroll
-  for (int r = 0; r < ROWS; ++r) d[r] = pair_t{p.v[2 * r], p.v[2 * r + 1]};
+    for (int c = 0; c < 2 * ROWS / V; ++c) {
+      vec_t v;
+#pragma unroll
+      for (int e = 0; e < V; ++e) v[e] = p.v[c * V + e];
+      d[c] = v;
+    }
+  } else {
+    typedef TM pair_t __attribute__((ext_vector_type(2)));
+    const auto d = reinterpret_cast<gptr<pair_t>>(dst);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) d[r] = pair_t{p.v[2 * r], p.v[2 * r + 1]};
+  }
 }
 
 // P1b: orthonormal DCT-II along x of the eight row-major fields, for a band
@@ -474,12 +488,21 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
   constexpr int R = fft_radix<TM>();
   using LS = LineSlots<NX, NTHR, R, MAP>;
   constexpr int CPT = NX >= NTHR ? NX / NTHR : 1;            // loads per thread and line
-  constexpr int SPT = NX / 2 >= NTHR ? NX / 2 / NTHR : 1;    // column pairs per thread
+  // Post-processing: HALVES lanes share the rows of one column pair sp, so
+  // that the ROWS x 2 values of a field leave as one 32-byte sector written
+  // by adjacent lanes in the same store instruction (lane h of the pair takes
+  // rows h RH .. h RH + RH - 1).
+  constexpr int HALVES = ROWS >= 2 ? 2 : 1;
+  constexpr int RH = ROWS / HALVES;
+  constexpr int SPL = NTHR / HALVES;                         // column pairs per pass
+  constexpr int SPT = NX / 2 >= SPL ? NX / 2 / SPL : 1;      // passes
   const LS sl(tid);
-  // Post-processing slots of bins 2 sp and 2 sp + 1 and of their mirrors
-  // N - 2 sp = (N - 1) ^ (2 (sp - 1) + 1) and N - 2 sp - 1 = (N - 1) ^ 2 sp.
-  const int g2 = LS::g(2 * tid);
-  const int g2m = MAP::at(NX - 1) ^ LS::g(1) ^ LS::g((2 * tid - 2) & (NX - 1));
+  const int spt = tid / HALVES, half = tid % HALVES;
+  // Slots of bins 2 sp and 2 sp + 1 and of their mirrors
+  // N - 2 sp = (N - 1) ^ (2 (sp - 1) + 1) and N - 2 sp - 1 = (N - 1) ^ 2 sp,
+  // for sp = spt + it SPL (2 sp = 2 spt + it 2 SPL, disjoint bits).
+  const int g2 = LS::g(2 * spt);
+  const int g2m = MAP::at(NX - 1) ^ LS::g(1) ^ LS::g((2 * spt - 2) & (NX - 1));
   const TM S0 = (TM)(0.5 * sqrt(1.0 / NX)), S1 = (TM)(0.5 * sqrt(2.0 / NX));
 
   auto round = [&](auto ir) {
@@ -503,30 +526,31 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
     fft_lines<TM, NX, ROWS * NP, NTHR, R, MAP>(line, rt, tid);
 #pragma unroll 1
     for (int it = 0; it < SPT; ++it) {
-      const int sp = tid + it * NTHR;
-      if (NX / 2 >= NTHR || sp < NX / 2) {
-        const int pk0 = g2 ^ LS::g(2 * it * NTHR);
+      const int sp = spt + it * SPL;
+      if (NX / 2 >= SPL || sp < NX / 2) {
+        const int pk0 = g2 ^ LS::g(2 * it * SPL);
         const int pk1 = pk0 ^ LS::g(1);
         const int pm1 = pk0 ^ MAP::at(NX - 1);
-        const int pm0 = tid == 0 ? (it == 0 ? 0 : (MAP::at(NX - 1) ^ LS::g(1) ^
-                                                   LS::g((2 * it * NTHR - 2) & (NX - 1))))
-                                 : (g2m ^ LS::g(2 * it * NTHR));
+        const int pm0 = spt == 0 ? (it == 0 ? 0 : (MAP::at(NX - 1) ^ LS::g(1) ^
+                                                   LS::g((2 * it * SPL - 2) & (NX - 1))))
+                                 : (g2m ^ LS::g(2 * it * SPL));
         const cpx<TM> w0 = rt.omega(2 * sp), w1 = rt.omega(2 * sp + 1);
         const TM s0 = sp == 0 ? S0 : S1;
 #pragma unroll
         for (int l = 0; l < NP; ++l) {
           const int pr = r * NP + l;
-          RowPiece<TM, ROWS> pa, pb;
+          RowPiece<TM, RH> pa, pb;
 #pragma unroll
-          for (int rr = 0; rr < ROWS; ++rr) {
+          for (int q = 0; q < RH; ++q) {
+            const int rr = half * RH + q;
             const int lo = MAP::at((rr * NP + l) * NX);
-            dct2_bin<TM>(line[lo ^ pk0], line[lo ^ pm0], w0, s0, pa.v[2 * rr], pb.v[2 * rr]);
-            dct2_bin<TM>(line[lo ^ pk1], line[lo ^ pm1], w1, S1, pa.v[2 * rr + 1],
-                         pb.v[2 * rr + 1]);
+            dct2_bin<TM>(line[lo ^ pk0], line[lo ^ pm0], w0, s0, pa.v[2 * q], pb.v[2 * q]);
+            dct2_bin<TM>(line[lo ^ pk1], line[lo ^ pm1], w1, S1, pa.v[2 * q + 1],
+                         pb.v[2 * q + 1]);
           }
-          const size_t o = (size_t)sp * SS + 2 * (size_t)j0;
-          store_piece<TM, ROWS>(mid + PAIR_A[pr] * FSM + o, pa);
-          store_piece<TM, ROWS>(mid + PAIR_B[pr] * FSM + o, pb);
+          const size_t o = (size_t)sp * SS + 2 * (size_t)(j0 + half * RH);
+          store_piece<TM, RH>(mid + PAIR_A[pr] * FSM + o, pa);
+          store_piece<TM, RH>(mid + PAIR_B[pr] * FSM + o, pb);
         }
       }
     }

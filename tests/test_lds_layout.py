@@ -116,7 +116,7 @@ def test_line_slots_match_direct_definitions(esz):
         for cls, nthrs, rad in (
                 ("SWZ_LINE", {G.line_threads(n), G.one_line_threads(esz, n)}, radix),
                 ("SWZ_GRAM", {G.gram_threads(n)}, G.gram_radix(n)),
-                ("SWZ_ROW", {G.line_threads(n)}, radix)):
+                ("SWZ_ROW", {G.row_dct_threads(n, 0), G.row_dct_threads(n, 1)}, radix)):
             at = mapper(esz, n, cls)
             for nthr in nthrs:
                 for key, (fast, direct) in line_slots(n, nthr, rad, at).items():
@@ -125,29 +125,34 @@ def test_line_slots_match_direct_definitions(esz):
 
 @pytest.mark.parametrize("esz", [8, 16])
 def test_row_dct_post_slots(esz):
-    """Slots of bins 2 sp, 2 sp + 1 and their mirrors in the row DCT."""
+    """Slots of bins 2 sp, 2 sp + 1 and their mirrors in the row DCT, where
+    HALVES adjacent lanes share column pair sp = t / HALVES + it NTHR / HALVES."""
     radix = G.fft_radix(esz)
     for n in G.SIZES:
         at = mapper(esz, n, "SWZ_ROW")
-        nthr = G.line_threads(n)
 
         def g(k):
             return at(G.digit_rev(k, n, radix))
-        spt = n // 2 // nthr if n // 2 >= nthr else 1
-        for tid in range(nthr):
-            g2 = g(2 * tid)
-            g2m = at(n - 1) ^ g(1) ^ g((2 * tid - 2) & (n - 1))
-            for it in range(spt):
-                sp = tid + it * nthr
-                if sp >= n // 2:
-                    continue
-                c0 = 0 if it == 0 else at(n - 1) ^ g(1) ^ g((2 * it * nthr - 2) & (n - 1))
-                pk0 = g2 ^ g(2 * it * nthr)
-                pk1 = pk0 ^ g(1)
-                pm1 = pk0 ^ at(n - 1)
-                pm0 = c0 if tid == 0 else g2m ^ g(2 * it * nthr)
-                assert pk0 == g(2 * sp) and pk1 == g(2 * sp + 1)
-                assert pm0 == g((n - 2 * sp) % n) and pm1 == g(n - 2 * sp - 1)
+        for v in (0, 1):
+            nthr = G.row_dct_threads(n, v)
+            halves = 2 if G.p1_rows_v(esz, n, v) >= 2 else 1
+            spl = nthr // halves
+            spt_n = n // 2 // spl if n // 2 >= spl else 1
+            for tid in range(nthr):
+                spt = tid // halves
+                g2 = g(2 * spt)
+                g2m = at(n - 1) ^ g(1) ^ g((2 * spt - 2) & (n - 1))
+                for it in range(spt_n):
+                    sp = spt + it * spl
+                    if sp >= n // 2:
+                        continue
+                    c0 = 0 if it == 0 else at(n - 1) ^ g(1) ^ g((2 * it * spl - 2) & (n - 1))
+                    pk0 = g2 ^ g(2 * it * spl)
+                    pk1 = pk0 ^ g(1)
+                    pm1 = pk0 ^ at(n - 1)
+                    pm0 = c0 if spt == 0 else g2m ^ g(2 * it * spl)
+                    assert pk0 == g(2 * sp) and pk1 == g(2 * sp + 1)
+                    assert pm0 == g((n - 2 * sp) % n) and pm1 == g(n - 2 * sp - 1)
 
 
 @pytest.mark.parametrize("esz", [8, 16])
@@ -160,7 +165,7 @@ def test_fft_stage_slots(esz):
         cases.append(("SWZ_GRAM", 1, G.gram_threads(n), G.gram_radix(n)))
         for v in (0, 1):
             cases.append(("SWZ_ROW", G.p1_rows_v(esz, n, v) * G.p1_pairs_v(esz, n, v),
-                          G.line_threads(n), radix))
+                          G.row_dct_threads(n, v), radix))
         for cls, nl, nthr, rad in cases:
             at = mapper(esz, n, cls)
             length = n
