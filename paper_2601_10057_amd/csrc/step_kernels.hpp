@@ -301,8 +301,8 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
   for (int q = 0; q < P1_NSUM; ++q) sums[q] = 0.0;
 
   // Window: rows j-1, j, j+1 (pointwise), the raw state of row j+2, and
-  // Delta_h phi^n of rows j-1, j. The loop takes two rows per trip with two
-  // raw buffers, so that a row's loads are issued one to two rows before
+  // Delta_h phi^n of rows j-1, j. The loop takes four rows per trip with
+  // rotating raw buffers, so that a row's loads are issued two rows before
   // their use.
   Row rs = make_row(load_raw(j0 - 1)), rc = make_row(load_raw(j0)), rn = make_row(load_raw(j0 + 1));
   double Ls = 0.0, Lc = 0.0;
@@ -411,13 +411,17 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
     Ls = Lc;
     Lc = Ln;
   };
-  Raw ra = load_raw(j0 + 2);
+  Raw r0 = load_raw(j0 + 2), r1 = load_raw(j0 + 3);
 #pragma unroll 1
-  for (int j = j0; j < j0 + iters; j += 2) {
-    const Raw rb = load_raw(j + 3);
-    row_step(j, ra);
-    if (j + 2 < j0 + iters) ra = load_raw(j + 4);
-    row_step(j + 1, rb);
+  for (int j = j0; j < j0 + iters; j += 4) {
+    const Raw r2 = load_raw(j + 4);
+    row_step(j, r0);
+    const Raw r3 = load_raw(j + 5);
+    row_step(j + 1, r1);
+    if (j + 4 < j0 + iters) r0 = load_raw(j + 6);
+    row_step(j + 2, r2);
+    if (j + 4 < j0 + iters) r1 = load_raw(j + 7);
+    row_step(j + 3, r3);
   }
   block_sum<P1_NSUM, STENCIL_THREADS>(sums, red, tid);
   if (tid < P1_NSUM) part[(size_t)blk * P1_NSUM + tid] = red[tid];
@@ -989,21 +993,44 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
   const int nf = grp == 0 ? nchi : nzeta;
   const auto cf = coef + (grp == 0 ? 0 : 5);
 
-  // combine the x-transformed right-hand sides of this group
-  static_for<LPT>([&](auto iq) {
-    constexpr int q = decltype(iq)::value;
-    const int jj = tid + q * NTHR;
-    if (NY >= NTHR || jj < NY) {
-      double ur = 0.0, ui = 0.0;
-      for (int f = 0; f < nf; ++f) {
-        const cpx<TM> v = gload<TM>(reinterpret_cast<gptr<const cpx<TM>>>(
-                                        mid + (size_t)(base + f) * FSM + (size_t)s * SS) + jj);
-        ur += cf[f] * (double)v.re;
-        ui += cf[f] * (double)v.im;
+  // Combine the x-transformed right-hand sides of this group: field by field,
+  // all of a field's loads in flight together (the number of fields is a
+  // compile-time constant for the step's groups: 5 for chi, 2 for zeta, and
+  // 1 in a standalone solve).
+  auto combine = [&](auto inf) {
+    constexpr int NF = decltype(inf)::value;
+    double ur[LPT], ui[LPT];
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) { ur[q] = 0.0; ui[q] = 0.0; }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const double w = cf[f];
+      const auto src = reinterpret_cast<gptr<const cpx<TM>>>(mid + (size_t)(base + f) * FSM +
+                                                            (size_t)s * SS);
+      cpx<TM> v[LPT];
+#pragma unroll
+      for (int q = 0; q < LPT; ++q) {
+        const int jj = tid + q * NTHR;
+        v[q] = (NY >= NTHR || jj < NY) ? gload<TM>(src + jj) : cpx<TM>{(TM)0, (TM)0};
       }
-      line[sl.template mak<q>()] = {(TM)ur, (TM)ui};
+#pragma unroll
+      for (int q = 0; q < LPT; ++q) {
+        ur[q] += w * (double)v[q].re;
+        ui[q] += w * (double)v[q].im;
+      }
     }
-  });
+    static_for<LPT>([&](auto iq) {
+      constexpr int q = decltype(iq)::value;
+      if (NY >= NTHR || tid + q * NTHR < NY) line[sl.template mak<q>()] = {(TM)ur[q], (TM)ui[q]};
+    });
+  };
+  if (nf == 5) {
+    combine(std::integral_constant<int, 5>{});
+  } else if (nf == 2) {
+    combine(std::integral_constant<int, 2>{});
+  } else {
+    combine(std::integral_constant<int, 1>{});
+  }
   lds_sync();
   fft_lines<TM, NY, 1, NTHR, R, MAP>(line, rt, tid);
   // Per pair unit: DCT-II post-processing of both bins, divide by the operator
