@@ -1245,12 +1245,23 @@ __device__ __forceinline__ const MemberArgs& batch_member(const MemberArgs* __re
   return tab[idx[b / per]];
 }
 
+// The stencil pass runs as a resident grid: workgroup b takes virtual blocks
+// (bands) vb until all `total` are done, each XCD working through a
+// contiguous range of them, so that no half-empty last wave of workgroups is
+// left on the chip.
 template <typename TM>
-__global__ void __launch_bounds__(STENCIL_THREADS) k_stencil(BATCH_PARAMS) {
-  int blk;
-  const MemberArgs& m = batch_member(tab, idx, per, blk);
-  const RowArgs a{m.phn, m.phm, m.phmm, m.psn, m.psm, m.psmm};
-  stencil_body<TM>(a, static_cast<gptr<TM>>(m.rm), m.part1, m.nx, m.ny, m.iters, m.k, blk);
+__global__ void __launch_bounds__(STENCIL_THREADS) k_stencil(BATCH_PARAMS, int total) {
+  const int g = gridDim.x, b = blockIdx.x;
+  const bool xcd = (g & 7) == 0 && (total & 7) == 0;
+  const int first = xcd ? (b & 7) * (total >> 3) + (b >> 3) : b;
+  const int last = xcd ? (b & 7) * (total >> 3) + (total >> 3) : total;
+  const int step = xcd ? g >> 3 : g;
+  for (int vb = first; vb < last; vb += step) {
+    const int blk = vb % per;
+    const MemberArgs& m = tab[idx[vb / per]];
+    const RowArgs a{m.phn, m.phm, m.phmm, m.psn, m.psm, m.psmm};
+    stencil_body<TM>(a, static_cast<gptr<TM>>(m.rm), m.part1, m.nx, m.ny, m.iters, m.k, blk);
+  }
 }
 
 template <typename TM, int NX, int V>
