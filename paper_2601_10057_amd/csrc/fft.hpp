@@ -147,17 +147,39 @@ template <typename T, int N, int CLS> struct LdsMap {
   }
 };
 
-// Multiplies v[q] by w^q, q = 1..R-1, for w = exp(-2 pi i t / N): one table
-// lookup, then the powers by a running FP64 product (relative error about
-// R ulp of FP64), each rounded to T.
+// Multiplies v[q] by w^q, q = 1..R-1, for w = exp(-2 pi i t / N), from one
+// table lookup. FP64 lines: the powers by a running FP64 product (relative
+// error about R ulp of FP64). FP32 lines: w^(2^b) by repeated FP64 squaring,
+// each rounded once to FP32, and the other powers as FP32 products
+// w^q = w^(q - 2^b) w^(2^b) over the lowest set bit 2^b of q (at most
+// log2 R - 1 FP32 roundings per power; the transform error grows by about a
+// quarter against twiddles rounded once from FP64).
 template <typename T, int N, int R>
 __device__ __forceinline__ void apply_twiddles(const Roots<T, N>& rt, int t, cpx<T>* v) {
   const cpx<double> w1 = rt.tw64(t);
-  cpx<double> w = w1;
+  if constexpr (sizeof(T) == 4) {
+    constexpr int LR = ilog2(R);
+    cpx<T> p2[LR > 0 ? LR : 1];          // w^(2^b)
+    cpx<double> w = w1;
 #pragma unroll
-  for (int q = 1; q < R; ++q) {
-    v[q] = cmul(v[q], cpx<T>{(T)w.re, (T)w.im});
-    if (q + 1 < R) w = cmul(w, w1);
+    for (int b = 0; b < LR; ++b) {
+      p2[b] = {(T)w.re, (T)w.im};
+      if (b + 1 < LR) w = {w.re * w.re - w.im * w.im, 2.0 * w.re * w.im};
+    }
+    cpx<T> pw[R];
+#pragma unroll
+    for (int q = 1; q < R; ++q) {
+      const int lb = q & -q;
+      pw[q] = (q == lb) ? p2[ilog2(lb)] : cmul(pw[q - lb], p2[ilog2(lb)]);
+      v[q] = cmul(v[q], pw[q]);
+    }
+  } else {
+    cpx<double> w = w1;
+#pragma unroll
+    for (int q = 1; q < R; ++q) {
+      v[q] = cmul(v[q], cpx<T>{(T)w.re, (T)w.im});
+      if (q + 1 < R) w = cmul(w, w1);
+    }
   }
 }
 
