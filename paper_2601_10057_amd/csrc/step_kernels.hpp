@@ -655,7 +655,7 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   __shared__ cpx<TM> line[NY];
   __shared__ cpx<TM> keep[S_LDS ? NY : 1];
   __shared__ cpx<double> rtab[Roots<TM, NY>::SIZE];
-  __shared__ double red[8 * (NTHR / 64 + 1)];
+  __shared__ double red[P2_NSUM * (NTHR / 64 + 1)];
   __shared__ double acc[ACC_LDS ? P2_NSUM * NTHR : P2_NSUM];
   const int tid = threadIdx.x;
   const size_t SS = strip_stride(NY, sizeof(TM));
@@ -732,84 +732,86 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
     }
     column_dct2<TM, NY, LPT, UPT, NTHR, GR, MAP>(cur, line, rt, sl, tid, A, B);
   };
-  constexpr int GIDX[4][4] = {{P2_SS, P2_SH, P2_SQ, P2_SK},
-                              {P2_SH, P2_HH, P2_HQ, P2_HK},
-                              {P2_SQ, P2_HQ, P2_QQ, P2_QK},
-                              {P2_SK, P2_HK, P2_QK, P2_KK}};
-  // chi group: S~, H, Q~, K~ in turn, each multiplied with the earlier ones.
-  auto chi_stage = [&](auto ia) {
+  // chi group: S~, H, Q~, K~ transformed and kept; their inner products are
+  // taken together with those of f_lin, bin by bin, so that each bin's
+  // weights 1/sigma are formed once.
+  auto keep_stage = [&](auto ia) {
     constexpr int a = decltype(ia)::value;
     TM A[KPT], B[KPT];
     transform_next(ia, A, B);
-    double v[a + 1];
-    int idx[a + 1];
 #pragma unroll
-    for (int b = 0; b <= a; ++b) { v[b] = 0.0; idx[b] = GIDX[b][a]; }
+    for (int j = 0; j < KPT; ++j) {
+      if (S_LDS && a == 0) {
+        if (valid) keep[tid + j * KS] = {A[j], B[j]};
+      } else {
+        ka[a][j] = A[j];
+        kb[a][j] = B[j];
+      }
+    }
+  };
+  keep_stage(std::integral_constant<int, 0>{});
+  keep_stage(std::integral_constant<int, 1>{});
+  keep_stage(std::integral_constant<int, 2>{});
+  keep_stage(std::integral_constant<int, 3>{});
+  {
+    TM A[KPT], B[KPT];
+    transform_next(std::integral_constant<int, 4>{}, A, B);
+    // pairs (x, y) of {S~, H, Q~, K~, f_lin} = indices 0..4
+    constexpr int NPR = 14;
+    constexpr int PX[NPR] = {0, 0, 0, 0, 1, 1, 1, 2, 2, 3, 4, 4, 4, 4};
+    constexpr int PY[NPR] = {0, 1, 2, 3, 1, 2, 3, 2, 3, 3, 0, 1, 2, 3};
+    const int idx[NPR] = {P2_SS, P2_SH, P2_SQ, P2_SK, P2_HH, P2_HQ, P2_HK,
+                          P2_QQ, P2_QK, P2_KK, P2_FS, P2_FH, P2_FQ, P2_FK};
+    double v[NPR];
+#pragma unroll
+    for (int q = 0; q < NPR; ++q) v[q] = 0.0;
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       if (!valid) continue;                  // blocks wider than half the line
       double i0, i1;
       inv_op(bin_of(j), true, i0, i1);
+      double xa[5], xb[5];
 #pragma unroll
-      for (int b = 0; b < a; ++b) {
+      for (int f = 0; f < 4; ++f) {
         TM ea, eb;
-        kept(b, j, ea, eb);
-        v[b] += (double)A[j] * (double)ea * i0 + (double)B[j] * (double)eb * i1;
+        kept(f, j, ea, eb);
+        xa[f] = (double)ea;
+        xb[f] = (double)eb;
       }
-      v[a] += (double)A[j] * (double)A[j] * i0 + (double)B[j] * (double)B[j] * i1;
-      if (S_LDS && a == 0) {
-        keep[tid + j * KS] = {A[j], B[j]};
-      } else {
-        ka[a][j] = A[j];
-        kb[a][j] = B[j];
+      xa[4] = (double)A[j];
+      xb[4] = (double)B[j];
+      double wa[5], wb[5];
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        wa[f] = xa[f] * i0;
+        wb[f] = xb[f] * i1;
       }
+#pragma unroll
+      for (int q = 0; q < NPR; ++q) v[q] += wa[PX[q]] * xa[PY[q]] + wb[PX[q]] * xb[PY[q]];
       __builtin_amdgcn_sched_barrier(0);
     }
     accumulate(v, idx);
-  };
-  chi_stage(std::integral_constant<int, 0>{});
-  chi_stage(std::integral_constant<int, 1>{});
-  chi_stage(std::integral_constant<int, 2>{});
-  chi_stage(std::integral_constant<int, 3>{});
-  // f_lin against the four kept spectra.
+  }
+  // zeta group: P~ and g_lin kept (in the H and Q~ slots), then L~; both
+  // inner products with one weight per bin.
+  transform_next(std::integral_constant<int, 5>{}, ka[1], kb[1]);
+  transform_next(std::integral_constant<int, 6>{}, ka[2], kb[2]);
   {
     TM A[KPT], B[KPT];
-    transform_next(std::integral_constant<int, 4>{}, A, B);
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    const int idx[4] = {P2_FS, P2_FH, P2_FQ, P2_FK};
-#pragma unroll
-    for (int j = 0; j < KPT; ++j) {
-      if (!valid) continue;
-      double i0, i1;
-      inv_op(bin_of(j), true, i0, i1);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        TM ea, eb;
-        kept(b, j, ea, eb);
-        v[b] += (double)A[j] * (double)ea * i0 + (double)B[j] * (double)eb * i1;
-      }
-    }
-    accumulate(v, idx);
-  }
-  // zeta group: P~ kept (in the H slot), then g_lin and L~.
-  transform_next(std::integral_constant<int, 5>{}, ka[1], kb[1]);
-  auto zeta_stage = [&](auto ig) {
-    constexpr int g = decltype(ig)::value;
-    TM A[KPT], B[KPT];
-    transform_next(std::integral_constant<int, 6 + g>{}, A, B);
-    double v[1] = {0.0};
-    const int idx[1] = {g == 0 ? P2_PG : P2_PL};
+    transform_next(std::integral_constant<int, 7>{}, A, B);
+    double v[2] = {0.0, 0.0};
+    const int idx[2] = {P2_PG, P2_PL};
 #pragma unroll
     for (int j = 0; j < KPT; ++j) {
       if (!valid) continue;
       double i0, i1;
       inv_op(bin_of(j), false, i0, i1);
-      v[0] += (double)A[j] * (double)ka[1][j] * i0 + (double)B[j] * (double)kb[1][j] * i1;
+      const double pa = (double)ka[1][j] * i0, pb = (double)kb[1][j] * i1;
+      v[0] += pa * (double)ka[2][j] + pb * (double)kb[2][j];
+      v[1] += pa * (double)A[j] + pb * (double)B[j];
     }
     accumulate(v, idx);
-  };
-  zeta_stage(std::integral_constant<int, 0>{});
-  zeta_stage(std::integral_constant<int, 1>{});
+  }
   if constexpr (ACC_LDS) {
     // Sum the per-thread partials: thread t adds 16 consecutive threads'
     // values of sum t / (NTHR / 16) (in a rotated order that keeps the lanes
