@@ -62,7 +62,7 @@ def kernel_bytes_per_cell(precision: str):
         "col_gram": 8 * m,
         "solve5": 0,
         "col_solve": 7 * m + 2 * m,
-        "row_idct": 2 * m + 2 * 8 + (2 * 8 if precision == "mixed" else 0),
+        "row_idct": 2 * m + 2 * 8 + (2 * 8 if precision != "fp64" else 0),
     }
 
 
