@@ -368,6 +368,10 @@ struct ccmsav_ctx {
   hipStream_t gstream = nullptr;
   hipGraphExec_t gexec = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // graph branches of the size classes beyond the first
+  std::vector<hipStream_t> bstream;
+  std::vector<hipEvent_t> bevent;
+  hipEvent_t ev_fork = nullptr;
   // DCT-as-GEMM variant
   rocblas_handle blas = nullptr;
   // resident workgroups of the stencil pass on this device ([0] FP32, [1] FP64 intermediates)
@@ -486,11 +490,16 @@ void run_tuned(ccmsav_ctx* c, Tuner& tu, size_t ki, int t, hipStream_t st, F lau
 }
 
 template <typename TM>
-void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe, Tuner& tu) {
+void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe, Tuner& tu,
+                       int only) {
   const MemberArgs* tab = c->d_args + (size_t)table * c->mem.size();
   using LT = typename Launch<TM>::T;
+  // `only` >= 0 restricts the step to one size class (a branch of the graph).
+  auto skip = [&](size_t ki) { return only >= 0 && (int)ki != only; };
   pe.mark(0, st);
-  for (const SizeClass& k : c->cls) {
+  for (size_t ki = 0; ki < c->cls.size(); ++ki) {
+    if (skip(ki)) continue;
+    const SizeClass& k = c->cls[ki];
     const int total = k.count * k.sh.blocks;
     hipLaunchKernelGGL(k_stencil<TM>, dim3(stencil_grid(c, sizeof(TM) == 8, total)),
                        dim3(STENCIL_THREADS), 0, st, tab, k.d_idx, k.sh.blocks, total);
@@ -498,6 +507,7 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe,
   pe.mark(1, st);
   pe.mark(2, st);
   for (size_t ki = 0; ki < c->cls.size(); ++ki) {
+    if (skip(ki)) continue;
     const SizeClass& k = c->cls[ki];
     run_tuned<TM>(c, tu, ki, TUNE_ROW_DCT, st, [&](int v) {
       const int per = (1 << k.ly) / row_dct_rows(c->precision, 1 << k.lx, v);
@@ -506,17 +516,23 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe,
   }
   pe.mark(3, st);
   pe.mark(4, st);
-  for (const SizeClass& k : c->cls) {
+  for (size_t ki = 0; ki < c->cls.size(); ++ki) {
+    if (skip(ki)) continue;
+    const SizeClass& k = c->cls[ki];
     const int per = (1 << k.lx) / 2;
     LT::t_gram[k.ly - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
   }
   pe.mark(5, st);
   pe.mark(6, st);
-  for (const SizeClass& k : c->cls)
+  for (size_t ki = 0; ki < c->cls.size(); ++ki) {
+    if (skip(ki)) continue;
+    const SizeClass& k = c->cls[ki];
     hipLaunchKernelGGL(k_solve, dim3(k.count), dim3(SOLVE_THREADS), 0, st, tab, k.d_idx, 1);
+  }
   pe.mark(7, st);
   pe.mark(8, st);
   for (size_t ki = 0; ki < c->cls.size(); ++ki) {
+    if (skip(ki)) continue;
     const SizeClass& k = c->cls[ki];
     run_tuned<TM>(c, tu, ki, TUNE_COL_SOLVE, st, [&](int v) {
       const int per = 1 << k.lx;     // two groups (chi, zeta) per strip of two columns
@@ -526,6 +542,7 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe,
   pe.mark(9, st);
   pe.mark(10, st);
   for (size_t ki = 0; ki < c->cls.size(); ++ki) {
+    if (skip(ki)) continue;
     const SizeClass& k = c->cls[ki];
     run_tuned<TM>(c, tu, ki, TUNE_ROW_IDCT, st, [&](int v) {
       const int per = 1 << k.ly;
@@ -620,7 +637,7 @@ int enqueue_step_gemm(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEvents 
 }
 
 int enqueue_step_level(ccmsav_ctx* c, int64_t level, hipStream_t st,
-                       PhaseEvents pe = PhaseEvents{nullptr}) {
+                       PhaseEvents pe = PhaseEvents{nullptr}, int only = -1) {
   if (is_gemm(c->precision)) return enqueue_step_gemm(c, level, st, pe);
   const int t = table_of_level(level);
   Tuner tu;
@@ -631,9 +648,9 @@ int enqueue_step_level(ccmsav_ctx* c, int64_t level, hipStream_t st,
       if (hipEventCreate(&e) != hipSuccess) return CCMSAV_EHIP;
   }
   if (c->precision == CCMSAV_MIXED)
-    enqueue_step_kind<float>(c, t, st, pe, tu);
+    enqueue_step_kind<float>(c, t, st, pe, tu, only);
   else
-    enqueue_step_kind<double>(c, t, st, pe, tu);
+    enqueue_step_kind<double>(c, t, st, pe, tu, only);
   if (tu.on) {
     int rc = hipStreamSynchronize(st) == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
     for (size_t ki = 0; ki < c->cls.size() && rc == CCMSAV_OK; ++ki)
@@ -662,13 +679,46 @@ int enqueue_step_level(ccmsav_ctx* c, int64_t level, hipStream_t st,
 }
 
 // Capture three steady-state steps (levels 3k, 3k+1, 3k+2, k >= 1) into a graph.
+// Size classes are independent (members share no data), so with several of
+// them each class's three steps form their own branch of the graph, forked
+// from and joined to the capture stream, and the device runs the branches
+// side by side.
 int capture_graph(ccmsav_ctx* c) {
   if (c->gexec) return CCMSAV_OK;
+  const size_t nb = c->cls.size() > 1 ? c->cls.size() - 1 : 0;
+  while (c->bstream.size() < nb) {
+    hipStream_t s = nullptr;
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    c->bstream.push_back(s);
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    c->bevent.push_back(e);
+  }
+  if (nb > 0 && !c->ev_fork) HIP_TRY(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
   HIP_TRY(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeRelaxed));
-  for (int64_t lv = 3; lv < 6; ++lv) enqueue_step_level(c, lv, c->gstream);
+  bool ok = true;   // the capture is ended whatever happens inside it
+  if (nb == 0) {
+    for (int64_t lv = 3; lv < 6; ++lv) ok &= enqueue_step_level(c, lv, c->gstream) == CCMSAV_OK;
+  } else {
+    ok &= hipEventRecord(c->ev_fork, c->gstream) == hipSuccess;
+    for (size_t i = 0; i < nb && ok; ++i) {
+      ok &= hipStreamWaitEvent(c->bstream[i], c->ev_fork, 0) == hipSuccess;
+      for (int64_t lv = 3; lv < 6; ++lv)
+        ok &= enqueue_step_level(c, lv, c->bstream[i], PhaseEvents{nullptr}, (int)i + 1) ==
+              CCMSAV_OK;
+      ok &= hipEventRecord(c->bevent[i], c->bstream[i]) == hipSuccess;
+    }
+    for (int64_t lv = 3; lv < 6; ++lv)
+      ok &= enqueue_step_level(c, lv, c->gstream, PhaseEvents{nullptr}, 0) == CCMSAV_OK;
+    for (size_t i = 0; i < nb; ++i)
+      ok &= hipStreamWaitEvent(c->gstream, c->bevent[i], 0) == hipSuccess;
+  }
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->gstream, &g);
-  if (e != hipSuccess || !g) return CCMSAV_EHIP;
+  if (!ok || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    return CCMSAV_EHIP;
+  }
   const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (ei != hipSuccess) {
@@ -702,6 +752,9 @@ void free_ctx(ccmsav_ctx* c) {
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   if (c->gstream) (void)hipStreamDestroy(c->gstream);
+  for (hipStream_t b : c->bstream) (void)hipStreamDestroy(b);
+  for (hipEvent_t e : c->bevent) (void)hipEventDestroy(e);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->owns_ws && c->ws) (void)hipFree(c->ws);
   delete c;
 }
