@@ -545,7 +545,7 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe,
     if (skip(ki)) continue;
     const SizeClass& k = c->cls[ki];
     run_tuned<TM>(c, tu, ki, TUNE_ROW_IDCT, st, [&](int v) {
-      const int per = 1 << k.ly;
+      const int per = (1 << k.ly) / row_idct_rows<TM>(1 << k.lx, v);
       LT::t_row_idct[v][k.lx - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
     });
   }
@@ -1202,8 +1202,9 @@ int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, dou
     LT::t_rd[m.lx - kMinLog](c->stream, m.p.ny, rhs, static_cast<TM*>(m.mid), M_F, m.p.ny);
     LT::t_col_solve[k.var[TUNE_COL_SOLVE]][m.ly - kMinLog](c->stream, m.p.nx,
                                                            Batch{d, k.d_idx, m.p.nx});
-    LT::t_row_idct[k.var[TUNE_ROW_IDCT]][m.lx - kMinLog](c->stream, m.p.ny,
-                                                         Batch{d, k.d_idx, m.p.ny});
+    const int vi = k.var[TUNE_ROW_IDCT];
+    const int per = m.p.ny / row_idct_rows<TM>(m.p.nx, vi);
+    LT::t_row_idct[vi][m.lx - kMinLog](c->stream, per, Batch{d, k.d_idx, per});
   };
   if (c->precision != CCMSAV_FP64)
     run(0.0f);

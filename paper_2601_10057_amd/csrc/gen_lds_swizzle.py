@@ -177,18 +177,36 @@ def rec_pair_post(rec, n, nthr, radix):
             rec.wave([None if u is None else digit_rev(n - u if u else n // 2, n, radix) for u in us])
 
 
-def rec_pair_natural(rec, n, nthr):
+def rec_pair_natural(rec, n, nthr, line=0):
     for w in lanes(nthr):
         for u0 in range(0, n // 2, nthr):
             us = [u0 + t if u0 + t < n // 2 else None for t in w]
-            rec.wave([None if u is None else u for u in us])
-            rec.wave([None if u is None else (n - u if u else n // 2) for u in us])
+            rec.wave([None if u is None else line * n + u for u in us])
+            rec.wave([None if u is None else line * n + (n - u if u else n // 2) for u in us])
 
 
-def rec_final(rec, n, nthr, radix):
+def rec_final(rec, n, nthr, radix, line=0):
     for w in lanes(nthr):
         for i0 in range(0, n, nthr):
-            rec.wave([digit_rev(makhoul_slot(i0 + t, n), n, radix) if i0 + t < n else None for t in w])
+            rec.wave([line * n + digit_rev(makhoul_slot(i0 + t, n), n, radix) if i0 + t < n else None
+                      for t in w])
+
+
+def rec_band_inverse(rec, n, nthr, radix, rows):
+    """Row inverse over a band: strip pieces stored by column pair, the in-place
+    DCT-III pre-processing, the batched FFT and the outputs, row by row."""
+    for w in lanes(nthr):
+        for s0 in range(0, n // 2, nthr):
+            sts = [s0 + t if s0 + t < n // 2 else None for t in w]
+            for r in range(rows):
+                for kk in (0, 1):
+                    rec.wave([None if st is None else r * n + 2 * st + kk for st in sts])
+    for r in range(rows):
+        rec_pair_natural(rec, n, nthr, r)      # reads
+        rec_pair_natural(rec, n, nthr, r)      # writes
+    rec_fft(rec, n, rows, nthr, radix)
+    for r in range(rows):
+        rec_final(rec, n, nthr, radix, r)
 
 
 def patterns(esz, n, cls):
@@ -220,6 +238,7 @@ def patterns(esz, n, cls):
                                           for k, ln in zip(ks, lns)])
                                 rec.wave([None if k is None else ln * n + digit_rev((n - k) % n, n, radix)
                                           for k, ln in zip(ks, lns)])
+        rec_band_inverse(rec, n, line_threads(n), radix, p1_rows(esz, n))
     elif cls == "SWZ_LINE":
         for nthr in sorted({line_threads(n), one_line_threads(esz, n)}):
             # column solve
@@ -229,10 +248,11 @@ def patterns(esz, n, cls):
             rec_pair_natural(rec, n, nthr)
             rec_fft(rec, n, 1, nthr, radix)
             rec_final(rec, n, nthr, radix)
-            # row inverse
-            rec_pair_natural(rec, n, nthr)
-            rec_fft(rec, n, 1, nthr, radix)
-            rec_final(rec, n, nthr, radix)
+        # row inverse, one row with one butterfly per thread
+        nthr = one_line_threads(esz, n)
+        rec_pair_natural(rec, n, nthr)
+        rec_fft(rec, n, 1, nthr, radix)
+        rec_final(rec, n, nthr, radix)
         # row DCT of a single field
         nthr = line_threads(n)
         rec_makhoul(rec, n, nthr)

@@ -17,8 +17,9 @@
 //   P3  k_col_solve  : per strip, combines the x-transformed fields into the
 //       right-hand sides of chi phi^{n+1} and zeta psi^{n+1}, DCT-II along y,
 //       divides by sigma / tau, DCT-III along y.
-//   P4  k_row_idct   : per row, DCT-III along x of both results -> phi^{n+1},
-//       psi^{n+1} (added to phi^n, psi^n in the increment form).
+//   P4  k_row_idct   : per band of rows (or per row), DCT-III along x of both
+//       results -> phi^{n+1}, psi^{n+1} (added to phi^n, psi^n in the
+//       increment form).
 // The intermediate fields use a strip-major layout: element (k, j) of a field
 // lives at ((k / 2) * ny + j) * 2 + (k % 2), so that a column pair is one
 // contiguous complex line.
@@ -68,6 +69,11 @@ template <typename TM> constexpr int p1_rows(int n) {
   const int want = 32 / (2 * (int)sizeof(TM));
   const int fit = lds_line_budget<TM>(n);
   return fit >= want ? want : (fit >= 2 ? 2 : 1);
+}
+// Rows per workgroup of row inverse variant v (0: the row pass's band, which
+// reads each strip's rows of the band as one piece).
+template <typename TM> constexpr int row_idct_rows(int n, int v) {
+  return v == 0 ? p1_rows<TM>(n) : 1;
 }
 // Field pairs transformed together per round of the row pass (4 / pairs rounds).
 template <typename TM> constexpr int p1_pairs(int n) {
@@ -141,6 +147,23 @@ template <int N> __device__ __forceinline__ double tree_sum(double* buf, int tid
   }
   lds_sync();
   return buf[0];
+}
+
+// tree_sum of ROWS rows at once, row r at buf + r RS: the same pairs per row.
+template <int N, int ROWS, int RS>
+__device__ __forceinline__ void tree_sum_rows(double* buf, int tid, int nthr,
+                                              double (&res)[ROWS]) {
+#pragma unroll 1
+  for (int half = N / 2; half >= 1; half >>= 1) {
+    lds_sync();
+    for (int i = tid; i < ROWS * half; i += nthr) {
+      const int r = i / half, k = i - r * half;
+      buf[r * RS + k] += buf[r * RS + k + half];
+    }
+  }
+  lds_sync();
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) res[r] = buf[r * RS];
 }
 
 // 1 / x for positive, normal x: the hardware reciprocal estimate refined by
@@ -463,6 +486,21 @@ __device__ __forceinline__ void store_piece(gptr<TM> dst, const RowPiece<TM, ROW
     const auto d = reinterpret_cast<gptr<pair_t>>(dst);
 #pragma unroll
     for (int r = 0; r < ROWS; ++r) d[r] = pair_t{p.v[2 * r], p.v[2 * r + 1]};
+  }
+}
+
+// Load a piece (aligned to its size) with 16-byte reads.
+template <typename TM, int ROWS>
+__device__ __forceinline__ void load_piece(gptr<const TM> src, RowPiece<TM, ROWS>& p) {
+  constexpr int V = 16 / (int)sizeof(TM);
+  static_assert(2 * ROWS >= V, "a piece spans at least one 16-byte read");
+  typedef TM vec_t __attribute__((ext_vector_type(V)));
+  const auto s = reinterpret_cast<gptr<const vec_t>>(src);
+#pragma unroll
+  for (int c = 0; c < 2 * ROWS / V; ++c) {
+    const vec_t v = s[c];
+#pragma unroll
+    for (int e = 0; e < V; ++e) p.v[c * V + e] = v[e];
   }
 }
 
@@ -1196,6 +1234,131 @@ __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
   }
 }
 
+// P4 over a band of ROWS rows (the row pass's band height): each thread loads
+// the band's rows of its column pairs from both strip-major fields as one
+// piece per strip and field, into LDS lines in natural bin order (line r, bin
+// k holding (A_k, B_k)); the DCT-III pre-processing then runs in place, unit
+// by unit, since unit u reads and writes only bins u and N - u. The
+// transforms, outputs and row sums are those of row_idct_body, row by row.
+template <typename TM, int NX>
+__device__ __forceinline__ void row_idct_band_body(gptr<const TM> __restrict__ out,
+                                                   gptr<double> __restrict__ phi_new,
+                                                   gptr<double> __restrict__ psi_new, int ny,
+                                                   gptr<const double> __restrict__ phi_base,
+                                                   gptr<const double> __restrict__ psi_base,
+                                                   gptr<const double> __restrict__ colsum,
+                                                   int blk) {
+  constexpr int NTHR = line_threads(NX);
+  constexpr int ROWS = row_idct_rows<TM>(NX, 0);
+  constexpr int CPT = NX >= NTHR ? NX / NTHR : 1;            // outputs per thread and row
+  constexpr int UPT = NX / 2 >= NTHR ? NX / 2 / NTHR : 1;    // strips (and units) per thread
+  constexpr int R = fft_radix<TM>();
+  constexpr int RS = NX * (int)sizeof(cpx<TM>) / (int)sizeof(double);   // row buffer stride
+  using MAP = LdsMap<TM, NX, SWZ_ROW>;
+  using LS = LineSlots<NX, NTHR, R, MAP>;
+  __shared__ cpx<TM> line[ROWS * NX];
+  __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
+  const int tid = threadIdx.x;
+  const int j0 = blk * ROWS;
+  const size_t SS = strip_stride(ny, sizeof(TM));
+  const size_t FSM = strip_field(NX, ny, sizeof(TM));
+  Roots<TM, NX> rt;
+  rt.init(rtab, tid, NTHR);
+  const LS sl(tid);
+  int lo[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) lo[r] = MAP::at(r * NX);
+  // strip s = tid + q NTHR: rows j0 .. j0 + ROWS - 1 of bins 2 s and 2 s + 1
+#pragma unroll
+  for (int q = 0; q < UPT; ++q) {
+    const int st = tid + q * NTHR;
+    if (NX / 2 >= NTHR || st < NX / 2) {
+      const size_t o = (size_t)st * SS + 2 * (size_t)j0;
+      RowPiece<TM, ROWS> a, b;
+      load_piece<TM, ROWS>(out + o, a);
+      load_piece<TM, ROWS>(out + FSM + o, b);
+      const int k0 = MAP::at(2 * st), k1 = MAP::at(2 * st + 1);
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) {
+        line[lo[r] ^ k0] = {a.v[2 * r], b.v[2 * r]};
+        line[lo[r] ^ k1] = {a.v[2 * r + 1], b.v[2 * r + 1]};
+      }
+    }
+  }
+  lds_sync();
+  static_for<UPT>([&](auto iq) {
+    constexpr int q = decltype(iq)::value;
+    const int u = tid + q * NTHR;
+    if (NX / 2 >= NTHR || u < NX / 2) {
+      const int pn = sl.template nat<q>(), pm = sl.template natm<q>();
+#pragma unroll
+      for (int r = 0; r < ROWS; ++r) {
+        const cpx<TM> x = line[lo[r] ^ pn], xm = line[lo[r] ^ pm];
+        cpx<TM> Z, Zm;
+        dct3_pair<TM, NX>(rt, u, x.re, xm.re, x.im, xm.im, Z, Zm);
+        line[lo[r] ^ pn] = Z;
+        line[lo[r] ^ pm] = Zm;
+      }
+    }
+  });
+  lds_sync();
+  fft_lines<TM, NX, ROWS, NTHR, R, MAP>(line, rt, tid);
+  if (!colsum) {
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+      static_for<CPT>([&](auto iq) {
+        constexpr int q = decltype(iq)::value;
+        const int i = tid + q * NTHR;
+        if (NX >= NTHR || i < NX) {
+          const cpx<TM> y = line[lo[r] ^ sl.template out<q>()];
+          const size_t o = (size_t)(j0 + r) * NX + i;
+          phi_new[o] = (double)y.re;
+          psi_new[o] = -(double)y.im;
+        }
+      });
+    }
+    return;
+  }
+  // Increment form: new = base + increment, the psi increment of each row
+  // shifted so that its FP64 sum equals sqrt(NX) colsum[j].
+  cpx<TM> Y[ROWS][CPT];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+    static_for<CPT>([&](auto iq) {
+      constexpr int q = decltype(iq)::value;
+      const int i = tid + q * NTHR;
+      Y[r][q] = {(TM)0, (TM)0};
+      if (NX >= NTHR || i < NX) Y[r][q] = line[lo[r] ^ sl.template out<q>()];
+    });
+  }
+  double* buf = reinterpret_cast<double*>(line);     // the lines are no longer read
+  lds_sync();
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int i = tid + q * NTHR;
+      if (i < NX) buf[r * RS + i] = -(double)Y[r][q].im;
+    }
+  }
+  double tot[ROWS];
+  tree_sum_rows<NX, ROWS, RS>(buf, tid, NTHR, tot);
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+    const int j = j0 + r;
+    const double shift = (sqrt((double)NX) * colsum[j] - tot[r]) / NX;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int i = tid + q * NTHR;
+      if (i < NX) {
+        const size_t o = (size_t)j * NX + i;
+        phi_new[o] = phi_base[o] + (double)Y[r][q].re;
+        psi_new[o] = psi_base[o] + (-(double)Y[r][q].im + shift);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Row DCT-II of one plain field into intermediate slot `slot` (elliptic solve).
 // ---------------------------------------------------------------------------
@@ -1313,12 +1476,20 @@ __global__ void __launch_bounds__(line_threads_v<TM>(NY, V)) k_col_solve(BATCH_P
                          m.nzeta, m.colsum, o, blk);
 }
 
+// Row inverse variants: 0 takes a band of row_idct_rows rows per workgroup,
+// 1 one row with one FFT butterfly per thread.
 template <typename TM, int NX, int V>
 __global__ void __launch_bounds__(line_threads_v<TM>(NX, V)) k_row_idct(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
-  row_idct_body<TM, NX, line_threads_v<TM>(NX, V)>(static_cast<gptr<const TM>>(m.outc), m.phi_new, m.psi_new, m.ny,
-                        m.phi_base, m.psi_base, m.colsum, blk);
+  if constexpr (V == 0) {
+    row_idct_band_body<TM, NX>(static_cast<gptr<const TM>>(m.outc), m.phi_new, m.psi_new, m.ny,
+                               m.phi_base, m.psi_base, m.colsum, blk);
+  } else {
+    row_idct_body<TM, NX, line_threads_v<TM>(NX, V)>(static_cast<gptr<const TM>>(m.outc),
+                                                     m.phi_new, m.psi_new, m.ny, m.phi_base,
+                                                     m.psi_base, m.colsum, blk);
+  }
 }
 
 }  // namespace ccm

@@ -166,6 +166,8 @@ def test_fft_stage_slots(esz):
         for v in (0, 1):
             cases.append(("SWZ_ROW", G.p1_rows_v(esz, n, v) * G.p1_pairs_v(esz, n, v),
                           G.row_dct_threads(n, v), radix))
+        # row inverse over a band of rows
+        cases.append(("SWZ_ROW", G.p1_rows(esz, n), G.line_threads(n), radix))
         for cls, nl, nthr, rad in cases:
             at = mapper(esz, n, cls)
             length = n
