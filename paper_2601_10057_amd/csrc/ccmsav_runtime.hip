@@ -83,7 +83,7 @@ template <typename TM> struct Launch {
   }
   template <int N, int V>
   static void row_idct(hipStream_t st, int grid, const Batch& b) {
-    hipLaunchKernelGGL((k_row_idct<TM, N, V>), dim3(grid), dim3(line_threads_v<TM>(N, V)), 0, st,
+    hipLaunchKernelGGL((k_row_idct<TM, N, V>), dim3(grid), dim3(row_idct_threads<TM>(N, V)), 0, st,
                        b.m, b.idx, b.per);
   }
   using RD = void (*)(hipStream_t, int, const double*, TM*, int, int);

@@ -90,6 +90,16 @@ def row_dct_threads(n, v):
     return line_threads(n)
 
 
+def row_idct_rows(esz, n):
+    """Rows per workgroup of the band row inverse (launch variant 0)."""
+    return max(p1_rows(esz, n) // 2, 1)
+
+
+def row_idct_threads(esz, n):
+    bf = row_idct_rows(esz, n) * n // fft_radix(esz)
+    return clamp_threads(bf) if bf < line_threads(n) else line_threads(n)
+
+
 # ---- FFT index rules (mirror fft.hpp) ----------------------------------------
 def ilog2(n):
     return n.bit_length() - 1
@@ -238,7 +248,7 @@ def patterns(esz, n, cls):
                                           for k, ln in zip(ks, lns)])
                                 rec.wave([None if k is None else ln * n + digit_rev((n - k) % n, n, radix)
                                           for k, ln in zip(ks, lns)])
-        rec_band_inverse(rec, n, line_threads(n), radix, p1_rows(esz, n))
+        rec_band_inverse(rec, n, row_idct_threads(esz, n), radix, row_idct_rows(esz, n))
     elif cls == "SWZ_LINE":
         for nthr in sorted({line_threads(n), one_line_threads(esz, n)}):
             # column solve

@@ -70,10 +70,17 @@ template <typename TM> constexpr int p1_rows(int n) {
   const int fit = lds_line_budget<TM>(n);
   return fit >= want ? want : (fit >= 2 ? 2 : 1);
 }
-// Rows per workgroup of row inverse variant v (0: the row pass's band, which
-// reads each strip's rows of the band as one piece).
+// Rows per workgroup of row inverse variant v (0: half the row pass's band,
+// read as one piece per strip, with two workgroups per CU at N = 4096).
 template <typename TM> constexpr int row_idct_rows(int n, int v) {
-  return v == 0 ? p1_rows<TM>(n) : 1;
+  return v == 0 ? (p1_rows<TM>(n) / 2 > 0 ? p1_rows<TM>(n) / 2 : 1) : 1;
+}
+// Threads of row inverse variant v: variant 0 has one FFT butterfly per
+// thread over its band's lines, variant 1 over its one line.
+template <typename TM> constexpr int row_idct_threads(int n, int v) {
+  const int bf = row_idct_rows<TM>(n, v) * n / fft_radix<TM>();
+  return v == 0 ? (bf < line_threads(n) ? clamp_threads(bf) : line_threads(n))
+                : one_line_threads<TM>(n);
 }
 // Field pairs transformed together per round of the row pass (4 / pairs rounds).
 template <typename TM> constexpr int p1_pairs(int n) {
@@ -489,18 +496,19 @@ __device__ __forceinline__ void store_piece(gptr<TM> dst, const RowPiece<TM, ROW
   }
 }
 
-// Load a piece (aligned to its size) with 16-byte reads.
+// Load a piece (aligned to its size) with 16-byte reads, or with one pair
+// read when it is shorter.
 template <typename TM, int ROWS>
 __device__ __forceinline__ void load_piece(gptr<const TM> src, RowPiece<TM, ROWS>& p) {
   constexpr int V = 16 / (int)sizeof(TM);
-  static_assert(2 * ROWS >= V, "a piece spans at least one 16-byte read");
-  typedef TM vec_t __attribute__((ext_vector_type(V)));
+  constexpr int W = 2 * ROWS >= V ? V : 2;
+  typedef TM vec_t __attribute__((ext_vector_type(W)));
   const auto s = reinterpret_cast<gptr<const vec_t>>(src);
 #pragma unroll
-  for (int c = 0; c < 2 * ROWS / V; ++c) {
+  for (int c = 0; c < 2 * ROWS / W; ++c) {
     const vec_t v = s[c];
 #pragma unroll
-    for (int e = 0; e < V; ++e) p.v[c * V + e] = v[e];
+    for (int e = 0; e < W; ++e) p.v[c * W + e] = v[e];
   }
 }
 
@@ -1234,7 +1242,7 @@ __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
   }
 }
 
-// P4 over a band of ROWS rows (the row pass's band height): each thread loads
+// P4 over a band of ROWS rows (row_idct_rows): each thread loads
 // the band's rows of its column pairs from both strip-major fields as one
 // piece per strip and field, into LDS lines in natural bin order (line r, bin
 // k holding (A_k, B_k)); the DCT-III pre-processing then runs in place, unit
@@ -1248,7 +1256,7 @@ __device__ __forceinline__ void row_idct_band_body(gptr<const TM> __restrict__ o
                                                    gptr<const double> __restrict__ psi_base,
                                                    gptr<const double> __restrict__ colsum,
                                                    int blk) {
-  constexpr int NTHR = line_threads(NX);
+  constexpr int NTHR = row_idct_threads<TM>(NX, 0);
   constexpr int ROWS = row_idct_rows<TM>(NX, 0);
   constexpr int CPT = NX >= NTHR ? NX / NTHR : 1;            // outputs per thread and row
   constexpr int UPT = NX / 2 >= NTHR ? NX / 2 / NTHR : 1;    // strips (and units) per thread
@@ -1479,7 +1487,9 @@ __global__ void __launch_bounds__(line_threads_v<TM>(NY, V)) k_col_solve(BATCH_P
 // Row inverse variants: 0 takes a band of row_idct_rows rows per workgroup,
 // 1 one row with one FFT butterfly per thread.
 template <typename TM, int NX, int V>
-__global__ void __launch_bounds__(line_threads_v<TM>(NX, V)) k_row_idct(BATCH_PARAMS) {
+__global__ void __launch_bounds__(row_idct_threads<TM>(NX, V),
+                                  V == 0 && row_idct_threads<TM>(NX, V) == 512 ? 4 : 1)
+k_row_idct(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
   if constexpr (V == 0) {

@@ -116,7 +116,8 @@ def test_line_slots_match_direct_definitions(esz):
         for cls, nthrs, rad in (
                 ("SWZ_LINE", {G.line_threads(n), G.one_line_threads(esz, n)}, radix),
                 ("SWZ_GRAM", {G.gram_threads(n)}, G.gram_radix(n)),
-                ("SWZ_ROW", {G.row_dct_threads(n, 0), G.row_dct_threads(n, 1)}, radix)):
+                ("SWZ_ROW", {G.row_dct_threads(n, 0), G.row_dct_threads(n, 1),
+                             G.row_idct_threads(esz, n)}, radix)):
             at = mapper(esz, n, cls)
             for nthr in nthrs:
                 for key, (fast, direct) in line_slots(n, nthr, rad, at).items():
@@ -167,7 +168,7 @@ def test_fft_stage_slots(esz):
             cases.append(("SWZ_ROW", G.p1_rows_v(esz, n, v) * G.p1_pairs_v(esz, n, v),
                           G.row_dct_threads(n, v), radix))
         # row inverse over a band of rows
-        cases.append(("SWZ_ROW", G.p1_rows(esz, n), G.line_threads(n), radix))
+        cases.append(("SWZ_ROW", G.row_idct_rows(esz, n), G.row_idct_threads(esz, n), radix))
         for cls, nl, nthr, rad in cases:
             at = mapper(esz, n, cls)
             length = n
