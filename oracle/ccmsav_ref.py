@@ -12,7 +12,9 @@ written, in its order and notation, with numpy for array arithmetic:
   discrete forms of Sec. 3.4.1;
 * one BDF2 step: eqs. (AC_BDF2)-(Z_BDF2), solved by the procedure of App. B
   (f^n, g^n, seven elliptic solves, the 5x5 system, field recovery, SAV
-  update of Algorithm 1); the first step uses the BDF1 variant of App. B;
+  update of Algorithm 1); the first step uses the BDF1 variant of App. B,
+  and a state created with ``bdf1=True`` takes every step with it (the
+  CC-MSAV-BDF1 scheme of the App. B remark);
 * elliptic solves: App. C (2D DCT, divide by the operator spectrum, inverse
   DCT); the DCT is the orthonormal DCT-II written out as a matrix
   (definition), with scipy's DCT as an equivalent fast library primitive for
@@ -359,10 +361,12 @@ class State:
     n: int = 0
     d_acc: float = 0.0           # sum_{j>=2} (dt/2) ||d^j||^2
     history: List[Dict] = field(default_factory=list)
+    bdf1: bool = False           # every step with the BDF1 scheme
 
 
-def initial_state(phi0, psi0, params: Dict) -> State:
-    """Initial fields and SAVs (eq. msav_ic); A defaults to int f_surf(phi0)."""
+def initial_state(phi0, psi0, params: Dict, bdf1: bool = False) -> State:
+    """Initial fields and SAVs (eq. msav_ic); A defaults to int f_surf(phi0).
+    With ``bdf1`` every step uses the CC-MSAV-BDF1 scheme (App. B remark)."""
     p = Params.from_dict(params)
     phi0 = np.array(phi0, dtype=np.float64)
     psi0 = np.array(psi0, dtype=np.float64)
@@ -370,7 +374,7 @@ def initial_state(phi0, psi0, params: Dict) -> State:
         p.A = integral(f_surf(phi0, p), p.h)
     sav = np.array([sav_V(phi0, p), sav_U(phi0, p), sav_W(phi0, p),
                     sav_Z(phi0, psi0, p)])
-    return State(p, phi0, psi0, None, None, sav, None)
+    return State(p, phi0, psi0, None, None, sav, None, bdf1=bdf1)
 
 
 def chi_coefficients(p: Params, alpha: float):
@@ -395,13 +399,14 @@ def sav_weights(p: Params):
 
 
 def step(st: State, use_matrix: Optional[bool] = None, keep: bool = False) -> Dict:
-    """Advance one step: BDF1 variant first (App. B remark), BDF2 after.
+    """Advance one step: BDF1 variant first (App. B remark), BDF2 after (or
+    BDF1 throughout for a state of the BDF1 scheme).
 
     Returns a dict of intermediate quantities (the 5x5 system, etc.).
     """
     p = st.p
     h, dt = p.h, p.dt
-    bdf2 = st.phi_prev is not None
+    bdf2 = st.phi_prev is not None and not st.bdf1
     phi_n, psi_n = st.phi, st.psi
     Vn, Un, Wn, Zn = st.sav
     if bdf2:
@@ -498,9 +503,9 @@ def step(st: State, use_matrix: Optional[bool] = None, keep: bool = False) -> Di
     return info
 
 
-def run(phi0, psi0, params: Dict, nsteps: int, use_matrix=None) -> State:
-    """Initialise and take ``nsteps`` steps."""
-    st = initial_state(phi0, psi0, params)
+def run(phi0, psi0, params: Dict, nsteps: int, use_matrix=None, bdf1: bool = False) -> State:
+    """Initialise and take ``nsteps`` steps (of the BDF1 scheme with ``bdf1``)."""
+    st = initial_state(phi0, psi0, params, bdf1)
     for _ in range(nsteps):
         step(st, use_matrix)
     return st
@@ -558,6 +563,8 @@ def energy(st: State) -> Dict:
     """E^{n,n-1}_mod of the current state (levels n and n-1)."""
     if st.phi_prev is None:
         raise ValueError("energy needs two time levels")
+    if st.bdf1:
+        raise ValueError("E^{n,n-1}_mod is the energy of the BDF2 scheme")
     return modified_energy(st.phi, st.phi_prev, st.sav, st.sav_prev, st.d_acc, st.p)
 
 

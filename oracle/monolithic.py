@@ -24,7 +24,7 @@ def monolithic_step(st: R.State):
     nc = p.nx * p.ny
     L = R.lap_matrix(p.nx, p.ny, h)
     I = np.eye(nc)
-    bdf2 = st.phi_prev is not None
+    bdf2 = st.phi_prev is not None and not st.bdf1
     phi_n, psi_n = st.phi.ravel(), st.psi.ravel()
     Vn, Un, Wn, Zn = st.sav
     if bdf2:

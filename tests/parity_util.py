@@ -21,14 +21,15 @@ def rel_linf(a, b):
     return float(np.abs(a - b).max() / (den if den > 0 else 1.0))
 
 
-def oracle_trajectory(phi0, psi0, params, steps, perturb_seed=None):
-    """Oracle states after each of ``steps`` steps: list of (phi, psi, sav, sav_prev)."""
+def oracle_trajectory(phi0, psi0, params, steps, perturb_seed=None, bdf1=False):
+    """Oracle states after each of ``steps`` steps: list of (phi, psi, sav, sav_prev)
+    (of the BDF1 scheme with ``bdf1``)."""
     if perturb_seed is not None:
         rng = np.random.default_rng(perturb_seed)
         ulp = 2.0 ** -52
         phi0 = phi0 * (1.0 + ulp * rng.choice([-1.0, 1.0], phi0.shape))
         psi0 = psi0 * (1.0 + ulp * rng.choice([-1.0, 1.0], psi0.shape))
-    st = R.initial_state(phi0, psi0, params)
+    st = R.initial_state(phi0, psi0, params, bdf1)
     out = [(st.phi.copy(), st.psi.copy(), st.sav.copy(), st.sav.copy())]
     for _ in range(steps):
         R.step(st)

@@ -313,3 +313,58 @@ def test_oracle_catches_a_planted_sign_error(monkeypatch):
     old = st.phi
     R.step(st, use_matrix=True)
     assert np.abs((st.phi - old) - (ph - old)).max() > 1e-6 * np.abs(ph - old).max()
+
+
+# ---------------------------------------------------------------- CC-MSAV-BDF1 (App. B remark)
+
+def test_bdf1_scheme_steps_equal_monolithic_solve():
+    """Every step of the BDF1 scheme reaches the dense solution of the BDF1
+    counterparts of eqs. (AC_BDF2)-(Z_BDF2)."""
+    nx, ny, h = 6, 5, 0.45
+    params = moderate_params(nx, ny, h)
+    phi, psi = smooth_fields(nx, ny, h, seed=9)
+    st = R.initial_state(phi, psi, params, bdf1=True)
+    for _ in range(4):
+        ph, ps, sv = monolithic_step(st)
+        dphi_ref, dpsi_ref = ph - st.phi, ps - st.psi
+        old_phi, old_psi = st.phi, st.psi
+        R.step(st, use_matrix=True)
+        np.testing.assert_allclose(st.phi - old_phi, dphi_ref, rtol=1e-8,
+                                   atol=1e-10 * np.abs(dphi_ref).max())
+        np.testing.assert_allclose(st.psi - old_psi, dpsi_ref, rtol=1e-8,
+                                   atol=1e-10 * np.abs(dpsi_ref).max())
+        np.testing.assert_allclose(st.sav, sv, rtol=1e-9, atol=1e-12)
+    # the BDF2 scheme from the same state differs after the first step
+    st2 = R.run(phi, psi, params, 4, use_matrix=True)
+    assert np.abs(st2.phi - st.phi).max() > 1e-6 * np.abs(st.phi - phi).max()
+
+
+def test_bdf1_scheme_is_first_order_in_time():
+    """Cauchy errors of the BDF1 scheme at dt, dt/2, dt/4, dt/8 fall by about 2."""
+    nx = ny = 24
+    h, eps, T = 0.25, 0.5, 0.002
+    x = (np.arange(nx) + 0.5) * h
+    X, Y = np.meshgrid(x, x)
+    r = np.hypot(X - 0.52 * nx * h, (Y - 0.48 * nx * h) * 1.3)
+    phi = np.tanh((0.3 * nx * h - r) / (math.sqrt(2) * eps))
+    psi = 0.6 - 0.2 * phi
+    sols = []
+    for dt in (2e-4, 1e-4, 5e-5, 2.5e-5):
+        params = moderate_params(nx, ny, h, dt=dt, eps=eps)
+        st = R.run(phi, psi, params, int(round(T / dt)), use_matrix=True, bdf1=True)
+        sols.append((st.phi, st.psi))
+    errs = [math.sqrt(R.ip(a[0] - b[0], a[0] - b[0], h) + R.ip(a[1] - b[1], a[1] - b[1], h))
+            for a, b in zip(sols[:-1], sols[1:])]
+    rates = [math.log2(e1 / e2) for e1, e2 in zip(errs[:-1], errs[1:])]
+    assert all(0.9 < r < 1.1 for r in rates), rates
+
+
+def test_bdf1_scheme_conserves_mass_and_has_no_bdf2_energy():
+    m = vesicle_member(48, 11, dt=1e-5)
+    st = R.initial_state(m.phi0, m.psi0, m.params, bdf1=True)
+    m0 = R.mass(st)[0]
+    for _ in range(10):
+        R.step(st, use_matrix=True)
+        assert abs(R.mass(st)[0] - m0) <= 1e-13 * abs(m0)
+    with pytest.raises(ValueError):
+        R.energy(st)
