@@ -54,10 +54,12 @@ def gemm_flops(members):
 BF16_PEAK_TFLOPS = 2500.0
 
 
-def kernel_bytes_per_cell(precision: str):
+def kernel_bytes_per_cell(precision: str, scheme: str = "bdf2"):
     m = 8 if precision == "fp64" else 4
+    # The BDF1 scheme's stencil pass reads level n only (phi*, psi* = phi^n, psi^n).
+    levels = 3 if scheme == "bdf2" else 1
     return {
-        "stencil": 6 * 8 + 8 * m,
+        "stencil": 2 * levels * 8 + 8 * m,
         "row_dct": 16 * m,
         "col_gram": 8 * m,
         "solve5": 0,
@@ -121,7 +123,8 @@ def cpu_baseline(members, budget_s: float = 12.0):
                       f"member(s) (N={sizes}): {used:.2f} s, single-threaded numpy/scipy"}
 
 
-def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, graph):
+def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, graph,
+              bdf1=False):
     """Warm up, time ``steps`` steps between two synchronisations, then take
     ``profile_steps`` more with per-kernel events. Returns timings and the
     final states (after warmup + steps + profile_steps steps)."""
@@ -129,7 +132,7 @@ def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, g
     psi0 = [torch.from_numpy(m.psi0).to(dev) for m in members]
     stream = torch.cuda.current_stream(dev)
     ctx = C.Context.ensemble([m.params for m in members], phi0, psi0, precision,
-                             stream=stream.cuda_stream, graph=graph)
+                             stream=stream.cuda_stream, graph=graph, bdf1=bdf1)
     nm = len(members)
     mass0 = [ctx.mass(i)[0] for i in range(nm)]
     ctx.step(warmup)
@@ -149,7 +152,7 @@ def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, g
     mass = [ctx.mass(i)[0] for i in range(nm)]
     out = dict(wall=wall, ev_ms=ev0.elapsed_time(ev1), prof=prof, tuning=tuning,
                drift=max(abs(a - b) / abs(b) for a, b in zip(mass, mass0)),
-               energy=[ctx.energy(member=i) for i in range(nm)],
+               energy=[None if bdf1 else ctx.energy(member=i) for i in range(nm)],
                fields=[ctx.fields(i) for i in range(nm)],
                savs=[ctx.savs(i)[0] for i in range(nm)])
     ctx.close()
@@ -167,6 +170,9 @@ def main():
                     help="replay the steady-state steps from a captured HIP graph")
     ap.add_argument("--profile-steps", type=int, default=50,
                     help="steps of the per-kernel event pass that feeds the roofline")
+    ap.add_argument("--scheme", default="bdf2", choices=["bdf2", "bdf1"],
+                    help="time-stepping scheme: CC-MSAV-BDF2 (the default), or the "
+                         "first-order CC-MSAV-BDF1 scheme at every step")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 run that the mixed path is checked and compared against")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -189,8 +195,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    bdf1 = args.scheme == "bdf1"
     run = timed_run(C, torch, members, args.precision, args.steps, args.warmup,
-                    args.profile_steps, dev, args.graph)
+                    args.profile_steps, dev, args.graph, bdf1)
     wall = run["wall"]
     ms_per_step = 1e3 * wall / args.steps
     value = cells * args.steps / wall / 1e6
@@ -199,7 +206,7 @@ def main():
           file=sys.stderr, flush=True)
 
     prof = run["prof"]
-    per_cell = kernel_bytes_per_cell(args.precision)
+    per_cell = kernel_bytes_per_cell(args.precision, args.scheme)
     for k, ms in prof.items():
         gbs = per_cell[k] * cells / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         print(f"[bench] kernel {k}: {ms * 1e3:.1f} us/launch, {per_cell[k]} B/cell, "
@@ -229,12 +236,14 @@ def main():
                     "step_bytes_per_cell": sum(per_cell.values()),
                     "step_frac": sum(per_cell.values()) * value * 1e6 / 1e9 / HBM_PEAK_GBS}
 
-    check = {"mass_drift": run["drift"], "E_mod": run["energy"][0],
-             "finite": bool(np.all(np.isfinite(run["energy"])))}
+    finite = all(bool(np.all(np.isfinite(f[0]))) for f in run["fields"])
+    if not bdf1:
+        finite = finite and bool(np.all(np.isfinite(run["energy"])))
+    check = {"mass_drift": run["drift"], "E_mod": run["energy"][0], "finite": finite}
     compare = None
     if args.precision != "fp64" and not args.no_compare:
         ref = timed_run(C, torch, members, "fp64", args.steps, args.warmup, args.profile_steps,
-                        dev, args.graph)
+                        dev, args.graph, bdf1)
         rel = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())  # noqa: E731
         check.update(
             rel_linf_phi_vs_fp64=max(rel(a[0], b[0]) for a, b in zip(run["fields"], ref["fields"])),
@@ -259,7 +268,7 @@ def main():
     m0 = members[0]
     config = {"workload": args.workload, "members": len(members), "cells": cells,
               "grids": sorted({(m.params["nx"], m.params["ny"]) for m in members}),
-              "precision": args.precision, "graph": args.graph,
+              "precision": args.precision, "graph": args.graph, "scheme": args.scheme,
               "dt": sorted({m.params["dt"] for m in members}),
               "eps_cells": sorted({m.meta.get("eps_cells", 4.0) for m in members})}
     if len(members) == 1:

@@ -82,7 +82,7 @@ typedef enum {
  *  lam          Cahn-Hilliard stabilisation lambda >= 0               (Sec. 3.2)
  *  beta         linear SAV splitting constant                         (Sec. 2.2)
  *  precision    a ccmsav_precision value
- *  flags        0 or CCMSAV_FLAG_GRAPH
+ *  flags        0 or CCMSAV_FLAG_GRAPH and/or CCMSAV_FLAG_BDF1
  */
 typedef struct {
   int32_t nx, ny;
@@ -98,6 +98,13 @@ typedef struct {
  * three steps and replay it from then on. The graph runs on a stream of the
  * library's own, ordered after and before the context's stream by events. */
 #define CCMSAV_FLAG_GRAPH 1
+
+/* flags: take every step with the first-order CC-MSAV-BDF1 scheme (the BDF1
+ * remark of App. B: phi* = phi^n, psi* = psi^n, C1 and zeta with 1/dt, and
+ * the SAV brackets of level n only) instead of BDF2 after the first step.
+ * ccmsav_energy then returns EUNSUPPORTED: E^{n,n-1}_mod is the energy of
+ * the BDF2 scheme. */
+#define CCMSAV_FLAG_BDF1 2
 
 /* Device workspace bytes a context needs for these parameters (0 if the
  * parameters are invalid or unsupported). */
@@ -148,7 +155,8 @@ int ccmsav_get_savs_m(ccmsav_ctx* c, int32_t member, double out8[8]);
 
 /*
  * Enqueue nsteps >= 0 time steps (Algorithm 1 of App. B per step; BDF1 for the
- * step from level 0). Asynchronous: returns once the work is on the stream.
+ * step from level 0, and for every step under CCMSAV_FLAG_BDF1). Asynchronous:
+ * returns once the work is on the stream.
  */
 int ccmsav_step(ccmsav_ctx* c, int32_t nsteps);
 
@@ -158,7 +166,7 @@ int ccmsav_step(ccmsav_ctx* c, int32_t nsteps);
  * -sum_{j=2}^{n} (dt/2) ||d^j||^2 (Sec. 3.3). parts (nullable) receives 9
  * values: bending, surface+theta, -theta_tilde term, beta term, V, U, W, Z
  * terms, and minus the accumulated sum. Synchronises the stream.
- * EINVAL if n == 0.
+ * EINVAL if n == 0; EUNSUPPORTED for a context of the BDF1 scheme.
  */
 int ccmsav_energy(ccmsav_ctx* c, double* E_mod, double* parts);
 

@@ -167,7 +167,7 @@ bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 
 int check_params(const ccmsav_params* p) {
   if (!p) return CCMSAV_EINVAL;
-  if ((p->flags & ~CCMSAV_FLAG_GRAPH) != 0) return CCMSAV_EINVAL;
+  if ((p->flags & ~(CCMSAV_FLAG_GRAPH | CCMSAV_FLAG_BDF1)) != 0) return CCMSAV_EINVAL;
   if (p->precision != CCMSAV_FP64 && p->precision != CCMSAV_MIXED &&
       p->precision != CCMSAV_MIXED_GEMM_BF16X3)
     return CCMSAV_EUNSUPPORTED;
@@ -356,6 +356,7 @@ struct ccmsav_ctx {
   std::vector<SizeClass> cls;
   int precision = CCMSAV_FP64;
   bool graph = false;
+  bool bdf1 = false;       // every step with the BDF1 scheme (CCMSAV_FLAG_BDF1)
   hipStream_t stream = nullptr;
   bool owns_ws = false;
   void* ws = nullptr;
@@ -407,13 +408,14 @@ MemberArgs member_args(const Member& m, int precision, int table) {
     return a;
   }
   const int64_t lv = level_of_table(table);
-  const bool bdf2 = lv >= 1;
+  // BDF2 from level 1 on, or the BDF1 scheme (App. B remark) at every level.
+  const bool bdf2 = lv >= 1 && (m.p.flags & CCMSAV_FLAG_BDF1) == 0;
   const int sn = (int)(lv % 3), sm = (int)((lv + 2) % 3), snew = (int)((lv + 1) % 3);
   a.k = make_const(m.p, bdf2);
   a.k.slot_n = sn;
   a.k.slot_m = bdf2 ? sm : sn;
   a.k.slot_new = snew;
-  a.k.lag_d = lv >= 2 ? 1 : 0;
+  a.k.lag_d = bdf2 && lv >= 2 ? 1 : 0;
   const double* phn = m.phi[sn];
   const double* psn = m.psi[sn];
   const double* phm = bdf2 ? m.phi[sm] : phn;
@@ -422,8 +424,8 @@ MemberArgs member_args(const Member& m, int precision, int table) {
   a.psn = to_global(psn);
   a.phm = to_global(phm);
   a.psm = to_global(psm);
-  a.phmm = to_global<const double>(lv >= 2 ? m.phi[snew] : phm);
-  a.psmm = to_global<const double>(lv >= 2 ? m.psi[snew] : psm);
+  a.phmm = to_global<const double>(bdf2 && lv >= 2 ? m.phi[snew] : phm);
+  a.psmm = to_global<const double>(bdf2 && lv >= 2 ? m.psi[snew] : psm);
   a.phi_new = to_global(m.phi[snew]);
   a.psi_new = to_global(m.psi[snew]);
   a.coef = to_global<const double>(m.ds->coef);
@@ -857,6 +859,7 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
   if (!c) return CCMSAV_ENOMEM;
   c->precision = p[0].precision;
   c->graph = (p[0].flags & CCMSAV_FLAG_GRAPH) != 0;
+  c->bdf1 = (p[0].flags & CCMSAV_FLAG_BDF1) != 0;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->owns_ws = workspace == nullptr;
   if (c->owns_ws) {
@@ -1087,6 +1090,7 @@ int32_t ccmsav_members(const ccmsav_ctx* c) { return c ? (int32_t)c->mem.size() 
 
 int ccmsav_energy_m(ccmsav_ctx* c, int32_t member, double* E_mod, double* parts) {
   if (!valid_member(c, member) || !E_mod) return CCMSAV_EINVAL;
+  if (c->bdf1) return CCMSAV_EUNSUPPORTED;
   if (c->level < 1) return CCMSAV_EINVAL;
   int r = run_diag(c, member, true);
   if (r != CCMSAV_OK) return r;

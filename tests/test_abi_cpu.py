@@ -87,7 +87,7 @@ def test_init_rejects_null_and_unknown_modes():
     buf = (ctypes.c_double * 4)()
     assert lib.ccmsav_init(ctypes.byref(h), ctypes.byref(p), buf, buf, None, 0, None) == -6
     p.precision = 0
-    p.flags = 3
+    p.flags = 4          # no such flag
     assert lib.ccmsav_init(ctypes.byref(h), ctypes.byref(p), buf, buf, None, 0, None) == -1
     assert lib.ccmsav_step(None, 1) == -1
     assert lib.ccmsav_destroy(None) == -1
