@@ -20,7 +20,9 @@ written, in its order and notation, with numpy for array arithmetic:
   (definition), with scipy's DCT as an equivalent fast library primitive for
   large grids;
 * modified discrete energy: eq. (modified_discrete_energy); the dissipation
-  quantities K^n, ||mu||^2, ||c + d/2||^2 of Thm. 3.1 / App. A.
+  quantities K^n, ||mu||^2, ||c + d/2||^2 of Thm. 3.1 / App. A;
+* smoothed initial conditions: App. F (constant-mobility Cahn-Hilliard
+  relaxation, biharmonic term implicit, then clipping).
 
 Readings where the paper is silent or ambiguous:
 face mobility is M_psi of the face-averaged phi*; the face average of phi^2
@@ -509,6 +511,37 @@ def run(phi0, psi0, params: Dict, nsteps: int, use_matrix=None, bdf1: bool = Fal
     for _ in range(nsteps):
         step(st, use_matrix)
     return st
+
+
+# ---------------------------------------------------------------------------
+# Smoothed initial conditions (App. F)
+# ---------------------------------------------------------------------------
+
+def smooth_ic(phi_sharp, h, eps, M=0.01, dt=1e-6, nsteps=10, use_matrix=None, clip=True):
+    """Relax a sharp phase field by nsteps steps of the constant-mobility
+    Cahn-Hilliard equation phi_t = M Lap((phi^3 - phi) / eps - eps Lap phi)
+    with Neumann boundaries (App. F): first-order semi-implicit, the
+    biharmonic term implicit and the nonlinear term explicit,
+        (1/dt + M eps Lap_h^2) phi^{n+1} = phi^n / dt + (M / eps) Lap_h(phi^3 - phi)^n,
+    solved with the DCT (App. C); then clip to [-1, 1]. App. F's choice is
+    M = 0.01, dt = 1e-6 and T = 1e-5, i.e. ten steps. ``clip=False`` returns
+    the field before clipping."""
+    phi = np.array(phi_sharp, dtype=np.float64)
+    ny, nx = phi.shape
+    lam_h = neumann_lap_eigs(nx, ny, h)
+    sigma = 1.0 / dt + M * eps * lam_h ** 2
+    for _ in range(nsteps):
+        rhs = phi / dt + (M / eps) * lap(phi ** 3 - phi, h)
+        phi = spectral_solve(rhs, sigma, use_matrix)
+    return np.clip(phi, -1.0, 1.0) if clip else phi
+
+
+def ch_free_energy(phi, h, eps):
+    """Free energy of the smoothing flow: int eps/2 |grad phi|^2 + (phi^2 - 1)^2 / (4 eps)."""
+    gx = Dx(phi, h)
+    gy = Dy(phi, h)
+    grad = 0.5 * eps * (h * h * float(np.sum(gx * gx)) + h * h * float(np.sum(gy * gy)))
+    return grad + integral((phi ** 2 - 1.0) ** 2 / (4.0 * eps), h)
 
 
 # ---------------------------------------------------------------------------

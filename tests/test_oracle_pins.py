@@ -368,3 +368,58 @@ def test_bdf1_scheme_conserves_mass_and_has_no_bdf2_energy():
         assert abs(R.mass(st)[0] - m0) <= 1e-13 * abs(m0)
     with pytest.raises(ValueError):
         R.energy(st)
+
+
+# ---------------------------------------------------------------- App. F smoothing
+
+def test_smoothing_step_equals_dense_solve():
+    """One step of the App. F relaxation against the dense linear system
+    (I / dt + M eps L^2) phi^1 = phi^0 / dt + (M / eps) L (phi0^3 - phi0)."""
+    nx, ny, h, eps, M, dt = 6, 5, 0.3, 0.5, 0.01, 1e-3
+    phi0, _ = smooth_fields(nx, ny, h, seed=3)
+    phi0 = 0.5 * phi0 / np.abs(phi0).max()
+    got = R.smooth_ic(phi0, h, eps, M, dt, 1, use_matrix=True, clip=False)
+    L = R.lap_matrix(nx, ny, h)
+    A = np.eye(nx * ny) / dt + M * eps * (L @ L)
+    b = phi0.ravel() / dt + (M / eps) * (L @ (phi0.ravel() ** 3 - phi0.ravel()))
+    ref = np.linalg.solve(A, b).reshape(ny, nx)
+    np.testing.assert_allclose(got, ref, rtol=1e-10, atol=1e-12)
+
+
+def _sharp_disc(n, h):
+    x = (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(x, x)
+    return np.where(np.hypot(X - 0.5, (Y - 0.5) * 1.4) < 0.3, 1.0, -1.0)
+
+
+def test_smoothing_conserves_mass_and_decreases_the_free_energy():
+    n = 64
+    h = 1.0 / n
+    eps = 4 * h
+    phi = _sharp_disc(n, h)
+    mass0 = R.integral(phi, h)
+    E = [R.ch_free_energy(phi, h, eps)]
+    for _ in range(10):
+        phi = R.smooth_ic(phi, h, eps, 0.01, 1e-6, 1, clip=False)
+        E.append(R.ch_free_energy(phi, h, eps))
+        assert abs(R.integral(phi, h) - mass0) <= 1e-12 * abs(mass0) + 1e-14
+    assert all(b < a for a, b in zip(E[:-1], E[1:])), E
+    assert E[-1] < 0.7 * E[0]
+    out = R.smooth_ic(_sharp_disc(n, h), h, eps)
+    assert out.min() >= -1.0 and out.max() <= 1.0
+
+
+def test_smoothing_keeps_the_equilibrium_profile():
+    """tanh((x - x0) / (sqrt 2 eps)) solves the steady equation, so the flow
+    barely moves it, while it moves a sharp step of the same interface."""
+    n = 64
+    h = 1.0 / n
+    eps = 4 * h
+    x = (np.arange(n) + 0.5) * h
+    X, _ = np.meshgrid(x, x)
+    prof = np.tanh((X - 0.5) / (math.sqrt(2.0) * eps))
+    step = np.where(X < 0.5, -1.0, 1.0)
+    args = (h, eps, 0.01, 1e-6, 10)
+    moved_prof = np.abs(R.smooth_ic(prof, *args, clip=False) - prof).max()
+    moved_step = np.abs(R.smooth_ic(step, *args, clip=False) - step).max()
+    assert moved_prof < 0.02 * moved_step, (moved_prof, moved_step)
