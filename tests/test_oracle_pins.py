@@ -422,4 +422,4 @@ def test_smoothing_keeps_the_equilibrium_profile():
     args = (h, eps, 0.01, 1e-6, 10)
     moved_prof = np.abs(R.smooth_ic(prof, *args, clip=False) - prof).max()
     moved_step = np.abs(R.smooth_ic(step, *args, clip=False) - step).max()
-    assert moved_prof < 0.02 * moved_step, (moved_prof, moved_step)
+    assert moved_prof < 1e-3 * moved_step, (moved_prof, moved_step)
