@@ -159,6 +159,48 @@ def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, g
     return out
 
 
+# HBM bytes per cell of one relaxation step with FP64 transforms: right-hand
+# side (read phi, write rhs), row DCT (read rhs, write one field), column solve
+# (read one, write two), row inverse (read two, write two FP64 fields).
+SMOOTH_BYTES_PER_CELL_FP64 = 16 + 16 + 24 + 32
+
+
+def smooth_bench(C, torch, np, member, args, dev):
+    """Time ccmsav_smooth_ic (App. F: M = 0.01, dt = 1e-6, ten steps per call)."""
+    nsub = 10
+    sharp = torch.from_numpy(np.where(member.phi0 > 0.0, 1.0, -1.0)).to(dev)
+    out = torch.empty_like(sharp)
+    ctx = C.Context(member.params, member.phi0, member.psi0, args.precision)
+    lib = C.load()
+    call = lambda: C._check(lib.ccmsav_smooth_ic(ctx._h, 0.01, 1e-6, nsub, sharp.data_ptr(),  # noqa: E731
+                                                 out.data_ptr()), "ccmsav_smooth_ic")
+    for _ in range(max(1, args.warmup)):
+        call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        call()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.close()
+    cells = member.phi0.size
+    value = cells * nsub * args.steps / wall / 1e6
+    ms_call = 1e3 * wall / args.steps
+    frac = None
+    if args.precision == "fp64":
+        frac = SMOOTH_BYTES_PER_CELL_FP64 * value * 1e6 / 1e9 / HBM_PEAK_GBS
+    print(json.dumps({"metric": "App. F smoothing, Mcell-steps/s", "value": value,
+                      "unit": "Mcell-steps/s", "n_gpus": 1, "calls": args.steps,
+                      "steps_per_call": nsub, "ms_per_call": ms_call,
+                      "higher_is_better": True, "dtype": {"fp64": "f64", "mixed": "f32+f64"}.get(
+                          args.precision, args.precision),
+                      "data": "synthetic", "config": {"workload": args.workload,
+                                                      "nx": member.params["nx"],
+                                                      "ny": member.params["ny"],
+                                                      "precision": args.precision},
+                      "hbm_frac_of_step_model": frac}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +215,9 @@ def main():
     ap.add_argument("--scheme", default="bdf2", choices=["bdf2", "bdf1"],
                     help="time-stepping scheme: CC-MSAV-BDF2 (the default), or the "
                          "first-order CC-MSAV-BDF1 scheme at every step")
+    ap.add_argument("--smooth-ic", action="store_true",
+                    help="instead of the step, time the App. F initial-condition relaxation "
+                         "(ccmsav_smooth_ic, ten steps per call) on the workload's first grid")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 run that the mixed path is checked and compared against")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -194,6 +239,9 @@ def main():
     cells = sum(m.phi0.size for m in members)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.smooth_ic:
+        smooth_bench(C, torch, np, members[0], args, dev)
+        return
 
     bdf1 = args.scheme == "bdf1"
     run = timed_run(C, torch, members, args.precision, args.steps, args.warmup,

@@ -224,6 +224,23 @@ int ccmsav_sync(ccmsav_ctx* c);
  */
 int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, double* out_zeta);
 
+/*
+ * Smoothed initial phase field (App. F): from phi_sharp, take nsteps steps of
+ * the constant-mobility Cahn-Hilliard relaxation phi_t = M Delta(f'(phi)/eps
+ * - eps Delta phi), first order and semi-implicit,
+ *   (1/dt + M eps Delta_h^2) phi^{k+1} = phi^k/dt + (M/eps) Delta_h((phi^k)^3 - phi^k),
+ * with Neumann boundaries, the biharmonic term solved by the fast direct
+ * solver of App. C; then clip to [-1, 1] and write phi_out. App. F takes
+ * M = 0.01, dt = 1e-6 and ten steps. The grid, h and eps are the context's
+ * (single-member contexts), the transforms its precision (FP64, or FP32 for
+ * CCMSAV_MIXED). phi_sharp, phi_out: nx*ny doubles, host or device; they may
+ * be the same array. Uses the context's work buffers, not its state.
+ * Synchronises the stream. EINVAL for NULL pointers, M or dt not positive,
+ * nsteps < 0 or an ensemble; EUNSUPPORTED for the DCT-as-GEMM precision.
+ */
+int ccmsav_smooth_ic(ccmsav_ctx* c, double M, double dt, int32_t nsteps, const double* phi_sharp,
+                     double* phi_out);
+
 /* Release the context (and the workspace if the library allocated it). */
 int ccmsav_destroy(ccmsav_ctx* c);
 

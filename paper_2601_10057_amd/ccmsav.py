@@ -33,7 +33,7 @@ EXPORTED = (
     "ccmsav_sync", "ccmsav_elliptic_solve", "ccmsav_destroy", "ccmsav_strerror",
     "ccmsav_profile_steps", "ccmsav_workspace_bytes_batch", "ccmsav_init_batch",
     "ccmsav_members", "ccmsav_energy_m", "ccmsav_mass_m", "ccmsav_get_fields_m",
-    "ccmsav_get_savs_m", "ccmsav_tuning",
+    "ccmsav_get_savs_m", "ccmsav_tuning", "ccmsav_smooth_ic",
 )
 PHASES = ("stencil", "row_dct", "col_gram", "solve5", "col_solve", "row_idct")
 
@@ -99,6 +99,7 @@ def load() -> ctypes.CDLL:
     lib.ccmsav_sync.argtypes = [vp]
     lib.ccmsav_profile_steps.argtypes = [vp, ctypes.c_int32, dp]
     lib.ccmsav_elliptic_solve.argtypes = [vp, vp, vp, vp]
+    lib.ccmsav_smooth_ic.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp]
     lib.ccmsav_destroy.argtypes = [vp]
     lib.ccmsav_workspace_bytes_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Params)]
     lib.ccmsav_workspace_bytes_batch.restype = ctypes.c_size_t
@@ -117,7 +118,8 @@ def load() -> ctypes.CDLL:
     lib.ccmsav_strerror.restype = ctypes.c_char_p
     for fn in ("ccmsav_init", "ccmsav_step", "ccmsav_energy", "ccmsav_mass",
                "ccmsav_get_fields", "ccmsav_get_savs", "ccmsav_sync",
-               "ccmsav_elliptic_solve", "ccmsav_destroy", "ccmsav_profile_steps",
+               "ccmsav_elliptic_solve", "ccmsav_smooth_ic", "ccmsav_destroy",
+               "ccmsav_profile_steps",
                "ccmsav_init_batch", "ccmsav_energy_m", "ccmsav_mass_m",
                "ccmsav_get_fields_m", "ccmsav_get_savs_m"):
         getattr(lib, fn).restype = ctypes.c_int
@@ -292,6 +294,19 @@ class Context:
         """chi^{-1} rhs and zeta^{-1} rhs (device tensors) with the BDF2 operators."""
         _check(load().ccmsav_elliptic_solve(self._h, _ptr(rhs), _ptr(out_chi), _ptr(out_zeta)),
                "ccmsav_elliptic_solve")
+
+    def smooth_ic(self, phi_sharp, M: float = 0.01, dt: float = 1e-6, nsteps: int = 10):
+        """App. F relaxation of a sharp phase field on this context's grid;
+        returns the smoothed, clipped field as a numpy array."""
+        src = phi_sharp
+        if isinstance(src, np.ndarray):
+            src = np.ascontiguousarray(src, dtype=np.float64)
+        if tuple(src.shape) != self.shapes[0]:
+            raise ValueError(f"phi_sharp must have shape {self.shapes[0]}")
+        out = np.empty(self.shapes[0], dtype=np.float64)
+        _check(load().ccmsav_smooth_ic(self._h, float(M), float(dt), int(nsteps), _ptr(src),
+                                       _ptr(out)), "ccmsav_smooth_ic")
+        return out
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -21,6 +21,7 @@
 #include "ccmsav.h"
 #include "diag_kernels.hpp"
 #include "gemm_dct.hpp"
+#include "smooth_kernels.hpp"
 #include "step_kernels.hpp"
 
 using namespace ccm;
@@ -832,6 +833,49 @@ const char* kStatusText[] = {
 
 }  // namespace
 
+namespace {
+
+// Upload `a` (a copy of the standalone-solve table entry, with the operator
+// constants to use) as that entry, with the outputs of member 0's solve: an
+// output that is not requested goes to intermediate slots 2-3, which the
+// solve does not read.
+int set_solve_args(ccmsav_ctx* c, MemberArgs a, double* out_chi, double* out_zeta) {
+  const Member& m = c->mem[0];
+  const size_t me = mid_elem(c->precision);
+  double* tmp = reinterpret_cast<double*>(static_cast<char*>(m.mid) +
+                                          2 * strip_field(m.p.nx, m.p.ny, (int)me) * me);
+  a.phi_new = to_global(out_chi ? out_chi : tmp);
+  a.psi_new = to_global(out_zeta ? out_zeta : tmp);
+  MemberArgs* d = c->d_args + (size_t)kSolveTable * c->mem.size();
+  HIP_TRY(hipMemcpyAsync(d, &a, sizeof(MemberArgs), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return CCMSAV_OK;
+}
+
+// chi^{-1} rhs and zeta^{-1} rhs of member 0 with the uploaded solve entry,
+// on the context's stream: row DCT-II, column solve, row DCT-III.
+void launch_solve(ccmsav_ctx* c, const double* rhs) {
+  const Member& m = c->mem[0];
+  const MemberArgs* d = c->d_args + (size_t)kSolveTable * c->mem.size();
+  const SizeClass& k = c->cls[0];
+  auto run = [&](auto tm) {
+    using TM = decltype(tm);
+    using LT = typename Launch<TM>::T;
+    LT::t_rd[m.lx - kMinLog](c->stream, m.p.ny, rhs, static_cast<TM*>(m.mid), M_F, m.p.ny);
+    LT::t_col_solve[k.var[TUNE_COL_SOLVE]][m.ly - kMinLog](c->stream, m.p.nx,
+                                                           Batch{d, k.d_idx, m.p.nx});
+    const int vi = k.var[TUNE_ROW_IDCT];
+    const int per = m.p.ny / row_idct_rows<TM>(m.p.nx, vi);
+    LT::t_row_idct[vi][m.lx - kMinLog](c->stream, per, Batch{d, k.d_idx, per});
+  };
+  if (c->precision != CCMSAV_FP64)
+    run(0.0f);
+  else
+    run(0.0);
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t ccmsav_workspace_bytes_batch(int32_t nmemb, const ccmsav_params* p) {
@@ -1185,37 +1229,49 @@ int32_t ccmsav_tuning(const ccmsav_ctx* c, int32_t max_shapes, int32_t* info, do
   return (int32_t)c->cls.size();
 }
 
+
 int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, double* out_zeta) {
   if (!c || !rhs || c->mem.size() != 1) return CCMSAV_EINVAL;
+  const int r = set_solve_args(c, c->h_args[(size_t)kSolveTable * c->mem.size()], out_chi,
+                               out_zeta);
+  if (r != CCMSAV_OK) return r;
+  launch_solve(c, rhs);
+  return hipGetLastError() == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
+}
+
+int ccmsav_smooth_ic(ccmsav_ctx* c, double M, double dt, int32_t nsteps, const double* phi_sharp,
+                     double* phi_out) {
+  if (!c || !phi_sharp || !phi_out || c->mem.size() != 1 || nsteps < 0) return CCMSAV_EINVAL;
+  if (!(M > 0.0) || !(dt > 0.0) || !std::isfinite(M) || !std::isfinite(dt)) return CCMSAV_EINVAL;
+  if (is_gemm(c->precision)) return CCMSAV_EUNSUPPORTED;
   const Member& m = c->mem[0];
-  // The row DCT-III writes both results; an output that is not requested goes
-  // to intermediate slots 2-3, which the solve does not read.
-  const size_t me = mid_elem(c->precision);
-  double* tmp = reinterpret_cast<double*>(static_cast<char*>(m.mid) +
-                                          2 * strip_field(m.p.nx, m.p.ny, (int)me) * me);
-  MemberArgs& a = c->h_args[(size_t)kSolveTable * c->mem.size()];
-  a.phi_new = to_global(out_chi ? out_chi : tmp);
-  a.psi_new = to_global(out_zeta ? out_zeta : tmp);
-  MemberArgs* d = c->d_args + (size_t)kSolveTable * c->mem.size();
-  HIP_TRY(hipMemcpyAsync(d, &a, sizeof(MemberArgs), hipMemcpyHostToDevice, c->stream));
+  const int nx = m.p.nx, ny = m.p.ny;
+  const size_t cells = (size_t)nx * ny;
+  // The stencil output region holds 8 fields of >= 4 bytes per cell: room for
+  // the iterate and the right-hand side in FP64. It is rewritten by every step.
+  double* cur = static_cast<double*>(m.rm);
+  double* rhs = cur + cells;
+  HIP_TRY(hipMemcpyAsync(cur, phi_sharp, cells * sizeof(double), hipMemcpyDefault, c->stream));
+  // chi = C1 - C2 Delta_h + C3 Delta_h^2 with C1 = 1/dt, C2 = 0, C3 = M eps
+  MemberArgs a = c->h_args[(size_t)kSolveTable * c->mem.size()];
+  a.k.C1 = 1.0 / dt;
+  a.k.C2 = 0.0;
+  a.k.C3 = M * m.p.eps;
+  a.k.alpha = 1.0 / dt;      // the unused zeta output stays well defined
+  a.k.lam = 0.0;
+  const int r = set_solve_args(c, a, cur, nullptr);
+  if (r != CCMSAV_OK) return r;
+  const dim3 grid((nx + SMOOTH_THREADS - 1) / SMOOTH_THREADS, ny);
+  for (int32_t s = 0; s < nsteps; ++s) {
+    hipLaunchKernelGGL(k_smooth_rhs, grid, dim3(SMOOTH_THREADS), 0, c->stream, cur, rhs, nx, ny,
+                       1.0 / dt, M / m.p.eps, 1.0 / (m.p.h * m.p.h));
+    launch_solve(c, rhs);
+  }
+  const int blocks = (int)std::min<size_t>((cells + SMOOTH_THREADS - 1) / SMOOTH_THREADS, 4096);
+  hipLaunchKernelGGL(k_clip_unit, dim3(blocks), dim3(SMOOTH_THREADS), 0, c->stream, cur, cells);
+  HIP_TRY(hipMemcpyAsync(phi_out, cur, cells * sizeof(double), hipMemcpyDefault, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
-  const SizeClass& k = c->cls[0];
-  auto run = [&](auto tm) {
-    using TM = decltype(tm);
-    using LT = typename Launch<TM>::T;
-    LT::t_rd[m.lx - kMinLog](c->stream, m.p.ny, rhs, static_cast<TM*>(m.mid), M_F, m.p.ny);
-    LT::t_col_solve[k.var[TUNE_COL_SOLVE]][m.ly - kMinLog](c->stream, m.p.nx,
-                                                           Batch{d, k.d_idx, m.p.nx});
-    const int vi = k.var[TUNE_ROW_IDCT];
-    const int per = m.p.ny / row_idct_rows<TM>(m.p.nx, vi);
-    LT::t_row_idct[vi][m.lx - kMinLog](c->stream, per, Batch{d, k.d_idx, per});
-  };
-  if (c->precision != CCMSAV_FP64)
-    run(0.0f);
-  else
-    run(0.0);
-  if (hipGetLastError() != hipSuccess) return CCMSAV_EHIP;
-  return CCMSAV_OK;
+  return hipGetLastError() == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
 }
 
 int ccmsav_destroy(ccmsav_ctx* c) {
