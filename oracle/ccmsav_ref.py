@@ -514,6 +514,26 @@ def run(phi0, psi0, params: Dict, nsteps: int, use_matrix=None, bdf1: bool = Fal
 
 
 # ---------------------------------------------------------------------------
+# Physical free energy and arc length (Sec. 2.1)
+# ---------------------------------------------------------------------------
+
+def physical_energy(phi, psi, p: Params) -> Dict:
+    """F = F^surf + F^bend + F^area + F^osm of eq. (energy_functional) with
+    the densities of eq. (energy_densities), in the discrete forms of the
+    scheme (cell |grad phi|^2, five-point Laplacian, h^2 sums); the arc
+    length is int f_surf, the quantity F^area holds at A."""
+    L = integral(f_surf(phi, p), p.h)
+    omega = (phi ** 3 - phi) / p.eps - p.eps * lap(phi, p.h)
+    bend = p.gamma_bend * integral(3.0 * SQ2 / (16.0 * p.eps) * omega ** 2, p.h)
+    surf = p.gamma_surf * L
+    area = 0.5 * p.gamma_area * (L - p.A) ** 2
+    pp = p_interp(phi)
+    osm = integral(0.5 * (1.0 + pp) * f_in(psi, p) + 0.5 * (1.0 - pp) * f_out(psi, p), p.h)
+    return dict(F=surf + bend + area + osm, surf=surf, bend=bend, area=area, osm=osm,
+                arc_length=L)
+
+
+# ---------------------------------------------------------------------------
 # Smoothed initial conditions (App. F)
 # ---------------------------------------------------------------------------
 

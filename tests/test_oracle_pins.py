@@ -423,3 +423,45 @@ def test_smoothing_keeps_the_equilibrium_profile():
     moved_prof = np.abs(R.smooth_ic(prof, *args, clip=False) - prof).max()
     moved_step = np.abs(R.smooth_ic(step, *args, clip=False) - step).max()
     assert moved_prof < 1e-3 * moved_step, (moved_prof, moved_step)
+
+
+# ---------------------------------------------------------------- physical energy (Sec. 2.1)
+
+def test_physical_energy_of_uniform_states():
+    """phi = 1 everywhere: no interface, so F^surf = F^bend = 0, F^area = A^2
+    gamma_area / 2, and F^osm = |Omega| f_in(psi)."""
+    n, h = 16, 0.1
+    params = moderate_params(n, n, h, A=0.7)
+    p = R.Params.from_dict(params)
+    phi = np.ones((n, n))
+    psi = np.full((n, n), 0.3)
+    e = R.physical_energy(phi, psi, p)
+    area = (n * h) ** 2
+    assert e["surf"] == 0.0 and e["bend"] == 0.0 and e["arc_length"] == 0.0
+    assert math.isclose(e["area"], 0.5 * p.gamma_area * 0.7 ** 2, rel_tol=1e-14)
+    f_in = 0.5 * p.gamma_in * (0.3 - p.psi_in) ** 2 + p.beta_in
+    assert math.isclose(e["osm"], area * f_in, rel_tol=1e-12)
+    e2 = R.physical_energy(-phi, psi, p)
+    f_out = 0.5 * p.gamma_out * (0.3 - p.psi_out) ** 2 + p.beta_out
+    assert math.isclose(e2["osm"], area * f_out, rel_tol=1e-12)
+
+
+def test_arc_length_and_bending_energy_of_a_circle():
+    """Sharp-interface limits for phi = tanh((R - r)/(sqrt2 eps)): the
+    normalised surface density integrates to the perimeter 2 pi R, and the
+    bending density to pi / (2 R) (kappa^2 / 4 per unit length: the 1D profile
+    has int phi'^2 = 2 sqrt2 / (3 eps)); corrections are O((eps / R)^2) and,
+    with about 8 cells across eps, O((h / eps)^2)."""
+    n = 512
+    Lbox = 2.0 * math.pi
+    h = Lbox / n
+    x = (np.arange(n) + 0.5) * h
+    X, Y = np.meshgrid(x, x)
+    R0 = 0.3 * Lbox
+    eps = R0 / 20.0
+    phi = np.tanh((R0 - np.hypot(X - Lbox / 2, Y - Lbox / 2)) / (math.sqrt(2.0) * eps))
+    psi = np.zeros_like(phi)
+    p = R.Params.from_dict(moderate_params(n, n, h, eps=eps, gamma_bend=1.0, A=0.0))
+    e = R.physical_energy(phi, psi, p)
+    assert abs(e["arc_length"] / (2.0 * math.pi * R0) - 1.0) < 1e-3, e["arc_length"]
+    assert abs(e["bend"] / (math.pi / (2.0 * R0)) - 1.0) < 1e-2, e["bend"]
