@@ -174,6 +174,16 @@ int ccmsav_energy(ccmsav_ctx* c, double* E_mod, double* parts);
  * NULL. Synchronises the stream. */
 int ccmsav_mass(ccmsav_ctx* c, double* mass_psi, double* mass_phi);
 
+/*
+ * Physical free energy of Sec. 2.1 at level n (eq. energy_functional with the
+ * densities of eq. energy_densities, in the scheme's discrete forms: cell
+ * |grad phi|^2, five-point Delta_h with Neumann ghosts, h^2 sums), into
+ * out6 = {F, F^surf, F^bend, F^area, F^osm, int f_surf}; the last is the arc
+ * length that F^area holds at A. Synchronises the stream.
+ */
+int ccmsav_physical_energy(ccmsav_ctx* c, double out6[6]);
+int ccmsav_physical_energy_m(ccmsav_ctx* c, int32_t member, double out6[6]);
+
 /* Copy phi^n and psi^n (nx*ny doubles each, host or device; either may be
  * NULL). Synchronises the stream. */
 int ccmsav_get_fields(ccmsav_ctx* c, double* phi, double* psi);

@@ -33,7 +33,8 @@ EXPORTED = (
     "ccmsav_sync", "ccmsav_elliptic_solve", "ccmsav_destroy", "ccmsav_strerror",
     "ccmsav_profile_steps", "ccmsav_workspace_bytes_batch", "ccmsav_init_batch",
     "ccmsav_members", "ccmsav_energy_m", "ccmsav_mass_m", "ccmsav_get_fields_m",
-    "ccmsav_get_savs_m", "ccmsav_tuning", "ccmsav_smooth_ic",
+    "ccmsav_get_savs_m", "ccmsav_tuning", "ccmsav_smooth_ic", "ccmsav_physical_energy",
+    "ccmsav_physical_energy_m",
 )
 PHASES = ("stencil", "row_dct", "col_gram", "solve5", "col_solve", "row_idct")
 
@@ -100,6 +101,8 @@ def load() -> ctypes.CDLL:
     lib.ccmsav_profile_steps.argtypes = [vp, ctypes.c_int32, dp]
     lib.ccmsav_elliptic_solve.argtypes = [vp, vp, vp, vp]
     lib.ccmsav_smooth_ic.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp]
+    lib.ccmsav_physical_energy.argtypes = [vp, dp]
+    lib.ccmsav_physical_energy_m.argtypes = [vp, ctypes.c_int32, dp]
     lib.ccmsav_destroy.argtypes = [vp]
     lib.ccmsav_workspace_bytes_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Params)]
     lib.ccmsav_workspace_bytes_batch.restype = ctypes.c_size_t
@@ -119,6 +122,7 @@ def load() -> ctypes.CDLL:
     for fn in ("ccmsav_init", "ccmsav_step", "ccmsav_energy", "ccmsav_mass",
                "ccmsav_get_fields", "ccmsav_get_savs", "ccmsav_sync",
                "ccmsav_elliptic_solve", "ccmsav_smooth_ic", "ccmsav_destroy",
+               "ccmsav_physical_energy", "ccmsav_physical_energy_m",
                "ccmsav_profile_steps",
                "ccmsav_init_batch", "ccmsav_energy_m", "ccmsav_mass_m",
                "ccmsav_get_fields_m", "ccmsav_get_savs_m"):
@@ -294,6 +298,13 @@ class Context:
         """chi^{-1} rhs and zeta^{-1} rhs (device tensors) with the BDF2 operators."""
         _check(load().ccmsav_elliptic_solve(self._h, _ptr(rhs), _ptr(out_chi), _ptr(out_zeta)),
                "ccmsav_elliptic_solve")
+
+    def physical_energy(self, member: int = 0):
+        """F and its parts (Sec. 2.1) at the current level, and the arc length."""
+        out = (ctypes.c_double * 6)()
+        _check(load().ccmsav_physical_energy_m(self._h, int(member), out),
+               "ccmsav_physical_energy_m")
+        return dict(zip(("F", "surf", "bend", "area", "osm", "arc_length"), list(out)))
 
     def smooth_ic(self, phi_sharp, M: float = 0.01, dt: float = 1e-6, nsteps: int = 10):
         """App. F relaxation of a sharp phase field on this context's grid;

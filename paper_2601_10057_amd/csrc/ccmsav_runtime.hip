@@ -1174,6 +1174,29 @@ int ccmsav_mass(ccmsav_ctx* c, double* mass_psi, double* mass_phi) {
   return ccmsav_mass_m(c, 0, mass_psi, mass_phi);
 }
 
+int ccmsav_physical_energy_m(ccmsav_ctx* c, int32_t member, double out6[6]) {
+  if (!valid_member(c, member) || !out6) return CCMSAV_EINVAL;
+  const Member& m = c->mem[member];
+  const int sn = (int)(c->level % 3);
+  const DiagConst d = make_diag(m.p);
+  hipLaunchKernelGGL(k_phys_sums, dim3(m.p.ny), dim3(DIAG_THREADS), 0, c->stream, m.phi[sn],
+                     m.psi[sn], m.parte, m.p.nx, m.p.ny, d);
+  hipLaunchKernelGGL(k_phys_final, dim3(1), dim3(DIAG_THREADS), 0, c->stream, m.parte, m.p.ny,
+                     m.ds, d);
+  if (hipGetLastError() != hipSuccess) return CCMSAV_EHIP;
+  double t[9];
+  HIP_TRY(hipMemcpyAsync(t, m.ds->totals, sizeof(t), hipMemcpyDeviceToHost, c->stream));
+  int err = 0;
+  const int r = read_err_member(c, member, &err);
+  if (r != CCMSAV_OK) return r;
+  for (int i = 0; i < 6; ++i) out6[i] = t[3 + i];
+  return status_from_err(err);
+}
+
+int ccmsav_physical_energy(ccmsav_ctx* c, double out6[6]) {
+  return ccmsav_physical_energy_m(c, 0, out6);
+}
+
 int ccmsav_get_fields_m(ccmsav_ctx* c, int32_t member, double* phi, double* psi) {
   if (!valid_member(c, member)) return CCMSAV_EINVAL;
   const Member& m = c->mem[member];

@@ -74,6 +74,65 @@ k_init_final(const double* __restrict__ part, int ny, DevScalars* __restrict__ d
   ds->err = err;
 }
 
+// Physical free energy of Sec. 2.1 (eq. energy_functional, densities of eq.
+// energy_densities) at (phi, psi): sums of f_surf, of (g'(phi)/eps - eps
+// Delta_h phi)^2 and of f_osm, one row per block (Neumann ghosts copy the
+// boundary cell).
+enum PhysSum { Q_SURF = 0, Q_BEND, Q_OSM, Q_NSUM };
+
+__global__ void __launch_bounds__(DIAG_THREADS)
+k_phys_sums(const double* __restrict__ phi, const double* __restrict__ psi,
+            double* __restrict__ part, int nx, int ny, DiagConst c) {
+  __shared__ double red[Q_NSUM * (DIAG_THREADS / 64 + 1)];
+  const int tid = threadIdx.x, j = blockIdx.x;
+  const int jn = min(j + 1, ny - 1), js = max(j - 1, 0);
+  const double k32 = 0.75 * 1.4142135623730950488;
+  double v[Q_NSUM] = {0.0, 0.0, 0.0};
+  for (int i = tid; i < nx; i += DIAG_THREADS) {
+    const int ie = min(i + 1, nx - 1), iw = max(i - 1, 0);
+    const double p = phi[(size_t)j * nx + i];
+    const double gxe = (phi[(size_t)j * nx + ie] - p) * c.inv_h;
+    const double gxw = (p - phi[(size_t)j * nx + iw]) * c.inv_h;
+    const double gyn = (phi[(size_t)jn * nx + i] - p) * c.inv_h;
+    const double gys = (p - phi[(size_t)js * nx + i]) * c.inv_h;
+    const double grad2 = 0.5 * (gxe * gxe + gxw * gxw + gyn * gyn + gys * gys);
+    const double lap = ((gxe - gxw) + (gyn - gys)) * c.inv_h;
+    const double t = p * p - 1.0;
+    v[Q_SURF] += k32 * (0.25 * t * t / c.eps + 0.5 * c.eps * grad2);
+    const double om = p * t / c.eps - c.eps * lap;
+    v[Q_BEND] += om * om;
+    const double s = psi[(size_t)j * nx + i];
+    const double pp = sinpi(0.5 * p);
+    const double fin = 0.5 * c.gamma_in * (s - c.psi_in) * (s - c.psi_in) + c.beta_in;
+    const double fout = 0.5 * c.gamma_out * (s - c.psi_out) * (s - c.psi_out) + c.beta_out;
+    v[Q_OSM] += 0.5 * ((1.0 + pp) * fin + (1.0 - pp) * fout);
+  }
+  block_sum<Q_NSUM, DIAG_THREADS>(v, red, tid);
+  if (tid < Q_NSUM) part[(size_t)j * Q_NSUM + tid] = red[tid];
+}
+
+// F, F^surf, F^bend, F^area, F^osm and the arc length int f_surf into
+// totals[3..8] (the arc-length target A is totals[0]).
+__global__ void __launch_bounds__(DIAG_THREADS)
+k_phys_final(const double* __restrict__ part, int ny, DevScalars* __restrict__ ds, DiagConst c) {
+  __shared__ double red[Q_NSUM * (DIAG_THREADS / 64 + 1)];
+  double T[Q_NSUM];
+  reduce_rows<Q_NSUM, DIAG_THREADS>(part, ny, red, threadIdx.x, T);
+  if (threadIdx.x != 0) return;
+  const double L = c.h2 * T[Q_SURF];
+  const double surf = c.gamma_surf * L;
+  const double bend = c.gamma_bend * 3.0 * 1.4142135623730950488 / (16.0 * c.eps) * c.h2 * T[Q_BEND];
+  const double dA = L - ds->totals[0];
+  const double area = 0.5 * c.gamma_area * dA * dA;
+  const double osm = c.h2 * T[Q_OSM];
+  ds->totals[3] = surf + bend + area + osm;
+  ds->totals[4] = surf;
+  ds->totals[5] = bend;
+  ds->totals[6] = area;
+  ds->totals[7] = osm;
+  ds->totals[8] = L;
+}
+
 // Energy norms of levels (n, n-1), ||d^n||^2 from (n, n-1, n-2), and masses.
 __global__ void __launch_bounds__(DIAG_THREADS)
 k_energy_sums(const double* __restrict__ p1, const double* __restrict__ p0,
