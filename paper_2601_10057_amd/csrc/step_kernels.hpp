@@ -633,21 +633,60 @@ __device__ __forceinline__ void fetch_strip(gptr<const cpx<TM>> __restrict__ src
   }
 }
 
+// Whether the column transform can take its first FFT stage straight from the
+// loaded registers: one radix-R butterfly per thread in every stage, so that
+// thread tid's first butterfly reads Makhoul-ordered elements tid + q (N/R).
+template <int NY, int NTHR, int R> constexpr bool first_stage_in_registers() {
+  return NY / R == NTHR && Plan<NY, R>::FIRST == R && NY > R;
+}
+
+// Loads for first_stage_in_registers: v[q] = element k = tid + q (NY/R) of the
+// Makhoul-reordered strip, i.e. row 2k for k < NY/2 and row 2(NY-1-k)+1 above.
+template <typename TM, int NY, int R, int NTHR>
+__device__ __forceinline__ void fetch_strip_first(gptr<const cpx<TM>> __restrict__ src, int tid,
+                                                  StripRegs<TM, R>& r) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int k = tid + q * (NY / R);
+    const int row = k < NY / 2 ? 2 * k : 2 * (NY - 1 - k) + 1;
+    r.v[q] = gload<TM>(src + row);
+  }
+}
+
 // DCT-II along y of a strip held in registers: A (column 2s) and B (column
 // 2s + 1) for the bins of the thread's pair units u = tid + q NTHR, bin u at
 // index 2q and bin pair_mirror(u) at 2q + 1. The FFT radix R gives one
-// butterfly per thread in each stage.
-template <typename TM, int NY, int LPT, int UPT, int NTHR, int R, typename MAP>
+// butterfly per thread in each stage. With FIRST_IN_REGS the registers hold
+// the inputs of the thread's first-stage butterfly (fetch_strip_first): that
+// stage runs on them and stores its outputs, saving one pass through LDS.
+template <typename TM, int NY, int LPT, int UPT, int NTHR, int R, typename MAP,
+          bool FIRST_IN_REGS = false>
 __device__ __forceinline__ void column_dct2(const StripRegs<TM, LPT>& in, cpx<TM>* line,
                                             const Roots<TM, NY>& rt,
                                             const LineSlots<NY, NTHR, R, MAP>& sl, int tid,
                                             TM (&A)[2 * UPT], TM (&B)[2 * UPT]) {
-  static_for<LPT>([&](auto iq) {
-    constexpr int q = decltype(iq)::value;
-    if (NY >= NTHR || tid + q * NTHR < NY) line[sl.template mak<q>()] = in.v[q];
-  });
-  lds_sync();
-  fft_lines<TM, NY, 1, NTHR, R, MAP>(line, rt, tid);
+  if constexpr (FIRST_IN_REGS) {
+    static_assert(LPT == R && first_stage_in_registers<NY, NTHR, R>(), "one butterfly per thread");
+    // the first stage of fft_lines (block length NY, stride NY/R) on butterfly tid
+    constexpr int S = NY / R;
+    cpx<TM> v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) v[q] = in.v[q];
+    SmallDFT<TM, R>::run(v);
+    apply_twiddles<TM, NY, R>(rt, tid, v);
+    const int e = MAP::at(tid);
+#pragma unroll
+    for (int q = 0; q < R; ++q) line[e ^ MAP::at(q * S)] = v[q];
+    lds_sync();
+    DifRunner<TM, NY, 1, NTHR, S, false, R, MAP>::run(line, rt, tid);
+  } else {
+    static_for<LPT>([&](auto iq) {
+      constexpr int q = decltype(iq)::value;
+      if (NY >= NTHR || tid + q * NTHR < NY) line[sl.template mak<q>()] = in.v[q];
+    });
+    lds_sync();
+    fft_lines<TM, NY, 1, NTHR, R, MAP>(line, rt, tid);
+  }
   static_for<UPT>([&](auto iq) {
     constexpr int q = decltype(iq)::value;
     const int u = tid + q * NTHR;
@@ -765,18 +804,28 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   // lines have no registers to spare for it).
   constexpr int ORDER[8] = {M_S, M_H, M_Q, M_K, M_F, M_P, M_G, M_L};
   constexpr bool PREFETCH = sizeof(TM) == 4;
+  // The first FFT stage runs on the loaded registers where every stage has
+  // one butterfly per thread.
+  constexpr bool FIRST_IN_REGS = first_stage_in_registers<NY, NTHR, GR>() && LPT == GR;
   StripRegs<TM, LPT> nxt;
-  if constexpr (PREFETCH) fetch_strip<TM, NY, LPT, NTHR>(strip(ORDER[0]), tid, nxt);
+  auto fetch = [&](int f, StripRegs<TM, LPT>& r) {
+    if constexpr (FIRST_IN_REGS) {
+      fetch_strip_first<TM, NY, GR, NTHR>(strip(f), tid, r);
+    } else {
+      fetch_strip<TM, NY, LPT, NTHR>(strip(f), tid, r);
+    }
+  };
+  if constexpr (PREFETCH) fetch(ORDER[0], nxt);
   auto transform_next = [&](auto ii, TM (&A)[KPT], TM (&B)[KPT]) {
     constexpr int i = decltype(ii)::value;
     StripRegs<TM, LPT> cur;
     if constexpr (PREFETCH) {
       cur = nxt;
-      if constexpr (i + 1 < 8) fetch_strip<TM, NY, LPT, NTHR>(strip(ORDER[i + 1]), tid, nxt);
+      if constexpr (i + 1 < 8) fetch(ORDER[i + 1], nxt);
     } else {
-      fetch_strip<TM, NY, LPT, NTHR>(strip(ORDER[i]), tid, cur);
+      fetch(ORDER[i], cur);
     }
-    column_dct2<TM, NY, LPT, UPT, NTHR, GR, MAP>(cur, line, rt, sl, tid, A, B);
+    column_dct2<TM, NY, LPT, UPT, NTHR, GR, MAP, FIRST_IN_REGS>(cur, line, rt, sl, tid, A, B);
   };
   // chi group: S~, H, Q~, K~ transformed and kept; their inner products are
   // taken together with those of f_lin, bin by bin, so that each bin's
