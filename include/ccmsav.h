@@ -210,6 +210,18 @@ int64_t ccmsav_level(const ccmsav_ctx* c);
 int32_t ccmsav_tuning(const ccmsav_ctx* c, int32_t max_shapes, int32_t* info, double* ms);
 
 /*
+ * Fix the launch variants instead of the autotuner's choice: var3[t] for the
+ * row DCT, column solve and row inverse (0 or 1, or -1 to keep the current
+ * choice; before the first step the current choice is 0). Applies to every
+ * grid shape of the context, skips the autotuning of the first step, and
+ * drops a captured graph so that the next graph step captures the new
+ * launches. All variants compute bit-identical results. Synchronises the
+ * stream. EINVAL for a value outside [-1, 1]; EUNSUPPORTED for the
+ * DCT-as-GEMM precision, which has no variants.
+ */
+int ccmsav_set_launch_variants(ccmsav_ctx* c, const int32_t* var3);
+
+/*
  * Take nsteps >= 1 steps like ccmsav_step, with HIP events recorded on the
  * context's stream around each of the six kernels of a step, then wait and
  * write the mean duration in milliseconds of each kernel launch to

@@ -34,7 +34,7 @@ EXPORTED = (
     "ccmsav_profile_steps", "ccmsav_workspace_bytes_batch", "ccmsav_init_batch",
     "ccmsav_members", "ccmsav_energy_m", "ccmsav_mass_m", "ccmsav_get_fields_m",
     "ccmsav_get_savs_m", "ccmsav_tuning", "ccmsav_smooth_ic", "ccmsav_physical_energy",
-    "ccmsav_physical_energy_m",
+    "ccmsav_physical_energy_m", "ccmsav_set_launch_variants",
 )
 PHASES = ("stencil", "row_dct", "col_gram", "solve5", "col_solve", "row_idct")
 
@@ -103,6 +103,7 @@ def load() -> ctypes.CDLL:
     lib.ccmsav_smooth_ic.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp]
     lib.ccmsav_physical_energy.argtypes = [vp, dp]
     lib.ccmsav_physical_energy_m.argtypes = [vp, ctypes.c_int32, dp]
+    lib.ccmsav_set_launch_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     lib.ccmsav_destroy.argtypes = [vp]
     lib.ccmsav_workspace_bytes_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(Params)]
     lib.ccmsav_workspace_bytes_batch.restype = ctypes.c_size_t
@@ -123,6 +124,7 @@ def load() -> ctypes.CDLL:
                "ccmsav_get_fields", "ccmsav_get_savs", "ccmsav_sync",
                "ccmsav_elliptic_solve", "ccmsav_smooth_ic", "ccmsav_destroy",
                "ccmsav_physical_energy", "ccmsav_physical_energy_m",
+               "ccmsav_set_launch_variants",
                "ccmsav_profile_steps",
                "ccmsav_init_batch", "ccmsav_energy_m", "ccmsav_mass_m",
                "ccmsav_get_fields_m", "ccmsav_get_savs_m"):
@@ -298,6 +300,11 @@ class Context:
         """chi^{-1} rhs and zeta^{-1} rhs (device tensors) with the BDF2 operators."""
         _check(load().ccmsav_elliptic_solve(self._h, _ptr(rhs), _ptr(out_chi), _ptr(out_zeta)),
                "ccmsav_elliptic_solve")
+
+    def set_launch_variants(self, row_dct: int = -1, col_solve: int = -1, row_idct: int = -1):
+        """Fix the launch variants (0 or 1; -1 keeps the current choice)."""
+        v = (ctypes.c_int32 * 3)(row_dct, col_solve, row_idct)
+        _check(load().ccmsav_set_launch_variants(self._h, v), "ccmsav_set_launch_variants")
 
     def physical_energy(self, member: int = 0):
         """F and its parts (Sec. 2.1) at the current level, and the arc length."""

@@ -1235,6 +1235,30 @@ int ccmsav_get_savs(ccmsav_ctx* c, double out8[8]) { return ccmsav_get_savs_m(c,
 
 int64_t ccmsav_level(const ccmsav_ctx* c) { return c ? c->level : -1; }
 
+int ccmsav_set_launch_variants(ccmsav_ctx* c, const int32_t* var3) {
+  if (!c || !var3) return CCMSAV_EINVAL;
+  for (int t = 0; t < kNumTuned; ++t)
+    if (var3[t] < -1 || var3[t] >= kNumVariants) return CCMSAV_EINVAL;
+  if (is_gemm(c->precision)) return CCMSAV_EUNSUPPORTED;
+  // Finish the work enqueued with the old choice, and drop a graph captured
+  // with it (the next graph step captures again).
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->gstream) HIP_TRY(hipStreamSynchronize(c->gstream));
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  for (SizeClass& k : c->cls)
+    for (int t = 0; t < kNumTuned; ++t) {
+      if (var3[t] >= 0) k.var[t] = var3[t];
+      else if (!c->tuned) k.var[t] = 0;
+      if (!c->tuned)
+        for (int v = 0; v < kNumVariants; ++v) k.tune_ms[t][v] = 0.0f;
+    }
+  c->tuned = true;
+  return CCMSAV_OK;
+}
+
 int32_t ccmsav_tuning(const ccmsav_ctx* c, int32_t max_shapes, int32_t* info, double* ms) {
   if (!c || max_shapes < 0 || (max_shapes > 0 && !info)) return CCMSAV_EINVAL;
   if (!c->tuned) return 0;
