@@ -22,7 +22,9 @@ written, in its order and notation, with numpy for array arithmetic:
 * modified discrete energy: eq. (modified_discrete_energy); the dissipation
   quantities K^n, ||mu||^2, ||c + d/2||^2 of Thm. 3.1 / App. A;
 * smoothed initial conditions: App. F (constant-mobility Cahn-Hilliard
-  relaxation, biharmonic term implicit, then clipping).
+  relaxation, biharmonic term implicit, then clipping);
+* homogeneous Dirichlet boundaries for the fast solver (the DST that App. C
+  names for them): Laplacian with odd ghosts, DST-II matrix, eigenvalues.
 
 Readings where the paper is silent or ambiguous:
 face mobility is M_psi of the face-averaged phi*; the face average of phi^2
@@ -201,6 +203,64 @@ def neumann_lap_eigs(nx, ny, h):
 def spectral_solve(rhs, spectrum, use_matrix=None):
     """Fast direct solve of an operator diagonal in the DCT basis (App. C)."""
     return idct2(dct2(rhs, use_matrix) / spectrum, use_matrix)
+
+
+# ---------------------------------------------------------------------------
+# Homogeneous Dirichlet boundaries: the DST form of the fast solver (App. C)
+# ---------------------------------------------------------------------------
+
+def lap_dirichlet(u, h):
+    """Five-point Laplacian with homogeneous Dirichlet ghosts: the ghost cell
+    is minus its boundary neighbour (zero on the wall)."""
+    ny, nx = u.shape
+    g = np.zeros((ny + 2, nx + 2))
+    g[1:-1, 1:-1] = u
+    g[0, 1:-1], g[-1, 1:-1] = -u[0], -u[-1]
+    g[1:-1, 0], g[1:-1, -1] = -u[:, 0], -u[:, -1]
+    return (g[1:-1, 2:] + g[1:-1, :-2] + g[2:, 1:-1] + g[:-2, 1:-1] - 4.0 * u) / (h * h)
+
+
+def lap_dirichlet_matrix(nx, ny, h):
+    """Dense matrix of lap_dirichlet, built by applying it to unit vectors."""
+    n = nx * ny
+    L = np.zeros((n, n))
+    e = np.zeros((ny, nx))
+    for c in range(n):
+        e.flat[c] = 1.0
+        L[:, c] = lap_dirichlet(e, h).ravel()
+        e.flat[c] = 0.0
+    return L
+
+
+def dst_matrix(n: int) -> np.ndarray:
+    """Orthonormal DST-II matrix S[k, i] = s_k sin(pi (k + 1)(2 i + 1) / (2 n)),
+    s_k = sqrt(2/n) except s_{n-1} = sqrt(1/n)."""
+    k = np.arange(n)[:, None]
+    i = np.arange(n)[None, :]
+    S = np.sin(math.pi * (k + 1) * (2 * i + 1) / (2.0 * n)) * math.sqrt(2.0 / n)
+    S[-1, :] *= math.sqrt(0.5)
+    return S
+
+
+def dirichlet_lap_eigs(nx, ny, h):
+    """Eigenvalues of lap_dirichlet on the ``[ky, kx]`` grid of the DST-II:
+    -(4/h^2)(sin^2(pi (i+1)/2m) + sin^2(pi (j+1)/2n))."""
+    lx = -(4.0 / h ** 2) * np.sin(math.pi * (np.arange(nx) + 1) / (2.0 * nx)) ** 2
+    ly = -(4.0 / h ** 2) * np.sin(math.pi * (np.arange(ny) + 1) / (2.0 * ny)) ** 2
+    return ly[:, None] + lx[None, :]
+
+
+def spectral_solve_dirichlet(rhs, spectrum, use_matrix=None):
+    """Fast direct solve of an operator diagonal in the DST-II basis (the
+    Dirichlet counterpart of App. C's DCT solver)."""
+    ny, nx = rhs.shape
+    if use_matrix is None:
+        use_matrix = max(nx, ny) <= MATRIX_DCT_MAX
+    if use_matrix:
+        Sy, Sx = dst_matrix(ny), dst_matrix(nx)
+        return Sy.T @ ((Sy @ rhs @ Sx.T) / spectrum) @ Sx
+    from scipy.fft import dstn, idstn
+    return idstn(dstn(rhs, type=2, norm="ortho") / spectrum, type=2, norm="ortho")
 
 
 # ---------------------------------------------------------------------------

@@ -465,3 +465,42 @@ def test_arc_length_and_bending_energy_of_a_circle():
     e = R.physical_energy(phi, psi, p)
     assert abs(e["arc_length"] / (2.0 * math.pi * R0) - 1.0) < 1e-3, e["arc_length"]
     assert abs(e["bend"] / (math.pi / (2.0 * R0)) - 1.0) < 1e-2, e["bend"]
+
+
+# ---------------------------------------------------------------- Dirichlet solver (App. C)
+
+def test_dst_matrix_diagonalises_the_dirichlet_laplacian():
+    """Closed form: the orthonormal DST-II rows are eigenvectors of the 1D
+    Laplacian with odd ghosts, eigenvalue -(4/h^2) sin^2(pi (k+1) / 2n)."""
+    n, h = 12, 0.3
+    S = R.dst_matrix(n)
+    np.testing.assert_allclose(S @ S.T, np.eye(n), atol=1e-14)
+    L1 = np.zeros((n, n))
+    for i in range(n):
+        L1[i, i] = -2.0
+        if i > 0:
+            L1[i, i - 1] = 1.0
+        if i < n - 1:
+            L1[i, i + 1] = 1.0
+    L1[0, 0] = L1[-1, -1] = -3.0               # ghost = minus the boundary cell
+    L1 /= h * h
+    lam = -(4.0 / h ** 2) * np.sin(math.pi * (np.arange(n) + 1) / (2.0 * n)) ** 2
+    np.testing.assert_allclose(S @ L1 @ S.T, np.diag(lam), atol=1e-10 / h ** 2)
+    from scipy.fft import dst
+    x = np.random.default_rng(1).standard_normal(n)
+    np.testing.assert_allclose(S @ x, dst(x, type=2, norm="ortho"), atol=1e-13)
+
+
+def test_dirichlet_spectral_solve_equals_dense_solve():
+    nx, ny, h = 7, 5, 0.4
+    C1, C2, C3, alpha, lam = 3.0, 0.7, 0.2, 2.5, 0.9
+    rhs = np.random.default_rng(2).standard_normal((ny, nx))
+    L = R.lap_dirichlet_matrix(nx, ny, h)
+    lam_h = R.dirichlet_lap_eigs(nx, ny, h)
+    A_chi = C1 * np.eye(nx * ny) - C2 * L + C3 * (L @ L)
+    A_zeta = alpha * np.eye(nx * ny) - lam * L
+    for A, spec in ((A_chi, C1 - C2 * lam_h + C3 * lam_h ** 2), (A_zeta, alpha - lam * lam_h)):
+        ref = np.linalg.solve(A, rhs.ravel()).reshape(ny, nx)
+        for um in (True, False):
+            got = R.spectral_solve_dirichlet(rhs, spec, use_matrix=um)
+            np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-12)
