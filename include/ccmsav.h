@@ -246,6 +246,27 @@ int ccmsav_sync(ccmsav_ctx* c);
  */
 int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, double* out_zeta);
 
+/* Boundary conditions of the standalone fast direct solver. */
+#define CCMSAV_BC_NEUMANN 0
+#define CCMSAV_BC_DIRICHLET 1
+
+/*
+ * ccmsav_elliptic_solve with a choice of boundary condition. App. C pairs
+ * the DCT with homogeneous Neumann boundaries (CCMSAV_BC_NEUMANN, the same
+ * as ccmsav_elliptic_solve) and names the DST for homogeneous Dirichlet ones
+ * (CCMSAV_BC_DIRICHLET): Delta_h with ghost cells equal to minus their
+ * boundary neighbours, diagonalised by the orthonormal DST-II with
+ * eigenvalues -(4/h^2)(sin^2(pi (i+1)/(2 nx)) + sin^2(pi (j+1)/(2 ny))).
+ * The Dirichlet solve runs the DCT kernels on the input multiplied by
+ * (-1)^(i+j), with the eigenvalues re-indexed, and multiplies the outputs by
+ * (-1)^(i+j) (a DST-II is a DCT-II of the sign-alternated input read in
+ * reverse order). Same operators, buffers and ordering as
+ * ccmsav_elliptic_solve; EINVAL for another bc, EUNSUPPORTED for the
+ * DCT-as-GEMM precision with CCMSAV_BC_DIRICHLET.
+ */
+int ccmsav_elliptic_solve_bc(ccmsav_ctx* c, int32_t bc, const double* rhs, double* out_chi,
+                             double* out_zeta);
+
 /*
  * Smoothed initial phase field (App. F): from phi_sharp, take nsteps steps of
  * the constant-mobility Cahn-Hilliard relaxation phi_t = M Delta(f'(phi)/eps

@@ -26,6 +26,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDOMAIN",
 
 FLAG_GRAPH = 1
 FLAG_BDF1 = 2
+BC_NEUMANN, BC_DIRICHLET = 0, 1
 
 EXPORTED = (
     "ccmsav_workspace_bytes", "ccmsav_init", "ccmsav_step", "ccmsav_energy",
@@ -34,7 +35,7 @@ EXPORTED = (
     "ccmsav_profile_steps", "ccmsav_workspace_bytes_batch", "ccmsav_init_batch",
     "ccmsav_members", "ccmsav_energy_m", "ccmsav_mass_m", "ccmsav_get_fields_m",
     "ccmsav_get_savs_m", "ccmsav_tuning", "ccmsav_smooth_ic", "ccmsav_physical_energy",
-    "ccmsav_physical_energy_m", "ccmsav_set_launch_variants",
+    "ccmsav_physical_energy_m", "ccmsav_set_launch_variants", "ccmsav_elliptic_solve_bc",
 )
 PHASES = ("stencil", "row_dct", "col_gram", "solve5", "col_solve", "row_idct")
 
@@ -100,6 +101,7 @@ def load() -> ctypes.CDLL:
     lib.ccmsav_sync.argtypes = [vp]
     lib.ccmsav_profile_steps.argtypes = [vp, ctypes.c_int32, dp]
     lib.ccmsav_elliptic_solve.argtypes = [vp, vp, vp, vp]
+    lib.ccmsav_elliptic_solve_bc.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
     lib.ccmsav_smooth_ic.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp]
     lib.ccmsav_physical_energy.argtypes = [vp, dp]
     lib.ccmsav_physical_energy_m.argtypes = [vp, ctypes.c_int32, dp]
@@ -124,7 +126,7 @@ def load() -> ctypes.CDLL:
                "ccmsav_get_fields", "ccmsav_get_savs", "ccmsav_sync",
                "ccmsav_elliptic_solve", "ccmsav_smooth_ic", "ccmsav_destroy",
                "ccmsav_physical_energy", "ccmsav_physical_energy_m",
-               "ccmsav_set_launch_variants",
+               "ccmsav_set_launch_variants", "ccmsav_elliptic_solve_bc",
                "ccmsav_profile_steps",
                "ccmsav_init_batch", "ccmsav_energy_m", "ccmsav_mass_m",
                "ccmsav_get_fields_m", "ccmsav_get_savs_m"):
@@ -296,10 +298,12 @@ class Context:
         v = np.array(list(buf))
         return v[:4], v[4:]
 
-    def elliptic_solve(self, rhs, out_chi, out_zeta):
-        """chi^{-1} rhs and zeta^{-1} rhs (device tensors) with the BDF2 operators."""
-        _check(load().ccmsav_elliptic_solve(self._h, _ptr(rhs), _ptr(out_chi), _ptr(out_zeta)),
-               "ccmsav_elliptic_solve")
+    def elliptic_solve(self, rhs, out_chi, out_zeta, bc: str = "neumann"):
+        """chi^{-1} rhs and zeta^{-1} rhs (device tensors) with the BDF2
+        operators, for homogeneous Neumann (DCT) or Dirichlet (DST) boundaries."""
+        code = {"neumann": BC_NEUMANN, "dirichlet": BC_DIRICHLET}[bc]
+        _check(load().ccmsav_elliptic_solve_bc(self._h, code, _ptr(rhs), _ptr(out_chi),
+                                               _ptr(out_zeta)), "ccmsav_elliptic_solve_bc")
 
     def set_launch_variants(self, row_dct: int = -1, col_solve: int = -1, row_idct: int = -1):
         """Fix the launch variants (0 or 1; -1 keeps the current choice)."""

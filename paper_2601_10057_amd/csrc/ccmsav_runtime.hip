@@ -1286,6 +1286,50 @@ int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, dou
   return hipGetLastError() == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
 }
 
+int ccmsav_elliptic_solve_bc(ccmsav_ctx* c, int32_t bc, const double* rhs, double* out_chi,
+                             double* out_zeta) {
+  if (!c || !rhs || c->mem.size() != 1) return CCMSAV_EINVAL;
+  if (bc == CCMSAV_BC_NEUMANN) return ccmsav_elliptic_solve(c, rhs, out_chi, out_zeta);
+  if (bc != CCMSAV_BC_DIRICHLET) return CCMSAV_EINVAL;
+  if (is_gemm(c->precision)) return CCMSAV_EUNSUPPORTED;
+  const Member& m = c->mem[0];
+  const int nx = m.p.nx, ny = m.p.ny;
+  const size_t cells = (size_t)nx * ny;
+  // Work space in the stencil output region (rewritten by every step): the
+  // sign-alternated right-hand side and the two eigenvalue tables.
+  double* alt = static_cast<double*>(m.rm);
+  double* lx_d = alt + cells;
+  double* ly_d = lx_d + nx;
+  // Dirichlet eigenvalues of -Delta_h, (4/h^2) sin^2(pi (k+1) / (2 n)) for
+  // DST index k, at DCT index N - 1 - k: (4/h^2) cos^2(pi k' / (2 n)).
+  std::vector<double> lx(nx), ly(ny);
+  for (int k = 0; k < nx; ++k) {
+    const double cs = std::cos(M_PI * k / (2.0 * nx));
+    lx[k] = 4.0 / (m.p.h * m.p.h) * cs * cs;
+  }
+  for (int k = 0; k < ny; ++k) {
+    const double cs = std::cos(M_PI * k / (2.0 * ny));
+    ly[k] = 4.0 / (m.p.h * m.p.h) * cs * cs;
+  }
+  HIP_TRY(hipMemcpyAsync(lx_d, lx.data(), nx * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipMemcpyAsync(ly_d, ly.data(), ny * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  const dim3 grid((nx + SMOOTH_THREADS - 1) / SMOOTH_THREADS, ny);
+  hipLaunchKernelGGL(k_alternate_sign, grid, dim3(SMOOTH_THREADS), 0, c->stream, rhs, alt, nx, ny);
+  MemberArgs a = c->h_args[(size_t)kSolveTable * c->mem.size()];
+  a.lamx = to_global<const double>(lx_d);
+  a.lamy = to_global<const double>(ly_d);
+  const int r = set_solve_args(c, a, out_chi, out_zeta);   // also completes the table copies
+  if (r != CCMSAV_OK) return r;
+  launch_solve(c, alt);
+  if (out_chi)
+    hipLaunchKernelGGL(k_alternate_sign, grid, dim3(SMOOTH_THREADS), 0, c->stream, out_chi,
+                       out_chi, nx, ny);
+  if (out_zeta)
+    hipLaunchKernelGGL(k_alternate_sign, grid, dim3(SMOOTH_THREADS), 0, c->stream, out_zeta,
+                       out_zeta, nx, ny);
+  return hipGetLastError() == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
+}
+
 int ccmsav_smooth_ic(ccmsav_ctx* c, double M, double dt, int32_t nsteps, const double* phi_sharp,
                      double* phi_out) {
   if (!c || !phi_sharp || !phi_out || c->mem.size() != 1 || nsteps < 0) return CCMSAV_EINVAL;

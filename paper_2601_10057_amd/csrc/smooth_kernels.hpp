@@ -1,7 +1,8 @@
-// Kernels of the initial-condition relaxation of App. F: the explicit
-// right-hand side of the constant-mobility Cahn-Hilliard step and the final
-// clipping to [-1, 1]. The implicit biharmonic part is the fast direct solver
-// of App. C (the elliptic-solve kernels with the relaxation's constants).
+// Pointwise kernels around the standalone fast direct solver of App. C: the
+// initial-condition relaxation of App. F (the explicit right-hand side of the
+// constant-mobility Cahn-Hilliard step, the final clipping to [-1, 1]) and
+// the sign alternation that turns the DCT solver into the DST one for
+// homogeneous Dirichlet boundaries.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -36,6 +37,21 @@ __global__ void __launch_bounds__(SMOOTH_THREADS) k_clip_unit(double* __restrict
   for (size_t k = (size_t)blockIdx.x * SMOOTH_THREADS + threadIdx.x; k < n;
        k += (size_t)gridDim.x * SMOOTH_THREADS)
     u[k] = fmin(1.0, fmax(-1.0, u[k]));
+}
+
+// out = (-1)^(i + j) in, row-major nx x ny (may alias). With it a DST-II is a
+// DCT-II read in reverse order: sum_i x_i sin(pi (N - k)(2 i + 1) / (2 N)) =
+// sum_i (-1)^i x_i cos(pi k (2 i + 1) / (2 N)), so the DCT kernels solve the
+// homogeneous Dirichlet problem once the eigenvalues are re-indexed.
+// Grid: (ceil(nx / SMOOTH_THREADS), ny).
+__global__ void __launch_bounds__(SMOOTH_THREADS)
+k_alternate_sign(const double* in, double* out, int nx, int ny) {
+  const int i = blockIdx.x * SMOOTH_THREADS + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= nx || j >= ny) return;
+  const size_t o = (size_t)j * nx + i;
+  const double v = in[o];
+  out[o] = ((i + j) & 1) ? -v : v;
 }
 
 }  // namespace ccm
