@@ -24,7 +24,9 @@ written, in its order and notation, with numpy for array arithmetic:
 * smoothed initial conditions: App. F (constant-mobility Cahn-Hilliard
   relaxation, biharmonic term implicit, then clipping);
 * homogeneous Dirichlet boundaries for the fast solver (the DST that App. C
-  names for them): Laplacian with odd ghosts, DST-II matrix, eigenvalues.
+  names for them): Laplacian with odd ghosts, DST-II matrix, eigenvalues;
+  periodic boundaries (the FFT that App. C names): wrap-around Laplacian,
+  eigenvalues, numpy's FFT.
 
 Readings where the paper is silent or ambiguous:
 face mobility is M_psi of the face-averaged phi*; the face average of phi^2
@@ -261,6 +263,42 @@ def spectral_solve_dirichlet(rhs, spectrum, use_matrix=None):
         return Sy.T @ ((Sy @ rhs @ Sx.T) / spectrum) @ Sx
     from scipy.fft import dstn, idstn
     return idstn(dstn(rhs, type=2, norm="ortho") / spectrum, type=2, norm="ortho")
+
+
+# ---------------------------------------------------------------------------
+# Periodic boundaries: the FFT form of the fast solver (App. C)
+# ---------------------------------------------------------------------------
+
+def lap_periodic(u, h):
+    """Five-point Laplacian with periodic wrap-around."""
+    return (np.roll(u, 1, 1) + np.roll(u, -1, 1) + np.roll(u, 1, 0) + np.roll(u, -1, 0)
+            - 4.0 * u) / (h * h)
+
+
+def lap_periodic_matrix(nx, ny, h):
+    """Dense matrix of lap_periodic, built by applying it to unit vectors."""
+    n = nx * ny
+    L = np.zeros((n, n))
+    e = np.zeros((ny, nx))
+    for c in range(n):
+        e.flat[c] = 1.0
+        L[:, c] = lap_periodic(e, h).ravel()
+        e.flat[c] = 0.0
+    return L
+
+
+def periodic_lap_eigs(nx, ny, h):
+    """Eigenvalues of lap_periodic on the ``[ky, kx]`` grid of the 2D DFT:
+    -(4/h^2)(sin^2(pi i/m) + sin^2(pi j/n))."""
+    lx = -(4.0 / h ** 2) * np.sin(math.pi * np.arange(nx) / nx) ** 2
+    ly = -(4.0 / h ** 2) * np.sin(math.pi * np.arange(ny) / ny) ** 2
+    return ly[:, None] + lx[None, :]
+
+
+def spectral_solve_periodic(rhs, spectrum):
+    """Fast direct solve of an operator diagonal in the Fourier basis (the
+    periodic counterpart of App. C's DCT solver), with numpy's FFT."""
+    return np.real(np.fft.ifft2(np.fft.fft2(rhs) / spectrum))
 
 
 # ---------------------------------------------------------------------------

@@ -504,3 +504,21 @@ def test_dirichlet_spectral_solve_equals_dense_solve():
         for um in (True, False):
             got = R.spectral_solve_dirichlet(rhs, spec, use_matrix=um)
             np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-12)
+
+
+def test_periodic_spectral_solve_equals_dense_solve():
+    """The wrap-around Laplacian's eigenvalues (closed form) and the FFT solve
+    against the dense solve of chi and zeta with periodic boundaries."""
+    nx, ny, h = 8, 6, 0.35
+    C1, C2, C3, alpha, lam = 3.0, 0.7, 0.2, 2.5, 0.9
+    L = R.lap_periodic_matrix(nx, ny, h)
+    ev = np.sort(np.linalg.eigvalsh(0.5 * (L + L.T)))
+    np.testing.assert_allclose(ev, np.sort(R.periodic_lap_eigs(nx, ny, h).ravel()),
+                               atol=1e-10 / h ** 2)
+    rhs = np.random.default_rng(3).standard_normal((ny, nx))
+    lam_h = R.periodic_lap_eigs(nx, ny, h)
+    for A, spec in ((C1 * np.eye(nx * ny) - C2 * L + C3 * (L @ L), C1 - C2 * lam_h + C3 * lam_h ** 2),
+                    (alpha * np.eye(nx * ny) - lam * L, alpha - lam * lam_h)):
+        ref = np.linalg.solve(A, rhs.ravel()).reshape(ny, nx)
+        np.testing.assert_allclose(R.spectral_solve_periodic(rhs, spec), ref, rtol=1e-11,
+                                   atol=1e-12)
