@@ -249,6 +249,7 @@ int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, dou
 /* Boundary conditions of the standalone fast direct solver. */
 #define CCMSAV_BC_NEUMANN 0
 #define CCMSAV_BC_DIRICHLET 1
+#define CCMSAV_BC_PERIODIC 2
 
 /*
  * ccmsav_elliptic_solve with a choice of boundary condition. App. C pairs
@@ -260,9 +261,14 @@ int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, dou
  * The Dirichlet solve runs the DCT kernels on the input multiplied by
  * (-1)^(i+j), with the eigenvalues re-indexed, and multiplies the outputs by
  * (-1)^(i+j) (a DST-II is a DCT-II of the sign-alternated input read in
- * reverse order). Same operators, buffers and ordering as
- * ccmsav_elliptic_solve; EINVAL for another bc, EUNSUPPORTED for the
- * DCT-as-GEMM precision with CCMSAV_BC_DIRICHLET.
+ * reverse order). CCMSAV_BC_PERIODIC, the FFT case: Delta_h with wrap-around,
+ * diagonal in the Fourier basis with eigenvalues
+ * -(4/h^2)(sin^2(pi i/nx) + sin^2(pi j/ny)); FP64 transforms in any
+ * precision (two real rows per complex FFT line, half spectra by conjugate
+ * symmetry), grids up to 4096 per direction. Same operators, buffers and
+ * ordering as ccmsav_elliptic_solve; EINVAL for another bc, EUNSUPPORTED for
+ * the DCT-as-GEMM precision with CCMSAV_BC_DIRICHLET and for periodic grids
+ * beyond 4096.
  */
 int ccmsav_elliptic_solve_bc(ccmsav_ctx* c, int32_t bc, const double* rhs, double* out_chi,
                              double* out_zeta);

@@ -26,7 +26,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDOMAIN",
 
 FLAG_GRAPH = 1
 FLAG_BDF1 = 2
-BC_NEUMANN, BC_DIRICHLET = 0, 1
+BC_NEUMANN, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2
 
 EXPORTED = (
     "ccmsav_workspace_bytes", "ccmsav_init", "ccmsav_step", "ccmsav_energy",
@@ -300,8 +300,9 @@ class Context:
 
     def elliptic_solve(self, rhs, out_chi, out_zeta, bc: str = "neumann"):
         """chi^{-1} rhs and zeta^{-1} rhs (device tensors) with the BDF2
-        operators, for homogeneous Neumann (DCT) or Dirichlet (DST) boundaries."""
-        code = {"neumann": BC_NEUMANN, "dirichlet": BC_DIRICHLET}[bc]
+        operators, for homogeneous Neumann (DCT), Dirichlet (DST) or periodic
+        (FFT) boundaries."""
+        code = {"neumann": BC_NEUMANN, "dirichlet": BC_DIRICHLET, "periodic": BC_PERIODIC}[bc]
         _check(load().ccmsav_elliptic_solve_bc(self._h, code, _ptr(rhs), _ptr(out_chi),
                                                _ptr(out_zeta)), "ccmsav_elliptic_solve_bc")
 

@@ -21,6 +21,7 @@
 #include "ccmsav.h"
 #include "diag_kernels.hpp"
 #include "gemm_dct.hpp"
+#include "periodic_kernels.hpp"
 #include "smooth_kernels.hpp"
 #include "step_kernels.hpp"
 
@@ -835,6 +836,64 @@ const char* kStatusText[] = {
 
 namespace {
 
+// Launches of the periodic solver over the line length (16 .. 4096).
+constexpr int kPerMaxLog = 12;
+struct PerLaunch {
+  using Rows = void (*)(hipStream_t, int, const double*, cpx<double>*, int, size_t);
+  using Cols = void (*)(hipStream_t, int, const cpx<double>*, cpx<double>*, cpx<double>*, int,
+                        size_t, PerConst);
+  using Inv = void (*)(hipStream_t, int, const cpx<double>*, double*, int, size_t);
+  template <int N>
+  static void rows(hipStream_t st, int grid, const double* rhs, cpx<double>* col, int ny,
+                   size_t cs) {
+    hipLaunchKernelGGL(k_per_rows<N>, dim3(grid), dim3(line_threads(N)), 0, st, rhs, col, ny, cs);
+  }
+  template <int N>
+  static void cols(hipStream_t st, int grid, const cpx<double>* col, cpx<double>* oc,
+                   cpx<double>* oz, int nx, size_t cs, PerConst k) {
+    hipLaunchKernelGGL(k_per_cols<N>, dim3(grid), dim3(line_threads(N)), 0, st, col, oc, oz, nx,
+                       cs, k);
+  }
+  template <int N>
+  static void inv(hipStream_t st, int grid, const cpx<double>* col, double* out, int ny,
+                  size_t cs) {
+    hipLaunchKernelGGL(k_per_rows_inv<N>, dim3(grid), dim3(line_threads(N)), 0, st, col, out, ny,
+                       cs);
+  }
+  template <int... L> struct Tables {
+    static constexpr Rows t_rows[] = {&rows<(1 << L)>...};
+    static constexpr Cols t_cols[] = {&cols<(1 << L)>...};
+    static constexpr Inv t_inv[] = {&inv<(1 << L)>...};
+  };
+  using T = Tables<4, 5, 6, 7, 8, 9, 10, 11, 12>;
+};
+
+// Periodic chi^{-1} rhs and zeta^{-1} rhs of member 0 (FP64 transforms), with
+// three column buffers of (nx/2 + 1) columns in the intermediate region.
+int periodic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, double* out_zeta) {
+  const Member& m = c->mem[0];
+  const int nx = m.p.nx, ny = m.p.ny;
+  if (m.lx > kPerMaxLog || m.ly > kPerMaxLog) return CCMSAV_EUNSUPPORTED;
+  const size_t cs = (size_t)ny + 66;             // column stride, off a power of two
+  const size_t colb = (size_t)(nx / 2 + 1) * cs;
+  const size_t need = 3 * colb * sizeof(cpx<double>);
+  const size_t have = M_NFIELD * strip_field(nx, ny, (int)mid_elem(c->precision)) *
+                      mid_elem(c->precision);
+  if (need > have) return CCMSAV_EUNSUPPORTED;
+  cpx<double>* col = static_cast<cpx<double>*>(m.mid);
+  cpx<double>* cc = col + colb;
+  cpx<double>* cz = cc + colb;
+  const StepConst& k = c->h_args[(size_t)kSolveTable * c->mem.size()].k;
+  const PerConst pc{k.C1, k.C2, k.C3, k.alpha, k.lam, m.p.h};
+  using PT = PerLaunch::T;
+  PT::t_rows[m.lx - kMinLog](c->stream, ny / 2, rhs, col, ny, cs);
+  PT::t_cols[m.ly - kMinLog](c->stream, nx / 2 + 1, col, out_chi ? cc : nullptr,
+                             out_zeta ? cz : nullptr, nx, cs, pc);
+  if (out_chi) PT::t_inv[m.lx - kMinLog](c->stream, ny / 2, cc, out_chi, ny, cs);
+  if (out_zeta) PT::t_inv[m.lx - kMinLog](c->stream, ny / 2, cz, out_zeta, ny, cs);
+  return hipGetLastError() == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
+}
+
 // Upload `a` (a copy of the standalone-solve table entry, with the operator
 // constants to use) as that entry, with the outputs of member 0's solve: an
 // output that is not requested goes to intermediate slots 2-3, which the
@@ -1290,6 +1349,7 @@ int ccmsav_elliptic_solve_bc(ccmsav_ctx* c, int32_t bc, const double* rhs, doubl
                              double* out_zeta) {
   if (!c || !rhs || c->mem.size() != 1) return CCMSAV_EINVAL;
   if (bc == CCMSAV_BC_NEUMANN) return ccmsav_elliptic_solve(c, rhs, out_chi, out_zeta);
+  if (bc == CCMSAV_BC_PERIODIC) return periodic_solve(c, rhs, out_chi, out_zeta);
   if (bc != CCMSAV_BC_DIRICHLET) return CCMSAV_EINVAL;
   if (is_gemm(c->precision)) return CCMSAV_EUNSUPPORTED;
   const Member& m = c->mem[0];

@@ -1,6 +1,7 @@
-"""The fast direct solver for homogeneous Dirichlet boundaries
-(ccmsav_elliptic_solve_bc with CCMSAV_BC_DIRICHLET: the DCT kernels on the
-sign-alternated input, App. C's DST form) against the oracle's DST solve."""
+"""The fast direct solver for homogeneous Dirichlet and periodic boundaries
+(ccmsav_elliptic_solve_bc: CCMSAV_BC_DIRICHLET runs the DCT kernels on the
+sign-alternated input, App. C's DST form; CCMSAV_BC_PERIODIC the FFT form)
+against the oracle's DST and FFT solves."""
 import sys
 
 import numpy as np
@@ -36,6 +37,9 @@ def solve_case(nx, ny, precision, bc):
     if bc == "dirichlet":
         lam = R.dirichlet_lap_eigs(nx, ny, p.h)
         solve = R.spectral_solve_dirichlet
+    elif bc == "periodic":
+        lam = R.periodic_lap_eigs(nx, ny, p.h)
+        solve = R.spectral_solve_periodic
     else:
         lam = R.neumann_lap_eigs(nx, ny, p.h)
         solve = R.spectral_solve
@@ -82,3 +86,29 @@ def test_unknown_boundary_condition_is_rejected():
     with C.Context(m.params, m.phi0, m.psi0) as ctx:
         rc = C.load().ccmsav_elliptic_solve_bc(ctx._h, 7, dev.data_ptr(), dev.data_ptr(), None)
         assert C.STATUS.get(rc) == "EINVAL"
+
+
+@pytest.mark.parametrize("nx,ny,precision", [
+    (16, 16, "fp64"), (64, 32, "fp64"), (32, 128, "fp64"), (256, 256, "fp64"),
+    (1024, 1024, "fp64"), (4096, 4096, "fp64"),
+    (16, 16, "mixed"), (64, 32, "mixed"), (256, 256, "mixed")])
+def test_periodic_solves_match_oracle(nx, ny, precision):
+    """FP64 transforms in either precision of the context."""
+    note(f"periodic solve {nx}x{ny} {precision}")
+    oc, oz, rc, rz = solve_case(nx, ny, precision, "periodic")
+    assert rel_linf(oc, rc) <= 1e-12
+    assert rel_linf(oz, rz) <= 1e-12
+
+
+def test_periodic_solve_of_one_output_and_its_limits():
+    m = circle_member(64)
+    rhs = torch.from_numpy(np.random.default_rng(5).standard_normal((64, 64))).cuda()
+    oz = torch.empty_like(rhs)
+    note("periodic zeta only")
+    with C.Context(m.params, m.phi0, m.psi0) as ctx:
+        ctx.elliptic_solve(rhs, None, oz, bc="periodic")
+        torch.cuda.synchronize()
+    p = R.Params.from_dict(dict(m.params, A=1.0))
+    lam = R.periodic_lap_eigs(64, 64, p.h)
+    ref = R.spectral_solve_periodic(rhs.cpu().numpy(), 1.5 / p.dt - p.lam * lam)
+    assert rel_linf(oz.cpu().numpy(), ref) <= 1e-12
