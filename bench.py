@@ -201,6 +201,32 @@ def smooth_bench(C, torch, np, member, args, dev):
                       "hbm_frac_of_step_model": frac}), flush=True)
 
 
+def elliptic_bench(C, torch, np, member, args, dev):
+    """Time ccmsav_elliptic_solve_bc (both outputs) on the workload's grid."""
+    ny, nx = member.phi0.shape
+    rhs = torch.from_numpy(np.random.default_rng(1).standard_normal((ny, nx))).to(dev)
+    oc, oz = torch.empty_like(rhs), torch.empty_like(rhs)
+    ctx = C.Context(member.params, member.phi0, member.psi0, args.precision)
+    for _ in range(max(1, args.warmup)):
+        ctx.elliptic_solve(rhs, oc, oz, bc=args.elliptic)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.elliptic_solve(rhs, oc, oz, bc=args.elliptic)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.close()
+    value = nx * ny * args.steps / wall / 1e6
+    print(json.dumps({"metric": "fast direct solve (chi and zeta), Mcell-solves/s", "value": value,
+                      "unit": "Mcell-solves/s", "n_gpus": 1, "calls": args.steps,
+                      "ms_per_call": 1e3 * wall / args.steps, "higher_is_better": True,
+                      "dtype": "f64" if args.elliptic == "periodic" or args.precision == "fp64"
+                      else "f32+f64", "data": "synthetic",
+                      "config": {"workload": args.workload, "nx": nx, "ny": ny,
+                                 "boundaries": args.elliptic, "precision": args.precision}}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -218,6 +244,9 @@ def main():
     ap.add_argument("--smooth-ic", action="store_true",
                     help="instead of the step, time the App. F initial-condition relaxation "
                          "(ccmsav_smooth_ic, ten steps per call) on the workload's first grid")
+    ap.add_argument("--elliptic", choices=["neumann", "dirichlet", "periodic"], default=None,
+                    help="instead of the step, time the standalone fast direct solver "
+                         "(chi^{-1} and zeta^{-1} of one field) with these boundaries")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the FP64 run that the mixed path is checked and compared against")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -241,6 +270,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.smooth_ic:
         smooth_bench(C, torch, np, members[0], args, dev)
+        return
+    if args.elliptic:
+        elliptic_bench(C, torch, np, members[0], args, dev)
         return
 
     bdf1 = args.scheme == "bdf1"
