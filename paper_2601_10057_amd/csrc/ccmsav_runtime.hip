@@ -1371,14 +1371,19 @@ int ccmsav_elliptic_solve_bc(ccmsav_ctx* c, int32_t bc, const double* rhs, doubl
     const double cs = std::cos(M_PI * k / (2.0 * ny));
     ly[k] = 4.0 / (m.p.h * m.p.h) * cs * cs;
   }
-  HIP_TRY(hipMemcpyAsync(lx_d, lx.data(), nx * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(hipMemcpyAsync(ly_d, ly.data(), ny * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  const bool copied =
+      hipMemcpyAsync(lx_d, lx.data(), nx * sizeof(double), hipMemcpyHostToDevice, c->stream) ==
+          hipSuccess &&
+      hipMemcpyAsync(ly_d, ly.data(), ny * sizeof(double), hipMemcpyHostToDevice, c->stream) ==
+          hipSuccess;
+  // the host tables must outlive the copies, also when one of them failed
+  if (hipStreamSynchronize(c->stream) != hipSuccess || !copied) return CCMSAV_EHIP;
   const dim3 grid((nx + SMOOTH_THREADS - 1) / SMOOTH_THREADS, ny);
   hipLaunchKernelGGL(k_alternate_sign, grid, dim3(SMOOTH_THREADS), 0, c->stream, rhs, alt, nx, ny);
   MemberArgs a = c->h_args[(size_t)kSolveTable * c->mem.size()];
   a.lamx = to_global<const double>(lx_d);
   a.lamy = to_global<const double>(ly_d);
-  const int r = set_solve_args(c, a, out_chi, out_zeta);   // also completes the table copies
+  const int r = set_solve_args(c, a, out_chi, out_zeta);
   if (r != CCMSAV_OK) return r;
   launch_solve(c, alt);
   if (out_chi)
