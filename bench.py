@@ -19,6 +19,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -68,16 +69,21 @@ def kernel_bytes_per_cell(precision: str, scheme: str = "bdf2"):
     }
 
 
+_COMMENT = re.compile(r"//[^\n]*|/\*.*?\*/", re.S)
+
+
 def source_digest() -> str:
-    """Hash of the HIP sources, to tell whether stored counters are stale."""
+    """Hash of the code of the HIP sources, to tell whether stored counters are
+    stale. Comments and whitespace are left out: they compile to nothing."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2601_10057_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
         if not name.endswith((".hip", ".hpp")):
             continue
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode())
-            h.update(f.read())
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
+            code = " ".join(_COMMENT.sub(" ", f.read()).split())
+        h.update(name.encode())
+        h.update(code.encode())
     return h.hexdigest()[:16]
 
 

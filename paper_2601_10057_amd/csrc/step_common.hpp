@@ -5,7 +5,7 @@
 
 namespace ccm {
 
-// Partial sums written by the fused stencil + row-DCT pass, one row each.
+// Partial sums written by the stencil pass, one row per workgroup.
 enum P1Sum {
   P1_RS = 0,      // sum (phi*^2 - 1 - beta)^2 / (4 eps)          -> r_S^2 / h^2
   P1_RW,          // sum 6 phi*^2 |grad phi*|^2 + (phi*^3-phi*)^2/eps^2 -> r_W^2 / h^2

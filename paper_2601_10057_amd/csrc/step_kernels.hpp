@@ -949,19 +949,56 @@ __device__ void reduce_rows(P part, int nrows, double* red, int tid, double (&to
   lds_sync();
 }
 
+// Column sums of an nrows x NV row-major array of partials. Thread t < G NV
+// (G = NTHR / NV row groups) adds column t mod NV over rows t / NV + i G, so a
+// wave's loads read consecutive doubles; the G group sums of a column are then
+// added in group order, a fixed order for any launch. Every thread receives
+// the totals; red holds NTHR + NV doubles.
+template <int NV, int NTHR, typename P>
+__device__ void reduce_columns(P part, int nrows, double* red, int tid, double (&tot)[NV]) {
+  static_assert(NV <= NTHR, "one thread per column at least");
+  constexpr int G = NTHR / NV;
+  constexpr size_t ACT = (size_t)G * NV;
+  // The kernel is bound by load latency: every round issues U independent
+  // loads per thread (absent ones read as zero) before adding them in order.
+  constexpr int U = 16;
+  const size_t total = (size_t)nrows * NV;
+  double v = 0.0;
+  if ((size_t)tid < ACT) {
+    for (size_t e = tid; e < total; e += U * ACT) {
+      double a[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) a[u] = e + u * ACT < total ? part[e + u * ACT] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) v += a[u];
+    }
+  }
+  red[tid] = v;
+  lds_sync();
+  if (tid < NV) {
+    double t = 0.0;
+    for (int g = 0; g < G; ++g) t += red[g * NV + tid];
+    red[NTHR + tid] = t;
+  }
+  lds_sync();
+#pragma unroll
+  for (int q = 0; q < NV; ++q) tot[q] = red[NTHR + q];
+  lds_sync();
+}
+
 // ---------------------------------------------------------------------------
 // S: the 5x5 reduced system of App. B, Step 4, and the SAV update.
 // ---------------------------------------------------------------------------
-constexpr int SOLVE_THREADS = 256;
+constexpr int SOLVE_THREADS = 512;
 
 __device__ __forceinline__ void solve_body(gptr<const double> __restrict__ p1, int n1,
                                            gptr<const double> __restrict__ p2, int n2,
                                            gptr<DevScalars> __restrict__ ds, const StepConst& c) {
-  __shared__ double red[P2_NSUM * (SOLVE_THREADS / 64 + 1)];
+  __shared__ double red[SOLVE_THREADS + (P1_NSUM > P2_NSUM ? P1_NSUM : P2_NSUM)];
   const int tid = threadIdx.x;
   double T1[P1_NSUM], T2[P2_NSUM];
-  reduce_rows<P1_NSUM, SOLVE_THREADS>(p1, n1, red, tid, T1);
-  reduce_rows<P2_NSUM, SOLVE_THREADS>(p2, n2, red, tid, T2);
+  reduce_columns<P1_NSUM, SOLVE_THREADS>(p1, n1, red, tid, T1);
+  reduce_columns<P2_NSUM, SOLVE_THREADS>(p2, n2, red, tid, T2);
   if (tid != 0) return;
 
   int err = 0;
@@ -1006,28 +1043,50 @@ __device__ __forceinline__ void solve_body(gptr<const double> __restrict__ p1, i
     for (int jx = 0; jx < 5; ++jx) ds->diag[15 + 5 * i + jx] = M[i][jx];
   }
 
-  // Gaussian elimination with partial pivoting.
+  // Gaussian elimination with partial pivoting. Every array index is a
+  // compile-time constant (the pivot row is exchanged by selects), so the
+  // system stays in registers instead of per-lane scratch memory.
   double scale = 0.0;
+#pragma unroll
   for (int i = 0; i < 5; ++i)
+#pragma unroll
     for (int jx = 0; jx < 5; ++jx) scale = fmax(scale, fabs(M[i][jx]));
+#pragma unroll
   for (int col = 0; col < 5; ++col) {
     int piv = col;
-    for (int r = col + 1; r < 5; ++r)
-      if (fabs(M[r][col]) > fabs(M[piv][col])) piv = r;
-    if (!(fabs(M[piv][col]) > 1e-14 * scale)) err |= ERR_PIVOT;
-    if (piv != col) {
-      for (int jx = 0; jx < 5; ++jx) { double t = M[col][jx]; M[col][jx] = M[piv][jx]; M[piv][jx] = t; }
-      double t = b[col]; b[col] = b[piv]; b[piv] = t;
+    double best = fabs(M[col][col]);
+#pragma unroll
+    for (int r = col + 1; r < 5; ++r) {
+      const double a = fabs(M[r][col]);
+      if (a > best) { best = a; piv = r; }
     }
+    if (!(best > 1e-14 * scale)) err |= ERR_PIVOT;
+#pragma unroll
+    for (int r = col + 1; r < 5; ++r) {
+      const bool sw = r == piv;
+#pragma unroll
+      for (int jx = col; jx < 5; ++jx) {
+        const double u = M[col][jx], w = M[r][jx];
+        M[col][jx] = sw ? w : u;
+        M[r][jx] = sw ? u : w;
+      }
+      const double u = b[col], w = b[r];
+      b[col] = sw ? w : u;
+      b[r] = sw ? u : w;
+    }
+#pragma unroll
     for (int r = col + 1; r < 5; ++r) {
       const double m = M[r][col] / M[col][col];
+#pragma unroll
       for (int jx = col; jx < 5; ++jx) M[r][jx] -= m * M[col][jx];
       b[r] -= m * b[col];
     }
   }
   double x[5];
+#pragma unroll
   for (int r = 4; r >= 0; --r) {
     double t = b[r];
+#pragma unroll
     for (int jx = r + 1; jx < 5; ++jx) t -= M[r][jx] * x[jx];
     x[r] = t / M[r][r];
   }
