@@ -809,12 +809,13 @@ int upload_dct_matrix(uint16_t* d_hi, uint16_t* d_lo, int n, hipStream_t st) {
       hi[(size_t)k + (size_t)i * n] = h;
       lo[(size_t)k + (size_t)i * n] = host_bf16((float)(v - (double)host_bf16_to_f32(h)));
     }
-  if (hipMemcpyAsync(d_hi, hi.data(), hi.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st) !=
-          hipSuccess ||
-      hipMemcpyAsync(d_lo, lo.data(), lo.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st) !=
-          hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    return CCMSAV_EHIP;
+  const bool ok =
+      hipMemcpyAsync(d_hi, hi.data(), hi.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st) ==
+          hipSuccess &&
+      hipMemcpyAsync(d_lo, lo.data(), lo.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st) ==
+          hipSuccess;
+  // the host tables must outlive the copies, also when one of them failed
+  if (hipStreamSynchronize(st) != hipSuccess || !ok) return CCMSAV_EHIP;
   return CCMSAV_OK;
 }
 
@@ -1048,8 +1049,8 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
                              c->stream) == hipSuccess &&
               hipMemcpyAsync(m.psi[0], psi0[mi], cells * sizeof(double), hipMemcpyDefault,
                              c->stream) == hipSuccess;
-    if (ok) ok = hipStreamSynchronize(c->stream) == hipSuccess;
-    if (!ok) return fail(CCMSAV_EHIP);
+    // the host tables must outlive the copies, also when one of them failed
+    if (hipStreamSynchronize(c->stream) != hipSuccess || !ok) return fail(CCMSAV_EHIP);
     const DiagConst d = make_diag(m.p);
     hipLaunchKernelGGL(k_init_sums, dim3(m.p.ny), dim3(DIAG_THREADS), 0, c->stream, m.phi[0],
                        m.psi[0], m.parte, m.p.nx, m.p.ny, d);
@@ -1094,9 +1095,9 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
                                  hipMemcpyHostToDevice, c->stream) == hipSuccess &&
                   hipMemcpyAsync(c->d_args, c->h_args.data(),
                                  c->h_args.size() * sizeof(MemberArgs), hipMemcpyHostToDevice,
-                                 c->stream) == hipSuccess &&
-                  hipStreamSynchronize(c->stream) == hipSuccess;
-  if (!ok) return fail(CCMSAV_EHIP);
+                                 c->stream) == hipSuccess;
+  // the index order must outlive the copies, also when one of them failed
+  if (hipStreamSynchronize(c->stream) != hipSuccess || !ok) return fail(CCMSAV_EHIP);
   if (c->graph) {
     if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
