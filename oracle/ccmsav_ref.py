@@ -19,6 +19,10 @@ written, in its order and notation, with numpy for array arithmetic:
   DCT); the DCT is the orthonormal DCT-II written out as a matrix
   (definition), with scipy's DCT as an equivalent fast library primitive for
   large grids;
+* a residual check of a proposed step: the discrete equations of App. B
+  that determine it (chi phi^{n+1}, zeta psi^{n+1}, the SAV relations from
+  the rows of the 5x5 system), by stencils and inner products with no solve,
+  for grids where a full oracle step would take minutes;
 * modified discrete energy: eq. (modified_discrete_energy); the dissipation
   quantities K^n, ||mu||^2, ||c + d/2||^2 of Thm. 3.1 / App. A;
 * smoothed initial conditions: App. F (constant-mobility Cahn-Hilliard
@@ -601,6 +605,74 @@ def step(st: State, use_matrix: Optional[bool] = None, keep: bool = False) -> Di
     st.phi, st.psi, st.sav = phi_new, psi_new, sav_new
     st.n += 1
     return info
+
+
+def step_residuals(phi_n, psi_n, sav_n, phi_new, psi_new, sav_new, p: Params,
+                   phi_m=None, psi_m=None, sav_m=None) -> Dict:
+    """How far a proposed step result is from the step's discrete equations.
+
+    The BDF2 step (BDF1 when no level n-1 is given) of App. B is the unique
+    solution of, with x = (B, C, D, E + G) = (V, U, W, Z)^{n+1} minus the
+    bracketed explicit SAV parts:
+      chi phi^{n+1} = f - c_gs B S - c_ga C H - c_gb D Q - c_go (E + G) K,
+      zeta psi^{n+1} = g + (E + G) div(M grad P),
+      B = (S, phi^{n+1}), C = (H, phi^{n+1}), D = (Q, phi^{n+1}),
+      E + G = (K, phi^{n+1}) + (P, psi^{n+1}),
+    where the last four follow from the 5x5 system's rows. Checking them needs
+    stencils and inner products only (no solve), at any grid size.
+
+    Returns relative residuals: ``chi`` = max|chi phi - rhs| over
+    sigma_max max|phi|, ``zeta`` likewise with tau_max, ``sav`` = the largest
+    |x_i - (F_i, .)| over (|F_i|, |.|).
+    """
+    h, dt = p.h, p.dt
+    bdf2 = phi_m is not None
+    if bdf2:
+        phis, psis = 2.0 * phi_n - phi_m, 2.0 * psi_n - psi_m
+        alpha = 3.0 / (2.0 * dt)
+    else:
+        phis, psis = phi_n, psi_n
+        alpha = 1.0 / dt
+    S, H, Q = basis_S(phis, p), basis_H(phis, p), basis_Q(phis, p)
+    K, P = basis_K(phis, psis, p), basis_P(phis, psis, p)
+    mx, my = face_mobility(phis, p)
+    LP_src = div_mobility_grad(mx, my, P, h)
+    Vn, Un, Wn, Zn = sav_n
+    if bdf2:
+        Vm, Um, Wm, Zm = sav_m
+        dphi, dpsi = -4.0 * phi_n + phi_m, -4.0 * psi_n + psi_m
+        s = [(4.0 * Vn - Vm + ip(S, dphi, h)) / 3.0, (4.0 * Un - Um + ip(H, dphi, h)) / 3.0,
+             (4.0 * Wn - Wm + ip(Q, dphi, h)) / 3.0,
+             (4.0 * Zn - Zm + ip(K, dphi, h) + ip(P, dpsi, h)) / 3.0]
+        a_phi, a_psi = (4.0 * phi_n - phi_m) / (2.0 * dt), (4.0 * psi_n - psi_m) / (2.0 * dt)
+    else:
+        s = [Vn - ip(S, phi_n, h), Un - ip(H, phi_n, h), Wn - ip(Q, phi_n, h),
+             Zn - ip(K, phi_n, h) - ip(P, psi_n, h)]
+        a_phi, a_psi = phi_n / dt, psi_n / dt
+    tt = theta_tilde(p)
+    f = a_phi - p.M_phi * (tt * lap(phis, h) + p.gamma_surf * 1.5 * SQ2 * s[0] * S
+                           + p.gamma_area * s[1] * H
+                           + p.gamma_bend * 3.0 * SQ2 / (8.0 * p.eps) * s[2] * Q + s[3] * K)
+    g = a_psi - p.lam * lap(psis, h) + div_mobility_grad(mx, my, s[3] * P, h)
+    x = [sav_new[i] - s[i] for i in range(4)]
+    cgs, cga, cgb, cgo = sav_weights(p)
+    C1, C2, C3 = chi_coefficients(p, alpha)
+    L_phi = lap(phi_new, h)
+    r_phi = (C1 * phi_new - C2 * L_phi + C3 * lap(L_phi, h)
+             - (f - cgs * x[0] * S - cga * x[1] * H - cgb * x[2] * Q - cgo * x[3] * K))
+    r_psi = alpha * psi_new - p.lam * lap(psi_new, h) - (g + x[3] * LP_src)
+    lmax = 8.0 / (h * h)                                # spectral radius of -Delta_h
+    sig_max = abs(C1) + abs(C2) * lmax + abs(C3) * lmax * lmax
+    tau_max = alpha + abs(p.lam) * lmax
+    aphi, apsi = np.abs(phi_new), np.abs(psi_new)
+    sav = 0.0
+    for xi, F in zip(x[:3], (S, H, Q)):
+        sav = max(sav, abs(xi - ip(F, phi_new, h)) / ip(np.abs(F), aphi, h))
+    sav = max(sav, abs(x[3] - ip(K, phi_new, h) - ip(P, psi_new, h))
+              / (ip(np.abs(K), aphi, h) + ip(np.abs(P), apsi, h)))
+    return dict(chi=float(np.max(np.abs(r_phi)) / (sig_max * np.max(aphi))),
+                zeta=float(np.max(np.abs(r_psi)) / (tau_max * np.max(apsi))),
+                sav=float(sav))
 
 
 def run(phi0, psi0, params: Dict, nsteps: int, use_matrix=None, bdf1: bool = False) -> State:

@@ -522,3 +522,36 @@ def test_periodic_spectral_solve_equals_dense_solve():
         ref = np.linalg.solve(A, rhs.ravel()).reshape(ny, nx)
         np.testing.assert_allclose(R.spectral_solve_periodic(rhs, spec), ref, rtol=1e-11,
                                    atol=1e-12)
+
+
+def _three_levels(n=64):
+    m = vesicle_member(n, 4)
+    st = R.initial_state(m.phi0, m.psi0, m.params)
+    lv = [(st.phi.copy(), st.psi.copy(), np.array(st.sav, float))]
+    for _ in range(2):
+        R.step(st)
+        lv.append((st.phi.copy(), st.psi.copy(), np.array(st.sav, float)))
+    return st.p, lv
+
+
+def test_step_residuals_vanish_on_oracle_steps():
+    """The discrete equations that determine a step (App. B), checked with
+    stencils and inner products only, hold for the oracle's own BDF1 and BDF2
+    steps to rounding: the residual check and the solve agree."""
+    p, (l0, l1, l2) = _three_levels()
+    for r in (R.step_residuals(*l0, *l1, p), R.step_residuals(*l1, *l2, p, *l0)):
+        assert max(r.values()) <= 1e-13, r
+
+
+def test_step_residuals_detect_perturbations():
+    """A change of 1e-9 in phi, psi or any one SAV shows in the residuals,
+    well above their rounding level (a dropped or mis-signed term gives O(1))."""
+    p, (l0, l1, l2) = _three_levels()
+    rng = np.random.default_rng(7)
+    noise = 1e-9 * rng.standard_normal(l2[0].shape)
+    assert R.step_residuals(*l1, l2[0] + noise, l2[1], l2[2], p, *l0)["chi"] >= 1e-10
+    assert R.step_residuals(*l1, l2[0], l2[1] + noise, l2[2], p, *l0)["zeta"] >= 1e-10
+    for i in range(4):
+        sav = l2[2].copy()
+        sav[i] += 1e-9 * abs(sav[i])
+        assert R.step_residuals(*l1, l2[0], l2[1], sav, p, *l0)["sav"] >= 1e-12, i
