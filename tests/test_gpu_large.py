@@ -10,7 +10,9 @@ against properties that hold at any size:
 The mixed path and the DCT-as-GEMM variant are then held to the FP64 path:
 mixed over the workload's 200 steps within 1e-6 (relative L-inf of phi, psi,
 the SAVs), with its mass drift at most 5e-11 and its modified energy decaying;
-DCT-as-GEMM over 20 steps within 5e-4 (its bf16x3 products).
+DCT-as-GEMM over 20 steps within 5e-4 (its bf16x3 products). The mixed path's
+BDF2 step, and the N = 4096 benchmark grid's step after 100 steps in FP64 and
+mixed, are held to the same discrete equations.
 
 Residual bound: chi and zeta are normalised by their spectral radii, so the
 residuals scale the FP64 path's error by at most one; on the grids where the
@@ -115,3 +117,39 @@ def test_gemm_variant_tracks_fp64(member):
         err = max(rel_linf(g[1], r[1]), rel_linf(g[2], r[2]))
         note(f"step {g[0]}: {err:.2e}")
         assert err <= GEMM_TOL
+
+
+def late_levels(m, precision, k):
+    """Levels k-2, k-1 and k of (phi, psi, SAVs) from one context."""
+    levels = []
+    with C.Context(m.params, m.phi0, m.psi0, precision) as ctx:
+        if k > 2:
+            ctx.step(k - 2)
+        for j in range(3):
+            if j:
+                ctx.step(1)
+            phi, psi = ctx.fields()
+            levels.append((phi, psi, np.array(ctx.savs()[0], float)))
+    return levels
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", RES_TOL), ("mixed", REL_TOL)])
+def test_bench_grid_late_step_satisfies_the_discrete_equations(precision, tol):
+    """N = 4096 in the benchmark's launch configuration: the BDF2 step after
+    100 steps, where the oracle comparison covers only the first. The mixed
+    path's bound is its 1e-6 tolerance against FP64 (the residuals scale its
+    error by at most one)."""
+    m = make_workload("vesicle4096")[0]
+    note(f"vesicle4096 {precision}: residuals of step 100")
+    l0, l1, l2 = late_levels(m, precision, 100)
+    r = R.step_residuals(*l1, *l2, R.Params.from_dict(m.params), *l0)
+    note(f"{precision} step 100 {r}")
+    assert max(r.values()) <= tol, r
+
+
+def test_mixed_step_satisfies_the_discrete_equations(member):
+    note("vesicle8192 mixed: residuals of step 2")
+    l0, l1, l2 = late_levels(member, "mixed", 2)
+    r = R.step_residuals(*l1, *l2, R.Params.from_dict(member.params), *l0)
+    note(f"mixed step 2 {r}")
+    assert max(r.values()) <= REL_TOL, r
