@@ -181,6 +181,38 @@ def test_ensemble_workload_mixed_against_fp64():
             assert np.all(err <= 1e-6), (k, np.flatnonzero(err > 1e-6).tolist())
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_ensemble_workload_step_2000_satisfies_the_discrete_equations(precision, tol):
+    """Every member of the 48 x 256^2 + 16 x 512^2 workload, graph-captured,
+    at its last step (2000): the BDF2 step from levels 1998 and 1999 satisfies
+    the discrete equations of App. B (oracle step_residuals: chi phi, zeta psi
+    and the SAV relations, normalised by the operators' spectral radii). This
+    holds however far the trajectory has drifted from another rounding of it,
+    so it checks the late steps that the comparison with FP64 cannot. Bounds:
+    1e-12 in FP64, the 1e-6 tolerance of the mixed path."""
+    ms = make_workload("ensemble48x256_16x512")
+    nm = len(ms)
+    note(f"ensemble workload {precision}: residuals of step 2000, {nm} members")
+    levels = [[] for _ in ms]
+    with C.Context.ensemble([m.params for m in ms], [m.phi0 for m in ms],
+                            [m.psi0 for m in ms], precision, graph=True) as ens:
+        ens.step(1998)
+        for j in range(3):
+            if j:
+                ens.step(1)
+            for i in range(nm):
+                phi, psi = ens.fields(i)
+                levels[i].append((phi, psi, np.array(ens.savs(i)[0], float)))
+    worst = {"chi": 0.0, "zeta": 0.0, "sav": 0.0}
+    for i, m in enumerate(ms):
+        l0, l1, l2 = levels[i]
+        r = R.step_residuals(*l1, *l2, R.Params.from_dict(m.params), *l0)
+        for key in worst:
+            worst[key] = max(worst[key], r[key])
+        assert max(r.values()) <= tol, (i, r)
+    note(f"{precision} worst over members {worst}")
+
+
 def test_autotuner_reports_its_choices():
     ms = small_members()[:2]
     with C.Context.ensemble([m.params for m in ms], [m.phi0 for m in ms],
