@@ -11,8 +11,8 @@ The mixed path and the DCT-as-GEMM variant are then held to the FP64 path:
 mixed over the workload's 200 steps within 1e-6 (relative L-inf of phi, psi,
 the SAVs), with its mass drift at most 5e-11 and its modified energy decaying;
 DCT-as-GEMM over 20 steps within 5e-4 (its bf16x3 products). The mixed path's
-BDF2 step, and the N = 4096 benchmark grid's step after 100 steps in FP64 and
-mixed, are held to the same discrete equations.
+BDF2 step, the last step of the N = 1024, 2048 and 4096 workloads and the
+BDF1 scheme at N = 4096 are held to the same discrete equations.
 
 Residual bound: chi and zeta are normalised by their spectral radii, so the
 residuals scale the FP64 path's error by at most one; on the grids where the
@@ -28,7 +28,7 @@ import pytest
 
 from oracle import ccmsav_ref as R
 from parity_util import rel_linf
-from workloads import make_workload
+from workloads import WORKLOADS, make_workload
 
 pytestmark = pytest.mark.gpu
 
@@ -119,10 +119,10 @@ def test_gemm_variant_tracks_fp64(member):
         assert err <= GEMM_TOL
 
 
-def late_levels(m, precision, k):
+def late_levels(m, precision, k, bdf1=False):
     """Levels k-2, k-1 and k of (phi, psi, SAVs) from one context."""
     levels = []
-    with C.Context(m.params, m.phi0, m.psi0, precision) as ctx:
+    with C.Context(m.params, m.phi0, m.psi0, precision, bdf1=bdf1) as ctx:
         if k > 2:
             ctx.step(k - 2)
         for j in range(3):
@@ -133,17 +133,30 @@ def late_levels(m, precision, k):
     return levels
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", RES_TOL), ("mixed", REL_TOL)])
-def test_bench_grid_late_step_satisfies_the_discrete_equations(precision, tol):
-    """N = 4096 in the benchmark's launch configuration: the BDF2 step after
-    100 steps, where the oracle comparison covers only the first. The mixed
-    path's bound is its 1e-6 tolerance against FP64 (the residuals scale its
-    error by at most one)."""
-    m = make_workload("vesicle4096")[0]
-    note(f"vesicle4096 {precision}: residuals of step 100")
-    l0, l1, l2 = late_levels(m, precision, 100)
+@pytest.mark.parametrize("name,precision", [("vesicle1024", "fp64"), ("vesicle2048", "mixed"),
+                                            ("vesicle4096", "fp64"), ("vesicle4096", "mixed")])
+def test_last_step_of_each_workload_satisfies_the_discrete_equations(name, precision):
+    """The single-vesicle workloads in the benchmark's launch configuration, at
+    their last step (1000 at N = 1024, 500 at 2048 and 4096), where the oracle
+    comparison covers only the first steps. Bounds: 1e-12 in FP64, the 1e-6
+    tolerance of the mixed path (the residuals scale its error by at most one)."""
+    m = make_workload(name)[0]
+    k = WORKLOADS[name]["steps"]
+    note(f"{name} {precision}: residuals of step {k}")
+    l0, l1, l2 = late_levels(m, precision, k)
     r = R.step_residuals(*l1, *l2, R.Params.from_dict(m.params), *l0)
-    note(f"{precision} step 100 {r}")
+    note(f"{name} {precision} step {k} {r}")
+    assert max(r.values()) <= (RES_TOL if precision == "fp64" else REL_TOL), r
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", RES_TOL), ("mixed", REL_TOL)])
+def test_bdf1_scheme_on_the_bench_grid_satisfies_its_equations(precision, tol):
+    """The CC-MSAV-BDF1 scheme (every step BDF1) at N = 4096 after 100 steps."""
+    m = make_workload("vesicle4096")[0]
+    note(f"vesicle4096 bdf1 scheme {precision}: residuals of step 100")
+    _, l1, l2 = late_levels(m, precision, 100, bdf1=True)
+    r = R.step_residuals(*l1, *l2, R.Params.from_dict(m.params))
+    note(f"bdf1 {precision} step 100 {r}")
     assert max(r.values()) <= tol, r
 
 
