@@ -994,7 +994,8 @@ constexpr int SOLVE_THREADS = 512;
 __device__ __forceinline__ void solve_body(gptr<const double> __restrict__ p1, int n1,
                                            gptr<const double> __restrict__ p2, int n2,
                                            gptr<DevScalars> __restrict__ ds, const StepConst& c) {
-  __shared__ double red[SOLVE_THREADS + (P1_NSUM > P2_NSUM ? P1_NSUM : P2_NSUM)];
+  constexpr int NV_MAX = (int)P1_NSUM > (int)P2_NSUM ? (int)P1_NSUM : (int)P2_NSUM;
+  __shared__ double red[SOLVE_THREADS + NV_MAX];
   const int tid = threadIdx.x;
   double T1[P1_NSUM], T2[P2_NSUM];
   reduce_columns<P1_NSUM, SOLVE_THREADS>(p1, n1, red, tid, T1);
