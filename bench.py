@@ -55,6 +55,31 @@ def gemm_flops(members):
 BF16_PEAK_TFLOPS = 2500.0
 
 
+# Algorithmic bytes per cell of the step's four passes in the pipeline model
+# of the measurement plan (FP64 state; FP64 or FP32 intermediates):
+#   P1 stencil terms + row DCT-II, one pass: reads phi, psi at levels n and
+#      n-1 (level n only in the BDF1 scheme), writes the 8 x-transformed fields;
+#   P2 column DCT-II + Parseval sums: reads 8;
+#   P3 combine, divide, column DCT-III: reads 7, writes 2;
+#   P4 row DCT-III: reads 2 (+ phi^n, psi^n in the increment form), writes the
+#      2 new state fields.
+# FP64: 96 + 64 + 72 + 32 = 264 B; mixed: 64 + 32 + 36 + 40 = 172 B. This build
+# runs P1 as two launches (k_stencil, then k_row_dct8) with the 8 stencil
+# fields in HBM between them, and its stencil reads level n-2 as well for the
+# lagged ||d||^2: kernel_bytes_per_cell below counts those extra bytes
+# (252 B mixed, 408 B FP64), this model does not.
+PASSES = {"P1": ("stencil", "row_dct"), "P2": ("col_gram",), "P3": ("col_solve",),
+          "P4": ("row_idct",)}
+
+
+def pass_bytes_per_cell(precision: str, scheme: str = "bdf2"):
+    m = 8 if precision == "fp64" else 4
+    levels = 2 if scheme == "bdf2" else 1
+    inc = precision != "fp64"
+    return {"P1": 2 * levels * 8 + 8 * m, "P2": 8 * m, "P3": 9 * m,
+            "P4": 2 * m + 2 * 8 + (2 * 8 if inc else 0)}
+
+
 def kernel_bytes_per_cell(precision: str, scheme: str = "bdf2"):
     m = 8 if precision == "fp64" else 4
     # The BDF1 scheme's stencil pass reads level n only (phi*, psi* = phi^n, psi^n).
@@ -87,9 +112,10 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(workload: str, precision: str, kernel: str, cells: int):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.txt")
+def _traffic_record(workload: str, precision: str):
+    """key: value lines of profiles/traffic_<workload>_<precision>.txt, or None
+    when absent or taken on other kernel sources than these."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -99,34 +125,200 @@ def stored_traffic(workload: str, precision: str, kernel: str, cells: int):
             kv[k.strip()] = v.strip()
     if kv.get("source_sha") != source_digest():
         return None
+    return kv
+
+
+def stored_traffic(workload: str, precision: str, pass_name: str, cells: int):
+    """HBM bytes of one run of a pass (the sum over its launches) from the
+    committed rocprofv3 counter summary, or None."""
+    kv = _traffic_record(workload, precision)
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv[f"{pass_name}_bytes_per_cell"]) * cells if kv else None
     except (KeyError, ValueError):
         return None
 
 
-def cpu_baseline(members, budget_s: float = 12.0):
-    """FP64 oracle timed on this host over a bounded sample of the workload:
-    the first two steps (one BDF1, one BDF2) of as many members as fit in
-    about ``budget_s`` seconds (at least one)."""
+def stored_step_traffic(workload: str, precision: str):
+    """HBM bytes per cell of one step from the committed counter summary, or None."""
+    kv = _traffic_record(workload, precision)
+    try:
+        return float(kv["step_bytes_per_cell"]) if kv else None
+    except (KeyError, ValueError):
+        return None
+
+
+# ---- digests of rocprofv3 output into the summaries under profiles/ ----------
+
+def _csv_rows(directory: str, suffix: str):
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(directory, "**", f"*{suffix}"), recursive=True)):
+        with open(path, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {directory}")
+    return rows
+
+
+def _short(name: str) -> str:
+    """Kernel name without the argument list."""
+    depth = 0
+    for i, ch in enumerate(name):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i]
+    return name
+
+
+def digest_trace(directory: str, name: str, command: str):
+    """profiles/kernel_trace_<name>.md from a rocprofv3 --kernel-trace --stats run."""
+    rows = _csv_rows(directory, "kernel_stats.csv")
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# rocprofv3 kernel trace: {name}", "",
+             "Command (run from the repository root on one MI355X):", "", "```", command, "```", "",
+             "| kernel | calls | avg us | min us | max us | share % |",
+             "|---|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+        lines.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
+                     f"{100.0 * float(r['TotalDurationNs']) / total:.1f} |")
+    path = os.path.join(ROOT, "profiles", f"kernel_trace_{name}.md")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(path)
+
+
+def _counter_means(directory: str, counter: str):
+    """{kernel: (dispatches, mean KiB per dispatch)} and the largest copy-kernel value."""
+    acc = {}
+    copy = 0.0
+    for r in _csv_rows(directory, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        k = _short(r["Kernel_Name"])
+        v = float(r["Counter_Value"])
+        n, t = acc.get(k, (0, 0.0))
+        acc[k] = (n + 1, t + v)
+        if "copyBuffer" in k:
+            copy = max(copy, v)
+    return {k: (n, t / n) for k, (n, t) in acc.items()}, copy
+
+
+def digest_counters(fetch_dir: str, write_dir: str, workload: str, precision: str,
+                    probe_mib: int, commands: str, autotuned: str):
+    """profiles/traffic_<workload>_<precision>.{md,txt} from one FETCH_SIZE and
+    one WRITE_SIZE run of the same command ending with a plain device copy of
+    probe_mib MiB: each counter is scaled so that the copy reads and writes
+    its size, and per-dispatch bytes are divided by the cells of the grid.
+    ``autotuned`` names the launch variant of each tuned kernel that the timed
+    steps used, as `row_dct=1,col_solve=1,row_idct=0` (the first step runs
+    both variants)."""
+    from workloads import make_workload
+    cells = sum(m.phi0.size for m in make_workload(workload))
+    fetch, copy_f = _counter_means(fetch_dir, "FETCH_SIZE")
+    write, copy_w = _counter_means(write_dir, "WRITE_SIZE")
+    kib = probe_mib * 1024.0
+    if copy_f <= 0 or copy_w <= 0:
+        raise SystemExit("no copy-kernel dispatch found for the calibration")
+    sf, sw = kib / copy_f, kib / copy_w
+    per_cell = lambda v, s: v * s * 1024.0 / cells  # noqa: E731
+    var = dict(kv.split("=") for kv in autotuned.split(",")) if autotuned else {}
+    names = {"stencil": "k_stencil", "row_dct": "k_row_dct8", "col_gram": "k_col_gram",
+             "solve5": "k_solve", "col_solve": "k_col_solve", "row_idct": "k_row_idct"}
+    algo = kernel_bytes_per_cell(precision)
+    rows, used = [], {}
+    for k in sorted(set(fetch) | set(write)):
+        nf, f = fetch.get(k, (0, 0.0))
+        nw, w = write.get(k, (0, 0.0))
+        bf, bw = per_cell(f, sf), per_cell(w, sw)
+        phase = next((ph for ph, kn in names.items() if f"ccm::{kn}<" in k or k == f"ccm::{kn}"), None)
+        chosen = phase is not None and (phase not in var or k.rstrip(">").endswith(f", {var[phase]}"))
+        if chosen:
+            # launches of several grid shapes (an ensemble) add up
+            used[phase] = (used.get(phase, (0.0, ""))[0] + bf + bw, k)
+        rows.append(f"| `{k}` | {max(nf, nw)} | {bf:.2f} | {bw:.2f} | {bf + bw:.2f} | "
+                    f"{algo.get(phase, '') if phase else ''} | {'yes' if chosen else ''} |")
+    step = sum(b for b, _ in used.values())
+    passes = {ps: sum(used[k][0] for k in ks if k in used) for ps, ks in PASSES.items()}
+    digest = source_digest()
+    md = [f"# HBM traffic per kernel launch: {workload}, {precision}", "",
+          "Two rocprofv3 counter runs, from the repository root on one MI355X:", "", "```",
+          commands, "```", "",
+          f"Calibration: each run ends with a plain {probe_mib} MiB device copy. For that copy "
+          f"FETCH_SIZE reads {copy_f:.1f} KiB and WRITE_SIZE {copy_w:.1f} KiB of {kib:.0f} KiB moved, "
+          f"so FETCH_SIZE is scaled by {sf:.4f} and WRITE_SIZE by {sw:.4f}. Bytes per cell = scaled "
+          f"KiB per dispatch x 1024 / {cells} cells. Kernel sources hashed `{digest}` (code only, "
+          "as bench.py's source_digest). The first step runs both launch variants of the "
+          "autotuned kernels; 'step' marks the ones the timed steps use.", "",
+          "| kernel | dispatches | fetch B/cell | write B/cell | total B/cell | algorithmic B/cell "
+          "(this build's kernels) | step |", "|---|---|---|---|---|---|---|", *rows, "",
+          f"Per step (the kernels marked 'step'): {step:.2f} B/cell. Per pass of the pipeline "
+          f"model (algorithmic {pass_bytes_per_cell(precision)}): " +
+          ", ".join(f"{ps} {b:.2f}" for ps, b in passes.items()) + " B/cell."]
+    base = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}")
+    with open(base + ".md", "w") as f:
+        f.write("\n".join(md) + "\n")
+    txt = [f"# counter bytes per cell, {workload} {precision}; see traffic_{workload}_{precision}.md",
+           f"workload: {workload}", f"precision: {precision}", f"source_sha: {digest}",
+           f"fetch_scale: {sf:.6f}", f"write_scale: {sw:.6f}",
+           f"step_bytes_per_cell: {step:.4f}"]
+    txt += [f"{ps}_bytes_per_cell: {b:.4f}" for ps, b in passes.items()]
+    txt += [f"{ph}_bytes_per_cell: {b:.4f}" for ph, (b, _) in sorted(used.items())]
+    with open(base + ".txt", "w") as f:
+        f.write("\n".join(txt) + "\n")
+    print(base + ".md")
+
+
+def host_cores() -> int:
+    """Cores this process may run on (the affinity mask), else os.cpu_count()."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+def _oracle_leg(members, budget_s: float, workers: int):
+    """The FP64 oracle as it stands over the first two steps (one BDF1, one
+    BDF2) of as many members as fit in about ``budget_s`` seconds (at least
+    one), with scipy's transforms on ``workers`` threads."""
+    import scipy.fft
     from oracle import ccmsav_ref as R
     cells = 0
     taken = 0
     used = 0.0
-    for m in members:
-        st = R.initial_state(m.phi0, m.psi0, m.params)
-        t0 = time.perf_counter()
-        R.step(st)
-        R.step(st)
-        used += time.perf_counter() - t0
-        cells += m.phi0.size * 2
-        taken += 1
-        if used > budget_s:
-            break
+    with scipy.fft.set_workers(workers):
+        for m in members:
+            st = R.initial_state(m.phi0, m.psi0, m.params)
+            t0 = time.perf_counter()
+            R.step(st)
+            R.step(st)
+            used += time.perf_counter() - t0
+            cells += m.phi0.size * 2
+            taken += 1
+            if used > budget_s:
+                break
+    return cells / used / 1e6, taken, used
+
+
+def cpu_baseline(members, budget_s: float = 12.0):
+    """FP64 oracle timed on this host over a bounded sample of the workload:
+    once with scipy's transforms (the oracle's DCTs above N = 512) on every
+    core of the host, once on one thread. The all-core leg is the reported
+    value; numpy's pointwise and stencil arithmetic stays on one thread in
+    both, as the oracle is written."""
+    cores = host_cores()
+    v_all, taken, used_all = _oracle_leg(members, budget_s, cores)
+    v_one, _, used_one = _oracle_leg(members[:taken], budget_s, 1)
     sizes = sorted({m.params["nx"] for m in members[:taken]})
-    return {"value": cells / used / 1e6, "unit": "Mcell-steps/s", "cores": 1, "kind": "oracle",
+    return {"value": v_all, "unit": "Mcell-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"the first 2 steps (one BDF1, one BDF2) of {taken} of {len(members)} "
-                      f"member(s) (N={sizes}): {used:.2f} s, single-threaded numpy/scipy"}
+                      f"member(s) (N={sizes}), numpy/scipy FP64: {used_all:.2f} s with scipy.fft "
+                      f"on {cores} threads; {used_one:.2f} s on one thread",
+            "single_thread_value": v_one, "host_cpu_count": os.cpu_count()}
 
 
 def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, graph,
@@ -259,7 +451,24 @@ def main():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="after timing, copy this many MiB with a plain torch copy "
                          "(a known-size kernel that calibrates rocprofv3 byte counters)")
+    ap.add_argument("--digest-trace", nargs=2, metavar=("DIR", "NAME"),
+                    help="write profiles/kernel_trace_NAME.md from a rocprofv3 --stats output "
+                         "directory (no GPU work); --digest-command gives the command text")
+    ap.add_argument("--digest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic_<workload>_<precision>.{md,txt} from a "
+                         "FETCH_SIZE and a WRITE_SIZE rocprofv3 run (no GPU work)")
+    ap.add_argument("--digest-command", default="", help="command text for the digests")
+    ap.add_argument("--digest-autotuned", default="",
+                    help="launch variants of the timed steps, e.g. row_dct=1,col_solve=1,row_idct=0")
     args = ap.parse_args()
+    if args.digest_trace:
+        digest_trace(args.digest_trace[0], args.digest_trace[1], args.digest_command)
+        return
+    if args.digest_counters:
+        digest_counters(args.digest_counters[0], args.digest_counters[1], args.workload,
+                        args.precision, args.copy_probe_mib or 256, args.digest_command,
+                        args.digest_autotuned)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the single-grid step is run on one MI355X).", file=sys.stderr)
@@ -312,15 +521,30 @@ def main():
                     "step_flops": sum(fl.values()),
                     "step_frac": sum(fl.values()) / (ms_per_step * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}
     elif prof:
-        dom = max(prof, key=prof.get)
-        dom_bytes = per_cell[dom] * cells
-        achieved = dom_bytes / (prof[dom] * 1e-3) / 1e9
+        # The dominant pass of the pipeline model, by its launches' mean
+        # durations on the library's stream (HIP events); P1 is the stencil
+        # launch plus the row DCT launch.
+        pb = pass_bytes_per_cell(args.precision, args.scheme)
+        pass_ms = {ps: sum(prof[k] for k in ks) for ps, ks in PASSES.items()}
+        for ps, ms in pass_ms.items():
+            print(f"[bench] pass {ps} ({'+'.join(PASSES[ps])}): {ms * 1e3:.1f} us, {pb[ps]} B/cell "
+                  f"(pipeline model), {pb[ps] * cells / (ms * 1e-3) / 1e9:.0f} GB/s",
+                  file=sys.stderr, flush=True)
+        dom = max(pass_ms, key=pass_ms.get)
+        dom_bytes = pb[dom] * cells
+        achieved = dom_bytes / (pass_ms[dom] * 1e-3) / 1e9
         traffic = stored_traffic(args.workload, args.precision, dom, cells)
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                    "bytes_per_launch": dom_bytes, "us_per_launch": prof[dom] * 1e3,
-                    "step_bytes_per_cell": sum(per_cell.values()),
-                    "step_frac": sum(per_cell.values()) * value * 1e6 / 1e9 / HBM_PEAK_GBS}
+        roofline = {"bound": "hbm", "kernel": f"{dom}: " + " + ".join(PASSES[dom]),
+                    "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                    "bytes_per_launch": dom_bytes, "us_per_launch": pass_ms[dom] * 1e3,
+                    "pass_us": {ps: ms * 1e3 for ps, ms in pass_ms.items()},
+                    "step_bytes_per_cell": sum(pb.values()),
+                    "step_frac": sum(pb.values()) * value * 1e6 / 1e9 / HBM_PEAK_GBS,
+                    "kernel_bytes_per_cell": per_cell,
+                    "kernel_step_frac": sum(per_cell.values()) * value * 1e6 / 1e9 / HBM_PEAK_GBS,
+                    "counter_bytes_per_cell_step": stored_step_traffic(args.workload,
+                                                                       args.precision)}
 
     finite = all(bool(np.all(np.isfinite(f[0]))) for f in run["fields"])
     if not bdf1:

@@ -623,7 +623,13 @@ def step_residuals(phi_n, psi_n, sav_n, phi_new, psi_new, sav_new, p: Params,
 
     Returns relative residuals: ``chi`` = max|chi phi - rhs| over
     sigma_max max|phi|, ``zeta`` likewise with tau_max, ``sav`` = the largest
-    |x_i - (F_i, .)| over (|F_i|, |.|).
+    |x_i - (F_i, .)| over (|F_i|, |.|). The first two weigh every mode by the
+    largest eigenvalue of the operator, so a smooth error (weighted by sigma
+    near C1 and tau near alpha) shows sigma_max / C1 times smaller than it is.
+    ``chi_inv`` = max|chi^{-1} r_phi| / max|phi^{n+1}| and ``zeta_inv`` =
+    max|zeta^{-1} r_psi| / max|psi^{n+1}| map the residuals back through the
+    operators (App. C's spectral solve): chi^{-1} r_phi is the change of
+    phi^{n+1} that the residual stands for, in every mode alike.
     """
     h, dt = p.h, p.dt
     bdf2 = phi_m is not None
@@ -670,9 +676,14 @@ def step_residuals(phi_n, psi_n, sav_n, phi_new, psi_new, sav_new, p: Params,
         sav = max(sav, abs(xi - ip(F, phi_new, h)) / ip(np.abs(F), aphi, h))
     sav = max(sav, abs(x[3] - ip(K, phi_new, h) - ip(P, psi_new, h))
               / (ip(np.abs(K), aphi, h) + ip(np.abs(P), apsi, h)))
+    lam_h = neumann_lap_eigs(p.nx, p.ny, h)
+    e_phi = spectral_solve(r_phi, C1 - C2 * lam_h + C3 * lam_h ** 2)
+    e_psi = spectral_solve(r_psi, alpha - p.lam * lam_h)
     return dict(chi=float(np.max(np.abs(r_phi)) / (sig_max * np.max(aphi))),
                 zeta=float(np.max(np.abs(r_psi)) / (tau_max * np.max(apsi))),
-                sav=float(sav))
+                sav=float(sav),
+                chi_inv=float(np.max(np.abs(e_phi)) / np.max(aphi)),
+                zeta_inv=float(np.max(np.abs(e_psi)) / np.max(apsi)))
 
 
 def run(phi0, psi0, params: Dict, nsteps: int, use_matrix=None, bdf1: bool = False) -> State:

@@ -555,3 +555,39 @@ def test_step_residuals_detect_perturbations():
         sav = l2[2].copy()
         sav[i] += 1e-9 * abs(sav[i])
         assert R.step_residuals(*l1, l2[0], l2[1], sav, p, *l0)["sav"] >= 1e-12, i
+
+
+@pytest.mark.parametrize("mode", ["constant", "lowest", "diagonal", "noise"])
+def test_operator_inverted_residuals_recover_planted_errors(mode):
+    """chi^{-1} r_phi and zeta^{-1} r_psi return an error planted in phi^{n+1}
+    or psi^{n+1} at its own size, whatever its mode: the residual of
+    phi^{n+1} + e is chi e (the equations are linear in the new level), so
+    the operator-inverted residual is e itself, and its relative size is
+    max|e| / max|phi^{n+1}| up to rounding. The spectral-radius normalised
+    residual sees a constant e only at C1 / sigma_max of that size."""
+    p, (l0, l1, l2) = _three_levels()
+    ny, nx = l2[0].shape
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+    shape = {"constant": np.ones((ny, nx)), "lowest": np.cos(math.pi * X),
+             "diagonal": np.cos(math.pi * X) * np.cos(2 * math.pi * Y),
+             "noise": np.random.default_rng(5).uniform(-1.0, 1.0, (ny, nx))}[mode]
+    for which, key, key_inv in ((0, "chi", "chi_inv"), (1, "zeta", "zeta_inv")):
+        amp = 1e-9 * np.abs(l2[which]).max()
+        e = amp * shape / np.abs(shape).max()
+        new = [l2[0], l2[1]]
+        new[which] = new[which] + e
+        r = R.step_residuals(*l1, new[0], new[1], l2[2], p, *l0)
+        want = np.abs(e).max() / np.abs(new[which]).max()
+        assert r[key_inv] == pytest.approx(want, rel=1e-3), (which, mode, r)
+        if mode == "constant":
+            # the spectral-radius normalisation sees the (0, 0) mode at
+            # op(0) / op_max of its size: C1 / sigma_max for chi, alpha /
+            # tau_max for zeta (393 and 1.8e3 at N = 4096 for the vesicle family)
+            alpha = 1.5 / p.dt
+            C1, C2, C3 = R.chi_coefficients(p, alpha)
+            lmax = 8.0 / p.h ** 2
+            ratio = (C1 / (C1 + C2 * lmax + C3 * lmax ** 2) if which == 0
+                     else alpha / (alpha + p.lam * lmax))
+            assert r[key] == pytest.approx(want * ratio, rel=1e-3), (which, mode, r)

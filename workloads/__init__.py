@@ -9,6 +9,10 @@ from .generators import (  # noqa: F401
     VESICLE_DT,
     ENSEMBLE_DT,
     WORKLOADS,
+    GENERAL_SETS,
+    general_dt,
+    general_member,
+    general_params,
     Member,
     circle_member,
     vesicle_member,

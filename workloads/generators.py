@@ -79,6 +79,47 @@ def table_g_params(n: int, eps_cells: float, shrink: bool, c_in: float,
     )
 
 
+# Parameter sets in which every coefficient differs from the App. G table, so
+# that each term of the scheme carries its own weight: M_phi != 1 multiplies
+# every Allen-Cahn constant, beta > 0 enters S~, r_S and C1, beta_in and
+# beta_out differ and enter r_Z, gamma_in != gamma_out makes P~ asymmetric,
+# and M0, theta, lambda all move. Row 0 is the reference set; the other rows
+# vary it for the members of a mixed ensemble.
+GENERAL_SETS = (
+    dict(M_phi=0.7, M0=0.3, gamma_surf=1.3, gamma_bend=0.5, gamma_area=20.0,
+         gamma_in=40.0, gamma_out=60.0, beta_in=0.2, beta_out=0.1,
+         theta=3.0, lam=5.0, beta=0.3),
+    dict(M_phi=1.4, M0=0.45, gamma_surf=0.8, gamma_bend=0.9, gamma_area=35.0,
+         gamma_in=70.0, gamma_out=30.0, beta_in=0.05, beta_out=0.25,
+         theta=1.0, lam=8.0, beta=0.15),
+    dict(M_phi=0.5, M0=0.1, gamma_surf=1.6, gamma_bend=0.3, gamma_area=10.0,
+         gamma_in=25.0, gamma_out=45.0, beta_in=0.3, beta_out=0.3,
+         theta=4.5, lam=3.0, beta=0.5),
+    dict(M_phi=1.1, M0=0.6, gamma_surf=1.15, gamma_bend=1.2, gamma_area=50.0,
+         gamma_in=55.0, gamma_out=20.0, beta_in=0.15, beta_out=0.02,
+         theta=2.0, lam=12.0, beta=0.05),
+)
+
+
+def general_dt(n: int) -> float:
+    """Time step of the general parameter sets on a grid of n cells per side:
+    1e-4 (16 / n)^2, where an FP64 run from inputs changed by one ulp stays
+    within about 1e-13 of the unchanged run over 60 steps (16^2 .. 256^2)."""
+    return 1.0e-4 * (16.0 / n) ** 2
+
+
+def general_params(nx: int, ny: int, variant: int = 0, eps_cells: float = 4.0,
+                   c_in: float = 1.0, dt: Optional[float] = None,
+                   length: float = DOMAIN_L) -> Dict:
+    """Parameters of GENERAL_SETS[variant] on an nx x ny grid with h = length / max(nx, ny)."""
+    n = max(nx, ny)
+    h = length / n
+    p = dict(nx=nx, ny=ny, h=h, dt=general_dt(n) if dt is None else dt, eps=eps_cells * h,
+             A=float("nan"), psi_in=c_in - PSI_GAP, psi_out=c_in + PSI_GAP)
+    p.update(GENERAL_SETS[variant])
+    return p
+
+
 @dataclasses.dataclass
 class Member:
     """One vesicle: initial fields plus its parameter dictionary."""
@@ -143,6 +184,26 @@ def vesicle_member(n: int, seed: int, c_out_range=(0.8, 1.2),
     return Member(name or f"vesicle{n}_s{seed}", phi0, psi0, params,
                   dict(seed=seed, c_in=c_in, c_out=c_out, amps=amps.tolist(),
                        phases=phases.tolist(), eps_cells=eps_cells))
+
+
+def general_member(nx: int, ny: int, seed: int, variant: int = 0,
+                   eps_cells: float = 4.0) -> Member:
+    """A perturbed vesicle (the recipe of vesicle_member on the square grid of
+    max(nx, ny) cells, cut to ny x nx: the lower-left part for a rectangle)
+    with the parameters of GENERAL_SETS[variant]."""
+    n = max(nx, ny)
+    base = vesicle_member(n, seed, eps_choices=None)
+    params = general_params(nx, ny, variant, eps_cells)
+    phi0 = np.ascontiguousarray(base.phi0[:ny, :nx])
+    psi0 = np.ascontiguousarray(base.psi0[:ny, :nx])
+    if eps_cells != 4.0:
+        # re-profile the same boundary at this interface width
+        phi0 = np.ascontiguousarray(np.tanh(np.arctanh(np.clip(phi0, -1 + 1e-15, 1 - 1e-15))
+                                            * 4.0 / eps_cells))
+        c_in, c_out = base.meta["c_in"], base.meta["c_out"]
+        psi0 = np.ascontiguousarray(c_in * (1.0 + phi0) * 0.5 + c_out * (1.0 - phi0) * 0.5)
+    return Member(f"general{nx}x{ny}_s{seed}_v{variant}", phi0, psi0, params,
+                  dict(base.meta, variant=variant))
 
 
 # Named workloads with their sizes and step counts.
