@@ -273,6 +273,42 @@ int ccmsav_elliptic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, dou
 int ccmsav_elliptic_solve_bc(ccmsav_ctx* c, int32_t bc, const double* rhs, double* out_chi,
                              double* out_zeta);
 
+/* Bytes of device memory that ccmsav_elliptic_solve_noalloc holds on each GPU
+ * the library runs on (a fixed array, kept until the process ends). */
+#define CCMSAV_NOALLOC_SCRATCH_BYTES (27u * 1024u * 1024u)
+
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, and harnesses that forbid hipMalloc. The
+ * solve of ccmsav_elliptic_solve without a context: out_chi = chi^{-1} rhs and
+ * out_zeta = zeta^{-1} rhs with the BDF2 operators (the constants listed at
+ * ccmsav_elliptic_solve) of the parameters p, homogeneous Neumann boundaries,
+ * FP64 transforms (p->precision CCMSAV_FP64) or FP32 transforms
+ * (CCMSAV_MIXED). The same kernels as ccmsav_elliptic_solve; results agree
+ * with it to rounding (the eigenvalue tables are formed on the device).
+ *  - p: the parameters of the grid and operators (checked as at init; p->A,
+ *    flags and the osmotic parameters are not used). nx, ny powers of two in
+ *    [16, 1024].
+ *  - rhs: nx*ny doubles, row-major, in device (or managed) memory of the
+ *    current device; out_chi, out_zeta likewise, or NULL to skip. Outputs may
+ *    not alias rhs. The caller owns all three.
+ *  - hip_stream: a hipStream_t of the current device (NULL = default stream).
+ *    The work is enqueued on it and the call returns without waiting.
+ *  - Scratch: every call uses the library's CCMSAV_NOALLOC_SCRATCH_BYTES array
+ *    on the current device, and keeps no state in it between calls (nothing
+ *    has to start at zero). Calls on one GPU that overlap in time (other
+ *    streams, other host threads) race on that array: order them, for
+ *    example on one stream.
+ *  - Allocates nothing: no hipMalloc or hipFree and no host-to-device copy;
+ *    the tables and the kernels' argument block are written by a kernel. The
+ *    first call on a device looks up the array's device address.
+ * Returns EINVAL (NULL rhs, bad parameter, a pointer that is not device memory
+ * of the current device), EUNSUPPORTED (a grid beyond 1024 per direction,
+ * the DCT-as-GEMM precision), EHIP.
+ */
+int ccmsav_elliptic_solve_noalloc(const ccmsav_params* p, const double* rhs, double* out_chi,
+                                  double* out_zeta, void* hip_stream);
+
 /*
  * Smoothed initial phase field (App. F): from phi_sharp, take nsteps steps of
  * the constant-mobility Cahn-Hilliard relaxation phi_t = M Delta(f'(phi)/eps

@@ -36,6 +36,7 @@ EXPORTED = (
     "ccmsav_members", "ccmsav_energy_m", "ccmsav_mass_m", "ccmsav_get_fields_m",
     "ccmsav_get_savs_m", "ccmsav_tuning", "ccmsav_smooth_ic", "ccmsav_physical_energy",
     "ccmsav_physical_energy_m", "ccmsav_set_launch_variants", "ccmsav_elliptic_solve_bc",
+    "ccmsav_elliptic_solve_noalloc",
 )
 PHASES = ("stencil", "row_dct", "col_gram", "solve5", "col_solve", "row_idct")
 
@@ -102,6 +103,7 @@ def load() -> ctypes.CDLL:
     lib.ccmsav_profile_steps.argtypes = [vp, ctypes.c_int32, dp]
     lib.ccmsav_elliptic_solve.argtypes = [vp, vp, vp, vp]
     lib.ccmsav_elliptic_solve_bc.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+    lib.ccmsav_elliptic_solve_noalloc.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp]
     lib.ccmsav_smooth_ic.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp]
     lib.ccmsav_physical_energy.argtypes = [vp, dp]
     lib.ccmsav_physical_energy_m.argtypes = [vp, ctypes.c_int32, dp]
@@ -127,7 +129,7 @@ def load() -> ctypes.CDLL:
                "ccmsav_elliptic_solve", "ccmsav_smooth_ic", "ccmsav_destroy",
                "ccmsav_physical_energy", "ccmsav_physical_energy_m",
                "ccmsav_set_launch_variants", "ccmsav_elliptic_solve_bc",
-               "ccmsav_profile_steps",
+               "ccmsav_elliptic_solve_noalloc", "ccmsav_profile_steps",
                "ccmsav_init_batch", "ccmsav_energy_m", "ccmsav_mass_m",
                "ccmsav_get_fields_m", "ccmsav_get_savs_m"):
         getattr(lib, fn).restype = ctypes.c_int
@@ -142,6 +144,20 @@ def strerror(code: int) -> str:
 def workspace_bytes(params: Dict, precision=FP64) -> int:
     p = Params.from_dict(params, precision)
     return int(load().ccmsav_workspace_bytes(ctypes.byref(p)))
+
+
+def elliptic_solve_noalloc(params: Dict, rhs, out_chi, out_zeta, precision="fp64",
+                           stream=None):
+    """chi^{-1} rhs and zeta^{-1} rhs (device tensors) without a context and
+    without allocating: ccmsav_elliptic_solve_noalloc on ``stream`` (default:
+    torch's current stream)."""
+    p = Params.from_dict(dict(params, A=params.get("A", float("nan"))), precision)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(load().ccmsav_elliptic_solve_noalloc(ctypes.byref(p), _ptr(rhs), _ptr(out_chi),
+                                                _ptr(out_zeta), stream),
+           "ccmsav_elliptic_solve_noalloc")
 
 
 def _ptr(x) -> Optional[int]:

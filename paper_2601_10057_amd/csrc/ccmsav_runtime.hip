@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -40,6 +41,7 @@ constexpr int kNumTables = 6;
 constexpr int kSolveTable = 5;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr size_t align_up_c(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 int log2_exact(int n) {
   if (n <= 0 || (n & (n - 1)) != 0) return -1;
@@ -934,6 +936,97 @@ void launch_solve(ccmsav_ctx* c, const double* rhs) {
     run(0.0);
 }
 
+// ---- allocation-free standalone solve ------------------------------------------
+
+// Largest grid of ccmsav_elliptic_solve_noalloc: 1024 cells per direction.
+constexpr int kNoallocMaxLog = 10;
+constexpr int kNoallocMaxN = 1 << kNoallocMaxLog;
+// Scratch of one call, sized for FP64 intermediates at the largest grid:
+// the row-transformed right-hand side (one strip-major field, which also
+// takes an output that is not requested once the column solve has read it),
+// the two column-solved fields, the two eigenvalue tables, the unit
+// combination weights, the argument block and the member index.
+constexpr size_t kNoallocField = strip_field(kNoallocMaxN, kNoallocMaxN, 8) * 8;
+constexpr size_t kNoallocLayout =
+    align_up_c(kNoallocField) + align_up_c(2 * kNoallocField) + 2 * align_up_c(kNoallocMaxN * 8) +
+    align_up_c(8 * sizeof(double)) + align_up_c(sizeof(MemberArgs)) + align_up_c(sizeof(int));
+static_assert(kNoallocLayout <= CCMSAV_NOALLOC_SCRATCH_BYTES, "scratch layout exceeds its size");
+static_assert(sizeof(MemberArgs) % sizeof(uint64_t) == 0, "argument block copied as 8-byte words");
+
+// Operator tables, unit weights, argument block and member index of one
+// allocation-free solve, written on the device (no host-to-device copy).
+__global__ void __launch_bounds__(256)
+k_noalloc_setup(MemberArgs a, gptr<MemberArgs> args, gptr<int> idx, gptr<double> lamx,
+                gptr<double> lamy, gptr<double> coef, int nx, int ny, double h) {
+  const int tid = threadIdx.x;
+  // Eigenvalues of -Delta_h per direction (App. C): (4/h^2) sin^2(pi k / (2 n)).
+  for (int k = tid; k < nx; k += blockDim.x) {
+    const double s = sin(M_PI * k / (2.0 * nx));
+    lamx[k] = 4.0 / (h * h) * s * s;
+  }
+  for (int k = tid; k < ny; k += blockDim.x) {
+    const double s = sin(M_PI * k / (2.0 * ny));
+    lamy[k] = 4.0 / (h * h) * s * s;
+  }
+  if (tid < 8) coef[tid] = (tid == 0 || tid == 5) ? 1.0 : 0.0;
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(&a);
+  const auto dst = reinterpret_cast<gptr<uint64_t>>(args);
+  for (int i = tid; i < (int)(sizeof(MemberArgs) / sizeof(uint64_t)); i += blockDim.x)
+    dst[i] = src[i];
+  if (tid == 0) idx[0] = 0;
+}
+
+// Device address of the scratch array on each device, looked up once per
+// device with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch[kMaxDevices] = {};
+
+// Whether p is device (or managed) memory of device dev.
+bool on_device(const void* p, int dev) {
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();     // clear the error this query leaves for a host pointer
+    return false;
+  }
+  return (at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged) && at.device == dev;
+}
+
+}  // namespace
+
+// Scratch memory of ccmsav_elliptic_solve_noalloc: a fixed array on every
+// GPU the library runs on, held until the process ends. Host code never
+// uses this name as an address; it uses the device address looked up per
+// device (noalloc_scratch).
+static __device__ __align__(256) unsigned char scratch[CCMSAV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of `scratch` on the current device (set up at the first
+// call on that device), or nullptr with *rc set.
+char* noalloc_scratch(int* rc) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    *rc = CCMSAV_EHIP;
+    return nullptr;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    *rc = CCMSAV_EUNSUPPORTED;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      *rc = CCMSAV_EHIP;
+      return nullptr;
+    }
+    g_scratch[dev] = static_cast<char*>(ptr);
+  }
+  *rc = CCMSAV_OK;
+  return g_scratch[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -1428,6 +1521,67 @@ int ccmsav_smooth_ic(ccmsav_ctx* c, double M, double dt, int32_t nsteps, const d
   hipLaunchKernelGGL(k_clip_unit, dim3(blocks), dim3(SMOOTH_THREADS), 0, c->stream, cur, cells);
   HIP_TRY(hipMemcpyAsync(phi_out, cur, cells * sizeof(double), hipMemcpyDefault, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  return hipGetLastError() == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
+}
+
+int ccmsav_elliptic_solve_noalloc(const ccmsav_params* p, const double* rhs, double* out_chi,
+                                  double* out_zeta, void* hip_stream) {
+  if (!rhs) return CCMSAV_EINVAL;
+  const int pc = check_params(p);
+  if (pc != CCMSAV_OK) return pc;
+  if (is_gemm(p->precision)) return CCMSAV_EUNSUPPORTED;
+  const int lx = log2_exact(p->nx), ly = log2_exact(p->ny);
+  if (lx > kNoallocMaxLog || ly > kNoallocMaxLog) return CCMSAV_EUNSUPPORTED;
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (!on_device(rhs, dev) || (out_chi && !on_device(out_chi, dev)) ||
+      (out_zeta && !on_device(out_zeta, dev)))
+    return CCMSAV_EINVAL;
+  int rc = CCMSAV_OK;
+  char* base = noalloc_scratch(&rc);
+  if (!base) return rc;
+  // Scratch layout (kNoallocLayout); every part 256-byte aligned.
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* q = base + off;
+    off += align_up(bytes);
+    return q;
+  };
+  Member m{};
+  m.p = *p;
+  m.lx = lx;
+  m.ly = ly;
+  m.sh = stencil_shape(p->nx, p->ny);
+  m.mid = take(kNoallocField);
+  m.outc = take(2 * kNoallocField);
+  m.lamx = reinterpret_cast<double*>(take(kNoallocMaxN * sizeof(double)));
+  m.lamy = reinterpret_cast<double*>(take(kNoallocMaxN * sizeof(double)));
+  m.unit_coef = reinterpret_cast<double*>(take(8 * sizeof(double)));
+  MemberArgs* d_args = reinterpret_cast<MemberArgs*>(take(sizeof(MemberArgs)));
+  int* d_idx = reinterpret_cast<int*>(take(sizeof(int)));
+  MemberArgs a = member_args(m, p->precision, kSolveTable);
+  // An output that is not requested goes to the row-transformed right-hand
+  // side's region (FP64-sized), which the column solve has read before the
+  // row inverse writes.
+  a.phi_new = to_global(out_chi ? out_chi : reinterpret_cast<double*>(m.mid));
+  a.psi_new = to_global(out_zeta ? out_zeta : reinterpret_cast<double*>(m.mid));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipLaunchKernelGGL(k_noalloc_setup, dim3(1), dim3(256), 0, st, a, to_global(d_args),
+                     to_global(d_idx), to_global(m.lamx), to_global(m.lamy),
+                     to_global(m.unit_coef), p->nx, p->ny, p->h);
+  const int nx = p->nx, ny = p->ny;
+  auto run = [&](auto tm) {
+    using TM = decltype(tm);
+    using LT = typename Launch<TM>::T;
+    LT::t_rd[lx - kMinLog](st, ny, rhs, static_cast<TM*>(m.mid), M_F, ny);
+    LT::t_col_solve[0][ly - kMinLog](st, nx, Batch{d_args, d_idx, nx});
+    const int per = ny / row_idct_rows<TM>(nx, 0);
+    LT::t_row_idct[0][lx - kMinLog](st, per, Batch{d_args, d_idx, per});
+  };
+  if (p->precision != CCMSAV_FP64)
+    run(0.0f);
+  else
+    run(0.0);
   return hipGetLastError() == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
 }
 
