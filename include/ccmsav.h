@@ -58,11 +58,13 @@ typedef enum {
                                that h^2 sum psi is conserved to FP64 rounding.
                                FP64 state, SAVs, inner-product sums and 5x5 */
   CCMSAV_MIXED_GEMM_BF16X3 = 2 /* as CCMSAV_MIXED, with every transform a dense
-                               product with the DCT matrix on the matrix cores:
-                               bfloat16 hi/lo splits of both operands, three
-                               products (hi hi + hi lo + lo hi) accumulated in
-                               FP32. Single-member contexts without
-                               CCMSAV_FLAG_GRAPH only (else EUNSUPPORTED). */
+                               product with the DCT matrix on the matrix cores
+                               (the library's bf16 MFMA kernels): bfloat16
+                               hi/lo splits of both operands, three products
+                               (hi hi + hi lo + lo hi) accumulated in FP32; the
+                               DCT matrices live in the workspace. Single-member
+                               contexts without CCMSAV_FLAG_GRAPH, grids of at
+                               least 64 per direction (else EUNSUPPORTED). */
 } ccmsav_precision;
 
 /*

@@ -11,8 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libccmsav.so")
 SOURCES = ["ccmsav_runtime.hip"]
-# rocBLAS runs the dense products of the DCT-as-GEMM variant.
-LIBS = ["-lrocblas"]
+LIBS: list = []
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

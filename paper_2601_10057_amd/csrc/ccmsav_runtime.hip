@@ -17,11 +17,10 @@
 #include <new>
 #include <vector>
 
-#include <rocblas/rocblas.h>
-
 #include "ccmsav.h"
 #include "diag_kernels.hpp"
 #include "gemm_dct.hpp"
+#include "gemm_mfma.hpp"
 #include "periodic_kernels.hpp"
 #include "smooth_kernels.hpp"
 #include "step_kernels.hpp"
@@ -132,7 +131,7 @@ size_t p2_rows(const ccmsav_params* p) {
 
 struct Layout {
   size_t state, rm, mid, outc, part1, part2, parte, lamx, lamy, colsum, unit, ds;
-  size_t split, dx, dy;   // GEMM variant: bf16 operand halves, DCT matrices (hi, lo)
+  size_t dx, dy;   // GEMM variant: DCT matrix and its transpose per direction, bf16 hi and lo
   size_t total;
 };
 
@@ -158,9 +157,8 @@ Layout layout(const ccmsav_params* p) {
   L.unit = off;  off = align_up(off + 8 * sizeof(double));
   L.ds = off;    off = align_up(off + sizeof(DevScalars));
   if (is_gemm(p->precision)) {
-    L.split = off; off = align_up(off + 2 * M_NFIELD * cells * sizeof(uint16_t));
-    L.dx = off;    off = align_up(off + 2 * (size_t)p->nx * p->nx * sizeof(uint16_t));
-    L.dy = off;    off = align_up(off + 2 * (size_t)p->ny * p->ny * sizeof(uint16_t));
+    L.dx = off;    off = align_up(off + 4 * (size_t)p->nx * p->nx * sizeof(uint16_t));
+    L.dy = off;    off = align_up(off + 4 * (size_t)p->ny * p->ny * sizeof(uint16_t));
   }
   L.total = off;
   return L;
@@ -179,6 +177,8 @@ int check_params(const ccmsav_params* p) {
   if (p->nx <= 0 || p->ny <= 0) return CCMSAV_EINVAL;
   const int lx = log2_exact(p->nx), ly = log2_exact(p->ny);
   if (lx < kMinLog || lx > kMaxLog || ly < kMinLog || ly > kMaxLog) return CCMSAV_EUNSUPPORTED;
+  // the matrix-core products take tiles of at least 64 along each direction
+  if (is_gemm(p->precision) && (p->nx < 64 || p->ny < 64)) return CCMSAV_EUNSUPPORTED;
   if (!finite_pos(p->h) || !finite_pos(p->dt) || !finite_pos(p->eps) || !finite_pos(p->M_phi))
     return CCMSAV_EINVAL;
   if (!std::isfinite(p->M0) || p->M0 < 0.0 || p->M0 >= 1.0) return CCMSAV_EINVAL;
@@ -334,13 +334,16 @@ struct Member {
   double* unit_coef;       // {1, 0, 0, 0, 0, 1, 0, 0} for the standalone solve
   DevScalars* ds;
   StencilShape sh;
-  // GEMM variant
-  uint16_t* split_hi;      // bf16 halves of the current product operand (8 fields)
-  uint16_t* split_lo;
-  uint16_t* dx_hi;         // DCT-II matrix along x, column-major D_x (hi, lo halves)
+  // GEMM variant: bf16 hi and lo halves of the orthonormal DCT-II matrix D
+  // and of its transpose per direction, row-major
+  uint16_t* dx_hi;
   uint16_t* dx_lo;
+  uint16_t* dxt_hi;
+  uint16_t* dxt_lo;
   uint16_t* dy_hi;
   uint16_t* dy_lo;
+  uint16_t* dyt_hi;
+  uint16_t* dyt_lo;
 };
 
 // Members with one grid shape; d_idx lists their indices in device memory.
@@ -377,8 +380,6 @@ struct ccmsav_ctx {
   std::vector<hipStream_t> bstream;
   std::vector<hipEvent_t> bevent;
   hipEvent_t ev_fork = nullptr;
-  // DCT-as-GEMM variant
-  rocblas_handle blas = nullptr;
   // resident workgroups of the stencil pass on this device ([0] FP32, [1] FP64 intermediates)
   int stencil_slots[2] = {0, 0};
 };
@@ -560,36 +561,33 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe,
 
 // ---- DCT-as-GEMM variant ------------------------------------------------------
 
-// C = op(A) op(B) with both operands given as bf16 (hi, lo) halves:
-// C = A_hi B_hi + A_hi B_lo + A_lo B_hi, FP32 accumulation (column-major).
-int gemm3(ccmsav_ctx* c, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
-          const uint16_t* a_hi, const uint16_t* a_lo, int lda, int64_t sa, const uint16_t* b_hi,
-          const uint16_t* b_lo, int ldb, int64_t sb, float* out, int ldc, int64_t sc,
-          int batch) {
-  const float one = 1.0f, zero = 0.0f;
-  const uint16_t* as[3] = {a_hi, a_hi, a_lo};
-  const uint16_t* bs[3] = {b_hi, b_lo, b_hi};
-  for (int t = 0; t < 3; ++t) {
-    const rocblas_status r = rocblas_gemm_strided_batched_ex(
-        c->blas, ta, tb, m, n, k, &one, as[t], rocblas_datatype_bf16_r, lda, sa, bs[t],
-        rocblas_datatype_bf16_r, ldb, sb, t == 0 ? &zero : &one, out, rocblas_datatype_f32_r,
-        ldc, sc, out, rocblas_datatype_f32_r, ldc, sc, batch, rocblas_datatype_f32_r,
-        rocblas_gemm_algo_standard, 0, 0);
-    if (r != rocblas_status_success) return CCMSAV_EHIP;
-  }
-  return CCMSAV_OK;
-}
-
-void split(ccmsav_ctx* c, const Member& m, const float* x, size_t n, hipStream_t st) {
-  const int grid = (int)std::min<size_t>((n + GEMM_THREADS - 1) / GEMM_THREADS, 8192);
-  hipLaunchKernelGGL(k_split_bf16, dim3(grid), dim3(GEMM_THREADS), 0, st, x, m.split_hi,
-                     m.split_lo, n);
+// One product of the DCT-as-GEMM variant (gemm_mfma.hpp) with the largest
+// tiles that divide the grid.
+template <int MODE>
+void mf_product(hipStream_t st, const uint16_t* d_hi, const uint16_t* d_lo, const float* x,
+                float* out, int M, int N, int K, int ldx, int ldc, size_t sx, size_t sc,
+                int batch) {
+  const int bm = mf_tile(M), bn = mf_tile(N);
+  const dim3 grid((unsigned)(batch * (M / bm) * (N / bn)));
+  if (bm == 128 && bn == 128)
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 128>), grid, dim3(MF_THREADS), 0, st, d_hi,
+                       d_lo, x, out, M, N, K, ldx, ldc, sx, sc);
+  else if (bm == 128)
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 64>), grid, dim3(MF_THREADS), 0, st, d_hi,
+                       d_lo, x, out, M, N, K, ldx, ldc, sx, sc);
+  else if (bn == 128)
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 128>), grid, dim3(MF_THREADS), 0, st, d_hi,
+                       d_lo, x, out, M, N, K, ldx, ldc, sx, sc);
+  else
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 64>), grid, dim3(MF_THREADS), 0, st, d_hi,
+                       d_lo, x, out, M, N, K, ldx, ldc, sx, sc);
 }
 
 // One step of the single member with every transform a product with D.
-// Data flow (FP32, row-major [field][y][x]): stencil -> rm; rows: rm D_x^T ->
-// mid; columns: D_y mid -> rm (2D spectra); inner products, 5x5; combine ->
-// outc; columns: D_y^T outc -> mid; rows: mid D_x -> outc; state update.
+// Data flow (FP32, row-major [field][y][x]): stencil -> rm; rows: D_x rm ->
+// mid (the 8 fields' rows stacked); columns: mid_f D_y^T -> rm (2D spectra);
+// inner products, 5x5; combine -> outc; columns: outc_f D_y -> mid; rows:
+// D_x^T mid -> outc; state update.
 int enqueue_step_gemm(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEvents pe) {
   const Member& m = c->mem[0];
   const SizeClass& k = c->cls[0];
@@ -600,21 +598,15 @@ int enqueue_step_gemm(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEvents 
   float* rm = static_cast<float*>(m.rm);
   float* mid = static_cast<float*>(m.mid);
   float* outc = static_cast<float*>(m.outc);
-  const rocblas_operation N_ = rocblas_operation_none, T_ = rocblas_operation_transpose;
-  int r = CCMSAV_OK;
   pe.mark(0, st);
   hipLaunchKernelGGL(k_stencil<float>, dim3(stencil_grid(c, false, k.sh.blocks)),
                      dim3(STENCIL_THREADS), 0, st, tab, k.d_idx, k.sh.blocks, k.sh.blocks);
   pe.mark(1, st);
   pe.mark(2, st);
-  split(c, m, rm, M_NFIELD * cells, st);
-  r |= gemm3(c, N_, N_, nx, M_NFIELD * ny, nx, m.dx_hi, m.dx_lo, nx, 0, m.split_hi, m.split_lo,
-             nx, 0, mid, nx, 0, 1);
+  mf_product<MF_ROW>(st, m.dx_hi, m.dx_lo, rm, mid, nx, M_NFIELD * ny, nx, nx, nx, 0, 0, 1);
   pe.mark(3, st);
   pe.mark(4, st);
-  split(c, m, mid, M_NFIELD * cells, st);
-  r |= gemm3(c, N_, T_, nx, ny, ny, m.split_hi, m.split_lo, nx, (int64_t)cells, m.dy_hi,
-             m.dy_lo, ny, 0, rm, nx, (int64_t)cells, M_NFIELD);
+  mf_product<MF_COL>(st, m.dy_hi, m.dy_lo, mid, rm, nx, ny, ny, nx, nx, cells, cells, M_NFIELD);
   hipLaunchKernelGGL(k_gemm_gram, dim3((unsigned)gemm_gram_blocks(&m.p)), dim3(GEMM_THREADS), 0,
                      st, rm, m.lamx, m.lamy, m.part2, nx, ny, kGramPerThread, ha.k);
   pe.mark(5, st);
@@ -625,21 +617,17 @@ int enqueue_step_gemm(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEvents 
   hipLaunchKernelGGL(k_gemm_combine, dim3((unsigned)std::min<size_t>(cells / GEMM_THREADS + 1, 8192)),
                      dim3(GEMM_THREADS), 0, st, rm, m.ds->coef, m.lamx, m.lamy, outc, nx, ny,
                      ha.k);
-  split(c, m, outc, 2 * cells, st);
-  r |= gemm3(c, N_, N_, nx, ny, ny, m.split_hi, m.split_lo, nx, (int64_t)cells, m.dy_hi,
-             m.dy_lo, ny, 0, mid, nx, (int64_t)cells, 2);
+  mf_product<MF_COL>(st, m.dyt_hi, m.dyt_lo, outc, mid, nx, ny, ny, nx, nx, cells, cells, 2);
   hipLaunchKernelGGL(k_gemm_colsum, dim3(1), dim3(GEMM_THREADS), 0, st, mid + cells, m.colsum,
                      nx, ny);
   pe.mark(9, st);
   pe.mark(10, st);
-  split(c, m, mid, 2 * cells, st);
-  r |= gemm3(c, T_, N_, nx, 2 * ny, nx, m.dx_hi, m.dx_lo, nx, 0, m.split_hi, m.split_lo, nx, 0,
-             outc, nx, 0, 1);
+  mf_product<MF_ROW>(st, m.dxt_hi, m.dxt_lo, mid, outc, nx, 2 * ny, nx, nx, nx, 0, 0, 1);
   const int sn = (int)(level % 3), snew = (int)((level + 1) % 3);
   hipLaunchKernelGGL(k_gemm_finalize, dim3(ny), dim3(GEMM_THREADS), 0, st, outc, m.phi[sn],
                      m.psi[sn], m.colsum, m.phi[snew], m.psi[snew], nx, ny);
   pe.mark(11, st);
-  return r;
+  return CCMSAV_OK;
 }
 
 int enqueue_step_level(ccmsav_ctx* c, int64_t level, hipStream_t st,
@@ -753,7 +741,6 @@ int read_err(ccmsav_ctx* c, int* err) {
 }
 
 void free_ctx(ccmsav_ctx* c) {
-  if (c->blas) (void)rocblas_destroy_handle(c->blas);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
@@ -799,24 +786,27 @@ float host_bf16_to_f32(uint16_t h) {
   return f;
 }
 
-// Orthonormal DCT-II matrix of size n (App. C), column-major
-// (element (k, i) = s_k cos(pi k (2i + 1) / (2n)) at k + i n), as bf16 halves.
-int upload_dct_matrix(uint16_t* d_hi, uint16_t* d_lo, int n, hipStream_t st) {
-  std::vector<uint16_t> hi((size_t)n * n), lo((size_t)n * n);
+// Orthonormal DCT-II matrix of size n (App. C), D(k, i) = s_k cos(pi k (2i + 1) / (2n)),
+// and its transpose, row-major, as bf16 hi and lo halves at
+// out + {0, 1, 2, 3} n^2: D hi, D lo, D^T hi, D^T lo.
+int upload_dct_matrix(uint16_t* out, int n, hipStream_t st) {
+  const size_t nn = (size_t)n * n;
+  std::vector<uint16_t> h(4 * nn);
   const double s0 = std::sqrt(1.0 / n), s1 = std::sqrt(2.0 / n);
-  for (int i = 0; i < n; ++i)
-    for (int k = 0; k < n; ++k) {
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < n; ++i) {
       const double v = (k == 0 ? s0 : s1) * std::cos(M_PI * k * (2.0 * i + 1.0) / (2.0 * n));
-      const uint16_t h = host_bf16((float)v);
-      hi[(size_t)k + (size_t)i * n] = h;
-      lo[(size_t)k + (size_t)i * n] = host_bf16((float)(v - (double)host_bf16_to_f32(h)));
+      const uint16_t hi = host_bf16((float)v);
+      const uint16_t lo = host_bf16((float)(v - (double)host_bf16_to_f32(hi)));
+      h[(size_t)k * n + i] = hi;
+      h[nn + (size_t)k * n + i] = lo;
+      h[2 * nn + (size_t)i * n + k] = hi;
+      h[3 * nn + (size_t)i * n + k] = lo;
     }
   const bool ok =
-      hipMemcpyAsync(d_hi, hi.data(), hi.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st) ==
-          hipSuccess &&
-      hipMemcpyAsync(d_lo, lo.data(), lo.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st) ==
-          hipSuccess;
-  // the host tables must outlive the copies, also when one of them failed
+      hipMemcpyAsync(out, h.data(), h.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st) ==
+      hipSuccess;
+  // the host table must outlive the copy, also when it failed
   if (hipStreamSynchronize(st) != hipSuccess || !ok) return CCMSAV_EHIP;
   return CCMSAV_OK;
 }
@@ -1106,17 +1096,17 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
     m.unit_coef = reinterpret_cast<double*>(mb + L.unit);
     m.ds = reinterpret_cast<DevScalars*>(mb + L.ds);
     if (is_gemm(m.p.precision)) {
-      m.split_hi = reinterpret_cast<uint16_t*>(mb + L.split);
-      m.split_lo = m.split_hi + M_NFIELD * cells;
+      const size_t nxx = (size_t)m.p.nx * m.p.nx, nyy = (size_t)m.p.ny * m.p.ny;
       m.dx_hi = reinterpret_cast<uint16_t*>(mb + L.dx);
-      m.dx_lo = m.dx_hi + (size_t)m.p.nx * m.p.nx;
+      m.dx_lo = m.dx_hi + nxx;
+      m.dxt_hi = m.dx_hi + 2 * nxx;
+      m.dxt_lo = m.dx_hi + 3 * nxx;
       m.dy_hi = reinterpret_cast<uint16_t*>(mb + L.dy);
-      m.dy_lo = m.dy_hi + (size_t)m.p.ny * m.p.ny;
-      if (upload_dct_matrix(m.dx_hi, m.dx_lo, m.p.nx, c->stream) != CCMSAV_OK ||
-          upload_dct_matrix(m.dy_hi, m.dy_lo, m.p.ny, c->stream) != CCMSAV_OK)
-        return fail(CCMSAV_EHIP);
-      if (rocblas_create_handle(&c->blas) != rocblas_status_success ||
-          rocblas_set_stream(c->blas, c->stream) != rocblas_status_success)
+      m.dy_lo = m.dy_hi + nyy;
+      m.dyt_hi = m.dy_hi + 2 * nyy;
+      m.dyt_lo = m.dy_hi + 3 * nyy;
+      if (upload_dct_matrix(m.dx_hi, m.p.nx, c->stream) != CCMSAV_OK ||
+          upload_dct_matrix(m.dy_hi, m.p.ny, c->stream) != CCMSAV_OK)
         return fail(CCMSAV_EHIP);
     }
 

@@ -7,9 +7,10 @@
 // x_lo = bf16(x - x_hi), and a product A B is taken as
 // A_hi B_hi + A_hi B_lo + A_lo B_hi (three bf16 GEMMs, relative error about
 // 2^-16 per product). The products only ever see the increment-form residuals
-// of the mixed path, so that error scales with the step's change. The kernels
-// here prepare the operands and do the spectral work between the products:
-// inner products, combination and divide, and the FP64 update of the state.
+// of the mixed path, so that error scales with the step's change. The
+// products themselves are in gemm_mfma.hpp; the kernels here do the spectral
+// work between them: inner products, combination and divide, and the FP64
+// update of the state.
 #pragma once
 #include <stdint.h>
 
@@ -28,19 +29,6 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
 }
 
 constexpr int GEMM_THREADS = 256;
-
-// x = hi + lo + O(2^-16 |x|), both halves bfloat16.
-__global__ void __launch_bounds__(GEMM_THREADS)
-k_split_bf16(const float* __restrict__ x, uint16_t* __restrict__ hi, uint16_t* __restrict__ lo,
-             size_t n) {
-  const size_t stride = (size_t)gridDim.x * GEMM_THREADS;
-  for (size_t i = (size_t)blockIdx.x * GEMM_THREADS + threadIdx.x; i < n; i += stride) {
-    const float v = x[i];
-    const uint16_t h = bf16_rne(v);
-    hi[i] = h;
-    lo[i] = bf16_rne(v - bf16_to_f32(h));
-  }
-}
 
 // The Parseval inner products of App. B Step 4 from the 2D spectra of the
 // eight fields (field-major, [field][ky][kx], kx fastest): one row of P2Sum

@@ -1,0 +1,217 @@
+// Dense products with the orthonormal DCT matrix on the gfx950 matrix cores,
+// for the DCT-as-GEMM variant of the step: bfloat16 operands split in hi/lo
+// halves, three products (hi hi + hi lo + lo hi) accumulated in FP32 by
+// v_mfma_f32_32x32x16_bf16.
+//
+// Every product of the step pairs a constant matrix d (a DCT matrix or its
+// transpose, split once at context creation, row-major with K contiguous)
+// with an FP32 data operand x that is split into bf16 halves while it is
+// staged into LDS, so no separate splitting pass touches HBM:
+//   row mode (transforms along x): C(m, n) = sum_k d[m K + k] x[n ldx + k],
+//     the data rows of all fields stacked along n;
+//   column mode (transforms along y): C(m, n) = sum_k x[k ldx + m] d[n K + k],
+//     one field per batch entry.
+// Both write C(m, n) at c[n ldc + m], so that an output row is contiguous.
+#pragma once
+#include <stdint.h>
+
+#include "gemm_dct.hpp"
+
+namespace ccm {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
+
+enum MfMode { MF_ROW = 0, MF_COL = 1 };
+
+constexpr int MF_THREADS = 256;   // four waves, each owning a quarter of the block tile
+constexpr int MF_BK = 32;         // K per staged slice
+// LDS row of one tile line: 32 bf16 of K plus 8 of padding (80 bytes), so
+// that the 16-byte fragment reads of 16 consecutive lanes (16 lines) fall on
+// 16 disjoint groups of four banks.
+constexpr int MF_ROW16 = 5;       // 16-byte units per LDS line
+
+// Tile edge along m and n: 128, or 64 for the smallest grids.
+__host__ __device__ constexpr int mf_tile(int dim) { return dim >= 128 ? 128 : 64; }
+
+// x = hi + lo + O(2^-16 |x|): bfloat16 halves of eight FP32 values.
+__device__ __forceinline__ void split8(const float (&v)[8], bf16x8_t& hi, bf16x8_t& lo) {
+  u16x8_t h, l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const uint16_t he = bf16_rne(v[e]);
+    h[e] = he;
+    l[e] = bf16_rne(v[e] - bf16_to_f32(he));
+  }
+  hi = __builtin_bit_cast(bf16x8_t, h);
+  lo = __builtin_bit_cast(bf16x8_t, l);
+}
+
+// Block tile (m0, n0) and batch entry z of block b: blocks are spread over
+// the eight XCDs in contiguous ranges (xcd_remap), and within a batch entry
+// the tiles go in groups of 8 x 8, so that the blocks one XCD holds at once
+// share eight m-slices and eight n-slices of the operands in its L2.
+__device__ __forceinline__ void mf_block_tile(int mb_count, int nb_count, int& z, int& mb,
+                                              int& nb) {
+  const int total = gridDim.x;
+  const int b = xcd_remap(blockIdx.x, total);
+  const int per = mb_count * nb_count;
+  z = b / per;
+  const int t = b - z * per;
+  if ((mb_count & 7) == 0 && (nb_count & 7) == 0) {
+    const int g = t >> 6, w = t & 63;
+    const int gm = mb_count >> 3;
+    mb = (g % gm) * 8 + (w & 7);
+    nb = (g / gm) * 8 + (w >> 3);
+  } else {
+    mb = t % mb_count;
+    nb = t / mb_count;
+  }
+}
+
+// C = the product of MODE (above) for an M x N tile grid of BM x BN blocks,
+// batch entries z = 0 .. gridDim.x / (M/BM N/BN) - 1 at strides sx (x) and sc
+// (c); d_hi, d_lo are shared by the batch.
+template <int MODE, int BM, int BN>
+__global__ void __launch_bounds__(MF_THREADS)
+k_gemm_bf16x3(const uint16_t* __restrict__ d_hi, const uint16_t* __restrict__ d_lo,
+              const float* __restrict__ x, float* __restrict__ c, int M, int N, int K,
+              int ldx, int ldc, size_t sx, size_t sc) {
+  constexpr int TM = BM / 64, TN = BN / 64;   // 32 x 32 subtiles per wave along m, n
+  // LDS tiles, hi and lo: lines indexed by m (Lm) and by n (Ln), K contiguous.
+  __shared__ bf16x8_t Lm_hi[BM * MF_ROW16], Lm_lo[BM * MF_ROW16];
+  __shared__ bf16x8_t Ln_hi[BN * MF_ROW16], Ln_lo[BN * MF_ROW16];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  int z, mb, nb;
+  mf_block_tile(M / BM, N / BN, z, mb, nb);
+  const int m0 = mb * BM, n0 = nb * BN;
+  const float* xz = x + (size_t)z * sx;
+  float* cz = c + (size_t)z * sc;
+
+  // Staging: the d tile is (rows R0 .., K slice) with R = m (row mode) or n
+  // (column mode); the x tile is (rows S0 .., K slice) with S the other one.
+  constexpr int RD = MODE == MF_ROW ? BM : BN;   // lines of the d tile
+  constexpr int RX = MODE == MF_ROW ? BN : BM;   // lines of the x tile
+  constexpr int CD = RD * 4 / MF_THREADS;        // 16-byte chunks per thread (d)
+  constexpr int CX = RX * 4 / MF_THREADS;        // 8-value chunks per thread (x)
+  const int d0 = MODE == MF_ROW ? m0 : n0;
+  const int x0 = MODE == MF_ROW ? n0 : m0;
+  bf16x8_t* Ld_hi = MODE == MF_ROW ? Lm_hi : Ln_hi;
+  bf16x8_t* Ld_lo = MODE == MF_ROW ? Lm_lo : Ln_lo;
+  bf16x8_t* Lx_hi = MODE == MF_ROW ? Ln_hi : Lm_hi;
+  bf16x8_t* Lx_lo = MODE == MF_ROW ? Ln_lo : Lm_lo;
+
+  bf16x8_t rd_hi[CD], rd_lo[CD];
+  float rx[CX][8];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < CD; ++i) {
+      const int ch = tid + i * MF_THREADS;
+      const int r = ch >> 2, k8 = ch & 3;
+      const size_t o = (size_t)(d0 + r) * K + k0 + 8 * k8;
+      rd_hi[i] = *reinterpret_cast<const bf16x8_t*>(d_hi + o);
+      rd_lo[i] = *reinterpret_cast<const bf16x8_t*>(d_lo + o);
+    }
+#pragma unroll
+    for (int i = 0; i < CX; ++i) {
+      const int ch = tid + i * MF_THREADS;
+      if constexpr (MODE == MF_ROW) {
+        // line s = n, eight consecutive k of a data row (two 16-byte loads)
+        const int s = ch >> 2, k8 = ch & 3;
+        const f32x4_t* p =
+            reinterpret_cast<const f32x4_t*>(xz + (size_t)(x0 + s) * ldx + k0 + 8 * k8);
+        const f32x4_t a = p[0], b = p[1];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          rx[i][e] = a[e];
+          rx[i][4 + e] = b[e];
+        }
+      } else {
+        // line s = m, eight consecutive k: consecutive lanes read consecutive m
+        const int s = ch % RX, k8 = ch / RX;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) rx[i][e] = xz[(size_t)(k0 + 8 * k8 + e) * ldx + x0 + s];
+      }
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int i = 0; i < CD; ++i) {
+      const int ch = tid + i * MF_THREADS;
+      const int r = ch >> 2, k8 = ch & 3;
+      Ld_hi[r * MF_ROW16 + k8] = rd_hi[i];
+      Ld_lo[r * MF_ROW16 + k8] = rd_lo[i];
+    }
+#pragma unroll
+    for (int i = 0; i < CX; ++i) {
+      const int ch = tid + i * MF_THREADS;
+      const int s = MODE == MF_ROW ? ch >> 2 : ch % RX;
+      const int k8 = MODE == MF_ROW ? ch & 3 : ch / RX;
+      bf16x8_t h, l;
+      split8(rx[i], h, l);
+      Lx_hi[s * MF_ROW16 + k8] = h;
+      Lx_lo[s * MF_ROW16 + k8] = l;
+    }
+  };
+
+  // Wave tile: n range wn .. wn + BN/2, m range wm .. wm + BM/2.
+  const int wm = (wave & 1) * (BM / 2), wn = (wave >> 1) * (BN / 2);
+  f32x16_t acc[TN][TM];
+#pragma unroll
+  for (int a = 0; a < TN; ++a)
+#pragma unroll
+    for (int b = 0; b < TM; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
+
+  fetch(0);
+  for (int k0 = 0; k0 < K; k0 += MF_BK) {
+    __syncthreads();                 // the previous slice's fragments are read
+    stage();
+    __syncthreads();
+    if (k0 + MF_BK < K) fetch(k0 + MF_BK);   // next slice in flight during the products
+#pragma unroll
+    for (int ks = 0; ks < MF_BK / 16; ++ks) {
+      const int kc = ks * 2 + (lane >> 5);  // this lane's 8 k of the 16
+      bf16x8_t an_hi[TN], an_lo[TN], bm_hi[TM], bm_lo[TM];
+#pragma unroll
+      for (int a = 0; a < TN; ++a) {
+        const int line = wn + a * 32 + (lane & 31);
+        an_hi[a] = Ln_hi[line * MF_ROW16 + kc];
+        an_lo[a] = Ln_lo[line * MF_ROW16 + kc];
+      }
+#pragma unroll
+      for (int b = 0; b < TM; ++b) {
+        const int line = wm + b * 32 + (lane & 31);
+        bm_hi[b] = Lm_hi[line * MF_ROW16 + kc];
+        bm_lo[b] = Lm_lo[line * MF_ROW16 + kc];
+      }
+#pragma unroll
+      for (int a = 0; a < TN; ++a)
+#pragma unroll
+        for (int b = 0; b < TM; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an_hi[a], bm_hi[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an_hi[a], bm_lo[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an_lo[a], bm_hi[b], acc[a][b], 0, 0, 0);
+        }
+    }
+  }
+  // Accumulator element v of lane l: MFMA row (n) (v/4) 8 + (l/32) 4 + v%4,
+  // column (m) l % 32; a wave's store covers 32 consecutive m of two rows.
+#pragma unroll
+  for (int a = 0; a < TN; ++a)
+#pragma unroll
+    for (int b = 0; b < TM; ++b) {
+      const int m = m0 + wm + b * 32 + (lane & 31);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int n = n0 + wn + a * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        cz[(size_t)n * ldc + m] = acc[a][b][v];
+      }
+    }
+}
+
+}  // namespace ccm

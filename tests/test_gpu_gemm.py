@@ -3,10 +3,14 @@ accumulation on the matrix cores) against the FP64 path and the oracle.
 
 Each product carries a relative error of about 2^-16 (two bf16 halves per
 operand, the lo x lo term dropped) of the increment-form residuals it acts on,
-150 times the FP32 rounding of the mixed path; over these runs that leaves
-the fields within about 2e-4 of the FP64 path (bound 5e-4). A wrong sign,
-index or transpose anywhere in the products gives O(1) errors. Mass stays
-exact to FP64 rounding and the modified energy keeps decaying.
+150 times the FP32 rounding of the mixed path. Bounds against the FP64 path:
+1e-6 on the perturbed-vesicle grids (N = 512 and 2048; measured 4e-7 and
+3e-7), whose steps change the fields by a small fraction; 1e-4 on circle128,
+whose time step of 1e-4 changes them by up to a few percent per step, so
+that 2^-16 of the increment is 1e-6 of the field per step (measured 3e-5
+after 100 steps). A wrong sign, index or transpose anywhere in the products
+gives O(1) errors. Mass stays exact to FP64 rounding and the modified energy
+keeps decaying.
 """
 import sys
 
@@ -40,9 +44,10 @@ def run(m, precision, steps, every):
     return m0, out
 
 
-@pytest.mark.parametrize("name,n,steps", [("circle128", None, 100), ("vesicle1024", 512, 60),
-                                          ("vesicle2048", None, 100)])
-def test_gemm_variant_tracks_fp64(name, n, steps):
+@pytest.mark.parametrize("name,n,steps,tol", [("circle128", None, 100, 1e-4),
+                                              ("vesicle1024", 512, 60, 1e-6),
+                                              ("vesicle2048", None, 100, 1e-6)])
+def test_gemm_variant_tracks_fp64(name, n, steps, tol):
     m = make_workload(name, n)[0]
     note(f"gemm vs fp64 {name} n={m.params['nx']} {steps} steps")
     m0, ref = run(m, "fp64", steps, steps // 4)
@@ -58,12 +63,15 @@ def test_gemm_variant_tracks_fp64(name, n, steps):
             assert g[4] <= prev + 1e-12 * abs(prev)
         prev = g[4]
     note(f"worst rel L-inf {worst:.3e}, mass drift {drift:.2e}")
-    assert worst <= 5e-4
+    assert worst <= tol
     assert drift <= 5e-11
 
 
-def test_gemm_variant_rejects_ensembles_and_graphs():
+def test_gemm_variant_rejects_ensembles_graphs_and_small_grids():
     m = circle_member(32)
+    with pytest.raises(C.CcmsavError) as e:
+        C.Context(m.params, m.phi0, m.psi0, "gemm")      # tiles need 64 per direction
+    assert e.value.name == "EUNSUPPORTED"
     with pytest.raises(C.CcmsavError) as e:
         C.Context.ensemble([m.params, m.params], [m.phi0] * 2, [m.psi0] * 2, "gemm")
     assert e.value.name == "EUNSUPPORTED"

@@ -10,7 +10,8 @@ against properties that hold at any size:
 The mixed path and the DCT-as-GEMM variant are then held to the FP64 path:
 mixed over the workload's 200 steps within 1e-6 (relative L-inf of phi, psi,
 the SAVs), with its mass drift at most 5e-11 and its modified energy decaying;
-DCT-as-GEMM over 20 steps within 5e-4 (its bf16x3 products). The mixed path's
+DCT-as-GEMM over 20 steps within 1e-6 (its bf16x3 products on the matrix
+cores; measured 4e-7). The mixed path's
 BDF2 step, the last step of the N = 1024, 2048 and 4096 workloads and the
 BDF1 scheme at N = 4096 are held to the same discrete equations.
 
@@ -43,7 +44,7 @@ from paper_2601_10057_amd import ccmsav as C  # noqa: E402
 RES_TOL = 1e-12
 REL_TOL = 1e-6
 MASS_DRIFT_TOL = 5e-11
-GEMM_TOL = 5e-4
+GEMM_TOL = 1e-6
 
 
 def note(msg):
