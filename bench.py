@@ -162,7 +162,9 @@ def _csv_rows(directory: str, suffix: str):
 
 
 def _short(name: str) -> str:
-    """Kernel name without the argument list."""
+    """Kernel name without the return type and the argument list."""
+    if name.startswith("void "):
+        name = name[5:]
     depth = 0
     for i, ch in enumerate(name):
         if ch == "<":
@@ -179,7 +181,7 @@ def digest_trace(directory: str, name: str, command: str):
     rows = _csv_rows(directory, "kernel_stats.csv")
     total = sum(float(r["TotalDurationNs"]) for r in rows)
     lines = [f"# rocprofv3 kernel trace: {name}", "",
-             "Command (run from the repository root on one MI355X):", "", "```", command, "```", "",
+             "Command (on one MI355X; $REPO is the repository root):", "", "```", command, "```", "",
              "| kernel | calls | avg us | min us | max us | share % |",
              "|---|---|---|---|---|---|"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
@@ -246,7 +248,7 @@ def digest_counters(fetch_dir: str, write_dir: str, workload: str, precision: st
     passes = {ps: sum(used[k][0] for k in ks if k in used) for ps, ks in PASSES.items()}
     digest = source_digest()
     md = [f"# HBM traffic per kernel launch: {workload}, {precision}", "",
-          "Two rocprofv3 counter runs, from the repository root on one MI355X:", "", "```",
+          "Two rocprofv3 counter runs on one MI355X ($REPO is the repository root):", "", "```",
           commands, "```", "",
           f"Calibration: each run ends with a plain {probe_mib} MiB device copy. For that copy "
           f"FETCH_SIZE reads {copy_f:.1f} KiB and WRITE_SIZE {copy_w:.1f} KiB of {kib:.0f} KiB moved, "
