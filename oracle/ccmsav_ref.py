@@ -60,32 +60,40 @@ MATRIX_DCT_MAX = 512
 # Discrete operators on the staggered cell-centred grid (App. D)
 # ---------------------------------------------------------------------------
 
-def with_ghosts(u: np.ndarray) -> np.ndarray:
-    """Ghost ring phi_0 = phi_1, phi_{m+1} = phi_m (App. D, boundary conditions)."""
-    return np.pad(u, 1, mode="edge")
+BOUNDARIES = ("neumann", "periodic")
 
 
-def Dx(u, h):
-    """(D_x u)_{i+1/2, j} on all east-west faces i = 0..m, shape (ny, nx+1)."""
-    g = with_ghosts(u)[1:-1, :]
+def with_ghosts(u: np.ndarray, bc: str = "neumann") -> np.ndarray:
+    """Ghost ring of the cell-centred grid: phi_0 = phi_1, phi_{m+1} = phi_m for
+    homogeneous Neumann boundaries (App. D); phi_0 = phi_m, phi_{m+1} = phi_1
+    (wrap-around) for periodic ones, the case App. C pairs with the FFT."""
+    if bc not in BOUNDARIES:
+        raise ValueError(f"boundary condition {bc!r}")
+    return np.pad(u, 1, mode="edge" if bc == "neumann" else "wrap")
+
+
+def Dx(u, h, bc="neumann"):
+    """(D_x u)_{i+1/2, j} on all east-west faces i = 0..m, shape (ny, nx+1)
+    (with periodic boundaries faces 0 and m are the same face)."""
+    g = with_ghosts(u, bc)[1:-1, :]
     return (g[:, 1:] - g[:, :-1]) / h
 
 
-def Dy(u, h):
+def Dy(u, h, bc="neumann"):
     """(D_y u)_{i, j+1/2} on all north-south faces j = 0..n, shape (ny+1, nx)."""
-    g = with_ghosts(u)[:, 1:-1]
+    g = with_ghosts(u, bc)[:, 1:-1]
     return (g[1:, :] - g[:-1, :]) / h
 
 
-def Ax(u):
+def Ax(u, bc="neumann"):
     """(A_x u)_{i+1/2, j} = (u_i + u_{i+1}) / 2 on east-west faces."""
-    g = with_ghosts(u)[1:-1, :]
+    g = with_ghosts(u, bc)[1:-1, :]
     return 0.5 * (g[:, 1:] + g[:, :-1])
 
 
-def Ay(u):
+def Ay(u, bc="neumann"):
     """(A_y u)_{i, j+1/2} = (u_j + u_{j+1}) / 2 on north-south faces."""
-    g = with_ghosts(u)[:, 1:-1]
+    g = with_ghosts(u, bc)[:, 1:-1]
     return 0.5 * (g[1:, :] + g[:-1, :])
 
 
@@ -99,20 +107,20 @@ def dy(g, h):
     return (g[1:, :] - g[:-1, :]) / h
 
 
-def lap(u, h):
-    """Five-point Laplacian Delta_h = d_x D_x + d_y D_y with Neumann ghosts."""
-    return dx(Dx(u, h), h) + dy(Dy(u, h), h)
+def lap(u, h, bc="neumann"):
+    """Five-point Laplacian Delta_h = d_x D_x + d_y D_y with the ghosts of bc."""
+    return dx(Dx(u, h, bc), h) + dy(Dy(u, h, bc), h)
 
 
-def div_mobility_grad(mob_x, mob_y, u, h):
+def div_mobility_grad(mob_x, mob_y, u, h, bc="neumann"):
     """d_x(M_x D_x u) + d_y(M_y D_y u) with face mobilities (Sec. 3.4.1)."""
-    return dx(mob_x * Dx(u, h), h) + dy(mob_y * Dy(u, h), h)
+    return dx(mob_x * Dx(u, h, bc), h) + dy(mob_y * Dy(u, h, bc), h)
 
 
-def grad_sq_cell(u, h):
+def grad_sq_cell(u, h, bc="neumann"):
     """Cell value of |grad u|^2: mean of the squared face gradients (Sec. 3.4.1)."""
-    gx = Dx(u, h) ** 2
-    gy = Dy(u, h) ** 2
+    gx = Dx(u, h, bc) ** 2
+    gy = Dy(u, h, bc) ** 2
     return 0.5 * (gx[:, 1:] + gx[:, :-1]) + 0.5 * (gy[1:, :] + gy[:-1, :])
 
 
@@ -133,20 +141,20 @@ def face_ip(fx, fy, gx, gy, h):
     return float(ew + ns)
 
 
-def grad_norm_sq(u, h):
+def grad_norm_sq(u, h, bc="neumann"):
     """||grad_h u||^2 = [D_x u, D_x u]_ew + [D_y u, D_y u]_ns (App. D)."""
-    gx, gy = Dx(u, h), Dy(u, h)
+    gx, gy = Dx(u, h, bc), Dy(u, h, bc)
     return face_ip(gx, gy, gx, gy, h)
 
 
-def lap_matrix(nx, ny, h):
+def lap_matrix(nx, ny, h, bc="neumann"):
     """Dense matrix of Delta_h, built by applying the stencil to unit vectors."""
     n = nx * ny
     L = np.zeros((n, n))
     e = np.zeros((ny, nx))
     for c in range(n):
         e.flat[c] = 1.0
-        L[:, c] = lap(e, h).ravel()
+        L[:, c] = lap(e, h, bc).ravel()
         e.flat[c] = 0.0
     return L
 
@@ -305,6 +313,21 @@ def spectral_solve_periodic(rhs, spectrum):
     return np.real(np.fft.ifft2(np.fft.fft2(rhs) / spectrum))
 
 
+def lap_eigs(p: "Params"):
+    """Eigenvalues of Delta_h for the boundary conditions of p, on the grid of
+    the transform that diagonalises it (DCT-II for Neumann, DFT for periodic)."""
+    if p.bc == "periodic":
+        return periodic_lap_eigs(p.nx, p.ny, p.h)
+    return neumann_lap_eigs(p.nx, p.ny, p.h)
+
+
+def fast_solve(rhs, spectrum, p: "Params", use_matrix=None):
+    """App. C's fast direct solve with the transform of p's boundary conditions."""
+    if p.bc == "periodic":
+        return spectral_solve_periodic(rhs, spectrum)
+    return spectral_solve(rhs, spectrum, use_matrix)
+
+
 # ---------------------------------------------------------------------------
 # Model pieces (Sec. 2)
 # ---------------------------------------------------------------------------
@@ -331,11 +354,12 @@ class Params:
     theta: float
     lam: float
     beta: float
+    bc: str = "neumann"      # "neumann" (App. D) or "periodic"
 
     @classmethod
     def from_dict(cls, d: Dict) -> "Params":
-        names = cls.__dataclass_fields__.keys()
-        return cls(**{k: d[k] for k in names})
+        names = [k for k in cls.__dataclass_fields__ if k != "bc"]
+        return cls(**{k: d[k] for k in names}, bc=d.get("bc", "neumann"))
 
 
 def p_interp(phi):
@@ -371,7 +395,7 @@ def double_well(phi):
 def f_surf(phi, p: Params):
     """Surface density (3 sqrt2/4)(g/eps + eps/2 |grad phi|^2), cell form."""
     return 0.75 * SQ2 * (double_well(phi) / p.eps
-                         + 0.5 * p.eps * grad_sq_cell(phi, p.h))
+                         + 0.5 * p.eps * grad_sq_cell(phi, p.h, p.bc))
 
 
 def sav_V(phi, p: Params):
@@ -386,7 +410,7 @@ def sav_U(phi, p: Params):
 
 def w_density(phi, p: Params):
     """Integrand of W^2: 6 phi^2 |grad phi|^2 + (phi^3 - phi)^2 / eps^2."""
-    return (6.0 * phi * phi * grad_sq_cell(phi, p.h)
+    return (6.0 * phi * phi * grad_sq_cell(phi, p.h, p.bc)
             + (phi ** 3 - phi) ** 2 / p.eps ** 2)
 
 
@@ -413,7 +437,7 @@ def basis_S(phi, p: Params):
 
 def basis_H(phi, p: Params):
     """H(phi) = (3 sqrt2/4)(phi (phi^2 - 1)/eps - eps Delta_h phi)."""
-    return 0.75 * SQ2 * (phi * (phi * phi - 1.0) / p.eps - p.eps * lap(phi, p.h))
+    return 0.75 * SQ2 * (phi * (phi * phi - 1.0) / p.eps - p.eps * lap(phi, p.h, p.bc))
 
 
 def basis_Q(phi, p: Params):
@@ -422,10 +446,10 @@ def basis_Q(phi, p: Params):
     [phi |grad phi|^2] and [div(phi^2 grad phi)] follow Sec. 3.4.1 with the
     face average of phi^2 taken as (phi_i^2 + phi_{i+1}^2)/2.
     """
-    h = p.h
+    h, bc = p.h, p.bc
     sq = phi * phi
-    term_a = phi * grad_sq_cell(phi, h)
-    term_b = dx(Ax(sq) * Dx(phi, h), h) + dy(Ay(sq) * Dy(phi, h), h)
+    term_a = phi * grad_sq_cell(phi, h, bc)
+    term_b = dx(Ax(sq, bc) * Dx(phi, h, bc), h) + dy(Ay(sq, bc) * Dy(phi, h, bc), h)
     num = 6.0 * (term_a - term_b) + (phi ** 3 - phi) * (3.0 * sq - 1.0) / p.eps ** 2
     return num / sav_W(phi, p)
 
@@ -445,7 +469,7 @@ def basis_P(phi, psi, p: Params):
 
 def face_mobility(phi, p: Params):
     """M_psi evaluated at the face-averaged phi (Sec. 3.4.1)."""
-    return mobility_psi(Ax(phi), p), mobility_psi(Ay(phi), p)
+    return mobility_psi(Ax(phi, p.bc), p), mobility_psi(Ay(phi, p.bc), p)
 
 
 # ---------------------------------------------------------------------------
@@ -529,7 +553,7 @@ def step(st: State, use_matrix: Optional[bool] = None, keep: bool = False) -> Di
     K = basis_K(phis, psis, p)
     P = basis_P(phis, psis, p)
     mx, my = face_mobility(phis, p)
-    LP_src = div_mobility_grad(mx, my, P, h)    # div(M_psi(phi*) grad P*)
+    LP_src = div_mobility_grad(mx, my, P, h, p.bc)    # div(M_psi(phi*) grad P*)
 
     # Bracketed explicit SAV parts: BDF2 carries the 1/3 of the paper's f^n.
     if bdf2:
@@ -550,21 +574,21 @@ def step(st: State, use_matrix: Optional[bool] = None, keep: bool = False) -> Di
         a_psi = psi_n / dt
 
     tt = theta_tilde(p)
-    f = a_phi - p.M_phi * (tt * lap(phis, h)
+    f = a_phi - p.M_phi * (tt * lap(phis, h, p.bc)
                            + p.gamma_surf * 1.5 * SQ2 * sV * S
                            + p.gamma_area * sU * H
                            + p.gamma_bend * 3.0 * SQ2 / (8.0 * p.eps) * sW * Q
                            + sZ * K)
     nu_tilde = sZ * P
-    g = a_psi - p.lam * lap(psis, h) + div_mobility_grad(mx, my, nu_tilde, h)
+    g = a_psi - p.lam * lap(psis, h, p.bc) + div_mobility_grad(mx, my, nu_tilde, h, p.bc)
 
     C1, C2, C3 = chi_coefficients(p, alpha)
-    lam_h = neumann_lap_eigs(p.nx, p.ny, h)
+    lam_h = lap_eigs(p)
     sigma = C1 - C2 * lam_h + C3 * lam_h ** 2
     tau = alpha - p.lam * lam_h
 
-    chi_inv = lambda r: spectral_solve(r, sigma, use_matrix)   # noqa: E731
-    zeta_inv = lambda r: spectral_solve(r, tau, use_matrix)    # noqa: E731
+    chi_inv = lambda r: fast_solve(r, sigma, p, use_matrix)   # noqa: E731
+    zeta_inv = lambda r: fast_solve(r, tau, p, use_matrix)    # noqa: E731
     f_hat = chi_inv(f)
     S_hat, H_hat, Q_hat, K_hat = chi_inv(S), chi_inv(H), chi_inv(Q), chi_inv(K)
     g_hat = zeta_inv(g)
@@ -642,7 +666,7 @@ def step_residuals(phi_n, psi_n, sav_n, phi_new, psi_new, sav_new, p: Params,
     S, H, Q = basis_S(phis, p), basis_H(phis, p), basis_Q(phis, p)
     K, P = basis_K(phis, psis, p), basis_P(phis, psis, p)
     mx, my = face_mobility(phis, p)
-    LP_src = div_mobility_grad(mx, my, P, h)
+    LP_src = div_mobility_grad(mx, my, P, h, p.bc)
     Vn, Un, Wn, Zn = sav_n
     if bdf2:
         Vm, Um, Wm, Zm = sav_m
@@ -656,17 +680,17 @@ def step_residuals(phi_n, psi_n, sav_n, phi_new, psi_new, sav_new, p: Params,
              Zn - ip(K, phi_n, h) - ip(P, psi_n, h)]
         a_phi, a_psi = phi_n / dt, psi_n / dt
     tt = theta_tilde(p)
-    f = a_phi - p.M_phi * (tt * lap(phis, h) + p.gamma_surf * 1.5 * SQ2 * s[0] * S
+    f = a_phi - p.M_phi * (tt * lap(phis, h, p.bc) + p.gamma_surf * 1.5 * SQ2 * s[0] * S
                            + p.gamma_area * s[1] * H
                            + p.gamma_bend * 3.0 * SQ2 / (8.0 * p.eps) * s[2] * Q + s[3] * K)
-    g = a_psi - p.lam * lap(psis, h) + div_mobility_grad(mx, my, s[3] * P, h)
+    g = a_psi - p.lam * lap(psis, h, p.bc) + div_mobility_grad(mx, my, s[3] * P, h, p.bc)
     x = [sav_new[i] - s[i] for i in range(4)]
     cgs, cga, cgb, cgo = sav_weights(p)
     C1, C2, C3 = chi_coefficients(p, alpha)
-    L_phi = lap(phi_new, h)
-    r_phi = (C1 * phi_new - C2 * L_phi + C3 * lap(L_phi, h)
+    L_phi = lap(phi_new, h, p.bc)
+    r_phi = (C1 * phi_new - C2 * L_phi + C3 * lap(L_phi, h, p.bc)
              - (f - cgs * x[0] * S - cga * x[1] * H - cgb * x[2] * Q - cgo * x[3] * K))
-    r_psi = alpha * psi_new - p.lam * lap(psi_new, h) - (g + x[3] * LP_src)
+    r_psi = alpha * psi_new - p.lam * lap(psi_new, h, p.bc) - (g + x[3] * LP_src)
     lmax = 8.0 / (h * h)                                # spectral radius of -Delta_h
     sig_max = abs(C1) + abs(C2) * lmax + abs(C3) * lmax * lmax
     tau_max = alpha + abs(p.lam) * lmax
@@ -676,9 +700,9 @@ def step_residuals(phi_n, psi_n, sav_n, phi_new, psi_new, sav_new, p: Params,
         sav = max(sav, abs(xi - ip(F, phi_new, h)) / ip(np.abs(F), aphi, h))
     sav = max(sav, abs(x[3] - ip(K, phi_new, h) - ip(P, psi_new, h))
               / (ip(np.abs(K), aphi, h) + ip(np.abs(P), apsi, h)))
-    lam_h = neumann_lap_eigs(p.nx, p.ny, h)
-    e_phi = spectral_solve(r_phi, C1 - C2 * lam_h + C3 * lam_h ** 2)
-    e_psi = spectral_solve(r_psi, alpha - p.lam * lam_h)
+    lam_h = lap_eigs(p)
+    e_phi = fast_solve(r_phi, C1 - C2 * lam_h + C3 * lam_h ** 2, p)
+    e_psi = fast_solve(r_psi, alpha - p.lam * lam_h, p)
     return dict(chi=float(np.max(np.abs(r_phi)) / (sig_max * np.max(aphi))),
                 zeta=float(np.max(np.abs(r_psi)) / (tau_max * np.max(apsi))),
                 sav=float(sav),
@@ -704,7 +728,7 @@ def physical_energy(phi, psi, p: Params) -> Dict:
     scheme (cell |grad phi|^2, five-point Laplacian, h^2 sums); the arc
     length is int f_surf, the quantity F^area holds at A."""
     L = integral(f_surf(phi, p), p.h)
-    omega = (phi ** 3 - phi) / p.eps - p.eps * lap(phi, p.h)
+    omega = (phi ** 3 - phi) / p.eps - p.eps * lap(phi, p.h, p.bc)
     bend = p.gamma_bend * integral(3.0 * SQ2 / (16.0 * p.eps) * omega ** 2, p.h)
     surf = p.gamma_surf * L
     area = 0.5 * p.gamma_area * (L - p.A) ** 2
@@ -753,8 +777,8 @@ def d_faces(psi_new, psis, phis, p: Params):
     """d^{n+1} = lambda D(psi^{n+1} - psi*) / sqrt(M_psi(A phi*)) on faces."""
     mx, my = face_mobility(phis, p)
     dpsi = psi_new - psis
-    return (p.lam * Dx(dpsi, p.h) / np.sqrt(mx),
-            p.lam * Dy(dpsi, p.h) / np.sqrt(my))
+    return (p.lam * Dx(dpsi, p.h, p.bc) / np.sqrt(mx),
+            p.lam * Dy(dpsi, p.h, p.bc) / np.sqrt(my))
 
 
 def d_norm_sq(psi_new, psis, phis, p: Params):
@@ -773,12 +797,12 @@ def modified_energy(phi1, phi0, sav1, sav0, d_acc, p: Params) -> Dict:
     V1, U1, W1, Z1 = sav1
     V0, U0, W0, Z0 = sav0
     tt = theta_tilde(p)
-    l1, l0 = lap(phi1, h), lap(phi0, h)
+    l1, l0 = lap(phi1, h, p.bc), lap(phi0, h, p.bc)
     bend = 0.5 * p.gamma_bend * 3.0 * SQ2 * p.eps / 8.0 * (
         ip(l1, l1, h) + ip(2.0 * l1 - l0, 2.0 * l1 - l0, h))
-    g1 = grad_norm_sq(phi1, h)
-    g2 = grad_norm_sq(2.0 * phi1 - phi0, h)
-    gd = grad_norm_sq(phi1 - phi0, h)
+    g1 = grad_norm_sq(phi1, h, p.bc)
+    g2 = grad_norm_sq(2.0 * phi1 - phi0, h, p.bc)
+    gd = grad_norm_sq(phi1 - phi0, h, p.bc)
     surf = 0.5 * (p.gamma_surf * 3.0 * SQ2 * p.eps / 4.0 + p.theta) * (g1 + g2)
     stab = -0.5 * tt * (g1 + g2 - 2.0 * gd)
     lin = 0.5 * p.gamma_surf * 3.0 * SQ2 * p.beta / (4.0 * p.eps) * (
@@ -812,8 +836,8 @@ def dissipation_terms(phi2, phi1, phi0, sav2, sav1, sav0, psi2, psis, phis, p: P
     h = p.h
     tt = theta_tilde(p)
     sec = phi2 - 2.0 * phi1 + phi0
-    lsec = lap(sec, h)
-    gsec = grad_norm_sq(sec, h)
+    lsec = lap(sec, h, p.bc)
+    gsec = grad_norm_sq(sec, h, p.bc)
     Kn = (0.5 * p.gamma_bend * 3.0 * SQ2 * p.eps / 8.0 * ip(lsec, lsec, h)
           + 0.5 * (p.gamma_surf * 3.0 * SQ2 * p.eps / 4.0 + p.theta) * gsec
           + 1.5 * tt * gsec
@@ -828,8 +852,8 @@ def dissipation_terms(phi2, phi1, phi0, sav2, sav1, sav0, psi2, psis, phis, p: P
     P = basis_P(phis, psis, p)
     nu = sav2[3] * P
     mx, my = face_mobility(phis, p)
-    cx = np.sqrt(mx) * Dx(nu, h)
-    cy = np.sqrt(my) * Dy(nu, h)
+    cx = np.sqrt(mx) * Dx(nu, h, p.bc)
+    cy = np.sqrt(my) * Dy(nu, h, p.bc)
     dxf, dyf = d_faces(psi2, psis, phis, p)
     ex, ey = cx + 0.5 * dxf, cy + 0.5 * dyf
     cd_sq = face_ip(ex, ey, ex, ey, h)

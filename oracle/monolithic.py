@@ -22,7 +22,7 @@ def monolithic_step(st: R.State):
     p = st.p
     h, dt = p.h, p.dt
     nc = p.nx * p.ny
-    L = R.lap_matrix(p.nx, p.ny, h)
+    L = R.lap_matrix(p.nx, p.ny, h, p.bc)
     I = np.eye(nc)
     bdf2 = st.phi_prev is not None and not st.bdf1
     phi_n, psi_n = st.phi.ravel(), st.psi.ravel()
@@ -51,7 +51,7 @@ def monolithic_step(st: R.State):
     K = R.basis_K(phis2, psis2, p).ravel()
     P = R.basis_P(phis2, psis2, p).ravel()
     mx, my = R.face_mobility(phis2, p)
-    divMgradP = R.div_mobility_grad(mx, my, P.reshape(p.ny, p.nx), h).ravel()
+    divMgradP = R.div_mobility_grad(mx, my, P.reshape(p.ny, p.nx), h, p.bc).ravel()
 
     sq = 3.0 * np.sqrt(2.0)
     nt = 2 * nc + 4
