@@ -30,7 +30,14 @@ written, in its order and notation, with numpy for array arithmetic:
 * homogeneous Dirichlet boundaries for the fast solver (the DST that App. C
   names for them): Laplacian with odd ghosts, DST-II matrix, eigenvalues;
   periodic boundaries (the FFT that App. C names): wrap-around Laplacian,
-  eigenvalues, numpy's FFT.
+  eigenvalues, numpy's FFT; the whole time step with periodic boundaries
+  (every operator with wrap-around ghosts, FFT solves);
+* the classical MSAV scheme of the App. B remarks, the comparison system of
+  Sec. 4: the Cahn-Hilliard stabilisation inside the chemical potential, so
+  that zeta = alpha - lambda div(M_psi(phi*) grad) has variable coefficients;
+  solved directly (sparse LU: the definition) or by the DCT-preconditioned
+  conjugate gradient iteration of Sec. 4 (preconditioner alpha - lambda M_bar
+  Delta_h with the spatial mean mobility M_bar, solved by App. C's DCT).
 
 Readings where the paper is silent or ambiguous:
 face mobility is M_psi of the face-averaged phi*; the face average of phi^2
@@ -490,11 +497,19 @@ class State:
     d_acc: float = 0.0           # sum_{j>=2} (dt/2) ||d^j||^2
     history: List[Dict] = field(default_factory=list)
     bdf1: bool = False           # every step with the BDF1 scheme
+    scheme: str = "cc"           # "cc", or "classical" (App. B remarks)
+    ch_solver: str = "direct"    # classical zeta solves: "direct" or "pcg"
+    pcg_tol: float = 1e-12       # relative residual at which PCG stops
+    pcg_maxit: int = 200
 
 
-def initial_state(phi0, psi0, params: Dict, bdf1: bool = False) -> State:
+def initial_state(phi0, psi0, params: Dict, bdf1: bool = False, scheme: str = "cc",
+                  ch_solver: str = "direct", pcg_tol: float = 1e-12,
+                  pcg_maxit: int = 200) -> State:
     """Initial fields and SAVs (eq. msav_ic); A defaults to int f_surf(phi0).
-    With ``bdf1`` every step uses the CC-MSAV-BDF1 scheme (App. B remark)."""
+    With ``bdf1`` every step uses the CC-MSAV-BDF1 scheme (App. B remark).
+    ``scheme="classical"`` takes the classical MSAV scheme instead (App. B
+    remarks), its variable-coefficient zeta solved by ``ch_solver``."""
     p = Params.from_dict(params)
     phi0 = np.array(phi0, dtype=np.float64)
     psi0 = np.array(psi0, dtype=np.float64)
@@ -502,7 +517,12 @@ def initial_state(phi0, psi0, params: Dict, bdf1: bool = False) -> State:
         p.A = integral(f_surf(phi0, p), p.h)
     sav = np.array([sav_V(phi0, p), sav_U(phi0, p), sav_W(phi0, p),
                     sav_Z(phi0, psi0, p)])
-    return State(p, phi0, psi0, None, None, sav, None, bdf1=bdf1)
+    if scheme not in ("cc", "classical") or ch_solver not in ("direct", "pcg"):
+        raise ValueError(f"scheme {scheme!r}, solver {ch_solver!r}")
+    if scheme == "classical" and p.bc != "neumann":
+        raise ValueError("the classical scheme is taken with Neumann boundaries")
+    return State(p, phi0, psi0, None, None, sav, None, bdf1=bdf1, scheme=scheme,
+                 ch_solver=ch_solver, pcg_tol=pcg_tol, pcg_maxit=pcg_maxit)
 
 
 def chi_coefficients(p: Params, alpha: float):
@@ -524,6 +544,88 @@ def sav_weights(p: Params):
             p.M_phi * p.gamma_area,
             p.M_phi * p.gamma_bend * 3.0 * SQ2 / (8.0 * p.eps),
             p.M_phi)
+
+
+# ---------------------------------------------------------------------------
+# The classical MSAV scheme's Cahn-Hilliard operator (App. B remarks, Sec. 4)
+# ---------------------------------------------------------------------------
+
+def div_mobility_grad_matrix(mx, my, h):
+    """Sparse matrix of u -> div(M grad u) = d_x(M_x D_x u) + d_y(M_y D_y u)
+    with Neumann ghosts (the wall faces carry no flux), for face mobilities
+    mx (ny, nx+1) and my (ny+1, nx)."""
+    import scipy.sparse as sp
+    ny, nx = mx.shape[0], my.shape[1]
+    ie = mx[:, 1:].copy()            # east face of cell (i, j)
+    iw = mx[:, :-1].copy()           # west face
+    jn = my[1:, :].copy()            # north face
+    js = my[:-1, :].copy()           # south face
+    ie[:, -1] = 0.0
+    iw[:, 0] = 0.0
+    jn[-1, :] = 0.0
+    js[0, :] = 0.0
+    diag = -(ie + iw + jn + js).ravel()
+    n = nx * ny
+    A = sp.diags([diag, ie.ravel()[:-1], iw.ravel()[1:], jn.ravel()[:-nx], js.ravel()[nx:]],
+                 [0, 1, -1, nx, -nx], shape=(n, n), format="csr")
+    return A / (h * h)
+
+
+def pcg(apply_A, b, apply_Pinv, tol, maxit, h):
+    """Preconditioned conjugate gradients (Hestenes-Stiefel form) from x = 0
+    for a symmetric positive definite A, stopping when the discrete L2 norm of
+    the residual is at most tol times that of b. Returns (x, iterations)."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    bnorm = math.sqrt(ip(b, b, h))
+    if bnorm == 0.0:
+        return x, 0
+    z = apply_Pinv(r)
+    p = z.copy()
+    rz = ip(r, z, h)
+    for it in range(1, maxit + 1):
+        q = apply_A(p)
+        a = rz / ip(p, q, h)
+        x = x + a * p
+        r = r - a * q
+        if math.sqrt(ip(r, r, h)) <= tol * bnorm:
+            return x, it
+        z = apply_Pinv(r)
+        rz_new = ip(r, z, h)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, maxit
+
+
+def classical_zeta_solver(st: "State", mx, my, alpha: float, phis):
+    """The classical scheme's zeta^{-1} for this step: zeta = alpha -
+    lambda div(M grad) with the face mobilities of phi*. Direct: sparse LU
+    (the definition). PCG (Sec. 4): the preconditioner alpha - lambda M_bar
+    Delta_h, M_bar the spatial mean of M_psi(phi*) over the cells, solved by
+    App. C's DCT; afterwards the mean of the iterate is set to the exact
+    mean(b) / alpha (summing zeta x = b over the cells gives alpha sum x =
+    sum b, since the fluxes cancel), so that mass is conserved to rounding
+    whatever the residual. Returns (solve, iteration counts)."""
+    p = st.p
+    h = p.h
+    n = p.nx * p.ny
+    iters = []
+    if st.ch_solver == "direct":
+        import scipy.sparse as sp
+        from scipy.sparse.linalg import splu
+        A = sp.identity(n, format="csc") * alpha - p.lam * div_mobility_grad_matrix(mx, my, h).tocsc()
+        lu = splu(A.tocsc())
+        return (lambda r: lu.solve(r.ravel()).reshape(p.ny, p.nx)), iters
+    m_bar = float(np.mean(mobility_psi(phis, p)))
+    spectrum = alpha - p.lam * m_bar * neumann_lap_eigs(p.nx, p.ny, h)
+    apply_A = lambda u: alpha * u - p.lam * div_mobility_grad(mx, my, u, h)   # noqa: E731
+    apply_P = lambda r: spectral_solve(r, spectrum)                           # noqa: E731
+
+    def solve(b):
+        x, it = pcg(apply_A, b, apply_P, st.pcg_tol, st.pcg_maxit, h)
+        iters.append(it)
+        return x + (np.sum(b) / alpha - np.sum(x)) / n
+    return solve, iters
 
 
 def step(st: State, use_matrix: Optional[bool] = None, keep: bool = False) -> Dict:
@@ -580,7 +682,13 @@ def step(st: State, use_matrix: Optional[bool] = None, keep: bool = False) -> Di
                            + p.gamma_bend * 3.0 * SQ2 / (8.0 * p.eps) * sW * Q
                            + sZ * K)
     nu_tilde = sZ * P
-    g = a_psi - p.lam * lap(psis, h, p.bc) + div_mobility_grad(mx, my, nu_tilde, h, p.bc)
+    classical = st.scheme == "classical"
+    if classical:
+        # the stabilisation inside the chemical potential (App. B remarks):
+        # g = b^n + div(M grad(-lambda psi* + s_Z P))
+        g = a_psi + div_mobility_grad(mx, my, -p.lam * psis + nu_tilde, h, p.bc)
+    else:
+        g = a_psi - p.lam * lap(psis, h, p.bc) + div_mobility_grad(mx, my, nu_tilde, h, p.bc)
 
     C1, C2, C3 = chi_coefficients(p, alpha)
     lam_h = lap_eigs(p)
@@ -588,7 +696,11 @@ def step(st: State, use_matrix: Optional[bool] = None, keep: bool = False) -> Di
     tau = alpha - p.lam * lam_h
 
     chi_inv = lambda r: fast_solve(r, sigma, p, use_matrix)   # noqa: E731
-    zeta_inv = lambda r: fast_solve(r, tau, p, use_matrix)    # noqa: E731
+    pcg_iters = []
+    if classical:
+        zeta_inv, pcg_iters = classical_zeta_solver(st, mx, my, alpha, phis)
+    else:
+        zeta_inv = lambda r: fast_solve(r, tau, p, use_matrix)    # noqa: E731
     f_hat = chi_inv(f)
     S_hat, H_hat, Q_hat, K_hat = chi_inv(S), chi_inv(H), chi_inv(Q), chi_inv(K)
     g_hat = zeta_inv(g)
@@ -618,12 +730,13 @@ def step(st: State, use_matrix: Optional[bool] = None, keep: bool = False) -> Di
     sav_new = np.array([B + sV, C + sU, D + sW, E + G + sZ])
 
     info = dict(bdf2=bdf2, M=M, b=b, x=x, s=np.array([sV, sU, sW, sZ]),
-                norms=np.array([sav_V(phis, p), sav_W(phis, p), sav_Z(phis, psis, p)]))
+                norms=np.array([sav_V(phis, p), sav_W(phis, p), sav_Z(phis, psis, p)]),
+                pcg_iters=list(pcg_iters))
     if keep:
         info.update(S=S, H=H, Q=Q, K=K, P=P, LP=LP_src, f=f, g=g,
                     phis=phis, psis=psis, sigma=sigma, tau=tau)
 
-    if bdf2:
+    if bdf2 and not classical:
         st.d_acc += 0.5 * dt * d_norm_sq(psi_new, psis, phis, p)
     st.phi_prev, st.psi_prev, st.sav_prev = phi_n, psi_n, st.sav
     st.phi, st.psi, st.sav = phi_new, psi_new, sav_new
@@ -823,6 +936,8 @@ def energy(st: State) -> Dict:
         raise ValueError("energy needs two time levels")
     if st.bdf1:
         raise ValueError("E^{n,n-1}_mod is the energy of the BDF2 scheme")
+    if st.scheme != "cc":
+        raise ValueError("E^{n,n-1}_mod with the lambda-dissipation sum is the CC-MSAV energy")
     return modified_energy(st.phi, st.phi_prev, st.sav, st.sav_prev, st.d_acc, st.p)
 
 

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see ``ccmsav_ref``).
 
 Eqs. (AC_BDF2)-(Z_BDF2) of Sec. 3.2 (or their BDF1 counterparts, App. B
-remark) form one linear system in the 2 N^2 + 4 unknowns
+remark, or the classical MSAV scheme's, App. B remarks) form one linear system in the 2 N^2 + 4 unknowns
 (phi^{n+1}, psi^{n+1}, V^{n+1}, U^{n+1}, W^{n+1}, Z^{n+1}) once mu^{n+1} and
 nu^{n+1} are substituted. This module assembles that system densely, with
 Delta_h as an explicit matrix, and solves it with LU. It shares the basis
@@ -70,10 +70,15 @@ def monolithic_step(st: R.State):
     A[:nc, iZ] = p.M_phi * K
     b[:nc] = rhs_phi - p.M_phi * (p.theta + p.gamma_bend * sq / (4.0 * p.eps)) * (L @ phis)
 
-    # Cahn-Hilliard: k_new psi - lambda L psi - Z div(M grad P*) = explicit - lambda L psi*
-    A[nc:2 * nc, nc:2 * nc] = k_new * I - p.lam * L
+    # Cahn-Hilliard: k_new psi - lambda L psi - Z div(M grad P*) = explicit - lambda L psi*;
+    # in the classical scheme (App. B remarks) L is div(M_psi(phi*) grad) in both places
+    if st.scheme == "classical":
+        L_ch = R.div_mobility_grad_matrix(mx, my, h).toarray()
+    else:
+        L_ch = L
+    A[nc:2 * nc, nc:2 * nc] = k_new * I - p.lam * L_ch
     A[nc:2 * nc, iZ] = -divMgradP
-    b[nc:2 * nc] = rhs_psi - p.lam * (L @ psis)
+    b[nc:2 * nc] = rhs_psi - p.lam * (L_ch @ psis)
 
     # SAV equations
     for row, F, old in ((iV, S, Vn), (iU, H, Un), (iW, Q, Wn)):
