@@ -84,7 +84,7 @@ typedef enum {
  *  lam          Cahn-Hilliard stabilisation lambda >= 0               (Sec. 3.2)
  *  beta         linear SAV splitting constant                         (Sec. 2.2)
  *  precision    a ccmsav_precision value
- *  flags        0 or CCMSAV_FLAG_GRAPH and/or CCMSAV_FLAG_BDF1
+ *  flags        0 or CCMSAV_FLAG_GRAPH, CCMSAV_FLAG_BDF1, CCMSAV_FLAG_PERIODIC
  */
 typedef struct {
   int32_t nx, ny;
@@ -107,6 +107,19 @@ typedef struct {
  * ccmsav_energy then returns EUNSUPPORTED: E^{n,n-1}_mod is the energy of
  * the BDF2 scheme. */
 #define CCMSAV_FLAG_BDF1 2
+
+/* flags: periodic boundaries instead of homogeneous Neumann ones, the case
+ * App. C pairs with the FFT. Every discrete operator of App. D takes
+ * wrap-around ghosts (the neighbour across a boundary is the cell on the
+ * other side of the grid, and the faces across the wrap are faces of the
+ * grid), in the step, the initial SAVs and the energy, mass and physical
+ * energy queries. Each step is Algorithm 1 of App. B: the seven elliptic
+ * solves by the periodic fast solver (the FFT of ccmsav_elliptic_solve_bc
+ * with CCMSAV_BC_PERIODIC), the inner products of the 5x5 system in physical
+ * space. CCMSAV_FP64 only, single-member contexts without CCMSAV_FLAG_GRAPH,
+ * grids up to 4096 per direction (else EUNSUPPORTED). ccmsav_elliptic_solve
+ * keeps solving with Neumann boundaries. */
+#define CCMSAV_FLAG_PERIODIC 4
 
 /* Device workspace bytes a context needs for these parameters (0 if the
  * parameters are invalid or unsupported). */

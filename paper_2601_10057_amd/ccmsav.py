@@ -26,6 +26,7 @@ STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDOMAIN",
 
 FLAG_GRAPH = 1
 FLAG_BDF1 = 2
+FLAG_PERIODIC = 4
 BC_NEUMANN, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2
 
 EXPORTED = (
@@ -188,14 +189,15 @@ class Context:
     ``Context(params, phi0, psi0)`` holds one member; ``Context.ensemble``
     builds a context of several (each with its own parameters and grid).
     Member-indexed queries take ``member`` (default 0). ``bdf1=True`` takes
-    every step with the first-order CC-MSAV-BDF1 scheme.
+    every step with the first-order CC-MSAV-BDF1 scheme; ``periodic=True``
+    takes periodic boundaries (FP64, one member).
     """
 
     def __init__(self, params, phi0, psi0, precision="fp64", workspace=None,
                  stream=None, torch_workspace: bool = True, graph: bool = False,
-                 bdf1: bool = False):
+                 bdf1: bool = False, periodic: bool = False):
         self._init([params], [phi0], [psi0], precision, workspace, stream, torch_workspace, graph,
-                   bdf1)
+                   bdf1, periodic)
 
     @classmethod
     def ensemble(cls, params_list, phi0_list, psi0_list, precision="fp64", workspace=None,
@@ -207,14 +209,15 @@ class Context:
         return self
 
     def _init(self, params_list, phi0_list, psi0_list, precision, workspace, stream,
-              torch_workspace, graph, bdf1=False):
+              torch_workspace, graph, bdf1=False, periodic=False):
         lib = load()
         self._h = None
         n = len(params_list)
         if n == 0 or len(phi0_list) != n or len(psi0_list) != n:
             raise ValueError("one parameter set and two initial fields per member")
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
-        flags = (FLAG_GRAPH if graph else 0) | (FLAG_BDF1 if bdf1 else 0)
+        flags = ((FLAG_GRAPH if graph else 0) | (FLAG_BDF1 if bdf1 else 0)
+                 | (FLAG_PERIODIC if periodic else 0))
         self.params_list = [dict(p) for p in params_list]
         self.params = self.params_list[0]
         parr = (Params * n)(*[Params.from_dict(p, self.precision, flags) for p in params_list])

@@ -125,13 +125,18 @@ size_t gemm_gram_blocks(const ccmsav_params* p) {
   const size_t per_block = (size_t)GEMM_THREADS * kGramPerThread;
   return (cells + per_block - 1) / per_block;
 }
+bool is_periodic(const ccmsav_params* p) { return (p->flags & CCMSAV_FLAG_PERIODIC) != 0; }
+// Rows of inner-product partials: one per strip (spectral path), per block of
+// cells (DCT-as-GEMM) or per grid row (periodic step, physical space).
 size_t p2_rows(const ccmsav_params* p) {
+  if (is_periodic(p)) return (size_t)p->ny;
   return is_gemm(p->precision) ? gemm_gram_blocks(p) : (size_t)(p->nx / 2);
 }
 
 struct Layout {
   size_t state, rm, mid, outc, part1, part2, parte, lamx, lamy, colsum, unit, ds;
   size_t dx, dy;   // GEMM variant: DCT matrix and its transpose per direction, bf16 hi and lo
+  size_t psol;     // periodic step: chi^{-1} of S~, H, Q~, K~ (4 FP64 fields)
   size_t total;
 };
 
@@ -160,6 +165,9 @@ Layout layout(const ccmsav_params* p) {
     L.dx = off;    off = align_up(off + 4 * (size_t)p->nx * p->nx * sizeof(uint16_t));
     L.dy = off;    off = align_up(off + 4 * (size_t)p->ny * p->ny * sizeof(uint16_t));
   }
+  if (is_periodic(p)) {
+    L.psol = off;  off = align_up(off + 4 * cells * sizeof(double));
+  }
   L.total = off;
   return L;
 }
@@ -169,7 +177,8 @@ bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 
 int check_params(const ccmsav_params* p) {
   if (!p) return CCMSAV_EINVAL;
-  if ((p->flags & ~(CCMSAV_FLAG_GRAPH | CCMSAV_FLAG_BDF1)) != 0) return CCMSAV_EINVAL;
+  if ((p->flags & ~(CCMSAV_FLAG_GRAPH | CCMSAV_FLAG_BDF1 | CCMSAV_FLAG_PERIODIC)) != 0)
+    return CCMSAV_EINVAL;
   if (p->precision != CCMSAV_FP64 && p->precision != CCMSAV_MIXED &&
       p->precision != CCMSAV_MIXED_GEMM_BF16X3)
     return CCMSAV_EUNSUPPORTED;
@@ -179,6 +188,10 @@ int check_params(const ccmsav_params* p) {
   if (lx < kMinLog || lx > kMaxLog || ly < kMinLog || ly > kMaxLog) return CCMSAV_EUNSUPPORTED;
   // the matrix-core products take tiles of at least 64 along each direction
   if (is_gemm(p->precision) && (p->nx < 64 || p->ny < 64)) return CCMSAV_EUNSUPPORTED;
+  // the periodic step: FP64, the FFT solver's grids (up to 4096), no graph
+  if (is_periodic(p) && (p->precision != CCMSAV_FP64 || lx > 12 || ly > 12 ||
+                         (p->flags & CCMSAV_FLAG_GRAPH)))
+    return CCMSAV_EUNSUPPORTED;
   if (!finite_pos(p->h) || !finite_pos(p->dt) || !finite_pos(p->eps) || !finite_pos(p->M_phi))
     return CCMSAV_EINVAL;
   if (!std::isfinite(p->M0) || p->M0 < 0.0 || p->M0 >= 1.0) return CCMSAV_EINVAL;
@@ -201,7 +214,7 @@ int check_batch(int32_t nmemb, const ccmsav_params* p) {
     if (r != CCMSAV_OK) return r;
     if (p[m].precision != p[0].precision || p[m].flags != p[0].flags) return CCMSAV_EINVAL;
   }
-  if (nmemb > 1 && is_gemm(p[0].precision)) return CCMSAV_EUNSUPPORTED;
+  if (nmemb > 1 && (is_gemm(p[0].precision) || is_periodic(&p[0]))) return CCMSAV_EUNSUPPORTED;
   return CCMSAV_OK;
 }
 
@@ -273,6 +286,7 @@ StepConst make_const(const ccmsav_params& p, bool bdf2) {
   k.cgo = p.M_phi;
   k.C1b = k.C1 - k.alpha;
   k.half_dt = 0.5 * p.dt;
+  k.periodic = is_periodic(&p) ? 1 : 0;
   return k;
 }
 
@@ -299,6 +313,7 @@ DiagConst make_diag(const ccmsav_params& p) {
   d.lam = p.lam;
   d.half_dt = 0.5 * p.dt;
   d.A = p.A;
+  d.periodic = is_periodic(&p) ? 1 : 0;
   return d;
 }
 
@@ -344,6 +359,8 @@ struct Member {
   uint16_t* dy_lo;
   uint16_t* dyt_hi;
   uint16_t* dyt_lo;
+  // periodic step: chi^{-1} of S~, H, Q~, K~
+  double* psol;
 };
 
 // Members with one grid shape; d_idx lists their indices in device memory.
@@ -364,6 +381,7 @@ struct ccmsav_ctx {
   int precision = CCMSAV_FP64;
   bool graph = false;
   bool bdf1 = false;       // every step with the BDF1 scheme (CCMSAV_FLAG_BDF1)
+  bool periodic = false;   // periodic boundaries (CCMSAV_FLAG_PERIODIC)
   hipStream_t stream = nullptr;
   bool owns_ws = false;
   void* ws = nullptr;
@@ -630,9 +648,62 @@ int enqueue_step_gemm(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEvents 
   return CCMSAV_OK;
 }
 
+int periodic_solve_pc(const Member& m, int precision, hipStream_t st, const double* rhs,
+                      double* out_chi, double* out_zeta, const PerConst& pc);
+
+// One step of the single member with periodic boundaries (FP64): the stencil
+// pass with wrap-around ghosts, the seven elliptic solves of Algorithm 1 by
+// the FFT solver (chi^{-1} f_lin, zeta^{-1} g_lin and zeta^{-1} L~ in place,
+// chi^{-1} of S~, H, Q~, K~ into psol), the inner products of App. B Step 4
+// in physical space, the 5x5 solve, and the combination into level n+1.
+int enqueue_step_periodic(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEvents pe) {
+  const Member& m = c->mem[0];
+  const SizeClass& k = c->cls[0];
+  const int t = table_of_level(level);
+  const MemberArgs* tab = c->d_args + (size_t)t * c->mem.size();
+  const StepConst& sc = c->h_args[(size_t)t * c->mem.size()].k;
+  const int nx = m.p.nx, ny = m.p.ny;
+  const size_t cells = (size_t)nx * ny;
+  double* rm = static_cast<double*>(m.rm);
+  auto field = [&](int f) { return rm + (size_t)f * cells; };
+  const PerConst pc{sc.C1, sc.C2, sc.C3, sc.alpha, sc.lam, m.p.h};
+  pe.mark(0, st);
+  hipLaunchKernelGGL(k_stencil<double>, dim3(stencil_grid(c, true, k.sh.blocks)),
+                     dim3(STENCIL_THREADS), 0, st, tab, k.d_idx, k.sh.blocks, k.sh.blocks);
+  pe.mark(1, st);
+  pe.mark(2, st);
+  int r = periodic_solve_pc(m, c->precision, st, field(M_F), field(M_F), nullptr, pc);
+  const int chi_src[4] = {M_S, M_H, M_Q, M_K};
+  for (int i = 0; i < 4 && r == CCMSAV_OK; ++i)
+    r = periodic_solve_pc(m, c->precision, st, field(chi_src[i]), m.psol + (size_t)i * cells,
+                          nullptr, pc);
+  if (r == CCMSAV_OK)
+    r = periodic_solve_pc(m, c->precision, st, field(M_G), nullptr, field(M_G), pc);
+  if (r == CCMSAV_OK)
+    r = periodic_solve_pc(m, c->precision, st, field(M_L), nullptr, field(M_L), pc);
+  if (r != CCMSAV_OK) return r;
+  pe.mark(3, st);
+  pe.mark(4, st);
+  hipLaunchKernelGGL(k_per_gram, dim3(ny), dim3(PER_THREADS), 0, st, rm, m.psol, m.part2, nx, ny);
+  pe.mark(5, st);
+  pe.mark(6, st);
+  hipLaunchKernelGGL(k_solve, dim3(1), dim3(SOLVE_THREADS), 0, st, tab, k.d_idx, 1);
+  pe.mark(7, st);
+  pe.mark(8, st);
+  const int snew = (int)((level + 1) % 3);
+  const int blocks = (int)std::min<size_t>((cells + PER_THREADS - 1) / PER_THREADS, 8192);
+  hipLaunchKernelGGL(k_per_combine, dim3(blocks), dim3(PER_THREADS), 0, st, rm, m.psol,
+                     m.ds->coef, m.phi[snew], m.psi[snew], cells);
+  pe.mark(9, st);
+  pe.mark(10, st);
+  pe.mark(11, st);
+  return hipGetLastError() == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
+}
+
 int enqueue_step_level(ccmsav_ctx* c, int64_t level, hipStream_t st,
                        PhaseEvents pe = PhaseEvents{nullptr}, int only = -1) {
   if (is_gemm(c->precision)) return enqueue_step_gemm(c, level, st, pe);
+  if (c->periodic) return enqueue_step_periodic(c, level, st, pe);
   const int t = table_of_level(level);
   Tuner tu;
   if (!c->tuned) {
@@ -861,30 +932,37 @@ struct PerLaunch {
   using T = Tables<4, 5, 6, 7, 8, 9, 10, 11, 12>;
 };
 
-// Periodic chi^{-1} rhs and zeta^{-1} rhs of member 0 (FP64 transforms), with
-// three column buffers of (nx/2 + 1) columns in the intermediate region.
-int periodic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, double* out_zeta) {
-  const Member& m = c->mem[0];
+// Periodic chi^{-1} rhs and zeta^{-1} rhs of member m (FP64 transforms) with
+// the operator constants pc, on stream st, with three column buffers of
+// (nx/2 + 1) columns in the member's intermediate region. An output may be
+// rhs itself (the row pass has read rhs before the inverse rows write).
+int periodic_solve_pc(const Member& m, int precision, hipStream_t st, const double* rhs,
+                      double* out_chi, double* out_zeta, const PerConst& pc) {
   const int nx = m.p.nx, ny = m.p.ny;
   if (m.lx > kPerMaxLog || m.ly > kPerMaxLog) return CCMSAV_EUNSUPPORTED;
   const size_t cs = (size_t)ny + 66;             // column stride, off a power of two
   const size_t colb = (size_t)(nx / 2 + 1) * cs;
   const size_t need = 3 * colb * sizeof(cpx<double>);
-  const size_t have = M_NFIELD * strip_field(nx, ny, (int)mid_elem(c->precision)) *
-                      mid_elem(c->precision);
+  const size_t have = M_NFIELD * strip_field(nx, ny, (int)mid_elem(precision)) *
+                      mid_elem(precision);
   if (need > have) return CCMSAV_EUNSUPPORTED;
   cpx<double>* col = static_cast<cpx<double>*>(m.mid);
   cpx<double>* cc = col + colb;
   cpx<double>* cz = cc + colb;
-  const StepConst& k = c->h_args[(size_t)kSolveTable * c->mem.size()].k;
-  const PerConst pc{k.C1, k.C2, k.C3, k.alpha, k.lam, m.p.h};
   using PT = PerLaunch::T;
-  PT::t_rows[m.lx - kMinLog](c->stream, ny / 2, rhs, col, ny, cs);
-  PT::t_cols[m.ly - kMinLog](c->stream, nx / 2 + 1, col, out_chi ? cc : nullptr,
+  PT::t_rows[m.lx - kMinLog](st, ny / 2, rhs, col, ny, cs);
+  PT::t_cols[m.ly - kMinLog](st, nx / 2 + 1, col, out_chi ? cc : nullptr,
                              out_zeta ? cz : nullptr, nx, cs, pc);
-  if (out_chi) PT::t_inv[m.lx - kMinLog](c->stream, ny / 2, cc, out_chi, ny, cs);
-  if (out_zeta) PT::t_inv[m.lx - kMinLog](c->stream, ny / 2, cz, out_zeta, ny, cs);
+  if (out_chi) PT::t_inv[m.lx - kMinLog](st, ny / 2, cc, out_chi, ny, cs);
+  if (out_zeta) PT::t_inv[m.lx - kMinLog](st, ny / 2, cz, out_zeta, ny, cs);
   return hipGetLastError() == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
+}
+
+// The standalone periodic solve of member 0 with the BDF2 operators.
+int periodic_solve(ccmsav_ctx* c, const double* rhs, double* out_chi, double* out_zeta) {
+  const StepConst& k = c->h_args[(size_t)kSolveTable * c->mem.size()].k;
+  const PerConst pc{k.C1, k.C2, k.C3, k.alpha, k.lam, c->mem[0].p.h};
+  return periodic_solve_pc(c->mem[0], c->precision, c->stream, rhs, out_chi, out_zeta, pc);
 }
 
 // Upload `a` (a copy of the standalone-solve table entry, with the operator
@@ -1047,6 +1125,8 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
   c->precision = p[0].precision;
   c->graph = (p[0].flags & CCMSAV_FLAG_GRAPH) != 0;
   c->bdf1 = (p[0].flags & CCMSAV_FLAG_BDF1) != 0;
+  c->periodic = is_periodic(&p[0]);
+  c->tuned = c->periodic;  // the periodic step has no launch variants
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->owns_ws = workspace == nullptr;
   if (c->owns_ws) {
@@ -1095,6 +1175,7 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
     m.colsum = reinterpret_cast<double*>(mb + L.colsum);
     m.unit_coef = reinterpret_cast<double*>(mb + L.unit);
     m.ds = reinterpret_cast<DevScalars*>(mb + L.ds);
+    m.psol = is_periodic(&m.p) ? reinterpret_cast<double*>(mb + L.psol) : nullptr;
     if (is_gemm(m.p.precision)) {
       const size_t nxx = (size_t)m.p.nx * m.p.nx, nyy = (size_t)m.p.ny * m.p.ny;
       m.dx_hi = reinterpret_cast<uint16_t*>(mb + L.dx);

@@ -15,7 +15,17 @@ struct DiagConst {
   double gamma_surf, gamma_bend, gamma_area, theta, theta_t, lam, half_dt;
   double A;          // NaN: use the discrete surface energy of phi0
   int with_d;        // add ||d^n||^2 of the last step to the accumulator
+  int periodic;      // wrap-around ghosts (periodic boundaries), else Neumann
 };
+
+// Neighbour indices of cell i on a line of n cells: the ghost copy of the
+// boundary cell (Neumann), or the cell on the other side (periodic).
+__device__ __forceinline__ int next_cell(int i, int n, int periodic) {
+  return i + 1 < n ? i + 1 : (periodic ? 0 : n - 1);
+}
+__device__ __forceinline__ int prev_cell(int i, int n, int periodic) {
+  return i > 0 ? i - 1 : (periodic ? n - 1 : 0);
+}
 
 // Sums of the SAV functionals of Sec. 2.2 at (phi, psi), one row per block.
 __global__ void __launch_bounds__(DIAG_THREADS)
@@ -23,11 +33,11 @@ k_init_sums(const double* __restrict__ phi, const double* __restrict__ psi, doub
             int nx, int ny, DiagConst c) {
   __shared__ double red[I_NSUM * (DIAG_THREADS / 64 + 1)];
   const int tid = threadIdx.x, j = blockIdx.x;
-  const int jn = min(j + 1, ny - 1), js = max(j - 1, 0);
+  const int jn = next_cell(j, ny, c.periodic), js = prev_cell(j, ny, c.periodic);
   const double k32 = 0.75 * 1.4142135623730950488;
   double v[I_NSUM] = {0.0, 0.0, 0.0, 0.0};
   for (int i = tid; i < nx; i += DIAG_THREADS) {
-    const int ie = min(i + 1, nx - 1), iw = max(i - 1, 0);
+    const int ie = next_cell(i, nx, c.periodic), iw = prev_cell(i, nx, c.periodic);
     const double p = phi[(size_t)j * nx + i];
     const double gxe = (phi[(size_t)j * nx + ie] - p) * c.inv_h;
     const double gxw = (p - phi[(size_t)j * nx + iw]) * c.inv_h;
@@ -77,7 +87,7 @@ k_init_final(const double* __restrict__ part, int ny, DevScalars* __restrict__ d
 // Physical free energy of Sec. 2.1 (eq. energy_functional, densities of eq.
 // energy_densities) at (phi, psi): sums of f_surf, of (g'(phi)/eps - eps
 // Delta_h phi)^2 and of f_osm, one row per block (Neumann ghosts copy the
-// boundary cell).
+// boundary cell; periodic ones wrap around).
 enum PhysSum { Q_SURF = 0, Q_BEND, Q_OSM, Q_NSUM };
 
 __global__ void __launch_bounds__(DIAG_THREADS)
@@ -85,11 +95,11 @@ k_phys_sums(const double* __restrict__ phi, const double* __restrict__ psi,
             double* __restrict__ part, int nx, int ny, DiagConst c) {
   __shared__ double red[Q_NSUM * (DIAG_THREADS / 64 + 1)];
   const int tid = threadIdx.x, j = blockIdx.x;
-  const int jn = min(j + 1, ny - 1), js = max(j - 1, 0);
+  const int jn = next_cell(j, ny, c.periodic), js = prev_cell(j, ny, c.periodic);
   const double k32 = 0.75 * 1.4142135623730950488;
   double v[Q_NSUM] = {0.0, 0.0, 0.0};
   for (int i = tid; i < nx; i += DIAG_THREADS) {
-    const int ie = min(i + 1, nx - 1), iw = max(i - 1, 0);
+    const int ie = next_cell(i, nx, c.periodic), iw = prev_cell(i, nx, c.periodic);
     const double p = phi[(size_t)j * nx + i];
     const double gxe = (phi[(size_t)j * nx + ie] - p) * c.inv_h;
     const double gxw = (p - phi[(size_t)j * nx + iw]) * c.inv_h;
@@ -141,13 +151,13 @@ k_energy_sums(const double* __restrict__ p1, const double* __restrict__ p0,
               double* __restrict__ part, int nx, int ny, DiagConst c) {
   __shared__ double red[E_NSUM * (DIAG_THREADS / 64 + 1)];
   const int tid = threadIdx.x, j = blockIdx.x;
-  const int jn = min(j + 1, ny - 1), js = max(j - 1, 0);
+  const int jn = next_cell(j, ny, c.periodic), js = prev_cell(j, ny, c.periodic);
   double v[E_NSUM];
 #pragma unroll
   for (int q = 0; q < E_NSUM; ++q) v[q] = 0.0;
   auto at = [&](const double* f, int i, int jj) { return f[(size_t)jj * nx + i]; };
   for (int i = tid; i < nx; i += DIAG_THREADS) {
-    const int ie = min(i + 1, nx - 1), iw = max(i - 1, 0);
+    const int ie = next_cell(i, nx, c.periodic), iw = prev_cell(i, nx, c.periodic);
     // level n and the extrapolation 2 phi^n - phi^{n-1}
     const double a = at(p1, i, j), b = 2.0 * a - at(p0, i, j);
     const double ae = at(p1, ie, j), aw = at(p1, iw, j), an = at(p1, i, jn), as = at(p1, i, js);
@@ -160,12 +170,14 @@ k_energy_sums(const double* __restrict__ p1, const double* __restrict__ p0,
     v[E_P1] += a * a;
     v[E_P2] += b * b;
     const double d0 = a - at(p0, i, j);
-    if (i < nx - 1) {
+    // east and north faces of the cell (across the wrap when periodic)
+    const bool face_e = c.periodic || i < nx - 1, face_n = c.periodic || j < ny - 1;
+    if (face_e) {
       const double ga = (ae - a) * c.inv_h, gb = (be - b) * c.inv_h;
       const double gd = ((ae - at(p0, ie, j)) - d0) * c.inv_h;
       v[E_G1] += ga * ga; v[E_G2] += gb * gb; v[E_GD] += gd * gd;
     }
-    if (j < ny - 1) {
+    if (face_n) {
       const double ga = (an - a) * c.inv_h, gb = (bn - b) * c.inv_h;
       const double gd = ((an - at(p0, i, jn)) - d0) * c.inv_h;
       v[E_G1] += ga * ga; v[E_G2] += gb * gb; v[E_GD] += gd * gd;
@@ -175,13 +187,13 @@ k_energy_sums(const double* __restrict__ p1, const double* __restrict__ p0,
     if (c.with_d) {
       const double dc = at(s1, i, j) - 2.0 * at(s0, i, j) + at(sm, i, j);
       const double fc = 2.0 * at(p0, i, j) - at(pm, i, j);
-      if (i < nx - 1) {
+      if (face_e) {
         const double de = at(s1, ie, j) - 2.0 * at(s0, ie, j) + at(sm, ie, j);
         const double fe = 2.0 * at(p0, ie, j) - at(pm, ie, j);
         const double g = (de - dc) * c.inv_h;
         v[E_D] += g * g / mobility(0.5 * (fc + fe), c.M0);
       }
-      if (j < ny - 1) {
+      if (face_n) {
         const double dn = at(s1, i, jn) - 2.0 * at(s0, i, jn) + at(sm, i, jn);
         const double fn = 2.0 * at(p0, i, jn) - at(pm, i, jn);
         const double g = (dn - dc) * c.inv_h;

@@ -124,4 +124,70 @@ k_per_rows_inv(const cpx<double>* __restrict__ col, double* __restrict__ out, in
   }
 }
 
+// ---------------------------------------------------------------------------
+// The time step with periodic boundaries (FP64). Algorithm 1 of App. B with
+// the seven elliptic solves done by the solver above: chi^{-1} of f_lin (in
+// place) and of S~, H, Q~, K~ (into four fields of their own), zeta^{-1} of
+// g_lin and L~ (in place). The inner products of App. B Step 4 are then taken
+// in physical space and the solution combined from the solved fields.
+// ---------------------------------------------------------------------------
+constexpr int PER_THREADS = 256;
+
+// P2Sum partials of one grid row: (F_i, chi^{-1} F_j) for F in {S~, H, Q~, K~},
+// (F_i, chi^{-1} f_lin), (P~, zeta^{-1} g_lin), (P~, zeta^{-1} L~).
+// rm: the eight stencil fields (slots of Mid) with f_lin, g_lin and L~
+// already replaced by their solves; xs: chi^{-1} of S~, H, Q~, K~.
+__global__ void __launch_bounds__(PER_THREADS)
+k_per_gram(const double* __restrict__ rm, const double* __restrict__ xs, double* __restrict__ part,
+           int nx, int ny) {
+  __shared__ double red[P2_NSUM * (PER_THREADS / 64 + 1)];
+  const int j = blockIdx.x, tid = threadIdx.x;
+  const size_t FS = (size_t)nx * ny;
+  double v[P2_NSUM];
+#pragma unroll
+  for (int q = 0; q < P2_NSUM; ++q) v[q] = 0.0;
+  for (int i = tid; i < nx; i += PER_THREADS) {
+    const size_t o = (size_t)j * nx + i;
+    const double f = rm[M_F * FS + o];
+    const double F[4] = {rm[M_S * FS + o], rm[M_H * FS + o], rm[M_Q * FS + o], rm[M_K * FS + o]};
+    const double X[4] = {xs[o], xs[FS + o], xs[2 * FS + o], xs[3 * FS + o]};
+    v[P2_FS] += F[0] * f;
+    v[P2_FH] += F[1] * f;
+    v[P2_FQ] += F[2] * f;
+    v[P2_FK] += F[3] * f;
+    v[P2_SS] += F[0] * X[0];
+    v[P2_SH] += F[0] * X[1];
+    v[P2_SQ] += F[0] * X[2];
+    v[P2_SK] += F[0] * X[3];
+    v[P2_HH] += F[1] * X[1];
+    v[P2_HQ] += F[1] * X[2];
+    v[P2_HK] += F[1] * X[3];
+    v[P2_QQ] += F[2] * X[2];
+    v[P2_QK] += F[2] * X[3];
+    v[P2_KK] += F[3] * X[3];
+    const double P = rm[M_P * FS + o];
+    v[P2_PG] += P * rm[M_G * FS + o];
+    v[P2_PL] += P * rm[M_L * FS + o];
+  }
+  block_sum<P2_NSUM, PER_THREADS>(v, red, tid);
+  if (tid < P2_NSUM) part[(size_t)j * P2_NSUM + tid] = red[tid];
+}
+
+// phi^{n+1} = sum of coef[f] times the solved chi fields (f_lin, S~, H, Q~,
+// K~), psi^{n+1} = coef[5] zeta^{-1} g_lin + coef[6] zeta^{-1} L~, with the
+// combination coefficients of the 5x5 solve (App. B Step 4 recovery).
+__global__ void __launch_bounds__(PER_THREADS)
+k_per_combine(const double* __restrict__ rm, const double* __restrict__ xs,
+              const double* __restrict__ coef, double* __restrict__ phi_new,
+              double* __restrict__ psi_new, size_t n) {
+  const double c0 = coef[0], c1 = coef[1], c2 = coef[2], c3 = coef[3], c4 = coef[4];
+  const double c5 = coef[5], c6 = coef[6];
+  const size_t stride = (size_t)gridDim.x * PER_THREADS;
+  for (size_t o = (size_t)blockIdx.x * PER_THREADS + threadIdx.x; o < n; o += stride) {
+    phi_new[o] = c0 * rm[M_F * n + o] + c1 * xs[o] + c2 * xs[n + o] + c3 * xs[2 * n + o] +
+                 c4 * xs[3 * n + o];
+    psi_new[o] = c5 * rm[M_G * n + o] + c6 * rm[M_L * n + o];
+  }
+}
+
 }  // namespace ccm

@@ -92,6 +92,7 @@ struct StepConst {
   double half_dt;
   int lag_d;             // accumulate ||d^n||^2 of the previous (BDF2) step
   int slot_n, slot_m, slot_new;   // SAV ring slots of levels n, n-1, n+1
+  int periodic;          // wrap-around ghosts (periodic boundaries), else Neumann
 };
 
 // Pointer into global memory. The kernels read their pointers from tables in

@@ -222,7 +222,8 @@ __device__ __forceinline__ double lane_from_above(double v) {
 // registers and takes the values at the left and right neighbours from the
 // adjacent lanes, so every pointwise quantity (phi*, psi*, P~ and its sine) is
 // formed once per cell. Neighbours outside the grid are the ghost copies of
-// App. D (index clamping). The eight fields are the right-hand sides of
+// App. D (index clamping), or with periodic boundaries the cells on the other
+// side of the grid (index wrapping). The eight fields are the right-hand sides of
 // eqs. (AC_BDF2)-(Z_BDF2) at phi* = x0 phi^n + x1 phi^{n-1} (slot order of Mid)
 // and leave row-major ([field][ny][nx], x fastest).
 constexpr int STENCIL_THREADS = 256;
@@ -253,9 +254,13 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
   const int nseg = (nx + SW_COLS - 1) / SW_COLS;
   const int seg = blk % nseg, band = blk / nseg;
   const int ci = seg * SW_COLS + wave * SW_OUT - 2 + lane;   // this lane's column
-  const int cl = min(max(ci, 0), nx - 1);                    // its ghost-clamped column
+  const bool per = c.periodic != 0;
+  // the column this lane loads: its ghost source (clamped, or wrapped)
+  const int cl = per ? ((ci % nx) + nx) % nx : min(max(ci, 0), nx - 1);
   const bool out_lane = lane >= 2 && lane < 2 + SW_OUT && ci < nx;
-  const bool at_w = ci == 0, at_e = ci == nx - 1;
+  // Neumann ghosts at the west and east walls are the cell itself; periodic
+  // neighbours are the adjacent lanes, which hold the wrapped columns
+  const bool at_w = !per && ci == 0, at_e = !per && ci == nx - 1;
   const int j0 = band * iters;
   const size_t FS = (size_t)nx * ny;
   const double k32 = 0.75 * 1.4142135623730950488;   // 3 sqrt(2) / 4
@@ -271,7 +276,10 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
     const double u = lane_from_above(v);
     return at_e ? v : u;
   };
-  auto at = [&](int r) { return (size_t)min(max(r, 0), ny - 1) * nx + cl; };
+  auto at = [&](int r) {
+    const int rr = per ? ((r % ny) + ny) % ny : min(max(r, 0), ny - 1);
+    return (size_t)rr * nx + cl;
+  };
 
   // Pointwise quantities of one row at this column.
   struct Row {
@@ -420,15 +428,18 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
         sums[P1_XK] += Kt * rc.phn;
         sums[P1_XP] += Pc * rc.psn;
       }
-      if (ci < nx - 1 && !(Me > 0.0)) sums[P1_MOBNEG] += 1.0;
-      if (j < ny - 1 && !(Mn > 0.0)) sums[P1_MOBNEG] += 1.0;
+      // the east and north faces of the cell (with periodic boundaries the
+      // faces across the wrap belong to the last column and row)
+      const bool face_e = per || ci < nx - 1, face_n = per || j < ny - 1;
+      if (face_e && !(Me > 0.0)) sums[P1_MOBNEG] += 1.0;
+      if (face_n && !(Mn > 0.0)) sums[P1_MOBNEG] += 1.0;
       if (c.lag_d) {
         // ||d^n||^2 of the previous step over the east and north faces
-        if (ci < nx - 1) {
+        if (face_e) {
           const double g = de - rc.dl;
           sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (rc.fl + fe), c.M0);
         }
-        if (j < ny - 1) {
+        if (face_n) {
           const double g = rn.dl - rc.dl;
           sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (rc.fl + rn.fl), c.M0);
         }

@@ -87,8 +87,20 @@ def test_init_rejects_null_and_unknown_modes():
     buf = (ctypes.c_double * 4)()
     assert lib.ccmsav_init(ctypes.byref(h), ctypes.byref(p), buf, buf, None, 0, None) == -6
     p.precision = 0
-    p.flags = 4          # no such flag
+    p.flags = 8          # no such flag
     assert lib.ccmsav_init(ctypes.byref(h), ctypes.byref(p), buf, buf, None, 0, None) == -1
+    # the periodic step: FP64 only, no graph, grids up to 4096, one member
+    for prec, flags, n in ((C.MIXED, C.FLAG_PERIODIC, 64), (C.FP64, C.FLAG_PERIODIC | C.FLAG_GRAPH, 64),
+                           (C.FP64, C.FLAG_PERIODIC, 8192)):
+        q = _params(nx=n, ny=n)
+        q.precision, q.flags = prec, flags
+        assert lib.ccmsav_init(ctypes.byref(h), ctypes.byref(q), buf, buf, None, 0, None) == -6
+        assert lib.ccmsav_workspace_bytes(ctypes.byref(q)) == 0
+    q = _params()
+    q.flags = C.FLAG_PERIODIC
+    assert lib.ccmsav_workspace_bytes(ctypes.byref(q)) > lib.ccmsav_workspace_bytes(ctypes.byref(p))
+    pair = (C.Params * 2)(q, q)
+    assert lib.ccmsav_workspace_bytes_batch(2, pair) == 0
     assert lib.ccmsav_step(None, 1) == -1
     assert lib.ccmsav_destroy(None) == -1
     assert C.strerror(-6).startswith("unsupported")
