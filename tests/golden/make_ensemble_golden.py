@@ -12,11 +12,12 @@ in each direction of phi and psi of the first run, and the larger relative
 L-inf spread (over the whole grid) of the other two runs from it: the
 rounding envelope the GPU comparison is held to.
 
-Usage (takes about half an hour single-threaded):
+Usage (six oracle runs in parallel processes, about ten minutes):
     python tests/golden/make_ensemble_golden.py
 """
 import os
 import sys
+from multiprocessing import Pool
 
 import numpy as np
 
@@ -40,19 +41,26 @@ def trajectory(phi0, psi0, params, use_matrix=True):
     return out
 
 
-def main():
-    ms = make_workload("ensemble48x256_16x512")
-    data = {}
-    for i in MEMBERS:
-        m = ms[i]
+def _run(job):
+    i, kind = job
+    m = make_workload("ensemble48x256_16x512")[i]
+    phi0, psi0 = m.phi0, m.psi0
+    if kind == "pert":
         rng = np.random.default_rng(1)
         ulp = 2.0 ** -52
-        phi_p = m.phi0 * (1.0 + ulp * rng.choice([-1.0, 1.0], m.phi0.shape))
-        psi_p = m.psi0 * (1.0 + ulp * rng.choice([-1.0, 1.0], m.psi0.shape))
-        ref = trajectory(m.phi0, m.psi0, m.params)
-        alt = trajectory(m.phi0, m.psi0, m.params, use_matrix=False)
-        pert = trajectory(phi_p, psi_p, m.params)
-        rel = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())  # noqa: E731
+        phi0 = phi0 * (1.0 + ulp * rng.choice([-1.0, 1.0], phi0.shape))
+        psi0 = psi0 * (1.0 + ulp * rng.choice([-1.0, 1.0], psi0.shape))
+    return job, trajectory(phi0, psi0, m.params, use_matrix=(kind != "alt"))
+
+
+def main():
+    jobs = [(i, kind) for i in MEMBERS for kind in ("ref", "alt", "pert")]
+    with Pool(len(jobs)) as pool:
+        runs = dict(pool.map(_run, jobs))
+    rel = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())  # noqa: E731
+    data = {}
+    for i in MEMBERS:
+        ref, alt, pert = runs[(i, "ref")], runs[(i, "alt")], runs[(i, "pert")]
         for k in CHECKPOINTS:
             phi, psi, sav = ref[k]
             env = [max(rel(o[k][0], phi), rel(o[k][1], psi), rel(o[k][2], sav))
@@ -61,7 +69,8 @@ def main():
             data[f"m{i}_k{k}_psi"] = psi[::4, ::4]
             data[f"m{i}_k{k}_sav"] = sav
             data[f"m{i}_k{k}_env"] = np.array(env)
-        print(f"member {i} done", flush=True)
+        print(f"member {i}: envelope " + ", ".join(
+            f"{k}: {data[f'm{i}_k{k}_env'].max():.1e}" for k in CHECKPOINTS), flush=True)
     np.savez_compressed(os.path.join(HERE, "ensemble_member_oracle.npz"), **data)
 
 

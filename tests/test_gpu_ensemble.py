@@ -119,14 +119,13 @@ def test_ensemble_workload_mixed_against_fp64():
     """48 x 256^2 + 16 x 512^2, eps in {3h, 4h, 5h}, c_out ~ U(0.8, 1.25), 2000 steps,
     mixed precision (graph-captured) against the FP64 ensemble, member by member.
 
-    Some members reach configurations in which the scheme amplifies small
-    perturbations by orders of magnitude: by step 500 an FP64 run from inputs
-    rounded to FP32 ends up to 4e-4 away from the FP64 run, and per-step
-    perturbations of FP32 size are amplified further. There no two roundings
-    of the scheme agree, so the 1e-6 bar is held for every member at step 100,
-    where the FP32-input spread of every member is below 1e-7; the later
-    checkpoints are reported. Mass drift (5e-11) and energy decay are held for
-    all members at every checkpoint."""
+    At every checkpoint (100, 500, 1000, 2000) every member's mixed run is
+    held to 1e-6 of its FP64 run (relative L-inf of phi and psi), mass drift
+    to 5e-11, and the modified energy must decay. The FP64 run from inputs
+    rounded to FP32 is held within 1e-7 of the FP64 run: the workload's time
+    step keeps every member's trajectory determined to that level by
+    FP32-sized input changes, which is what makes the 1e-6 bar meaningful for
+    the mixed form."""
     ms = make_workload("ensemble48x256_16x512")
     checkpoints = (100, 500, 1000, 2000)
     golden = np.load(os.path.join(os.path.dirname(__file__), "golden",
@@ -176,9 +175,8 @@ def test_ensemble_workload_mixed_against_fp64():
              f"{int((err <= 1e-6).sum())}/{nm}; FP32-input envelope worst {env.max():.2e}, "
              f"members with envelope <= 1e-6: {int(well.sum())}, worst error among them "
              f"{err[well].max() if well.any() else 0.0:.2e}")
-        if k == checkpoints[0]:
-            assert np.all(env <= 1e-7), k
-            assert np.all(err <= 1e-6), (k, np.flatnonzero(err > 1e-6).tolist())
+        assert np.all(env <= 1e-7), (k, np.flatnonzero(env > 1e-7).tolist())
+        assert np.all(err <= 1e-6), (k, np.flatnonzero(err > 1e-6).tolist())
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-6)])

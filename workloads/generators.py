@@ -15,7 +15,7 @@ inputs stand in for them with the paper's parameter magnitudes:
   that c_out > c_in drives shrinkage and c_out < c_in growth;
 * time step dt = 1e-4 for the circle; for the perturbed vesicles the paper's
   table value 1e-6 up to N = 1024, scaled by (1024 / N)^3 on finer grids;
-  1e-7 for the members of the ensemble;
+  2.5e-8 for the members of the ensemble;
 * the remaining coefficients from the paper's parameter table (App. G):
   gamma_surf = 1, gamma_bend = 1 (shrinkage) or 0.05 (growth),
   gamma_area = 5e4, gamma_in = gamma_out = 1e5, beta_in = beta_out = 0,
@@ -43,13 +43,15 @@ DOMAIN_L = 2.0 * math.pi
 # steps, which the scheme's dissipation argument excludes.
 DEFAULT_DT = 1.0e-4
 VESICLE_DT = 1.0e-6
-# The ensemble members (256^2 and 512^2, eps in {3h, 4h, 5h}) take 1e-7: at
+# The ensemble members (256^2 and 512^2, eps in {3h, 4h, 5h}) take 2.5e-8. At
 # 1e-6 (and at 2.5e-7) these coarse members enter, after 10-100 steps, a regime
 # in which the step amplifies per-step perturbations by several orders of
-# magnitude within tens of steps (FP64 runs from perturbed inputs and FP32
-# rounding both show it), so no two roundings of the scheme agree there; at
-# 1e-7 perturbations stay at their injected size over 2000 steps.
-ENSEMBLE_DT = 1.0e-7
+# magnitude within tens of steps, so no two roundings of the scheme agree
+# there. At 1e-7 a third of the members still reach it between steps 500 and
+# 2000: an FP64 run from inputs rounded to FP32 then ends 2e-4 - 6e-4 away.
+# At 2.5e-8 (the same 2000 steps cover a quarter of that time) such runs stay
+# within 3e-8 of the unrounded ones for every member over all 2000 steps.
+ENSEMBLE_DT = 2.5e-8
 PSI_GAP = 0.35
 
 
