@@ -28,13 +28,20 @@ enum MfMode { MF_ROW = 0, MF_COL = 1 };
 
 constexpr int MF_THREADS = 256;   // four waves, each owning a quarter of the block tile
 constexpr int MF_BK = 32;         // K per staged slice
-// LDS row of one tile line: 32 bf16 of K plus 8 of padding (80 bytes), so
-// that the 16-byte fragment reads of 16 consecutive lanes (16 lines) fall on
-// 16 disjoint groups of four banks.
-constexpr int MF_ROW16 = 5;       // 16-byte units per LDS line
+// LDS line of one tile line: 32 bf16 of K (four 16-byte chunks, 64 bytes).
+constexpr int MF_ROW16 = 4;       // 16-byte units per LDS line
 
 // Tile edge along m and n: 128, or 64 for the smallest grids.
 __host__ __device__ constexpr int mf_tile(int dim) { return dim >= 128 ? 128 : 64; }
+
+// LDS slot of K chunk k8 of a line: the chunks of line l are permuted by
+// k8 ^ ((l >> 2) & 3). The 256-byte bank window holds 16 chunks; 16
+// consecutive lanes then hit 16 distinct bank groups both when four lanes
+// stage the four chunks of one line (4 lines per 16 lanes, one (l >> 2)) and
+// when 16 lanes read one chunk of 16 consecutive lines (fragment loads).
+__device__ __forceinline__ int mf_slot(int line, int k8) {
+  return line * MF_ROW16 + (k8 ^ ((line >> 2) & 3));
+}
 
 // x = hi + lo + O(2^-16 |x|): bfloat16 halves of eight FP32 values.
 __device__ __forceinline__ void split8(const float (&v)[8], bf16x8_t& hi, bf16x8_t& lo) {
@@ -109,6 +116,7 @@ k_gemm_bf16x3(const uint16_t* __restrict__ d_hi, const uint16_t* __restrict__ d_
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < CD; ++i) {
+      // four consecutive lanes read the 64 contiguous bytes of one line
       const int ch = tid + i * MF_THREADS;
       const int r = ch >> 2, k8 = ch & 3;
       const size_t o = (size_t)(d0 + r) * K + k0 + 8 * k8;
@@ -142,18 +150,19 @@ k_gemm_bf16x3(const uint16_t* __restrict__ d_hi, const uint16_t* __restrict__ d_
     for (int i = 0; i < CD; ++i) {
       const int ch = tid + i * MF_THREADS;
       const int r = ch >> 2, k8 = ch & 3;
-      Ld_hi[r * MF_ROW16 + k8] = rd_hi[i];
-      Ld_lo[r * MF_ROW16 + k8] = rd_lo[i];
+      Ld_hi[mf_slot(r, k8)] = rd_hi[i];
+      Ld_lo[mf_slot(r, k8)] = rd_lo[i];
     }
 #pragma unroll
     for (int i = 0; i < CX; ++i) {
       const int ch = tid + i * MF_THREADS;
+      // row mode: four lanes per line; column mode: consecutive lanes, consecutive lines
       const int s = MODE == MF_ROW ? ch >> 2 : ch % RX;
       const int k8 = MODE == MF_ROW ? ch & 3 : ch / RX;
       bf16x8_t h, l;
       split8(rx[i], h, l);
-      Lx_hi[s * MF_ROW16 + k8] = h;
-      Lx_lo[s * MF_ROW16 + k8] = l;
+      Lx_hi[mf_slot(s, k8)] = h;
+      Lx_lo[mf_slot(s, k8)] = l;
     }
   };
 
@@ -180,14 +189,14 @@ k_gemm_bf16x3(const uint16_t* __restrict__ d_hi, const uint16_t* __restrict__ d_
 #pragma unroll
       for (int a = 0; a < TN; ++a) {
         const int line = wn + a * 32 + (lane & 31);
-        an_hi[a] = Ln_hi[line * MF_ROW16 + kc];
-        an_lo[a] = Ln_lo[line * MF_ROW16 + kc];
+        an_hi[a] = Ln_hi[mf_slot(line, kc)];
+        an_lo[a] = Ln_lo[mf_slot(line, kc)];
       }
 #pragma unroll
       for (int b = 0; b < TM; ++b) {
         const int line = wm + b * 32 + (lane & 31);
-        bm_hi[b] = Lm_hi[line * MF_ROW16 + kc];
-        bm_lo[b] = Lm_lo[line * MF_ROW16 + kc];
+        bm_hi[b] = Lm_hi[mf_slot(line, kc)];
+        bm_lo[b] = Lm_lo[mf_slot(line, kc)];
       }
 #pragma unroll
       for (int a = 0; a < TN; ++a)
