@@ -210,6 +210,55 @@ def _counter_means(directory: str, counter: str):
     return {k: (n, t / n) for k, (n, t) in acc.items()}, copy
 
 
+def digest_pmc(directory: str, name: str, command: str, cus: int = 256):
+    """profiles/counters_<name>.md: the mean per dispatch of every counter of
+    a rocprofv3 --pmc run, per kernel, with the derived figures the summary
+    uses: MFMA busy share = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x CUs),
+    matrix-core TFLOP/s = 512 x SQ_INSTS_VALU_MFMA_MOPS_BF16 / kernel time,
+    LDS bank-conflict share = SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS, mean
+    resident waves = SQ_WAVE_CYCLES / SQ_BUSY_CYCLES."""
+    rows = _csv_rows(directory, "counter_collection.csv")
+    acc = {}
+    for r in rows:
+        k = _short(r["Kernel_Name"])
+        d = acc.setdefault(k, {})
+        cn = r["Counter_Name"]
+        n, t = d.get(cn, (0, 0.0))
+        d[cn] = (n + 1, t + float(r["Counter_Value"]))
+        if cn == next(iter(d)):          # one duration sample per dispatch
+            n2, t2 = d.get("_ns", (0, 0.0))
+            d["_ns"] = (n2 + 1, t2 + float(r["End_Timestamp"]) - float(r["Start_Timestamp"]))
+    names = sorted({c for d in acc.values() for c in d if c != "_ns"})
+    lines = [f"# rocprofv3 counters: {name}", "",
+             "Command (on one MI355X; $REPO is the repository root):", "", "```", command, "```",
+             "", "Mean per dispatch. Derived: MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / "
+             f"(GRBM_GUI_ACTIVE x {cus} CUs); MFMA TFLOP/s = 512 x SQ_INSTS_VALU_MFMA_MOPS_BF16 / "
+             "dispatch time; LDS conflict = SQ_LDS_BANK_CONFLICT / SQ_ACTIVE_INST_LDS; waves = "
+             "SQ_WAVE_CYCLES / SQ_BUSY_CYCLES (mean resident waves per busy SQ cycle, summed over "
+             "the SQs).", "",
+             "| kernel | dispatches | us | " + " | ".join(names) + " | derived |",
+             "|---|---|---|" + "---|" * len(names) + "---|"]
+    for k in sorted(acc):
+        d = acc[k]
+        mean = {c: t / n for c, (n, t) in d.items()}
+        der = []
+        us = mean.get("_ns", 0.0) / 1e3
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in mean and mean.get("GRBM_GUI_ACTIVE"):
+            der.append(f"MFMA busy {mean['SQ_VALU_MFMA_BUSY_CYCLES'] / (mean['GRBM_GUI_ACTIVE'] * cus):.2f}")
+        if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in mean and us > 0:
+            der.append(f"MFMA {512 * mean['SQ_INSTS_VALU_MFMA_MOPS_BF16'] / (us * 1e-6) / 1e12:.0f} TFLOP/s")
+        if mean.get("SQ_ACTIVE_INST_LDS"):
+            der.append(f"LDS conflict {mean.get('SQ_LDS_BANK_CONFLICT', 0.0) / mean['SQ_ACTIVE_INST_LDS']:.3f}")
+        if mean.get("SQ_BUSY_CYCLES") and "SQ_WAVE_CYCLES" in mean:
+            der.append(f"waves {mean['SQ_WAVE_CYCLES'] / mean['SQ_BUSY_CYCLES']:.1f}")
+        vals = " | ".join(f"{mean[c]:.4g}" if c in mean else "" for c in names)
+        lines.append(f"| `{k}` | {d['_ns'][0]} | {us:.1f} | {vals} | {'; '.join(der)} |")
+    path = os.path.join(ROOT, "profiles", f"counters_{name}.md")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(path)
+
+
 def digest_counters(fetch_dir: str, write_dir: str, workload: str, precision: str,
                     probe_mib: int, commands: str, autotuned: str):
     """profiles/traffic_<workload>_<precision>.{md,txt} from one FETCH_SIZE and
@@ -324,7 +373,7 @@ def cpu_baseline(members, budget_s: float = 12.0):
 
 
 def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, graph,
-              bdf1=False):
+              bdf1=False, classical=False, periodic=False):
     """Warm up, time ``steps`` steps between two synchronisations, then take
     ``profile_steps`` more with per-kernel events. Returns timings and the
     final states (after warmup + steps + profile_steps steps)."""
@@ -332,7 +381,8 @@ def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, g
     psi0 = [torch.from_numpy(m.psi0).to(dev) for m in members]
     stream = torch.cuda.current_stream(dev)
     ctx = C.Context.ensemble([m.params for m in members], phi0, psi0, precision,
-                             stream=stream.cuda_stream, graph=graph, bdf1=bdf1)
+                             stream=stream.cuda_stream, graph=graph, bdf1=bdf1,
+                             classical=classical, periodic=periodic)
     nm = len(members)
     mass0 = [ctx.mass(i)[0] for i in range(nm)]
     ctx.step(warmup)
@@ -352,7 +402,8 @@ def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, g
     mass = [ctx.mass(i)[0] for i in range(nm)]
     out = dict(wall=wall, ev_ms=ev0.elapsed_time(ev1), prof=prof, tuning=tuning,
                drift=max(abs(a - b) / abs(b) for a, b in zip(mass, mass0)),
-               energy=[None if bdf1 else ctx.energy(member=i) for i in range(nm)],
+               pcg=ctx.pcg_stats() if classical else None,
+               energy=[None if (bdf1 or classical) else ctx.energy(member=i) for i in range(nm)],
                fields=[ctx.fields(i) for i in range(nm)],
                savs=[ctx.savs(i)[0] for i in range(nm)])
     ctx.close()
@@ -438,9 +489,15 @@ def main():
                     help="replay the steady-state steps from a captured HIP graph")
     ap.add_argument("--profile-steps", type=int, default=50,
                     help="steps of the per-kernel event pass that feeds the roofline")
-    ap.add_argument("--scheme", default="bdf2", choices=["bdf2", "bdf1"],
-                    help="time-stepping scheme: CC-MSAV-BDF2 (the default), or the "
-                         "first-order CC-MSAV-BDF1 scheme at every step")
+    ap.add_argument("--scheme", default="bdf2", choices=["bdf2", "bdf1", "classical"],
+                    help="time-stepping scheme: CC-MSAV-BDF2 (the default), the "
+                         "first-order CC-MSAV-BDF1 scheme at every step, or the classical "
+                         "MSAV scheme with its PCG solves (FP64)")
+    ap.add_argument("--periodic", action="store_true",
+                    help="periodic boundaries (FP64 step with FFT solves)")
+    ap.add_argument("--compare-classical", action="store_true",
+                    help="also time the classical MSAV scheme (FP64, PCG) on the same workload "
+                         "and report the CC-MSAV speedup on this GPU")
     ap.add_argument("--smooth-ic", action="store_true",
                     help="instead of the step, time the App. F initial-condition relaxation "
                          "(ccmsav_smooth_ic, ten steps per call) on the workload's first grid")
@@ -459,12 +516,17 @@ def main():
     ap.add_argument("--digest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_<workload>_<precision>.{md,txt} from a "
                          "FETCH_SIZE and a WRITE_SIZE rocprofv3 run (no GPU work)")
+    ap.add_argument("--digest-pmc", nargs=2, metavar=("DIR", "NAME"),
+                    help="write profiles/counters_NAME.md from a rocprofv3 --pmc run (no GPU work)")
     ap.add_argument("--digest-command", default="", help="command text for the digests")
     ap.add_argument("--digest-autotuned", default="",
                     help="launch variants of the timed steps, e.g. row_dct=1,col_solve=1,row_idct=0")
     args = ap.parse_args()
     if args.digest_trace:
         digest_trace(args.digest_trace[0], args.digest_trace[1], args.digest_command)
+        return
+    if args.digest_pmc:
+        digest_pmc(args.digest_pmc[0], args.digest_pmc[1], args.digest_command)
         return
     if args.digest_counters:
         digest_counters(args.digest_counters[0], args.digest_counters[1], args.workload,
@@ -493,8 +555,11 @@ def main():
         return
 
     bdf1 = args.scheme == "bdf1"
+    classical = args.scheme == "classical"
+    if classical or args.periodic:
+        args.precision = "fp64"
     run = timed_run(C, torch, members, args.precision, args.steps, args.warmup,
-                    args.profile_steps, dev, args.graph, bdf1)
+                    args.profile_steps, dev, args.graph, bdf1, classical, args.periodic)
     wall = run["wall"]
     ms_per_step = 1e3 * wall / args.steps
     value = cells * args.steps / wall / 1e6
@@ -522,7 +587,7 @@ def main():
                     "traffic": None, "flops_per_launch": fl[dom], "us_per_launch": prof[dom] * 1e3,
                     "step_flops": sum(fl.values()),
                     "step_frac": sum(fl.values()) / (ms_per_step * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}
-    elif prof:
+    elif prof and not (classical or args.periodic):
         # The dominant pass of the pipeline model, by its launches' mean
         # durations on the library's stream (HIP events); P1 is the stencil
         # launch plus the row DCT launch.
@@ -549,7 +614,7 @@ def main():
                                                                        args.precision)}
 
     finite = all(bool(np.all(np.isfinite(f[0]))) for f in run["fields"])
-    if not bdf1:
+    if not (bdf1 or classical):
         finite = finite and bool(np.all(np.isfinite(run["energy"])))
     check = {"mass_drift": run["drift"], "E_mod": run["energy"][0], "finite": finite}
     compare = None
@@ -569,6 +634,22 @@ def main():
               f"{fp64_value:.1f} Mcell-steps/s; mixed/fp64 = {compare['speedup_vs_fp64']:.3f}; "
               f"rel err phi {check['rel_linf_phi_vs_fp64']:.2e}", file=sys.stderr, flush=True)
 
+    if run["pcg"] is not None:
+        check["pcg_iterations_last_step"], check["pcg_rel_residual_last_step"] = run["pcg"]
+    if args.compare_classical and not classical:
+        cl = timed_run(C, torch, members, "fp64", args.steps, args.warmup, 0, dev, False, bdf1,
+                       True, False)
+        cl_value = cells * args.steps / cl["wall"] / 1e6
+        compare = dict(compare or {}, classical_value=cl_value,
+                       classical_ms_per_step=1e3 * cl["wall"] / args.steps,
+                       classical_pcg_iterations=cl["pcg"][0],
+                       speedup_vs_classical=value / cl_value)
+        if compare.get("fp64_value"):
+            compare["fp64_speedup_vs_classical"] = compare["fp64_value"] / cl_value
+        print(f"[bench] classical MSAV (FP64, PCG): {compare['classical_ms_per_step']:.4f} ms/step, "
+              f"{cl_value:.1f} Mcell-steps/s, iterations {cl['pcg'][0]}; this path / classical = "
+              f"{compare['speedup_vs_classical']:.2f}", file=sys.stderr, flush=True)
+
     if args.copy_probe_mib > 0:
         a = torch.empty(args.copy_probe_mib * 2 ** 18, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
@@ -581,6 +662,7 @@ def main():
     config = {"workload": args.workload, "members": len(members), "cells": cells,
               "grids": sorted({(m.params["nx"], m.params["ny"]) for m in members}),
               "precision": args.precision, "graph": args.graph, "scheme": args.scheme,
+              "boundaries": "periodic" if args.periodic else "neumann",
               "dt": sorted({m.params["dt"] for m in members}),
               "eps_cells": sorted({m.meta.get("eps_cells", 4.0) for m in members})}
     if len(members) == 1:

@@ -45,7 +45,9 @@ typedef enum {
   CCMSAV_EDOMAIN = -4,      /* SAV normaliser <= 0, singular 5x5 system, or a
                                face mobility M_psi <= 0 (energy undefined) */
   CCMSAV_ENONFINITE = -5,   /* NaN or Inf in the state or the SAVs */
-  CCMSAV_EUNSUPPORTED = -6  /* grid size or precision mode not provided */
+  CCMSAV_EUNSUPPORTED = -6, /* grid size or precision mode not provided */
+  CCMSAV_ECONVERGE = -7     /* an iterative solve (CCMSAV_FLAG_CLASSICAL) did not
+                               reach its tolerance within its iterations */
 } ccmsav_status;
 
 typedef enum {
@@ -84,7 +86,8 @@ typedef enum {
  *  lam          Cahn-Hilliard stabilisation lambda >= 0               (Sec. 3.2)
  *  beta         linear SAV splitting constant                         (Sec. 2.2)
  *  precision    a ccmsav_precision value
- *  flags        0 or CCMSAV_FLAG_GRAPH, CCMSAV_FLAG_BDF1, CCMSAV_FLAG_PERIODIC
+ *  flags        0 or CCMSAV_FLAG_GRAPH, CCMSAV_FLAG_BDF1, CCMSAV_FLAG_PERIODIC,
+ *               CCMSAV_FLAG_CLASSICAL
  */
 typedef struct {
   int32_t nx, ny;
@@ -120,6 +123,23 @@ typedef struct {
  * grids up to 4096 per direction (else EUNSUPPORTED). ccmsav_elliptic_solve
  * keeps solving with Neumann boundaries. */
 #define CCMSAV_FLAG_PERIODIC 4
+
+/* flags: the classical MSAV scheme of the App. B remarks instead of CC-MSAV,
+ * the comparison system of Sec. 4. The Cahn-Hilliard stabilisation sits in the
+ * chemical potential: g_lin carries -lambda div(M_psi(phi*) grad psi*) and the
+ * operator is zeta = alpha - lambda div(M_psi(phi*) grad), variable in space.
+ * Its two solves per step (zeta^{-1} g and zeta^{-1} L~) run as one lock-step
+ * conjugate gradient iteration preconditioned with alpha - lambda M_bar
+ * Delta_h (M_bar the mean of M_psi(phi*) over the cells, inverted by the DCT
+ * solver of App. C), from x = 0 until |r| <= tol |b| (discrete L2 norms),
+ * with the mean of x then set from the exact relation alpha sum x = sum b so
+ * that mass is conserved to rounding; the Allen-Cahn part and the 5x5
+ * reduction are those of CC-MSAV. CCMSAV_FP64 only, single-member contexts
+ * with Neumann boundaries, without CCMSAV_FLAG_GRAPH (else EUNSUPPORTED).
+ * Not converging within the allowed iterations is a sticky device error
+ * (ECONVERGE). ccmsav_energy returns EUNSUPPORTED (E^{n,n-1}_mod with the
+ * lambda dissipation sum is the CC-MSAV energy). */
+#define CCMSAV_FLAG_CLASSICAL 8
 
 /* Device workspace bytes a context needs for these parameters (0 if the
  * parameters are invalid or unsupported). */
@@ -340,6 +360,23 @@ int ccmsav_elliptic_solve_noalloc(const ccmsav_params* p, const double* rhs, dou
  */
 int ccmsav_smooth_ic(ccmsav_ctx* c, double M, double dt, int32_t nsteps, const double* phi_sharp,
                      double* phi_out);
+
+/*
+ * Classical scheme (CCMSAV_FLAG_CLASSICAL): the relative residual tol > 0 at
+ * which the conjugate gradient iteration stops (default 1e-12) and the
+ * iterations enqueued per step, 1 <= max_iter <= 10000 (default 40; those left
+ * after convergence return at once). Applies from the next step.
+ * EUNSUPPORTED for a context of another scheme, EINVAL for bad values.
+ */
+int ccmsav_pcg_config(ccmsav_ctx* c, double tol, int32_t max_iter);
+
+/*
+ * Classical scheme: the iterations the last step took for its two solves
+ * (iters[0] zeta^{-1} g, iters[1] zeta^{-1} L~) and their final relative
+ * residuals |r| / |b|. Synchronises the stream. EUNSUPPORTED for a context of
+ * another scheme.
+ */
+int ccmsav_pcg_stats(ccmsav_ctx* c, int32_t iters[2], double rel_residual[2]);
 
 /* Release the context (and the workspace if the library allocated it). */
 int ccmsav_destroy(ccmsav_ctx* c);

@@ -22,11 +22,12 @@ MIXED_GEMM_BF16X3 = 2
 PRECISIONS = {"fp64": FP64, "mixed": MIXED, "gemm": MIXED_GEMM_BF16X3}
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDOMAIN",
-          -5: "ENONFINITE", -6: "EUNSUPPORTED"}
+          -5: "ENONFINITE", -6: "EUNSUPPORTED", -7: "ECONVERGE"}
 
 FLAG_GRAPH = 1
 FLAG_BDF1 = 2
 FLAG_PERIODIC = 4
+FLAG_CLASSICAL = 8
 BC_NEUMANN, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2
 
 EXPORTED = (
@@ -37,7 +38,7 @@ EXPORTED = (
     "ccmsav_members", "ccmsav_energy_m", "ccmsav_mass_m", "ccmsav_get_fields_m",
     "ccmsav_get_savs_m", "ccmsav_tuning", "ccmsav_smooth_ic", "ccmsav_physical_energy",
     "ccmsav_physical_energy_m", "ccmsav_set_launch_variants", "ccmsav_elliptic_solve_bc",
-    "ccmsav_elliptic_solve_noalloc",
+    "ccmsav_elliptic_solve_noalloc", "ccmsav_pcg_config", "ccmsav_pcg_stats",
 )
 PHASES = ("stencil", "row_dct", "col_gram", "solve5", "col_solve", "row_idct")
 
@@ -105,6 +106,8 @@ def load() -> ctypes.CDLL:
     lib.ccmsav_elliptic_solve.argtypes = [vp, vp, vp, vp]
     lib.ccmsav_elliptic_solve_bc.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
     lib.ccmsav_elliptic_solve_noalloc.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp]
+    lib.ccmsav_pcg_config.argtypes = [vp, ctypes.c_double, ctypes.c_int32]
+    lib.ccmsav_pcg_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), dp]
     lib.ccmsav_smooth_ic.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp]
     lib.ccmsav_physical_energy.argtypes = [vp, dp]
     lib.ccmsav_physical_energy_m.argtypes = [vp, ctypes.c_int32, dp]
@@ -131,6 +134,7 @@ def load() -> ctypes.CDLL:
                "ccmsav_physical_energy", "ccmsav_physical_energy_m",
                "ccmsav_set_launch_variants", "ccmsav_elliptic_solve_bc",
                "ccmsav_elliptic_solve_noalloc", "ccmsav_profile_steps",
+               "ccmsav_pcg_config", "ccmsav_pcg_stats",
                "ccmsav_init_batch", "ccmsav_energy_m", "ccmsav_mass_m",
                "ccmsav_get_fields_m", "ccmsav_get_savs_m"):
         getattr(lib, fn).restype = ctypes.c_int
@@ -190,26 +194,28 @@ class Context:
     builds a context of several (each with its own parameters and grid).
     Member-indexed queries take ``member`` (default 0). ``bdf1=True`` takes
     every step with the first-order CC-MSAV-BDF1 scheme; ``periodic=True``
-    takes periodic boundaries (FP64, one member).
+    takes periodic boundaries (FP64, one member); ``classical=True`` the
+    classical MSAV scheme with its PCG solves (FP64, one member).
     """
 
     def __init__(self, params, phi0, psi0, precision="fp64", workspace=None,
                  stream=None, torch_workspace: bool = True, graph: bool = False,
-                 bdf1: bool = False, periodic: bool = False):
+                 bdf1: bool = False, periodic: bool = False, classical: bool = False):
         self._init([params], [phi0], [psi0], precision, workspace, stream, torch_workspace, graph,
-                   bdf1, periodic)
+                   bdf1, periodic, classical)
 
     @classmethod
     def ensemble(cls, params_list, phi0_list, psi0_list, precision="fp64", workspace=None,
                  stream=None, torch_workspace: bool = True, graph: bool = False,
-                 bdf1: bool = False) -> "Context":
+                 bdf1: bool = False, periodic: bool = False,
+                 classical: bool = False) -> "Context":
         self = cls.__new__(cls)
         self._init(list(params_list), list(phi0_list), list(psi0_list), precision, workspace,
-                   stream, torch_workspace, graph, bdf1)
+                   stream, torch_workspace, graph, bdf1, periodic, classical)
         return self
 
     def _init(self, params_list, phi0_list, psi0_list, precision, workspace, stream,
-              torch_workspace, graph, bdf1=False, periodic=False):
+              torch_workspace, graph, bdf1=False, periodic=False, classical=False):
         lib = load()
         self._h = None
         n = len(params_list)
@@ -217,7 +223,7 @@ class Context:
             raise ValueError("one parameter set and two initial fields per member")
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
         flags = ((FLAG_GRAPH if graph else 0) | (FLAG_BDF1 if bdf1 else 0)
-                 | (FLAG_PERIODIC if periodic else 0))
+                 | (FLAG_PERIODIC if periodic else 0) | (FLAG_CLASSICAL if classical else 0))
         self.params_list = [dict(p) for p in params_list]
         self.params = self.params_list[0]
         parr = (Params * n)(*[Params.from_dict(p, self.precision, flags) for p in params_list])
@@ -324,6 +330,17 @@ class Context:
         code = {"neumann": BC_NEUMANN, "dirichlet": BC_DIRICHLET, "periodic": BC_PERIODIC}[bc]
         _check(load().ccmsav_elliptic_solve_bc(self._h, code, _ptr(rhs), _ptr(out_chi),
                                                _ptr(out_zeta)), "ccmsav_elliptic_solve_bc")
+
+    def pcg_config(self, tol: float = 1e-12, max_iter: int = 40):
+        """Classical scheme: PCG stopping tolerance and iterations per step."""
+        _check(load().ccmsav_pcg_config(self._h, float(tol), int(max_iter)), "ccmsav_pcg_config")
+
+    def pcg_stats(self):
+        """Classical scheme: ([iterations], [relative residuals]) of the last step's two solves."""
+        it = (ctypes.c_int32 * 2)()
+        rr = (ctypes.c_double * 2)()
+        _check(load().ccmsav_pcg_stats(self._h, it, rr), "ccmsav_pcg_stats")
+        return list(it), list(rr)
 
     def set_launch_variants(self, row_dct: int = -1, col_solve: int = -1, row_idct: int = -1):
         """Fix the launch variants (0 or 1; -1 keeps the current choice)."""

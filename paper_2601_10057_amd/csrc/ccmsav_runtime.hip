@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "ccmsav.h"
+#include "classical_kernels.hpp"
 #include "diag_kernels.hpp"
 #include "gemm_dct.hpp"
 #include "gemm_mfma.hpp"
@@ -35,9 +36,14 @@ constexpr size_t kAlign = 256;
 constexpr int kNumPhases = 6;   // stencil, row DCT, column Gram, 5x5 solve, column solve, row IDCT
 constexpr int kMaxMembers = 4096;
 // Argument tables: 0 = level 0 (BDF1), 1 = level 1 (first BDF2 step, no
-// lagged ||d||^2), 2 + r = level n >= 2 with n % 3 == r; 5 = standalone solve.
-constexpr int kNumTables = 6;
+// lagged ||d||^2), 2 + r = level n >= 2 with n % 3 == r; 5 = standalone solve;
+// 6 = the classical scheme's preconditioner solve.
+constexpr int kNumTables = 7;
 constexpr int kSolveTable = 5;
+constexpr int kPcgTable = 6;
+// Classical scheme: default PCG tolerance (relative residual) and iterations.
+constexpr double kPcgTol = 1e-12;
+constexpr int kPcgMaxIter = 40;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr size_t align_up_c(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -89,11 +95,12 @@ template <typename TM> struct Launch {
     hipLaunchKernelGGL((k_row_idct<TM, N, V>), dim3(grid), dim3(row_idct_threads<TM>(N, V)), 0, st,
                        b.m, b.idx, b.per);
   }
-  using RD = void (*)(hipStream_t, int, const double*, TM*, int, int);
+  using RD = void (*)(hipStream_t, int, const double*, TM*, int, int, const int*);
   template <int N>
-  static void rd(hipStream_t st, int grid, const double* src, TM* mid, int slot, int ny) {
+  static void rd(hipStream_t st, int grid, const double* src, TM* mid, int slot, int ny,
+                 const int* skip) {
     hipLaunchKernelGGL((k_row_dct_field<TM, N>), dim3(grid), dim3(line_threads(N)), 0, st, src,
-                       mid, slot, ny);
+                       mid, slot, ny, skip);
   }
 
   template <int... L> struct Tables {
@@ -126,6 +133,7 @@ size_t gemm_gram_blocks(const ccmsav_params* p) {
   return (cells + per_block - 1) / per_block;
 }
 bool is_periodic(const ccmsav_params* p) { return (p->flags & CCMSAV_FLAG_PERIODIC) != 0; }
+bool is_classical(const ccmsav_params* p) { return (p->flags & CCMSAV_FLAG_CLASSICAL) != 0; }
 // Rows of inner-product partials: one per strip (spectral path), per block of
 // cells (DCT-as-GEMM) or per grid row (periodic step, physical space).
 size_t p2_rows(const ccmsav_params* p) {
@@ -137,6 +145,7 @@ struct Layout {
   size_t state, rm, mid, outc, part1, part2, parte, lamx, lamy, colsum, unit, ds;
   size_t dx, dy;   // GEMM variant: DCT matrix and its transpose per direction, bf16 hi and lo
   size_t psol;     // periodic step: chi^{-1} of S~, H, Q~, K~ (4 FP64 fields)
+  size_t cl, clpart, clsc;   // classical scheme: PCG fields, partial sums, scalars
   size_t total;
 };
 
@@ -168,6 +177,12 @@ Layout layout(const ccmsav_params* p) {
   if (is_periodic(p)) {
     L.psol = off;  off = align_up(off + 4 * cells * sizeof(double));
   }
+  if (is_classical(p)) {
+    // x, r, p (two buffers), q, z for both systems, and the two face mobilities
+    L.cl = off;     off = align_up(off + 14 * cells * sizeof(double));
+    L.clpart = off; off = align_up(off + (size_t)CL_BLOCKS * CL_NSUM * sizeof(double));
+    L.clsc = off;   off = align_up(off + sizeof(PcgScalars));
+  }
   L.total = off;
   return L;
 }
@@ -177,7 +192,8 @@ bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 
 int check_params(const ccmsav_params* p) {
   if (!p) return CCMSAV_EINVAL;
-  if ((p->flags & ~(CCMSAV_FLAG_GRAPH | CCMSAV_FLAG_BDF1 | CCMSAV_FLAG_PERIODIC)) != 0)
+  if ((p->flags & ~(CCMSAV_FLAG_GRAPH | CCMSAV_FLAG_BDF1 | CCMSAV_FLAG_PERIODIC |
+                     CCMSAV_FLAG_CLASSICAL)) != 0)
     return CCMSAV_EINVAL;
   if (p->precision != CCMSAV_FP64 && p->precision != CCMSAV_MIXED &&
       p->precision != CCMSAV_MIXED_GEMM_BF16X3)
@@ -191,6 +207,10 @@ int check_params(const ccmsav_params* p) {
   // the periodic step: FP64, the FFT solver's grids (up to 4096), no graph
   if (is_periodic(p) && (p->precision != CCMSAV_FP64 || lx > 12 || ly > 12 ||
                          (p->flags & CCMSAV_FLAG_GRAPH)))
+    return CCMSAV_EUNSUPPORTED;
+  // the classical scheme: FP64, Neumann boundaries, no graph
+  if (is_classical(p) && (p->precision != CCMSAV_FP64 || is_periodic(p) ||
+                          (p->flags & CCMSAV_FLAG_GRAPH)))
     return CCMSAV_EUNSUPPORTED;
   if (!finite_pos(p->h) || !finite_pos(p->dt) || !finite_pos(p->eps) || !finite_pos(p->M_phi))
     return CCMSAV_EINVAL;
@@ -214,7 +234,8 @@ int check_batch(int32_t nmemb, const ccmsav_params* p) {
     if (r != CCMSAV_OK) return r;
     if (p[m].precision != p[0].precision || p[m].flags != p[0].flags) return CCMSAV_EINVAL;
   }
-  if (nmemb > 1 && (is_gemm(p[0].precision) || is_periodic(&p[0]))) return CCMSAV_EUNSUPPORTED;
+  if (nmemb > 1 && (is_gemm(p[0].precision) || is_periodic(&p[0]) || is_classical(&p[0])))
+    return CCMSAV_EUNSUPPORTED;
   return CCMSAV_OK;
 }
 
@@ -287,6 +308,7 @@ StepConst make_const(const ccmsav_params& p, bool bdf2) {
   k.C1b = k.C1 - k.alpha;
   k.half_dt = 0.5 * p.dt;
   k.periodic = is_periodic(&p) ? 1 : 0;
+  k.classical = is_classical(&p) ? 1 : 0;
   return k;
 }
 
@@ -319,6 +341,7 @@ DiagConst make_diag(const ccmsav_params& p) {
 
 int status_from_err(int err) {
   if (err & ERR_NONFINITE) return CCMSAV_ENONFINITE;
+  if (err & ERR_PCG) return CCMSAV_ECONVERGE;
   if (err & (ERR_NORM | ERR_PIVOT)) return CCMSAV_EDOMAIN;
   return CCMSAV_OK;
 }
@@ -361,6 +384,17 @@ struct Member {
   uint16_t* dyt_lo;
   // periodic step: chi^{-1} of S~, H, Q~, K~
   double* psol;
+  // classical scheme: PCG fields (x, r, p0, p1, q, z; two systems each) and
+  // the face mobilities, partial sums, scalars
+  double* cl_x;
+  double* cl_r;
+  double* cl_p[2];
+  double* cl_q;
+  double* cl_z;
+  double* mob_e;
+  double* mob_n;
+  double* cl_part;
+  PcgScalars* cl_sc;
 };
 
 // Members with one grid shape; d_idx lists their indices in device memory.
@@ -382,6 +416,9 @@ struct ccmsav_ctx {
   bool graph = false;
   bool bdf1 = false;       // every step with the BDF1 scheme (CCMSAV_FLAG_BDF1)
   bool periodic = false;   // periodic boundaries (CCMSAV_FLAG_PERIODIC)
+  bool classical = false;  // classical MSAV scheme (CCMSAV_FLAG_CLASSICAL)
+  double pcg_tol = kPcgTol;
+  int pcg_max_iter = kPcgMaxIter;
   hipStream_t stream = nullptr;
   bool owns_ws = false;
   void* ws = nullptr;
@@ -417,9 +454,28 @@ MemberArgs member_args(const Member& m, int precision, int table) {
   a.ds = to_global(m.ds);
   a.nx = m.p.nx;
   a.ny = m.p.ny;
+  a.mob_e = to_global(m.mob_e);
+  a.mob_n = to_global(m.mob_n);
   a.iters = m.sh.iters;
   a.p1_blocks = m.sh.blocks;
   a.p2_rows = (int)p2_rows(&m.p);
+  if (table == kPcgTable) {
+    // The classical scheme's preconditioner alpha - lambda M_bar Delta_h for
+    // the residuals of both systems: slot M_F through the chi group and slot
+    // M_G through the zeta group, the constants written on the device each
+    // step (k_cl_setup), outputs z of system 0 and 1; the kernels return at
+    // once after both systems have converged.
+    a.k = make_const(m.p, true);
+    a.coef = to_global<const double>(m.unit_coef);
+    a.chi_base = M_F;
+    a.nchi = 1;
+    a.zeta_base = M_G;
+    a.nzeta = 1;
+    a.phi_new = to_global(m.cl_z);
+    a.psi_new = to_global(m.cl_z ? m.cl_z + (size_t)m.p.nx * m.p.ny : nullptr);
+    a.skip = to_global<const int>(m.cl_sc ? &m.cl_sc->done_all : nullptr);
+    return a;
+  }
   if (table == kSolveTable) {
     // chi^{-1} and zeta^{-1} of the single field in slot M_F (App. C).
     a.k = make_const(m.p, true);
@@ -514,6 +570,68 @@ void run_tuned(ccmsav_ctx* c, Tuner& tu, size_t ki, int t, hipStream_t st, F lau
     }
 }
 
+// The classical scheme's two variable-coefficient solves of one step (FP64,
+// one member), after the stencil pass has written g_lin (with lambda
+// div(M grad psi*)), L~, P~ and the face mobilities: the preconditioner's
+// constants, x = 0, r = b, z = P^{-1} r, then pcg_max_iter iterations of
+// {p = z + beta p, q = zeta p; a; x += a p, r -= a q; stop test; z = P^{-1} r;
+// (r, z), beta}, whose kernels return at once once both systems have met the
+// tolerance, and the inner products (P~, x_s) with the mean correction. The
+// intermediate fields serve as the preconditioner's scratch before the row
+// DCT of the step overwrites them.
+void enqueue_classical_solves(ccmsav_ctx* c, int table, hipStream_t st) {
+  const Member& m = c->mem[0];
+  const SizeClass& k = c->cls[0];
+  const int nx = m.p.nx, ny = m.p.ny;
+  const size_t n = (size_t)nx * ny;
+  const MemberArgs* pre = c->d_args + (size_t)kPcgTable * c->mem.size();
+  const StepConst& sc = c->h_args[(size_t)table * c->mem.size()].k;
+  double* rm = static_cast<double*>(m.rm);
+  const double* b = rm + (size_t)M_G * n;          // g_lin and L~ are consecutive slots
+  const int rows = CL_BLOCKS;
+  using LT = Launch<double>::T;
+  auto precondition = [&]() {
+    LT::t_rd[m.lx - kMinLog](st, ny, m.cl_r, static_cast<double*>(m.mid), M_F, ny,
+                             &m.cl_sc->done_all);
+    LT::t_rd[m.lx - kMinLog](st, ny, m.cl_r + n, static_cast<double*>(m.mid), M_G, ny,
+                             &m.cl_sc->done_all);
+    LT::t_col_solve[k.var[TUNE_COL_SOLVE]][m.ly - kMinLog](st, nx, Batch{pre, k.d_idx, nx});
+    const int vi = k.var[TUNE_ROW_IDCT];
+    const int per = ny / row_idct_rows<double>(nx, vi);
+    LT::t_row_idct[vi][m.lx - kMinLog](st, per, Batch{pre, k.d_idx, per});
+    hipLaunchKernelGGL(k_cl_dot_rz, dim3(CL_BLOCKS), dim3(CL_THREADS), 0, st, m.cl_r, m.cl_z,
+                       m.cl_part, n, m.cl_sc);
+    hipLaunchKernelGGL(k_cl_scalars<CL_RZ>, dim3(1), dim3(512), 0, st, m.cl_part, rows, m.cl_sc,
+                       m.ds, (double)n, 0);
+  };
+  hipLaunchKernelGGL(k_cl_setup, dim3(1), dim3(512), 0, st, m.part1, m.sh.blocks,
+                     const_cast<MemberArgs*>(pre), m.cl_sc, sc.alpha, m.p.lam, c->pcg_tol,
+                     (double)n);
+  hipLaunchKernelGGL(k_cl_start, dim3(CL_BLOCKS), dim3(CL_THREADS), 0, st, b, m.cl_x, m.cl_r,
+                     m.cl_part, n, m.cl_sc);
+  hipLaunchKernelGGL(k_cl_scalars<CL_INIT>, dim3(1), dim3(512), 0, st, m.cl_part, rows, m.cl_sc,
+                     m.ds, (double)n, 0);
+  precondition();
+  for (int it = 0; it < c->pcg_max_iter; ++it) {
+    double* p_old = m.cl_p[it & 1];
+    double* p_new = m.cl_p[(it + 1) & 1];
+    hipLaunchKernelGGL(k_cl_matvec, dim3(CL_BLOCKS), dim3(CL_THREADS), 0, st, m.cl_z, p_old,
+                       p_new, m.cl_q, m.mob_e, m.mob_n, nx, ny, 1.0 / (m.p.h * m.p.h), m.cl_part,
+                       m.cl_sc);
+    hipLaunchKernelGGL(k_cl_scalars<CL_PQ>, dim3(1), dim3(512), 0, st, m.cl_part, rows, m.cl_sc,
+                       m.ds, (double)n, 0);
+    hipLaunchKernelGGL(k_cl_update, dim3(CL_BLOCKS), dim3(CL_THREADS), 0, st, m.cl_x, m.cl_r,
+                       p_new, m.cl_q, m.cl_part, n, m.cl_sc);
+    hipLaunchKernelGGL(k_cl_scalars<CL_RR>, dim3(1), dim3(512), 0, st, m.cl_part, rows, m.cl_sc,
+                       m.ds, (double)n, it + 1 == c->pcg_max_iter ? 1 : 0);
+    if (it + 1 < c->pcg_max_iter) precondition();
+  }
+  hipLaunchKernelGGL(k_cl_gram, dim3(CL_BLOCKS), dim3(CL_THREADS), 0, st,
+                     rm + (size_t)M_P * n, m.cl_x, m.cl_part, n);
+  hipLaunchKernelGGL(k_cl_scalars<CL_FINAL>, dim3(1), dim3(512), 0, st, m.cl_part, rows, m.cl_sc,
+                     m.ds, (double)n, 0);
+}
+
 template <typename TM>
 void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe, Tuner& tu,
                        int only) {
@@ -528,6 +646,9 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe,
     const int total = k.count * k.sh.blocks;
     hipLaunchKernelGGL(k_stencil<TM>, dim3(stencil_grid(c, sizeof(TM) == 8, total)),
                        dim3(STENCIL_THREADS), 0, st, tab, k.d_idx, k.sh.blocks, total);
+  }
+  if constexpr (sizeof(TM) == 8) {
+    if (c->classical) enqueue_classical_solves(c, table, st);
   }
   pe.mark(1, st);
   pe.mark(2, st);
@@ -573,6 +694,14 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe,
       const int per = (1 << k.ly) / row_idct_rows<TM>(1 << k.lx, v);
       LT::t_row_idct[v][k.lx - kMinLog](st, k.count * per, Batch{tab, k.d_idx, per});
     });
+  }
+  if (c->classical) {
+    // psi^{n+1} from the iterative solves (the row inverse wrote the
+    // spectral zeta group's result, which the classical scheme does not use)
+    const Member& m = c->mem[0];
+    const int lv = (int)level_of_table(table);
+    hipLaunchKernelGGL(k_cl_combine, dim3(CL_BLOCKS), dim3(CL_THREADS), 0, st, m.cl_x, m.cl_sc,
+                       m.ds->coef, m.psi[(lv + 1) % 3], (size_t)m.p.nx * m.p.ny);
   }
   pe.mark(11, st);
 }
@@ -894,6 +1023,7 @@ const char* kStatusText[] = {
     "domain error (vanishing SAV normaliser, singular 5x5 system or non-positive mobility)",
     "non-finite value in the state",
     "unsupported grid size or precision mode",
+    "an iterative solve did not reach its tolerance",
 };
 
 }  // namespace
@@ -991,7 +1121,8 @@ void launch_solve(ccmsav_ctx* c, const double* rhs) {
   auto run = [&](auto tm) {
     using TM = decltype(tm);
     using LT = typename Launch<TM>::T;
-    LT::t_rd[m.lx - kMinLog](c->stream, m.p.ny, rhs, static_cast<TM*>(m.mid), M_F, m.p.ny);
+    LT::t_rd[m.lx - kMinLog](c->stream, m.p.ny, rhs, static_cast<TM*>(m.mid), M_F, m.p.ny,
+                             nullptr);
     LT::t_col_solve[k.var[TUNE_COL_SOLVE]][m.ly - kMinLog](c->stream, m.p.nx,
                                                            Batch{d, k.d_idx, m.p.nx});
     const int vi = k.var[TUNE_ROW_IDCT];
@@ -1126,6 +1257,7 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
   c->graph = (p[0].flags & CCMSAV_FLAG_GRAPH) != 0;
   c->bdf1 = (p[0].flags & CCMSAV_FLAG_BDF1) != 0;
   c->periodic = is_periodic(&p[0]);
+  c->classical = is_classical(&p[0]);
   c->tuned = c->periodic;  // the periodic step has no launch variants
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->owns_ws = workspace == nullptr;
@@ -1176,6 +1308,19 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
     m.unit_coef = reinterpret_cast<double*>(mb + L.unit);
     m.ds = reinterpret_cast<DevScalars*>(mb + L.ds);
     m.psol = is_periodic(&m.p) ? reinterpret_cast<double*>(mb + L.psol) : nullptr;
+    if (is_classical(&m.p)) {
+      double* f = reinterpret_cast<double*>(mb + L.cl);
+      m.cl_x = f;
+      m.cl_r = f + 2 * cells;
+      m.cl_p[0] = f + 4 * cells;
+      m.cl_p[1] = f + 6 * cells;
+      m.cl_q = f + 8 * cells;
+      m.cl_z = f + 10 * cells;
+      m.mob_e = f + 12 * cells;
+      m.mob_n = f + 13 * cells;
+      m.cl_part = reinterpret_cast<double*>(mb + L.clpart);
+      m.cl_sc = reinterpret_cast<PcgScalars*>(mb + L.clsc);
+    }
     if (is_gemm(m.p.precision)) {
       const size_t nxx = (size_t)m.p.nx * m.p.nx, nyy = (size_t)m.p.ny * m.p.ny;
       m.dx_hi = reinterpret_cast<uint16_t*>(mb + L.dx);
@@ -1358,7 +1503,7 @@ int32_t ccmsav_members(const ccmsav_ctx* c) { return c ? (int32_t)c->mem.size() 
 
 int ccmsav_energy_m(ccmsav_ctx* c, int32_t member, double* E_mod, double* parts) {
   if (!valid_member(c, member) || !E_mod) return CCMSAV_EINVAL;
-  if (c->bdf1) return CCMSAV_EUNSUPPORTED;
+  if (c->bdf1 || c->classical) return CCMSAV_EUNSUPPORTED;
   if (c->level < 1) return CCMSAV_EINVAL;
   int r = run_diag(c, member, true);
   if (r != CCMSAV_OK) return r;
@@ -1644,7 +1789,7 @@ int ccmsav_elliptic_solve_noalloc(const ccmsav_params* p, const double* rhs, dou
   auto run = [&](auto tm) {
     using TM = decltype(tm);
     using LT = typename Launch<TM>::T;
-    LT::t_rd[lx - kMinLog](st, ny, rhs, static_cast<TM*>(m.mid), M_F, ny);
+    LT::t_rd[lx - kMinLog](st, ny, rhs, static_cast<TM*>(m.mid), M_F, ny, nullptr);
     LT::t_col_solve[0][ly - kMinLog](st, nx, Batch{d_args, d_idx, nx});
     const int per = ny / row_idct_rows<TM>(nx, 0);
     LT::t_row_idct[0][lx - kMinLog](st, per, Batch{d_args, d_idx, per});
@@ -1656,6 +1801,28 @@ int ccmsav_elliptic_solve_noalloc(const ccmsav_params* p, const double* rhs, dou
   return hipGetLastError() == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
 }
 
+int ccmsav_pcg_config(ccmsav_ctx* c, double tol, int32_t max_iter) {
+  if (!c || !c->classical) return c ? CCMSAV_EUNSUPPORTED : CCMSAV_EINVAL;
+  if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 1 || max_iter > 10000)
+    return CCMSAV_EINVAL;
+  c->pcg_tol = tol;
+  c->pcg_max_iter = max_iter;
+  return CCMSAV_OK;
+}
+
+int ccmsav_pcg_stats(ccmsav_ctx* c, int32_t iters[2], double rel_residual[2]) {
+  if (!c || !iters || !rel_residual) return CCMSAV_EINVAL;
+  if (!c->classical) return CCMSAV_EUNSUPPORTED;
+  PcgScalars sc{};
+  HIP_TRY(hipMemcpyAsync(&sc, c->mem[0].cl_sc, sizeof(sc), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int s = 0; s < 2; ++s) {
+    iters[s] = sc.iters[s];
+    rel_residual[s] = sc.bnorm2[s] > 0.0 ? std::sqrt(sc.rnorm2[s] / sc.bnorm2[s]) : 0.0;
+  }
+  return CCMSAV_OK;
+}
+
 int ccmsav_destroy(ccmsav_ctx* c) {
   if (!c) return CCMSAV_EINVAL;
   (void)hipStreamSynchronize(c->stream);
@@ -1665,7 +1832,7 @@ int ccmsav_destroy(ccmsav_ctx* c) {
 }
 
 const char* ccmsav_strerror(int code) {
-  if (code > 0 || code < CCMSAV_EUNSUPPORTED) return "unknown status";
+  if (code > 0 || code < CCMSAV_ECONVERGE) return "unknown status";
   return kStatusText[-code];
 }
 

@@ -22,6 +22,7 @@ enum P1Sum {
   P1_XQ,
   P1_XK,
   P1_XP,          // increment form only: sum P~ psi^n
+  P1_MBAR,        // sum M_psi(phi*) over the cells (classical scheme's preconditioner)
   P1_NSUM
 };
 
@@ -60,6 +61,7 @@ enum ErrBits {
   ERR_NORM = 2,        // a SAV normaliser r^2 <= tiny
   ERR_PIVOT = 4,       // singular 5x5 system
   ERR_MOBILITY = 8,    // a face mobility <= 0 (energy undefined)
+  ERR_PCG = 16,        // the classical scheme's PCG did not reach its tolerance
 };
 
 // Device-resident scalar state. Everything the time loop needs lives here so
@@ -71,6 +73,7 @@ struct DevScalars {
   double diag[40];       // last step: s (4), norms r_S r_W r_Z, x (5), M (25), b... see runtime
   double energy[12];     // last energy query: E, then parts
   double totals[16];     // last reduction totals
+  double cl[2];          // classical scheme: (P~, zeta^{-1} g), (P~, zeta^{-1} L~)
   int err;
   int pad[3];
 };
@@ -93,6 +96,7 @@ struct StepConst {
   int lag_d;             // accumulate ||d^n||^2 of the previous (BDF2) step
   int slot_n, slot_m, slot_new;   // SAV ring slots of levels n, n-1, n+1
   int periodic;          // wrap-around ghosts (periodic boundaries), else Neumann
+  int classical;         // classical MSAV scheme: lambda div(M grad psi*) in g_lin
 };
 
 // Pointer into global memory. The kernels read their pointers from tables in
@@ -156,6 +160,9 @@ struct MemberArgs {
   gptr<double> colsum;           // increment form: row-sum targets of the psi increment
   gptr<DevScalars> ds;
   gptr<const double> coef;       // spectral combination (ds->coef, or unit weights)
+  gptr<double> mob_e;            // classical scheme: M_psi at the east and north face
+  gptr<double> mob_n;            //   of each cell (0 on the walls), written by the stencil
+  gptr<const int> skip;          // solve kernels return at once while *skip != 0
   int nx, ny;
   int iters, p1_blocks;          // stencil launch shape
   int p2_rows;                   // rows of column partial sums

@@ -246,7 +246,8 @@ inline StencilShape stencil_shape(int nx, int ny) {
 template <typename TM>
 __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restrict__ rm,
                                              gptr<double> __restrict__ part, int nx, int ny,
-                                             int iters, const StepConst& c, int blk) {
+                                             int iters, const StepConst& c, int blk,
+                                             gptr<double> mob_e, gptr<double> mob_n) {
   constexpr bool INC = increment_form<TM>();
   __shared__ double red[P1_NSUM * (STENCIL_THREADS / 64 + 1)];
   const int tid = threadIdx.x;
@@ -385,9 +386,19 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
       const double lap_dq = (dqe + dqw + rn.dq + rs.dq - 4.0 * rc.dq) * c.inv_h2;
       out[M_G] = -c.a1 * rc.dq - c.lam * (c.x0 - 1.0) * lap_dq;
     } else {
-      const double lap_q = (qe + qw + rn.q + rs.q - 4.0 * rc.q) * c.inv_h2;
       out[M_F] = c.a0 * rc.phn + c.a1 * rc.phm - c.M_phi * c.theta_t * lap_p;
-      out[M_G] = c.a0 * rc.psn + c.a1 * rc.psm - c.lam * lap_q;
+      double stab;
+      if (c.classical) {
+        // classical scheme (App. B remarks): lambda div(M_psi(phi*) grad psi*)
+        const double me = mobility(0.5 * (rc.p + pe), c.M0), mw = mobility(0.5 * (pw + rc.p), c.M0);
+        const double mn = mobility(0.5 * (rc.p + rn.p), c.M0);
+        const double ms = mobility(0.5 * (rs.p + rc.p), c.M0);
+        stab = (me * (qe - rc.q) - mw * (rc.q - qw) + mn * (rn.q - rc.q) - ms * (rc.q - rs.q)) *
+               c.inv_h2;
+      } else {
+        stab = (qe + qw + rn.q + rs.q - 4.0 * rc.q) * c.inv_h2;
+      }
+      out[M_G] = c.a0 * rc.psn + c.a1 * rc.psm - c.lam * stab;
     }
     const double St = pc * (pc2 - 1.0 - c.beta) * 0.5 * ieps;
     const double Hf = k32 * (cubic * ieps - c.eps * lap_p);
@@ -433,6 +444,11 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
       const bool face_e = per || ci < nx - 1, face_n = per || j < ny - 1;
       if (face_e && !(Me > 0.0)) sums[P1_MOBNEG] += 1.0;
       if (face_n && !(Mn > 0.0)) sums[P1_MOBNEG] += 1.0;
+      if (c.classical) {
+        sums[P1_MBAR] += mobility(pc, c.M0);
+        mob_e[o] = face_e ? Me : 0.0;
+        mob_n[o] = face_n ? Mn : 0.0;
+      }
       if (c.lag_d) {
         // ||d^n||^2 of the previous step over the east and north faces
         if (face_e) {
@@ -1046,6 +1062,12 @@ __device__ __forceinline__ void solve_body(gptr<const double> __restrict__ p1, i
     M[i][4] = c.cgo * G[i][3];
     b[i] = bi;
   }
+  if (c.classical) {
+    // the classical scheme's zeta is not diagonal in the DCT basis: its two
+    // inner products come from the iterative solves, in physical space
+    T2[P2_PG] = ds->cl[0];
+    T2[P2_PL] = ds->cl[1];
+  }
   const double PL = h2 * nK * nK * T2[P2_PL];
   M[4][0] = M[4][1] = M[4][2] = 0.0;
   M[4][3] = -PL;
@@ -1492,7 +1514,9 @@ __device__ __forceinline__ void row_idct_band_body(gptr<const TM> __restrict__ o
 // ---------------------------------------------------------------------------
 template <typename TM, int NX>
 __global__ void __launch_bounds__(line_threads(NX))
-k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, int ny) {
+k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, int ny,
+                const int* __restrict__ skip) {
+  if (skip && *skip) return;     // a converged iteration (whole workgroup)
   constexpr int NTHR = line_threads(NX);
   constexpr int CPT = NX >= NTHR ? NX / NTHR : 1;
   constexpr int UPT = NX / 2 >= NTHR ? NX / 2 / NTHR : 1;
@@ -1568,7 +1592,8 @@ __global__ void __launch_bounds__(STENCIL_THREADS) k_stencil(BATCH_PARAMS, int t
     const int blk = vb % per;
     const MemberArgs& m = tab[idx[vb / per]];
     const RowArgs a{m.phn, m.phm, m.phmm, m.psn, m.psm, m.psmm};
-    stencil_body<TM>(a, static_cast<gptr<TM>>(m.rm), m.part1, m.nx, m.ny, m.iters, m.k, blk);
+    stencil_body<TM>(a, static_cast<gptr<TM>>(m.rm), m.part1, m.nx, m.ny, m.iters, m.k, blk,
+                     m.mob_e, m.mob_n);
   }
 }
 
@@ -1577,7 +1602,7 @@ __global__ void __launch_bounds__(line_threads(NX)) k_row_dct8(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
   row_dct8_body<TM, NX, V>(static_cast<gptr<const TM>>(m.rm), static_cast<gptr<TM>>(m.mid), m.ny,
-                        blk);
+                           blk);
 }
 
 template <typename TM, int NY>
@@ -1598,6 +1623,7 @@ template <typename TM, int NY, int V>
 __global__ void __launch_bounds__(line_threads_v<TM>(NY, V)) k_col_solve(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
+  if (m.skip && *m.skip) return;     // a converged iteration (whole workgroup)
   const OpConst o{m.k.C1, m.k.C2, m.k.C3, m.k.alpha, m.k.lam};
   col_solve_body<TM, NY, line_threads_v<TM>(NY, V)>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.coef,
                          static_cast<gptr<TM>>(m.outc), m.nx, m.chi_base, m.nchi, m.zeta_base,
@@ -1612,6 +1638,7 @@ __global__ void __launch_bounds__(row_idct_threads<TM>(NX, V),
 k_row_idct(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
+  if (m.skip && *m.skip) return;     // a converged iteration (whole workgroup)
   if constexpr (V == 0) {
     row_idct_band_body<TM, NX>(static_cast<gptr<const TM>>(m.outc), m.phi_new, m.psi_new, m.ny,
                                m.phi_base, m.psi_base, m.colsum, blk);

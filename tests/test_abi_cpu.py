@@ -87,7 +87,7 @@ def test_init_rejects_null_and_unknown_modes():
     buf = (ctypes.c_double * 4)()
     assert lib.ccmsav_init(ctypes.byref(h), ctypes.byref(p), buf, buf, None, 0, None) == -6
     p.precision = 0
-    p.flags = 8          # no such flag
+    p.flags = 16         # no such flag
     assert lib.ccmsav_init(ctypes.byref(h), ctypes.byref(p), buf, buf, None, 0, None) == -1
     # the periodic step: FP64 only, no graph, grids up to 4096, one member
     for prec, flags, n in ((C.MIXED, C.FLAG_PERIODIC, 64), (C.FP64, C.FLAG_PERIODIC | C.FLAG_GRAPH, 64),
@@ -101,6 +101,18 @@ def test_init_rejects_null_and_unknown_modes():
     assert lib.ccmsav_workspace_bytes(ctypes.byref(q)) > lib.ccmsav_workspace_bytes(ctypes.byref(p))
     pair = (C.Params * 2)(q, q)
     assert lib.ccmsav_workspace_bytes_batch(2, pair) == 0
+    # the classical scheme: FP64 only, Neumann, no graph, one member
+    for prec, flags in ((C.MIXED, C.FLAG_CLASSICAL), (C.FP64, C.FLAG_CLASSICAL | C.FLAG_GRAPH),
+                        (C.FP64, C.FLAG_CLASSICAL | C.FLAG_PERIODIC)):
+        q = _params()
+        q.precision, q.flags = prec, flags
+        assert lib.ccmsav_init(ctypes.byref(h), ctypes.byref(q), buf, buf, None, 0, None) == -6
+    q = _params()
+    q.flags = C.FLAG_CLASSICAL
+    assert lib.ccmsav_workspace_bytes(ctypes.byref(q)) > lib.ccmsav_workspace_bytes(ctypes.byref(p))
+    assert lib.ccmsav_workspace_bytes_batch(2, (C.Params * 2)(q, q)) == 0
+    assert lib.ccmsav_pcg_config(None, 1e-10, 10) == -1
+    assert C.strerror(-7).startswith("an iterative solve")
     assert lib.ccmsav_step(None, 1) == -1
     assert lib.ccmsav_destroy(None) == -1
     assert C.strerror(-6).startswith("unsupported")
