@@ -171,6 +171,46 @@ def test_bench_grid_first_step_matches_oracle():
     assert rel_linf(got[2], st.sav) <= 1e-12
 
 
+def test_vesicle1024_workload_matches_stored_oracle_trajectory():
+    """The N = 1024 workload (seed 10057), 1000 FP64 steps in the benchmark's
+    launch configuration, against the oracle trajectory that
+    tests/golden/make_vesicle1024_golden.py stores (it calls only the oracle):
+    every eighth cell of phi and psi, the SAVs at levels n and n-1, the mass and
+    the modified energy at steps 1, 2, 250, 500 and 1000. Bound: max(1e-12,
+    10 x the stored envelope) for the fields, SAVs and mass, where the envelope
+    is the largest spread from the stored run of oracle runs that round
+    differently: the DCT written out as the cosine-matrix product instead of
+    scipy's FFT-based DCT (1.7e-11 at step 1000, the largest), and one-ulp
+    perturbations at the start or after every step; the library's own mass
+    drift within 5e-11; E_mod within 1e-10 (it squares Laplacians of the
+    fields, which amplify a field difference by up to 8 / h^2 against
+    1 / eps^2)."""
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "vesicle1024_oracle.npz"))
+    m = make_workload("vesicle1024")[0]
+    note("vesicle1024 fp64, 1000 steps against the stored oracle trajectory")
+    done = 0
+    with C.Context(m.params, m.phi0, m.psi0) as ctx:
+        m0 = ctx.mass()[0]
+        for k in (1, 2, 250, 500, 1000):
+            ctx.step(k - done)
+            done = k
+            phi, psi = ctx.fields()
+            s1, s0 = ctx.savs()
+            tol = max(1e-12, 10.0 * float(g[f"k{k}_env"].max()))
+            errs = (rel_linf(phi[::8, ::8], g[f"k{k}_phi"]), rel_linf(psi[::8, ::8], g[f"k{k}_psi"]),
+                    rel_linf(s1, g[f"k{k}_sav"]), rel_linf(s0, g[f"k{k}_sav_prev"]))
+            e = ctx.energy()
+            e_ref = float(g[f"k{k}_energy"])
+            note(f"  step {k}: fields/SAVs {max(errs):.2e} (bound {tol:.1e}), "
+                 f"E_mod {abs(e - e_ref) / abs(e_ref):.2e}")
+            assert max(errs) <= tol, (k, errs, tol)
+            mass = ctx.mass()[0]
+            assert abs(mass - float(g[f"k{k}_mass"])) <= tol * abs(mass)
+            assert abs(mass - m0) <= 5e-11 * abs(m0)
+            assert abs(e - e_ref) <= 1e-10 * abs(e_ref), (k, e, e_ref)
+
+
 # ------------------------------------------------------------------ error paths
 
 def test_degenerate_inputs_report_domain_errors():
