@@ -373,7 +373,7 @@ def cpu_baseline(members, budget_s: float = 12.0):
 
 
 def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, graph,
-              bdf1=False, classical=False, periodic=False):
+              bdf1=False, classical=False, periodic=False, persistent=False):
     """Warm up, time ``steps`` steps between two synchronisations, then take
     ``profile_steps`` more with per-kernel events. Returns timings and the
     final states (after warmup + steps + profile_steps steps)."""
@@ -382,7 +382,7 @@ def timed_run(C, torch, members, precision, steps, warmup, profile_steps, dev, g
     stream = torch.cuda.current_stream(dev)
     ctx = C.Context.ensemble([m.params for m in members], phi0, psi0, precision,
                              stream=stream.cuda_stream, graph=graph, bdf1=bdf1,
-                             classical=classical, periodic=periodic)
+                             classical=classical, periodic=periodic, persistent=persistent)
     nm = len(members)
     mass0 = [ctx.mass(i)[0] for i in range(nm)]
     ctx.step(warmup)
@@ -493,6 +493,12 @@ def main():
                     help="time-stepping scheme: CC-MSAV-BDF2 (the default), the "
                          "first-order CC-MSAV-BDF1 scheme at every step, or the classical "
                          "MSAV scheme with its PCG solves (FP64)")
+    ap.add_argument("--persistent", action="store_true",
+                    help="every step as one persistent kernel launch (mixed precision, grids "
+                         "of 64 to 512)")
+    ap.add_argument("--compare-persistent", action="store_true",
+                    help="also time the persistent launch on the same workload and check that "
+                         "its states equal the timed run's bit for bit")
     ap.add_argument("--periodic", action="store_true",
                     help="periodic boundaries (FP64 step with FFT solves)")
     ap.add_argument("--compare-classical", action="store_true",
@@ -559,7 +565,8 @@ def main():
     if classical or args.periodic:
         args.precision = "fp64"
     run = timed_run(C, torch, members, args.precision, args.steps, args.warmup,
-                    args.profile_steps, dev, args.graph, bdf1, classical, args.periodic)
+                    args.profile_steps, dev, args.graph, bdf1, classical, args.periodic,
+                    args.persistent)
     wall = run["wall"]
     ms_per_step = 1e3 * wall / args.steps
     value = cells * args.steps / wall / 1e6
@@ -587,7 +594,7 @@ def main():
                     "traffic": None, "flops_per_launch": fl[dom], "us_per_launch": prof[dom] * 1e3,
                     "step_flops": sum(fl.values()),
                     "step_frac": sum(fl.values()) / (ms_per_step * 1e-3) / 1e12 / BF16_PEAK_TFLOPS}
-    elif prof and not (classical or args.periodic):
+    elif prof and not (classical or args.periodic or args.persistent):
         # The dominant pass of the pipeline model, by its launches' mean
         # durations on the library's stream (HIP events); P1 is the stencil
         # launch plus the row DCT launch.
@@ -650,6 +657,21 @@ def main():
               f"{cl_value:.1f} Mcell-steps/s, iterations {cl['pcg'][0]}; this path / classical = "
               f"{compare['speedup_vs_classical']:.2f}", file=sys.stderr, flush=True)
 
+    if args.compare_persistent and not args.persistent:
+        ps = timed_run(C, torch, members, args.precision, args.steps, args.warmup,
+                       args.profile_steps, dev, args.graph, bdf1, False, False, True)
+        same = all(np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+                   for a, b in zip(ps["fields"], run["fields"])) and all(
+            np.array_equal(a, b) for a, b in zip(ps["savs"], run["savs"]))
+        ps_value = cells * args.steps / ps["wall"] / 1e6
+        compare = dict(compare or {}, persistent_value=ps_value,
+                       persistent_ms_per_step=1e3 * ps["wall"] / args.steps,
+                       persistent_bit_identical=bool(same),
+                       persistent_vs_this=ps_value / value)
+        print(f"[bench] persistent launch: {compare['persistent_ms_per_step']:.4f} ms/step, "
+              f"{ps_value:.1f} Mcell-steps/s, bit-identical {same}; persistent / this = "
+              f"{compare['persistent_vs_this']:.3f}", file=sys.stderr, flush=True)
+
     if args.copy_probe_mib > 0:
         a = torch.empty(args.copy_probe_mib * 2 ** 18, dtype=torch.float32, device=dev).fill_(1.0)
         b = torch.empty_like(a)
@@ -663,6 +685,7 @@ def main():
               "grids": sorted({(m.params["nx"], m.params["ny"]) for m in members}),
               "precision": args.precision, "graph": args.graph, "scheme": args.scheme,
               "boundaries": "periodic" if args.periodic else "neumann",
+              "launch": "persistent" if args.persistent else "per-pass",
               "dt": sorted({m.params["dt"] for m in members}),
               "eps_cells": sorted({m.meta.get("eps_cells", 4.0) for m in members})}
     if len(members) == 1:

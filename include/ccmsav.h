@@ -46,8 +46,13 @@ typedef enum {
                                face mobility M_psi <= 0 (energy undefined) */
   CCMSAV_ENONFINITE = -5,   /* NaN or Inf in the state or the SAVs */
   CCMSAV_EUNSUPPORTED = -6, /* grid size or precision mode not provided */
-  CCMSAV_ECONVERGE = -7     /* an iterative solve (CCMSAV_FLAG_CLASSICAL) did not
+  CCMSAV_ECONVERGE = -7,    /* an iterative solve (CCMSAV_FLAG_CLASSICAL) did not
                                reach its tolerance within its iterations */
+  CCMSAV_EBARRIER = -8      /* a grid-wide barrier of the persistent step launch
+                               (CCMSAV_FLAG_PERSISTENT) failed (a wait timed out,
+                               or the waves of a workgroup left it out of step):
+                               the step was abandoned and the context must be
+                               destroyed */
 } ccmsav_status;
 
 typedef enum {
@@ -87,7 +92,7 @@ typedef enum {
  *  beta         linear SAV splitting constant                         (Sec. 2.2)
  *  precision    a ccmsav_precision value
  *  flags        0 or CCMSAV_FLAG_GRAPH, CCMSAV_FLAG_BDF1, CCMSAV_FLAG_PERIODIC,
- *               CCMSAV_FLAG_CLASSICAL
+ *               CCMSAV_FLAG_CLASSICAL, CCMSAV_FLAG_PERSISTENT
  */
 typedef struct {
   int32_t nx, ny;
@@ -140,6 +145,21 @@ typedef struct {
  * (ECONVERGE). ccmsav_energy returns EUNSUPPORTED (E^{n,n-1}_mod with the
  * lambda dissipation sum is the CC-MSAV energy). */
 #define CCMSAV_FLAG_CLASSICAL 8
+
+/* flags: every step of the context (Algorithm 1 of App. B with the
+ * transforms of App. C, for all members) as ONE persistent kernel launch:
+ * the stencil, row DCT, column Gram, 5x5, column solve and row inverse passes
+ * run one after the other inside it, separated by grid-wide barriers, on a
+ * grid of as many workgroups as the GPU holds at once. The passes are the
+ * same computations with the same thread counts as the default launches,
+ * and give bit-identical results. A barrier wait that exceeds its spin limit
+ * (ccmsav_set_spin_limit; a grid that is not all resident, e.g. beside other
+ * work on the GPU) ends every workgroup and is reported as EBARRIER.
+ * CCMSAV_MIXED only, Neumann boundaries, the CC-MSAV scheme, grids of 64 to
+ * 512 per direction (else EUNSUPPORTED); combines with CCMSAV_FLAG_GRAPH
+ * (a graph of three launches) and CCMSAV_FLAG_BDF1. ccmsav_profile_steps
+ * reports the whole step as its first phase. */
+#define CCMSAV_FLAG_PERSISTENT 16
 
 /* Device workspace bytes a context needs for these parameters (0 if the
  * parameters are invalid or unsupported). */
@@ -377,6 +397,15 @@ int ccmsav_pcg_config(ccmsav_ctx* c, double tol, int32_t max_iter);
  * another scheme.
  */
 int ccmsav_pcg_stats(ccmsav_ctx* c, int32_t iters[2], double rel_residual[2]);
+
+/*
+ * Persistent launch (CCMSAV_FLAG_PERSISTENT): the number of polls (each
+ * about a hundred cycles) a workgroup waits at a grid barrier before giving
+ * up; 0 gives up at once unless the workgroup arrives last (a way to test
+ * the failure path: every kernel still ends normally). Default 1 << 22.
+ * Applies from the next step. EUNSUPPORTED for another context.
+ */
+int ccmsav_set_spin_limit(ccmsav_ctx* c, uint32_t polls);
 
 /* Release the context (and the workspace if the library allocated it). */
 int ccmsav_destroy(ccmsav_ctx* c);

@@ -22,12 +22,13 @@ MIXED_GEMM_BF16X3 = 2
 PRECISIONS = {"fp64": FP64, "mixed": MIXED, "gemm": MIXED_GEMM_BF16X3}
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "EDOMAIN",
-          -5: "ENONFINITE", -6: "EUNSUPPORTED", -7: "ECONVERGE"}
+          -5: "ENONFINITE", -6: "EUNSUPPORTED", -7: "ECONVERGE", -8: "EBARRIER"}
 
 FLAG_GRAPH = 1
 FLAG_BDF1 = 2
 FLAG_PERIODIC = 4
 FLAG_CLASSICAL = 8
+FLAG_PERSISTENT = 16
 BC_NEUMANN, BC_DIRICHLET, BC_PERIODIC = 0, 1, 2
 
 EXPORTED = (
@@ -39,6 +40,7 @@ EXPORTED = (
     "ccmsav_get_savs_m", "ccmsav_tuning", "ccmsav_smooth_ic", "ccmsav_physical_energy",
     "ccmsav_physical_energy_m", "ccmsav_set_launch_variants", "ccmsav_elliptic_solve_bc",
     "ccmsav_elliptic_solve_noalloc", "ccmsav_pcg_config", "ccmsav_pcg_stats",
+    "ccmsav_set_spin_limit",
 )
 PHASES = ("stencil", "row_dct", "col_gram", "solve5", "col_solve", "row_idct")
 
@@ -108,6 +110,7 @@ def load() -> ctypes.CDLL:
     lib.ccmsav_elliptic_solve_noalloc.argtypes = [ctypes.POINTER(Params), vp, vp, vp, vp]
     lib.ccmsav_pcg_config.argtypes = [vp, ctypes.c_double, ctypes.c_int32]
     lib.ccmsav_pcg_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), dp]
+    lib.ccmsav_set_spin_limit.argtypes = [vp, ctypes.c_uint32]
     lib.ccmsav_smooth_ic.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int32, vp, vp]
     lib.ccmsav_physical_energy.argtypes = [vp, dp]
     lib.ccmsav_physical_energy_m.argtypes = [vp, ctypes.c_int32, dp]
@@ -134,7 +137,7 @@ def load() -> ctypes.CDLL:
                "ccmsav_physical_energy", "ccmsav_physical_energy_m",
                "ccmsav_set_launch_variants", "ccmsav_elliptic_solve_bc",
                "ccmsav_elliptic_solve_noalloc", "ccmsav_profile_steps",
-               "ccmsav_pcg_config", "ccmsav_pcg_stats",
+               "ccmsav_pcg_config", "ccmsav_pcg_stats", "ccmsav_set_spin_limit",
                "ccmsav_init_batch", "ccmsav_energy_m", "ccmsav_mass_m",
                "ccmsav_get_fields_m", "ccmsav_get_savs_m"):
         getattr(lib, fn).restype = ctypes.c_int
@@ -195,27 +198,31 @@ class Context:
     Member-indexed queries take ``member`` (default 0). ``bdf1=True`` takes
     every step with the first-order CC-MSAV-BDF1 scheme; ``periodic=True``
     takes periodic boundaries (FP64, one member); ``classical=True`` the
-    classical MSAV scheme with its PCG solves (FP64, one member).
+    classical MSAV scheme with its PCG solves (FP64, one member);
+    ``persistent=True`` runs every step as one persistent kernel launch
+    (mixed precision, grids of 64 to 512).
     """
 
     def __init__(self, params, phi0, psi0, precision="fp64", workspace=None,
                  stream=None, torch_workspace: bool = True, graph: bool = False,
-                 bdf1: bool = False, periodic: bool = False, classical: bool = False):
+                 bdf1: bool = False, periodic: bool = False, classical: bool = False,
+                 persistent: bool = False):
         self._init([params], [phi0], [psi0], precision, workspace, stream, torch_workspace, graph,
-                   bdf1, periodic, classical)
+                   bdf1, periodic, classical, persistent)
 
     @classmethod
     def ensemble(cls, params_list, phi0_list, psi0_list, precision="fp64", workspace=None,
                  stream=None, torch_workspace: bool = True, graph: bool = False,
                  bdf1: bool = False, periodic: bool = False,
-                 classical: bool = False) -> "Context":
+                 classical: bool = False, persistent: bool = False) -> "Context":
         self = cls.__new__(cls)
         self._init(list(params_list), list(phi0_list), list(psi0_list), precision, workspace,
-                   stream, torch_workspace, graph, bdf1, periodic, classical)
+                   stream, torch_workspace, graph, bdf1, periodic, classical, persistent)
         return self
 
     def _init(self, params_list, phi0_list, psi0_list, precision, workspace, stream,
-              torch_workspace, graph, bdf1=False, periodic=False, classical=False):
+              torch_workspace, graph, bdf1=False, periodic=False, classical=False,
+              persistent=False):
         lib = load()
         self._h = None
         n = len(params_list)
@@ -223,7 +230,8 @@ class Context:
             raise ValueError("one parameter set and two initial fields per member")
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
         flags = ((FLAG_GRAPH if graph else 0) | (FLAG_BDF1 if bdf1 else 0)
-                 | (FLAG_PERIODIC if periodic else 0) | (FLAG_CLASSICAL if classical else 0))
+                 | (FLAG_PERIODIC if periodic else 0) | (FLAG_CLASSICAL if classical else 0)
+                 | (FLAG_PERSISTENT if persistent else 0))
         self.params_list = [dict(p) for p in params_list]
         self.params = self.params_list[0]
         parr = (Params * n)(*[Params.from_dict(p, self.precision, flags) for p in params_list])
@@ -334,6 +342,11 @@ class Context:
     def pcg_config(self, tol: float = 1e-12, max_iter: int = 40):
         """Classical scheme: PCG stopping tolerance and iterations per step."""
         _check(load().ccmsav_pcg_config(self._h, float(tol), int(max_iter)), "ccmsav_pcg_config")
+
+    def set_spin_limit(self, polls: int):
+        """Persistent launch: polls a workgroup waits at a grid barrier before
+        giving up (EBARRIER at the next synchronising call)."""
+        _check(load().ccmsav_set_spin_limit(self._h, int(polls)), "ccmsav_set_spin_limit")
 
     def pcg_stats(self):
         """Classical scheme: ([iterations], [relative residuals]) of the last step's two solves."""

@@ -22,6 +22,7 @@
 #include "diag_kernels.hpp"
 #include "gemm_dct.hpp"
 #include "gemm_mfma.hpp"
+#include "persist_kernels.hpp"
 #include "periodic_kernels.hpp"
 #include "smooth_kernels.hpp"
 #include "step_kernels.hpp"
@@ -134,6 +135,7 @@ size_t gemm_gram_blocks(const ccmsav_params* p) {
 }
 bool is_periodic(const ccmsav_params* p) { return (p->flags & CCMSAV_FLAG_PERIODIC) != 0; }
 bool is_classical(const ccmsav_params* p) { return (p->flags & CCMSAV_FLAG_CLASSICAL) != 0; }
+bool is_persistent(const ccmsav_params* p) { return (p->flags & CCMSAV_FLAG_PERSISTENT) != 0; }
 // Rows of inner-product partials: one per strip (spectral path), per block of
 // cells (DCT-as-GEMM) or per grid row (periodic step, physical space).
 size_t p2_rows(const ccmsav_params* p) {
@@ -193,7 +195,7 @@ bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 int check_params(const ccmsav_params* p) {
   if (!p) return CCMSAV_EINVAL;
   if ((p->flags & ~(CCMSAV_FLAG_GRAPH | CCMSAV_FLAG_BDF1 | CCMSAV_FLAG_PERIODIC |
-                     CCMSAV_FLAG_CLASSICAL)) != 0)
+                     CCMSAV_FLAG_CLASSICAL | CCMSAV_FLAG_PERSISTENT)) != 0)
     return CCMSAV_EINVAL;
   if (p->precision != CCMSAV_FP64 && p->precision != CCMSAV_MIXED &&
       p->precision != CCMSAV_MIXED_GEMM_BF16X3)
@@ -211,6 +213,12 @@ int check_params(const ccmsav_params* p) {
   // the classical scheme: FP64, Neumann boundaries, no graph
   if (is_classical(p) && (p->precision != CCMSAV_FP64 || is_periodic(p) ||
                           (p->flags & CCMSAV_FLAG_GRAPH)))
+    return CCMSAV_EUNSUPPORTED;
+  // the persistent launch: FP32 transforms, the CC-MSAV Neumann step, the
+  // grid sizes its kernel is built for
+  if (is_persistent(p) && (p->precision != CCMSAV_MIXED || is_periodic(p) || is_classical(p) ||
+                           lx < PS_MIN_LOG || lx > PS_MAX_LOG || ly < PS_MIN_LOG ||
+                           ly > PS_MAX_LOG))
     return CCMSAV_EUNSUPPORTED;
   if (!finite_pos(p->h) || !finite_pos(p->dt) || !finite_pos(p->eps) || !finite_pos(p->M_phi))
     return CCMSAV_EINVAL;
@@ -243,7 +251,7 @@ int check_batch(int32_t nmemb, const ccmsav_params* p) {
 // argument tables and the member index lists.
 struct BatchLayout {
   std::vector<size_t> member;   // offset of each member's region
-  size_t args, idx, total;
+  size_t args, idx, bar, total;
 };
 
 BatchLayout batch_layout(int32_t nmemb, const ccmsav_params* p) {
@@ -257,6 +265,8 @@ BatchLayout batch_layout(int32_t nmemb, const ccmsav_params* p) {
   off = align_up(off + (size_t)kNumTables * nmemb * sizeof(MemberArgs));
   B.idx = off;
   off = align_up(off + (size_t)nmemb * sizeof(int));
+  B.bar = off;                  // grid barrier of the persistent launch
+  off = align_up(off + sizeof(GridBarrier));
   B.total = off;
   return B;
 }
@@ -341,6 +351,7 @@ DiagConst make_diag(const ccmsav_params& p) {
 
 int status_from_err(int err) {
   if (err & ERR_NONFINITE) return CCMSAV_ENONFINITE;
+  if (err & ERR_BARRIER) return CCMSAV_EBARRIER;
   if (err & ERR_PCG) return CCMSAV_ECONVERGE;
   if (err & (ERR_NORM | ERR_PIVOT)) return CCMSAV_EDOMAIN;
   return CCMSAV_OK;
@@ -417,6 +428,11 @@ struct ccmsav_ctx {
   bool bdf1 = false;       // every step with the BDF1 scheme (CCMSAV_FLAG_BDF1)
   bool periodic = false;   // periodic boundaries (CCMSAV_FLAG_PERIODIC)
   bool classical = false;  // classical MSAV scheme (CCMSAV_FLAG_CLASSICAL)
+  bool persistent = false; // one launch per step (CCMSAV_FLAG_PERSISTENT)
+  unsigned spin_limit = 1u << 22;
+  int ps_grid = 0;         // resident workgroups of the persistent kernel
+  PersistPlan ps_plan{};
+  GridBarrier* bar = nullptr;
   double pcg_tol = kPcgTol;
   int pcg_max_iter = kPcgMaxIter;
   hipStream_t stream = nullptr;
@@ -632,6 +648,17 @@ void enqueue_classical_solves(ccmsav_ctx* c, int table, hipStream_t st) {
                      m.ds, (double)n, 0);
 }
 
+// The 5x5 kernel of `count` members of class k, with the thread count of
+// their grid size (every path of a grid uses the same, so results agree).
+void launch_solve(hipStream_t st, const SizeClass& k, int count, const MemberArgs* tab) {
+  if (solve_threads((size_t)1 << (k.lx + k.ly)) == SOLVE_THREADS)
+    hipLaunchKernelGGL(k_solve<SOLVE_THREADS>, dim3(count), dim3(SOLVE_THREADS), 0, st, tab,
+                       k.d_idx, 1);
+  else
+    hipLaunchKernelGGL(k_solve<SOLVE_THREADS_SMALL>, dim3(count), dim3(SOLVE_THREADS_SMALL), 0,
+                       st, tab, k.d_idx, 1);
+}
+
 template <typename TM>
 void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe, Tuner& tu,
                        int only) {
@@ -673,7 +700,7 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe,
   for (size_t ki = 0; ki < c->cls.size(); ++ki) {
     if (skip(ki)) continue;
     const SizeClass& k = c->cls[ki];
-    hipLaunchKernelGGL(k_solve, dim3(k.count), dim3(SOLVE_THREADS), 0, st, tab, k.d_idx, 1);
+    launch_solve(st, k, k.count, tab);
   }
   pe.mark(7, st);
   pe.mark(8, st);
@@ -758,7 +785,7 @@ int enqueue_step_gemm(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEvents 
                      st, rm, m.lamx, m.lamy, m.part2, nx, ny, kGramPerThread, ha.k);
   pe.mark(5, st);
   pe.mark(6, st);
-  hipLaunchKernelGGL(k_solve, dim3(1), dim3(SOLVE_THREADS), 0, st, tab, k.d_idx, 1);
+  launch_solve(st, k, 1, tab);
   pe.mark(7, st);
   pe.mark(8, st);
   hipLaunchKernelGGL(k_gemm_combine, dim3((unsigned)std::min<size_t>(cells / GEMM_THREADS + 1, 8192)),
@@ -816,7 +843,7 @@ int enqueue_step_periodic(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEve
   hipLaunchKernelGGL(k_per_gram, dim3(ny), dim3(PER_THREADS), 0, st, rm, m.psol, m.part2, nx, ny);
   pe.mark(5, st);
   pe.mark(6, st);
-  hipLaunchKernelGGL(k_solve, dim3(1), dim3(SOLVE_THREADS), 0, st, tab, k.d_idx, 1);
+  launch_solve(st, k, 1, tab);
   pe.mark(7, st);
   pe.mark(8, st);
   const int snew = (int)((level + 1) % 3);
@@ -829,10 +856,58 @@ int enqueue_step_periodic(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEve
   return hipGetLastError() == hipSuccess ? CCMSAV_OK : CCMSAV_EHIP;
 }
 
+// The whole step as one launch of the persistent kernel (all members, all
+// passes); the step is reported as phase 0 of the per-phase timing.
+int enqueue_step_persistent(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEvents pe) {
+  const MemberArgs* tab = c->d_args + (size_t)table_of_level(level) * c->mem.size();
+  pe.mark(0, st);
+  hipLaunchKernelGGL(k_persist_step<float>, dim3(c->ps_grid), dim3(PS_THREADS), 0, st,
+                     c->ps_plan, tab, c->bar, c->spin_limit);
+  for (int i = 1; i < 2 * kNumPhases; ++i) pe.mark(i, st);
+  return CCMSAV_OK;
+}
+
+// Work list and grid of the persistent launch: per pass and size class, the
+// groups of virtual blocks one workgroup runs at once (PS_THREADS / threads
+// of the body), and as many workgroups as the device holds at once.
+int build_persist_plan(ccmsav_ctx* c) {
+  static_assert(STENCIL_THREADS == PS_THREADS && SOLVE_THREADS_SMALL == PS_THREADS,
+                "one stencil band and one 5x5 system per workgroup");
+  if (c->cls.size() > (size_t)PS_MAX_CLASSES) return CCMSAV_EUNSUPPORTED;
+  PersistPlan& pl = c->ps_plan;
+  pl = PersistPlan{};
+  pl.ncls = (int)c->cls.size();
+  for (size_t ki = 0; ki < c->cls.size(); ++ki) {
+    const SizeClass& k = c->cls[ki];
+    // every member of the class takes the 256-thread 5x5 kernel in both paths
+    if (solve_threads((size_t)1 << (k.lx + k.ly)) != SOLVE_THREADS_SMALL) return CCMSAV_EUNSUPPORTED;
+    pl.cls[ki] = PersistClass{k.lx, k.ly, k.count, k.d_idx, k.sh.blocks};
+    const int nx = 1 << k.lx, ny = 1 << k.ly;
+    for (int ph = 0; ph < PS_PHASES; ++ph) {
+      const int n = (ph == 1 || ph == 5) ? nx : ny;
+      const int nt = ps_body_threads<float>(ph, n);
+      if (nt > PS_THREADS || PS_THREADS % nt != 0) return CCMSAV_EUNSUPPORTED;
+      const int g = PS_THREADS / nt;
+      const long total = (long)k.count * ps_blocks_per_member<float>(ph, nx, ny, k.sh.blocks);
+      if (total % g != 0) return CCMSAV_EUNSUPPORTED;
+      pl.off[ph][ki + 1] = pl.off[ph][ki] + (int)(total / g);
+    }
+  }
+  int dev = 0, cus = 0, per_cu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &per_cu, reinterpret_cast<const void*>(k_persist_step<float>), PS_THREADS, 0));
+  if (per_cu < 1 || cus < 1) return CCMSAV_EUNSUPPORTED;
+  c->ps_grid = per_cu * cus;
+  return CCMSAV_OK;
+}
+
 int enqueue_step_level(ccmsav_ctx* c, int64_t level, hipStream_t st,
                        PhaseEvents pe = PhaseEvents{nullptr}, int only = -1) {
   if (is_gemm(c->precision)) return enqueue_step_gemm(c, level, st, pe);
   if (c->periodic) return enqueue_step_periodic(c, level, st, pe);
+  if (c->persistent) return enqueue_step_persistent(c, level, st, pe);
   const int t = table_of_level(level);
   Tuner tu;
   if (!c->tuned) {
@@ -879,7 +954,8 @@ int enqueue_step_level(ccmsav_ctx* c, int64_t level, hipStream_t st,
 // side by side.
 int capture_graph(ccmsav_ctx* c) {
   if (c->gexec) return CCMSAV_OK;
-  const size_t nb = c->cls.size() > 1 ? c->cls.size() - 1 : 0;
+  // one branch per size class (the persistent launch covers them all)
+  const size_t nb = (c->cls.size() > 1 && !c->persistent) ? c->cls.size() - 1 : 0;
   while (c->bstream.size() < nb) {
     hipStream_t s = nullptr;
     hipEvent_t e = nullptr;
@@ -924,19 +1000,27 @@ int capture_graph(ccmsav_ctx* c) {
 
 int read_err_member(ccmsav_ctx* c, int m, int* err) {
   *err = 0;
+  GridBarrier b{};
   HIP_TRY(hipMemcpyAsync(err, &c->mem[m].ds->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  if (c->persistent && c->bar)
+    HIP_TRY(hipMemcpyAsync(&b, c->bar, sizeof(b), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  if (b.err) *err |= ERR_BARRIER;
   return CCMSAV_OK;
 }
 
 int read_err(ccmsav_ctx* c, int* err) {
   *err = 0;
   std::vector<int> e(c->mem.size(), 0);
+  GridBarrier b{};
   for (size_t m = 0; m < c->mem.size(); ++m)
     HIP_TRY(hipMemcpyAsync(&e[m], &c->mem[m].ds->err, sizeof(int), hipMemcpyDeviceToHost,
                            c->stream));
+  if (c->persistent)
+    HIP_TRY(hipMemcpyAsync(&b, c->bar, sizeof(b), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   for (int v : e) *err |= v;
+  if (b.err) *err |= ERR_BARRIER;
   return CCMSAV_OK;
 }
 
@@ -1024,6 +1108,7 @@ const char* kStatusText[] = {
     "non-finite value in the state",
     "unsupported grid size or precision mode",
     "an iterative solve did not reach its tolerance",
+    "a grid barrier of the persistent launch failed",
 };
 
 }  // namespace
@@ -1258,7 +1343,9 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
   c->bdf1 = (p[0].flags & CCMSAV_FLAG_BDF1) != 0;
   c->periodic = is_periodic(&p[0]);
   c->classical = is_classical(&p[0]);
-  c->tuned = c->periodic;  // the periodic step has no launch variants
+  c->persistent = is_persistent(&p[0]);
+  // the periodic step has no launch variants, the persistent one fixed ones
+  c->tuned = c->periodic || c->persistent;
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->owns_ws = workspace == nullptr;
   if (c->owns_ws) {
@@ -1275,11 +1362,15 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
   char* base = static_cast<char*>(c->ws);
   c->d_args = reinterpret_cast<MemberArgs*>(base + BL.args);
   int* d_idx = reinterpret_cast<int*>(base + BL.idx);
+  c->bar = reinterpret_cast<GridBarrier*>(base + BL.bar);
   auto fail = [&](int code) {
     (void)hipStreamSynchronize(c->stream);
     free_ctx(c);
     return code;
   };
+  // the barrier state is read by every status check, the first ones below
+  if (hipMemsetAsync(c->bar, 0, sizeof(GridBarrier), c->stream) != hipSuccess)
+    return fail(CCMSAV_EHIP);
 
   c->mem.resize(nmemb);
   for (int32_t mi = 0; mi < nmemb; ++mi) {
@@ -1407,6 +1498,10 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
                                  c->stream) == hipSuccess;
   // the index order must outlive the copies, also when one of them failed
   if (hipStreamSynchronize(c->stream) != hipSuccess || !ok) return fail(CCMSAV_EHIP);
+  if (c->persistent) {
+    const int r = build_persist_plan(c);
+    if (r != CCMSAV_OK) return fail(r);
+  }
   if (c->graph) {
     if (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
@@ -1823,6 +1918,13 @@ int ccmsav_pcg_stats(ccmsav_ctx* c, int32_t iters[2], double rel_residual[2]) {
   return CCMSAV_OK;
 }
 
+int ccmsav_set_spin_limit(ccmsav_ctx* c, uint32_t polls) {
+  if (!c) return CCMSAV_EINVAL;
+  if (!c->persistent) return CCMSAV_EUNSUPPORTED;
+  c->spin_limit = polls;
+  return CCMSAV_OK;
+}
+
 int ccmsav_destroy(ccmsav_ctx* c) {
   if (!c) return CCMSAV_EINVAL;
   (void)hipStreamSynchronize(c->stream);
@@ -1832,7 +1934,7 @@ int ccmsav_destroy(ccmsav_ctx* c) {
 }
 
 const char* ccmsav_strerror(int code) {
-  if (code > 0 || code < CCMSAV_ECONVERGE) return "unknown status";
+  if (code > 0 || code < CCMSAV_EBARRIER) return "unknown status";
   return kStatusText[-code];
 }
 

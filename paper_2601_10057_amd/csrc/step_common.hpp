@@ -62,6 +62,7 @@ enum ErrBits {
   ERR_PIVOT = 4,       // singular 5x5 system
   ERR_MOBILITY = 8,    // a face mobility <= 0 (energy undefined)
   ERR_PCG = 16,        // the classical scheme's PCG did not reach its tolerance
+  ERR_BARRIER = 32,    // a grid barrier of the persistent launch timed out
 };
 
 // Device-resident scalar state. Everything the time loop needs lives here so

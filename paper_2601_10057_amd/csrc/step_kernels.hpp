@@ -232,6 +232,18 @@ constexpr int SW_OUT = 60;                    // output columns per wave
 constexpr int SW_COLS = SW_WAVES * SW_OUT;    // output columns per workgroup
 constexpr int SW_BAND = 32;                   // rows per workgroup (ny if smaller)
 
+// LDS of one invocation of a kernel body, its arrays gathered in one struct:
+// the kernels declare one as __shared__, and the persistent step kernel
+// places several side by side and reuses the space from phase to phase.
+struct StencilLds {
+  double red[P1_NSUM * (STENCIL_THREADS / 64 + 1)];
+};
+// A transform line (or band of lines) and the twiddle roots of length N.
+template <typename TM, int LINE, int N> struct LinesLds {
+  cpx<TM> line[LINE];
+  cpx<double> rtab[Roots<TM, N>::SIZE];
+};
+
 // Launch shape of P1a for an nx x ny grid: rows per workgroup and the number
 // of workgroups (one row of partial sums each).
 struct StencilShape {
@@ -247,10 +259,10 @@ template <typename TM>
 __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restrict__ rm,
                                              gptr<double> __restrict__ part, int nx, int ny,
                                              int iters, const StepConst& c, int blk,
-                                             gptr<double> mob_e, gptr<double> mob_n) {
+                                             gptr<double> mob_e, gptr<double> mob_n,
+                                             StencilLds& L, int tid) {
   constexpr bool INC = increment_form<TM>();
-  __shared__ double red[P1_NSUM * (STENCIL_THREADS / 64 + 1)];
-  const int tid = threadIdx.x;
+  double* red = L.red;
   const int lane = tid & 63, wave = tid >> 6;
   const int nseg = (nx + SW_COLS - 1) / SW_COLS;
   const int seg = blk % nseg, band = blk / nseg;
@@ -541,19 +553,21 @@ __device__ __forceinline__ void load_piece(gptr<const TM> src, RowPiece<TM, ROWS
 
 // P1b: orthonormal DCT-II along x of the eight row-major fields, for a band
 // of ROWS rows, into the strip-major intermediates.
+// Each round of the row pass loads NP field pairs of its ROWS rows into LDS
+// lines (row r, pair l at (r NP + l) NX, two real fields per complex line) and
+// transforms them with one batched FFT; 4 / NP rounds cover the pairs.
+template <typename TM, int NX, int V>
+using RowDctLds = LinesLds<TM, p1_rows_v<TM>(NX, V) * p1_pairs_v<TM>(NX, V) * NX, NX>;
+
 template <typename TM, int NX, int V>
 __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
                                               gptr<TM> __restrict__ mid,
-                                              int ny, int blk) {
+                                              int ny, int blk, RowDctLds<TM, NX, V>& L, int tid) {
   constexpr int NTHR = line_threads(NX);
   constexpr int ROWS = p1_rows_v<TM>(NX, V);
-  // Each round loads NP field pairs of the ROWS rows into LDS lines (row r,
-  // pair l at (r NP + l) NX, two real fields per complex line) and transforms
-  // them with one batched FFT; 4 / NP rounds cover the pairs.
   constexpr int NP = p1_pairs_v<TM>(NX, V);
-  __shared__ cpx<TM> line[ROWS * NP * NX];
-  __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
-  const int tid = threadIdx.x;
+  cpx<TM>* line = L.line;
+  cpx<double>* rtab = L.rtab;
   const int j0 = blk * ROWS;
   const size_t FS = (size_t)NX * ny;                            // row-major fields
   const size_t SS = strip_stride(ny, sizeof(TM));
@@ -735,13 +749,42 @@ __device__ __forceinline__ void stage_accumulate(double (&v)[NV], const int (&id
   if (tid < NV) acc[idx[tid]] += red[tid];
 }
 
+// LDS plan of the Gram kernel: the line, the S~ spectrum (waiting for its
+// products with the later fields) and, where they fit, per-thread partial
+// sums that are reduced over the block once per strip instead of once per
+// field.
+template <typename TM, int NY> struct GramPlan {
+  static constexpr int NTHR = gram_threads(NY);
+  static constexpr int LINE_B = NY * (int)sizeof(cpx<TM>);
+  static constexpr int ROOT_B = Roots<TM, NY>::SIZE * (int)sizeof(cpx<double>);
+  // The partial sums only go to LDS while the CU still holds 8 waves of
+  // workgroups.
+  static constexpr int BUDGET = 150 * 1024;
+  static constexpr int WAVES = NTHR / 64;
+  static constexpr int ACC_BUDGET = WAVES >= 8 ? BUDGET : (160 * 1024) / (8 / WAVES);
+  static constexpr bool S_LDS = 2 * LINE_B + ROOT_B <= BUDGET;
+  static constexpr bool ACC_LDS =
+      (S_LDS ? 2 : 1) * LINE_B + ROOT_B + P2_NSUM * NTHR * (int)sizeof(double) <= ACC_BUDGET &&
+      NTHR % 16 == 0;
+};
+template <typename TM, int NY> struct GramLds {
+  using GP = GramPlan<TM, NY>;
+  cpx<TM> line[NY];
+  cpx<TM> keep[GP::S_LDS ? NY : 1];
+  cpx<double> rtab[Roots<TM, NY>::SIZE];
+  double red[GP::ACC_LDS ? 1 : P2_NSUM * (GP::NTHR / 64 + 1)];   // per-field block sums
+  double acc[GP::ACC_LDS ? P2_NSUM * GP::NTHR : P2_NSUM];
+};
+
 template <typename TM, int NY>
 __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
                                               gptr<const double> __restrict__ lamx,
                                               gptr<const double> __restrict__ lamy,
                                               gptr<double> __restrict__ part, int nx,
-                                              const OpConst c, int s) {
-  constexpr int NTHR = gram_threads(NY);
+                                              const OpConst c, int s, GramLds<TM, NY>& L,
+                                              int tid) {
+  using GP = GramPlan<TM, NY>;
+  constexpr int NTHR = GP::NTHR;
   constexpr int LPT = NY >= NTHR ? NY / NTHR : 1;            // strip loads per thread
   constexpr int UPT = NY / 2 >= NTHR ? NY / 2 / NTHR : 1;    // pair units per thread
   constexpr int KPT = 2 * UPT;                               // bins per thread
@@ -750,26 +793,13 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   constexpr int GR = NY / NTHR >= 8 ? 8 : (NY / NTHR >= 4 ? 4 : 2);
   using MAP = LdsMap<TM, NY, SWZ_GRAM>;
   using LS = LineSlots<NY, NTHR, GR, MAP>;
-  // LDS plan: the line, the S~ spectrum (waiting for its products with the
-  // later fields) and, where they fit, per-thread partial sums that are
-  // reduced over the block once per strip instead of once per field.
-  constexpr int LINE_B = NY * (int)sizeof(cpx<TM>);
-  constexpr int ROOT_B = Roots<TM, NY>::SIZE * (int)sizeof(cpx<double>);
-  // The partial sums only go to LDS while the CU still holds 8 waves of
-  // workgroups.
-  constexpr int BUDGET = 150 * 1024;
-  constexpr int WAVES = NTHR / 64;
-  constexpr int ACC_BUDGET = WAVES >= 8 ? BUDGET : (160 * 1024) / (8 / WAVES);
-  constexpr bool S_LDS = 2 * LINE_B + ROOT_B <= BUDGET;
-  constexpr bool ACC_LDS =
-      (S_LDS ? 2 : 1) * LINE_B + ROOT_B + P2_NSUM * NTHR * (int)sizeof(double) <= ACC_BUDGET &&
-      NTHR % 16 == 0;
-  __shared__ cpx<TM> line[NY];
-  __shared__ cpx<TM> keep[S_LDS ? NY : 1];
-  __shared__ cpx<double> rtab[Roots<TM, NY>::SIZE];
-  __shared__ double red[P2_NSUM * (NTHR / 64 + 1)];
-  __shared__ double acc[ACC_LDS ? P2_NSUM * NTHR : P2_NSUM];
-  const int tid = threadIdx.x;
+  constexpr bool S_LDS = GP::S_LDS;
+  constexpr bool ACC_LDS = GP::ACC_LDS;
+  cpx<TM>* line = L.line;
+  cpx<TM>* keep = L.keep;
+  cpx<double>* rtab = L.rtab;
+  double* red = L.red;
+  double* acc = L.acc;
   const size_t SS = strip_stride(NY, sizeof(TM));
   const size_t FSM = strip_field(nx, NY, sizeof(TM));
   Roots<TM, NY> rt;
@@ -1016,17 +1046,28 @@ __device__ void reduce_columns(P part, int nrows, double* red, int tid, double (
 // ---------------------------------------------------------------------------
 // S: the 5x5 reduced system of App. B, Step 4, and the SAV update.
 // ---------------------------------------------------------------------------
+// Threads of the 5x5 kernel: 512 for grids above 512^2 (thousands of partial
+// rows, read with many loads in flight), 256 up to 512^2. The two orders of
+// the partial sums differ, so every path of one grid uses the same count.
 constexpr int SOLVE_THREADS = 512;
+constexpr int SOLVE_THREADS_SMALL = 256;
+inline int solve_threads(size_t cells) {
+  return cells > (size_t)512 * 512 ? SOLVE_THREADS : SOLVE_THREADS_SMALL;
+}
+constexpr int SOLVE_NV_MAX = (int)P1_NSUM > (int)P2_NSUM ? (int)P1_NSUM : (int)P2_NSUM;
+template <int NTHR> struct SolveLds {
+  double red[NTHR + SOLVE_NV_MAX];
+};
 
+template <int NTHR>
 __device__ __forceinline__ void solve_body(gptr<const double> __restrict__ p1, int n1,
                                            gptr<const double> __restrict__ p2, int n2,
-                                           gptr<DevScalars> __restrict__ ds, const StepConst& c) {
-  constexpr int NV_MAX = (int)P1_NSUM > (int)P2_NSUM ? (int)P1_NSUM : (int)P2_NSUM;
-  __shared__ double red[SOLVE_THREADS + NV_MAX];
-  const int tid = threadIdx.x;
+                                           gptr<DevScalars> __restrict__ ds, const StepConst& c,
+                                           SolveLds<NTHR>& L, int tid) {
+  double* red = L.red;
   double T1[P1_NSUM], T2[P2_NSUM];
-  reduce_columns<P1_NSUM, SOLVE_THREADS>(p1, n1, red, tid, T1);
-  reduce_columns<P2_NSUM, SOLVE_THREADS>(p2, n2, red, tid, T2);
+  reduce_columns<P1_NSUM, NTHR>(p1, n1, red, tid, T1);
+  reduce_columns<P2_NSUM, NTHR>(p2, n2, red, tid, T2);
   if (tid != 0) return;
 
   int err = 0;
@@ -1154,7 +1195,10 @@ __device__ __forceinline__ void solve_body(gptr<const double> __restrict__ p1, i
 // ---------------------------------------------------------------------------
 // P3: spectral combination, divide by the operator spectrum, DCT-III along y.
 // ---------------------------------------------------------------------------
-template <typename TM, int NY, int NTHR>
+// UNIFORM_SYNC: every invocation passes the same workgroup barriers, also the
+// ones of the k_x = 0 row-sum block below (needed where several invocations
+// share a workgroup in lockstep).
+template <typename TM, int NY, int NTHR, bool UNIFORM_SYNC = false>
 __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
                                                gptr<const double> __restrict__ lamx,
                                                gptr<const double> __restrict__ lamy,
@@ -1162,15 +1206,15 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
                                                gptr<TM> __restrict__ out, int nx, int chi_base,
                                                int nchi, int zeta_base, int nzeta,
                                                gptr<double> __restrict__ colsum,
-                                               const OpConst c, int lin) {
+                                               const OpConst c, int lin,
+                                               LinesLds<TM, NY, NY>& L, int tid) {
   constexpr int LPT = NY >= NTHR ? NY / NTHR : 1;            // elements per thread
   constexpr int UPT = NY / 2 >= NTHR ? NY / 2 / NTHR : 1;    // pair units per thread
   constexpr int R = fft_radix<TM>();
   using MAP = LdsMap<TM, NY, SWZ_LINE>;
   using LS = LineSlots<NY, NTHR, R, MAP>;
-  __shared__ cpx<TM> line[NY];
-  __shared__ cpx<double> rtab[Roots<TM, NY>::SIZE];
-  const int tid = threadIdx.x;
+  cpx<TM>* line = L.line;
+  cpx<double>* rtab = L.rtab;
   const int nstrip = nx / 2;
   const int s = lin % nstrip;
   const int grp = lin / nstrip;            // 0: chi (Allen-Cahn), 1: zeta (Cahn-Hilliard)
@@ -1270,23 +1314,24 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
       y0[q] = y.re;
     }
   });
-  if (colsum && grp == 1 && s == 0) {
+  const bool sums_here = colsum && grp == 1 && s == 0;
+  if (sums_here || (UNIFORM_SYNC && colsum)) {
     // Column k_x = 0 of the psi increment, y physical: its FP32 values sum to
     // rounding noise instead of zero. Hand the row-inverse pass FP64 targets
     // for the row sums that add up to zero, so that the increment it writes
-    // has zero sum in FP64 arithmetic.
+    // has zero sum in FP64 arithmetic. (Other strips pass the barriers only.)
     double* buf = reinterpret_cast<double*>(line);   // the line is no longer read
     lds_sync();
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int i = tid + q * NTHR;
-      if (i < NY) buf[i] = (double)y0[q];
+      if (sums_here && i < NY) buf[i] = (double)y0[q];
     }
     const double mean = tree_sum<NY>(buf, tid, NTHR) / NY;
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
       const int i = tid + q * NTHR;
-      if (i < NY) colsum[i] = (double)y0[q] - mean;
+      if (sums_here && i < NY) colsum[i] = (double)y0[q] - mean;
     }
   }
 }
@@ -1300,15 +1345,15 @@ __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
                                               gptr<double> __restrict__ psi_new, int ny,
                                               gptr<const double> __restrict__ phi_base,
                                               gptr<const double> __restrict__ psi_base,
-                                              gptr<const double> __restrict__ colsum, int j) {
+                                              gptr<const double> __restrict__ colsum, int j,
+                                              LinesLds<TM, NX, NX>& L, int tid) {
   constexpr int CPT = NX >= NTHR ? NX / NTHR : 1;            // outputs per thread
   constexpr int UPT = NX / 2 >= NTHR ? NX / 2 / NTHR : 1;    // pair units per thread
   constexpr int R = fft_radix<TM>();
   using MAP = LdsMap<TM, NX, SWZ_LINE>;
   using LS = LineSlots<NX, NTHR, R, MAP>;
-  __shared__ cpx<TM> line[NX];
-  __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
-  const int tid = threadIdx.x;
+  cpx<TM>* line = L.line;
+  cpx<double>* rtab = L.rtab;
   const size_t SS = strip_stride(ny, sizeof(TM));
   const size_t FSM = strip_field(NX, ny, sizeof(TM));
   Roots<TM, NX> rt;
@@ -1391,13 +1436,16 @@ __device__ __forceinline__ void row_idct_body(gptr<const TM> __restrict__ out,
 // by unit, since unit u reads and writes only bins u and N - u. The
 // transforms, outputs and row sums are those of row_idct_body, row by row.
 template <typename TM, int NX>
+using RowIdctBandLds = LinesLds<TM, row_idct_rows<TM>(NX, 0) * NX, NX>;
+
+template <typename TM, int NX>
 __device__ __forceinline__ void row_idct_band_body(gptr<const TM> __restrict__ out,
                                                    gptr<double> __restrict__ phi_new,
                                                    gptr<double> __restrict__ psi_new, int ny,
                                                    gptr<const double> __restrict__ phi_base,
                                                    gptr<const double> __restrict__ psi_base,
                                                    gptr<const double> __restrict__ colsum,
-                                                   int blk) {
+                                                   int blk, RowIdctBandLds<TM, NX>& L, int tid) {
   constexpr int NTHR = row_idct_threads<TM>(NX, 0);
   constexpr int ROWS = row_idct_rows<TM>(NX, 0);
   constexpr int CPT = NX >= NTHR ? NX / NTHR : 1;            // outputs per thread and row
@@ -1406,9 +1454,8 @@ __device__ __forceinline__ void row_idct_band_body(gptr<const TM> __restrict__ o
   constexpr int RS = NX * (int)sizeof(cpx<TM>) / (int)sizeof(double);   // row buffer stride
   using MAP = LdsMap<TM, NX, SWZ_ROW>;
   using LS = LineSlots<NX, NTHR, R, MAP>;
-  __shared__ cpx<TM> line[ROWS * NX];
-  __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
-  const int tid = threadIdx.x;
+  cpx<TM>* line = L.line;
+  cpx<double>* rtab = L.rtab;
   const int j0 = blk * ROWS;
   const size_t SS = strip_stride(ny, sizeof(TM));
   const size_t FSM = strip_field(NX, ny, sizeof(TM));
@@ -1583,6 +1630,7 @@ __device__ __forceinline__ const MemberArgs& batch_member(const MemberArgs* __re
 // left on the chip.
 template <typename TM>
 __global__ void __launch_bounds__(STENCIL_THREADS) k_stencil(BATCH_PARAMS, int total) {
+  __shared__ StencilLds L;
   const int g = gridDim.x, b = blockIdx.x;
   const bool xcd = (g & 7) == 0 && (total & 7) == 0;
   const int first = xcd ? (b & 7) * (total >> 3) + (b >> 3) : b;
@@ -1593,41 +1641,47 @@ __global__ void __launch_bounds__(STENCIL_THREADS) k_stencil(BATCH_PARAMS, int t
     const MemberArgs& m = tab[idx[vb / per]];
     const RowArgs a{m.phn, m.phm, m.phmm, m.psn, m.psm, m.psmm};
     stencil_body<TM>(a, static_cast<gptr<TM>>(m.rm), m.part1, m.nx, m.ny, m.iters, m.k, blk,
-                     m.mob_e, m.mob_n);
+                     m.mob_e, m.mob_n, L, threadIdx.x);
   }
 }
 
 template <typename TM, int NX, int V>
 __global__ void __launch_bounds__(line_threads(NX)) k_row_dct8(BATCH_PARAMS) {
+  __shared__ RowDctLds<TM, NX, V> L;
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
   row_dct8_body<TM, NX, V>(static_cast<gptr<const TM>>(m.rm), static_cast<gptr<TM>>(m.mid), m.ny,
-                           blk);
+                           blk, L, threadIdx.x);
 }
 
 template <typename TM, int NY>
 __global__ void __launch_bounds__(gram_threads(NY)) k_col_gram(BATCH_PARAMS) {
+  __shared__ GramLds<TM, NY> L;
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
   const OpConst o{m.k.C1, m.k.C2, m.k.C3, m.k.alpha, m.k.lam};
-  col_gram_body<TM, NY>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.part2, m.nx, o, blk);
+  col_gram_body<TM, NY>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.part2, m.nx, o, blk,
+                        L, threadIdx.x);
 }
 
-__global__ void __launch_bounds__(SOLVE_THREADS) k_solve(BATCH_PARAMS) {
+template <int NTHR>
+__global__ void __launch_bounds__(NTHR) k_solve(BATCH_PARAMS) {
+  __shared__ SolveLds<NTHR> L;
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
-  solve_body(m.part1, m.p1_blocks, m.part2, m.p2_rows, m.ds, m.k);
+  solve_body<NTHR>(m.part1, m.p1_blocks, m.part2, m.p2_rows, m.ds, m.k, L, threadIdx.x);
 }
 
 template <typename TM, int NY, int V>
 __global__ void __launch_bounds__(line_threads_v<TM>(NY, V)) k_col_solve(BATCH_PARAMS) {
+  __shared__ LinesLds<TM, NY, NY> L;
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
   if (m.skip && *m.skip) return;     // a converged iteration (whole workgroup)
   const OpConst o{m.k.C1, m.k.C2, m.k.C3, m.k.alpha, m.k.lam};
   col_solve_body<TM, NY, line_threads_v<TM>(NY, V)>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.coef,
                          static_cast<gptr<TM>>(m.outc), m.nx, m.chi_base, m.nchi, m.zeta_base,
-                         m.nzeta, m.colsum, o, blk);
+                         m.nzeta, m.colsum, o, blk, L, threadIdx.x);
 }
 
 // Row inverse variants: 0 takes a band of row_idct_rows rows per workgroup,
@@ -1640,12 +1694,14 @@ k_row_idct(BATCH_PARAMS) {
   const MemberArgs& m = batch_member(tab, idx, per, blk);
   if (m.skip && *m.skip) return;     // a converged iteration (whole workgroup)
   if constexpr (V == 0) {
+    __shared__ RowIdctBandLds<TM, NX> L;
     row_idct_band_body<TM, NX>(static_cast<gptr<const TM>>(m.outc), m.phi_new, m.psi_new, m.ny,
-                               m.phi_base, m.psi_base, m.colsum, blk);
+                               m.phi_base, m.psi_base, m.colsum, blk, L, threadIdx.x);
   } else {
+    __shared__ LinesLds<TM, NX, NX> L;
     row_idct_body<TM, NX, line_threads_v<TM>(NX, V)>(static_cast<gptr<const TM>>(m.outc),
                                                      m.phi_new, m.psi_new, m.ny, m.phi_base,
-                                                     m.psi_base, m.colsum, blk);
+                                                     m.psi_base, m.colsum, blk, L, threadIdx.x);
   }
 }
 

@@ -87,7 +87,7 @@ def test_init_rejects_null_and_unknown_modes():
     buf = (ctypes.c_double * 4)()
     assert lib.ccmsav_init(ctypes.byref(h), ctypes.byref(p), buf, buf, None, 0, None) == -6
     p.precision = 0
-    p.flags = 16         # no such flag
+    p.flags = 32         # no such flag
     assert lib.ccmsav_init(ctypes.byref(h), ctypes.byref(p), buf, buf, None, 0, None) == -1
     # the periodic step: FP64 only, no graph, grids up to 4096, one member
     for prec, flags, n in ((C.MIXED, C.FLAG_PERIODIC, 64), (C.FP64, C.FLAG_PERIODIC | C.FLAG_GRAPH, 64),
@@ -113,10 +113,26 @@ def test_init_rejects_null_and_unknown_modes():
     assert lib.ccmsav_workspace_bytes_batch(2, (C.Params * 2)(q, q)) == 0
     assert lib.ccmsav_pcg_config(None, 1e-10, 10) == -1
     assert C.strerror(-7).startswith("an iterative solve")
+    # the persistent launch: FP32 transforms, CC-MSAV with Neumann boundaries,
+    # grids of 64 to 512 per direction
+    for prec, flags, n in ((C.FP64, C.FLAG_PERSISTENT, 64),
+                           (C.MIXED, C.FLAG_PERSISTENT | C.FLAG_PERIODIC, 64),
+                           (C.MIXED_GEMM_BF16X3, C.FLAG_PERSISTENT, 64),
+                           (C.MIXED, C.FLAG_PERSISTENT, 32), (C.MIXED, C.FLAG_PERSISTENT, 1024)):
+        q = _params(nx=n, ny=n)
+        q.precision, q.flags = prec, flags
+        assert lib.ccmsav_init(ctypes.byref(h), ctypes.byref(q), buf, buf, None, 0, None) == -6
+        assert lib.ccmsav_workspace_bytes(ctypes.byref(q)) == 0
+    q = _params(nx=64, ny=128)
+    q.precision, q.flags = C.MIXED, C.FLAG_PERSISTENT | C.FLAG_GRAPH | C.FLAG_BDF1
+    assert lib.ccmsav_workspace_bytes(ctypes.byref(q)) > 0
+    assert lib.ccmsav_set_spin_limit(None, 0) == -1
+    assert C.strerror(-8).startswith("a grid barrier")
     assert lib.ccmsav_step(None, 1) == -1
     assert lib.ccmsav_destroy(None) == -1
     assert C.strerror(-6).startswith("unsupported")
     assert C.strerror(5) == "unknown status"
+    assert C.strerror(-9) == "unknown status"
 
 
 def test_batch_workspace_and_validation_without_a_device():
