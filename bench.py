@@ -37,18 +37,36 @@ HBM_PEAK_GBS = 8000.0
 # column pass reads eight; the column solve reads seven and writes two; the
 # row inverse reads two and writes the two new state fields. The mixed path
 # solves for increments, so its row inverse also reads phi^n, psi^n.
+def fs_n1(n):
+    """First factor N1 of the factored (four-step) transform of n points, 0 for
+    the dense product with the n x n DCT matrix (the library's choice)."""
+    return 64 if n >= 4096 else (32 if n == 2048 else 0)
+
+
+def line_flops(n, inverse):
+    """Matrix-core flops of one DCT of n points (2 m n k per product). Dense:
+    three bf16 products with the n x n matrix, 6 n^2. Factored (n = N1 N2, six
+    bf16 products of three-part operands, real and imaginary parts stacked):
+    forward 2 N1 x N1 and N2 x 2 N2 matrices, 24 (N1 + N2) n; inverse
+    2 N1 x 2 N1 and N2 x 2 N2, 48 N1 n + 24 N2 n."""
+    n1 = fs_n1(n)
+    if n1 == 0:
+        return 3 * 2.0 * n * n
+    n2 = n // n1
+    return 6 * 2.0 * n * ((4 * n1 + 2 * n2) if inverse else (2 * n1 + 2 * n2))
+
+
 def gemm_flops(members):
     """Matrix-core flops per launch of each phase of the DCT-as-GEMM variant:
-    three bf16 products (hi hi, hi lo, lo hi) of 2 m n k flops each, for the
-    row products of 8 (forward) and 2 (inverse) fields against the nx x nx DCT
-    matrix and the column products against the ny x ny one."""
+    the row transforms of 8 (forward) and 2 (inverse) fields along x, the
+    column transforms along y."""
     f = {"row_dct": 0.0, "col_gram": 0.0, "col_solve": 0.0, "row_idct": 0.0}
     for mb in members:
         nx, ny = mb.params["nx"], mb.params["ny"]
-        f["row_dct"] += 3 * 2.0 * (8 * ny) * nx * nx
-        f["col_gram"] += 3 * 2.0 * 8 * nx * ny * ny
-        f["col_solve"] += 3 * 2.0 * 2 * nx * ny * ny
-        f["row_idct"] += 3 * 2.0 * (2 * ny) * nx * nx
+        f["row_dct"] += 8 * ny * line_flops(nx, False)
+        f["col_gram"] += 8 * nx * line_flops(ny, False)
+        f["col_solve"] += 2 * nx * line_flops(ny, True)
+        f["row_idct"] += 2 * ny * line_flops(nx, True)
     return f
 
 
@@ -702,7 +720,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "mixed": "f32+f64", "gemm": "bf16x3+f32+f64"}[args.precision],
+        "dtype": {"fp64": "f64", "mixed": "f32+f64", "gemm": "bf16-split+f32+f64"}[args.precision],
         "data": "synthetic",
         "config": config,
         "roofline": roofline,

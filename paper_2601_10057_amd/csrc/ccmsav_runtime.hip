@@ -21,6 +21,7 @@
 #include "classical_kernels.hpp"
 #include "diag_kernels.hpp"
 #include "gemm_dct.hpp"
+#include "gemm_fourstep.hpp"
 #include "gemm_mfma.hpp"
 #include "persist_kernels.hpp"
 #include "periodic_kernels.hpp"
@@ -143,9 +144,30 @@ size_t p2_rows(const ccmsav_params* p) {
   return is_gemm(p->precision) ? gemm_gram_blocks(p) : (size_t)(p->nx / 2);
 }
 
+// DCT-as-GEMM variant: a direction of n points takes the factored transform
+// (gemm_fourstep.hpp) with n = N1 N2, N1 returned here, where both products
+// fill the matrix-core tiles (N1 >= 32 for K, N2 >= 64 for M); 0: the dense
+// product with the n x n DCT matrix.
+int fs_n1(int n) { return n >= 4096 ? 64 : n == 2048 ? 32 : 0; }
+// bf16 parts of the factored transform's four matrices (three parts each),
+// and the offset of its two twiddle tables behind them.
+size_t fs_mat_elems(int n1, int n2) {
+  return 3 * (6 * (size_t)n1 * n1 + 4 * (size_t)n2 * n2);
+}
+size_t fs_table_offset(int n1, int n2) { return align_up(fs_mat_elems(n1, n2) * sizeof(uint16_t)); }
+// Bytes of a direction's transform data: D and D^T (hi and lo halves each), or
+// the factored transform's matrices and its two tables of n float2 factors.
+size_t gemm_mat_bytes(int n) {
+  const int n1 = fs_n1(n);
+  if (n1 == 0) return 4 * (size_t)n * n * sizeof(uint16_t);
+  return fs_table_offset(n1, n / n1) + 2 * (size_t)n * sizeof(float2);
+}
+bool uses_fs(const ccmsav_params* p) { return fs_n1(p->nx) != 0 || fs_n1(p->ny) != 0; }
+
 struct Layout {
   size_t state, rm, mid, outc, part1, part2, parte, lamx, lamy, colsum, unit, ds;
-  size_t dx, dy;   // GEMM variant: DCT matrix and its transpose per direction, bf16 hi and lo
+  size_t dx, dy;   // GEMM variant: the transform matrices per direction, bf16 hi and lo
+  size_t fs;       // GEMM variant, factored transforms: complex work buffer
   size_t psol;     // periodic step: chi^{-1} of S~, H, Q~, K~ (4 FP64 fields)
   size_t cl, clpart, clsc;   // classical scheme: PCG fields, partial sums, scalars
   size_t total;
@@ -173,8 +195,11 @@ Layout layout(const ccmsav_params* p) {
   L.unit = off;  off = align_up(off + 8 * sizeof(double));
   L.ds = off;    off = align_up(off + sizeof(DevScalars));
   if (is_gemm(p->precision)) {
-    L.dx = off;    off = align_up(off + 4 * (size_t)p->nx * p->nx * sizeof(uint16_t));
-    L.dy = off;    off = align_up(off + 4 * (size_t)p->ny * p->ny * sizeof(uint16_t));
+    L.dx = off;    off = align_up(off + gemm_mat_bytes(p->nx));
+    L.dy = off;    off = align_up(off + gemm_mat_bytes(p->ny));
+    // Re and Im planes of all M_NFIELD fields (the inverse's two fields and
+    // their turned spectra fit as well)
+    if (uses_fs(p)) { L.fs = off; off = align_up(off + 2 * M_NFIELD * cells * sizeof(float)); }
   }
   if (is_periodic(p)) {
     L.psol = off;  off = align_up(off + 4 * cells * sizeof(double));
@@ -366,6 +391,21 @@ struct PhaseEvents {
 };
 
 // One member (one grid) of a context.
+// The matrices and twiddle tables of a factored transform along one
+// direction (n = N1 N2, gemm_fourstep.hpp): bf16 parts (hi, mid, lo), row-major
+// with the product dimension contiguous. Rows 2k and 2k + 1 of the
+// complex-output matrices give the real and imaginary part of output k; the
+// columns of complex inputs are [real parts, imaginary parts].
+struct FsMats {
+  int l1 = 0, l2 = 0;   // log2 of N1 and N2; l1 = 0: dense products
+  MfMat d1;             // forward step 1: W_N1^(n1 k1), 2 N1 x N1
+  MfMat d2;             // forward step 3: sqrt(2/N) exp(-i pi k2 (4 n2 + 1) / 2 N2), N2 x 2 N2
+  MfMat d1i;            // inverse step 1: sqrt(N/2) exp(-i pi a1 (4 b1 + 1) / 2 N1), 2 N1 x 2 N1
+  MfMat d2i;            // inverse step 3: W_N2^(a2 b2) / N, N2 x 2 N2
+  const float2* twf;    // forward step 2: exp(-i pi k1 (4 n2 + 1) / 2N), [k1][n2]
+  const float2* twi;    // inverse step 2: exp(-i pi a2 (4 b1 + 1) / 2N), [b1][a2]
+};
+
 struct Member {
   ccmsav_params p;
   int lx, ly;
@@ -384,7 +424,10 @@ struct Member {
   DevScalars* ds;
   StencilShape sh;
   // GEMM variant: bf16 hi and lo halves of the orthonormal DCT-II matrix D
-  // and of its transpose per direction, row-major
+  // and of its transpose per direction, row-major (dense directions), or the
+  // DFT matrices of the factored transform (fsx, fsy) and its work buffers
+  FsMats fsx, fsy;
+  float* fs_w;
   uint16_t* dx_hi;
   uint16_t* dx_lo;
   uint16_t* dxt_hi;
@@ -736,32 +779,116 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe,
 // ---- DCT-as-GEMM variant ------------------------------------------------------
 
 // One product of the DCT-as-GEMM variant (gemm_mfma.hpp) with the largest
-// tiles that divide the grid.
-template <int MODE>
-void mf_product(hipStream_t st, const uint16_t* d_hi, const uint16_t* d_lo, const float* x,
-                float* out, int M, int N, int K, int ldx, int ldc, size_t sx, size_t sc,
-                int batch) {
+// tiles that divide the grid, NP products per K step, stored through the
+// epilogue EPI.
+template <int MODE, int EPI = EPI_STORE, int NP = 3>
+void mf_product(hipStream_t st, const MfMat& d, const float* x, float* out, int M, int N, int K,
+                int ldx, int ldc, size_t sx, size_t sc, int batch,
+                FsArgs fa = FsArgs{0, 0, 0, nullptr}) {
   const int bm = mf_tile(M), bn = mf_tile(N);
   const dim3 grid((unsigned)(batch * (M / bm) * (N / bn)));
   if (bm == 128 && bn == 128)
-    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 128>), grid, dim3(MF_THREADS), 0, st, d_hi,
-                       d_lo, x, out, M, N, K, ldx, ldc, sx, sc);
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 128, EPI, NP>), grid, dim3(MF_THREADS), 0, st,
+                       d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
   else if (bm == 128)
-    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 64>), grid, dim3(MF_THREADS), 0, st, d_hi,
-                       d_lo, x, out, M, N, K, ldx, ldc, sx, sc);
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 64, EPI, NP>), grid, dim3(MF_THREADS), 0, st,
+                       d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
   else if (bn == 128)
-    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 128>), grid, dim3(MF_THREADS), 0, st, d_hi,
-                       d_lo, x, out, M, N, K, ldx, ldc, sx, sc);
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 128, EPI, NP>), grid, dim3(MF_THREADS), 0, st,
+                       d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
   else
-    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 64>), grid, dim3(MF_THREADS), 0, st, d_hi,
-                       d_lo, x, out, M, N, K, ldx, ldc, sx, sc);
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 64, EPI, NP>), grid, dim3(MF_THREADS), 0, st,
+                       d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
 }
 
-// One step of the single member with every transform a product with D.
-// Data flow (FP32, row-major [field][y][x]): stencil -> rm; rows: D_x rm ->
-// mid (the 8 fields' rows stacked); columns: mid_f D_y^T -> rm (2D spectra);
-// inner products, 5x5; combine -> outc; columns: outc_f D_y -> mid; rows:
-// D_x^T mid -> outc; state update.
+// Grid of the passes in front of the factored transforms' first product.
+dim3 fs_grid(uint32_t total) {
+  return dim3(std::min<uint32_t>((total + FS_THREADS - 1) / FS_THREADS, 16384u));
+}
+
+// The factored transforms' products take three bf16 parts per operand.
+constexpr int kFsProducts = 6;
+
+// DCT-II (inverse = false) or DCT-III along x of `lines` contiguous rows,
+// src -> dst: one product with D (D^T), or the factored transform, whose
+// forward direction also uses dst for the reordered lines.
+void gemm_dct_rows(const Member& m, hipStream_t st, const float* src, float* dst, int lines,
+                   bool inverse) {
+  const int nx = m.p.nx;
+  const FsMats& f = m.fsx;
+  if (f.l1 == 0) {
+    const MfMat d = inverse ? MfMat{{m.dxt_hi, m.dxt_lo, nullptr}}
+                            : MfMat{{m.dx_hi, m.dx_lo, nullptr}};
+    mf_product<MF_ROW>(st, d, src, dst, nx, lines, nx, nx, nx, 0, 0, 1);
+    return;
+  }
+  constexpr int NP = kFsProducts;
+  const int n1 = 1 << f.l1, n2 = 1 << f.l2, ln = f.l1 + f.l2;
+  const uint32_t total = (uint32_t)lines << ln;
+  float* t = m.fs_w;                                   // T: 2 nx per line
+  const dim3 g = fs_grid(total), b(FS_THREADS);
+  if (!inverse) {
+    const FsArgs fa{f.l1, f.l2, 0, f.twf};
+    hipLaunchKernelGGL(k_fs_reorder_rows, g, b, 0, st, src, dst, ln, total);
+    mf_product<MF_COL, EPI_TW_M, NP>(st, f.d1, dst, t, n2, 2 * n1, n1, n2, n2, (size_t)nx,
+                                     2 * (size_t)nx, lines, fa);
+    mf_product<MF_ROW, EPI_POST_ROWS, NP>(st, f.d2, t, dst, n2, lines * n1, 2 * n2, 2 * n2, 0,
+                                          0, 0, 1, fa);
+  } else {
+    const FsArgs fa{f.l1, f.l2, 0, f.twi};
+    float* zz = m.fs_w + (size_t)2 * lines * nx;      // Z: 2 nx per line, after T
+    hipLaunchKernelGGL(k_fs_pre_inv_rows, g, b, 0, st, src, zz, ln, total);
+    mf_product<MF_COL, EPI_TW_M, NP>(st, f.d1i, zz, t, n2, 2 * n1, 2 * n1, n2, n2,
+                                     2 * (size_t)nx, 2 * (size_t)nx, lines, fa);
+    mf_product<MF_ROW, EPI_IPOST_ROWS, NP>(st, f.d2i, t, dst, n2, lines * n1, 2 * n2, 2 * n2, 0,
+                                           0, 0, 1, fa);
+  }
+}
+
+// DCT-II or DCT-III along y of `fields` fields of ny x nx values, src -> dst.
+void gemm_dct_cols(const Member& m, hipStream_t st, const float* src, float* dst, int fields,
+                   bool inverse) {
+  const int nx = m.p.nx, ny = m.p.ny;
+  const size_t cells = (size_t)nx * ny;
+  const FsMats& f = m.fsy;
+  if (f.l1 == 0) {
+    const MfMat d = inverse ? MfMat{{m.dyt_hi, m.dyt_lo, nullptr}}
+                            : MfMat{{m.dy_hi, m.dy_lo, nullptr}};
+    mf_product<MF_COL>(st, d, src, dst, nx, ny, ny, nx, nx, cells, cells, fields);
+    return;
+  }
+  constexpr int NP = kFsProducts;
+  const int n1 = 1 << f.l1, n2 = 1 << f.l2, ln = f.l1 + f.l2, lx = m.lx;
+  const uint32_t total = (uint32_t)fields << (ln + lx);
+  const int ld = n2 * nx;                  // stride of n1 (and of k1 in T) in a field
+  const size_t sv = 2 * (size_t)n2 * nx;   // one k1 block of T
+  float* t = m.fs_w;                       // T: 2 cells per field
+  const dim3 g = fs_grid(total), b(FS_THREADS);
+  if (!inverse) {
+    const FsArgs fa{f.l1, f.l2, lx, f.twf};
+    hipLaunchKernelGGL(k_fs_reorder_cols, g, b, 0, st, src, dst, ln, lx, total);
+    for (int fl = 0; fl < fields; ++fl)
+      mf_product<MF_COL, EPI_TW_Z, NP>(st, f.d1, dst + fl * cells, t + 2 * fl * cells, nx,
+                                       2 * n1, n1, ld, ld, (size_t)nx, (size_t)nx, n2, fa);
+    mf_product<MF_COL, EPI_POST_COLS, NP>(st, f.d2, t, dst, nx, n2, 2 * n2, nx, 0, sv, 0,
+                                          fields * n1, fa);
+  } else {
+    const FsArgs fa{f.l1, f.l2, lx, f.twi};
+    float* zz = m.fs_w + 2 * fields * cells;   // Z: 2 cells per field, after T
+    hipLaunchKernelGGL(k_fs_pre_inv_cols, g, b, 0, st, src, zz, ln, lx, total);
+    for (int fl = 0; fl < fields; ++fl)
+      mf_product<MF_COL, EPI_TW_Z, NP>(st, f.d1i, zz + 2 * fl * cells, t + 2 * fl * cells, nx,
+                                       2 * n1, 2 * n1, ld, ld, (size_t)nx, (size_t)nx, n2, fa);
+    mf_product<MF_COL, EPI_IPOST_COLS, NP>(st, f.d2i, t, dst, nx, n2, 2 * n2, nx, 0, sv, 0,
+                                           fields * n1, fa);
+  }
+}
+
+// One step of the single member with every transform on the matrix cores.
+// Data flow (FP32, row-major [field][y][x]): stencil -> rm; rows: DCT along x
+// rm -> mid (the 8 fields' rows stacked); columns: DCT along y mid -> rm (2D
+// spectra); inner products, 5x5; combine -> outc; columns: inverse along y
+// outc -> mid; rows: inverse along x mid -> outc; state update.
 int enqueue_step_gemm(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEvents pe) {
   const Member& m = c->mem[0];
   const SizeClass& k = c->cls[0];
@@ -777,10 +904,10 @@ int enqueue_step_gemm(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEvents 
                      dim3(STENCIL_THREADS), 0, st, tab, k.d_idx, k.sh.blocks, k.sh.blocks);
   pe.mark(1, st);
   pe.mark(2, st);
-  mf_product<MF_ROW>(st, m.dx_hi, m.dx_lo, rm, mid, nx, M_NFIELD * ny, nx, nx, nx, 0, 0, 1);
+  gemm_dct_rows(m, st, rm, mid, M_NFIELD * ny, false);
   pe.mark(3, st);
   pe.mark(4, st);
-  mf_product<MF_COL>(st, m.dy_hi, m.dy_lo, mid, rm, nx, ny, ny, nx, nx, cells, cells, M_NFIELD);
+  gemm_dct_cols(m, st, mid, rm, M_NFIELD, false);
   hipLaunchKernelGGL(k_gemm_gram, dim3((unsigned)gemm_gram_blocks(&m.p)), dim3(GEMM_THREADS), 0,
                      st, rm, m.lamx, m.lamy, m.part2, nx, ny, kGramPerThread, ha.k);
   pe.mark(5, st);
@@ -791,12 +918,12 @@ int enqueue_step_gemm(ccmsav_ctx* c, int64_t level, hipStream_t st, PhaseEvents 
   hipLaunchKernelGGL(k_gemm_combine, dim3((unsigned)std::min<size_t>(cells / GEMM_THREADS + 1, 8192)),
                      dim3(GEMM_THREADS), 0, st, rm, m.ds->coef, m.lamx, m.lamy, outc, nx, ny,
                      ha.k);
-  mf_product<MF_COL>(st, m.dyt_hi, m.dyt_lo, outc, mid, nx, ny, ny, nx, nx, cells, cells, 2);
+  gemm_dct_cols(m, st, outc, mid, 2, true);
   hipLaunchKernelGGL(k_gemm_colsum, dim3(1), dim3(GEMM_THREADS), 0, st, mid + cells, m.colsum,
                      nx, ny);
   pe.mark(9, st);
   pe.mark(10, st);
-  mf_product<MF_ROW>(st, m.dxt_hi, m.dxt_lo, mid, outc, nx, 2 * ny, nx, nx, nx, 0, 0, 1);
+  gemm_dct_rows(m, st, mid, outc, 2 * ny, true);
   const int sn = (int)(level % 3), snew = (int)((level + 1) % 3);
   hipLaunchKernelGGL(k_gemm_finalize, dim3(ny), dim3(GEMM_THREADS), 0, st, outc, m.phi[sn],
                      m.psi[sn], m.colsum, m.phi[snew], m.psi[snew], nx, ny);
@@ -1090,6 +1217,82 @@ int upload_dct_matrix(uint16_t* out, int n, hipStream_t st) {
   const bool ok =
       hipMemcpyAsync(out, h.data(), h.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st) ==
       hipSuccess;
+  // the host table must outlive the copy, also when it failed
+  if (hipStreamSynchronize(st) != hipSuccess || !ok) return CCMSAV_EHIP;
+  return CCMSAV_OK;
+}
+
+// The matrices and tables of the factored transform of n1 n2 points (FsMats),
+// built in FP64: each matrix as three bf16 parts at out (the matrices one
+// after another, each as hi, mid, lo), the two tables as float2 behind them.
+int upload_fs_matrices(void* out, int n1, int n2, hipStream_t st, FsMats& f) {
+  const int n = n1 * n2;
+  const size_t e1 = 2 * (size_t)n1 * n1, e2 = 2 * (size_t)n2 * n2, e3 = 4 * (size_t)n1 * n1,
+               e4 = 2 * (size_t)n2 * n2;
+  const size_t o1 = 0, o2 = 3 * e1, o3 = o2 + 3 * e2, o4 = o3 + 3 * e3;
+  const size_t tab = fs_table_offset(n1, n2);
+  std::vector<uint8_t> h(tab + 2 * (size_t)n * sizeof(float2), 0);
+  uint16_t* hm = reinterpret_cast<uint16_t*>(h.data());
+  // v = hi + mid + lo, each part the bf16 rounding of what the earlier leave
+  auto put = [&](size_t off, size_t e, size_t idx, double v) {
+    for (int q = 0; q < 3; ++q) {
+      const uint16_t b = host_bf16((float)v);
+      hm[off + q * e + idx] = b;
+      v -= (double)host_bf16_to_f32(b);
+    }
+  };
+  // exp(-i pi num / den) as (c, s), num reduced mod 2 den first
+  auto ex = [](long num, long den, double& c, double& sn) {
+    const double a = M_PI * (double)(num % (2 * den)) / (double)den;
+    c = std::cos(a);
+    sn = -std::sin(a);
+  };
+  const double up = std::sqrt(0.5 * n), down = std::sqrt(2.0 / n);
+  double c, sn;
+  for (int k = 0; k < n1; ++k)
+    for (int j = 0; j < n1; ++j) {
+      ex(2L * j * k, n1, c, sn);               // W_N1^(jk)
+      put(o1, e1, (size_t)(2 * k) * n1 + j, c);
+      put(o1, e1, (size_t)(2 * k + 1) * n1 + j, sn);
+      ex((long)j * (4 * k + 1), 2L * n1, c, sn);
+      c *= up;
+      sn *= up;
+      const size_t w = 2 * (size_t)n1;
+      put(o3, e3, (size_t)(2 * k) * w + j, c);
+      put(o3, e3, (size_t)(2 * k) * w + n1 + j, -sn);
+      put(o3, e3, (size_t)(2 * k + 1) * w + j, sn);
+      put(o3, e3, (size_t)(2 * k + 1) * w + n1 + j, c);
+    }
+  for (int k = 0; k < n2; ++k)
+    for (int j = 0; j < n2; ++j) {
+      const size_t w = 2 * (size_t)n2;
+      ex((long)k * (4 * j + 1), 2L * n2, c, sn);
+      put(o2, e2, (size_t)k * w + j, down * c);
+      put(o2, e2, (size_t)k * w + n2 + j, -down * sn);
+      ex(2L * j * k, n2, c, sn);               // W_N2^(jk)
+      put(o4, e4, (size_t)k * w + j, c / n);
+      put(o4, e4, (size_t)k * w + n2 + j, -sn / n);
+    }
+  float2* tw = reinterpret_cast<float2*>(h.data() + tab);
+  for (int k1 = 0; k1 < n1; ++k1)
+    for (int j = 0; j < n2; ++j) {
+      ex((long)k1 * (4 * j + 1), 2L * n, c, sn);
+      tw[(size_t)k1 * n2 + j] = make_float2((float)c, (float)sn);
+      ex((long)j * (4 * k1 + 1), 2L * n, c, sn);
+      tw[(size_t)n + (size_t)k1 * n2 + j] = make_float2((float)c, (float)sn);
+    }
+  const uint16_t* dm = static_cast<const uint16_t*>(out);
+  auto mat = [&](size_t off, size_t e) { return MfMat{{dm + off, dm + off + e, dm + off + 2 * e}}; };
+  f.l1 = log2_exact(n1);
+  f.l2 = log2_exact(n2);
+  f.d1 = mat(o1, e1);
+  f.d2 = mat(o2, e2);
+  f.d1i = mat(o3, e3);
+  f.d2i = mat(o4, e4);
+  f.twf = reinterpret_cast<const float2*>(static_cast<const char*>(out) + tab);
+  f.twi = f.twf + n;
+  const bool ok =
+      hipMemcpyAsync(out, h.data(), h.size(), hipMemcpyHostToDevice, st) == hipSuccess;
   // the host table must outlive the copy, also when it failed
   if (hipStreamSynchronize(st) != hipSuccess || !ok) return CCMSAV_EHIP;
   return CCMSAV_OK;
@@ -1413,18 +1616,23 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
       m.cl_sc = reinterpret_cast<PcgScalars*>(mb + L.clsc);
     }
     if (is_gemm(m.p.precision)) {
-      const size_t nxx = (size_t)m.p.nx * m.p.nx, nyy = (size_t)m.p.ny * m.p.ny;
-      m.dx_hi = reinterpret_cast<uint16_t*>(mb + L.dx);
-      m.dx_lo = m.dx_hi + nxx;
-      m.dxt_hi = m.dx_hi + 2 * nxx;
-      m.dxt_lo = m.dx_hi + 3 * nxx;
-      m.dy_hi = reinterpret_cast<uint16_t*>(mb + L.dy);
-      m.dy_lo = m.dy_hi + nyy;
-      m.dyt_hi = m.dy_hi + 2 * nyy;
-      m.dyt_lo = m.dy_hi + 3 * nyy;
-      if (upload_dct_matrix(m.dx_hi, m.p.nx, c->stream) != CCMSAV_OK ||
-          upload_dct_matrix(m.dy_hi, m.p.ny, c->stream) != CCMSAV_OK)
+      // per direction: the factored transform's DFT matrices, or D and D^T
+      auto setup = [&](int n, size_t off, FsMats& f, uint16_t*& d_hi, uint16_t*& d_lo,
+                       uint16_t*& dt_hi, uint16_t*& dt_lo) {
+        uint16_t* q = reinterpret_cast<uint16_t*>(mb + off);
+        d_hi = d_lo = dt_hi = dt_lo = nullptr;
+        if (const int n1 = fs_n1(n)) return upload_fs_matrices(mb + off, n1, n / n1, c->stream, f);
+        const size_t nn = (size_t)n * n;
+        d_hi = q;
+        d_lo = q + nn;
+        dt_hi = q + 2 * nn;
+        dt_lo = q + 3 * nn;
+        return upload_dct_matrix(q, n, c->stream);
+      };
+      if (setup(m.p.nx, L.dx, m.fsx, m.dx_hi, m.dx_lo, m.dxt_hi, m.dxt_lo) != CCMSAV_OK ||
+          setup(m.p.ny, L.dy, m.fsy, m.dy_hi, m.dy_lo, m.dyt_hi, m.dyt_lo) != CCMSAV_OK)
         return fail(CCMSAV_EHIP);
+      m.fs_w = uses_fs(&m.p) ? reinterpret_cast<float*>(mb + L.fs) : nullptr;
     }
 
     // Eigenvalues of -Delta_h per direction (App. C): (4/h^2) sin^2(pi k / (2 n)).

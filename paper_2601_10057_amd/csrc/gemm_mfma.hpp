@@ -1,21 +1,26 @@
-// Dense products with the orthonormal DCT matrix on the gfx950 matrix cores,
-// for the DCT-as-GEMM variant of the step: bfloat16 operands split in hi/lo
-// halves, three products (hi hi + hi lo + lo hi) accumulated in FP32 by
-// v_mfma_f32_32x32x16_bf16.
+// Products with constant matrices on the gfx950 matrix cores, for the
+// DCT-as-GEMM variant of the step: bfloat16 operands split into parts,
+// products of the parts accumulated in FP32 by v_mfma_f32_32x32x16_bf16 --
+// three of them (hi hi + hi lo + lo hi) for two parts per operand, six for
+// three parts (mf_parts).
 //
-// Every product of the step pairs a constant matrix d (a DCT matrix or its
-// transpose, split once at context creation, row-major with K contiguous)
-// with an FP32 data operand x that is split into bf16 halves while it is
-// staged into LDS, so no separate splitting pass touches HBM:
+// Every product of the step pairs a constant matrix d (a DCT matrix, its
+// transpose, or a DFT matrix of the factored transforms, split once at
+// context creation, row-major with K contiguous) with an FP32 data operand x
+// that is split into bf16 parts while it is staged into LDS, so no separate
+// splitting pass touches HBM:
 //   row mode (transforms along x): C(m, n) = sum_k d[m K + k] x[n ldx + k],
 //     the data rows of all fields stacked along n;
 //   column mode (transforms along y): C(m, n) = sum_k x[k ldx + m] d[n K + k],
-//     one field per batch entry.
-// Both write C(m, n) at c[n ldc + m], so that an output row is contiguous.
+//     one field (or block of a field) per batch entry.
+// Both write C(m, n) at c[n ldc + m], so that an output row is contiguous,
+// or pass it through an epilogue of the factored transforms
+// (gemm_fourstep.hpp).
 #pragma once
 #include <stdint.h>
 
 #include "gemm_dct.hpp"
+#include "gemm_fourstep.hpp"
 
 namespace ccm {
 
@@ -43,18 +48,36 @@ __device__ __forceinline__ int mf_slot(int line, int k8) {
   return line * MF_ROW16 + (k8 ^ ((line >> 2) & 3));
 }
 
-// x = hi + lo + O(2^-16 |x|): bfloat16 halves of eight FP32 values.
-__device__ __forceinline__ void split8(const float (&v)[8], bf16x8_t& hi, bf16x8_t& lo) {
-  u16x8_t h, l;
+// x = x_0 + .. + x_{P-1} + O(2^-(9 + 8 (P-1)) |x|): P bfloat16 parts of
+// eight FP32 values, each the rounding of what the earlier parts leave.
+template <int P>
+__device__ __forceinline__ void split8(const float (&v)[8], bf16x8_t (&part)[P]) {
+  float r[8];
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const uint16_t he = bf16_rne(v[e]);
-    h[e] = he;
-    l[e] = bf16_rne(v[e] - bf16_to_f32(he));
+  for (int e = 0; e < 8; ++e) r[e] = v[e];
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    u16x8_t h;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      h[e] = bf16_rne(r[e]);
+      r[e] -= bf16_to_f32(h[e]);
+    }
+    part[q] = __builtin_bit_cast(bf16x8_t, h);
   }
-  hi = __builtin_bit_cast(bf16x8_t, h);
-  lo = __builtin_bit_cast(bf16x8_t, l);
 }
+
+// A constant matrix operand as bf16 parts (hi, lo; or hi, mid, lo), each
+// row-major with K contiguous.
+struct MfMat {
+  const uint16_t* part[3];
+};
+
+// Products per K step: NP = 3 takes two parts per operand and the terms
+// hi hi, hi lo, lo hi (relative error about 2^-16); NP = 6 three parts and
+// every term whose parts' orders add up to at most 2 (about 2^-24, the
+// rounding of FP32).
+__host__ __device__ constexpr int mf_parts(int np) { return np == 6 ? 3 : 2; }
 
 // Block tile (m0, n0) and batch entry z of block b: blocks are spread over
 // the eight XCDs in contiguous ranges (xcd_remap), and within a batch entry
@@ -80,16 +103,18 @@ __device__ __forceinline__ void mf_block_tile(int mb_count, int nb_count, int& z
 
 // C = the product of MODE (above) for an M x N tile grid of BM x BN blocks,
 // batch entries z = 0 .. gridDim.x / (M/BM N/BN) - 1 at strides sx (x) and sc
-// (c); d_hi, d_lo are shared by the batch.
-template <int MODE, int BM, int BN>
+// (c); d is shared by the batch. EPI: how C is stored (FsEpilogue); NP: the
+// products per K step (mf_parts).
+template <int MODE, int BM, int BN, int EPI, int NP>
 __global__ void __launch_bounds__(MF_THREADS)
-k_gemm_bf16x3(const uint16_t* __restrict__ d_hi, const uint16_t* __restrict__ d_lo,
-              const float* __restrict__ x, float* __restrict__ c, int M, int N, int K,
-              int ldx, int ldc, size_t sx, size_t sc) {
+k_gemm_bf16x3(MfMat d, const float* __restrict__ x, float* __restrict__ c, int M, int N, int K,
+              int ldx, int ldc, size_t sx, size_t sc, FsArgs fa) {
+  constexpr bool SWAP = fs_swapped(EPI);
+  constexpr int PT = mf_parts(NP);
   constexpr int TM = BM / 64, TN = BN / 64;   // 32 x 32 subtiles per wave along m, n
-  // LDS tiles, hi and lo: lines indexed by m (Lm) and by n (Ln), K contiguous.
-  __shared__ bf16x8_t Lm_hi[BM * MF_ROW16], Lm_lo[BM * MF_ROW16];
-  __shared__ bf16x8_t Ln_hi[BN * MF_ROW16], Ln_lo[BN * MF_ROW16];
+  // LDS tiles per part: lines indexed by m (Lm) and by n (Ln), K contiguous.
+  __shared__ bf16x8_t Lm[PT][BM * MF_ROW16];
+  __shared__ bf16x8_t Ln[PT][BN * MF_ROW16];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   int z, mb, nb;
@@ -106,12 +131,15 @@ k_gemm_bf16x3(const uint16_t* __restrict__ d_hi, const uint16_t* __restrict__ d_
   constexpr int CX = RX * 4 / MF_THREADS;        // 8-value chunks per thread (x)
   const int d0 = MODE == MF_ROW ? m0 : n0;
   const int x0 = MODE == MF_ROW ? n0 : m0;
-  bf16x8_t* Ld_hi = MODE == MF_ROW ? Lm_hi : Ln_hi;
-  bf16x8_t* Ld_lo = MODE == MF_ROW ? Lm_lo : Ln_lo;
-  bf16x8_t* Lx_hi = MODE == MF_ROW ? Ln_hi : Lm_hi;
-  bf16x8_t* Lx_lo = MODE == MF_ROW ? Ln_lo : Lm_lo;
+  // LDS slot i of part q of the d tile and of the x tile
+  auto ld = [&](int q, int i) -> bf16x8_t& {
+    if constexpr (MODE == MF_ROW) return Lm[q][i]; else return Ln[q][i];
+  };
+  auto lx = [&](int q, int i) -> bf16x8_t& {
+    if constexpr (MODE == MF_ROW) return Ln[q][i]; else return Lm[q][i];
+  };
 
-  bf16x8_t rd_hi[CD], rd_lo[CD];
+  bf16x8_t rd[CD][PT];
   float rx[CX][8];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -120,8 +148,8 @@ k_gemm_bf16x3(const uint16_t* __restrict__ d_hi, const uint16_t* __restrict__ d_
       const int ch = tid + i * MF_THREADS;
       const int r = ch >> 2, k8 = ch & 3;
       const size_t o = (size_t)(d0 + r) * K + k0 + 8 * k8;
-      rd_hi[i] = *reinterpret_cast<const bf16x8_t*>(d_hi + o);
-      rd_lo[i] = *reinterpret_cast<const bf16x8_t*>(d_lo + o);
+#pragma unroll
+      for (int q = 0; q < PT; ++q) rd[i][q] = *reinterpret_cast<const bf16x8_t*>(d.part[q] + o);
     }
 #pragma unroll
     for (int i = 0; i < CX; ++i) {
@@ -150,8 +178,8 @@ k_gemm_bf16x3(const uint16_t* __restrict__ d_hi, const uint16_t* __restrict__ d_
     for (int i = 0; i < CD; ++i) {
       const int ch = tid + i * MF_THREADS;
       const int r = ch >> 2, k8 = ch & 3;
-      Ld_hi[mf_slot(r, k8)] = rd_hi[i];
-      Ld_lo[mf_slot(r, k8)] = rd_lo[i];
+#pragma unroll
+      for (int q = 0; q < PT; ++q) ld(q, mf_slot(r, k8)) = rd[i][q];
     }
 #pragma unroll
     for (int i = 0; i < CX; ++i) {
@@ -159,10 +187,10 @@ k_gemm_bf16x3(const uint16_t* __restrict__ d_hi, const uint16_t* __restrict__ d_
       // row mode: four lanes per line; column mode: consecutive lanes, consecutive lines
       const int s = MODE == MF_ROW ? ch >> 2 : ch % RX;
       const int k8 = MODE == MF_ROW ? ch & 3 : ch / RX;
-      bf16x8_t h, l;
-      split8(rx[i], h, l);
-      Lx_hi[mf_slot(s, k8)] = h;
-      Lx_lo[mf_slot(s, k8)] = l;
+      bf16x8_t part[PT];
+      split8<PT>(rx[i], part);
+#pragma unroll
+      for (int q = 0; q < PT; ++q) lx(q, mf_slot(s, k8)) = part[q];
     }
   };
 
@@ -176,6 +204,13 @@ k_gemm_bf16x3(const uint16_t* __restrict__ d_hi, const uint16_t* __restrict__ d_
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
 
+  // ac += (n-line fragment an) x (m-line fragment bm), operands in the
+  // order the accumulator layout asks for.
+  auto mma = [&](f32x16_t& ac, const bf16x8_t& an, const bf16x8_t& bm) {
+    ac = SWAP ? __builtin_amdgcn_mfma_f32_32x32x16_bf16(bm, an, ac, 0, 0, 0)
+              : __builtin_amdgcn_mfma_f32_32x32x16_bf16(an, bm, ac, 0, 0, 0);
+  };
+
   fetch(0);
   for (int k0 = 0; k0 < K; k0 += MF_BK) {
     __syncthreads();                 // the previous slice's fragments are read
@@ -185,40 +220,50 @@ k_gemm_bf16x3(const uint16_t* __restrict__ d_hi, const uint16_t* __restrict__ d_
 #pragma unroll
     for (int ks = 0; ks < MF_BK / 16; ++ks) {
       const int kc = ks * 2 + (lane >> 5);  // this lane's 8 k of the 16
-      bf16x8_t an_hi[TN], an_lo[TN], bm_hi[TM], bm_lo[TM];
+      bf16x8_t an[PT][TN], bm[PT][TM];
 #pragma unroll
-      for (int a = 0; a < TN; ++a) {
-        const int line = wn + a * 32 + (lane & 31);
-        an_hi[a] = Ln_hi[mf_slot(line, kc)];
-        an_lo[a] = Ln_lo[mf_slot(line, kc)];
-      }
+      for (int q = 0; q < PT; ++q) {
 #pragma unroll
-      for (int b = 0; b < TM; ++b) {
-        const int line = wm + b * 32 + (lane & 31);
-        bm_hi[b] = Lm_hi[mf_slot(line, kc)];
-        bm_lo[b] = Lm_lo[mf_slot(line, kc)];
+        for (int a = 0; a < TN; ++a) an[q][a] = Ln[q][mf_slot(wn + a * 32 + (lane & 31), kc)];
+#pragma unroll
+        for (int b = 0; b < TM; ++b) bm[q][b] = Lm[q][mf_slot(wm + b * 32 + (lane & 31), kc)];
       }
 #pragma unroll
       for (int a = 0; a < TN; ++a)
 #pragma unroll
         for (int b = 0; b < TM; ++b) {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an_hi[a], bm_hi[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an_hi[a], bm_lo[b], acc[a][b], 0, 0, 0);
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(an_lo[a], bm_hi[b], acc[a][b], 0, 0, 0);
+          // the smaller terms first
+          if constexpr (NP == 6) {
+            mma(acc[a][b], an[1][a], bm[1][b]);
+            mma(acc[a][b], an[0][a], bm[2][b]);
+            mma(acc[a][b], an[2][a], bm[0][b]);
+          }
+          mma(acc[a][b], an[0][a], bm[1][b]);
+          mma(acc[a][b], an[1][a], bm[0][b]);
+          mma(acc[a][b], an[0][a], bm[0][b]);
         }
     }
   }
-  // Accumulator element v of lane l: MFMA row (n) (v/4) 8 + (l/32) 4 + v%4,
-  // column (m) l % 32; a wave's store covers 32 consecutive m of two rows.
+  // Accumulator element v of lane l: MFMA row (v/4) 8 + (l/32) 4 + v%4, column
+  // l % 32; rows are n and columns m (swapped: the other way round). Elements
+  // v and v + 1 (v even) are two consecutive rows of one column.
 #pragma unroll
   for (int a = 0; a < TN; ++a)
 #pragma unroll
     for (int b = 0; b < TM; ++b) {
-      const int m = m0 + wm + b * 32 + (lane & 31);
+      const int mb0 = m0 + wm + b * 32, nb0 = n0 + wn + a * 32;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int n = n0 + wn + a * 32 + (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
-        cz[(size_t)n * ldc + m] = acc[a][b][v];
+      for (int v = 0; v < 16; v += 2) {
+        const int r = (v >> 2) * 8 + (lane >> 5) * 4 + (v & 3);
+        const int m = SWAP ? mb0 + r : mb0 + (lane & 31);
+        const int n = SWAP ? nb0 + (lane & 31) : nb0 + r;
+        if constexpr (EPI == EPI_STORE) {
+          cz[(size_t)n * ldc + m] = acc[a][b][v];
+          cz[(size_t)(n + 1) * ldc + m] = acc[a][b][v + 1];
+        } else {
+          fs_epilogue<EPI>(cz, ldc, (uint32_t)z, (uint32_t)m, (uint32_t)n, acc[a][b][v],
+                           acc[a][b][v + 1], fa);
+        }
       }
     }
 }

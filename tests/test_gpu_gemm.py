@@ -1,16 +1,19 @@
-"""The DCT-as-GEMM variant (bf16 hi/lo splits, three products, FP32
-accumulation on the matrix cores) against the FP64 path and the oracle.
+"""The DCT-as-GEMM variant (products on the matrix cores, FP32 accumulation)
+against the FP64 path and the oracle.
 
-Each product carries a relative error of about 2^-16 (two bf16 halves per
-operand, the lo x lo term dropped) of the increment-form residuals it acts on,
-150 times the FP32 rounding of the mixed path. Bounds against the FP64 path:
-1e-6 on the perturbed-vesicle grids (N = 512 and 2048; measured 4e-7 and
-3e-7), whose steps change the fields by a small fraction; 1e-4 on circle128,
-whose time step of 1e-4 changes them by up to a few percent per step, so
-that 2^-16 of the increment is 1e-6 of the field per step (measured 3e-5
-after 100 steps). A wrong sign, index or transpose anywhere in the products
-gives O(1) errors. Mass stays exact to FP64 rounding and the modified energy
-keeps decaying.
+Directions of fewer than 2048 points take the dense product with the DCT
+matrix (bf16 hi/lo splits, three products): a relative error of about 2^-16
+of the increment-form residuals it acts on, 150 times the FP32 rounding of
+the mixed path. Directions of 2048 points and more take the factored form
+(N1-point and N2-point DFT products with a twiddle between them, three-part
+splits and six products): FP32-level rounding. Bounds against the FP64 path:
+1e-6 on the perturbed-vesicle grids (N = 512 dense, 2048 factored; measured
+3.4e-7 and 5e-8), whose steps change the fields by a small fraction; 1e-4 on
+circle128, whose time step of 1e-4 changes them by up to a few percent per
+step, so that 2^-16 of the increment is 1e-6 of the field per step (measured
+2e-5 after 100 steps). A wrong sign, index or transpose anywhere in the
+products gives O(1) errors. Mass stays exact to FP64 rounding and the
+modified energy keeps decaying.
 """
 import sys
 
@@ -18,7 +21,7 @@ import numpy as np
 import pytest
 
 from parity_util import rel_linf
-from workloads import make_workload, circle_member
+from workloads import make_workload, circle_member, vesicle_member
 
 pytestmark = pytest.mark.gpu
 
@@ -65,6 +68,40 @@ def test_gemm_variant_tracks_fp64(name, n, steps, tol):
     note(f"worst rel L-inf {worst:.3e}, mass drift {drift:.2e}")
     assert worst <= tol
     assert drift <= 5e-11
+
+
+def mirrored_tiles(m, rx, ry):
+    """rx x ry copies of a member's fields, every other copy mirrored, so that
+    the tiled fields stay smooth and satisfy the Neumann condition at the seams."""
+    def tile(f):
+        row = np.concatenate([f if i % 2 == 0 else f[:, ::-1] for i in range(rx)], axis=1)
+        return np.ascontiguousarray(
+            np.concatenate([row if j % 2 == 0 else row[::-1] for j in range(ry)], axis=0))
+    ny, nx = m.phi0.shape
+    return type(m)(f"{m.name}_{rx}x{ry}", tile(m.phi0), tile(m.psi0),
+                   dict(m.params, nx=nx * rx, ny=ny * ry), {})
+
+
+@pytest.mark.parametrize("rx,ry", [(8, 1), (1, 4)])
+def test_factored_and_dense_directions_on_rectangles(rx, ry):
+    """Directions of 2048 points and more take the factored transform (N1 x
+    N2 = 32 x 64, 64 x 64, 64 x 128), shorter ones the dense product: a
+    4096 x 512 grid (rows 64 x 64, columns dense) and a 512 x 2048 one (rows
+    dense, columns 32 x 64), mirrored tiles of the 512^2 vesicle of the
+    square-grid case above (the same dynamics per tile), against the FP64
+    path over 60 steps at the same bound. (On tiles of a 256^2 vesicle at its
+    time step the FP32 mixed path itself drifts from FP64 by 2e-5 in ten
+    steps, so those grids cannot tell the transforms' rounding apart.)"""
+    m = mirrored_tiles(make_workload("vesicle1024", 512)[0], rx, ry)
+    note(f"gemm vs fp64 {m.params['nx']}x{m.params['ny']}")
+    m0, ref = run(m, "fp64", 60, 15)
+    m0g, got = run(m, "gemm", 60, 15)
+    assert m0g == m0
+    worst = max(max(rel_linf(g[1], r[1]), rel_linf(g[2], r[2])) for r, g in zip(ref, got))
+    note(f"worst rel L-inf {worst:.3e}")
+    assert worst <= 1e-6
+    for g in got:
+        assert abs(g[5] - m0) <= 5e-11 * abs(m0)
 
 
 def test_gemm_variant_rejects_ensembles_graphs_and_small_grids():

@@ -10,8 +10,8 @@ against properties that hold at any size:
 The mixed path and the DCT-as-GEMM variant are then held to the FP64 path:
 mixed over the workload's 200 steps within 1e-6 (relative L-inf of phi, psi,
 the SAVs), with its mass drift at most 5e-11 and its modified energy decaying;
-DCT-as-GEMM over 20 steps within 1e-6 (its bf16x3 products on the matrix
-cores; measured 4e-7). The mixed path's
+DCT-as-GEMM over 20 steps within 1e-6 (the factored 64 x 128 transforms,
+six bf16 products per step of each; measured 9e-8). The mixed path's
 BDF2 step, the last step of the N = 1024, 2048 and 4096 workloads and the
 BDF1 scheme at N = 4096 are held to the same discrete equations.
 
