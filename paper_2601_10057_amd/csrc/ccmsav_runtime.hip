@@ -197,8 +197,7 @@ Layout layout(const ccmsav_params* p) {
   if (is_gemm(p->precision)) {
     L.dx = off;    off = align_up(off + gemm_mat_bytes(p->nx));
     L.dy = off;    off = align_up(off + gemm_mat_bytes(p->ny));
-    // Re and Im planes of all M_NFIELD fields (the inverse's two fields and
-    // their turned spectra fit as well)
+    // Re and Im planes of all M_NFIELD fields
     if (uses_fs(p)) { L.fs = off; off = align_up(off + 2 * M_NFIELD * cells * sizeof(float)); }
   }
   if (is_periodic(p)) {
@@ -779,39 +778,33 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe,
 // ---- DCT-as-GEMM variant ------------------------------------------------------
 
 // One product of the DCT-as-GEMM variant (gemm_mfma.hpp) with the largest
-// tiles that divide the grid, NP products per K step, stored through the
-// epilogue EPI.
-template <int MODE, int EPI = EPI_STORE, int NP = 3>
+// tiles that divide the grid, NP products per K step, the data operand read
+// as XL says, stored through the epilogue EPI.
+template <int MODE, int EPI = EPI_STORE, int NP = 3, int XL = XL_PLAIN>
 void mf_product(hipStream_t st, const MfMat& d, const float* x, float* out, int M, int N, int K,
                 int ldx, int ldc, size_t sx, size_t sc, int batch,
                 FsArgs fa = FsArgs{0, 0, 0, nullptr}) {
   const int bm = mf_tile(M), bn = mf_tile(N);
   const dim3 grid((unsigned)(batch * (M / bm) * (N / bn)));
   if (bm == 128 && bn == 128)
-    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 128, EPI, NP>), grid, dim3(MF_THREADS), 0, st,
-                       d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 128, EPI, NP, XL>), grid, dim3(MF_THREADS), 0,
+                       st, d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
   else if (bm == 128)
-    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 64, EPI, NP>), grid, dim3(MF_THREADS), 0, st,
-                       d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 64, EPI, NP, XL>), grid, dim3(MF_THREADS), 0,
+                       st, d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
   else if (bn == 128)
-    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 128, EPI, NP>), grid, dim3(MF_THREADS), 0, st,
-                       d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 128, EPI, NP, XL>), grid, dim3(MF_THREADS), 0,
+                       st, d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
   else
-    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 64, EPI, NP>), grid, dim3(MF_THREADS), 0, st,
-                       d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
-}
-
-// Grid of the passes in front of the factored transforms' first product.
-dim3 fs_grid(uint32_t total) {
-  return dim3(std::min<uint32_t>((total + FS_THREADS - 1) / FS_THREADS, 16384u));
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 64, EPI, NP, XL>), grid, dim3(MF_THREADS), 0,
+                       st, d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
 }
 
 // The factored transforms' products take three bf16 parts per operand.
 constexpr int kFsProducts = 6;
 
 // DCT-II (inverse = false) or DCT-III along x of `lines` contiguous rows,
-// src -> dst: one product with D (D^T), or the factored transform, whose
-// forward direction also uses dst for the reordered lines.
+// src -> dst: one product with D (D^T), or the factored transform.
 void gemm_dct_rows(const Member& m, hipStream_t st, const float* src, float* dst, int lines,
                    bool inverse) {
   const int nx = m.p.nx;
@@ -823,23 +816,17 @@ void gemm_dct_rows(const Member& m, hipStream_t st, const float* src, float* dst
     return;
   }
   constexpr int NP = kFsProducts;
-  const int n1 = 1 << f.l1, n2 = 1 << f.l2, ln = f.l1 + f.l2;
-  const uint32_t total = (uint32_t)lines << ln;
+  const int n1 = 1 << f.l1, n2 = 1 << f.l2;
   float* t = m.fs_w;                                   // T: 2 nx per line
-  const dim3 g = fs_grid(total), b(FS_THREADS);
+  const FsArgs fa{f.l1, f.l2, 0, inverse ? f.twi : f.twf};
   if (!inverse) {
-    const FsArgs fa{f.l1, f.l2, 0, f.twf};
-    hipLaunchKernelGGL(k_fs_reorder_rows, g, b, 0, st, src, dst, ln, total);
-    mf_product<MF_COL, EPI_TW_M, NP>(st, f.d1, dst, t, n2, 2 * n1, n1, n2, n2, (size_t)nx,
-                                     2 * (size_t)nx, lines, fa);
+    mf_product<MF_COL, EPI_TW_M, NP, XL_MAKHOUL_ROWS>(st, f.d1, src, t, n2, 2 * n1, n1, 0, n2,
+                                                      0, 2 * (size_t)nx, lines, fa);
     mf_product<MF_ROW, EPI_POST_ROWS, NP>(st, f.d2, t, dst, n2, lines * n1, 2 * n2, 2 * n2, 0,
                                           0, 0, 1, fa);
   } else {
-    const FsArgs fa{f.l1, f.l2, 0, f.twi};
-    float* zz = m.fs_w + (size_t)2 * lines * nx;      // Z: 2 nx per line, after T
-    hipLaunchKernelGGL(k_fs_pre_inv_rows, g, b, 0, st, src, zz, ln, total);
-    mf_product<MF_COL, EPI_TW_M, NP>(st, f.d1i, zz, t, n2, 2 * n1, 2 * n1, n2, n2,
-                                     2 * (size_t)nx, 2 * (size_t)nx, lines, fa);
+    mf_product<MF_COL, EPI_TW_M, NP, XL_Z_ROWS>(st, f.d1i, src, t, n2, 2 * n1, 2 * n1, 0, n2, 0,
+                                                2 * (size_t)nx, lines, fa);
     mf_product<MF_ROW, EPI_IPOST_ROWS, NP>(st, f.d2i, t, dst, n2, lines * n1, 2 * n2, 2 * n2, 0,
                                            0, 0, 1, fa);
   }
@@ -858,30 +845,27 @@ void gemm_dct_cols(const Member& m, hipStream_t st, const float* src, float* dst
     return;
   }
   constexpr int NP = kFsProducts;
-  const int n1 = 1 << f.l1, n2 = 1 << f.l2, ln = f.l1 + f.l2, lx = m.lx;
-  const uint32_t total = (uint32_t)fields << (ln + lx);
-  const int ld = n2 * nx;                  // stride of n1 (and of k1 in T) in a field
+  const int n1 = 1 << f.l1, n2 = 1 << f.l2, lx = m.lx;
+  const int ld = n2 * nx;                  // stride of k1 in T
   const size_t sv = 2 * (size_t)n2 * nx;   // one k1 block of T
   float* t = m.fs_w;                       // T: 2 cells per field
-  const dim3 g = fs_grid(total), b(FS_THREADS);
-  if (!inverse) {
-    const FsArgs fa{f.l1, f.l2, lx, f.twf};
-    hipLaunchKernelGGL(k_fs_reorder_cols, g, b, 0, st, src, dst, ln, lx, total);
-    for (int fl = 0; fl < fields; ++fl)
-      mf_product<MF_COL, EPI_TW_Z, NP>(st, f.d1, dst + fl * cells, t + 2 * fl * cells, nx,
-                                       2 * n1, n1, ld, ld, (size_t)nx, (size_t)nx, n2, fa);
+  const FsArgs fa{f.l1, f.l2, lx, inverse ? f.twi : f.twf};
+  for (int fl = 0; fl < fields; ++fl) {
+    if (!inverse)
+      mf_product<MF_COL, EPI_TW_Z, NP, XL_MAKHOUL_COLS>(st, f.d1, src + fl * cells,
+                                                        t + 2 * fl * cells, nx, 2 * n1, n1, 0,
+                                                        ld, 0, (size_t)nx, n2, fa);
+    else
+      mf_product<MF_COL, EPI_TW_Z, NP, XL_Z_COLS>(st, f.d1i, src + fl * cells,
+                                                  t + 2 * fl * cells, nx, 2 * n1, 2 * n1, 0, ld,
+                                                  0, (size_t)nx, n2, fa);
+  }
+  if (!inverse)
     mf_product<MF_COL, EPI_POST_COLS, NP>(st, f.d2, t, dst, nx, n2, 2 * n2, nx, 0, sv, 0,
                                           fields * n1, fa);
-  } else {
-    const FsArgs fa{f.l1, f.l2, lx, f.twi};
-    float* zz = m.fs_w + 2 * fields * cells;   // Z: 2 cells per field, after T
-    hipLaunchKernelGGL(k_fs_pre_inv_cols, g, b, 0, st, src, zz, ln, lx, total);
-    for (int fl = 0; fl < fields; ++fl)
-      mf_product<MF_COL, EPI_TW_Z, NP>(st, f.d1i, zz + 2 * fl * cells, t + 2 * fl * cells, nx,
-                                       2 * n1, 2 * n1, ld, ld, (size_t)nx, (size_t)nx, n2, fa);
+  else
     mf_product<MF_COL, EPI_IPOST_COLS, NP>(st, f.d2i, t, dst, nx, n2, 2 * n2, nx, 0, sv, 0,
                                            fields * n1, fa);
-  }
 }
 
 // One step of the single member with every transform on the matrix cores.

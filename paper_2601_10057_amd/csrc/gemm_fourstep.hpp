@@ -25,22 +25,20 @@
 // placement of step 3's outputs run in their epilogues. The output rows of
 // both complex-output matrices interleave real and imaginary parts (row
 // 2 k + re/im), so that both parts of one value land in one lane's
-// accumulator (consecutive MFMA rows). The passes left on their own are the
-// reordering (forward) and step 0 (inverse).
+// accumulator (consecutive MFMA rows). The reordering (forward) and step 0
+// (inverse) run in step 1's operand loader.
 //
 // Layouts (FP32) per line (rows: contiguous lines of length N) and per field
 // (columns: the lines run along y, nx columns side by side, x contiguous):
-//   A  reordered line                          rows [n]          cols [n][x]
+//   v  reordered line, read as [n1][n2]        rows [n]          cols [n][x]
 //   T  after step 2, Re and Im rows per k1      rows [k1][2][n2]  cols [k1][2][n2][x]
-//   Z  the inverse's input (planes Re, Im)      rows [2][k]       cols [2][k][x]
+//   Z  the inverse's input, read as [2][a1][a2]  rows [2][k]       cols [2][k][x]
 // Every size is a power of two and is passed as its base-2 logarithm; all
 // flat indices of one buffer fit 32 bits (at most 2^30 values).
 #pragma once
 #include <stdint.h>
 
 namespace ccm {
-
-constexpr int FS_THREADS = 256;
 
 // Epilogues of the matrix-core product (k_gemm_bf16x3).
 enum FsEpilogue {
@@ -64,11 +62,6 @@ struct FsArgs {
   int lx;                // log2 nx (columns)
   const float2* tw;      // step 2's factors, [k1][n2]
 };
-
-// Grid-stride loop over `total` flat indices.
-#define FS_FOR(i, total)                                                        \
-  for (uint32_t i = blockIdx.x * FS_THREADS + threadIdx.x; i < (total);         \
-       i += gridDim.x * FS_THREADS)
 
 // Position in x of v_m.
 __device__ __forceinline__ uint32_t fs_place(uint32_t m, uint32_t n) {
@@ -118,58 +111,46 @@ __device__ __forceinline__ void fs_epilogue(float* __restrict__ c, int ldc, uint
   }
 }
 
-// ---- the passes in front of step 1 -----------------------------------------------
+// ---- step 0 and the reordering, in step 1's operand loader ------------------------
+
+// How step 1 reads its data operand (column mode: element (k, m) of batch entry z).
+enum FsLoad {
+  XL_PLAIN = 0,        // x[z sx + k ldx + m]
+  XL_MAKHOUL_ROWS,     // reordered line z: v[k N2 + m] = x[z N + src(k N2 + m)]
+  XL_MAKHOUL_COLS,     // reordered rows: v[(k N2 + z) nx + m] = x[src(k N2 + z) nx + m]
+  XL_Z_ROWS,           // step 0 of line z: Z[re/im][k' N2 + m], k = re/im N1 + k'
+  XL_Z_COLS,           // step 0 along y: Z[re/im][(k' N2 + z) nx + m]
+};
 
 // Makhoul source index of position j of the reordered line.
 __device__ __forceinline__ uint32_t fs_src(uint32_t j, uint32_t n) {
   return j < n / 2 ? 2 * j : 2 * (n - 1 - j) + 1;
 }
 
-// A = reordered lines of x; total = lines << ln.
-__global__ void __launch_bounds__(FS_THREADS)
-k_fs_reorder_rows(const float* __restrict__ x, float* __restrict__ a, int ln, uint32_t total) {
-  const uint32_t n = 1u << ln;
-  FS_FOR(i, total) {
-    const uint32_t j = i & (n - 1);
-    a[i] = x[(i - j) + fs_src(j, n)];
-  }
+// Step 0 at natural index j of a line whose element i is at y[i * stride]:
+// the real part (re) or the imaginary part.
+__device__ __forceinline__ float fs_z(const float* __restrict__ y, uint32_t j, bool im,
+                                      uint32_t n, uint32_t stride) {
+  if (!im) return j == 0 ? y[0] * 1.41421356237309505f : y[(size_t)j * stride];
+  return j == 0 ? 0.0f : y[(size_t)(n - j) * stride];
 }
 
-// Rows of each field permuted by the reordering; total = fields << (ln + lx).
-__global__ void __launch_bounds__(FS_THREADS)
-k_fs_reorder_cols(const float* __restrict__ x, float* __restrict__ a, int ln, int lx,
-                  uint32_t total) {
-  const uint32_t n = 1u << ln;
-  FS_FOR(i, total) {
-    const uint32_t row = (i >> lx) & (n - 1);
-    a[i] = x[i + ((fs_src(row, n) - row) << lx)];
+// Element (k, m) of batch entry z of step 1's data operand; x is the whole
+// input (not offset by the batch entry).
+template <int XL>
+__device__ __forceinline__ float fs_load(const float* __restrict__ x, uint32_t z, uint32_t k,
+                                         uint32_t m, const FsArgs& f) {
+  const int ln = f.l1 + f.l2;
+  const uint32_t n = 1u << ln, n1m = (1u << f.l1) - 1;
+  if constexpr (XL == XL_MAKHOUL_ROWS) {
+    return x[((size_t)z << ln) + fs_src((k << f.l2) + m, n)];
+  } else if constexpr (XL == XL_MAKHOUL_COLS) {
+    return x[((size_t)fs_src((k << f.l2) + z, n) << f.lx) + m];
+  } else if constexpr (XL == XL_Z_ROWS) {
+    return fs_z(x + ((size_t)z << ln), ((k & n1m) << f.l2) + m, k > n1m, n, 1);
+  } else {
+    return fs_z(x + m, ((k & n1m) << f.l2) + z, k > n1m, n, 1u << f.lx);
   }
 }
-
-// Z (planes Re, Im per line) of the inverse's step 0.
-__global__ void __launch_bounds__(FS_THREADS)
-k_fs_pre_inv_rows(const float* __restrict__ y, float* __restrict__ zz, int ln, uint32_t total) {
-  const uint32_t n = 1u << ln;
-  FS_FOR(i, total) {
-    const uint32_t k = i & (n - 1), line = i - k;
-    zz[2 * line + k] = k == 0 ? y[i] * 1.41421356237309505f : y[i];
-    zz[2 * line + n + k] = k == 0 ? 0.0f : y[line + n - k];
-  }
-}
-
-// Z (planes Re, Im per field) of the inverse's step 0 along y.
-__global__ void __launch_bounds__(FS_THREADS)
-k_fs_pre_inv_cols(const float* __restrict__ y, float* __restrict__ zz, int ln, int lx,
-                  uint32_t total) {
-  const uint32_t n = 1u << ln, fsz = 1u << (ln + lx);
-  FS_FOR(i, total) {
-    const uint32_t e = i & (fsz - 1), fld = i - e;
-    const uint32_t k = e >> lx;
-    zz[2 * fld + e] = k == 0 ? y[i] * 1.41421356237309505f : y[i];
-    zz[2 * fld + fsz + e] = k == 0 ? 0.0f : y[i + ((n - 2 * k) << lx)];
-  }
-}
-
-#undef FS_FOR
 
 }  // namespace ccm

@@ -104,13 +104,15 @@ __device__ __forceinline__ void mf_block_tile(int mb_count, int nb_count, int& z
 // C = the product of MODE (above) for an M x N tile grid of BM x BN blocks,
 // batch entries z = 0 .. gridDim.x / (M/BM N/BN) - 1 at strides sx (x) and sc
 // (c); d is shared by the batch. EPI: how C is stored (FsEpilogue); NP: the
-// products per K step (mf_parts).
-template <int MODE, int BM, int BN, int EPI, int NP>
+// products per K step (mf_parts); XL: how the data operand is read (FsLoad,
+// column mode).
+template <int MODE, int BM, int BN, int EPI, int NP, int XL>
 __global__ void __launch_bounds__(MF_THREADS)
 k_gemm_bf16x3(MfMat d, const float* __restrict__ x, float* __restrict__ c, int M, int N, int K,
               int ldx, int ldc, size_t sx, size_t sc, FsArgs fa) {
   constexpr bool SWAP = fs_swapped(EPI);
   constexpr int PT = mf_parts(NP);
+  static_assert(XL == XL_PLAIN || MODE == MF_COL, "the fused loads are column-mode operands");
   constexpr int TM = BM / 64, TN = BN / 64;   // 32 x 32 subtiles per wave along m, n
   // LDS tiles per part: lines indexed by m (Lm) and by n (Ln), K contiguous.
   __shared__ bf16x8_t Lm[PT][BM * MF_ROW16];
@@ -169,7 +171,12 @@ k_gemm_bf16x3(MfMat d, const float* __restrict__ x, float* __restrict__ c, int M
         // line s = m, eight consecutive k: consecutive lanes read consecutive m
         const int s = ch % RX, k8 = ch / RX;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) rx[i][e] = xz[(size_t)(k0 + 8 * k8 + e) * ldx + x0 + s];
+        for (int e = 0; e < 8; ++e) {
+          if constexpr (XL == XL_PLAIN)
+            rx[i][e] = xz[(size_t)(k0 + 8 * k8 + e) * ldx + x0 + s];
+          else
+            rx[i][e] = fs_load<XL>(x, (uint32_t)z, (uint32_t)(k0 + 8 * k8 + e), (uint32_t)(x0 + s), fa);
+        }
       }
     }
   };
