@@ -44,14 +44,14 @@ def fs_n1(n):
 
 
 def line_flops(n, inverse):
-    """Matrix-core flops of one DCT of n points (2 m n k per product). Dense:
-    three bf16 products with the n x n matrix, 6 n^2. Factored (n = N1 N2, six
-    bf16 products of three-part operands, real and imaginary parts stacked):
-    forward 2 N1 x N1 and N2 x 2 N2 matrices, 24 (N1 + N2) n; inverse
-    2 N1 x 2 N1 and N2 x 2 N2, 48 N1 n + 24 N2 n."""
+    """Matrix-core flops of one DCT of n points: six bf16 products of
+    three-part operands, 2 m n k flops each. Dense: the n x n matrix, 12 n^2.
+    Factored (n = N1 N2, real and imaginary parts stacked): forward 2 N1 x N1
+    and N2 x 2 N2 matrices, 24 (N1 + N2) n; inverse 2 N1 x 2 N1 and N2 x 2 N2,
+    48 N1 n + 24 N2 n."""
     n1 = fs_n1(n)
     if n1 == 0:
-        return 3 * 2.0 * n * n
+        return 6 * 2.0 * n * n
     n2 = n // n1
     return 6 * 2.0 * n * ((4 * n1 + 2 * n2) if inverse else (2 * n1 + 2 * n2))
 

@@ -65,19 +65,18 @@ typedef enum {
                                that h^2 sum psi is conserved to FP64 rounding.
                                FP64 state, SAVs, inner-product sums and 5x5 */
   CCMSAV_MIXED_GEMM_BF16X3 = 2 /* as CCMSAV_MIXED, with every transform on the
-                               matrix cores (the library's bf16 MFMA kernels),
-                               products accumulated in FP32. A direction of
-                               fewer than 2048 points takes a dense product
-                               with the DCT matrix, bfloat16 hi/lo splits of
-                               both operands and three products (hi hi + hi lo
-                               + lo hi); a direction of 2048 or more the
-                               factored form N = N1 N2 (FFT means: an N1-point
-                               and an N2-point DFT product with a twiddle
-                               between them), three-part splits and six
-                               products (FP32-level rounding). The matrices
-                               live in the workspace. Single-member contexts
-                               without CCMSAV_FLAG_GRAPH, grids of at least 64
-                               per direction (else EUNSUPPORTED). */
+                               matrix cores (the library's bf16 MFMA kernels):
+                               both operands split into three bfloat16 parts,
+                               six products of parts accumulated in FP32 (the
+                               rounding of FP32 products). A direction of fewer
+                               than 2048 points is a dense product with the DCT
+                               matrix; a longer one takes the factored form
+                               N = N1 N2 (FFT means: an N1-point and an
+                               N2-point DFT product with a twiddle between
+                               them). The matrices live in the workspace.
+                               Single-member contexts without
+                               CCMSAV_FLAG_GRAPH, grids of at least 64 per
+                               direction (else EUNSUPPORTED). */
 } ccmsav_precision;
 
 /*

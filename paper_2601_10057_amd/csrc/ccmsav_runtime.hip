@@ -155,11 +155,11 @@ size_t fs_mat_elems(int n1, int n2) {
   return 3 * (6 * (size_t)n1 * n1 + 4 * (size_t)n2 * n2);
 }
 size_t fs_table_offset(int n1, int n2) { return align_up(fs_mat_elems(n1, n2) * sizeof(uint16_t)); }
-// Bytes of a direction's transform data: D and D^T (hi and lo halves each), or
+// Bytes of a direction's transform data: D and D^T (three bf16 parts each), or
 // the factored transform's matrices and its two tables of n float2 factors.
 size_t gemm_mat_bytes(int n) {
   const int n1 = fs_n1(n);
-  if (n1 == 0) return 4 * (size_t)n * n * sizeof(uint16_t);
+  if (n1 == 0) return 6 * (size_t)n * n * sizeof(uint16_t);
   return fs_table_offset(n1, n / n1) + 2 * (size_t)n * sizeof(float2);
 }
 bool uses_fs(const ccmsav_params* p) { return fs_n1(p->nx) != 0 || fs_n1(p->ny) != 0; }
@@ -422,19 +422,12 @@ struct Member {
   double* unit_coef;       // {1, 0, 0, 0, 0, 1, 0, 0} for the standalone solve
   DevScalars* ds;
   StencilShape sh;
-  // GEMM variant: bf16 hi and lo halves of the orthonormal DCT-II matrix D
-  // and of its transpose per direction, row-major (dense directions), or the
-  // DFT matrices of the factored transform (fsx, fsy) and its work buffers
+  // GEMM variant: per direction, the orthonormal DCT-II matrix D and its
+  // transpose as bf16 parts, row-major (dense directions), or the matrices of
+  // the factored transform (fsx, fsy) and its work buffer
   FsMats fsx, fsy;
   float* fs_w;
-  uint16_t* dx_hi;
-  uint16_t* dx_lo;
-  uint16_t* dxt_hi;
-  uint16_t* dxt_lo;
-  uint16_t* dy_hi;
-  uint16_t* dy_lo;
-  uint16_t* dyt_hi;
-  uint16_t* dyt_lo;
+  MfMat dx, dxt, dy, dyt;
   // periodic step: chi^{-1} of S~, H, Q~, K~
   double* psol;
   // classical scheme: PCG fields (x, r, p0, p1, q, z; two systems each) and
@@ -778,30 +771,27 @@ void enqueue_step_kind(ccmsav_ctx* c, int table, hipStream_t st, PhaseEvents pe,
 // ---- DCT-as-GEMM variant ------------------------------------------------------
 
 // One product of the DCT-as-GEMM variant (gemm_mfma.hpp) with the largest
-// tiles that divide the grid, NP products per K step, the data operand read
-// as XL says, stored through the epilogue EPI.
-template <int MODE, int EPI = EPI_STORE, int NP = 3, int XL = XL_PLAIN>
+// tiles that divide the grid, the data operand read as XL says, stored
+// through the epilogue EPI.
+template <int MODE, int EPI = EPI_STORE, int XL = XL_PLAIN>
 void mf_product(hipStream_t st, const MfMat& d, const float* x, float* out, int M, int N, int K,
                 int ldx, int ldc, size_t sx, size_t sc, int batch,
                 FsArgs fa = FsArgs{0, 0, 0, nullptr}) {
   const int bm = mf_tile(M), bn = mf_tile(N);
   const dim3 grid((unsigned)(batch * (M / bm) * (N / bn)));
   if (bm == 128 && bn == 128)
-    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 128, EPI, NP, XL>), grid, dim3(MF_THREADS), 0,
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 128, EPI, XL>), grid, dim3(MF_THREADS), 0,
                        st, d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
   else if (bm == 128)
-    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 64, EPI, NP, XL>), grid, dim3(MF_THREADS), 0,
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 128, 64, EPI, XL>), grid, dim3(MF_THREADS), 0,
                        st, d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
   else if (bn == 128)
-    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 128, EPI, NP, XL>), grid, dim3(MF_THREADS), 0,
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 128, EPI, XL>), grid, dim3(MF_THREADS), 0,
                        st, d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
   else
-    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 64, EPI, NP, XL>), grid, dim3(MF_THREADS), 0,
+    hipLaunchKernelGGL((k_gemm_bf16x3<MODE, 64, 64, EPI, XL>), grid, dim3(MF_THREADS), 0,
                        st, d, x, out, M, N, K, ldx, ldc, sx, sc, fa);
 }
-
-// The factored transforms' products take three bf16 parts per operand.
-constexpr int kFsProducts = 6;
 
 // DCT-II (inverse = false) or DCT-III along x of `lines` contiguous rows,
 // src -> dst: one product with D (D^T), or the factored transform.
@@ -810,24 +800,22 @@ void gemm_dct_rows(const Member& m, hipStream_t st, const float* src, float* dst
   const int nx = m.p.nx;
   const FsMats& f = m.fsx;
   if (f.l1 == 0) {
-    const MfMat d = inverse ? MfMat{{m.dxt_hi, m.dxt_lo, nullptr}}
-                            : MfMat{{m.dx_hi, m.dx_lo, nullptr}};
-    mf_product<MF_ROW>(st, d, src, dst, nx, lines, nx, nx, nx, 0, 0, 1);
+    mf_product<MF_ROW>(st, inverse ? m.dxt : m.dx, src, dst, nx,
+                                                 lines, nx, nx, nx, 0, 0, 1);
     return;
   }
-  constexpr int NP = kFsProducts;
   const int n1 = 1 << f.l1, n2 = 1 << f.l2;
   float* t = m.fs_w;                                   // T: 2 nx per line
   const FsArgs fa{f.l1, f.l2, 0, inverse ? f.twi : f.twf};
   if (!inverse) {
-    mf_product<MF_COL, EPI_TW_M, NP, XL_MAKHOUL_ROWS>(st, f.d1, src, t, n2, 2 * n1, n1, 0, n2,
+    mf_product<MF_COL, EPI_TW_M, XL_MAKHOUL_ROWS>(st, f.d1, src, t, n2, 2 * n1, n1, 0, n2,
                                                       0, 2 * (size_t)nx, lines, fa);
-    mf_product<MF_ROW, EPI_POST_ROWS, NP>(st, f.d2, t, dst, n2, lines * n1, 2 * n2, 2 * n2, 0,
+    mf_product<MF_ROW, EPI_POST_ROWS>(st, f.d2, t, dst, n2, lines * n1, 2 * n2, 2 * n2, 0,
                                           0, 0, 1, fa);
   } else {
-    mf_product<MF_COL, EPI_TW_M, NP, XL_Z_ROWS>(st, f.d1i, src, t, n2, 2 * n1, 2 * n1, 0, n2, 0,
+    mf_product<MF_COL, EPI_TW_M, XL_Z_ROWS>(st, f.d1i, src, t, n2, 2 * n1, 2 * n1, 0, n2, 0,
                                                 2 * (size_t)nx, lines, fa);
-    mf_product<MF_ROW, EPI_IPOST_ROWS, NP>(st, f.d2i, t, dst, n2, lines * n1, 2 * n2, 2 * n2, 0,
+    mf_product<MF_ROW, EPI_IPOST_ROWS>(st, f.d2i, t, dst, n2, lines * n1, 2 * n2, 2 * n2, 0,
                                            0, 0, 1, fa);
   }
 }
@@ -839,12 +827,10 @@ void gemm_dct_cols(const Member& m, hipStream_t st, const float* src, float* dst
   const size_t cells = (size_t)nx * ny;
   const FsMats& f = m.fsy;
   if (f.l1 == 0) {
-    const MfMat d = inverse ? MfMat{{m.dyt_hi, m.dyt_lo, nullptr}}
-                            : MfMat{{m.dy_hi, m.dy_lo, nullptr}};
-    mf_product<MF_COL>(st, d, src, dst, nx, ny, ny, nx, nx, cells, cells, fields);
+    mf_product<MF_COL>(st, inverse ? m.dyt : m.dy, src, dst, nx, ny,
+                                                 ny, nx, nx, cells, cells, fields);
     return;
   }
-  constexpr int NP = kFsProducts;
   const int n1 = 1 << f.l1, n2 = 1 << f.l2, lx = m.lx;
   const int ld = n2 * nx;                  // stride of k1 in T
   const size_t sv = 2 * (size_t)n2 * nx;   // one k1 block of T
@@ -852,19 +838,19 @@ void gemm_dct_cols(const Member& m, hipStream_t st, const float* src, float* dst
   const FsArgs fa{f.l1, f.l2, lx, inverse ? f.twi : f.twf};
   for (int fl = 0; fl < fields; ++fl) {
     if (!inverse)
-      mf_product<MF_COL, EPI_TW_Z, NP, XL_MAKHOUL_COLS>(st, f.d1, src + fl * cells,
+      mf_product<MF_COL, EPI_TW_Z, XL_MAKHOUL_COLS>(st, f.d1, src + fl * cells,
                                                         t + 2 * fl * cells, nx, 2 * n1, n1, 0,
                                                         ld, 0, (size_t)nx, n2, fa);
     else
-      mf_product<MF_COL, EPI_TW_Z, NP, XL_Z_COLS>(st, f.d1i, src + fl * cells,
+      mf_product<MF_COL, EPI_TW_Z, XL_Z_COLS>(st, f.d1i, src + fl * cells,
                                                   t + 2 * fl * cells, nx, 2 * n1, 2 * n1, 0, ld,
                                                   0, (size_t)nx, n2, fa);
   }
   if (!inverse)
-    mf_product<MF_COL, EPI_POST_COLS, NP>(st, f.d2, t, dst, nx, n2, 2 * n2, nx, 0, sv, 0,
+    mf_product<MF_COL, EPI_POST_COLS>(st, f.d2, t, dst, nx, n2, 2 * n2, nx, 0, sv, 0,
                                           fields * n1, fa);
   else
-    mf_product<MF_COL, EPI_IPOST_COLS, NP>(st, f.d2i, t, dst, nx, n2, 2 * n2, nx, 0, sv, 0,
+    mf_product<MF_COL, EPI_IPOST_COLS>(st, f.d2i, t, dst, nx, n2, 2 * n2, nx, 0, sv, 0,
                                            fields * n1, fa);
 }
 
@@ -1182,22 +1168,24 @@ float host_bf16_to_f32(uint16_t h) {
 }
 
 // Orthonormal DCT-II matrix of size n (App. C), D(k, i) = s_k cos(pi k (2i + 1) / (2n)),
-// and its transpose, row-major, as bf16 hi and lo halves at
-// out + {0, 1, 2, 3} n^2: D hi, D lo, D^T hi, D^T lo.
-int upload_dct_matrix(uint16_t* out, int n, hipStream_t st) {
+// and its transpose, row-major, each as three bf16 parts (hi, mid, lo) at
+// out + {0, 1, 2} n^2 (D) and out + {3, 4, 5} n^2 (D^T).
+int upload_dct_matrix(uint16_t* out, int n, hipStream_t st, MfMat& d, MfMat& dt) {
   const size_t nn = (size_t)n * n;
-  std::vector<uint16_t> h(4 * nn);
+  std::vector<uint16_t> h(6 * nn);
   const double s0 = std::sqrt(1.0 / n), s1 = std::sqrt(2.0 / n);
   for (int k = 0; k < n; ++k)
     for (int i = 0; i < n; ++i) {
-      const double v = (k == 0 ? s0 : s1) * std::cos(M_PI * k * (2.0 * i + 1.0) / (2.0 * n));
-      const uint16_t hi = host_bf16((float)v);
-      const uint16_t lo = host_bf16((float)(v - (double)host_bf16_to_f32(hi)));
-      h[(size_t)k * n + i] = hi;
-      h[nn + (size_t)k * n + i] = lo;
-      h[2 * nn + (size_t)i * n + k] = hi;
-      h[3 * nn + (size_t)i * n + k] = lo;
+      double v = (k == 0 ? s0 : s1) * std::cos(M_PI * k * (2.0 * i + 1.0) / (2.0 * n));
+      for (int q = 0; q < 3; ++q) {
+        const uint16_t b = host_bf16((float)v);
+        h[q * nn + (size_t)k * n + i] = b;
+        h[(3 + q) * nn + (size_t)i * n + k] = b;
+        v -= (double)host_bf16_to_f32(b);
+      }
     }
+  d = MfMat{{out, out + nn, out + 2 * nn}};
+  dt = MfMat{{out + 3 * nn, out + 4 * nn, out + 5 * nn}};
   const bool ok =
       hipMemcpyAsync(out, h.data(), h.size() * sizeof(uint16_t), hipMemcpyHostToDevice, st) ==
       hipSuccess;
@@ -1601,20 +1589,13 @@ int ccmsav_init_batch(ccmsav_ctx** out, int32_t nmemb, const ccmsav_params* p,
     }
     if (is_gemm(m.p.precision)) {
       // per direction: the factored transform's DFT matrices, or D and D^T
-      auto setup = [&](int n, size_t off, FsMats& f, uint16_t*& d_hi, uint16_t*& d_lo,
-                       uint16_t*& dt_hi, uint16_t*& dt_lo) {
-        uint16_t* q = reinterpret_cast<uint16_t*>(mb + off);
-        d_hi = d_lo = dt_hi = dt_lo = nullptr;
+      auto setup = [&](int n, size_t off, FsMats& f, MfMat& d, MfMat& dt) {
+        d = dt = MfMat{{nullptr, nullptr, nullptr}};
         if (const int n1 = fs_n1(n)) return upload_fs_matrices(mb + off, n1, n / n1, c->stream, f);
-        const size_t nn = (size_t)n * n;
-        d_hi = q;
-        d_lo = q + nn;
-        dt_hi = q + 2 * nn;
-        dt_lo = q + 3 * nn;
-        return upload_dct_matrix(q, n, c->stream);
+        return upload_dct_matrix(reinterpret_cast<uint16_t*>(mb + off), n, c->stream, d, dt);
       };
-      if (setup(m.p.nx, L.dx, m.fsx, m.dx_hi, m.dx_lo, m.dxt_hi, m.dxt_lo) != CCMSAV_OK ||
-          setup(m.p.ny, L.dy, m.fsy, m.dy_hi, m.dy_lo, m.dyt_hi, m.dyt_lo) != CCMSAV_OK)
+      if (setup(m.p.nx, L.dx, m.fsx, m.dx, m.dxt) != CCMSAV_OK ||
+          setup(m.p.ny, L.dy, m.fsy, m.dy, m.dyt) != CCMSAV_OK)
         return fail(CCMSAV_EHIP);
       m.fs_w = uses_fs(&m.p) ? reinterpret_cast<float*>(mb + L.fs) : nullptr;
     }

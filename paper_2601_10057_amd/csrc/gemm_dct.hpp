@@ -1,16 +1,15 @@
 // Pointwise kernels of the DCT-as-GEMM variant of the step.
 //
-// In this variant the four transform passes of a step are dense products
-// with the orthonormal DCT-II matrix D (D_kn = s_k cos(pi k (2n + 1) / 2N),
-// s_0 = sqrt(1/N), s_k = sqrt(2/N)), evaluated on the matrix cores in bfloat16
-// with FP32 accumulation: every FP32 operand x is split into x_hi = bf16(x) and
-// x_lo = bf16(x - x_hi), and a product A B is taken as
-// A_hi B_hi + A_hi B_lo + A_lo B_hi (three bf16 GEMMs, relative error about
-// 2^-16 per product). The products only ever see the increment-form residuals
-// of the mixed path, so that error scales with the step's change. The
-// products themselves are in gemm_mfma.hpp; the kernels here do the spectral
-// work between them: inner products, combination and divide, and the FP64
-// update of the state.
+// In this variant the four transform passes of a step run on the matrix
+// cores in bfloat16 with FP32 accumulation: every FP32 operand is split into
+// three bf16 parts and a product takes the six products of parts that carry
+// FP32 accuracy (gemm_mfma.hpp). A direction of fewer than 2048 points is a
+// dense product with the orthonormal DCT-II matrix D (D_kn = s_k cos(pi k
+// (2n + 1) / 2N), s_0 = sqrt(1/N), s_k = sqrt(2/N)); a longer one takes the
+// factored form of gemm_fourstep.hpp. The products only ever see the
+// increment-form residuals of the mixed path. The kernels here do the
+// spectral work between them: inner products, combination and divide, and
+// the FP64 update of the state.
 #pragma once
 #include <stdint.h>
 

@@ -40,7 +40,7 @@
 
 namespace ccm {
 
-// Epilogues of the matrix-core product (k_gemm_bf16x3).
+// Epilogues of the matrix-core product (k_gemm_bf16x3, gemm_mfma.hpp).
 enum FsEpilogue {
   EPI_STORE = 0,     // C(m, n) at c[n ldc + m]
   EPI_TW_M,          // step 2 on step 1's output, n2 = m (rows)

@@ -1,14 +1,15 @@
 // Products with constant matrices on the gfx950 matrix cores, for the
-// DCT-as-GEMM variant of the step: bfloat16 operands split into parts,
-// products of the parts accumulated in FP32 by v_mfma_f32_32x32x16_bf16 --
-// three of them (hi hi + hi lo + lo hi) for two parts per operand, six for
-// three parts (mf_parts).
+// DCT-as-GEMM variant of the step: both operands split into three bfloat16
+// parts (x = x_0 + x_1 + x_2 + O(2^-25 |x|)), and the six products of parts
+// whose orders add up to at most 2 accumulated in FP32 by
+// v_mfma_f32_32x32x16_bf16 -- the rounding of an FP32 product (the three
+// terms left out are below 2^-26 of the result's terms).
 //
 // Every product of the step pairs a constant matrix d (a DCT matrix, its
 // transpose, or a DFT matrix of the factored transforms, split once at
 // context creation, row-major with K contiguous) with an FP32 data operand x
-// that is split into bf16 parts while it is staged into LDS, so no separate
-// splitting pass touches HBM:
+// that is split while it is staged into LDS, so no separate splitting pass
+// touches HBM:
 //   row mode (transforms along x): C(m, n) = sum_k d[m K + k] x[n ldx + k],
 //     the data rows of all fields stacked along n;
 //   column mode (transforms along y): C(m, n) = sum_k x[k ldx + m] d[n K + k],
@@ -48,15 +49,17 @@ __device__ __forceinline__ int mf_slot(int line, int k8) {
   return line * MF_ROW16 + (k8 ^ ((line >> 2) & 3));
 }
 
-// x = x_0 + .. + x_{P-1} + O(2^-(9 + 8 (P-1)) |x|): P bfloat16 parts of
-// eight FP32 values, each the rounding of what the earlier parts leave.
-template <int P>
-__device__ __forceinline__ void split8(const float (&v)[8], bf16x8_t (&part)[P]) {
+// bf16 parts of each operand.
+constexpr int MF_PARTS = 3;
+
+// x = x_0 + x_1 + x_2 + O(2^-25 |x|): three bfloat16 parts of eight FP32
+// values, each the rounding of what the earlier parts leave.
+__device__ __forceinline__ void split8(const float (&v)[8], bf16x8_t (&part)[MF_PARTS]) {
   float r[8];
 #pragma unroll
   for (int e = 0; e < 8; ++e) r[e] = v[e];
 #pragma unroll
-  for (int q = 0; q < P; ++q) {
+  for (int q = 0; q < MF_PARTS; ++q) {
     u16x8_t h;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
@@ -67,17 +70,11 @@ __device__ __forceinline__ void split8(const float (&v)[8], bf16x8_t (&part)[P])
   }
 }
 
-// A constant matrix operand as bf16 parts (hi, lo; or hi, mid, lo), each
-// row-major with K contiguous.
+// A constant matrix operand as its bf16 parts (hi, mid, lo), each row-major
+// with K contiguous.
 struct MfMat {
-  const uint16_t* part[3];
+  const uint16_t* part[MF_PARTS];
 };
-
-// Products per K step: NP = 3 takes two parts per operand and the terms
-// hi hi, hi lo, lo hi (relative error about 2^-16); NP = 6 three parts and
-// every term whose parts' orders add up to at most 2 (about 2^-24, the
-// rounding of FP32).
-__host__ __device__ constexpr int mf_parts(int np) { return np == 6 ? 3 : 2; }
 
 // Block tile (m0, n0) and batch entry z of block b: blocks are spread over
 // the eight XCDs in contiguous ranges (xcd_remap), and within a batch entry
@@ -103,15 +100,14 @@ __device__ __forceinline__ void mf_block_tile(int mb_count, int nb_count, int& z
 
 // C = the product of MODE (above) for an M x N tile grid of BM x BN blocks,
 // batch entries z = 0 .. gridDim.x / (M/BM N/BN) - 1 at strides sx (x) and sc
-// (c); d is shared by the batch. EPI: how C is stored (FsEpilogue); NP: the
-// products per K step (mf_parts); XL: how the data operand is read (FsLoad,
-// column mode).
-template <int MODE, int BM, int BN, int EPI, int NP, int XL>
+// (c); d is shared by the batch. EPI: how C is stored (FsEpilogue); XL: how
+// the data operand is read (FsLoad, column mode).
+template <int MODE, int BM, int BN, int EPI, int XL>
 __global__ void __launch_bounds__(MF_THREADS)
 k_gemm_bf16x3(MfMat d, const float* __restrict__ x, float* __restrict__ c, int M, int N, int K,
               int ldx, int ldc, size_t sx, size_t sc, FsArgs fa) {
   constexpr bool SWAP = fs_swapped(EPI);
-  constexpr int PT = mf_parts(NP);
+  constexpr int PT = MF_PARTS;
   static_assert(XL == XL_PLAIN || MODE == MF_COL, "the fused loads are column-mode operands");
   constexpr int TM = BM / 64, TN = BN / 64;   // 32 x 32 subtiles per wave along m, n
   // LDS tiles per part: lines indexed by m (Lm) and by n (Ln), K contiguous.
@@ -195,7 +191,7 @@ k_gemm_bf16x3(MfMat d, const float* __restrict__ x, float* __restrict__ c, int M
       const int s = MODE == MF_ROW ? ch >> 2 : ch % RX;
       const int k8 = MODE == MF_ROW ? ch & 3 : ch / RX;
       bf16x8_t part[PT];
-      split8<PT>(rx[i], part);
+      split8(rx[i], part);
 #pragma unroll
       for (int q = 0; q < PT; ++q) lx(q, mf_slot(s, k8)) = part[q];
     }
@@ -240,11 +236,9 @@ k_gemm_bf16x3(MfMat d, const float* __restrict__ x, float* __restrict__ c, int M
 #pragma unroll
         for (int b = 0; b < TM; ++b) {
           // the smaller terms first
-          if constexpr (NP == 6) {
-            mma(acc[a][b], an[1][a], bm[1][b]);
-            mma(acc[a][b], an[0][a], bm[2][b]);
-            mma(acc[a][b], an[2][a], bm[0][b]);
-          }
+          mma(acc[a][b], an[1][a], bm[1][b]);
+          mma(acc[a][b], an[0][a], bm[2][b]);
+          mma(acc[a][b], an[2][a], bm[0][b]);
           mma(acc[a][b], an[0][a], bm[1][b]);
           mma(acc[a][b], an[1][a], bm[0][b]);
           mma(acc[a][b], an[0][a], bm[0][b]);
