@@ -362,6 +362,9 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
     Lc = lap_n(rc.phn, rn.phn, rs.phn);
     Ls = (j0 == 0) ? Lc : lap_n(rs.phn, rc.phn, u2);
   }
+  // Mobility on the face below the current row: the previous row's north
+  // face (the same operands in the same order, so the same value).
+  double m_south = mobility(0.5 * (rs.p + rc.p), c.M0);
   auto row_step = [&](int j, const Raw& r2) {
     double Ln = 0.0;
     if constexpr (INC) Ln = (j + 1 >= ny) ? Lc : lap_n(rn.phn, r2.phn, rc.phn);
@@ -427,8 +430,11 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
     out[M_Q] = Qt;
     out[M_K] = Kt;
     const double Pc = rc.P;
-    const double Me = mobility(0.5 * (pc + pe), c.M0), Mw = mobility(0.5 * (pw + pc), c.M0);
-    const double Mn = mobility(0.5 * (pc + pn), c.M0), Ms = mobility(0.5 * (ps + pc), c.M0);
+    // each face's mobility once: the west face is the west lane's east face
+    // (at the west wall the ghost lane's face, mobility(phi*_0), as the
+    // ghost rule gives), the south face the previous row's north face
+    const double Me = mobility(0.5 * (pc + pe), c.M0), Mn = mobility(0.5 * (pc + pn), c.M0);
+    const double Mw = lane_from_below(Me), Ms = m_south;
     out[M_L] = (Me * (Pe - Pc) - Mw * (Pc - Pw) + Mn * (rn.P - Pc) - Ms * (Pc - rs.P)) * c.inv_h2;
     out[M_P] = Pc;
     if (out_lane) {
@@ -465,15 +471,16 @@ __device__ __forceinline__ void stencil_body(const RowArgs& a, gptr<TM> __restri
         // ||d^n||^2 of the previous step over the east and north faces
         if (face_e) {
           const double g = de - rc.dl;
-          sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (rc.fl + fe), c.M0);
+          sums[P1_DLAG] += g * g * c.inv_h2 * rcp64(mobility(0.5 * (rc.fl + fe), c.M0));
         }
         if (face_n) {
           const double g = rn.dl - rc.dl;
-          sums[P1_DLAG] += g * g * c.inv_h2 / mobility(0.5 * (rc.fl + rn.fl), c.M0);
+          sums[P1_DLAG] += g * g * c.inv_h2 * rcp64(mobility(0.5 * (rc.fl + rn.fl), c.M0));
         }
       }
     }
     // advance the window
+    m_south = Mn;
     rs = rc;
     rc = rn;
     if (j + 1 < j0 + iters) rn = make_row(r2);
