@@ -166,7 +166,7 @@ bool uses_fs(const ccmsav_params* p) { return fs_n1(p->nx) != 0 || fs_n1(p->ny) 
 
 struct Layout {
   size_t state, rm, mid, outc, part1, part2, parte, lamx, lamy, colsum, unit, ds;
-  size_t dx, dy;   // GEMM variant: the transform matrices per direction, bf16 hi and lo
+  size_t dx, dy;   // GEMM variant: the transform matrices per direction, as bf16 parts
   size_t fs;       // GEMM variant, factored transforms: complex work buffer
   size_t psol;     // periodic step: chi^{-1} of S~, H, Q~, K~ (4 FP64 fields)
   size_t cl, clpart, clsc;   // classical scheme: PCG fields, partial sums, scalars
@@ -596,8 +596,10 @@ int stencil_grid(ccmsav_ctx* c, bool fp64, int total) {
 // Autotuner: at the first step every variant of each tuned kernel is run
 // (they compute bit-identical results from the same inputs, so the step's
 // outcome does not depend on the order) and timed with HIP events on the
-// context's stream; the fastest is kept for all later steps.
-constexpr int kTuneReps = 3;
+// context's stream; the fastest (the least of its repetitions) is kept for
+// all later steps. The repetitions alternate between the variants, so that
+// clock and cache drift over the tuning launches weigh on all of them.
+constexpr int kTuneReps = 5;
 struct Tuner {
   bool on = false;
   std::vector<hipEvent_t> ev;   // [class][kernel][variant][rep][2]
@@ -613,8 +615,8 @@ void run_tuned(ccmsav_ctx* c, Tuner& tu, size_t ki, int t, hipStream_t st, F lau
     launch(k.var[t]);
     return;
   }
-  for (int v = 0; v < kNumVariants; ++v)
-    for (int r = 0; r < kTuneReps; ++r) {
+  for (int r = 0; r < kTuneReps; ++r)
+    for (int v = 0; v < kNumVariants; ++v) {
       (void)hipEventRecord(tu.ev[tu.at(ki, t, v, r, 0)], st);
       launch(v);
       (void)hipEventRecord(tu.ev[tu.at(ki, t, v, r, 1)], st);

@@ -81,12 +81,13 @@ def mirrored_tiles(m, rx, ry):
                    dict(m.params, nx=nx * rx, ny=ny * ry), {})
 
 
-@pytest.mark.parametrize("rx,ry", [(8, 1), (1, 4)])
+@pytest.mark.parametrize("rx,ry", [(8, 1), (1, 4), (1, 8)])
 def test_factored_and_dense_directions_on_rectangles(rx, ry):
     """Directions of 2048 points and more take the factored transform (N1 x
     N2 = 32 x 64, 64 x 64, 64 x 128), shorter ones the dense product: a
-    4096 x 512 grid (rows 64 x 64, columns dense) and a 512 x 2048 one (rows
-    dense, columns 32 x 64), mirrored tiles of the 512^2 vesicle of the
+    4096 x 512 grid (rows 64 x 64, columns dense), a 512 x 2048 one (rows
+    dense, columns 32 x 64) and a 512 x 4096 one (columns 64 x 64), mirrored
+    tiles of the 512^2 vesicle of the
     square-grid case above (the same dynamics per tile), against the FP64
     path over 60 steps at the same bound. (On tiles of a 256^2 vesicle at its
     time step the FP32 mixed path itself drifts from FP64 by 2e-5 in ten
