@@ -328,9 +328,22 @@ def digest_counters(fetch_dir: str, write_dir: str, workload: str, precision: st
           f"Per step (the kernels marked 'step'): {step:.2f} B/cell. Per pass of the pipeline "
           f"model (algorithmic {pass_bytes_per_cell(precision)}): " +
           ", ".join(f"{ps} {b:.2f}" for ps, b in passes.items()) + " B/cell."]
+    if precision == "gemm":
+        # the matrix-core variant has its own kernels: the table only, no
+        # per-pass record for the roofline line
+        md = md[:md.index("| kernel | dispatches | fetch B/cell | write B/cell | total B/cell | "
+                          "algorithmic B/cell (this build's kernels) | step |")]
+        md = [ln.replace(" The first step runs both launch variants of the autotuned kernels; "
+                         "'step' marks the ones the timed steps use.", "") for ln in md]
+        md += ["| kernel | dispatches | fetch B/cell | write B/cell | total B/cell |",
+               "|---|---|---|---|---|"]
+        md += ["|".join(r.split("|")[:6]) + "|" for r in rows]
     base = os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}")
     with open(base + ".md", "w") as f:
         f.write("\n".join(md) + "\n")
+    if precision == "gemm":
+        print(base + ".md")
+        return
     txt = [f"# counter bytes per cell, {workload} {precision}; see traffic_{workload}_{precision}.md",
            f"workload: {workload}", f"precision: {precision}", f"source_sha: {digest}",
            f"fetch_scale: {sf:.6f}", f"write_scale: {sw:.6f}",
