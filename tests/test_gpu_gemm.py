@@ -104,6 +104,24 @@ def test_factored_and_dense_directions_on_rectangles(rx, ry):
         assert abs(g[5] - m0) <= 5e-11 * abs(m0)
 
 
+@pytest.mark.parametrize("rx,ry", [(32, 1), (1, 32), (128, 1), (1, 128)])
+def test_factored_directions_next_to_the_narrowest_dense_one(rx, ry):
+    """Strips of 2048 x 64, 64 x 2048, 8192 x 64 and 64 x 8192 cells (mirrored
+    tiles of the 64^2 vesicle): a factored direction (32 x 64 or 64 x 128)
+    beside a dense one of 64 points, so that every product runs its 64-wide
+    tiles. Three steps against the FP64 path within 1e-6 (measured
+    2.6-4.2e-8, the mixed path 3.4-4.2e-8)."""
+    m = mirrored_tiles(vesicle_member(64, 43), rx, ry)
+    note(f"gemm vs fp64 {m.params['nx']}x{m.params['ny']}")
+    _, ref = run(m, "fp64", 3, 1)
+    m0, got = run(m, "gemm", 3, 1)
+    worst = max(max(rel_linf(g[1], r[1]), rel_linf(g[2], r[2])) for r, g in zip(ref, got))
+    note(f"worst rel L-inf {worst:.3e}")
+    assert worst <= 1e-6
+    for g in got:
+        assert abs(g[5] - m0) <= 5e-11 * abs(m0)
+
+
 def test_gemm_variant_rejects_ensembles_graphs_and_small_grids():
     m = circle_member(32)
     with pytest.raises(C.CcmsavError) as e:
