@@ -140,6 +140,31 @@ __host__ __device__ constexpr size_t strip_field(int nx, int ny, int esize) {
   return (size_t)(nx / 2) * strip_stride(ny, esize);
 }
 
+// FP32 intermediates store the fields in pairs: the two fields of a pair share
+// one region, interleaved per row (row j of strip s holds f(2s, j), f(2s+1, j),
+// f'(2s, j), f'(2s+1, j): 16 bytes). The row pass then writes a band of rows of
+// both fields as one piece (64 bytes for four rows), and the column passes
+// load a row of both fields with one 16-byte load. The pairs follow the order
+// in which the Gram pass transforms the fields: (S~, H), (Q~, K~), (f_lin, P~),
+// (g_lin, L~); the column solve's chi group is f_lin (alone), S~, H, Q~, K~
+// and its zeta group g_lin, L~. FP64 intermediates keep one field per region.
+// A pair region has the size of one FP64 field region.
+__host__ __device__ constexpr int mid_pair(int f) {
+  return (f == M_F || f == M_P) ? 0 : (f + 1) / 2;
+}
+__host__ __device__ constexpr int mid_half(int f) {
+  return f == M_P ? 1 : (f == M_F ? 0 : (f + 1) % 2);
+}
+// Elements (FP32) of one pair strip and of one pair region.
+__host__ __device__ constexpr size_t pair_strip_stride(int ny) {
+  return 4 * (size_t)ny + (size_t)(kStripPadBytes / 4);
+}
+__host__ __device__ constexpr size_t pair_field(int nx, int ny) {
+  return (size_t)(nx / 2) * pair_strip_stride(ny);
+}
+static_assert(pair_strip_stride(64) * 4 == strip_stride(64, 8) * 8,
+              "a pair region of FP32 fields is the size of one FP64 field region");
+
 struct MemberArgs {
   gptr<const double> phn;        // phi^n, phi^{n-1}, phi^{n-2}
   gptr<const double> phm;

@@ -113,6 +113,17 @@ __device__ __forceinline__ size_t mid_index(int k, int j, size_t ss) {
   return (size_t)(k >> 1) * ss + 2 * (size_t)j + (k & 1);
 }
 
+// Element (k, j) of slot f of the strip-major intermediates of an nx x ny
+// grid: one field per region (FP64), or the pair layout (FP32, mid_pair).
+template <typename TM>
+__device__ __forceinline__ size_t mid_offset(int f, int k, int j, int nx, int ny) {
+  if constexpr (sizeof(TM) == 4)
+    return mid_pair(f) * pair_field(nx, ny) + (size_t)(k >> 1) * pair_strip_stride(ny) +
+           4 * (size_t)j + 2 * mid_half(f) + (k & 1);
+  else
+    return f * strip_field(nx, ny, sizeof(TM)) + mid_index(k, j, strip_stride(ny, sizeof(TM)));
+}
+
 // Sum NV doubles over the block in a fixed order; the totals land in red[0..NV).
 template <int NV, int NTHR>
 __device__ __forceinline__ void block_sum(double (&v)[NV], double* red, int tid) {
@@ -193,9 +204,26 @@ __device__ __forceinline__ double mobility(double phi, double M0) {
 // P1: fused stencil terms + row DCT-II of the eight right-hand-side fields.
 // ---------------------------------------------------------------------------
 // Field pairs of the row pass (two real fields per complex FFT line).
-enum Pair { PR_FG = 0, PR_SH = 1, PR_QK = 2, PR_LP = 3 };
-constexpr int PAIR_A[4] = {M_F, M_S, M_Q, M_L};
-constexpr int PAIR_B[4] = {M_G, M_H, M_K, M_P};
+// With FP32 intermediates they are the pairs of the layout (mid_pair), first
+// half in A; FP64 keeps its own pairing (which fixes its rounding).
+template <typename TM> struct RowPairs;
+template <> struct RowPairs<float> {
+  static constexpr int A[4] = {M_S, M_Q, M_F, M_G};
+  static constexpr int B[4] = {M_H, M_K, M_P, M_L};
+};
+template <> struct RowPairs<double> {
+  static constexpr int A[4] = {M_F, M_S, M_Q, M_L};
+  static constexpr int B[4] = {M_G, M_H, M_K, M_P};
+};
+static_assert(mid_pair(RowPairs<float>::A[0]) == mid_pair(RowPairs<float>::B[0]) &&
+                  mid_half(RowPairs<float>::B[0]) == 1 &&
+                  mid_pair(RowPairs<float>::A[1]) == mid_pair(RowPairs<float>::B[1]) &&
+                  mid_half(RowPairs<float>::B[1]) == 1 &&
+                  mid_pair(RowPairs<float>::A[2]) == mid_pair(RowPairs<float>::B[2]) &&
+                  mid_half(RowPairs<float>::B[2]) == 1 &&
+                  mid_pair(RowPairs<float>::A[3]) == mid_pair(RowPairs<float>::B[3]) &&
+                  mid_half(RowPairs<float>::B[3]) == 1,
+              "the FP32 row pass's FFT pairs are the layout pairs");
 
 __device__ __forceinline__ double ptilde(const StepConst& c, double psi, double p) {
   return 0.5 * (c.gamma_in * (1.0 + p) * (psi - c.psi_in) +
@@ -579,6 +607,7 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
   const size_t FS = (size_t)NX * ny;                            // row-major fields
   const size_t SS = strip_stride(ny, sizeof(TM));
   const size_t FSM = strip_field(NX, ny, sizeof(TM));           // strip-major fields
+  const size_t SSP = pair_strip_stride(ny), FSP = pair_field(NX, ny);   // FP32 pairs
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
 
@@ -610,8 +639,8 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
 #pragma unroll
       for (int l = 0; l < NP; ++l) {
         const int pr = r * NP + l;
-        const auto ra = rm + PAIR_A[pr] * FS + (size_t)(j0 + rr) * NX;
-        const auto rb = rm + PAIR_B[pr] * FS + (size_t)(j0 + rr) * NX;
+        const auto ra = rm + RowPairs<TM>::A[pr] * FS + (size_t)(j0 + rr) * NX;
+        const auto rb = rm + RowPairs<TM>::B[pr] * FS + (size_t)(j0 + rr) * NX;
         const int lo = MAP::at((rr * NP + l) * NX);
         static_for<CPT>([&](auto iq) {
           constexpr int q = decltype(iq)::value;
@@ -646,9 +675,23 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
             dct2_bin<TM>(line[lo ^ pk1], line[lo ^ pm1], w1, S1, pa.v[2 * q + 1],
                          pb.v[2 * q + 1]);
           }
-          const size_t o = (size_t)sp * SS + 2 * (size_t)(j0 + half * RH);
-          store_piece<TM, RH>(mid + PAIR_A[pr] * FSM + o, pa);
-          store_piece<TM, RH>(mid + PAIR_B[pr] * FSM + o, pb);
+          if constexpr (sizeof(TM) == 4) {
+            // both fields' rows, interleaved, as one piece
+            RowPiece<TM, 2 * RH> pc;
+#pragma unroll
+            for (int q = 0; q < RH; ++q) {
+              pc.v[4 * q] = pa.v[2 * q];
+              pc.v[4 * q + 1] = pa.v[2 * q + 1];
+              pc.v[4 * q + 2] = pb.v[2 * q];
+              pc.v[4 * q + 3] = pb.v[2 * q + 1];
+            }
+            const size_t o = (size_t)sp * SSP + 4 * (size_t)(j0 + half * RH);
+            store_piece<TM, 2 * RH>(mid + mid_pair(RowPairs<TM>::A[pr]) * FSP + o, pc);
+          } else {
+            const size_t o = (size_t)sp * SS + 2 * (size_t)(j0 + half * RH);
+            store_piece<TM, RH>(mid + RowPairs<TM>::A[pr] * FSM + o, pa);
+            store_piece<TM, RH>(mid + RowPairs<TM>::B[pr] * FSM + o, pb);
+          }
         }
       }
     }
@@ -681,6 +724,23 @@ __device__ __forceinline__ void fetch_strip(gptr<const cpx<TM>> __restrict__ src
   }
 }
 
+// Both fields of a strip of an FP32 pair region (mid_pair), the thread's
+// rows q = Q0 .. Q1 - 1: row jj is one 16-byte load; a takes the first field,
+// b the second.
+template <typename TM, int NY, int LPT, int NTHR, int Q0, int Q1>
+__device__ __forceinline__ void fetch_pair_strip(gptr<const TM> __restrict__ src, int tid,
+                                                 StripRegs<TM, LPT>& a, StripRegs<TM, LPT>& b) {
+  typedef TM tm4 __attribute__((ext_vector_type(4)));
+  const auto p = reinterpret_cast<gptr<const tm4>>(src);
+#pragma unroll
+  for (int q = Q0; q < Q1; ++q) {
+    const int jj = tid + q * NTHR;
+    const tm4 v = (NY >= NTHR || jj < NY) ? p[jj] : tm4{(TM)0, (TM)0, (TM)0, (TM)0};
+    a.v[q] = {v[0], v[1]};
+    b.v[q] = {v[2], v[3]};
+  }
+}
+
 // Whether the column transform can take its first FFT stage straight from the
 // loaded registers: one radix-R butterfly per thread in every stage, so that
 // thread tid's first butterfly reads Makhoul-ordered elements tid + q (N/R).
@@ -698,6 +758,22 @@ __device__ __forceinline__ void fetch_strip_first(gptr<const cpx<TM>> __restrict
     const int k = tid + q * (NY / R);
     const int row = k < NY / 2 ? 2 * k : 2 * (NY - 1 - k) + 1;
     r.v[q] = gload<TM>(src + row);
+  }
+}
+
+// fetch_strip_first for both fields of an FP32 pair strip, rows q = Q0 .. Q1 - 1.
+template <typename TM, int NY, int R, int NTHR, int Q0, int Q1>
+__device__ __forceinline__ void fetch_pair_strip_first(gptr<const TM> __restrict__ src, int tid,
+                                                       StripRegs<TM, R>& a, StripRegs<TM, R>& b) {
+  typedef TM tm4 __attribute__((ext_vector_type(4)));
+  const auto p = reinterpret_cast<gptr<const tm4>>(src);
+#pragma unroll
+  for (int q = Q0; q < Q1; ++q) {
+    const int k = tid + q * (NY / R);
+    const int row = k < NY / 2 ? 2 * k : 2 * (NY - 1 - k) + 1;
+    const tm4 v = p[row];
+    a.v[q] = {v[0], v[1]};
+    b.v[q] = {v[2], v[3]};
   }
 }
 
@@ -863,15 +939,22 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
       b = kb[f][j];
     }
   };
-  // Fields in the order they are transformed. With FP32 lines the strip of
-  // the next field is loaded while the current one is transformed (FP64
-  // lines have no registers to spare for it).
+  // Fields in the order they are transformed. With FP32 lines the fields
+  // come in the pairs of their layout (mid_pair), consecutive in this order:
+  // one 16-byte load per row brings a field and the next. The next pair is
+  // loaded while the current one is transformed, half of its rows during
+  // each of the two transforms (FP64 lines, one field per region, have no
+  // registers to spare for loads ahead).
   constexpr int ORDER[8] = {M_S, M_H, M_Q, M_K, M_F, M_P, M_G, M_L};
-  constexpr bool PREFETCH = sizeof(TM) == 4;
+  static_assert(mid_pair(ORDER[0]) == mid_pair(ORDER[1]) && mid_half(ORDER[0]) == 0 &&
+                    mid_pair(ORDER[2]) == mid_pair(ORDER[3]) && mid_half(ORDER[2]) == 0 &&
+                    mid_pair(ORDER[4]) == mid_pair(ORDER[5]) && mid_half(ORDER[4]) == 0 &&
+                    mid_pair(ORDER[6]) == mid_pair(ORDER[7]) && mid_half(ORDER[6]) == 0,
+                "the transform order takes the pairs' fields one after the other");
+  constexpr bool PAIRS = sizeof(TM) == 4;
   // The first FFT stage runs on the loaded registers where every stage has
   // one butterfly per thread.
   constexpr bool FIRST_IN_REGS = first_stage_in_registers<NY, NTHR, GR>() && LPT == GR;
-  StripRegs<TM, LPT> nxt;
   auto fetch = [&](int f, StripRegs<TM, LPT>& r) {
     if constexpr (FIRST_IN_REGS) {
       fetch_strip_first<TM, NY, GR, NTHR>(strip(f), tid, r);
@@ -879,13 +962,36 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
       fetch_strip<TM, NY, LPT, NTHR>(strip(f), tid, r);
     }
   };
-  if constexpr (PREFETCH) fetch(ORDER[0], nxt);
+  // FP32: the fields of pair k in set k % 2
+  StripRegs<TM, LPT> pa[2], pb[2];
+  constexpr int QH = LPT >= 2 ? LPT / 2 : LPT;
+  auto fetch_pair = [&](int f, auto iset, auto iq0, auto iq1) {
+    constexpr int st = decltype(iset)::value, q0 = decltype(iq0)::value,
+                  q1 = decltype(iq1)::value;
+    const auto src = mid + mid_pair(f) * pair_field(nx, NY) + (size_t)s * pair_strip_stride(NY);
+    if constexpr (FIRST_IN_REGS) {
+      fetch_pair_strip_first<TM, NY, GR, NTHR, q0, q1>(src, tid, pa[st], pb[st]);
+    } else {
+      fetch_pair_strip<TM, NY, LPT, NTHR, q0, q1>(src, tid, pa[st], pb[st]);
+    }
+  };
+  using I0 = std::integral_constant<int, 0>;
+  using IH = std::integral_constant<int, QH>;
+  using IL = std::integral_constant<int, LPT>;
+  if constexpr (PAIRS) fetch_pair(ORDER[0], I0{}, I0{}, IL{});
   auto transform_next = [&](auto ii, TM (&A)[KPT], TM (&B)[KPT]) {
     constexpr int i = decltype(ii)::value;
     StripRegs<TM, LPT> cur;
-    if constexpr (PREFETCH) {
-      cur = nxt;
-      if constexpr (i + 1 < 8) fetch(ORDER[i + 1], nxt);
+    if constexpr (PAIRS) {
+      constexpr int cs = (i / 2) % 2, ns = 1 - cs;
+      using INS = std::integral_constant<int, ns>;
+      if constexpr (i % 2 == 0) {
+        cur = pa[cs];
+        if constexpr (i + 2 < 8) fetch_pair(ORDER[i + 2], INS{}, I0{}, IH{});
+      } else {
+        cur = pb[cs];
+        if constexpr (i + 1 < 8 && QH < LPT) fetch_pair(ORDER[i + 1], INS{}, IH{}, IL{});
+      }
     } else {
       fetch(ORDER[i], cur);
     }
@@ -1237,8 +1343,53 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
   // Combine the x-transformed right-hand sides of this group: field by field,
   // all of a field's loads in flight together (the number of fields is a
   // compile-time constant for the step's groups: 5 for chi, 2 for zeta, and
-  // 1 in a standalone solve).
-  auto combine = [&](auto inf) {
+  // 1 in a standalone solve). FP32 intermediates come in pairs: a pair whose
+  // halves are consecutive slots of the group is loaded once (16 bytes a
+  // row) and both halves are added in slot order, so that the sums are those
+  // of the field-by-field order.
+  auto combine_pairs = [&](auto inf) {
+    constexpr int NF = decltype(inf)::value;
+    typedef TM tm4 __attribute__((ext_vector_type(4)));
+    const size_t SSP = pair_strip_stride(NY), FSP = pair_field(nx, NY);
+    double ur[LPT], ui[LPT];
+#pragma unroll
+    for (int q = 0; q < LPT; ++q) { ur[q] = 0.0; ui[q] = 0.0; }
+#pragma unroll 1
+    for (int f = 0; f < NF;) {
+      const int slot = base + f;
+      const int p = mid_pair(slot), h = mid_half(slot);
+      const bool both = h == 0 && f + 1 < NF && mid_pair(slot + 1) == p;
+      const double w0 = cf[f], w1 = both ? cf[f + 1] : 0.0;
+      const auto src = reinterpret_cast<gptr<const tm4>>(mid + p * FSP + (size_t)s * SSP);
+      // half of the rows at a time: as many bytes in flight as one field's
+      // rows, and as many registers
+      constexpr int QC = LPT >= 2 ? LPT / 2 : 1;
+#pragma unroll
+      for (int q0 = 0; q0 < LPT; q0 += QC) {
+        tm4 v[QC];
+#pragma unroll
+        for (int q = 0; q < QC; ++q) {
+          const int jj = tid + (q0 + q) * NTHR;
+          v[q] = (NY >= NTHR || jj < NY) ? src[jj] : tm4{(TM)0, (TM)0, (TM)0, (TM)0};
+        }
+#pragma unroll
+        for (int q = 0; q < QC; ++q) {
+          ur[q0 + q] += w0 * (double)(h == 0 ? v[q][0] : v[q][2]);
+          ui[q0 + q] += w0 * (double)(h == 0 ? v[q][1] : v[q][3]);
+          if (both) {
+            ur[q0 + q] += w1 * (double)v[q][2];
+            ui[q0 + q] += w1 * (double)v[q][3];
+          }
+        }
+      }
+      f += both ? 2 : 1;
+    }
+    static_for<LPT>([&](auto iq) {
+      constexpr int q = decltype(iq)::value;
+      if (NY >= NTHR || tid + q * NTHR < NY) line[sl.template mak<q>()] = {(TM)ur[q], (TM)ui[q]};
+    });
+  };
+  auto combine_fields = [&](auto inf) {
     constexpr int NF = decltype(inf)::value;
     double ur[LPT], ui[LPT];
 #pragma unroll
@@ -1264,6 +1415,12 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
       constexpr int q = decltype(iq)::value;
       if (NY >= NTHR || tid + q * NTHR < NY) line[sl.template mak<q>()] = {(TM)ur[q], (TM)ui[q]};
     });
+  };
+  auto combine = [&](auto inf) {
+    if constexpr (sizeof(TM) == 4)
+      combine_pairs(inf);
+    else
+      combine_fields(inf);
   };
   if (nf == 5) {
     combine(std::integral_constant<int, 5>{});
@@ -1581,8 +1738,6 @@ k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, 
   __shared__ cpx<double> rtab[Roots<TM, NX>::SIZE];
   const int tid = threadIdx.x;
   const int j = xcd_remap(blockIdx.x, gridDim.x);
-  const size_t SS = strip_stride(ny, sizeof(TM));
-  const size_t FSM = strip_field(NX, ny, sizeof(TM));
   Roots<TM, NX> rt;
   rt.init(rtab, tid, NTHR);
   const LS sl(tid);
@@ -1599,8 +1754,8 @@ k_row_dct_field(const double* __restrict__ src, TM* __restrict__ mid, int slot, 
     if (NX / 2 >= NTHR || u < NX / 2) {
       TM A, B, Am, Bm;
       dct2_unit<TM, NX>(line, sl.template bin<q>(), sl.template binm<q>(), rt, u, A, B, Am, Bm);
-      mid[(size_t)slot * FSM + mid_index(u, j, SS)] = A;
-      mid[(size_t)slot * FSM + mid_index(pair_mirror<NX>(u), j, SS)] = Am;
+      mid[mid_offset<TM>(slot, u, j, NX, ny)] = A;
+      mid[mid_offset<TM>(slot, pair_mirror<NX>(u), j, NX, ny)] = Am;
     }
   });
 }
