@@ -84,8 +84,10 @@ BF16_PEAK_TFLOPS = 2500.0
 # FP64: 96 + 64 + 72 + 32 = 264 B; mixed: 64 + 32 + 36 + 40 = 172 B. This build
 # runs P1 as two launches (k_stencil, then k_row_dct8) with the 8 stencil
 # fields in HBM between them, and its stencil reads level n-2 as well for the
-# lagged ||d||^2: kernel_bytes_per_cell below counts those extra bytes
-# (252 B mixed, 408 B FP64), this model does not.
+# lagged ||d||^2, and its FP32 intermediates come in pairs of fields, so that
+# the column solve's Allen-Cahn group reads f_lin next to the unused P~:
+# kernel_bytes_per_cell below counts those extra bytes (256 B mixed, 408 B
+# FP64), this model does not.
 PASSES = {"P1": ("stencil", "row_dct"), "P2": ("col_gram",), "P3": ("col_solve",),
           "P4": ("row_idct",)}
 
@@ -107,7 +109,7 @@ def kernel_bytes_per_cell(precision: str, scheme: str = "bdf2"):
         "row_dct": 16 * m,
         "col_gram": 8 * m,
         "solve5": 0,
-        "col_solve": 7 * m + 2 * m,
+        "col_solve": (7 if precision == "fp64" else 8) * m + 2 * m,
         "row_idct": 2 * m + 2 * 8 + (2 * 8 if precision != "fp64" else 0),
     }
 

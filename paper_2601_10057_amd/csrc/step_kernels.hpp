@@ -8,7 +8,8 @@
 //       SAV partial sums; each wave walks down a band of rows with a register
 //       window.
 //   P1b k_row_dct8   : orthonormal DCT-II along x of the 8 fields for a band of
-//       rows (the band's rows of a column pair leave as one 32-byte piece).
+//       rows (the band's rows of a column pair leave as one piece per FP64
+//       field or FP32 field pair).
 //   P2  k_col_gram   : per strip of two columns, DCT-II along y and the
 //       Parseval inner products (F_i, chi^{-1} F_j), (P, zeta^{-1} g), (P, zeta^{-1} L).
 //   S   k_solve      : reduces the partials, assembles and solves the 5x5
@@ -22,7 +23,8 @@
 //       increment form).
 // The intermediate fields use a strip-major layout: element (k, j) of a field
 // lives at ((k / 2) * ny + j) * 2 + (k % 2), so that a column pair is one
-// contiguous complex line.
+// contiguous complex line. FP32 fields go two to a region, side by side in
+// each row (mid_pair, step_common.hpp).
 #pragma once
 #include <type_traits>
 #include <utility>
@@ -62,9 +64,10 @@ template <typename TM> constexpr int lds_line_budget(int n) {
 }
 // Rows per workgroup of the row pass. The strip-major intermediates put the
 // rows of one column pair next to each other, so a workgroup holding R rows
-// writes each column pair of a field as one piece of 2 R values; HBM takes
-// writes in 32-byte sectors, so R is chosen to fill one (4 FP32 or 2 FP64
-// rows) as far as the LDS lines allow.
+// writes each column pair of a field as one piece of 2 R values (4 R for an
+// FP32 field pair); HBM takes writes in 32-byte sectors, so R is chosen to
+// fill one with a field's values (4 FP32 or 2 FP64 rows) as far as the LDS
+// lines allow.
 template <typename TM> constexpr int p1_rows(int n) {
   const int want = 32 / (2 * (int)sizeof(TM));
   const int fit = lds_line_budget<TM>(n);
@@ -616,9 +619,10 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
   using LS = LineSlots<NX, NTHR, R, MAP>;
   constexpr int CPT = NX >= NTHR ? NX / NTHR : 1;            // loads per thread and line
   // Post-processing: HALVES lanes share the rows of one column pair sp, so
-  // that the ROWS x 2 values of a field leave as one 32-byte sector written
-  // by adjacent lanes in the same store instruction (lane h of the pair takes
-  // rows h RH .. h RH + RH - 1).
+  // that the band's values of a field (FP64) or of a field pair (FP32, both
+  // fields side by side in each row) leave as one piece of ROWS x 16 bytes,
+  // written by adjacent lanes in the same store instruction (lane h of the
+  // pair takes rows h RH .. h RH + RH - 1).
   constexpr int HALVES = ROWS >= 2 ? 2 : 1;
   constexpr int RH = ROWS / HALVES;
   constexpr int SPL = NTHR / HALVES;                         // column pairs per pass
