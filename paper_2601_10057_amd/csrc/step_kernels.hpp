@@ -276,13 +276,21 @@ template <typename TM, int LINE, int N> struct LinesLds {
 };
 
 // Launch shape of P1a for an nx x ny grid: rows per workgroup and the number
-// of workgroups (one row of partial sums each).
+// of workgroups (one row of partial sums each). A grid of 1024 rows or more
+// that would give fewer than 2048 workgroups (eight per CU) takes bands of 16
+// rows instead of 32: at N = 2048 the 576 workgroups of 32-row bands left
+// most CUs with two (stencil 112 us; 16-row bands 98 us, 8-row bands 97 us).
+// Smaller grids keep 32 rows: they share their launches with the other
+// members of an ensemble, which fill the device.
 struct StencilShape {
   int iters, blocks;
 };
+constexpr int SW_BAND_MIN = 16;
+constexpr int SW_FILL_BLOCKS = 2048;
 inline StencilShape stencil_shape(int nx, int ny) {
   const int nseg = (nx + SW_COLS - 1) / SW_COLS;
-  const int iters = ny < SW_BAND ? ny : SW_BAND;
+  int iters = ny < SW_BAND ? ny : SW_BAND;
+  if (ny >= 1024 && nseg * (ny / iters) < SW_FILL_BLOCKS && iters == SW_BAND) iters = SW_BAND_MIN;
   return {iters, nseg * (ny / iters)};
 }
 
