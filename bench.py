@@ -306,7 +306,9 @@ def digest_counters(fetch_dir: str, write_dir: str, workload: str, precision: st
         nf, f = fetch.get(k, (0, 0.0))
         nw, w = write.get(k, (0, 0.0))
         bf, bw = per_cell(f, sf), per_cell(w, sw)
-        phase = next((ph for ph, kn in names.items() if f"ccm::{kn}<" in k or k == f"ccm::{kn}"), None)
+        # (the 5x5 kernel of large grids is k_solve_sliced)
+        phase = next((ph for ph, kn in names.items()
+                      if re.match(rf"ccm::{kn}(_sliced)?(<|$)", k)), None)
         chosen = phase is not None and (phase not in var or k.rstrip(">").endswith(f", {var[phase]}"))
         if chosen:
             # launches of several grid shapes (an ensemble) add up

@@ -67,6 +67,10 @@ enum ErrBits {
 
 // Device-resident scalar state. Everything the time loop needs lives here so
 // that a step never waits on the host.
+// Workgroups of the 5x5 kernel per grid of 2048^2 cells or more, each
+// reducing a slice of the partial rows.
+constexpr int SOLVE_SLICES = 16;
+
 struct DevScalars {
   double sav[3][4];      // V, U, W, Z of the three most recent levels (slot = level % 3)
   double coef[8];        // spectral combination: f, S~, H, Q~, K~ (chi); g, L~ (zeta)
@@ -77,6 +81,12 @@ struct DevScalars {
   double cl[2];          // classical scheme: (P~, zeta^{-1} g), (P~, zeta^{-1} L~)
   int err;
   int pad[3];
+  // 5x5 kernel over several workgroups (grids of 2048^2 cells or more): the
+  // column sums of each slice of the partial rows, and the slices done in the
+  // current step
+  double slice[SOLVE_SLICES][P1_NSUM + P2_NSUM];
+  unsigned slices_done;
+  int pad2[3];
 };
 
 // Constants of one step, passed by value to the kernels.

@@ -1184,17 +1184,12 @@ template <int NTHR> struct SolveLds {
   double red[NTHR + SOLVE_NV_MAX];
 };
 
-template <int NTHR>
-__device__ __forceinline__ void solve_body(gptr<const double> __restrict__ p1, int n1,
-                                           gptr<const double> __restrict__ p2, int n2,
-                                           gptr<DevScalars> __restrict__ ds, const StepConst& c,
-                                           SolveLds<NTHR>& L, int tid) {
-  double* red = L.red;
-  double T1[P1_NSUM], T2[P2_NSUM];
-  reduce_columns<P1_NSUM, NTHR>(p1, n1, red, tid, T1);
-  reduce_columns<P2_NSUM, NTHR>(p2, n2, red, tid, T2);
-  if (tid != 0) return;
-
+// The 5x5 system from the reduced sums T1 (stencil pass) and T2 (column
+// pass), its solution, the new SAVs and the combination coefficients; run by
+// one thread.
+__device__ __forceinline__ void solve_system(const double (&T1)[P1_NSUM], double (&T2)[P2_NSUM],
+                                             gptr<DevScalars> __restrict__ ds,
+                                             const StepConst& c) {
   int err = 0;
   const double h2 = c.h2;
   const double rS2 = h2 * T1[P1_RS], rW2 = h2 * T1[P1_RW], rZ2 = h2 * T1[P1_RZ];
@@ -1315,6 +1310,75 @@ __device__ __forceinline__ void solve_body(gptr<const double> __restrict__ p1, i
   if (T1[P1_MOBNEG] > 0.0) err |= ERR_MOBILITY;
   if (c.lag_d) ds->acc += c.half_dt * c.lam * c.lam * h2 * T1[P1_DLAG];
   ds->err |= err;
+}
+
+// One workgroup reduces all partial rows and solves.
+template <int NTHR>
+__device__ __forceinline__ void solve_body(gptr<const double> __restrict__ p1, int n1,
+                                           gptr<const double> __restrict__ p2, int n2,
+                                           gptr<DevScalars> __restrict__ ds, const StepConst& c,
+                                           SolveLds<NTHR>& L, int tid) {
+  double* red = L.red;
+  double T1[P1_NSUM], T2[P2_NSUM];
+  reduce_columns<P1_NSUM, NTHR>(p1, n1, red, tid, T1);
+  reduce_columns<P2_NSUM, NTHR>(p2, n2, red, tid, T2);
+  if (tid == 0) solve_system(T1, T2, ds, c);
+}
+
+// SOLVE_SLICES workgroups per grid: workgroup g reduces slice g of the
+// partial rows (rows g n / SOLVE_SLICES up to the next slice) into
+// ds->slice[g]; the workgroup that finishes last (an agent-scope counter)
+// adds the slices in slice order, solves, and sets the counter back to zero
+// for the next step. The sums do not depend on which workgroup finishes
+// last, so results repeat bit for bit. Workgroup g's slice and its counter
+// increment are ordered by a release fence, the last workgroup's reads by an
+// acquire fence.
+template <int NTHR>
+__device__ __forceinline__ void solve_sliced_body(gptr<const double> __restrict__ p1, int n1,
+                                                  gptr<const double> __restrict__ p2, int n2,
+                                                  gptr<DevScalars> __restrict__ ds,
+                                                  const StepConst& c, int g, SolveLds<NTHR>& L,
+                                                  int tid) {
+  static_assert(NTHR >= P1_NSUM + P2_NSUM, "one thread per sum for the slice totals");
+  double* red = L.red;
+  __shared__ int last;
+  {
+    const int a1 = (int)((long long)n1 * g / SOLVE_SLICES);
+    const int b1 = (int)((long long)n1 * (g + 1) / SOLVE_SLICES);
+    const int a2 = (int)((long long)n2 * g / SOLVE_SLICES);
+    const int b2 = (int)((long long)n2 * (g + 1) / SOLVE_SLICES);
+    double T1[P1_NSUM], T2[P2_NSUM];
+    reduce_columns<P1_NSUM, NTHR>(p1 + (size_t)a1 * P1_NSUM, b1 - a1, red, tid, T1);
+    reduce_columns<P2_NSUM, NTHR>(p2 + (size_t)a2 * P2_NSUM, b2 - a2, red, tid, T2);
+    if (tid == 0) {
+#pragma unroll
+      for (int q = 0; q < P1_NSUM; ++q) ds->slice[g][q] = T1[q];
+#pragma unroll
+      for (int q = 0; q < P2_NSUM; ++q) ds->slice[g][P1_NSUM + q] = T2[q];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned done = __hip_atomic_fetch_add(&ds->slices_done, 1u, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+      last = done == SOLVE_SLICES - 1;
+    }
+  }
+  lds_sync();
+  if (!last) return;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (tid < P1_NSUM + P2_NSUM) {
+    double t = 0.0;
+    for (int h = 0; h < SOLVE_SLICES; ++h) t += ds->slice[h][tid];
+    red[tid] = t;
+  }
+  lds_sync();
+  if (tid == 0) {
+    __hip_atomic_store(&ds->slices_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    double T1[P1_NSUM], T2[P2_NSUM];
+#pragma unroll
+    for (int q = 0; q < P1_NSUM; ++q) T1[q] = red[q];
+#pragma unroll
+    for (int q = 0; q < P2_NSUM; ++q) T2[q] = red[P1_NSUM + q];
+    solve_system(T1, T2, ds, c);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1844,6 +1908,16 @@ __global__ void __launch_bounds__(NTHR) k_solve(BATCH_PARAMS) {
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
   solve_body<NTHR>(m.part1, m.p1_blocks, m.part2, m.p2_rows, m.ds, m.k, L, threadIdx.x);
+}
+
+// per = SOLVE_SLICES workgroups per member
+template <int NTHR>
+__global__ void __launch_bounds__(NTHR) k_solve_sliced(BATCH_PARAMS) {
+  __shared__ SolveLds<NTHR> L;
+  int g;
+  const MemberArgs& m = batch_member(tab, idx, per, g);
+  solve_sliced_body<NTHR>(m.part1, m.p1_blocks, m.part2, m.p2_rows, m.ds, m.k, g, L,
+                          threadIdx.x);
 }
 
 template <typename TM, int NY, int V>

@@ -90,3 +90,22 @@ def test_graph_replays_with_fixed_variants_and_bad_values():
             with pytest.raises(C.CcmsavError) as e:
                 ctx.set_launch_variants(*bad)
             assert e.value.name == "EINVAL"
+
+
+def test_graph_replays_at_2048_match_eager_steps():
+    """Grids of 2048^2 cells and more reduce the 5x5 kernel's partial rows over
+    several workgroups, the last of which resets a counter for the next step;
+    graph replays must repeat the eager steps bit for bit, replay after replay,
+    with reads of the fields (eager work and synchronisations) in between."""
+    m = vesicle_member(2048, 16)
+    note("graph replays against eager steps, mixed 2048")
+    with C.Context(m.params, m.phi0, m.psi0, "mixed") as e, \
+            C.Context(m.params, m.phi0, m.psi0, "mixed", graph=True) as g:
+        for chunk in range(4):
+            e.step(3)
+            g.step(3)
+            pe, qe = e.fields()
+            pg, qg = g.fields()
+            assert np.array_equal(pe, pg), chunk
+            assert np.array_equal(qe, qg), chunk
+            assert np.array_equal(np.asarray(e.savs()[0]), np.asarray(g.savs()[0])), chunk
