@@ -726,13 +726,15 @@ template <typename TM, int LPT> struct StripRegs {
   cpx<TM> v[LPT];
 };
 
-template <typename TM, int NY, int LPT, int NTHR>
+// Row jj of the strip is src[jj STRIDE] (STRIDE 2: one field of an FP32 pair
+// region, the other field's values in between).
+template <typename TM, int NY, int LPT, int NTHR, int STRIDE = 1>
 __device__ __forceinline__ void fetch_strip(gptr<const cpx<TM>> __restrict__ src, int tid,
                                             StripRegs<TM, LPT>& r) {
 #pragma unroll
   for (int q = 0; q < LPT; ++q) {
     const int jj = tid + q * NTHR;
-    r.v[q] = (NY >= NTHR || jj < NY) ? gload<TM>(src + jj) : cpx<TM>{(TM)0, (TM)0};
+    r.v[q] = (NY >= NTHR || jj < NY) ? gload<TM>(src + jj * STRIDE) : cpx<TM>{(TM)0, (TM)0};
   }
 }
 
@@ -762,14 +764,14 @@ template <int NY, int NTHR, int R> constexpr bool first_stage_in_registers() {
 
 // Loads for first_stage_in_registers: v[q] = element k = tid + q (NY/R) of the
 // Makhoul-reordered strip, i.e. row 2k for k < NY/2 and row 2(NY-1-k)+1 above.
-template <typename TM, int NY, int R, int NTHR>
+template <typename TM, int NY, int R, int NTHR, int STRIDE = 1>
 __device__ __forceinline__ void fetch_strip_first(gptr<const cpx<TM>> __restrict__ src, int tid,
                                                   StripRegs<TM, R>& r) {
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int k = tid + q * (NY / R);
     const int row = k < NY / 2 ? 2 * k : 2 * (NY - 1 - k) + 1;
-    r.v[q] = gload<TM>(src + row);
+    r.v[q] = gload<TM>(src + row * STRIDE);
   }
 }
 
@@ -955,15 +957,18 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   // come in the pairs of their layout (mid_pair), consecutive in this order:
   // one 16-byte load per row brings a field and the next. The next pair is
   // loaded while the current one is transformed, half of its rows during
-  // each of the two transforms (FP64 lines, one field per region, have no
-  // registers to spare for loads ahead).
+  // each of the two transforms. FP64 lines (one field per region) and
+  // workgroups of more than 8 waves (at most 128 registers per thread) have
+  // no registers to spare for loads ahead: they load each field when it is
+  // transformed (FP32: its half of the pair region, the other half read
+  // from L2 one transform later).
   constexpr int ORDER[8] = {M_S, M_H, M_Q, M_K, M_F, M_P, M_G, M_L};
   static_assert(mid_pair(ORDER[0]) == mid_pair(ORDER[1]) && mid_half(ORDER[0]) == 0 &&
                     mid_pair(ORDER[2]) == mid_pair(ORDER[3]) && mid_half(ORDER[2]) == 0 &&
                     mid_pair(ORDER[4]) == mid_pair(ORDER[5]) && mid_half(ORDER[4]) == 0 &&
                     mid_pair(ORDER[6]) == mid_pair(ORDER[7]) && mid_half(ORDER[6]) == 0,
                 "the transform order takes the pairs' fields one after the other");
-  constexpr bool PAIRS = sizeof(TM) == 4;
+  constexpr bool PAIRS = sizeof(TM) == 4 && NTHR <= 512;
   // The first FFT stage runs on the loaded registers where every stage has
   // one butterfly per thread.
   constexpr bool FIRST_IN_REGS = first_stage_in_registers<NY, NTHR, GR>() && LPT == GR;
@@ -1003,6 +1008,15 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
       } else {
         cur = pb[cs];
         if constexpr (i + 1 < 8 && QH < LPT) fetch_pair(ORDER[i + 1], INS{}, IH{}, IL{});
+      }
+    } else if constexpr (sizeof(TM) == 4) {
+      const auto src = reinterpret_cast<gptr<const cpx<TM>>>(
+          mid + mid_pair(ORDER[i]) * pair_field(nx, NY) + (size_t)s * pair_strip_stride(NY) +
+          2 * mid_half(ORDER[i]));
+      if constexpr (FIRST_IN_REGS) {
+        fetch_strip_first<TM, NY, GR, NTHR, 2>(src, tid, cur);
+      } else {
+        fetch_strip<TM, NY, LPT, NTHR, 2>(src, tid, cur);
       }
     } else {
       fetch(ORDER[i], cur);
