@@ -797,8 +797,10 @@ __device__ __forceinline__ void fetch_pair_strip_first(gptr<const TM> __restrict
 // butterfly per thread in each stage. With FIRST_IN_REGS the registers hold
 // the inputs of the thread's first-stage butterfly (fetch_strip_first): that
 // stage runs on them and stores its outputs, saving one pass through LDS.
+// TRAIL_SYNC false: the caller writes its next line elsewhere, so the last
+// reads of this one need no barrier behind them.
 template <typename TM, int NY, int LPT, int UPT, int NTHR, int R, typename MAP,
-          bool FIRST_IN_REGS = false>
+          bool FIRST_IN_REGS = false, bool TRAIL_SYNC = true>
 __device__ __forceinline__ void column_dct2(const StripRegs<TM, LPT>& in, cpx<TM>* line,
                                             const Roots<TM, NY>& rt,
                                             const LineSlots<NY, NTHR, R, MAP>& sl, int tid,
@@ -835,7 +837,7 @@ __device__ __forceinline__ void column_dct2(const StripRegs<TM, LPT>& in, cpx<TM
       A[2 * q] = 0; B[2 * q] = 0; A[2 * q + 1] = 0; B[2 * q + 1] = 0;
     }
   });
-  lds_sync();
+  if constexpr (TRAIL_SYNC) lds_sync();
 }
 
 // Sum NV per-thread values over the block and add them to acc[IDX[q]].
@@ -859,14 +861,21 @@ template <typename TM, int NY> struct GramPlan {
   static constexpr int BUDGET = 150 * 1024;
   static constexpr int WAVES = NTHR / 64;
   static constexpr int ACC_BUDGET = WAVES >= 8 ? BUDGET : (160 * 1024) / (8 / WAVES);
-  static constexpr bool S_LDS = 2 * LINE_B + ROOT_B <= BUDGET;
+  static constexpr int ACC_B = P2_NSUM * NTHR * (int)sizeof(double);
+  // FP32 workgroups of 8 waves (one per CU): two line buffers, alternating
+  // from field to field, where they fit beside the partial sums (the S~
+  // spectrum then stays in registers), so that a transform needs no barrier
+  // after its last reads of its line. (With 4 waves the extra registers would
+  // halve the waves per SIMD.)
+  static constexpr bool DBL = sizeof(TM) == 4 && NTHR == 512 &&
+                              2 * LINE_B + ROOT_B + ACC_B <= ACC_BUDGET;
+  static constexpr bool S_LDS = !DBL && 2 * LINE_B + ROOT_B <= BUDGET;
   static constexpr bool ACC_LDS =
-      (S_LDS ? 2 : 1) * LINE_B + ROOT_B + P2_NSUM * NTHR * (int)sizeof(double) <= ACC_BUDGET &&
-      NTHR % 16 == 0;
+      (S_LDS || DBL ? 2 : 1) * LINE_B + ROOT_B + ACC_B <= ACC_BUDGET && NTHR % 16 == 0;
 };
 template <typename TM, int NY> struct GramLds {
   using GP = GramPlan<TM, NY>;
-  cpx<TM> line[NY];
+  cpx<TM> line[(GP::DBL ? 2 : 1) * NY];
   cpx<TM> keep[GP::S_LDS ? NY : 1];
   cpx<double> rtab[Roots<TM, NY>::SIZE];
   double red[GP::ACC_LDS ? 1 : P2_NSUM * (GP::NTHR / 64 + 1)];   // per-field block sums
@@ -1021,7 +1030,10 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
     } else {
       fetch(ORDER[i], cur);
     }
-    column_dct2<TM, NY, LPT, UPT, NTHR, GR, MAP, FIRST_IN_REGS>(cur, line, rt, sl, tid, A, B);
+    // field i's line (alternating buffers where GP::DBL)
+    cpx<TM>* ln = GP::DBL ? line + (i % 2) * NY : line;
+    column_dct2<TM, NY, LPT, UPT, NTHR, GR, MAP, FIRST_IN_REGS, !GP::DBL>(cur, ln, rt, sl, tid, A,
+                                                                        B);
   };
   // chi group: S~, H, Q~, K~ transformed and kept; their inner products are
   // taken together with those of f_lin, bin by bin, so that each bin's
