@@ -90,6 +90,13 @@ def load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing; build it with "
                           "`python -m paper_2601_10057_amd.build`")
+    # torch ships its own HIP runtime; loading it first makes the library bind
+    # to that same runtime, so that device pointers and streams from torch are
+    # valid in the library's calls (a second runtime instance would reject them).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
     lib.ccmsav_workspace_bytes.argtypes = [ctypes.POINTER(Params)]

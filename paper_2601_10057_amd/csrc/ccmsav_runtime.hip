@@ -84,7 +84,7 @@ template <typename TM> struct Launch {
   }
   template <int N>
   static void gram(hipStream_t st, int grid, const Batch& b) {
-    hipLaunchKernelGGL((k_col_gram<TM, N>), dim3(grid), dim3(gram_threads(N)), 0, st, b.m, b.idx,
+    hipLaunchKernelGGL((k_col_gram<TM, N>), dim3(grid), dim3(gram_threads<TM>(N)), 0, st, b.m, b.idx,
                        b.per);
   }
   template <int N, int V>

@@ -45,16 +45,16 @@ def one_line_threads(esz, n):
     return clamp_threads(n // (16 if esz == 8 else 8))
 
 
-def gram_threads(n):
-    return clamp_threads(n // 8)
+def gram_threads(esz, n):
+    return clamp_threads(n // (16 if esz == 8 and n >= 8192 else 8))
 
 
 def fft_radix(esz):
     return 16 if esz == 8 else 8
 
 
-def gram_radix(n):
-    q = n // gram_threads(n)
+def gram_radix(esz, n):
+    q = n // gram_threads(esz, n)
     return 8 if q >= 8 else (4 if q >= 4 else 2)
 
 
@@ -269,8 +269,8 @@ def patterns(esz, n, cls):
         rec_fft(rec, n, 1, nthr, radix)
         rec_pair_post(rec, n, nthr, radix)
     else:
-        nthr = gram_threads(n)
-        gr = gram_radix(n)
+        nthr = gram_threads(esz, n)
+        gr = gram_radix(esz, n)
         rec_makhoul(rec, n, nthr)
         rec_fft(rec, n, 1, nthr, gr)
         rec_pair_post(rec, n, nthr, gr)

@@ -53,7 +53,7 @@ __host__ __device__ constexpr int ps_max(int a, int b) { return a > b ? a : b; }
 template <typename TM> __host__ __device__ constexpr int ps_body_threads(int pass, int n) {
   return pass == 0 ? STENCIL_THREADS
        : pass == 1 ? line_threads(n)
-       : pass == 2 ? gram_threads(n)
+       : pass == 2 ? gram_threads<TM>(n)
        : pass == 3 ? SOLVE_THREADS_SMALL
        : pass == 4 ? line_threads_v<TM>(n, PS_COL_SOLVE_V)
                    : row_idct_threads<TM>(n, 0);
@@ -74,7 +74,7 @@ inline int ps_blocks_per_member(int pass, int nx, int ny, int sblocks) {
 // LDS bytes of the sub-groups of one workgroup for each body and size.
 template <typename TM, int N> constexpr int ps_lds_of_size() {
   constexpr int GD = PS_THREADS / line_threads(N);
-  constexpr int GG = PS_THREADS / gram_threads(N);
+  constexpr int GG = PS_THREADS / gram_threads<TM>(N);
   constexpr int GS = PS_THREADS / line_threads_v<TM>(N, PS_COL_SOLVE_V);
   constexpr int GI = PS_THREADS / row_idct_threads<TM>(N, 0);
   return ps_max(ps_max(GD * ps_stride(sizeof(RowDctLds<TM, N, PS_ROW_DCT_V>)),
@@ -178,7 +178,7 @@ __device__ __attribute__((noinline)) void ps_row_dct(const PersistClass& c, int 
 template <typename TM, int NY>
 __device__ __attribute__((noinline)) void ps_gram(const PersistClass& c, int grp,
                                         const MemberArgs* __restrict__ tab, char* smem) {
-  constexpr int NT = gram_threads(NY), G = PS_THREADS / NT;
+  constexpr int NT = gram_threads<TM>(NY), G = PS_THREADS / NT;
   using L = GramLds<TM, NY>;
   const int sg = (int)threadIdx.x / NT;
   const int per = (1 << c.lx) / 2;
@@ -187,7 +187,7 @@ __device__ __attribute__((noinline)) void ps_gram(const PersistClass& c, int grp
   const OpConst o{m.k.C1, m.k.C2, m.k.C3, m.k.alpha, m.k.lam};
   col_gram_body<TM, NY>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.part2, m.nx, o,
                         vb % per, *reinterpret_cast<L*>(smem + sg * ps_stride(sizeof(L))),
-                        (int)threadIdx.x % NT);
+                        (int)threadIdx.x % NT, static_cast<gptr<TM>>(m.rm));
 }
 
 __device__ __forceinline__ void ps_solve(const PersistClass& c, int grp,

@@ -43,6 +43,14 @@ template <int N, typename F> __device__ __forceinline__ void static_for(F&& f) {
   static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
+// The value x, which the compiler may no longer assume equal to any other
+// value: expressions formed from it are computed where they are used instead
+// of being shared with earlier ones and held (or spilled) in between.
+__device__ __forceinline__ int opaque_vgpr(int x) {
+  __asm__ volatile("" : "+v"(x));
+  return x;
+}
+
 constexpr int clamp_threads(int t) { return t < 64 ? 64 : (t > 1024 ? 1024 : t); }
 // Threads of a line kernel: four elements per thread.
 constexpr int line_threads(int n) { return clamp_threads(n / 4); }
@@ -56,8 +64,12 @@ template <typename TM> constexpr int line_threads_v(int n, int v) {
   return v == 0 ? line_threads(n) : one_line_threads<TM>(n);
 }
 // The Gram kernel keeps four spectra per thread: eight bins per thread give
-// each wave up to 256 registers at one workgroup per CU.
-constexpr int gram_threads(int n) { return clamp_threads(n / 8); }
+// each wave up to 256 registers at one workgroup per CU. FP32 lines of 8192
+// points and more take sixteen bins per thread (workgroups of 8 waves, up to
+// 256 registers each) and keep their spectra in global memory.
+template <typename TM> constexpr int gram_threads(int n) {
+  return clamp_threads(n / (sizeof(TM) == 4 && n >= 8192 ? 16 : 8));
+}
 // Complex lines of length n that fit in LDS next to the twiddle tables.
 template <typename TM> constexpr int lds_line_budget(int n) {
   return (136 * 1024) / (n * (int)sizeof(cpx<TM>));
@@ -635,17 +647,21 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
   constexpr int RH = ROWS / HALVES;
   constexpr int SPL = NTHR / HALVES;                         // column pairs per pass
   constexpr int SPT = NX / 2 >= SPL ? NX / 2 / SPL : 1;      // passes
-  const LS sl(tid);
-  const int spt = tid / HALVES, half = tid % HALVES;
-  // Slots of bins 2 sp and 2 sp + 1 and of their mirrors
-  // N - 2 sp = (N - 1) ^ (2 (sp - 1) + 1) and N - 2 sp - 1 = (N - 1) ^ 2 sp,
-  // for sp = spt + it SPL (2 sp = 2 spt + it 2 SPL, disjoint bits).
-  const int g2 = LS::g(2 * spt);
-  const int g2m = MAP::at(NX - 1) ^ LS::g(1) ^ LS::g((2 * spt - 2) & (NX - 1));
   const TM S0 = (TM)(0.5 * sqrt(1.0 / NX)), S1 = (TM)(0.5 * sqrt(2.0 / NX));
 
   auto round = [&](auto ir) {
     constexpr int r = decltype(ir)::value;
+    // Each round forms its LDS slots (a per-thread base XOR a constant) from
+    // a thread index of its own, so that the compiler does not hold them
+    // from round to round (at the register cap it spilled them).
+    const int tt = opaque_vgpr(tid);
+    const LS sl(tt);
+    const int spt = tt / HALVES, half = tt % HALVES;
+    // Slots of bins 2 sp and 2 sp + 1 and of their mirrors
+    // N - 2 sp = (N - 1) ^ (2 (sp - 1) + 1) and N - 2 sp - 1 = (N - 1) ^ 2 sp,
+    // for sp = spt + it SPL (2 sp = 2 spt + it 2 SPL, disjoint bits).
+    const int g2 = LS::g(2 * spt);
+    const int g2m = MAP::at(NX - 1) ^ LS::g(1) ^ LS::g((2 * spt - 2) & (NX - 1));
 #pragma unroll
     for (int rr = 0; rr < ROWS; ++rr) {
 #pragma unroll
@@ -656,13 +672,13 @@ __device__ __forceinline__ void row_dct8_body(gptr<const TM> __restrict__ rm,
         const int lo = MAP::at((rr * NP + l) * NX);
         static_for<CPT>([&](auto iq) {
           constexpr int q = decltype(iq)::value;
-          const int i = tid + q * NTHR;
+          const int i = tt + q * NTHR;
           if (NX >= NTHR || i < NX) line[lo ^ sl.template mak<q>()] = {ra[i], rb[i]};
         });
       }
     }
     lds_sync();
-    fft_lines<TM, NX, ROWS * NP, NTHR, R, MAP>(line, rt, tid);
+    fft_lines<TM, NX, ROWS * NP, NTHR, R, MAP>(line, rt, tt);
 #pragma unroll 1
     for (int it = 0; it < SPT; ++it) {
       const int sp = spt + it * SPL;
@@ -853,7 +869,7 @@ __device__ __forceinline__ void stage_accumulate(double (&v)[NV], const int (&id
 // sums that are reduced over the block once per strip instead of once per
 // field.
 template <typename TM, int NY> struct GramPlan {
-  static constexpr int NTHR = gram_threads(NY);
+  static constexpr int NTHR = gram_threads<TM>(NY);
   static constexpr int LINE_B = NY * (int)sizeof(cpx<TM>);
   static constexpr int ROOT_B = Roots<TM, NY>::SIZE * (int)sizeof(cpx<double>);
   // The partial sums only go to LDS while the CU still holds 8 waves of
@@ -872,6 +888,12 @@ template <typename TM, int NY> struct GramPlan {
   static constexpr bool S_LDS = !DBL && 2 * LINE_B + ROOT_B <= BUDGET;
   static constexpr bool ACC_LDS =
       (S_LDS || DBL ? 2 : 1) * LINE_B + ROOT_B + ACC_B <= ACC_BUDGET && NTHR % 16 == 0;
+  // FP32 lines of 8192 points and more: sixteen bins per thread leave no
+  // registers for the kept spectra beside a transform, so they go to
+  // per-thread slots in global memory (the stencil output region, unused
+  // while this pass runs), written once and read once by the same thread,
+  // coalesced across the wave.
+  static constexpr bool KEEP_GLOBAL = NY >= 8192;
 };
 template <typename TM, int NY> struct GramLds {
   using GP = GramPlan<TM, NY>;
@@ -888,7 +910,7 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
                                               gptr<const double> __restrict__ lamy,
                                               gptr<double> __restrict__ part, int nx,
                                               const OpConst c, int s, GramLds<TM, NY>& L,
-                                              int tid) {
+                                              int tid, gptr<TM> __restrict__ kg) {
   using GP = GramPlan<TM, NY>;
   constexpr int NTHR = GP::NTHR;
   constexpr int LPT = NY >= NTHR ? NY / NTHR : 1;            // strip loads per thread
@@ -950,16 +972,34 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
     }
   };
   // Spectra kept for the pairwise products: index 0 = S~ (unless in LDS),
-  // 1 = H, 2 = Q~, 3 = K~.
-  TM ka[4][KPT], kb[4][KPT];
+  // 1 = H, 2 = Q~, 3 = K~; later 1 = P~ and 2 = g_lin. With GP::KEEP_GLOBAL
+  // slot f of bin index j is element (f KPT + j) NTHR + tid of this strip's
+  // block of 4 NY complex values in kg.
+  constexpr bool KG = GP::KEEP_GLOBAL;
+  constexpr int KR = KG ? 1 : KPT;
+  TM ka[4][KR], kb[4][KR];
+  typedef TM tm2 __attribute__((ext_vector_type(2)));
+  const auto kgs = reinterpret_cast<gptr<tm2>>(kg) + (size_t)s * 4 * NY + tid;
   auto kept = [&](int f, int j, TM& a, TM& b) {
     if (S_LDS && f == 0) {
       const cpx<TM> v = keep[tid + j * KS];
       a = v.re;
       b = v.im;
+    } else if constexpr (KG) {
+      const tm2 v = kgs[(f * KPT + j) * NTHR];
+      a = v[0];
+      b = v[1];
     } else {
       a = ka[f][j];
       b = kb[f][j];
+    }
+  };
+  auto put = [&](int f, int j, TM a, TM b) {
+    if constexpr (KG) {
+      kgs[(f * KPT + j) * NTHR] = tm2{a, b};
+    } else {
+      ka[f][j] = a;
+      kb[f][j] = b;
     }
   };
   // Fields in the order they are transformed. With FP32 lines the fields
@@ -977,7 +1017,7 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
                     mid_pair(ORDER[4]) == mid_pair(ORDER[5]) && mid_half(ORDER[4]) == 0 &&
                     mid_pair(ORDER[6]) == mid_pair(ORDER[7]) && mid_half(ORDER[6]) == 0,
                 "the transform order takes the pairs' fields one after the other");
-  constexpr bool PAIRS = sizeof(TM) == 4 && NTHR <= 512;
+  constexpr bool PAIRS = sizeof(TM) == 4 && NTHR <= 512 && !GP::KEEP_GLOBAL;
   // The first FFT stage runs on the loaded registers where every stage has
   // one butterfly per thread.
   constexpr bool FIRST_IN_REGS = first_stage_in_registers<NY, NTHR, GR>() && LPT == GR;
@@ -1018,6 +1058,23 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
         cur = pb[cs];
         if constexpr (i + 1 < 8 && QH < LPT) fetch_pair(ORDER[i + 1], INS{}, IH{}, IL{});
       }
+    } else if constexpr (GP::KEEP_GLOBAL) {
+      // The eight transforms form their LDS slots (a per-thread base XOR a
+      // constant) from a thread index of their own, so that the compiler
+      // does not hold each slot across the kernel (it spilled them).
+      static_assert(!GP::DBL && !FIRST_IN_REGS, "one line buffer, loads into LDS");
+      const int tt = opaque_vgpr(tid);
+      const LS slt(tt);
+      if constexpr (sizeof(TM) == 4) {
+        const auto src = reinterpret_cast<gptr<const cpx<TM>>>(
+            mid + mid_pair(ORDER[i]) * pair_field(nx, NY) + (size_t)s * pair_strip_stride(NY) +
+            2 * mid_half(ORDER[i]));
+        fetch_strip<TM, NY, LPT, NTHR, 2>(src, tt, cur);
+      } else {
+        fetch_strip<TM, NY, LPT, NTHR>(strip(ORDER[i]), tt, cur);
+      }
+      column_dct2<TM, NY, LPT, UPT, NTHR, GR, MAP, false, true>(cur, line, rt, slt, tt, A, B);
+      return;
     } else if constexpr (sizeof(TM) == 4) {
       const auto src = reinterpret_cast<gptr<const cpx<TM>>>(
           mid + mid_pair(ORDER[i]) * pair_field(nx, NY) + (size_t)s * pair_strip_stride(NY) +
@@ -1047,8 +1104,7 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
       if (S_LDS && a == 0) {
         if (valid) keep[tid + j * KS] = {A[j], B[j]};
       } else {
-        ka[a][j] = A[j];
-        kb[a][j] = B[j];
+        put(a, j, A[j], B[j]);
       }
     }
   };
@@ -1097,8 +1153,19 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   }
   // zeta group: P~ and g_lin kept (in the H and Q~ slots), then L~; both
   // inner products with one weight per bin.
-  transform_next(std::integral_constant<int, 5>{}, ka[1], kb[1]);
-  transform_next(std::integral_constant<int, 6>{}, ka[2], kb[2]);
+  if constexpr (KG) {
+    auto keep_zeta = [&](auto ii, int f) {
+      TM A[KPT], B[KPT];
+      transform_next(ii, A, B);
+#pragma unroll
+      for (int j = 0; j < KPT; ++j) put(f, j, A[j], B[j]);
+    };
+    keep_zeta(std::integral_constant<int, 5>{}, 1);
+    keep_zeta(std::integral_constant<int, 6>{}, 2);
+  } else {
+    transform_next(std::integral_constant<int, 5>{}, ka[1], kb[1]);
+    transform_next(std::integral_constant<int, 6>{}, ka[2], kb[2]);
+  }
   {
     TM A[KPT], B[KPT];
     transform_next(std::integral_constant<int, 7>{}, A, B);
@@ -1109,8 +1176,11 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
       if (!valid) continue;
       double i0, i1;
       inv_op(bin_of(j), false, i0, i1);
-      const double pa = (double)ka[1][j] * i0, pb = (double)kb[1][j] * i1;
-      v[0] += pa * (double)ka[2][j] + pb * (double)kb[2][j];
+      TM p0, p1, g0, g1;
+      kept(1, j, p0, p1);
+      kept(2, j, g0, g1);
+      const double pa = (double)p0 * i0, pb = (double)p1 * i1;
+      v[0] += pa * (double)g0 + pb * (double)g1;
       v[1] += pa * (double)A[j] + pb * (double)B[j];
     }
     accumulate(v, idx);
@@ -1919,13 +1989,13 @@ __global__ void __launch_bounds__(line_threads(NX)) k_row_dct8(BATCH_PARAMS) {
 }
 
 template <typename TM, int NY>
-__global__ void __launch_bounds__(gram_threads(NY)) k_col_gram(BATCH_PARAMS) {
+__global__ void __launch_bounds__(gram_threads<TM>(NY)) k_col_gram(BATCH_PARAMS) {
   __shared__ GramLds<TM, NY> L;
   int blk;
   const MemberArgs& m = batch_member(tab, idx, per, blk);
   const OpConst o{m.k.C1, m.k.C2, m.k.C3, m.k.alpha, m.k.lam};
   col_gram_body<TM, NY>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.part2, m.nx, o, blk,
-                        L, threadIdx.x);
+                        L, threadIdx.x, static_cast<gptr<TM>>(m.rm));
 }
 
 template <int NTHR>

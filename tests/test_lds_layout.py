@@ -115,7 +115,7 @@ def test_line_slots_match_direct_definitions(esz):
     for n in G.SIZES:
         for cls, nthrs, rad in (
                 ("SWZ_LINE", {G.line_threads(n), G.one_line_threads(esz, n)}, radix),
-                ("SWZ_GRAM", {G.gram_threads(n)}, G.gram_radix(n)),
+                ("SWZ_GRAM", {G.gram_threads(esz, n)}, G.gram_radix(esz, n)),
                 ("SWZ_ROW", {G.row_dct_threads(n, 0), G.row_dct_threads(n, 1),
                              G.row_idct_threads(esz, n)}, radix)):
             at = mapper(esz, n, cls)
@@ -163,7 +163,7 @@ def test_fft_stage_slots(esz):
     radix = G.fft_radix(esz)
     for n in G.SIZES:
         cases = [("SWZ_LINE", 1, nt, radix) for nt in {G.line_threads(n), G.one_line_threads(esz, n)}]
-        cases.append(("SWZ_GRAM", 1, G.gram_threads(n), G.gram_radix(n)))
+        cases.append(("SWZ_GRAM", 1, G.gram_threads(esz, n), G.gram_radix(esz, n)))
         for v in (0, 1):
             cases.append(("SWZ_ROW", G.p1_rows_v(esz, n, v) * G.p1_pairs_v(esz, n, v),
                           G.row_dct_threads(n, v), radix))
