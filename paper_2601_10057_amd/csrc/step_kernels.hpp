@@ -1089,8 +1089,19 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
     }
     // field i's line (alternating buffers where GP::DBL)
     cpx<TM>* ln = GP::DBL ? line + (i % 2) * NY : line;
-    column_dct2<TM, NY, LPT, UPT, NTHR, GR, MAP, FIRST_IN_REGS, !GP::DBL>(cur, ln, rt, sl, tid, A,
-                                                                        B);
+    if constexpr (sizeof(TM) == 8) {
+      // FP64 lines form their slots per transform as well: fewer registers
+      // held across the kernel, two workgroups per CU at N = 1024 and 2048
+      // (with FP32 lines the extra address arithmetic costs more than the
+      // registers it frees).
+      const int tt = opaque_vgpr(tid);
+      const LS slt(tt);
+      column_dct2<TM, NY, LPT, UPT, NTHR, GR, MAP, FIRST_IN_REGS, !GP::DBL>(cur, ln, rt, slt, tt,
+                                                                          A, B);
+    } else {
+      column_dct2<TM, NY, LPT, UPT, NTHR, GR, MAP, FIRST_IN_REGS, !GP::DBL>(cur, ln, rt, sl, tid,
+                                                                          A, B);
+    }
   };
   // chi group: S~, H, Q~, K~ transformed and kept; their inner products are
   // taken together with those of f_lin, bin by bin, so that each bin's
