@@ -1614,6 +1614,13 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
   }
   lds_sync();
   fft_lines<TM, NY, 1, NTHR, R, MAP>(line, rt, tid);
+  // FP32 lines of 8192 points and more: the divide, the inverse transform
+  // and the stores form their LDS slots from a thread index of their own,
+  // so that the compiler does not hold the first half's slots through them
+  // (147 -> 111 registers with one butterfly per thread: two workgroups per
+  // CU). Shorter lines keep the shared slots, which measured faster there.
+  const int t2 = sizeof(TM) == 4 && NY >= 8192 ? opaque_vgpr(tid) : tid;
+  const LS sl2(t2);
   // Per pair unit: DCT-II post-processing of both bins, divide by the operator
   // spectrum, DCT-III pre-processing of both bins (the unit holds everything
   // the inverse needs, so the line is rewritten directly).
@@ -1624,10 +1631,10 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
   cpx<TM> Z[UPT], Zm[UPT];
   static_for<UPT>([&](auto iq) {
     constexpr int q = decltype(iq)::value;
-    const int u = tid + q * NTHR;
+    const int u = t2 + q * NTHR;
     if (NY / 2 >= NTHR || u < NY / 2) {
       TM A, B, Am, Bm;
-      dct2_unit<TM, NY>(line, sl.template bin<q>(), sl.template binm<q>(), rt, u, A, B, Am, Bm);
+      dct2_unit<TM, NY>(line, sl2.template bin<q>(), sl2.template binm<q>(), rt, u, A, B, Am, Bm);
       const double ly = lamy[u], lym = lamy[pair_mirror<NY>(u)];
       A = (TM)((double)A * rcp64(op(lx0 + ly)));
       B = (TM)((double)B * rcp64(op(lx1 + ly)));
@@ -1642,21 +1649,21 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
   lds_sync();
   static_for<UPT>([&](auto iq) {
     constexpr int q = decltype(iq)::value;
-    if (NY / 2 >= NTHR || tid < NY / 2) {
-      line[sl.template nat<q>()] = Z[q];
-      line[sl.template natm<q>()] = Zm[q];
+    if (NY / 2 >= NTHR || t2 < NY / 2) {
+      line[sl2.template nat<q>()] = Z[q];
+      line[sl2.template natm<q>()] = Zm[q];
     }
   });
   lds_sync();
-  fft_lines<TM, NY, 1, NTHR, R, MAP>(line, rt, tid);
+  fft_lines<TM, NY, 1, NTHR, R, MAP>(line, rt, t2);
   const auto dst = reinterpret_cast<gptr<cpx<TM>>>(out + (size_t)grp * FSM + (size_t)s * SS);
   TM y0[LPT];
   static_for<LPT>([&](auto iq) {
     constexpr int q = decltype(iq)::value;
-    const int i = tid + q * NTHR;
+    const int i = t2 + q * NTHR;
     y0[q] = (TM)0;
     if (NY >= NTHR || i < NY) {
-      const cpx<TM> y = line[sl.template out<q>()];
+      const cpx<TM> y = line[sl2.template out<q>()];
       gstore<TM>(dst + i, {y.re, -y.im});
       y0[q] = y.re;
     }
@@ -1671,13 +1678,13 @@ __device__ __forceinline__ void col_solve_body(gptr<const TM> __restrict__ mid,
     lds_sync();
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
-      const int i = tid + q * NTHR;
+      const int i = t2 + q * NTHR;
       if (sums_here && i < NY) buf[i] = (double)y0[q];
     }
-    const double mean = tree_sum<NY>(buf, tid, NTHR) / NY;
+    const double mean = tree_sum<NY>(buf, t2, NTHR) / NY;
 #pragma unroll
     for (int q = 0; q < LPT; ++q) {
-      const int i = tid + q * NTHR;
+      const int i = t2 + q * NTHR;
       if (sums_here && i < NY) colsum[i] = (double)y0[q] - mean;
     }
   }
