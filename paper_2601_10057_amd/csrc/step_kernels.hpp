@@ -1045,6 +1045,12 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
   using IH = std::integral_constant<int, QH>;
   using IL = std::integral_constant<int, LPT>;
   if constexpr (PAIRS) fetch_pair(ORDER[0], I0{}, I0{}, IL{});
+  // FP32 lines with the kept spectra in global memory: a pair's strip is
+  // loaded once, with 16-byte loads, when its first field is transformed;
+  // the second field waits in registers (loading each half on its own
+  // fetched the pair's sectors twice).
+  constexpr bool KG_PAIR = GP::KEEP_GLOBAL && sizeof(TM) == 4;
+  StripRegs<TM, KG_PAIR ? LPT : 1> kg_second;
   auto transform_next = [&](auto ii, TM (&A)[KPT], TM (&B)[KPT]) {
     constexpr int i = decltype(ii)::value;
     StripRegs<TM, LPT> cur;
@@ -1065,11 +1071,14 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
       static_assert(!GP::DBL && !FIRST_IN_REGS, "one line buffer, loads into LDS");
       const int tt = opaque_vgpr(tid);
       const LS slt(tt);
-      if constexpr (sizeof(TM) == 4) {
-        const auto src = reinterpret_cast<gptr<const cpx<TM>>>(
-            mid + mid_pair(ORDER[i]) * pair_field(nx, NY) + (size_t)s * pair_strip_stride(NY) +
-            2 * mid_half(ORDER[i]));
-        fetch_strip<TM, NY, LPT, NTHR, 2>(src, tt, cur);
+      if constexpr (KG_PAIR) {
+        if constexpr (i % 2 == 0) {
+          const auto src =
+              mid + mid_pair(ORDER[i]) * pair_field(nx, NY) + (size_t)s * pair_strip_stride(NY);
+          fetch_pair_strip<TM, NY, LPT, NTHR, 0, LPT>(src, tt, cur, kg_second);
+        } else {
+          cur = kg_second;
+        }
       } else {
         fetch_strip<TM, NY, LPT, NTHR>(strip(ORDER[i]), tt, cur);
       }
