@@ -185,7 +185,7 @@ __device__ __attribute__((noinline)) void ps_gram(const PersistClass& c, int grp
   const int vb = grp * G + sg;
   const MemberArgs& m = tab[c.idx[vb / per]];
   const OpConst o{m.k.C1, m.k.C2, m.k.C3, m.k.alpha, m.k.lam};
-  col_gram_body<TM, NY>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.part2, m.nx, o,
+  col_gram_body<TM, NY, true>(static_cast<gptr<const TM>>(m.mid), m.lamx, m.lamy, m.part2, m.nx, o,
                         vb % per, *reinterpret_cast<L*>(smem + sg * ps_stride(sizeof(L))),
                         (int)threadIdx.x % NT, static_cast<gptr<TM>>(m.rm));
 }

@@ -904,7 +904,9 @@ template <typename TM, int NY> struct GramLds {
   double acc[GP::ACC_LDS ? P2_NSUM * GP::NTHR : P2_NSUM];
 };
 
-template <typename TM, int NY>
+// FRESH_SLOTS: every transform forms its LDS slots anew (the persistent
+// launch, where the kernel's register budget is shared by all passes).
+template <typename TM, int NY, bool FRESH_SLOTS = false>
 __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
                                               gptr<const double> __restrict__ lamx,
                                               gptr<const double> __restrict__ lamy,
@@ -1098,11 +1100,11 @@ __device__ __forceinline__ void col_gram_body(gptr<const TM> __restrict__ mid,
     }
     // field i's line (alternating buffers where GP::DBL)
     cpx<TM>* ln = GP::DBL ? line + (i % 2) * NY : line;
-    if constexpr (sizeof(TM) == 8) {
+    if constexpr (sizeof(TM) == 8 || FRESH_SLOTS) {
       // FP64 lines form their slots per transform as well: fewer registers
       // held across the kernel, two workgroups per CU at N = 1024 and 2048
-      // (with FP32 lines the extra address arithmetic costs more than the
-      // registers it frees).
+      // (with FP32 lines in their own launch the extra address arithmetic
+      // costs more than the registers it frees).
       const int tt = opaque_vgpr(tid);
       const LS slt(tt);
       column_dct2<TM, NY, LPT, UPT, NTHR, GR, MAP, FIRST_IN_REGS, !GP::DBL>(cur, ln, rt, slt, tt,
